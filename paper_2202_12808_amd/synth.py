@@ -1,0 +1,167 @@
+"""Seeded synthetic sparse-coding problems (the compressed-sensing simulation of
+Sec. 4): a dictionary Phi, a sparse ground truth z*, and y = Phi z* + noise.
+
+This module only draws inputs.  It holds none of CoFEM's arithmetic; both the
+HIP path's tests and the FP64 oracle take their inputs from here.
+
+Recipes (one per named workload; the generative model is Eq. 1 with the noise
+precision beta known):
+
+* ``dense_256x1024``    Phi 256x1024 iid N(0, 1/N); 20 nonzeros at uniform
+                        positions, N(0,1) values; beta = 1e4; K = 20; eps 1e-6;
+                        U = 400; T_em = 50.
+* ``dense_4096x16384``  Phi 4096x16384 iid N(0, 1/N); 1% nonzeros N(0,1);
+                        beta = 1e3; K = 32; eps 1e-5; U = 400; T_em = 30.
+* ``conv_256x256_k7``   2D circular convolution, 7x7 taps iid N(0,1) scaled to
+                        unit l2 norm, 256x256 image; 2% nonzeros Laplace(1);
+                        beta = 1e4; K = 16; eps 1e-5; U = 400; T_em = 30.
+* ``conv_1024x1024_k9`` same law, 9x9 taps, 1024x1024 image; 1% nonzeros
+                        N(0,1); beta = 1e4; K = 16; eps 1e-5; U = 400; T_em = 30.
+* ``batched_64``        64 dense problems, D_i = 4*U{256..4096}, N_i = D_i/4,
+                        Phi iid N(0, 1/N_i) rounded to bfloat16; 2% nonzeros
+                        N(0,1); beta = 1e3; K = 16; eps 1e-5; U = 400; T_em = 30.
+
+The number of nonzeros is round(rho * D) (half up), positions uniform without
+replacement.  Phi and y are stored in float32 (the stored values are the
+problem); z* stays float64.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    kind: str                      # "dense" | "conv"
+    N: int
+    D: int
+    y: np.ndarray                  # float32 (N,)
+    z: np.ndarray                  # float64 (D,) ground truth
+    beta: float
+    K: int
+    tol: float
+    max_iter: int
+    T_em: int
+    seed: int
+    phi: Optional[np.ndarray] = None    # float32 (N, D), row-major
+    taps: Optional[np.ndarray] = None   # float32 (kh, kw)
+    H: int = 0
+    W: int = 0
+    name: str = ""
+
+
+def _sparse_signal(rng, D, nnz, law):
+    z = np.zeros(D)
+    pos = rng.choice(D, size=nnz, replace=False)
+    if law == "normal":
+        z[pos] = rng.standard_normal(nnz)
+    elif law == "laplace":
+        z[pos] = rng.laplace(0.0, 1.0, nnz)
+    elif law == "spikes":
+        z[pos] = rng.choice(np.array([-1.0, 1.0]), size=nnz)
+    else:
+        raise ValueError(law)
+    return z
+
+
+def _nnz(rho, D):
+    return int(math.floor(rho * D + 0.5))
+
+
+def dense_problem(N, D, *, nnz=None, rho=None, beta, K, tol, max_iter=400, T_em=30,
+                  seed=0, law="normal", bf16=False, name="") -> Problem:
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((N, D), dtype=np.float32)
+    phi *= np.float32(1.0 / math.sqrt(N))
+    if bf16:
+        phi = round_to_bf16(phi)
+    if nnz is None:
+        nnz = _nnz(rho, D)
+    z = _sparse_signal(rng, D, nnz, law)
+    noise = rng.standard_normal(N) / math.sqrt(beta)
+    y = (phi.astype(np.float64) @ z + noise).astype(np.float32)
+    return Problem("dense", N, D, y, z, float(beta), K, tol, max_iter, T_em, seed,
+                   phi=phi, name=name)
+
+
+def conv_taps(rng, kh, kw):
+    h = rng.standard_normal((kh, kw))
+    h /= np.linalg.norm(h)
+    return h.astype(np.float32)
+
+
+def _circ_conv_f64(taps, img):
+    """Forward model for data synthesis only (direct circular convolution)."""
+    kh, kw = taps.shape
+    ch, cw = (kh - 1) // 2, (kw - 1) // 2
+    out = np.zeros_like(img)
+    for a in range(kh):
+        for b in range(kw):
+            out += float(taps[a, b]) * np.roll(img, (a - ch, b - cw), axis=(0, 1))
+    return out
+
+
+def conv_problem(H, W, k, *, rho, beta, K, tol, max_iter=400, T_em=30, seed=0,
+                 law="normal", name="") -> Problem:
+    rng = np.random.default_rng(seed)
+    taps = conv_taps(rng, k, k)
+    D = H * W
+    z = _sparse_signal(rng, D, _nnz(rho, D), law)
+    clean = _circ_conv_f64(taps.astype(np.float64), z.reshape(H, W)).reshape(D)
+    y = (clean + rng.standard_normal(D) / math.sqrt(beta)).astype(np.float32)
+    return Problem("conv", D, D, y, z, float(beta), K, tol, max_iter, T_em, seed,
+                   taps=taps, H=H, W=W, name=name)
+
+
+def round_to_bf16(x: np.ndarray) -> np.ndarray:
+    """float32 -> nearest bfloat16 (ties to even), returned as float32."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return (r & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.float32)
+
+
+# ---- the named workloads -------------------------------------------------
+def dense_256x1024(seed=0):
+    return dense_problem(256, 1024, nnz=20, beta=1e4, K=20, tol=1e-6, max_iter=400,
+                         T_em=50, seed=seed, name="dense_256x1024")
+
+
+def dense_4096x16384(seed=0):
+    return dense_problem(4096, 16384, rho=0.01, beta=1e3, K=32, tol=1e-5, max_iter=400,
+                         T_em=30, seed=seed, name="dense_4096x16384")
+
+
+def conv_256x256_k7(seed=0):
+    return conv_problem(256, 256, 7, rho=0.02, beta=1e4, K=16, tol=1e-5, max_iter=400,
+                        T_em=30, seed=seed, law="laplace", name="conv_256x256_k7")
+
+
+def conv_1024x1024_k9(seed=0):
+    return conv_problem(1024, 1024, 9, rho=0.01, beta=1e4, K=16, tol=1e-5, max_iter=400,
+                        T_em=30, seed=seed, law="normal", name="conv_1024x1024_k9")
+
+
+def batched_sizes(seed=0, count=64):
+    rng = np.random.default_rng(10_000 + seed)
+    return [4 * int(v) for v in rng.integers(256, 4097, size=count)]
+
+
+def batched_64(seed=0, count=64, sizes=None):
+    sizes = batched_sizes(seed, count) if sizes is None else sizes
+    return [dense_problem(D // 4, D, rho=0.02, beta=1e3, K=16, tol=1e-5, max_iter=400,
+                          T_em=30, seed=seed * 1000 + i, bf16=True, name=f"batched_{i}")
+            for i, D in enumerate(sizes)]
+
+
+WORKLOADS = {
+    "dense_256x1024": dense_256x1024,
+    "dense_4096x16384": dense_4096x16384,
+    "conv_256x256_k7": conv_256x256_k7,
+    "conv_1024x1024_k9": conv_1024x1024_k9,
+}
