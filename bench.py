@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the CoFEM E-step hot path on one MI355X.
+
+A step is one full CoFEM solve of the workload: T_em EM iterations of
+Algorithm 1 from alpha = 1 (E-step by multi-right-hand-side CG, diagonal
+estimate, M-step), on inputs already resident in HBM.  The reported value is
+EM iterations per second over the timed steps.
+
+Besides the throughput line the JSON carries:
+  roofline      the dominant operator kernel's achieved HBM bandwidth
+                (algorithmic bytes per launch / mean launch time, HIP events on
+                the library's stream) against the 8 TB/s MI355X peak;
+  cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the
+                first E-step, its CG iteration count fixed to the GPU's),
+                scaled to EM iterations per second with the GPU's mean CG count;
+  parity        relative errors of that first GPU step against the oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EM iters/sec at fixed NMSE vs FP64 oracle; bf16+learned vs plain FP32 CG"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(p, which):
+    """Bytes one launch must move at minimum: the dictionary once plus the
+    skinny operands it is contracted with (K probe columns float32, the mean
+    column float64)."""
+    K, N, D = p.K, p.N, p.D
+    col = 4 * K + 8
+    if p.kind == "dense":
+        if which == "pass1":   # W = Phi P: Phi, P in, W out
+            return 4 * N * D + D * col + N * col
+        # pass 2: Phi, W in; P, R, alpha in; Q out
+        return 4 * N * D + N * col + 3 * D * col + 4 * D
+    # conv fused pass: P, R, alpha in; Q out (taps negligible)
+    return 3 * D * col + 4 * D
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="dense_4096x16384",
+                    choices=["dense_4096x16384", "dense_256x1024", "conv_256x256_k7", "conv_1024x1024_k9"])
+    ap.add_argument("--em-iters", type=int, default=0, help="EM iterations per step (default: workload's)")
+    ap.add_argument("--timing-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2202_12808_amd import synth
+    from paper_2202_12808_amd.cofem import CoFEM
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    p = synth.WORKLOADS[args.workload](0)
+    T_em = args.em_iters or p.T_em
+    log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} beta={p.beta} tol={p.tol} U={p.max_iter} "
+        f"T_em={T_em} (inputs generated in {time.perf_counter() - t_gen:.1f}s)")
+
+    y = torch.from_numpy(p.y).to(dev)
+    if p.kind == "dense":
+        phi = torch.from_numpy(p.phi).to(dev)
+        g = CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+    else:
+        taps = torch.from_numpy(p.taps).to(dev)
+        g = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+    ones = torch.ones(p.D, dtype=torch.float32, device=dev)
+
+    def one_step():
+        g.set_alpha(ones)
+        g.set_iteration(1)
+        return g.em_step(T_em)
+
+    # first E-step alone (for the parity and the CPU sample)
+    g.set_alpha(ones)
+    g.set_iteration(1)
+    first = g.em_step(1)[0]
+    mu1, s1, a1 = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+
+    for w in range(args.warmup):
+        st = one_step()
+        log(f"warmup {w + 1}/{args.warmup}: cg iters {sum(x['cg_iters'] for x in st)}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_stats = []
+    for k in range(args.steps):
+        all_stats.append(one_step())
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = all_stats[-1]
+    cg_counts = [x["cg_iters"] for x in stats]
+    mean_cg = float(np.mean(cg_counts))
+    value = args.steps * T_em / elapsed
+    mu_T = g.posterior()[0].cpu().numpy().astype(np.float64)
+    nrmse = float(np.linalg.norm(mu_T - p.z) / np.linalg.norm(p.z))
+    log(f"{value:.3f} EM it/s; CG iterations per EM iteration: mean {mean_cg:.1f}, "
+        f"min {min(cg_counts)}, max {max(cg_counts)}; NRMSE vs ground truth {nrmse:.4f}")
+
+    # roofline of the dominant operator kernel
+    ms = g.time_operator(args.timing_reps)
+    if p.kind == "dense":
+        kern = {"pass1": ms[0], "pass2": ms[1]}
+        names = {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2"}
+    else:
+        kern = {"pass": ms[0]}
+        names = {"pass": "k_conv_pass"}
+    dom = max(kern, key=kern.get)
+    nbytes = algorithmic_bytes(p, dom)
+    achieved = nbytes / (kern[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[dom],
+                "bytes_per_launch": nbytes, "ms_per_launch": round(kern[dom], 5),
+                "all_kernels_ms": {names[k]: round(v, 5) for k, v in kern.items()}}
+    log(f"roofline: {names[dom]} {kern[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
+        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count()])
+        except Exception:
+            threads = os.cpu_count()
+        if p.kind == "dense":
+            op = O.DenseOperator(p.phi.astype(np.float64))
+        else:
+            op = O.ConvOperator(p.taps.astype(np.float64), p.H, p.W)
+        n1 = first["cg_iters"]
+        tc0 = time.perf_counter()
+        b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+        e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1,
+                          fixed_iters=n1)
+        a_ref, _ = O.mstep(e.mu, e.s)
+        t_sample = time.perf_counter() - tc0
+        per_cg = t_sample / max(n1, 1)
+        cpu_em_per_s = 1.0 / (per_cg * mean_cg)
+        cpu = {"value": round(cpu_em_per_s, 5), "unit": "EM it/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"first E-step + M-step of {p.name} at {n1} CG iterations took {t_sample:.2f}s "
+                         f"on the host; scaled by the GPU run's mean of {mean_cg:.1f} CG iterations "
+                         f"per EM iteration"}
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        parity = {"step": 1, "cg_iters": n1, "relerr_mu": rel(mu1, e.mu), "relerr_s": rel(s1, e.s),
+                  "relerr_alpha": rel(a1, a_ref), "nmse_mu": rel(mu1, e.mu) ** 2}
+        log(f"cpu oracle: {cpu_em_per_s:.4f} EM it/s on {threads} threads; parity {parity}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "EM it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
+                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": "fp32 probes + fp64 mean column",
+                   "cg_iters_per_em_mean": round(mean_cg, 2), "nrmse_vs_truth": round(nrmse, 6)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * cofem.h -- C ABI of libcofem.so, the MI355X (gfx950) hot path of covariance-free
+ * EM (CoFEM) for sparse Bayesian learning (Lin, Song, Bilgic, Ba, arXiv 2202.12808).
+ *
+ * Problem (Sec. 2.1, Eq. 1): y = Phi z + noise, z ~ N(0, diag(alpha)^-1), noise
+ * precision beta.  One EM iteration (Algorithm 1) is
+ *   A = beta Phi^T Phi + diag(alpha)                        (Eq. 5, Eq. 7)
+ *   B = [p_1 .. p_K | beta Phi^T y],  p_k Rademacher       (Eq. 7, Sec. 3.1)
+ *   X = [x_1 .. x_K | mu] solves A X = B by CG             (Sec. 3.2)
+ *   s = (1/K) sum_k p_k (.) x_k                            (Eq. 6)
+ *   alpha <- 1 ./ max(mu (.) mu + s, 1/alpha_max)          (Eq. 8; floor: see below)
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented as "device" are HIP device pointers (e.g. torch CUDA
+ *    tensors on ROCm); "host" pointers are ordinary host memory.
+ *  - All GPU work is enqueued on the stream given to cofem_init (NULL = the
+ *    default stream).  A context is not thread-safe; use one per stream.
+ *  - Every call returns a cofem_status; on error, out-parameters are left
+ *    untouched and cofem_last_error() describes the failure.  No C++ exception
+ *    crosses this boundary.  Reaching the CG iteration cap U is not an error:
+ *    the paper caps CG by design (Sec. 3.2) and it shows as converged = 0.
+ *  - Readings of the paper fixed by this library: A carries beta in every
+ *    section (the CG subsection drops it: a typo); CG starts from X = 0 and
+ *    stops once the recursively updated residual satisfies
+ *    ||R||_F / ||B||_F < cg_tol (joint Frobenius over all K+1 columns, Sec. 3.2)
+ *    or after cg_max_iter iterations; probes are redrawn at every EM iteration
+ *    t from the counter-based SplitMix64 stream of `seed` (entry (j, k) takes
+ *    bit j mod 64 of stream word (t << 48 | k << 32 | j >> 6), counted from 1;
+ *    bit 0 -> +1); the M-step denominator is floored at 1/alpha_max.
+ */
+#ifndef COFEM_H_
+#define COFEM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cofem_status {
+  COFEM_OK = 0,
+  COFEM_ERR_INVALID_ARG = 1,   /* bad sizes, null pointers, beta <= 0, K out of range */
+  COFEM_ERR_OUT_OF_MEMORY = 2, /* device allocation failed (nothing leaked) */
+  COFEM_ERR_DEVICE = 3,        /* a HIP runtime call failed; message has hipGetErrorString */
+  COFEM_ERR_NUMERIC = 4,       /* NaN/Inf reached a CG scalar */
+  COFEM_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement */
+} cofem_status;
+
+/* cofem_problem.kind */
+enum { COFEM_DENSE = 0, COFEM_CONV2D_CIRC = 1 };
+/* cofem_problem.phi_dtype */
+enum { COFEM_F32 = 0, COFEM_BF16 = 1 };
+/* cofem_params.precision */
+enum { COFEM_PREC_FP32 = 0, COFEM_PREC_BF16_IR = 1 };
+/* cofem_params.stop_rule */
+enum { COFEM_STOP_FROBENIUS = 0 };
+
+/* Maximum number of probe vectors K per problem. */
+#define COFEM_MAX_K 32
+
+/*
+ * One SBL problem (Eq. 1).  Dictionary given either densely or as a 2D
+ * circular convolution (a structured Phi with a fast apply, Sec. 1, Sec. 3.2).
+ *
+ * kind == COFEM_DENSE:
+ *   phi     device, N x D, row-major with leading dimension ld_phi >= D
+ *           (elements), dtype phi_dtype (COFEM_F32).
+ * kind == COFEM_CONV2D_CIRC:
+ *   N == D == H * W; pixel j = u * W + v (row-major image);
+ *   taps    device, kh x kw float32, row-major; kh == kw, odd, 1..9;
+ *   (Phi z)[u, v] = sum_{a,b} taps[a, b] * z[(u - a + ch) mod H, (v - b + cw) mod W],
+ *   ch = (kh - 1) / 2, cw = (kw - 1) / 2; Phi^T is the matching correlation.
+ * y         device, N float32.
+ * phi, taps and y are read during cofem_init only (the library keeps its own
+ * packed copy of Phi and the vector beta Phi^T y); the caller keeps ownership.
+ */
+typedef struct cofem_problem {
+  int32_t kind;
+  int64_t N;
+  int64_t D;
+  const void* phi;
+  int64_t ld_phi;
+  int32_t phi_dtype;
+  int32_t H, W, kh, kw;
+  const float* taps;
+  const float* y;
+} cofem_problem;
+
+/*
+ * Solver parameters: Algorithm 1's beta and K, and the CG controls of
+ * Sec. 3.2 (tolerance eps = cg_tol, iteration cap U = cg_max_iter).
+ * alpha_max <= 0 selects 1e10.  poll_interval: CG iterations enqueued between
+ * host reads of the device stop flag (<= 0 selects a default); it changes
+ * nothing in the result, only host/device traffic.
+ */
+typedef struct cofem_params {
+  double beta;
+  int32_t K;
+  double cg_tol;
+  int32_t cg_max_iter;
+  uint64_t seed;
+  int32_t precision;
+  int32_t stop_rule;
+  double alpha_max;
+  int32_t flags;
+  int32_t poll_interval;
+} cofem_params;
+
+/* Per-EM-iteration statistics returned by cofem_em_step (host struct). */
+typedef struct cofem_iter_stats {
+  int32_t t;           /* EM iteration index that drew the probes */
+  int32_t cg_iters;    /* CG iterations run */
+  int32_t converged;   /* 1 if the stop test was met before the cap */
+  int32_t n_clamped;   /* coordinates whose M-step denominator hit the floor */
+  double rel_resid;    /* recursive ||R||_F / ||B||_F at exit */
+  double ms;           /* wall time of this EM iteration (device events) */
+} cofem_iter_stats;
+
+typedef struct cofem_ctx cofem_ctx;
+
+/*
+ * Creates a context for `n_problems` problems (this build: n_problems == 1)
+ * with alpha = 1 (Algorithm 1, first line) and the next EM iteration t = 1.
+ * Allocates device memory for the packed dictionary and the CG state
+ * (dense: 2 packed float32 copies of Phi plus 4 D x 32 float32 blocks;
+ * conv: 5 (K) x D float32 blocks), computes beta Phi^T y, and synchronises
+ * `hip_stream` before returning.  *out receives the context.
+ */
+cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems,
+                        const cofem_params* params, void* hip_stream, cofem_ctx** out);
+
+/*
+ * Runs `n_iters` EM iterations of Algorithm 1 (E-step by CG, diagonal
+ * estimate, M-step).  Synchronises the stream at the end of every EM
+ * iteration (the host reads the CG stop flag).  `stats` (host, nullable)
+ * receives n_iters entries.
+ */
+cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats);
+
+/*
+ * Copies Algorithm 1's return triple for problem `problem`: mu and s of the
+ * last E-step and alpha after the last M-step, each into a device float32
+ * buffer of length D (each pointer nullable).  Before any EM iteration mu and
+ * s are zero.  Enqueued on the context's stream.
+ */
+cofem_status cofem_posterior(cofem_ctx* ctx, int32_t problem, float* mu, float* s, float* alpha);
+
+/* Replaces alpha of `problem` (device float32, length D, all > 0): the next
+ * E-step uses it.  Used for step-by-step comparison with a reference. */
+cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha);
+
+/* Sets the EM iteration index t (>= 0, < 65536) whose probes the next E-step draws. */
+cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t);
+
+/* n > 0: every CG solve runs exactly n iterations, ignoring cg_tol (the cap is
+ * raised to n); n == 0 restores the stop test.  For step-by-step comparisons. */
+cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n);
+
+/*
+ * Test and learned-form support: the solution block X of the last E-step.
+ * probes: device float32, D x K column-major (column k at probes + k*D);
+ * mean: device float64, length D.  Either pointer nullable.
+ */
+cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, double* mean);
+
+/*
+ * Applies A = beta Phi^T Phi + diag(alpha) of `problem` with the context's
+ * own kernels: q_probes = A v_probes (float32, D x K column-major, device)
+ * and q_mean = A v_mean (float64, length D, device).  For operator tests.
+ */
+cofem_status cofem_apply_A(cofem_ctx* ctx, int32_t problem, const float* v_probes,
+                           const double* v_mean, float* q_probes, double* q_mean);
+
+/*
+ * Writes the Rademacher probe block of EM iteration t (Sec. 3.1) for `seed`:
+ * out is device float32, D x K column-major, entries +-1.  Enqueued on
+ * hip_stream (NULL = default) and synchronised.  Needs no context.
+ */
+cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, float* out,
+                               void* hip_stream);
+
+/*
+ * Measurement support: times the operator kernels of one CG iteration in the
+ * launch configuration the solver uses, `reps` times each, with HIP events on
+ * the context's stream, applied to the current direction block.  Writes the
+ * mean duration in milliseconds of each kernel to ms_out (host, 3 entries):
+ * dense -> {pass 1 (W = Phi P), pass 2 (Q = beta Phi^T W + alpha P), 0};
+ * conv  -> {fused stencil pass, 0, 0}.  Leaves the solver state unchanged.
+ */
+cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out);
+
+/* Frees every device buffer of the context (after synchronising its stream). */
+void cofem_destroy(cofem_ctx* ctx);
+
+/* Last error message of `ctx` (or of the last failed context-less call when
+ * ctx is NULL); never NULL; valid until the next call on the same context. */
+const char* cofem_last_error(const cofem_ctx* ctx);
+
+/* Name of a status code. */
+const char* cofem_status_string(cofem_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COFEM_H_ */

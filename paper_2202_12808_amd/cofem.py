@@ -1,0 +1,290 @@
+"""ctypes binding of libcofem.so (declared in include/cofem.h).
+
+Argument marshalling only: every step of the E-step and M-step runs in the
+library's HIP kernels.  The functions keep the C names; tensors are torch
+tensors on the GPU (PyTorch is used for device memory and streams), passed by
+``data_ptr()``.  ``CoFEM`` bundles a context with the tensors it borrows.
+
+Loading fails loudly (``CofemError``) when the library has not been built:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint64, c_void_p
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcofem.so")
+
+COFEM_OK = 0
+COFEM_ERR_INVALID_ARG = 1
+COFEM_ERR_OUT_OF_MEMORY = 2
+COFEM_ERR_DEVICE = 3
+COFEM_ERR_NUMERIC = 4
+COFEM_ERR_UNSUPPORTED = 5
+
+COFEM_DENSE = 0
+COFEM_CONV2D_CIRC = 1
+COFEM_F32 = 0
+COFEM_BF16 = 1
+COFEM_PREC_FP32 = 0
+COFEM_PREC_BF16_IR = 1
+COFEM_STOP_FROBENIUS = 0
+COFEM_MAX_K = 32
+
+
+class CofemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_STATUS_NAMES = {0: "COFEM_OK", 1: "COFEM_ERR_INVALID_ARG", 2: "COFEM_ERR_OUT_OF_MEMORY",
+                 3: "COFEM_ERR_DEVICE", 4: "COFEM_ERR_NUMERIC", 5: "COFEM_ERR_UNSUPPORTED"}
+
+
+class cofem_problem(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("N", c_int64), ("D", c_int64), ("phi", c_void_p),
+                ("ld_phi", c_int64), ("phi_dtype", c_int32), ("H", c_int32), ("W", c_int32),
+                ("kh", c_int32), ("kw", c_int32), ("taps", c_void_p), ("y", c_void_p)]
+
+
+class cofem_params(ctypes.Structure):
+    _fields_ = [("beta", c_double), ("K", c_int32), ("cg_tol", c_double), ("cg_max_iter", c_int32),
+                ("seed", c_uint64), ("precision", c_int32), ("stop_rule", c_int32),
+                ("alpha_max", c_double), ("flags", c_int32), ("poll_interval", c_int32)]
+
+
+class cofem_iter_stats(ctypes.Structure):
+    _fields_ = [("t", c_int32), ("cg_iters", c_int32), ("converged", c_int32), ("n_clamped", c_int32),
+                ("rel_resid", c_double), ("ms", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGNATURES = {
+    "cofem_init": (c_int32, [POINTER(cofem_problem), c_int32, POINTER(cofem_params), c_void_p,
+                             POINTER(c_void_p)]),
+    "cofem_em_step": (c_int32, [c_void_p, c_int32, POINTER(cofem_iter_stats)]),
+    "cofem_posterior": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "cofem_set_alpha": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "cofem_set_iteration": (c_int32, [c_void_p, c_int32]),
+    "cofem_set_fixed_cg_iters": (c_int32, [c_void_p, c_int32]),
+    "cofem_get_solution": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "cofem_apply_A": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cofem_probe_signs": (c_int32, [c_uint64, c_int32, c_int32, c_int64, c_void_p, c_void_p]),
+    "cofem_time_operator": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float)]),
+    "cofem_destroy": (None, [c_void_p]),
+    "cofem_last_error": (c_char_p, [c_void_p]),
+    "cofem_status_string": (c_char_p, [c_int32]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libcofem.so (once) and declares every entry point's signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise CofemError(COFEM_ERR_UNSUPPORTED,
+                         f"{path} is missing: build it with `python -m paper_2202_12808_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status != COFEM_OK:
+        msg = load().cofem_last_error(ctx)
+        raise CofemError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+# --------------------------------------------------------- C-named wrappers
+def cofem_init(problem: cofem_problem, params: cofem_params, stream=None):
+    ctx = c_void_p()
+    _check(load().cofem_init(ctypes.byref(problem), 1, ctypes.byref(params), _stream(stream),
+                             ctypes.byref(ctx)))
+    return ctx
+
+
+def cofem_em_step(ctx, n_iters: int):
+    stats = (cofem_iter_stats * max(n_iters, 1))()
+    _check(load().cofem_em_step(ctx, n_iters, stats), ctx)
+    return [stats[i].as_dict() for i in range(n_iters)]
+
+
+def cofem_posterior(ctx, mu=None, s=None, alpha=None, problem: int = 0):
+    _check(load().cofem_posterior(ctx, problem, _ptr(mu), _ptr(s), _ptr(alpha)), ctx)
+
+
+def cofem_set_alpha(ctx, alpha, problem: int = 0):
+    _check(load().cofem_set_alpha(ctx, problem, _ptr(alpha)), ctx)
+
+
+def cofem_set_iteration(ctx, t: int):
+    _check(load().cofem_set_iteration(ctx, t), ctx)
+
+
+def cofem_set_fixed_cg_iters(ctx, n: int):
+    _check(load().cofem_set_fixed_cg_iters(ctx, n), ctx)
+
+
+def cofem_get_solution(ctx, probes=None, mean=None, problem: int = 0):
+    _check(load().cofem_get_solution(ctx, problem, _ptr(probes), _ptr(mean)), ctx)
+
+
+def cofem_apply_A(ctx, v_probes, v_mean, q_probes, q_mean, problem: int = 0):
+    _check(load().cofem_apply_A(ctx, problem, _ptr(v_probes), _ptr(v_mean), _ptr(q_probes),
+                                _ptr(q_mean)), ctx)
+
+
+def cofem_probe_signs(seed: int, t: int, K: int, D: int, out, stream=None):
+    _check(load().cofem_probe_signs(seed, t, K, D, _ptr(out), _stream(stream)))
+
+
+def cofem_time_operator(ctx, reps: int):
+    out = (ctypes.c_float * 3)()
+    _check(load().cofem_time_operator(ctx, reps, out), ctx)
+    return [float(out[i]) for i in range(3)]
+
+
+def cofem_destroy(ctx):
+    if ctx:
+        load().cofem_destroy(ctx)
+
+
+# --------------------------------------------------------- convenience object
+class CoFEM:
+    """One CoFEM problem on the current GPU.
+
+    dense:  CoFEM.dense(phi[N, D] float32 cuda, y[N] float32 cuda, beta, K, ...)
+    conv:   CoFEM.conv(taps[k, k] float32 cuda, y[H*W] float32 cuda, H, W, beta, K, ...)
+    """
+
+    def __init__(self, problem: cofem_problem, params: cofem_params, keep, device, stream=None):
+        import torch
+        self._keep = keep
+        self.device = device
+        self.D = int(problem.D)
+        self.K = int(params.K)
+        self.params = params
+        self.problem = problem
+        with torch.cuda.device(device):
+            self.ctx = cofem_init(problem, params, stream)
+
+    @staticmethod
+    def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0):
+        return cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
+                            seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=COFEM_PREC_FP32,
+                            stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max), flags=0,
+                            poll_interval=int(poll_interval))
+
+    @classmethod
+    def dense(cls, phi, y, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
+        import torch
+        if phi.dtype != torch.float32 or y.dtype != torch.float32 or not phi.is_cuda or not y.is_cuda:
+            raise CofemError(COFEM_ERR_INVALID_ARG, "phi and y must be float32 GPU tensors")
+        phi = phi.contiguous()
+        y = y.contiguous()
+        N, D = phi.shape
+        prob = cofem_problem(kind=COFEM_DENSE, N=N, D=D, phi=phi.data_ptr(), ld_phi=D,
+                             phi_dtype=COFEM_F32, H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr())
+        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (phi, y), phi.device)
+
+    @classmethod
+    def conv(cls, taps, y, H, W, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
+        import torch
+        if taps.dtype != torch.float32 or y.dtype != torch.float32 or not taps.is_cuda or not y.is_cuda:
+            raise CofemError(COFEM_ERR_INVALID_ARG, "taps and y must be float32 GPU tensors")
+        taps = taps.contiguous()
+        y = y.contiguous()
+        th, tw = taps.shape
+        prob = cofem_problem(kind=COFEM_CONV2D_CIRC, N=H * W, D=H * W, phi=None, ld_phi=0,
+                             phi_dtype=COFEM_F32, H=H, W=W, kh=th, kw=tw, taps=taps.data_ptr(),
+                             y=y.data_ptr())
+        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (taps, y), taps.device)
+
+    def em_step(self, n_iters=1):
+        return cofem_em_step(self.ctx, n_iters)
+
+    def posterior(self):
+        import torch
+        mu = torch.empty(self.D, dtype=torch.float32, device=self.device)
+        s = torch.empty_like(mu)
+        alpha = torch.empty_like(mu)
+        cofem_posterior(self.ctx, mu, s, alpha)
+        torch.cuda.synchronize(self.device)
+        return mu, s, alpha
+
+    def solution(self):
+        import torch
+        X = torch.empty((self.K, self.D), dtype=torch.float32, device=self.device)
+        m = torch.empty(self.D, dtype=torch.float64, device=self.device)
+        cofem_get_solution(self.ctx, X, m)
+        torch.cuda.synchronize(self.device)
+        return X, m
+
+    def set_alpha(self, alpha):
+        alpha = alpha.to(device=self.device, dtype=self.dtype_f32()).contiguous()
+        cofem_set_alpha(self.ctx, alpha)
+        import torch
+        torch.cuda.synchronize(self.device)
+
+    @staticmethod
+    def dtype_f32():
+        import torch
+        return torch.float32
+
+    def set_iteration(self, t):
+        cofem_set_iteration(self.ctx, t)
+
+    def set_fixed_cg_iters(self, n):
+        cofem_set_fixed_cg_iters(self.ctx, n)
+
+    def apply_A(self, v_probes, v_mean):
+        import torch
+        v_probes = v_probes.to(device=self.device, dtype=torch.float32).contiguous()
+        v_mean = v_mean.to(device=self.device, dtype=torch.float64).contiguous()
+        q = torch.empty_like(v_probes)
+        qm = torch.empty_like(v_mean)
+        cofem_apply_A(self.ctx, v_probes, v_mean, q, qm)
+        return q, qm
+
+    def time_operator(self, reps=20):
+        return cofem_time_operator(self.ctx, reps)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            cofem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

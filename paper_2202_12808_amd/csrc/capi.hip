@@ -1,0 +1,547 @@
+// Host runtime and C ABI of libcofem.so: context set-up, the EM driver of
+// Algorithm 1 (arXiv 2202.12808) and the test hooks declared in cofem.h.
+//
+// Per EM iteration t the driver enqueues: the initial-residual kernel (probes
+// drawn from the counter-based generator, R = P = B, X = 0), chunks of CG
+// iterations (operator pass(es) then the update kernel), and the fused
+// diagonal-estimate + M-step kernel.  Every kernel of a CG iteration first
+// reads the device stop flag and returns at once when the solve has finished,
+// so the host can enqueue a chunk of iterations and read the flag only at the
+// end of each chunk: the result is the same as testing after every iteration.
+#include "cofem.h"
+#include "cofem_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace cofem;
+
+struct cofem_ctx {
+  int kind = COFEM_DENSE;
+  int64_t N = 0, D = 0;
+  int K = 0, KP = 0;
+  double beta = 1.0, tol = 1e-5, alpha_max = 1e10;
+  int U = 400;
+  uint64_t seed = 0;
+  int poll = 8;
+  int t_next = 1;
+  int fixed_iters = 0;
+  int prev_iters = 0;
+  bool has_solution = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  DenseDims dd{};
+  ConvDims cd{};
+  std::vector<void*> allocs;
+  // dictionary
+  float* phiA = nullptr;
+  float* phiB = nullptr;
+  float* taps = nullptr;
+  // solve state
+  double* b0 = nullptr;
+  float* alpha = nullptr;
+  float *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
+  double *xm = nullptr, *rm = nullptr, *pm = nullptr, *qm = nullptr;
+  // scratch for apply_A
+  float *Vs = nullptr, *Qs = nullptr;
+  double *Vsm = nullptr, *Qsm = nullptr;
+  // dense GEMM intermediates
+  float* W = nullptr;
+  double* wm = nullptr;
+  // reduction workspaces (tree partials and their self-resetting counters)
+  double *parts_init = nullptr, *parts_upd = nullptr, *parts_pass = nullptr;
+  uint32_t *cnts_init = nullptr, *cnts_upd = nullptr, *cnts_pass = nullptr;
+  ConvReduce red_init{}, red_upd{}, red_pass{};
+  CgScalars* st = nullptr;
+  CgScalars* host_st = nullptr;  // pinned
+  // outputs of the last E-step / M-step
+  float *mu = nullptr, *sdiag = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+cofem_status fail(cofem_ctx* c, cofem_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define COFEM_HIP(ctx, call)                                                                  \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? COFEM_ERR_OUT_OF_MEMORY : COFEM_ERR_DEVICE, \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+template <typename T>
+cofem_status alloc(cofem_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = (count == 0 ? 1 : count) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, e == hipErrorOutOfMemory ? COFEM_ERR_OUT_OF_MEMORY : COFEM_ERR_DEVICE,
+                "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  }
+  c->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  e = hipMemsetAsync(q, 0, bytes, c->stream);
+  if (e != hipSuccess) return fail(c, COFEM_ERR_DEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+  return COFEM_OK;
+}
+
+#define COFEM_TRY(expr)              \
+  do {                               \
+    cofem_status s_ = (expr);        \
+    if (s_ != COFEM_OK) return s_;   \
+  } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+void destroy_ctx(cofem_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->host_st) (void)hipHostFree(c->host_st);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+// Writes the solver controls (cap, tolerance, sizes) into the device scalars.
+cofem_status push_controls(cofem_ctx* c) {
+  CgScalars h;
+  memset(&h, 0, sizeof(h));
+  h.tol = c->tol;
+  h.limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
+  h.fixed = c->fixed_iters > 0 ? 1 : 0;
+  h.kp = c->KP;
+  h.k = c->K;
+  h.stop = 1;
+  COFEM_HIP(c, hipMemcpyAsync(c->st, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+  COFEM_HIP(c, hipStreamSynchronize(c->stream));
+  return COFEM_OK;
+}
+
+// Tree-reduction workspace for a grid of nblk blocks with ncols values each.
+cofem_status alloc_tree(cofem_ctx* c, double** parts, uint32_t** cnts, int64_t nblk, int ncols,
+                        int regions = 1) {
+  COFEM_TRY(alloc(c, parts, (size_t)(tree_rows(nblk) * ncols * regions)));
+  COFEM_TRY(alloc(c, cnts, (size_t)(tree_counters(nblk) * regions)));
+  return COFEM_OK;
+}
+
+cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
+  DenseDims& dd = c->dd;
+  dd.N = p.N;
+  dd.D = p.D;
+  dd.Np = round_up(p.N, 64);
+  dd.Dp = round_up(p.D, 64);
+  dd.waves1 = dense_pass_waves(dd.Np / 16);
+  dd.waves2 = dense_pass_waves(dd.Dp / 16);
+  c->KP = kDenseKP;
+
+  const size_t blk = (size_t)dd.Dp * kDenseKP;
+  COFEM_TRY(alloc(c, &c->phiA, (size_t)dd.Np * dd.Dp));
+  COFEM_TRY(alloc(c, &c->phiB, (size_t)dd.Np * dd.Dp));
+  COFEM_TRY(alloc(c, &c->b0, dd.Dp));
+  COFEM_TRY(alloc(c, &c->alpha, dd.Dp));
+  COFEM_TRY(alloc(c, &c->mu, dd.Dp));
+  COFEM_TRY(alloc(c, &c->sdiag, dd.Dp));
+  COFEM_TRY(alloc(c, &c->X, blk));
+  COFEM_TRY(alloc(c, &c->R, blk));
+  COFEM_TRY(alloc(c, &c->P, blk));
+  COFEM_TRY(alloc(c, &c->Q, blk));
+  COFEM_TRY(alloc(c, &c->Vs, blk));
+  COFEM_TRY(alloc(c, &c->Qs, blk));
+  COFEM_TRY(alloc(c, &c->xm, dd.Dp));
+  COFEM_TRY(alloc(c, &c->rm, dd.Dp));
+  COFEM_TRY(alloc(c, &c->pm, dd.Dp));
+  COFEM_TRY(alloc(c, &c->qm, dd.Dp));
+  COFEM_TRY(alloc(c, &c->Vsm, dd.Dp));
+  COFEM_TRY(alloc(c, &c->Qsm, dd.Dp));
+  COFEM_TRY(alloc(c, &c->W, (size_t)dd.Np * kDenseKP));
+  COFEM_TRY(alloc(c, &c->wm, dd.Np));
+  const int64_t nupd = dense_update_blocks(dd);
+  COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, kDenseKP + 1));
+  COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, kDenseKP + 1));
+  COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 16, 3 * (kDenseKP + 1)));
+
+  COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
+  COFEM_HIP(c, dense_b0(static_cast<const float*>(p.phi), p.ld_phi, p.y, c->beta, dd, c->b0, c->stream));
+  COFEM_HIP(c, fill_f32(c->alpha, 1.0f, dd.Dp, c->stream));
+  return COFEM_OK;
+}
+
+cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
+  ConvDims& cd = c->cd;
+  cd.H = p.H;
+  cd.W = p.W;
+  cd.ks = p.kh;
+  cd.D = (int64_t)p.H * p.W;
+  cd.ldD = round_up(cd.D, 256);
+  cd.K = c->K;
+  cd.tilesX = (p.W + 31) / 32;
+  cd.tilesY = (p.H + 31) / 32;
+  c->KP = c->K;
+  const size_t blk = (size_t)cd.ldD * c->K;
+  COFEM_TRY(alloc(c, &c->taps, (size_t)p.kh * p.kw));
+  COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
+                              c->stream));
+  COFEM_TRY(alloc(c, &c->b0, cd.ldD));
+  COFEM_TRY(alloc(c, &c->alpha, cd.ldD));
+  COFEM_TRY(alloc(c, &c->mu, cd.ldD));
+  COFEM_TRY(alloc(c, &c->sdiag, cd.ldD));
+  COFEM_TRY(alloc(c, &c->X, blk));
+  COFEM_TRY(alloc(c, &c->R, blk));
+  COFEM_TRY(alloc(c, &c->P, blk));
+  COFEM_TRY(alloc(c, &c->Q, blk));
+  COFEM_TRY(alloc(c, &c->Vs, blk));
+  COFEM_TRY(alloc(c, &c->Qs, blk));
+  COFEM_TRY(alloc(c, &c->xm, cd.ldD));
+  COFEM_TRY(alloc(c, &c->rm, cd.ldD));
+  COFEM_TRY(alloc(c, &c->pm, cd.ldD));
+  COFEM_TRY(alloc(c, &c->qm, cd.ldD));
+  COFEM_TRY(alloc(c, &c->Vsm, cd.ldD));
+  COFEM_TRY(alloc(c, &c->Qsm, cd.ldD));
+  const int ncols = c->K + 1;
+  const int64_t nupd = conv_update_blocks(cd), ntiles = (int64_t)cd.tilesX * cd.tilesY;
+  ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
+  const int64_t nblks[3] = {nupd, nupd, ntiles};
+  const int nvs[3] = {1, 1, 3};
+  for (int i = 0; i < 3; ++i) {
+    COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], nvs[i], ncols));
+    COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * 3));
+    COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
+  }
+  COFEM_HIP(c, conv_b0(cd, c->taps, p.y, c->beta, c->b0, c->stream));
+  COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
+  return COFEM_OK;
+}
+
+cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, std::string* why) {
+  if (!p || !q) return *why = "null problem or params", COFEM_ERR_INVALID_ARG;
+  if (n != 1) {
+    *why = "n_problems must be 1 in this build";
+    return n < 1 ? COFEM_ERR_INVALID_ARG : COFEM_ERR_UNSUPPORTED;
+  }
+  if (!(q->beta > 0.0) || !isfinite(q->beta)) return *why = "beta must be positive and finite", COFEM_ERR_INVALID_ARG;
+  if (q->K < 1 || q->K > COFEM_MAX_K) return *why = "K must be in [1, 32]", COFEM_ERR_INVALID_ARG;
+  if (!(q->cg_tol >= 0.0) || !isfinite(q->cg_tol)) return *why = "cg_tol must be >= 0", COFEM_ERR_INVALID_ARG;
+  if (q->cg_max_iter < 0) return *why = "cg_max_iter must be >= 0", COFEM_ERR_INVALID_ARG;
+  if (q->precision != COFEM_PREC_FP32) return *why = "only COFEM_PREC_FP32 is built", COFEM_ERR_UNSUPPORTED;
+  if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
+  if (!p->y) return *why = "y is null", COFEM_ERR_INVALID_ARG;
+  if (p->kind == COFEM_DENSE) {
+    if (p->N < 1 || p->D < 1) return *why = "N and D must be >= 1", COFEM_ERR_INVALID_ARG;
+    if (!p->phi) return *why = "phi is null", COFEM_ERR_INVALID_ARG;
+    if (p->ld_phi < p->D) return *why = "ld_phi < D", COFEM_ERR_INVALID_ARG;
+    if (p->phi_dtype != COFEM_F32) return *why = "only float32 Phi is built", COFEM_ERR_UNSUPPORTED;
+    if (p->N > (int64_t)1 << 30 || p->D > (int64_t)1 << 30) return *why = "N or D too large", COFEM_ERR_INVALID_ARG;
+  } else if (p->kind == COFEM_CONV2D_CIRC) {
+    if (p->H < 1 || p->W < 1) return *why = "H and W must be >= 1", COFEM_ERR_INVALID_ARG;
+    if (!p->taps) return *why = "taps is null", COFEM_ERR_INVALID_ARG;
+    if (p->kh != p->kw) return *why = "only square kernels are built", COFEM_ERR_UNSUPPORTED;
+    if (p->kh < 1 || p->kh > 9 || p->kh % 2 == 0) return *why = "kernel side must be odd, 1..9", COFEM_ERR_INVALID_ARG;
+    if (p->N != (int64_t)p->H * p->W || p->D != p->N) return *why = "conv needs N == D == H*W", COFEM_ERR_INVALID_ARG;
+    if ((int64_t)p->H * p->W > (int64_t)1 << 30) return *why = "image too large", COFEM_ERR_INVALID_ARG;
+  } else {
+    return *why = "unknown dictionary kind", COFEM_ERR_INVALID_ARG;
+  }
+  return COFEM_OK;
+}
+
+cofem_status run_cg_iterations(cofem_ctx* c, int n) {
+  for (int i = 0; i < n; ++i) {
+    if (c->kind == COFEM_DENSE) {
+      COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->W, c->wm, c->st, 0, c->stream));
+      COFEM_HIP(c, dense_pass2(c->dd, c->phiB, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
+                               c->Q, c->qm, c->parts_pass, c->cnts_pass, c->st, 0, c->stream));
+      COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
+                                c->cnts_upd, c->st, c->stream));
+    } else {
+      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->P, c->pm, c->R, c->rm, c->alpha, c->beta, c->Q, c->qm,
+                             c->red_pass, c->st, 0, c->stream));
+      COFEM_HIP(c, conv_update(c->cd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->red_upd,
+                               c->st, c->stream));
+    }
+  }
+  return COFEM_OK;
+}
+
+cofem_status read_state(cofem_ctx* c) {
+  COFEM_HIP(c, hipMemcpyAsync(c->host_st, c->st, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+  COFEM_HIP(c, hipStreamSynchronize(c->stream));
+  return COFEM_OK;
+}
+
+cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
+  const int t = c->t_next;
+  COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  if (c->kind == COFEM_DENSE)
+    COFEM_HIP(c, dense_init(c->dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm,
+                            c->parts_init, c->cnts_init, c->st, c->stream));
+  else
+    COFEM_HIP(c, conv_init(c->cd, c->seed, t, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->red_init,
+                           c->st, c->stream));
+  const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
+  // First chunk: the previous solve's count (CG counts drift slowly across EM
+  // iterations), then `poll`-sized chunks until the device flag says stop.
+  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 : c->poll;
+  if (chunk > limit) chunk = limit;
+  int enqueued = 0;
+  for (;;) {
+    if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk));
+    enqueued += chunk;
+    COFEM_TRY(read_state(c));
+    if (c->host_st->stop) break;
+    if (enqueued > limit + 2)
+      return fail(c, COFEM_ERR_DEVICE, "CG did not report completion after the iteration cap");
+    chunk = c->poll;
+    if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
+  }
+  if (c->host_st->numeric_error)
+    return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
+  if (c->kind == COFEM_DENSE)
+    COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
+                             c->sdiag, c->st, c->stream));
+  else
+    COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->X, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
+                            c->st, c->stream));
+  COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  COFEM_TRY(read_state(c));
+  c->has_solution = true;
+  c->prev_iters = c->host_st->iter;
+  c->t_next = t + 1;
+  if (out) {
+    float ms = 0.0f;
+    COFEM_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    out->t = t;
+    out->cg_iters = c->host_st->iter;
+    out->converged = c->host_st->ratio < c->tol ? 1 : 0;
+    out->n_clamped = c->host_st->n_clamped;
+    out->rel_resid = c->host_st->ratio;
+    out->ms = ms;
+  }
+  return COFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const cofem_params* params,
+                        void* hip_stream, cofem_ctx** out) {
+  if (!out) return fail(nullptr, COFEM_ERR_INVALID_ARG, "out is null");
+  std::string why;
+  cofem_status v = validate(problems, n_problems, params, &why);
+  if (v != COFEM_OK) return fail(nullptr, v, why);
+  cofem_ctx* c = new (std::nothrow) cofem_ctx();
+  if (!c) return fail(nullptr, COFEM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  const cofem_problem& p = problems[0];
+  c->kind = p.kind;
+  c->N = p.N;
+  c->D = p.D;
+  c->K = params->K;
+  c->beta = params->beta;
+  c->tol = params->cg_tol;
+  c->U = params->cg_max_iter;
+  c->seed = params->seed;
+  c->alpha_max = params->alpha_max > 0.0 ? params->alpha_max : 1e10;
+  c->poll = params->poll_interval > 0 ? params->poll_interval : 8;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  cofem_status s = COFEM_OK;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->host_st), sizeof(CgScalars));
+  if (e != hipSuccess) {
+    s = fail(c, COFEM_ERR_DEVICE, std::string("HIP set-up: ") + hipGetErrorString(e));
+  }
+  if (s == COFEM_OK) s = alloc(c, &c->st, 1);
+  if (s == COFEM_OK) s = (p.kind == COFEM_DENSE) ? init_dense(c, p) : init_conv(c, p);
+  if (s == COFEM_OK) s = push_controls(c);
+  if (s == COFEM_OK) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = fail(c, COFEM_ERR_DEVICE, std::string("init: ") + hipGetErrorString(e));
+  }
+  if (s != COFEM_OK) {
+    g_err = c->err;
+    destroy_ctx(c);
+    return s;
+  }
+  *out = c;
+  return COFEM_OK;
+}
+
+cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (n_iters < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "n_iters < 0");
+  for (int i = 0; i < n_iters; ++i) {
+    if (ctx->t_next >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
+    COFEM_TRY(em_iteration(ctx, stats ? &stats[i] : nullptr));
+  }
+  return COFEM_OK;
+}
+
+cofem_status cofem_posterior(cofem_ctx* ctx, int32_t problem, float* mu, float* s, float* alpha) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  const size_t bytes = sizeof(float) * (size_t)ctx->D;
+  if (mu) COFEM_HIP(ctx, hipMemcpyAsync(mu, ctx->mu, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (s) COFEM_HIP(ctx, hipMemcpyAsync(s, ctx->sdiag, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (alpha) COFEM_HIP(ctx, hipMemcpyAsync(alpha, ctx->alpha, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  if (!alpha) return fail(ctx, COFEM_ERR_INVALID_ARG, "alpha is null");
+  COFEM_HIP(ctx, hipMemcpyAsync(ctx->alpha, alpha, sizeof(float) * (size_t)ctx->D, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (t < 0 || t >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "t must be in [0, 65535]");
+  ctx->t_next = t;
+  return COFEM_OK;
+}
+
+cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (n < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "n must be >= 0");
+  ctx->fixed_iters = n;
+  ctx->prev_iters = n;
+  return push_controls(ctx);
+}
+
+cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, double* mean) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  if (probes) {
+    if (ctx->kind == COFEM_DENSE) {
+      COFEM_HIP(ctx, dense_to_colmajor(ctx->dd, ctx->K, ctx->X, probes, ctx->stream));
+    } else {
+      COFEM_HIP(ctx, hipMemcpy2DAsync(probes, sizeof(float) * ctx->D, ctx->X, sizeof(float) * ctx->cd.ldD,
+                                      sizeof(float) * ctx->D, ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+  }
+  if (mean)
+    COFEM_HIP(ctx, hipMemcpyAsync(mean, ctx->xm, sizeof(double) * (size_t)ctx->D, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_apply_A(cofem_ctx* ctx, int32_t problem, const float* v_probes, const double* v_mean,
+                           float* q_probes, double* q_mean) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  if (!v_probes || !v_mean || !q_probes || !q_mean) return fail(ctx, COFEM_ERR_INVALID_ARG, "null vector");
+  const size_t Dm = sizeof(double) * (size_t)ctx->D;
+  if (ctx->kind == COFEM_DENSE) {
+    const DenseDims& dd = ctx->dd;
+    COFEM_HIP(ctx, dense_from_colmajor(dd, ctx->K, v_probes, ctx->Vs, ctx->stream));
+    COFEM_HIP(ctx, hipMemsetAsync(ctx->Vsm, 0, sizeof(double) * dd.Dp, ctx->stream));
+    COFEM_HIP(ctx, hipMemcpyAsync(ctx->Vsm, v_mean, Dm, hipMemcpyDeviceToDevice, ctx->stream));
+    COFEM_HIP(ctx, dense_pass1(dd, ctx->phiA, ctx->Vs, ctx->Vsm, ctx->W, ctx->wm, ctx->st, 1, ctx->stream));
+    COFEM_HIP(ctx, dense_pass2(dd, ctx->phiB, ctx->W, ctx->wm, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm,
+                               ctx->alpha, ctx->beta, ctx->Qs, ctx->Qsm, ctx->parts_pass, ctx->cnts_pass,
+                               ctx->st, 1, ctx->stream));
+    COFEM_HIP(ctx, dense_to_colmajor(dd, ctx->K, ctx->Qs, q_probes, ctx->stream));
+  } else {
+    const ConvDims& cd = ctx->cd;
+    COFEM_HIP(ctx, hipMemcpy2DAsync(ctx->Vs, sizeof(float) * cd.ldD, v_probes, sizeof(float) * ctx->D,
+                                    sizeof(float) * ctx->D, ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+    COFEM_HIP(ctx, hipMemcpyAsync(ctx->Vsm, v_mean, Dm, hipMemcpyDeviceToDevice, ctx->stream));
+    COFEM_HIP(ctx, conv_pass(cd, ctx->taps, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm, ctx->alpha, ctx->beta,
+                             ctx->Qs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream));
+    COFEM_HIP(ctx, hipMemcpy2DAsync(q_probes, sizeof(float) * ctx->D, ctx->Qs, sizeof(float) * cd.ldD,
+                                    sizeof(float) * ctx->D, ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  COFEM_HIP(ctx, hipMemcpyAsync(q_mean, ctx->Qsm, Dm, hipMemcpyDeviceToDevice, ctx->stream));
+  COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, float* out, void* hip_stream) {
+  if (!out) return fail(nullptr, COFEM_ERR_INVALID_ARG, "out is null");
+  if (t < 0 || t >= (1 << 16) || K < 0 || K > (1 << 16) || D < 0 || D >= ((int64_t)1 << 38))
+    return fail(nullptr, COFEM_ERR_INVALID_ARG, "probe index out of range");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = probe_signs_colmajor(seed, t, K, D, out, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(nullptr, COFEM_ERR_DEVICE, std::string("probe kernel: ") + hipGetErrorString(e));
+  return COFEM_OK;
+}
+
+cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (reps < 1 || !ms_out) return fail(ctx, COFEM_ERR_INVALID_ARG, "reps < 1 or ms_out null");
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int r = 0; r < reps; ++r) {
+    float ms = 0.f;
+    if (ctx->kind == COFEM_DENSE) {
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+      COFEM_HIP(ctx, dense_pass1(ctx->dd, ctx->phiA, ctx->P, ctx->pm, ctx->W, ctx->wm, ctx->st, 1,
+                                 ctx->stream));
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
+      COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      acc[0] += ms;
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+      COFEM_HIP(ctx, dense_pass2(ctx->dd, ctx->phiB, ctx->W, ctx->wm, ctx->P, ctx->pm, ctx->R, ctx->rm,
+                                 ctx->alpha, ctx->beta, ctx->Qs, ctx->Qsm, ctx->parts_pass, ctx->cnts_pass,
+                                 ctx->st, 1, ctx->stream));
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
+      COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      acc[1] += ms;
+    } else {
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+      COFEM_HIP(ctx, conv_pass(ctx->cd, ctx->taps, ctx->P, ctx->pm, ctx->R, ctx->rm, ctx->alpha, ctx->beta,
+                               ctx->Qs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream));
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
+      COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+      acc[0] += ms;
+    }
+  }
+  for (int i = 0; i < 3; ++i) ms_out[i] = acc[i] / (float)reps;
+  return COFEM_OK;
+}
+
+void cofem_destroy(cofem_ctx* ctx) { destroy_ctx(ctx); }
+
+const char* cofem_last_error(const cofem_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_err.c_str();
+}
+
+const char* cofem_status_string(cofem_status s) {
+  switch (s) {
+    case COFEM_OK: return "COFEM_OK";
+    case COFEM_ERR_INVALID_ARG: return "COFEM_ERR_INVALID_ARG";
+    case COFEM_ERR_OUT_OF_MEMORY: return "COFEM_ERR_OUT_OF_MEMORY";
+    case COFEM_ERR_DEVICE: return "COFEM_ERR_DEVICE";
+    case COFEM_ERR_NUMERIC: return "COFEM_ERR_NUMERIC";
+    case COFEM_ERR_UNSUPPORTED: return "COFEM_ERR_UNSUPPORTED";
+  }
+  return "COFEM_UNKNOWN_STATUS";
+}
+
+}  // extern "C"

@@ -1,0 +1,371 @@
+// Internal declarations shared by the HIP translation units of libcofem.so.
+//
+// Device-side CG state.  Columns are numbered 0..KP-1 for probe slots
+// (slots >= K hold zeros and stay zero) and KP for the mean column
+// (beta Phi^T y, Eq. 7).  Probe columns are float32; the mean column is kept in
+// float64 end to end, because its error is amplified by the conditioning of A
+// (its right-hand side lies in the large-eigenvalue subspace of A while
+// float32 rounding leaks into the alpha-sized directions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cofem {
+
+constexpr int kMaxCols = 64;     // KP + 1 <= kMaxCols
+constexpr int kThreads = 256;    // every kernel uses 256-thread blocks (4 wave64)
+constexpr int kWaves = 4;
+constexpr int kDenseKP = 32;     // dense probe block width (two 16-column MFMA blocks)
+
+struct CgScalars {
+  double rho[kMaxCols];   // ||r_c||^2 of the current residual
+  double gam[kMaxCols];   // p_c^T A p_c
+  double del[kMaxCols];   // r_c^T A p_c
+  double eta[kMaxCols];   // ||A p_c||^2
+  double a[kMaxCols];     // step lengths
+  double b[kMaxCols];     // direction-update coefficients
+  double nB;              // ||B||_F
+  double ratio;           // sqrt(sum rho) / nB
+  double tol;
+  int32_t iter;           // CG iterations done in this solve
+  int32_t stop;           // 1 once the solve is finished (kernels then no-op)
+  int32_t limit;          // iteration cap
+  int32_t fixed;          // 1: ignore tol, run exactly `limit` iterations
+  int32_t kp;             // probe slots; mean column index
+  int32_t k;              // real probes
+  int32_t n_clamped;      // M-step floor hits of the last M-step
+  int32_t numeric_error;  // set when a CG scalar is not finite
+  uint32_t counter[4];    // last-block tickets (self-resetting)
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Rademacher sign of probe k, coordinate j, EM iteration t: bit (j & 63) of
+// SplitMix64 output number (t<<48 | k<<32 | j>>6) + 1 for `seed`; 0 -> +1.
+__device__ __forceinline__ float probe_sign(uint64_t seed, uint32_t t, uint32_t k, uint64_t j) {
+  const uint64_t idx = ((uint64_t)t << 48) | ((uint64_t)k << 32) | (j >> 6);
+  const uint64_t w = splitmix64_mix(seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
+  return ((w >> (j & 63)) & 1ull) ? -1.0f : 1.0f;
+}
+
+template <typename T>
+__device__ __forceinline__ T load_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide "am I the last block to finish" ticket on `counter` (which the
+// caller's last block resets to zero).  Every value another block will read
+// must have been written with store_agent (an agent-coherent write-through
+// store) and is read back with load_agent (an agent-coherent load).  Each
+// thread waits for its own stores to complete before the barrier, so the
+// ticket increment is ordered after all of the block's partials without a
+// device-wide cache write-back per block.
+__device__ __forceinline__ bool last_block_ticket(uint32_t* counter, uint32_t total) {
+  __shared__ bool s_last;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == total - 1u);
+  }
+  __syncthreads();
+  return s_last;
+}
+
+// Sum of v over the block (blockDim.x a multiple of 64, at most 512 threads);
+// result valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double* sh /* >= 8 doubles */) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int w = 0; w < nw; ++w) r += sh[w];
+  return r;
+}
+
+// Deterministic last-block total out_sh[c] = sum_b part[b * ncols + c] over
+// b < nblk, c < ncols (ncols <= blockDim.x); loads are issued eight at a time.
+__device__ __forceinline__ void total_partials(const double* part, int nblk, int ncols,
+                                               double* out_sh) {
+  __shared__ double red[512];
+  const int nt = blockDim.x;
+  const int tpc = nt / ncols;
+  const int c = threadIdx.x / tpc, j = threadIdx.x - c * tpc;
+  double v = 0.0;
+  if (c < ncols) {
+    int b = j;
+    for (; b + 7 * tpc < nblk; b += 8 * tpc) {
+      double t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = load_agent(&part[(int64_t)(b + i * tpc) * ncols + c]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v += t[i];
+    }
+    for (; b < nblk; b += tpc) v += load_agent(&part[(int64_t)b * ncols + c]);
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < ncols) {
+    double s = 0.0;
+    for (int i = 0; i < tpc; ++i) s += red[threadIdx.x * tpc + i];
+    out_sh[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Deterministic tree reduction of per-block partial vectors across a grid.
+// Every block calls it with its own ncols values in shared memory (`mine`,
+// ncols <= blockDim.x); blocks are grouped 32 at a time per level, and the last
+// block of each group sums the group (in index order) and moves up a level.
+// Returns true in the single block that ends with the totals in `out_sh`.
+// `parts` holds tree_rows(nblk) rows of ncols doubles and `cnts`
+// tree_counters(nblk) zero-initialised counters (left zero on exit).
+__host__ __device__ __forceinline__ int64_t tree_rows(int64_t n) {
+  int64_t rows = n;
+  while (n > 1) {
+    n = (n + 31) / 32;
+    rows += n;
+  }
+  return rows;
+}
+__host__ __device__ __forceinline__ int64_t tree_counters(int64_t n) {
+  int64_t c = 0;
+  while (n > 1) {
+    n = (n + 31) / 32;
+    c += n;
+  }
+  return c < 1 ? 1 : c;
+}
+
+__device__ __forceinline__ bool tree_reduce(double* parts, uint32_t* cnts, int64_t blk, int64_t nblk,
+                                            int ncols, const double* mine, double* out_sh) {
+  const int tid = threadIdx.x;
+  if (nblk == 1) {
+    if (tid < ncols) out_sh[tid] = mine[tid];
+    __syncthreads();
+    return true;
+  }
+  if (tid < ncols) store_agent(&parts[blk * ncols + tid], mine[tid]);
+  int64_t idx = blk, n = nblk;
+  double* p = parts;
+  uint32_t* c = cnts;
+  for (;;) {
+    const int64_t g = idx / 32;
+    const int64_t base = g * 32;
+    const int gs = (int)((n - base) < 32 ? (n - base) : 32);
+    if (!last_block_ticket(&c[g], (uint32_t)gs)) return false;
+    double v = 0.0;
+    if (tid < ncols) {
+      for (int i0 = 0; i0 < gs; i0 += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          t[u] = (i0 + u < gs) ? load_agent(&p[(base + i0 + u) * ncols + tid]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
+      }
+    }
+    if (tid == 0) store_agent(&c[g], 0u);
+    const int64_t ng = (n + 31) / 32;
+    if (ng == 1) {
+      if (tid < ncols) out_sh[tid] = v;
+      __syncthreads();
+      return true;
+    }
+    double* pn = p + n * ncols;
+    if (tid < ncols) store_agent(&pn[g * ncols + tid], v);
+    c += ng;
+    p = pn;
+    idx = g;
+    n = ng;
+  }
+}
+
+// Column-wise variant for grids of (block, column) pairs: block `blk` of
+// column `col` holds nv values (`mine`).  Each column's blocks are summed by
+// their own tree (parts/cnts regions of tree_rows(nblk)*nv doubles and
+// tree_counters(nblk) counters per column); the block finishing a column
+// stores the column's nv totals in colsum and takes a ticket on cnt_cols.
+// The last of those returns true with every total in out_sh[v * ncols + col].
+__device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts, double* colsum,
+                                                   uint32_t* cnt_cols, int64_t blk, int64_t nblk,
+                                                   int col, int ncols, int nv, const double* mine,
+                                                   double* out_sh) {
+  __shared__ double coltot[8];
+  double* p = parts + (int64_t)col * tree_rows(nblk) * nv;
+  uint32_t* c = cnts + (int64_t)col * tree_counters(nblk);
+  if (!tree_reduce(p, c, blk, nblk, nv, mine, coltot)) return false;
+  if (threadIdx.x < nv) store_agent(&colsum[col * nv + threadIdx.x], coltot[threadIdx.x]);
+  if (!last_block_ticket(cnt_cols, (uint32_t)ncols)) return false;
+  for (int e = threadIdx.x; e < ncols * nv; e += blockDim.x) {
+    const int cc = e / nv, v = e - (e / nv) * nv;
+    out_sh[v * ncols + cc] = load_agent(&colsum[e]);
+  }
+  if (threadIdx.x == 0) store_agent(cnt_cols, 0u);
+  __syncthreads();
+  return true;
+}
+
+// Finishes a CG update: called by the last block, all threads, after the new
+// ||r_c||^2 is in shared memory for every column 0..kp.  Applies the stop test
+// of the solve (joint Frobenius ratio of the recursive residual, or the cap).
+__device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho) {
+  if (threadIdx.x == 0) {
+    const int nc = st->kp + 1;
+    double sum = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      st->rho[c] = new_rho[c];
+      sum += new_rho[c];
+    }
+    const bool finite = isfinite(sum);
+    if (!finite) st->numeric_error = 1;
+    const double ratio = st->nB > 0.0 ? sqrt(sum) / st->nB : 0.0;
+    st->ratio = ratio;
+    const int it = st->iter + 1;
+    st->iter = it;
+    st->stop = (it >= st->limit) || (!st->fixed && ratio < st->tol) || !finite;
+  }
+}
+
+// Finishes a step-length computation from the three dot products of the
+// operator pass (gam = p^T q, del = r^T q, eta = q^T q, each kp+1 entries in
+// shared memory, laid out gam | del | eta):
+//   a_c = rho_c / gam_c, and the direction-update coefficient
+//   b_c = ||r_c - a_c q_c||^2 / rho_c = (rho_c - 2 a_c del_c + a_c^2 eta_c) / rho_c
+// (the same value Hestenes-Stiefel CG forms after the residual update; known
+// here one kernel earlier so the update kernel can also form p <- r + b p).
+__device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
+  if (threadIdx.x == 0) {
+    const int nc = st->kp + 1;
+    bool finite = true;
+    for (int c = 0; c < nc; ++c) {
+      const double g = dots[c], dl = dots[nc + c], et = dots[2 * nc + c];
+      const double rho = st->rho[c];
+      const double a = (g != 0.0) ? rho / g : 0.0;
+      st->gam[c] = g;
+      st->del[c] = dl;
+      st->eta[c] = et;
+      st->a[c] = a;
+      double rn = rho - 2.0 * a * dl + a * a * et;
+      if (rn < 0.0) rn = 0.0;
+      st->b[c] = (rho != 0.0) ? rn / rho : 0.0;
+      finite = finite && isfinite(g) && isfinite(dl) && isfinite(et);
+    }
+    if (!finite) {
+      st->numeric_error = 1;
+      st->stop = 1;
+    }
+  }
+}
+
+// Finishes the initial residual R = B: rho_c = ||b_c||^2 (in shared memory).
+__device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
+  if (threadIdx.x == 0) {
+    const int nc = st->kp + 1;
+    double sum = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      st->rho[c] = rho[c];
+      st->b[c] = 0.0;
+      st->a[c] = 0.0;
+      sum += rho[c];
+    }
+    st->nB = sqrt(sum);
+    st->ratio = sum > 0.0 ? 1.0 : 0.0;
+    st->iter = 0;
+    st->n_clamped = 0;
+    st->numeric_error = isfinite(sum) ? 0 : 1;
+    st->stop = (sum == 0.0) || (st->limit <= 0) || (!st->fixed && st->ratio < st->tol) ||
+               !isfinite(sum);
+  }
+}
+
+// ------------------------------------------------------------ host launchers
+// Dense problem geometry.  Np and Dp are N and D padded to multiples of 64.
+// Probe-column state uses the blocked-4 layout: element (d, c) of a Dp x 32
+// block lives at (d / 4) * 128 + c * 4 + d % 4, so four consecutive
+// coordinates of one column form a float4 (the MFMA B-operand and C-result
+// shape of v_mfma_f32_16x16x4f32).
+struct DenseDims {
+  int64_t N, D, Np, Dp;
+  int waves1, waves2;  // waves per workgroup of pass 1 / pass 2
+};
+
+__host__ __device__ __forceinline__ int64_t blk4(int64_t d, int c) {
+  return (d >> 2) * 128 + c * 4 + (d & 3);
+}
+
+hipError_t dense_pack(const float* phi, int64_t ld, const DenseDims& dd, float* phiA, float* phiB,
+                      hipStream_t s);
+hipError_t dense_b0(const float* phi, int64_t ld, const float* y, double beta, const DenseDims& dd,
+                    double* b0, hipStream_t s);
+hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
+                      float* X, float* R, float* P, double* xm, double* rm, double* pm,
+                      double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s);
+hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, const double* pm,
+                       float* W, double* wm, CgScalars* st, int apply_only, hipStream_t s);
+hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, const double* wm,
+                       const float* P, const double* pm, const float* R, const double* rm,
+                       const float* alpha, double beta, float* Q, double* qm, double* gpart,
+                       uint32_t* counter, CgScalars* st, int apply_only, hipStream_t s);
+hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
+                        double* xm, double* rm, double* pm, const double* qm, double* parts,
+                        uint32_t* cnts, CgScalars* st, hipStream_t s);
+int dense_pass_waves(int64_t tiles);
+hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,
+                       const double* xm, float* alpha, double alpha_max, float* mu, float* sdiag,
+                       CgScalars* st, hipStream_t s);
+hipError_t dense_to_colmajor(const DenseDims& dd, int K, const float* Xb, float* out, hipStream_t s);
+hipError_t dense_from_colmajor(const DenseDims& dd, int K, const float* in, float* Xb, hipStream_t s);
+int dense_update_blocks(const DenseDims& dd);
+
+struct ConvDims {
+  int H, W, ks;      // square odd kernel side
+  int64_t D, ldD;    // D = H*W, ldD = D rounded up to 256
+  int K;             // probe columns (column-major blocks of ldD floats)
+  int tilesX, tilesY;
+};
+
+hipError_t conv_b0(const ConvDims& cd, const float* taps, const float* y, double beta, double* b0,
+                   hipStream_t s);
+// Reduction workspace of the conv kernels (one region per column).
+struct ConvReduce {
+  double* parts;      // (K+1) regions of tree_rows(nblk) * nv doubles
+  uint32_t* cnts;     // (K+1) regions of tree_counters(nblk)
+  double* colsum;     // (K+1) * 3 doubles
+  uint32_t* cnt_cols; // 1 counter
+};
+
+hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, float* X, float* R,
+                     float* P, double* xm, double* rm, double* pm, const ConvReduce& red,
+                     CgScalars* st, hipStream_t s);
+hipError_t conv_pass(const ConvDims& cd, const float* taps, const float* P, const double* pm,
+                     const float* R, const double* rm, const float* alpha, double beta, float* Q,
+                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s);
+hipError_t conv_update(const ConvDims& cd, float* X, float* R, float* P, const float* Q,
+                       double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
+                       CgScalars* st, hipStream_t s);
+hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const float* X, const double* xm,
+                      float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
+                      hipStream_t s);
+
+hipError_t probe_signs_colmajor(uint64_t seed, int t, int K, int64_t D, float* out, hipStream_t s);
+hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
+
+int conv_update_blocks(const ConvDims& cd);
+
+}  // namespace cofem

@@ -1,0 +1,386 @@
+// 2D circular-convolution dictionary kernels of the CoFEM E-step.
+//
+// Phi is a circular convolution with an odd ks x ks kernel (a structured
+// dictionary with a fast apply, Sec. 1 and Sec. 3.2 of arXiv 2202.12808):
+//   (Phi z)[u, v]   = sum_{a,b} h[a,b] z[(u - a + c) mod H, (v - b + c) mod W]
+//   (Phi^T w)[u, v] = sum_{a,b} h[a,b] w[(u + a - c) mod H, (v + b - c) mod W]
+// with c = (ks - 1)/2.  One CG iteration's operator application
+//   q = beta Phi^T (Phi p) + alpha (.) p
+// runs as a single pass per 32x32 output tile and column: the tile of p with
+// a 2c halo is staged in LDS, Phi p is formed on the tile with a c halo in a
+// second LDS buffer, and Phi^T of that gives q on the tile.  Each output row
+// strip of 4 pixels is register-blocked against a column of taps.  The pass
+// also forms gam = p^T q, del = r^T q and eta = q^T q; the update kernel then
+// does x += a p, r -= a q and p <- r + b p in one sweep.
+//
+// State layout: probe columns are column-major images (column k at k * ldD,
+// pixel j = u * W + v); the mean column is a float64 image.
+#include "cofem_internal.h"
+
+namespace cofem {
+
+constexpr int kTile = 32;  // output tile side
+constexpr int kRB = 4;     // rows per thread (register blocking)
+
+template <int KS>
+struct ConvGeom {
+  static constexpr int c = (KS - 1) / 2;
+  static constexpr int stH = ((kTile + 2 * c + kRB - 1) / kRB) * kRB;  // rows of the Phi p buffer
+  static constexpr int stW = kTile + 2 * c;
+  static constexpr int spH = stH + 2 * c;  // rows of the p buffer
+  static constexpr int spW = kTile + 4 * c;
+};
+
+__device__ __forceinline__ int wrap(int x, int n) {
+  x %= n;
+  return x < 0 ? x + n : x;
+}
+
+// One (tile, column) of the fused operator pass, in precision T.
+template <int KS, typename T>
+__device__ __forceinline__ void conv_tile(const float* __restrict__ taps, int H, int W, int tu0,
+                                          int tv0, const T* __restrict__ P,
+                                          const T* __restrict__ R,
+                                          const float* __restrict__ alpha, T beta,
+                                          T* __restrict__ Q, T* sP, T* sT, double dots[3]) {
+  using G = ConvGeom<KS>;
+  constexpr int c = G::c;
+  const int tid = threadIdx.x;
+  // stage 0: p on the tile plus a 2c halo (circular wrap)
+  for (int e = tid; e < G::spH * G::spW; e += kThreads) {
+    const int i = e / G::spW, j = e - (e / G::spW) * G::spW;
+    const int u = wrap(tu0 - 2 * c + i, H), v = wrap(tv0 - 2 * c + j, W);
+    sP[e] = P[(int64_t)u * W + v];
+  }
+  __syncthreads();
+  // stage 1: t = Phi p on the tile plus a c halo
+  constexpr int nStrips = G::stH / kRB;
+  for (int item = tid; item < nStrips * G::stW; item += kThreads) {
+    const int j = item % G::stW;
+    const int i0 = (item / G::stW) * kRB;
+    T out[kRB];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) out[r] = T(0);
+#pragma unroll
+    for (int b = 0; b < KS; ++b) {
+      // rows i0 + r - a + 2c for r in [0, RB), a in [0, KS)
+      T strip[kRB + KS - 1];
+#pragma unroll
+      for (int q = 0; q < kRB + KS - 1; ++q) strip[q] = sP[(i0 + q) * G::spW + (j - b + 2 * c)];
+#pragma unroll
+      for (int a = 0; a < KS; ++a) {
+        const T h = (T)taps[a * KS + b];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) out[r] += h * strip[r - a + KS - 1];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) sT[(i0 + r) * G::stW + j] = out[r];
+  }
+  __syncthreads();
+  // stage 2: q = beta Phi^T t + alpha p on the tile
+  double g = 0.0, dl = 0.0, et = 0.0;
+  {
+    const int j = tid % kTile;
+    const int i0 = (tid / kTile) * kRB;
+    T out[kRB];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) out[r] = T(0);
+#pragma unroll
+    for (int b = 0; b < KS; ++b) {
+      T strip[kRB + KS - 1];
+#pragma unroll
+      for (int q = 0; q < kRB + KS - 1; ++q) strip[q] = sT[(i0 + q) * G::stW + j + b];
+#pragma unroll
+      for (int a = 0; a < KS; ++a) {
+        const T h = (T)taps[a * KS + b];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) out[r] += h * strip[r + a];
+      }
+    }
+    const int v = tv0 + j;
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) {
+      const int u = tu0 + i0 + r;
+      if (u < H && v < W) {
+        const int64_t idx = (int64_t)u * W + v;
+        const T p = sP[(i0 + r + 2 * c) * G::spW + j + 2 * c];
+        const T q = beta * out[r] + (T)alpha[idx] * p;
+        Q[idx] = q;
+        const double qd = (double)q;
+        g += (double)p * qd;
+        dl += (double)R[idx] * qd;
+        et += qd * qd;
+      }
+    }
+  }
+  dots[0] = g;
+  dots[1] = dl;
+  dots[2] = et;
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_conv_pass(
+    const float* __restrict__ taps, int H, int W, int64_t ldD, int K, const float* __restrict__ P,
+    const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
+    const float* __restrict__ alpha, double beta, float* __restrict__ Q, double* __restrict__ qm,
+    ConvReduce red, CgScalars* __restrict__ st, int apply_only) {
+  if (!apply_only && st->stop) return;
+  using G = ConvGeom<KS>;
+  __shared__ double sbuf[G::spH * G::spW + G::stH * G::stW];
+  const int col = blockIdx.z;
+  const int tu0 = blockIdx.y * kTile, tv0 = blockIdx.x * kTile;
+  double dots[3];
+  if (col == K) {
+    conv_tile<KS, double>(taps, H, W, tu0, tv0, pm, rm, alpha, beta, qm, sbuf,
+                          sbuf + G::spH * G::spW, dots);
+  } else {
+    float* sf = reinterpret_cast<float*>(sbuf);
+    const int64_t off = (int64_t)col * ldD;
+    conv_tile<KS, float>(taps, H, W, tu0, tv0, P + off, R + off, alpha, (float)beta, Q + off, sf,
+                         sf + G::spH * G::spW, dots);
+  }
+  if (apply_only) return;
+  __shared__ double shm[8];
+  __shared__ double mine[3], tot[3 * kMaxCols];
+  const double tg = block_sum(dots[0], shm);
+  const double td = block_sum(dots[1], shm);
+  const double te = block_sum(dots[2], shm);
+  if (threadIdx.x == 0) {
+    mine[0] = tg;
+    mine[1] = td;
+    mine[2] = te;
+  }
+  __syncthreads();
+  const int64_t ntiles = (int64_t)gridDim.x * gridDim.y;
+  const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, tile, ntiles, col, K + 1, 3,
+                          mine, tot))
+    return;
+  finish_step(st, tot);
+}
+
+hipError_t conv_pass(const ConvDims& cd, const float* taps, const float* P, const double* pm,
+                     const float* R, const double* rm, const float* alpha, double beta, float* Q,
+                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
+  const dim3 grid(cd.tilesX, cd.tilesY, cd.K + 1);
+#define COFEM_CONV_CASE(KS)                                                                       \
+  case KS:                                                                                        \
+    hipLaunchKernelGGL(k_conv_pass<KS>, grid, dim3(256), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K, P, \
+                       pm, R, rm, alpha, beta, Q, qm, red, st, apply_only);                     \
+    break;
+  switch (cd.ks) {
+    COFEM_CONV_CASE(1)
+    COFEM_CONV_CASE(3)
+    COFEM_CONV_CASE(5)
+    COFEM_CONV_CASE(7)
+    COFEM_CONV_CASE(9)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef COFEM_CONV_CASE
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ b0 = beta Phi^T y (Eq. 5), float64
+__global__ void k_conv_b0(const float* __restrict__ taps, int ks, int H, int W, int64_t ldD,
+                          const float* __restrict__ y, double beta, double* __restrict__ b0) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= ldD) return;
+  const int64_t D = (int64_t)H * W;
+  if (d >= D) {
+    b0[d] = 0.0;
+    return;
+  }
+  const int u = (int)(d / W), v = (int)(d % W), c = (ks - 1) / 2;
+  double acc = 0.0;
+  for (int a = 0; a < ks; ++a)
+    for (int b = 0; b < ks; ++b)
+      acc = fma((double)taps[a * ks + b], (double)y[(int64_t)wrap(u + a - c, H) * W + wrap(v + b - c, W)], acc);
+  b0[d] = beta * acc;
+}
+
+hipError_t conv_b0(const ConvDims& cd, const float* taps, const float* y, double beta, double* b0,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_b0, dim3((unsigned)((cd.ldD + 255) / 256)), dim3(256), 0, s, taps, cd.ks,
+                     cd.H, cd.W, cd.ldD, y, beta, b0);
+  return hipGetLastError();
+}
+
+int conv_update_blocks(const ConvDims& cd) {
+  const int64_t want = (cd.D + 4 * 256 - 1) / (4 * 256);
+  return (int)(want < 1 ? 1 : (want > 256 ? 256 : want));
+}
+
+// ------------------------------------------------ initial residual R = B (Eq. 7)
+__global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K, uint64_t seed,
+                                                   int t, const double* __restrict__ b0,
+                                                   float* __restrict__ X, float* __restrict__ R,
+                                                   float* __restrict__ P,
+                                                   double* __restrict__ xm, double* __restrict__ rm,
+                                                   double* __restrict__ pm, ConvReduce red,
+                                                   CgScalars* st) {
+  const int col = blockIdx.y;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  if (col == K) {
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const double b = b0[d];
+      rm[d] = b;
+      pm[d] = b;
+      xm[d] = 0.0;
+      acc += b * b;
+    }
+  } else {
+    const int64_t off = (int64_t)col * ldD;
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const float v = probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d);
+      R[off + d] = v;
+      P[off + d] = v;
+      X[off + d] = 0.0f;
+      acc += 1.0;
+    }
+  }
+  __shared__ double shm[8];
+  __shared__ double mine[1], tot[kMaxCols];
+  const double tot_b = block_sum(acc, shm);
+  if (threadIdx.x == 0) mine[0] = tot_b;
+  __syncthreads();
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col,
+                          K + 1, 1, mine, tot))
+    return;
+  finish_init(st, tot);
+}
+
+hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, float* X, float* R,
+                     float* P, double* xm, double* rm, double* pm, const ConvReduce& red,
+                     CgScalars* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_init, dim3(conv_update_blocks(cd), cd.K + 1), dim3(256), 0, s, cd.D,
+                     cd.ldD, cd.K, seed, t, b0, X, R, P, xm, rm, pm, red, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ CG update
+// x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2 and the stop test.
+__global__ __launch_bounds__(256) void k_conv_update(int64_t D, int64_t ldD, int K,
+                                                     float* __restrict__ X, float* __restrict__ R,
+                                                     float* __restrict__ P,
+                                                     const float* __restrict__ Q,
+                                                     double* __restrict__ xm,
+                                                     double* __restrict__ rm,
+                                                     double* __restrict__ pm,
+                                                     const double* __restrict__ qm, ConvReduce red,
+                                                     CgScalars* st) {
+  if (st->stop) return;
+  const int col = blockIdx.y;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  if (col == K) {
+    const double am = st->a[K], bm = st->b[K];
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const double p = pm[d];
+      xm[d] = fma(am, p, xm[d]);
+      const double r = fma(-am, qm[d], rm[d]);
+      rm[d] = r;
+      pm[d] = fma(bm, p, r);
+      acc += r * r;
+    }
+  } else {
+    const float a = (float)st->a[col], b = (float)st->b[col];
+    const int64_t off = (int64_t)col * ldD;
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const float p = P[off + d];
+      X[off + d] = fmaf(a, p, X[off + d]);
+      const float r = fmaf(-a, Q[off + d], R[off + d]);
+      R[off + d] = r;
+      P[off + d] = fmaf(b, p, r);
+      acc += (double)r * (double)r;
+    }
+  }
+  __shared__ double shm[8];
+  __shared__ double mine[1], tot[kMaxCols];
+  const double tot_b = block_sum(acc, shm);
+  if (threadIdx.x == 0) mine[0] = tot_b;
+  __syncthreads();
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col,
+                          K + 1, 1, mine, tot))
+    return;
+  finish_update(st, tot);
+}
+
+hipError_t conv_update(const ConvDims& cd, float* X, float* R, float* P, const float* Q,
+                       double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
+                       CgScalars* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_update, dim3(conv_update_blocks(cd), cd.K + 1), dim3(256), 0, s, cd.D,
+                     cd.ldD, cd.K, X, R, P, Q, xm, rm, pm, qm, red, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
+__global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, uint64_t seed,
+                                                    int t, const float* __restrict__ X,
+                                                    const double* __restrict__ xm,
+                                                    float* __restrict__ alpha, double alpha_max,
+                                                    float* __restrict__ mu,
+                                                    float* __restrict__ sdiag, CgScalars* st) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  const double floor_v = 1.0 / alpha_max;
+  double clamped = 0.0;
+  for (int64_t d = gtid; d < D; d += gstride) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k)
+      acc += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)d) * (double)X[(int64_t)k * ldD + d];
+    const double s = acc / (double)K;
+    const double m = xm[d];
+    const double den = m * m + s;
+    if (!(den >= floor_v)) clamped += 1.0;
+    alpha[d] = (float)(1.0 / (den >= floor_v ? den : floor_v));
+    mu[d] = (float)m;
+    sdiag[d] = (float)s;
+  }
+  __shared__ double shm[8];
+  const double tot = block_sum(clamped, shm);
+  if (threadIdx.x == 0 && tot > 0.0) atomicAdd(&st->n_clamped, (int)tot);
+}
+
+hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const float* X, const double* xm,
+                      float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
+                      hipStream_t s) {
+  const int64_t want = (cd.D + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
+  hipLaunchKernelGGL(k_conv_mstep, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, X, xm,
+                     alpha, alpha_max, mu, sdiag, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ probes for tests; fills
+__global__ void k_probe_signs(uint64_t seed, int t, int K, int64_t D, float* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D * K) return;
+  const int64_t k = idx / D, d = idx % D;
+  out[idx] = probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)d);
+}
+
+hipError_t probe_signs_colmajor(uint64_t seed, int t, int K, int64_t D, float* out, hipStream_t s) {
+  const int64_t tot = D * K;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe_signs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, seed, t, K,
+                     D, out);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, float v, int64_t n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) p[idx] = v;
+}
+
+hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace cofem

@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/cofem.h, and rejects bad arguments before touching the
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2202_12808_amd import cofem as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cofem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cofem_[A-Za-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(C.LIB_PATH):
+        from paper_2202_12808_amd import build
+        build.build()
+    return C.load()
+
+
+def test_header_declares_the_paper_entry_points():
+    names = _declared()
+    for n in ("cofem_init", "cofem_em_step", "cofem_posterior", "cofem_destroy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(C._SIGNATURES)
+
+
+def test_status_strings(lib):
+    for code, name in C._STATUS_NAMES.items():
+        assert lib.cofem_status_string(code).decode() == name
+
+
+def _problem(**kw):
+    p = C.cofem_problem(kind=C.COFEM_DENSE, N=8, D=16, phi=1, ld_phi=16, phi_dtype=C.COFEM_F32,
+                        H=0, W=0, kh=0, kw=0, taps=None, y=2)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _params(**kw):
+    q = C.cofem_params(beta=10.0, K=4, cg_tol=1e-5, cg_max_iter=100, seed=1, precision=0,
+                       stop_rule=0, alpha_max=0.0, flags=0, poll_interval=0)
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+@pytest.mark.parametrize("pkw,qkw,code", [
+    ({}, {"beta": 0.0}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"beta": -1.0}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"K": 0}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"K": 33}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"cg_tol": -1.0}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"cg_max_iter": -1}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"precision": 7}, C.COFEM_ERR_UNSUPPORTED),
+    ({"N": 0}, {}, C.COFEM_ERR_INVALID_ARG),
+    ({"D": 0}, {}, C.COFEM_ERR_INVALID_ARG),
+    ({"phi": None}, {}, C.COFEM_ERR_INVALID_ARG),
+    ({"y": None}, {}, C.COFEM_ERR_INVALID_ARG),
+    ({"ld_phi": 8}, {}, C.COFEM_ERR_INVALID_ARG),
+    ({"kind": 9}, {}, C.COFEM_ERR_INVALID_ARG),
+    ({"kind": C.COFEM_CONV2D_CIRC, "H": 4, "W": 4, "N": 16, "D": 16, "kh": 4, "kw": 4, "taps": 3}, {},
+     C.COFEM_ERR_INVALID_ARG),
+    ({"kind": C.COFEM_CONV2D_CIRC, "H": 4, "W": 4, "N": 16, "D": 16, "kh": 3, "kw": 5, "taps": 3}, {},
+     C.COFEM_ERR_UNSUPPORTED),
+    ({"kind": C.COFEM_CONV2D_CIRC, "H": 4, "W": 4, "N": 15, "D": 16, "kh": 3, "kw": 3, "taps": 3}, {},
+     C.COFEM_ERR_INVALID_ARG),
+    ({"kind": C.COFEM_CONV2D_CIRC, "H": 4, "W": 4, "N": 16, "D": 16, "kh": 3, "kw": 3, "taps": None}, {},
+     C.COFEM_ERR_INVALID_ARG),
+])
+def test_init_rejects_bad_arguments_without_device(lib, pkw, qkw, code):
+    ctx = ctypes.c_void_p()
+    st = lib.cofem_init(ctypes.byref(_problem(**pkw)), 1, ctypes.byref(_params(**qkw)), None,
+                        ctypes.byref(ctx))
+    assert st == code
+    assert not ctx.value
+    assert len(lib.cofem_last_error(None)) > 0
+
+
+def test_init_rejects_batch_count(lib):
+    ctx = ctypes.c_void_p()
+    assert lib.cofem_init(ctypes.byref(_problem()), 0, ctypes.byref(_params()), None,
+                          ctypes.byref(ctx)) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_init(None, 1, ctypes.byref(_params()), None,
+                          ctypes.byref(ctx)) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_init(ctypes.byref(_problem()), 1, ctypes.byref(_params()), None,
+                          None) == C.COFEM_ERR_INVALID_ARG
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    assert lib.cofem_em_step(None, 1, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_posterior(None, 0, None, None, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_set_alpha(None, 0, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_set_iteration(None, 1) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_set_fixed_cg_iters(None, 1) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_get_solution(None, 0, None, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_apply_A(None, 0, None, None, None, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_probe_signs(0, 1, 1, 10, None, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_probe_signs(0, -1, 1, 10, 8, None) == C.COFEM_ERR_INVALID_ARG
+    lib.cofem_destroy(None)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(C.CofemError):
+        C._lib_saved = C._lib
+        try:
+            C._lib = None
+            C.load(str(tmp_path / "missing.so"))
+        finally:
+            C._lib = C._lib_saved

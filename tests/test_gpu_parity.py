@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: probe-block quantities are float32 with float64 reductions, the
+mean column is float64 end to end.  Step parity (one E-step + M-step from the
+same alpha, the same probes, the oracle running the GPU's CG iteration count)
+must agree to a norm-wise relative error of 1e-4 on mu, s and the M-step
+denominator 1/alpha = max(mu^2 + s, 1/alpha_max).  alpha itself is compared
+through its reciprocal: alpha has a pole where mu^2 + s -> 0 and a jump at the
+floor, so its norm is dominated by the few coordinates whose floor decision
+flips with rounding noise.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_12808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-4
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_12808_amd import cofem as C
+    C.load()  # fails loudly when the library is missing
+    return torch
+
+
+def relerr(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _dense_ctx(torch, p, **kw):
+    from paper_2202_12808_amd.cofem import CoFEM
+    phi = torch.from_numpy(p.phi).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, **kw)
+
+
+def _conv_ctx(torch, p, **kw):
+    from paper_2202_12808_amd.cofem import CoFEM
+    taps = torch.from_numpy(p.taps).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    return CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, **kw)
+
+
+def _oracle_op(p):
+    if p.kind == "dense":
+        return O.DenseOperator(p.phi.astype(np.float64))
+    return O.ConvOperator(p.taps.astype(np.float64), p.H, p.W)
+
+
+# ------------------------------------------------------------------ probes
+def test_probe_signs_match_oracle(torch_dev, golden_dir):
+    torch = torch_dev
+    from paper_2202_12808_amd import cofem as C
+    _say("probe_signs golden seed=12345 t=3 K=5 D=300")
+    out = torch.empty((5, 300), dtype=torch.float32, device="cuda")
+    C.cofem_probe_signs(12345, 3, 5, 300, out)
+    ref = np.loadtxt(os.path.join(golden_dir, "probes_seed12345_t3_K5_D300.txt"))
+    assert np.array_equal(out.cpu().numpy().T, ref)
+    for seed, t, K, D in [(0, 0, 1, 64), (2**63 + 17, 65535, 7, 1000), (99, 1, 32, 4099)]:
+        _say("probe_signs", seed, t, K, D)
+        out = torch.empty((K, D), dtype=torch.float32, device="cuda")
+        C.cofem_probe_signs(seed, t, K, D, out)
+        assert np.array_equal(out.cpu().numpy().T, O.rademacher_probes(seed, t, K, D))
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("N,D,K", [(256, 1024, 20), (200, 700, 5), (1, 33, 1), (333, 129, 32), (64, 64, 32)])
+def test_dense_apply_A(torch_dev, N, D, K):
+    torch = torch_dev
+    _say("dense apply_A", N, D, K)
+    p = synth.dense_problem(N, D, nnz=min(5, D), beta=123.0, K=K, tol=1e-6, seed=N + D)
+    rng = np.random.default_rng(7)
+    alpha = (10.0 ** rng.uniform(-2, 6, D)).astype(np.float32)
+    V = rng.standard_normal((D, K)).astype(np.float32)
+    vm = rng.standard_normal(D)
+    with _dense_ctx(torch, p) as g:
+        g.set_alpha(torch.from_numpy(alpha))
+        q, qm = g.apply_A(torch.from_numpy(V.T.copy()), torch.from_numpy(vm))
+        q = q.cpu().numpy().T
+        qm = qm.cpu().numpy()
+    A = O.cofem_oracle.make_apply_A(_oracle_op(p), p.beta, alpha.astype(np.float64))
+    ref = A(V.astype(np.float64))
+    for k in range(K):
+        assert relerr(q[:, k], ref[:, k]) < 2e-6, k
+    assert relerr(qm, A(vm)) < 1e-13
+
+
+@pytest.mark.parametrize("H,W,k,K", [(32, 32, 7, 4), (40, 37, 7, 3), (64, 48, 9, 16), (13, 70, 3, 2),
+                                     (5, 9, 5, 1), (33, 33, 1, 2), (256, 256, 7, 16)])
+def test_conv_apply_A(torch_dev, H, W, k, K):
+    torch = torch_dev
+    _say("conv apply_A", H, W, k, K)
+    p = synth.conv_problem(H, W, k, rho=0.05, beta=321.0, K=K, tol=1e-6, seed=H * W + k)
+    rng = np.random.default_rng(11)
+    D = H * W
+    alpha = (10.0 ** rng.uniform(-2, 6, D)).astype(np.float32)
+    V = rng.standard_normal((D, K)).astype(np.float32)
+    vm = rng.standard_normal(D)
+    with _conv_ctx(torch, p) as g:
+        g.set_alpha(torch.from_numpy(alpha))
+        q, qm = g.apply_A(torch.from_numpy(V.T.copy()), torch.from_numpy(vm))
+        q = q.cpu().numpy().T
+        qm = qm.cpu().numpy()
+    A = O.cofem_oracle.make_apply_A(_oracle_op(p), p.beta, alpha.astype(np.float64))
+    ref = A(V.astype(np.float64))
+    for c in range(K):
+        assert relerr(q[:, c], ref[:, c]) < 2e-6, c
+    assert relerr(qm, A(vm)) < 1e-13
+
+
+# ------------------------------------------------------------------ step parity
+def _step_parity(torch, p, make_ctx, t_free, label):
+    """Free-run the GPU t_free EM iterations, then compare one teacher-forced
+    step (GPU alpha, same t, oracle at the GPU's CG count)."""
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with make_ctx(torch, p) as g:
+        if t_free:
+            g.em_step(t_free)
+        _, _, alpha = g.posterior()
+        alpha = alpha.cpu().numpy()
+        stats = g.em_step(1)[0]
+        mu, s, alpha_new = [x.cpu().numpy() for x in g.posterior()]
+    n = stats["cg_iters"]
+    t = stats["t"]
+    assert t == t_free + 1
+    e = O.cofem_estep(op, b0, p.beta, alpha.astype(np.float64), p.K, p.tol, p.max_iter, p.seed, t,
+                      fixed_iters=n)
+    a_ref, _ = O.mstep(e.mu, e.s)
+    errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / alpha_new.astype(np.float64), 1.0 / a_ref))
+    _say(label, "t", t, "cg", n, "relerr mu/s/(1/alpha)", errs, "alpha", relerr(alpha_new, a_ref))
+    # the oracle at the same count also meets the GPU's stop decision
+    assert stats["converged"] == 1 or n == p.max_iter
+    assert all(err < STEP_TOL for err in errs), errs
+    return errs
+
+
+@pytest.mark.parametrize("t_free", [0, 5, 20])
+def test_dense_256x1024_step_parity(torch_dev, t_free):
+    p = synth.dense_256x1024(0)
+    _step_parity(torch_dev, p, _dense_ctx, t_free, f"dense_256x1024 t_free={t_free}")
+
+
+def test_dense_ragged_step_parity(torch_dev):
+    p = synth.dense_problem(300, 777, nnz=9, beta=5e3, K=13, tol=1e-6, seed=3)
+    _step_parity(torch_dev, p, _dense_ctx, 3, "dense_300x777")
+
+
+@pytest.mark.parametrize("t_free", [0, 8])
+def test_conv_small_step_parity(torch_dev, t_free):
+    p = synth.conv_problem(64, 48, 7, rho=0.02, beta=1e4, K=8, tol=1e-6, seed=1, law="laplace")
+    _step_parity(torch_dev, p, _conv_ctx, t_free, f"conv_64x48_k7 t_free={t_free}")
+
+
+def test_conv_256x256_k7_step_parity(torch_dev):
+    p = synth.conv_256x256_k7(0)
+    _step_parity(torch_dev, p, _conv_ctx, 0, "conv_256x256_k7")
+
+
+# ------------------------------------------------------------------ closed form
+@pytest.mark.parametrize("kind", ["dense", "conv"])
+def test_identity_dictionary_closed_form(torch_dev, kind):
+    # Phi = I: mu_j = beta y_j/(beta+alpha_j), s_j = 1/(beta+alpha_j) for every K,
+    # the first CG solve takes one iteration
+    torch = torch_dev
+    _say("identity closed form", kind)
+    H, W = 16, 20
+    D = H * W
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(D).astype(np.float32)
+    beta = 50.0
+    from paper_2202_12808_amd.cofem import CoFEM
+    if kind == "dense":
+        g = CoFEM.dense(torch.eye(D, dtype=torch.float32, device="cuda"), torch.from_numpy(y).cuda(),
+                        beta, 4, tol=1e-7, max_iter=200, seed=3)
+    else:
+        taps = torch.zeros((3, 3), dtype=torch.float32, device="cuda")
+        taps[1, 1] = 1.0
+        g = CoFEM.conv(taps, torch.from_numpy(y).cuda(), H, W, beta, 4, tol=1e-7, max_iter=200, seed=3)
+    with g:
+        st = g.em_step(3)
+        mu, s, alpha = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    assert st[0]["cg_iters"] == 1
+    a = np.ones(D)
+    yd = y.astype(np.float64)
+    for _ in range(3):
+        m_ref = beta * yd / (beta + a)
+        v_ref = 1.0 / (beta + a)
+        a = 1.0 / (m_ref * m_ref + v_ref)
+    assert relerr(mu, m_ref) < 1e-6
+    assert relerr(s, v_ref) < 1e-6
+    assert relerr(alpha, a) < 1e-6
+
+
+# ------------------------------------------------------------------ edge cases
+def test_fixed_iteration_mode_and_cap(torch_dev):
+    torch = torch_dev
+    p = synth.dense_256x1024(1)
+    _say("fixed iterations and cap")
+    with _dense_ctx(torch, p) as g:
+        g.set_fixed_cg_iters(7)
+        st = g.em_step(2)
+        assert [s["cg_iters"] for s in st] == [7, 7]
+        g.set_fixed_cg_iters(0)
+    # cap U below what the tolerance needs: converged = 0, not an error
+    from paper_2202_12808_amd.cofem import CoFEM
+    g = CoFEM.dense(torch.from_numpy(p.phi).cuda(), torch.from_numpy(p.y).cuda(), p.beta, p.K,
+                    tol=1e-12, max_iter=3, seed=0)
+    with g:
+        st = g.em_step(1)[0]
+        assert st["cg_iters"] == 3 and st["converged"] == 0
+
+
+def test_zero_observation_gives_zero_mean(torch_dev):
+    torch = torch_dev
+    _say("zero y")
+    p = synth.dense_problem(64, 128, nnz=3, beta=100.0, K=4, tol=1e-6, seed=2)
+    p.y[:] = 0.0
+    with _dense_ctx(torch, p) as g:
+        g.em_step(1)
+        mu, s, alpha = [x.cpu().numpy() for x in g.posterior()]
+    assert np.all(mu == 0.0) and np.all(np.isfinite(s)) and np.all(alpha > 0)
+
+
+def test_trajectory_dense_256x1024(torch_dev):
+    # free-running 50 EM iterations, GPU vs oracle each with its own stop decisions
+    torch = torch_dev
+    p = synth.dense_256x1024(0)
+    _say("trajectory dense_256x1024")
+    with _dense_ctx(torch, p) as g:
+        st = g.em_step(p.T_em)
+        mu, s, alpha = [x.cpu().numpy() for x in g.posterior()]
+    r = O.cofem(_oracle_op(p), p.y, p.beta, p.T_em, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+    e_mu = relerr(mu, r.mu)
+    nrmse_gpu = relerr(mu, p.z)
+    nrmse_or = relerr(r.mu, p.z)
+    _say("trajectory relerr mu", e_mu, "NRMSE gpu/oracle", nrmse_gpu, nrmse_or,
+         "cg gpu", [x["cg_iters"] for x in st][:10], "oracle", [x["cg_iters"] for x in r.stats][:10])
+    assert e_mu < 1e-3
+    assert abs(nrmse_gpu - nrmse_or) < 1e-3 * max(nrmse_or, 1e-3) + 1e-4
+
+
+@pytest.mark.parametrize("kind", ["dense", "conv"])
+def test_runs_are_bit_reproducible(torch_dev, kind):
+    # the cross-workgroup reductions sum partials in a fixed order: two runs of
+    # the same solve give identical bits and identical CG counts
+    torch = torch_dev
+    _say("reproducibility", kind)
+    if kind == "dense":
+        p = synth.dense_problem(1000, 3000, nnz=30, beta=1e3, K=32, tol=1e-6, seed=4)
+        make = _dense_ctx
+    else:
+        p = synth.conv_problem(96, 80, 9, rho=0.02, beta=1e3, K=16, tol=1e-5, seed=4)
+        make = _conv_ctx
+    outs = []
+    for _ in range(2):
+        with make(torch, p) as g:
+            st = g.em_step(4)
+            outs.append(([x["cg_iters"] for x in st], [x.cpu().numpy() for x in g.posterior()]))
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
