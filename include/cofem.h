@@ -51,8 +51,13 @@ typedef enum cofem_status {
 enum { COFEM_DENSE = 0, COFEM_CONV2D_CIRC = 1 };
 /* cofem_problem.phi_dtype */
 enum { COFEM_F32 = 0, COFEM_BF16 = 1 };
-/* cofem_params.precision */
-enum { COFEM_PREC_FP32 = 0, COFEM_PREC_BF16_IR = 1 };
+/* cofem_params.precision:
+ *  COFEM_PREC_FP32  probe columns in float32 (float64 reductions), mean column
+ *                   in float64;
+ *  COFEM_PREC_FP64  every column in float64 (convolution dictionaries only in
+ *                   this build) -- for ill-conditioned solves whose float32
+ *                   probe iterates drift from a float64 reference. */
+enum { COFEM_PREC_FP32 = 0, COFEM_PREC_BF16_IR = 1, COFEM_PREC_FP64 = 2 };
 /* cofem_params.stop_rule */
 enum { COFEM_STOP_FROBENIUS = 0 };
 
@@ -182,9 +187,11 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
 
 /*
  * Measurement support: times the operator kernels of one CG iteration in the
- * launch configuration the solver uses, `reps` times each, with HIP events on
- * the context's stream, applied to the current direction block.  Writes the
- * mean duration in milliseconds of each kernel to ms_out (host, 3 entries):
+ * launch configuration the solver uses, applied to the current direction
+ * block: each kernel is launched once to warm up, then `reps` times back to
+ * back between two HIP events on the context's stream (the way the CG loop
+ * issues it).  Writes the mean per-launch time in milliseconds, dispatch gaps
+ * included, of each kernel to ms_out (host, 3 entries):
  * dense -> {pass 1 (W = Phi P), pass 2 (Q = beta Phi^T W + alpha P), 0};
  * conv  -> {fused stencil pass, 0, 0}.  Leaves the solver state unchanged.
  */

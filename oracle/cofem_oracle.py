@@ -116,7 +116,9 @@ class ConvOperator:
     (Phi z)[u, v] = sum_{a,b} h[a, b] * z[(u - a + ch) mod H, (v - b + cw) mod W]
     with ch = (kh - 1)/2, cw = (kw - 1)/2; Phi^T is the matching circular
     correlation.  Vectors are images flattened row-major (j = u*W + v).
-    Applied as a direct sum over taps (np.roll), the plain definition.
+    The sum over taps is evaluated per image by scipy.ndimage's wrap-mode
+    convolve / correlate (a library stencil: the plain definition, in C),
+    one thread per column.
     """
 
     def __init__(self, taps: np.ndarray, H: int, W: int):
@@ -128,34 +130,45 @@ class ConvOperator:
         self.N = self.D = self.H * self.W
         self.ch, self.cw = (kh - 1) // 2, (kw - 1) // 2
 
-    def _as_images(self, v):
+    def _map(self, fn, v):
+        import scipy.ndimage as nd
+
         v = np.asarray(v, dtype=np.float64)
         one = v.ndim == 1
-        img = v.reshape(self.H, self.W, -1)
-        return img, one
+        cols = v.reshape(self.D, -1)
+        f = getattr(nd, fn)
+
+        def one_col(k):
+            return f(cols[:, k].reshape(self.H, self.W), self.taps, mode="wrap").reshape(self.D)
+
+        m = cols.shape[1]
+        if m == 1:
+            out = one_col(0)[:, None]
+        else:
+            out = np.stack(list(_pool().map(one_col, range(m))), axis=1)
+        return out[:, 0] if one else out
 
     def apply(self, v: np.ndarray) -> np.ndarray:
-        img, one = self._as_images(v)
-        out = np.zeros_like(img)
-        kh, kw = self.taps.shape
-        for a in range(kh):
-            for b in range(kw):
-                out += self.taps[a, b] * np.roll(img, (a - self.ch, b - self.cw), axis=(0, 1))
-        out = out.reshape(self.D, -1)
-        return out[:, 0] if one else out
+        return self._map("convolve", v)
 
     def apply_t(self, w: np.ndarray) -> np.ndarray:
-        img, one = self._as_images(w)
-        out = np.zeros_like(img)
-        kh, kw = self.taps.shape
-        for a in range(kh):
-            for b in range(kw):
-                out += self.taps[a, b] * np.roll(img, (self.ch - a, self.cw - b), axis=(0, 1))
-        out = out.reshape(self.D, -1)
-        return out[:, 0] if one else out
+        return self._map("correlate", w)
 
     def column_norms_sq(self) -> np.ndarray:
         return np.full(self.D, float(np.sum(self.taps * self.taps)))
+
+
+_POOL = None
+
+
+def _pool():
+    global _POOL
+    if _POOL is None:
+        import os
+        from concurrent.futures import ThreadPoolExecutor
+
+        _POOL = ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1)))
+    return _POOL
 
 
 def make_apply_A(op, beta: float, alpha: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:

@@ -30,7 +30,9 @@ COFEM_F32 = 0
 COFEM_BF16 = 1
 COFEM_PREC_FP32 = 0
 COFEM_PREC_BF16_IR = 1
+COFEM_PREC_FP64 = 2
 COFEM_STOP_FROBENIUS = 0
+_PRECISIONS = {"fp32": COFEM_PREC_FP32, "bf16_ir": COFEM_PREC_BF16_IR, "fp64": COFEM_PREC_FP64}
 COFEM_MAX_K = 32
 
 
@@ -192,9 +194,9 @@ class CoFEM:
             self.ctx = cofem_init(problem, params, stream)
 
     @staticmethod
-    def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0):
+    def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0, precision="fp32"):
         return cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
-                            seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=COFEM_PREC_FP32,
+                            seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=_PRECISIONS[precision],
                             stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max), flags=0,
                             poll_interval=int(poll_interval))
 

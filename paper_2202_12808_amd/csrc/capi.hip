@@ -33,6 +33,7 @@ struct cofem_ctx {
   int t_next = 1;
   int fixed_iters = 0;
   int prev_iters = 0;
+  int precision = COFEM_PREC_FP32;
   bool has_solution = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -48,12 +49,17 @@ struct cofem_ctx {
   float* alpha = nullptr;
   float *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
   double *xm = nullptr, *rm = nullptr, *pm = nullptr, *qm = nullptr;
+  // conv probe blocks (float or double per the precision mode)
+  void *vX = nullptr, *vR = nullptr, *vP = nullptr, *vQ = nullptr, *vVs = nullptr, *vQs = nullptr;
   // scratch for apply_A
   float *Vs = nullptr, *Qs = nullptr;
   double *Vsm = nullptr, *Qsm = nullptr;
   // dense GEMM intermediates
   float* W = nullptr;
   double* wm = nullptr;
+  float *Wpart = nullptr, *Qpart = nullptr;  // split-K partials
+  double *wmpart = nullptr, *qmpart = nullptr;
+  uint32_t *cnt_split1 = nullptr, *cnt_split2 = nullptr;
   // reduction workspaces (tree partials and their self-resetting counters)
   double *parts_init = nullptr, *parts_upd = nullptr, *parts_pass = nullptr;
   uint32_t *cnts_init = nullptr, *cnts_upd = nullptr, *cnts_pass = nullptr;
@@ -149,8 +155,19 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   dd.D = p.D;
   dd.Np = round_up(p.N, 64);
   dd.Dp = round_up(p.D, 64);
-  dd.waves1 = dense_pass_waves(dd.Np / 16);
-  dd.waves2 = dense_pass_waves(dd.Dp / 16);
+  dd.S1 = dense_split(dd.Np / 32, dd.Dp / 8);
+  dd.S2 = dense_split(dd.Dp / 32, dd.Np / 8);
+  dd.ring = 4;
+  // tuning override: COFEM_GEMM="S1,S2,ring"
+  if (const char* e = getenv("COFEM_GEMM")) {
+    int s1, s2, rg;
+    if (sscanf(e, "%d,%d,%d", &s1, &s2, &rg) == 3 && dense_split_ok(dd.Dp / 8, s1) &&
+        dense_split_ok(dd.Np / 8, s2) && s1 <= 64 && s2 <= 64 && (rg == 1 || rg == 2 || rg == 4 || rg == 8)) {
+      dd.S1 = s1;
+      dd.S2 = s2;
+      dd.ring = rg;
+    }
+  }
   c->KP = kDenseKP;
 
   const size_t blk = (size_t)dd.Dp * kDenseKP;
@@ -177,7 +194,13 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   const int64_t nupd = dense_update_blocks(dd);
   COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, kDenseKP + 1));
   COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, kDenseKP + 1));
-  COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 16, 3 * (kDenseKP + 1)));
+  COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 32, 3 * (kDenseKP + 1)));
+  COFEM_TRY(alloc(c, &c->Wpart, (size_t)(dd.S1 > 1 ? dd.S1 : 0) * dd.Np * kDenseKP));
+  COFEM_TRY(alloc(c, &c->wmpart, (size_t)(dd.S1 > 1 ? dd.S1 : 0) * dd.Np));
+  COFEM_TRY(alloc(c, &c->Qpart, (size_t)(dd.S2 > 1 ? dd.S2 : 0) * dd.Dp * kDenseKP));
+  COFEM_TRY(alloc(c, &c->qmpart, (size_t)(dd.S2 > 1 ? dd.S2 : 0) * dd.Dp));
+  COFEM_TRY(alloc(c, &c->cnt_split1, (size_t)(dd.Np / 32)));
+  COFEM_TRY(alloc(c, &c->cnt_split2, (size_t)(dd.Dp / 32)));
 
   COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
   COFEM_HIP(c, dense_b0(static_cast<const float*>(p.phi), p.ld_phi, p.y, c->beta, dd, c->b0, c->stream));
@@ -196,6 +219,7 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   cd.tilesX = (p.W + 31) / 32;
   cd.tilesY = (p.H + 31) / 32;
   c->KP = c->K;
+  cd.fp64 = c->precision == COFEM_PREC_FP64 ? 1 : 0;
   const size_t blk = (size_t)cd.ldD * c->K;
   COFEM_TRY(alloc(c, &c->taps, (size_t)p.kh * p.kw));
   COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
@@ -204,12 +228,18 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->alpha, cd.ldD));
   COFEM_TRY(alloc(c, &c->mu, cd.ldD));
   COFEM_TRY(alloc(c, &c->sdiag, cd.ldD));
-  COFEM_TRY(alloc(c, &c->X, blk));
-  COFEM_TRY(alloc(c, &c->R, blk));
-  COFEM_TRY(alloc(c, &c->P, blk));
-  COFEM_TRY(alloc(c, &c->Q, blk));
-  COFEM_TRY(alloc(c, &c->Vs, blk));
-  COFEM_TRY(alloc(c, &c->Qs, blk));
+  void** blocks[6] = {&c->vX, &c->vR, &c->vP, &c->vQ, &c->vVs, &c->vQs};
+  for (void** b : blocks) {
+    if (cd.fp64) {
+      double* q = nullptr;
+      COFEM_TRY(alloc(c, &q, blk));
+      *b = q;
+    } else {
+      float* q = nullptr;
+      COFEM_TRY(alloc(c, &q, blk));
+      *b = q;
+    }
+  }
   COFEM_TRY(alloc(c, &c->xm, cd.ldD));
   COFEM_TRY(alloc(c, &c->rm, cd.ldD));
   COFEM_TRY(alloc(c, &c->pm, cd.ldD));
@@ -241,7 +271,10 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->K < 1 || q->K > COFEM_MAX_K) return *why = "K must be in [1, 32]", COFEM_ERR_INVALID_ARG;
   if (!(q->cg_tol >= 0.0) || !isfinite(q->cg_tol)) return *why = "cg_tol must be >= 0", COFEM_ERR_INVALID_ARG;
   if (q->cg_max_iter < 0) return *why = "cg_max_iter must be >= 0", COFEM_ERR_INVALID_ARG;
-  if (q->precision != COFEM_PREC_FP32) return *why = "only COFEM_PREC_FP32 is built", COFEM_ERR_UNSUPPORTED;
+  if (q->precision != COFEM_PREC_FP32 && q->precision != COFEM_PREC_FP64)
+    return *why = "precision mode not built", COFEM_ERR_UNSUPPORTED;
+  if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
+    return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
   if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
   if (!p->y) return *why = "y is null", COFEM_ERR_INVALID_ARG;
   if (p->kind == COFEM_DENSE) {
@@ -266,15 +299,17 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
 cofem_status run_cg_iterations(cofem_ctx* c, int n) {
   for (int i = 0; i < n; ++i) {
     if (c->kind == COFEM_DENSE) {
-      COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->W, c->wm, c->st, 0, c->stream));
+      COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
+                               c->cnt_split1, c->st, 0, c->stream));
       COFEM_HIP(c, dense_pass2(c->dd, c->phiB, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
-                               c->Q, c->qm, c->parts_pass, c->cnts_pass, c->st, 0, c->stream));
+                               c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
+                               c->cnt_split2, c->st, 0, c->stream));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
     } else {
-      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->P, c->pm, c->R, c->rm, c->alpha, c->beta, c->Q, c->qm,
+      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
                              c->red_pass, c->st, 0, c->stream));
-      COFEM_HIP(c, conv_update(c->cd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->red_upd,
+      COFEM_HIP(c, conv_update(c->cd, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm, c->red_upd,
                                c->st, c->stream));
     }
   }
@@ -294,7 +329,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     COFEM_HIP(c, dense_init(c->dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm,
                             c->parts_init, c->cnts_init, c->st, c->stream));
   else
-    COFEM_HIP(c, conv_init(c->cd, c->seed, t, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->red_init,
+    COFEM_HIP(c, conv_init(c->cd, c->seed, t, c->b0, c->vX, c->vR, c->vP, c->xm, c->rm, c->pm, c->red_init,
                            c->st, c->stream));
   const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
   // First chunk: the previous solve's count (CG counts drift slowly across EM
@@ -318,7 +353,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
                              c->sdiag, c->st, c->stream));
   else
-    COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->X, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
+    COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
                             c->st, c->stream));
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
   COFEM_TRY(read_state(c));
@@ -361,6 +396,7 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   c->seed = params->seed;
   c->alpha_max = params->alpha_max > 0.0 ? params->alpha_max : 1e10;
   c->poll = params->poll_interval > 0 ? params->poll_interval : 8;
+  c->precision = params->precision;
   c->stream = static_cast<hipStream_t>(hip_stream);
   cofem_status s = COFEM_OK;
   hipError_t e = hipGetDevice(&c->device);
@@ -437,8 +473,7 @@ cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, 
     if (ctx->kind == COFEM_DENSE) {
       COFEM_HIP(ctx, dense_to_colmajor(ctx->dd, ctx->K, ctx->X, probes, ctx->stream));
     } else {
-      COFEM_HIP(ctx, hipMemcpy2DAsync(probes, sizeof(float) * ctx->D, ctx->X, sizeof(float) * ctx->cd.ldD,
-                                      sizeof(float) * ctx->D, ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+      COFEM_HIP(ctx, conv_probes_out(ctx->cd, ctx->vX, probes, ctx->stream));
     }
   }
   if (mean)
@@ -458,20 +493,19 @@ cofem_status cofem_apply_A(cofem_ctx* ctx, int32_t problem, const float* v_probe
     COFEM_HIP(ctx, dense_from_colmajor(dd, ctx->K, v_probes, ctx->Vs, ctx->stream));
     COFEM_HIP(ctx, hipMemsetAsync(ctx->Vsm, 0, sizeof(double) * dd.Dp, ctx->stream));
     COFEM_HIP(ctx, hipMemcpyAsync(ctx->Vsm, v_mean, Dm, hipMemcpyDeviceToDevice, ctx->stream));
-    COFEM_HIP(ctx, dense_pass1(dd, ctx->phiA, ctx->Vs, ctx->Vsm, ctx->W, ctx->wm, ctx->st, 1, ctx->stream));
+    COFEM_HIP(ctx, dense_pass1(dd, ctx->phiA, ctx->Vs, ctx->Vsm, ctx->Wpart, ctx->wmpart, ctx->W, ctx->wm,
+                               ctx->cnt_split1, ctx->st, 1, ctx->stream));
     COFEM_HIP(ctx, dense_pass2(dd, ctx->phiB, ctx->W, ctx->wm, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm,
-                               ctx->alpha, ctx->beta, ctx->Qs, ctx->Qsm, ctx->parts_pass, ctx->cnts_pass,
-                               ctx->st, 1, ctx->stream));
+                               ctx->alpha, ctx->beta, ctx->Qpart, ctx->qmpart, ctx->Qs, ctx->Qsm,
+                               ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1, ctx->stream));
     COFEM_HIP(ctx, dense_to_colmajor(dd, ctx->K, ctx->Qs, q_probes, ctx->stream));
   } else {
     const ConvDims& cd = ctx->cd;
-    COFEM_HIP(ctx, hipMemcpy2DAsync(ctx->Vs, sizeof(float) * cd.ldD, v_probes, sizeof(float) * ctx->D,
-                                    sizeof(float) * ctx->D, ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+    COFEM_HIP(ctx, conv_probes_in(cd, v_probes, ctx->vVs, ctx->stream));
     COFEM_HIP(ctx, hipMemcpyAsync(ctx->Vsm, v_mean, Dm, hipMemcpyDeviceToDevice, ctx->stream));
-    COFEM_HIP(ctx, conv_pass(cd, ctx->taps, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm, ctx->alpha, ctx->beta,
-                             ctx->Qs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream));
-    COFEM_HIP(ctx, hipMemcpy2DAsync(q_probes, sizeof(float) * ctx->D, ctx->Qs, sizeof(float) * cd.ldD,
-                                    sizeof(float) * ctx->D, ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+    COFEM_HIP(ctx, conv_pass(cd, ctx->taps, ctx->vVs, ctx->Vsm, ctx->vVs, ctx->Vsm, ctx->alpha, ctx->beta,
+                             ctx->vQs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream));
+    COFEM_HIP(ctx, conv_probes_out(cd, ctx->vQs, q_probes, ctx->stream));
   }
   COFEM_HIP(ctx, hipMemcpyAsync(q_mean, ctx->Qsm, Dm, hipMemcpyDeviceToDevice, ctx->stream));
   COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -492,37 +526,38 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
 cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (reps < 1 || !ms_out) return fail(ctx, COFEM_ERR_INVALID_ARG, "reps < 1 or ms_out null");
-  float acc[3] = {0.f, 0.f, 0.f};
-  for (int r = 0; r < reps; ++r) {
+  // Each pass is launched `reps` times back to back between one pair of
+  // events, as the CG loop issues them, so the average is the kernel's
+  // duration plus the dispatch gap, not the latency of an isolated launch.
+  auto timed = [&](auto launch, float* out) -> cofem_status {
+    COFEM_HIP(ctx, launch());  // warm
+    COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    for (int r = 0; r < reps; ++r) COFEM_HIP(ctx, launch());
+    COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
     float ms = 0.f;
-    if (ctx->kind == COFEM_DENSE) {
-      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-      COFEM_HIP(ctx, dense_pass1(ctx->dd, ctx->phiA, ctx->P, ctx->pm, ctx->W, ctx->wm, ctx->st, 1,
-                                 ctx->stream));
-      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
-      COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      acc[0] += ms;
-      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-      COFEM_HIP(ctx, dense_pass2(ctx->dd, ctx->phiB, ctx->W, ctx->wm, ctx->P, ctx->pm, ctx->R, ctx->rm,
-                                 ctx->alpha, ctx->beta, ctx->Qs, ctx->Qsm, ctx->parts_pass, ctx->cnts_pass,
-                                 ctx->st, 1, ctx->stream));
-      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
-      COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      acc[1] += ms;
-    } else {
-      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-      COFEM_HIP(ctx, conv_pass(ctx->cd, ctx->taps, ctx->P, ctx->pm, ctx->R, ctx->rm, ctx->alpha, ctx->beta,
-                               ctx->Qs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream));
-      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
-      COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-      acc[0] += ms;
-    }
+    COFEM_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    *out = ms / (float)reps;
+    return COFEM_OK;
+  };
+  ms_out[0] = ms_out[1] = ms_out[2] = 0.f;
+  cofem_status rc;
+  if (ctx->kind == COFEM_DENSE) {
+    rc = timed([&] { return dense_pass1(ctx->dd, ctx->phiA, ctx->P, ctx->pm, ctx->Wpart, ctx->wmpart, ctx->W,
+                                        ctx->wm, ctx->cnt_split1, ctx->st, 1, ctx->stream); },
+               &ms_out[0]);
+    if (rc != COFEM_OK) return rc;
+    rc = timed([&] { return dense_pass2(ctx->dd, ctx->phiB, ctx->W, ctx->wm, ctx->P, ctx->pm, ctx->R, ctx->rm,
+                                        ctx->alpha, ctx->beta, ctx->Qpart, ctx->qmpart, ctx->Qs, ctx->Qsm,
+                                        ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1,
+                                        ctx->stream); },
+               &ms_out[1]);
+  } else {
+    rc = timed([&] { return conv_pass(ctx->cd, ctx->taps, ctx->vP, ctx->pm, ctx->vR, ctx->rm, ctx->alpha,
+                                      ctx->beta, ctx->vQs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream); },
+               &ms_out[0]);
   }
-  for (int i = 0; i < 3; ++i) ms_out[i] = acc[i] / (float)reps;
-  return COFEM_OK;
+  return rc;
 }
 
 void cofem_destroy(cofem_ctx* ctx) { destroy_ctx(ctx); }

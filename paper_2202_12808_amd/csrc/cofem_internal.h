@@ -302,7 +302,8 @@ __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
 // shape of v_mfma_f32_16x16x4f32).
 struct DenseDims {
   int64_t N, D, Np, Dp;
-  int waves1, waves2;  // waves per workgroup of pass 1 / pass 2
+  int S1, S2;  // workgroups sharing one tile's reduction in pass 1 / pass 2
+  int ring;    // outstanding 8-wide groups per wave (1, 2, 4 or 8)
 };
 
 __host__ __device__ __forceinline__ int64_t blk4(int64_t d, int c) {
@@ -317,15 +318,18 @@ hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const do
                       float* X, float* R, float* P, double* xm, double* rm, double* pm,
                       double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s);
 hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, const double* pm,
-                       float* W, double* wm, CgScalars* st, int apply_only, hipStream_t s);
+                       float* Wpart, double* wmpart, float* W, double* wm, uint32_t* cnts,
+                       CgScalars* st, int apply_only, hipStream_t s);
 hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, const double* wm,
                        const float* P, const double* pm, const float* R, const double* rm,
-                       const float* alpha, double beta, float* Q, double* qm, double* gpart,
-                       uint32_t* counter, CgScalars* st, int apply_only, hipStream_t s);
+                       const float* alpha, double beta, float* Qpart, double* qmpart, float* Q,
+                       double* qm, double* gpart, uint32_t* counter, uint32_t* split_cnts,
+                       CgScalars* st, int apply_only, hipStream_t s);
 hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
                         double* xm, double* rm, double* pm, const double* qm, double* parts,
                         uint32_t* cnts, CgScalars* st, hipStream_t s);
-int dense_pass_waves(int64_t tiles);
+int dense_split(int64_t tiles, int64_t groups);
+bool dense_split_ok(int64_t groups, int splits);
 hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,
                        const double* xm, float* alpha, double alpha_max, float* mu, float* sdiag,
                        CgScalars* st, hipStream_t s);
@@ -336,8 +340,9 @@ int dense_update_blocks(const DenseDims& dd);
 struct ConvDims {
   int H, W, ks;      // square odd kernel side
   int64_t D, ldD;    // D = H*W, ldD = D rounded up to 256
-  int K;             // probe columns (column-major blocks of ldD floats)
+  int K;             // probe columns (column-major blocks of ldD elements)
   int tilesX, tilesY;
+  int fp64;          // probe columns in float64 (else float32)
 };
 
 hipError_t conv_b0(const ConvDims& cd, const float* taps, const float* y, double beta, double* b0,
@@ -350,18 +355,21 @@ struct ConvReduce {
   uint32_t* cnt_cols; // 1 counter
 };
 
-hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, float* X, float* R,
-                     float* P, double* xm, double* rm, double* pm, const ConvReduce& red,
+// Probe-column blocks are float or double according to cd.fp64.
+hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, void* X, void* R,
+                     void* P, double* xm, double* rm, double* pm, const ConvReduce& red,
                      CgScalars* st, hipStream_t s);
-hipError_t conv_pass(const ConvDims& cd, const float* taps, const float* P, const double* pm,
-                     const float* R, const double* rm, const float* alpha, double beta, float* Q,
+hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
+                     const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s);
-hipError_t conv_update(const ConvDims& cd, float* X, float* R, float* P, const float* Q,
-                       double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
+hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void* Q, double* xm,
+                       double* rm, double* pm, const double* qm, const ConvReduce& red,
                        CgScalars* st, hipStream_t s);
-hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const float* X, const double* xm,
+hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
                       float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
                       hipStream_t s);
+hipError_t conv_probes_out(const ConvDims& cd, const void* X, float* out, hipStream_t s);
+hipError_t conv_probes_in(const ConvDims& cd, const float* in, void* X, hipStream_t s);
 
 hipError_t probe_signs_colmajor(uint64_t seed, int t, int K, int64_t D, float* out, hipStream_t s);
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);

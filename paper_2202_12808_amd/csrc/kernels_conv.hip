@@ -14,7 +14,8 @@
 // does x += a p, r -= a q and p <- r + b p in one sweep.
 //
 // State layout: probe columns are column-major images (column k at k * ldD,
-// pixel j = u * W + v); the mean column is a float64 image.
+// pixel j = u * W + v) of type TP (float, or double in the float64 mode); the
+// mean column is always a float64 image.
 #include "cofem_internal.h"
 
 namespace cofem {
@@ -119,11 +120,11 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ taps, int H,
   dots[2] = et;
 }
 
-template <int KS>
+template <int KS, typename TP>
 __global__ __launch_bounds__(256) void k_conv_pass(
-    const float* __restrict__ taps, int H, int W, int64_t ldD, int K, const float* __restrict__ P,
-    const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
-    const float* __restrict__ alpha, double beta, float* __restrict__ Q, double* __restrict__ qm,
+    const float* __restrict__ taps, int H, int W, int64_t ldD, int K, const TP* __restrict__ P,
+    const double* __restrict__ pm, const TP* __restrict__ R, const double* __restrict__ rm,
+    const float* __restrict__ alpha, double beta, TP* __restrict__ Q, double* __restrict__ qm,
     ConvReduce red, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
   using G = ConvGeom<KS>;
@@ -135,10 +136,10 @@ __global__ __launch_bounds__(256) void k_conv_pass(
     conv_tile<KS, double>(taps, H, W, tu0, tv0, pm, rm, alpha, beta, qm, sbuf,
                           sbuf + G::spH * G::spW, dots);
   } else {
-    float* sf = reinterpret_cast<float*>(sbuf);
+    TP* sb = reinterpret_cast<TP*>(sbuf);
     const int64_t off = (int64_t)col * ldD;
-    conv_tile<KS, float>(taps, H, W, tu0, tv0, P + off, R + off, alpha, (float)beta, Q + off, sf,
-                         sf + G::spH * G::spW, dots);
+    conv_tile<KS, TP>(taps, H, W, tu0, tv0, P + off, R + off, alpha, (TP)beta, Q + off, sb,
+                      sb + G::spH * G::spW, dots);
   }
   if (apply_only) return;
   __shared__ double shm[8];
@@ -160,14 +161,19 @@ __global__ __launch_bounds__(256) void k_conv_pass(
   finish_step(st, tot);
 }
 
-hipError_t conv_pass(const ConvDims& cd, const float* taps, const float* P, const double* pm,
-                     const float* R, const double* rm, const float* alpha, double beta, float* Q,
-                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
+template <typename TP>
+static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const void* P,
+                                   const double* pm, const void* R, const double* rm,
+                                   const float* alpha, double beta, void* Q, double* qm,
+                                   const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
   const dim3 grid(cd.tilesX, cd.tilesY, cd.K + 1);
-#define COFEM_CONV_CASE(KS)                                                                       \
-  case KS:                                                                                        \
-    hipLaunchKernelGGL(k_conv_pass<KS>, grid, dim3(256), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K, P, \
-                       pm, R, rm, alpha, beta, Q, qm, red, st, apply_only);                     \
+  const TP* Pt = static_cast<const TP*>(P);
+  const TP* Rt = static_cast<const TP*>(R);
+  TP* Qt = static_cast<TP*>(Q);
+#define COFEM_CONV_CASE(KS)                                                                           \
+  case KS:                                                                                            \
+    hipLaunchKernelGGL((k_conv_pass<KS, TP>), grid, dim3(256), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K, Pt, \
+                       pm, Rt, rm, alpha, beta, Qt, qm, red, st, apply_only);                         \
     break;
   switch (cd.ks) {
     COFEM_CONV_CASE(1)
@@ -180,6 +186,14 @@ hipError_t conv_pass(const ConvDims& cd, const float* taps, const float* P, cons
   }
 #undef COFEM_CONV_CASE
   return hipGetLastError();
+}
+
+hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
+                     const void* R, const double* rm, const float* alpha, double beta, void* Q,
+                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
+  if (cd.fp64)
+    return launch_conv_pass<double>(cd, taps, P, pm, R, rm, alpha, beta, Q, qm, red, st, apply_only, s);
+  return launch_conv_pass<float>(cd, taps, P, pm, R, rm, alpha, beta, Q, qm, red, st, apply_only, s);
 }
 
 // ------------------------------------------------ b0 = beta Phi^T y (Eq. 5), float64
@@ -212,14 +226,14 @@ int conv_update_blocks(const ConvDims& cd) {
   return (int)(want < 1 ? 1 : (want > 256 ? 256 : want));
 }
 
-// ------------------------------------------------ initial residual R = B (Eq. 7)
+// ------------------------------------------------ initial residual R = P = B (Eq. 7)
+template <typename TP>
 __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K, uint64_t seed,
                                                    int t, const double* __restrict__ b0,
-                                                   float* __restrict__ X, float* __restrict__ R,
-                                                   float* __restrict__ P,
-                                                   double* __restrict__ xm, double* __restrict__ rm,
-                                                   double* __restrict__ pm, ConvReduce red,
-                                                   CgScalars* st) {
+                                                   TP* __restrict__ X, TP* __restrict__ R,
+                                                   TP* __restrict__ P, double* __restrict__ xm,
+                                                   double* __restrict__ rm, double* __restrict__ pm,
+                                                   ConvReduce red, CgScalars* st) {
   const int col = blockIdx.y;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
@@ -235,10 +249,10 @@ __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K
   } else {
     const int64_t off = (int64_t)col * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const float v = probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d);
+      const TP v = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d);
       R[off + d] = v;
       P[off + d] = v;
-      X[off + d] = 0.0f;
+      X[off + d] = TP(0);
       acc += 1.0;
     }
   }
@@ -253,20 +267,45 @@ __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K
   finish_init(st, tot);
 }
 
-hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, float* X, float* R,
-                     float* P, double* xm, double* rm, double* pm, const ConvReduce& red,
+hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, void* X, void* R,
+                     void* P, double* xm, double* rm, double* pm, const ConvReduce& red,
                      CgScalars* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv_init, dim3(conv_update_blocks(cd), cd.K + 1), dim3(256), 0, s, cd.D,
-                     cd.ldD, cd.K, seed, t, b0, X, R, P, xm, rm, pm, red, st);
+  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_init<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+                       static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P), xm,
+                       rm, pm, red, st);
+  else
+    hipLaunchKernelGGL(k_conv_init<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+                       static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P), xm, rm,
+                       pm, red, st);
   return hipGetLastError();
 }
 
 // ------------------------------------------------ CG update
 // x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2 and the stop test.
+template <typename T>
+__device__ __forceinline__ double conv_update_column(int64_t D, T* __restrict__ X, T* __restrict__ R,
+                                                     T* __restrict__ P, const T* __restrict__ Q,
+                                                     T a, T b) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  for (int64_t d = gtid; d < D; d += gstride) {
+    const T p = P[d];
+    X[d] = fma(a, p, X[d]);
+    const T r = fma(-a, Q[d], R[d]);
+    R[d] = r;
+    P[d] = fma(b, p, r);
+    acc += (double)r * (double)r;
+  }
+  return acc;
+}
+
+template <typename TP>
 __global__ __launch_bounds__(256) void k_conv_update(int64_t D, int64_t ldD, int K,
-                                                     float* __restrict__ X, float* __restrict__ R,
-                                                     float* __restrict__ P,
-                                                     const float* __restrict__ Q,
+                                                     TP* __restrict__ X, TP* __restrict__ R,
+                                                     TP* __restrict__ P, const TP* __restrict__ Q,
                                                      double* __restrict__ xm,
                                                      double* __restrict__ rm,
                                                      double* __restrict__ pm,
@@ -274,30 +313,12 @@ __global__ __launch_bounds__(256) void k_conv_update(int64_t D, int64_t ldD, int
                                                      CgScalars* st) {
   if (st->stop) return;
   const int col = blockIdx.y;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
-  double acc = 0.0;
+  double acc;
   if (col == K) {
-    const double am = st->a[K], bm = st->b[K];
-    for (int64_t d = gtid; d < D; d += gstride) {
-      const double p = pm[d];
-      xm[d] = fma(am, p, xm[d]);
-      const double r = fma(-am, qm[d], rm[d]);
-      rm[d] = r;
-      pm[d] = fma(bm, p, r);
-      acc += r * r;
-    }
+    acc = conv_update_column<double>(D, xm, rm, pm, qm, st->a[K], st->b[K]);
   } else {
-    const float a = (float)st->a[col], b = (float)st->b[col];
     const int64_t off = (int64_t)col * ldD;
-    for (int64_t d = gtid; d < D; d += gstride) {
-      const float p = P[off + d];
-      X[off + d] = fmaf(a, p, X[off + d]);
-      const float r = fmaf(-a, Q[off + d], R[off + d]);
-      R[off + d] = r;
-      P[off + d] = fmaf(b, p, r);
-      acc += (double)r * (double)r;
-    }
+    acc = conv_update_column<TP>(D, X + off, R + off, P + off, Q + off, (TP)st->a[col], (TP)st->b[col]);
   }
   __shared__ double shm[8];
   __shared__ double mine[1], tot[kMaxCols];
@@ -310,17 +331,25 @@ __global__ __launch_bounds__(256) void k_conv_update(int64_t D, int64_t ldD, int
   finish_update(st, tot);
 }
 
-hipError_t conv_update(const ConvDims& cd, float* X, float* R, float* P, const float* Q,
-                       double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
+hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void* Q, double* xm,
+                       double* rm, double* pm, const double* qm, const ConvReduce& red,
                        CgScalars* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv_update, dim3(conv_update_blocks(cd), cd.K + 1), dim3(256), 0, s, cd.D,
-                     cd.ldD, cd.K, X, R, P, Q, xm, rm, pm, qm, red, st);
+  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_update<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K,
+                       static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P),
+                       static_cast<const double*>(Q), xm, rm, pm, qm, red, st);
+  else
+    hipLaunchKernelGGL(k_conv_update<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K,
+                       static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P),
+                       static_cast<const float*>(Q), xm, rm, pm, qm, red, st);
   return hipGetLastError();
 }
 
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
+template <typename TP>
 __global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, uint64_t seed,
-                                                    int t, const float* __restrict__ X,
+                                                    int t, const TP* __restrict__ X,
                                                     const double* __restrict__ xm,
                                                     float* __restrict__ alpha, double alpha_max,
                                                     float* __restrict__ mu,
@@ -346,13 +375,52 @@ __global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int 
   if (threadIdx.x == 0 && tot > 0.0) atomicAdd(&st->n_clamped, (int)tot);
 }
 
-hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const float* X, const double* xm,
+hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
                       float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
                       hipStream_t s) {
   const int64_t want = (cd.D + 255) / 256;
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
-  hipLaunchKernelGGL(k_conv_mstep, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, X, xm,
-                     alpha, alpha_max, mu, sdiag, st);
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t,
+                       static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, st);
+  else
+    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t,
+                       static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ strided copies between the caller's
+// float32 D x K blocks and the probe state (float or double, leading dimension ldD)
+template <typename TS, typename TD>
+__global__ void k_copy_cols(int64_t D, int K, const TS* __restrict__ src, int64_t lds,
+                            TD* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D * K) return;
+  const int64_t k = idx / D, d = idx % D;
+  dst[k * ldd + d] = (TD)src[k * lds + d];
+}
+
+hipError_t conv_probes_out(const ConvDims& cd, const void* X, float* out, hipStream_t s) {
+  const int64_t tot = cd.D * cd.K;
+  const dim3 grid((unsigned)((tot + 255) / 256));
+  if (cd.fp64)
+    hipLaunchKernelGGL((k_copy_cols<double, float>), grid, dim3(256), 0, s, cd.D, cd.K,
+                       static_cast<const double*>(X), cd.ldD, out, cd.D);
+  else
+    hipLaunchKernelGGL((k_copy_cols<float, float>), grid, dim3(256), 0, s, cd.D, cd.K,
+                       static_cast<const float*>(X), cd.ldD, out, cd.D);
+  return hipGetLastError();
+}
+
+hipError_t conv_probes_in(const ConvDims& cd, const float* in, void* X, hipStream_t s) {
+  const int64_t tot = cd.D * cd.K;
+  const dim3 grid((unsigned)((tot + 255) / 256));
+  if (cd.fp64)
+    hipLaunchKernelGGL((k_copy_cols<float, double>), grid, dim3(256), 0, s, cd.D, cd.K, in, cd.D,
+                       static_cast<double*>(X), cd.ldD);
+  else
+    hipLaunchKernelGGL((k_copy_cols<float, float>), grid, dim3(256), 0, s, cd.D, cd.K, in, cd.D,
+                       static_cast<float*>(X), cd.ldD);
   return hipGetLastError();
 }
 

