@@ -8,8 +8,11 @@ EM iterations per second over the timed steps.
 
 Besides the throughput line the JSON carries:
   roofline      the dominant operator kernel's achieved HBM bandwidth
-                (algorithmic bytes per launch / mean launch time, HIP events on
-                the library's stream) against the 8 TB/s MI355X peak;
+                (algorithmic bytes per launch / mean launch time, from HIP
+                events the library records on its stream before every launch
+                during the timed steps) against the 8 TB/s MI355X peak, and
+                the counter-measured HBM bytes per launch when a stored
+                rocprofv3 summary matches the current kernel source;
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the
                 first E-step, its CG iteration count fixed to the GPU's),
                 scaled to EM iterations per second with the GPU's mean CG count;
@@ -51,6 +54,37 @@ def algorithmic_bytes(p, which):
     return 3 * D * col + 4 * D
 
 
+KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "update": "k_dense_update"},
+                "conv": {"pass1": "k_conv_pass", "update": "k_conv_update"}}
+KERNEL_SOURCES = {"dense": "paper_2202_12808_amd/csrc/kernels_dense.hip",
+                  "conv": "paper_2202_12808_amd/csrc/kernels_conv.hip"}
+
+
+def stored_traffic(kind, kernel, workload):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    kept in profiles/, or None when there is none or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    with open(os.path.join(ROOT, KERNEL_SOURCES[kind]), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        log(f"{path}: kernel source changed since the counters were taken; traffic reported as null")
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +95,10 @@ def main():
     ap.add_argument("--em-iters", type=int, default=0, help="EM iterations per step (default: workload's)")
     ap.add_argument("--timing-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without the per-launch events (roofline from cofem_time_operator)")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +130,15 @@ def main():
         taps = torch.from_numpy(p.taps).to(dev)
         g = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
     ones = torch.ones(p.D, dtype=torch.float32, device=dev)
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration: 3 copies of {4 * n} bytes")
+        del src, dst
 
     def one_step():
         g.set_alpha(ones)
@@ -108,6 +155,7 @@ def main():
         st = one_step()
         log(f"warmup {w + 1}/{args.warmup}: cg iters {sum(x['cg_iters'] for x in st)}")
 
+    g.set_kernel_timing(not args.no_kernel_timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     all_stats = []
@@ -125,23 +173,34 @@ def main():
     log(f"{value:.3f} EM it/s; CG iterations per EM iteration: mean {mean_cg:.1f}, "
         f"min {min(cg_counts)}, max {max(cg_counts)}; NRMSE vs ground truth {nrmse:.4f}")
 
-    # roofline of the dominant operator kernel
-    ms = g.time_operator(args.timing_reps)
-    if p.kind == "dense":
-        kern = {"pass1": ms[0], "pass2": ms[1]}
-        names = {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2"}
+    # roofline of the dominant operator kernel: mean launch time inside the
+    # timed solves (events recorded by the library on its stream)
+    names = KERNEL_NAMES[p.kind]
+    ops = [k for k in ("pass1", "pass2") if k in names]
+    if not args.no_kernel_timing:
+        kt = g.kernel_timing()
+        g.set_kernel_timing(False)
+        total = {k: kt[k][0] for k in names}
+        per = {k: kt[k][0] / max(kt[k][1], 1) for k in names}
+        launches = {k: kt[k][1] for k in names}
+        source = "HIP events before every launch during the timed steps"
     else:
-        kern = {"pass": ms[0]}
-        names = {"pass": "k_conv_pass"}
-    dom = max(kern, key=kern.get)
+        ms = g.time_operator(args.timing_reps)
+        per = {k: ms[i] for i, k in enumerate(ops)}
+        total, launches = dict(per), {k: args.timing_reps for k in ops}
+        source = "cofem_time_operator back-to-back launches"
+    dom = max(ops, key=lambda k: total[k])
     nbytes = algorithmic_bytes(p, dom)
-    achieved = nbytes / (kern[dom] * 1e-3) / 1e9
+    achieved = nbytes / (per[dom] * 1e-3) / 1e9
+    traffic = stored_traffic(p.kind, names[dom], p.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": names[dom],
-                "bytes_per_launch": nbytes, "ms_per_launch": round(kern[dom], 5),
-                "all_kernels_ms": {names[k]: round(v, 5) for k, v in kern.items()}}
-    log(f"roofline: {names[dom]} {kern[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
-        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[dom],
+                "bytes_per_launch": nbytes, "ms_per_launch": round(per[dom], 5), "timing": source,
+                "kernels": {names[k]: {"ms_per_launch": round(per[k], 5), "launches": launches[k]}
+                            for k in per}}
+    log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
+        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak); per-launch us "
+        + ", ".join(f"{names[k]} {per[k] * 1e3:.1f}" for k in per))
 
     cpu = None
     parity = None

@@ -197,6 +197,33 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
  */
 cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out);
 
+/* Kernel slots of cofem_get_kernel_timing. */
+enum {
+  COFEM_KT_PASS1 = 0,  /* dense: W = Phi P;  conv: the fused stencil pass */
+  COFEM_KT_PASS2 = 1,  /* dense: Q = beta Phi^T W + alpha P with the CG dots */
+  COFEM_KT_UPDATE = 2, /* CG update x, r, p and the new residual norms */
+  COFEM_KT_INIT = 3,   /* probes, R = P = B, X = 0 */
+  COFEM_KT_MSTEP = 4,  /* diagonal estimate and M-step */
+  COFEM_KT_SLOTS = 5
+};
+
+/*
+ * Measurement support inside the solver itself.  enable != 0 makes every
+ * following cofem_em_step record a HIP event on the context's stream before
+ * each kernel launch (and one after the last), and resets the totals; 0 turns
+ * the recording off.  A launch lasts from its event to the next one, so a
+ * duration includes the dispatch gap.  CG launches enqueued after the solve
+ * stopped (they return at once) are not counted.
+ */
+cofem_status cofem_set_kernel_timing(cofem_ctx* ctx, int32_t enable);
+
+/*
+ * Totals since the last cofem_set_kernel_timing: ms_total[slot] is the summed
+ * duration in milliseconds and launches[slot] the number of launches counted,
+ * for the COFEM_KT_* slots (host arrays of COFEM_KT_SLOTS entries each).
+ */
+cofem_status cofem_get_kernel_timing(cofem_ctx* ctx, double* ms_total, int64_t* launches);
+
 /* Frees every device buffer of the context (after synchronising its stream). */
 void cofem_destroy(cofem_ctx* ctx);
 

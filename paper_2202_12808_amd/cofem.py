@@ -78,6 +78,8 @@ _SIGNATURES = {
     "cofem_apply_A": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cofem_probe_signs": (c_int32, [c_uint64, c_int32, c_int32, c_int64, c_void_p, c_void_p]),
     "cofem_time_operator": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float)]),
+    "cofem_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
+    "cofem_get_kernel_timing": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(c_int64)]),
     "cofem_destroy": (None, [c_void_p]),
     "cofem_last_error": (c_char_p, [c_void_p]),
     "cofem_status_string": (c_char_p, [c_int32]),
@@ -167,6 +169,21 @@ def cofem_time_operator(ctx, reps: int):
     out = (ctypes.c_float * 3)()
     _check(load().cofem_time_operator(ctx, reps, out), ctx)
     return [float(out[i]) for i in range(3)]
+
+
+KERNEL_SLOTS = ("pass1", "pass2", "update", "init", "mstep")  # COFEM_KT_* order
+
+
+def cofem_set_kernel_timing(ctx, enable: bool):
+    _check(load().cofem_set_kernel_timing(ctx, 1 if enable else 0), ctx)
+
+
+def cofem_get_kernel_timing(ctx):
+    """{slot: (total ms, launches)} since the last cofem_set_kernel_timing."""
+    ms = (ctypes.c_double * len(KERNEL_SLOTS))()
+    n = (c_int64 * len(KERNEL_SLOTS))()
+    _check(load().cofem_get_kernel_timing(ctx, ms, n), ctx)
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_SLOTS)}
 
 
 def cofem_destroy(ctx):
@@ -273,6 +290,12 @@ class CoFEM:
 
     def time_operator(self, reps=20):
         return cofem_time_operator(self.ctx, reps)
+
+    def set_kernel_timing(self, enable=True):
+        cofem_set_kernel_timing(self.ctx, enable)
+
+    def kernel_timing(self):
+        return cofem_get_kernel_timing(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

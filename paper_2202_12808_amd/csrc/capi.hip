@@ -69,6 +69,14 @@ struct cofem_ctx {
   // outputs of the last E-step / M-step
   float *mu = nullptr, *sdiag = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // optional per-kernel timing: one event before each launch of a solve
+  bool ktime = false;
+  std::vector<hipEvent_t> kev;
+  std::vector<int> kev_slot, kev_iter;  // kernel slot and CG iteration of launch i
+  size_t kev_used = 0;
+  double kt_ms[COFEM_KT_SLOTS] = {};
+  int64_t kt_n[COFEM_KT_SLOTS] = {};
+  int cg_enq = 0;  // CG iterations enqueued in the current solve
   std::string err;
 };
 
@@ -123,6 +131,7 @@ void destroy_ctx(cofem_ctx* c) {
   if (c->host_st) (void)hipHostFree(c->host_st);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -296,19 +305,67 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   return COFEM_OK;
 }
 
+// Kernel timing: an event is recorded before every launch (and one after the
+// last); launch i lasts from event i to event i + 1, dispatch gap included.
+cofem_status mark(cofem_ctx* c, int slot, int iter) {
+  if (!c->ktime) return COFEM_OK;
+  if (c->kev_used == c->kev.size()) {
+    hipEvent_t e;
+    // timing only: no system-scope fence (cache writeback) at each record
+    COFEM_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    c->kev.push_back(e);
+    c->kev_slot.push_back(0);
+    c->kev_iter.push_back(0);
+  }
+  COFEM_HIP(c, hipEventRecord(c->kev[c->kev_used], c->stream));
+  c->kev_slot[c->kev_used] = slot;
+  c->kev_iter[c->kev_used] = iter;
+  ++c->kev_used;
+  return COFEM_OK;
+}
+
+// Adds the recorded launches of a finished EM iteration to the totals.  CG
+// launches enqueued after the solve stopped (they return at once) are not
+// counted: `iters` is the solve's CG count.
+cofem_status collect_times(cofem_ctx* c, int iters) {
+  if (!c->ktime || c->kev_used < 2) {
+    c->kev_used = 0;
+    return COFEM_OK;
+  }
+  COFEM_HIP(c, hipEventSynchronize(c->kev[c->kev_used - 1]));
+  for (size_t i = 0; i + 1 < c->kev_used; ++i) {
+    const int slot = c->kev_slot[i];
+    if (slot < 0 || slot >= COFEM_KT_SLOTS) continue;
+    if ((slot == COFEM_KT_PASS1 || slot == COFEM_KT_PASS2 || slot == COFEM_KT_UPDATE) && c->kev_iter[i] >= iters)
+      continue;
+    float ms = 0.f;
+    COFEM_HIP(c, hipEventElapsedTime(&ms, c->kev[i], c->kev[i + 1]));
+    c->kt_ms[slot] += ms;
+    c->kt_n[slot] += 1;
+  }
+  c->kev_used = 0;
+  return COFEM_OK;
+}
+
 cofem_status run_cg_iterations(cofem_ctx* c, int n) {
   for (int i = 0; i < n; ++i) {
+    const int it = c->cg_enq++;
     if (c->kind == COFEM_DENSE) {
+      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
       COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
                                c->cnt_split1, c->st, 0, c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dense_pass2(c->dd, c->phiB, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
                                c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
                                c->cnt_split2, c->st, 0, c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
     } else {
+      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
       COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
                              c->red_pass, c->st, 0, c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, conv_update(c->cd, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm, c->red_upd,
                                c->st, c->stream));
     }
@@ -325,6 +382,9 @@ cofem_status read_state(cofem_ctx* c) {
 cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   const int t = c->t_next;
   COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  c->cg_enq = 0;
+  c->kev_used = 0;
+  COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_init(c->dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm,
                             c->parts_init, c->cnts_init, c->st, c->stream));
@@ -349,14 +409,17 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   }
   if (c->host_st->numeric_error)
     return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
+  COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
                              c->sdiag, c->st, c->stream));
   else
     COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
                             c->st, c->stream));
+  COFEM_TRY(mark(c, -1, 0));
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
   COFEM_TRY(read_state(c));
+  COFEM_TRY(collect_times(c, c->host_st->iter));
   c->has_solution = true;
   c->prev_iters = c->host_st->iter;
   c->t_next = t + 1;
@@ -558,6 +621,27 @@ cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
                &ms_out[0]);
   }
   return rc;
+}
+
+cofem_status cofem_set_kernel_timing(cofem_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  ctx->ktime = enable != 0;
+  ctx->kev_used = 0;
+  for (int i = 0; i < COFEM_KT_SLOTS; ++i) {
+    ctx->kt_ms[i] = 0.0;
+    ctx->kt_n[i] = 0;
+  }
+  return COFEM_OK;
+}
+
+cofem_status cofem_get_kernel_timing(cofem_ctx* ctx, double* ms_total, int64_t* launches) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (!ms_total || !launches) return fail(ctx, COFEM_ERR_INVALID_ARG, "null output array");
+  for (int i = 0; i < COFEM_KT_SLOTS; ++i) {
+    ms_total[i] = ctx->kt_ms[i];
+    launches[i] = ctx->kt_n[i];
+  }
+  return COFEM_OK;
 }
 
 void cofem_destroy(cofem_ctx* ctx) { destroy_ctx(ctx); }

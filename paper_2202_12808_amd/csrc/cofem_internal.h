@@ -171,14 +171,13 @@ __device__ __forceinline__ bool tree_reduce(double* parts, uint32_t* cnts, int64
     if (!last_block_ticket(&c[g], (uint32_t)gs)) return false;
     double v = 0.0;
     if (tid < ncols) {
-      for (int i0 = 0; i0 < gs; i0 += 8) {
-        double t[8];
+      // all (up to 32) loads in flight at once, summed in block order
+      double t[32];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          t[u] = (i0 + u < gs) ? load_agent(&p[(base + i0 + u) * ncols + tid]) : 0.0;
+      for (int u = 0; u < 32; ++u) t[u] = load_agent(&p[(base + (u < gs ? u : 0)) * ncols + tid]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v += t[u];
-      }
+      for (int u = 0; u < 32; ++u)
+        if (u < gs) v += t[u];
     }
     if (tid == 0) store_agent(&c[g], 0u);
     const int64_t ng = (n + 31) / 32;
@@ -221,24 +220,29 @@ __device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts
   return true;
 }
 
-// Finishes a CG update: called by the last block, all threads, after the new
-// ||r_c||^2 is in shared memory for every column 0..kp.  Applies the stop test
-// of the solve (joint Frobenius ratio of the recursive residual, or the cap).
+// The finish_* helpers run in the last block of a reduction, all threads,
+// with the per-column totals in shared memory.  Column c is handled by thread
+// c, so the loads of the scalar block are issued together (one round trip to
+// device-coherent memory, not one per column); column sums are formed by
+// thread 0 from shared memory in column order.
+
+// Finishes a CG update: the new ||r_c||^2 for columns 0..kp.  Applies the stop
+// test of the solve (joint Frobenius ratio of the recursive residual, or the
+// cap).
 __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho) {
+  const int nc = st->kp + 1;
+  if ((int)threadIdx.x < nc) st->rho[threadIdx.x] = new_rho[threadIdx.x];
   if (threadIdx.x == 0) {
-    const int nc = st->kp + 1;
+    const double nB = st->nB, tol = st->tol;
+    const int it = st->iter + 1, limit = st->limit, fixed = st->fixed;
     double sum = 0.0;
-    for (int c = 0; c < nc; ++c) {
-      st->rho[c] = new_rho[c];
-      sum += new_rho[c];
-    }
+    for (int c = 0; c < nc; ++c) sum += new_rho[c];
     const bool finite = isfinite(sum);
     if (!finite) st->numeric_error = 1;
-    const double ratio = st->nB > 0.0 ? sqrt(sum) / st->nB : 0.0;
+    const double ratio = nB > 0.0 ? sqrt(sum) / nB : 0.0;
     st->ratio = ratio;
-    const int it = st->iter + 1;
     st->iter = it;
-    st->stop = (it >= st->limit) || (!st->fixed && ratio < st->tol) || !finite;
+    st->stop = (it >= limit) || (!fixed && ratio < tol) || !finite;
   }
 }
 
@@ -250,47 +254,50 @@ __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_r
 // (the same value Hestenes-Stiefel CG forms after the residual update; known
 // here one kernel earlier so the update kernel can also form p <- r + b p).
 __device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
-  if (threadIdx.x == 0) {
-    const int nc = st->kp + 1;
-    bool finite = true;
-    for (int c = 0; c < nc; ++c) {
-      const double g = dots[c], dl = dots[nc + c], et = dots[2 * nc + c];
-      const double rho = st->rho[c];
-      const double a = (g != 0.0) ? rho / g : 0.0;
-      st->gam[c] = g;
-      st->del[c] = dl;
-      st->eta[c] = et;
-      st->a[c] = a;
-      double rn = rho - 2.0 * a * dl + a * a * et;
-      if (rn < 0.0) rn = 0.0;
-      st->b[c] = (rho != 0.0) ? rn / rho : 0.0;
-      finite = finite && isfinite(g) && isfinite(dl) && isfinite(et);
-    }
-    if (!finite) {
-      st->numeric_error = 1;
-      st->stop = 1;
-    }
+  __shared__ int s_bad;
+  const int nc = st->kp + 1;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < nc) {
+    const double g = dots[c], dl = dots[nc + c], et = dots[2 * nc + c];
+    const double rho = st->rho[c];
+    const double a = (g != 0.0) ? rho / g : 0.0;
+    st->gam[c] = g;
+    st->del[c] = dl;
+    st->eta[c] = et;
+    st->a[c] = a;
+    double rn = rho - 2.0 * a * dl + a * a * et;
+    if (rn < 0.0) rn = 0.0;
+    st->b[c] = (rho != 0.0) ? rn / rho : 0.0;
+    if (!(isfinite(g) && isfinite(dl) && isfinite(et))) s_bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_bad) {
+    st->numeric_error = 1;
+    st->stop = 1;
   }
 }
 
 // Finishes the initial residual R = B: rho_c = ||b_c||^2 (in shared memory).
 __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
+  const int nc = st->kp + 1;
+  if ((int)threadIdx.x < nc) {
+    st->rho[threadIdx.x] = rho[threadIdx.x];
+    st->b[threadIdx.x] = 0.0;
+    st->a[threadIdx.x] = 0.0;
+  }
   if (threadIdx.x == 0) {
-    const int nc = st->kp + 1;
+    const int limit = st->limit, fixed = st->fixed;
+    const double tol = st->tol;
     double sum = 0.0;
-    for (int c = 0; c < nc; ++c) {
-      st->rho[c] = rho[c];
-      st->b[c] = 0.0;
-      st->a[c] = 0.0;
-      sum += rho[c];
-    }
+    for (int c = 0; c < nc; ++c) sum += rho[c];
     st->nB = sqrt(sum);
     st->ratio = sum > 0.0 ? 1.0 : 0.0;
     st->iter = 0;
     st->n_clamped = 0;
     st->numeric_error = isfinite(sum) ? 0 : 1;
-    st->stop = (sum == 0.0) || (st->limit <= 0) || (!st->fixed && st->ratio < st->tol) ||
-               !isfinite(sum);
+    st->stop = (sum == 0.0) || (limit <= 0) || (!fixed && 1.0 < tol) || !isfinite(sum);
   }
 }
 

@@ -314,18 +314,40 @@ __device__ __forceinline__ bool split_reduce32(int nsplit, int split, int64_t ro
   }
   if (e < 32) store_agent(&partm[(int64_t)split * rows_total + row0 + e], *vm);
   if (!last_block_ticket(counter, (uint32_t)nsplit)) return false;
+  // partials loaded four splits at a time (16 loads in flight), summed in
+  // split order
   if (e < 256) {
     float t[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int sp = 0; sp < nsplit; ++sp) {
-      const float* src = part + ((int64_t)sp * (rows_total / 4) * 32 + tile_f4(row0, e)) * 4;
+    for (int sp0 = 0; sp0 < nsplit; sp0 += 4) {
+      float x[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) t[q] += load_agent(src + q);
+      for (int u = 0; u < 4; ++u) {
+        const int sp = sp0 + u < nsplit ? sp0 + u : sp0;
+        const float* src = part + ((int64_t)sp * (rows_total / 4) * 32 + tile_f4(row0, e)) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[u][q] = load_agent(src + q);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (sp0 + u < nsplit)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t[q] += x[u][q];
     }
     *v = make_float4(t[0], t[1], t[2], t[3]);
   }
   if (e < 32) {
     double t = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) t += load_agent(&partm[(int64_t)sp * rows_total + row0 + e]);
+    for (int sp0 = 0; sp0 < nsplit; sp0 += 4) {
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int sp = sp0 + u < nsplit ? sp0 + u : sp0;
+        x[u] = load_agent(&partm[(int64_t)sp * rows_total + row0 + e]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (sp0 + u < nsplit) t += x[u];
+    }
     *vm = t;
   }
   if (e == 0) store_agent(counter, 0u);
