@@ -56,15 +56,23 @@ def algorithmic_bytes(p, which):
 
 KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "update": "k_dense_update"},
                 "conv": {"pass1": "k_conv_pass", "update": "k_conv_update"}}
-KERNEL_SOURCES = {"dense": "paper_2202_12808_amd/csrc/kernels_dense.hip",
-                  "conv": "paper_2202_12808_amd/csrc/kernels_conv.hip"}
+KERNEL_SOURCES = {"dense": ("paper_2202_12808_amd/csrc/kernels_dense.hip", "paper_2202_12808_amd/csrc/cofem_internal.h"),
+                  "conv": ("paper_2202_12808_amd/csrc/kernels_conv.hip", "paper_2202_12808_amd/csrc/cofem_internal.h")}
+
+
+def kernel_source_sha256(kind):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def stored_traffic(kind, kernel, workload):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary
     kept in profiles/, or None when there is none or the kernel source has
     changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
@@ -74,9 +82,7 @@ def stored_traffic(kind, kernel, workload):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    with open(os.path.join(ROOT, KERNEL_SOURCES[kind]), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
+    if fields.get("kernel_source_sha256") != kernel_source_sha256(kind):
         log(f"{path}: kernel source changed since the counters were taken; traffic reported as null")
         return None
     try:
