@@ -61,6 +61,14 @@ enum { COFEM_PREC_FP32 = 0, COFEM_PREC_BF16_IR = 1, COFEM_PREC_FP64 = 2 };
 /* cofem_params.stop_rule */
 enum { COFEM_STOP_FROBENIUS = 0 };
 
+/* cofem_params.flags */
+enum {
+  /* After each CG solve, form the true residual ||B - A X||_F / ||B||_F with
+   * one more operator application over X and float64 sums (reported in
+   * cofem_iter_stats.rel_resid_true; costs one CG iteration's operator). */
+  COFEM_FLAG_TRUE_RESIDUAL = 1
+};
+
 /* Maximum number of probe vectors K per problem. */
 #define COFEM_MAX_K 32
 
@@ -120,6 +128,8 @@ typedef struct cofem_iter_stats {
   int32_t n_clamped;   /* coordinates whose M-step denominator hit the floor */
   double rel_resid;    /* recursive ||R||_F / ||B||_F at exit */
   double ms;           /* wall time of this EM iteration (device events) */
+  double rel_resid_true; /* ||B - A X||_F / ||B||_F at exit, float64 sums
+                            (COFEM_FLAG_TRUE_RESIDUAL), else -1 */
 } cofem_iter_stats;
 
 typedef struct cofem_ctx cofem_ctx;
@@ -204,7 +214,8 @@ enum {
   COFEM_KT_UPDATE = 2, /* CG update x, r, p and the new residual norms */
   COFEM_KT_INIT = 3,   /* probes, R = P = B, X = 0 */
   COFEM_KT_MSTEP = 4,  /* diagonal estimate and M-step */
-  COFEM_KT_SLOTS = 5
+  COFEM_KT_CHECK = 5,  /* true-residual check: operator over X and the residual sums */
+  COFEM_KT_SLOTS = 6
 };
 
 /*

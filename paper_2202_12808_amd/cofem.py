@@ -32,6 +32,7 @@ COFEM_PREC_FP32 = 0
 COFEM_PREC_BF16_IR = 1
 COFEM_PREC_FP64 = 2
 COFEM_STOP_FROBENIUS = 0
+COFEM_FLAG_TRUE_RESIDUAL = 1
 _PRECISIONS = {"fp32": COFEM_PREC_FP32, "bf16_ir": COFEM_PREC_BF16_IR, "fp64": COFEM_PREC_FP64}
 COFEM_MAX_K = 32
 
@@ -60,7 +61,7 @@ class cofem_params(ctypes.Structure):
 
 class cofem_iter_stats(ctypes.Structure):
     _fields_ = [("t", c_int32), ("cg_iters", c_int32), ("converged", c_int32), ("n_clamped", c_int32),
-                ("rel_resid", c_double), ("ms", c_double)]
+                ("rel_resid", c_double), ("ms", c_double), ("rel_resid_true", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -171,7 +172,7 @@ def cofem_time_operator(ctx, reps: int):
     return [float(out[i]) for i in range(3)]
 
 
-KERNEL_SLOTS = ("pass1", "pass2", "update", "init", "mstep")  # COFEM_KT_* order
+KERNEL_SLOTS = ("pass1", "pass2", "update", "init", "mstep", "check")  # COFEM_KT_* order
 
 
 def cofem_set_kernel_timing(ctx, enable: bool):
@@ -211,10 +212,12 @@ class CoFEM:
             self.ctx = cofem_init(problem, params, stream)
 
     @staticmethod
-    def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0, precision="fp32"):
+    def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0, precision="fp32",
+                true_residual=True):
+        flags = COFEM_FLAG_TRUE_RESIDUAL if true_residual else 0
         return cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
                             seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=_PRECISIONS[precision],
-                            stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max), flags=0,
+                            stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max), flags=flags,
                             poll_interval=int(poll_interval))
 
     @classmethod

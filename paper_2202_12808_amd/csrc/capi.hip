@@ -34,6 +34,7 @@ struct cofem_ctx {
   int fixed_iters = 0;
   int prev_iters = 0;
   int precision = COFEM_PREC_FP32;
+  bool true_resid = false;
   bool has_solution = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -373,6 +374,28 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n) {
   return COFEM_OK;
 }
 
+// Final check of a solve: Q = A X with the operator kernels (the same
+// launches as a CG iteration, applied to X instead of the direction block),
+// then ||b_c - q_c||^2 per column in float64 against B regenerated for EM
+// iteration t.  Uses alpha of this E-step, so it runs before the M-step.
+cofem_status true_residual(cofem_ctx* c, int t) {
+  COFEM_TRY(mark(c, COFEM_KT_CHECK, 0));
+  if (c->kind == COFEM_DENSE) {
+    COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->X, c->xm, c->Wpart, c->wmpart, c->W, c->wm, c->cnt_split1,
+                             c->st, 1, c->stream));
+    COFEM_HIP(c, dense_pass2(c->dd, c->phiB, c->W, c->wm, c->X, c->xm, c->R, c->rm, c->alpha, c->beta,
+                             c->Qpart, c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2,
+                             c->st, 1, c->stream));
+    COFEM_HIP(c, dense_true_resid(c->dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->parts_upd, c->cnts_upd,
+                                  c->st, c->stream));
+  } else {
+    COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm,
+                           c->red_pass, c->st, 1, c->stream));
+    COFEM_HIP(c, conv_true_resid(c->cd, c->seed, t, c->b0, c->vQs, c->Qsm, c->red_upd, c->st, c->stream));
+  }
+  return COFEM_OK;
+}
+
 cofem_status read_state(cofem_ctx* c) {
   COFEM_HIP(c, hipMemcpyAsync(c->host_st, c->st, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
   COFEM_HIP(c, hipStreamSynchronize(c->stream));
@@ -409,6 +432,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   }
   if (c->host_st->numeric_error)
     return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
+  if (c->true_resid) COFEM_TRY(true_residual(c, t));
   COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
@@ -432,6 +456,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     out->n_clamped = c->host_st->n_clamped;
     out->rel_resid = c->host_st->ratio;
     out->ms = ms;
+    out->rel_resid_true = c->true_resid ? c->host_st->true_ratio : -1.0;
   }
   return COFEM_OK;
 }
@@ -460,6 +485,7 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   c->alpha_max = params->alpha_max > 0.0 ? params->alpha_max : 1e10;
   c->poll = params->poll_interval > 0 ? params->poll_interval : 8;
   c->precision = params->precision;
+  c->true_resid = (params->flags & COFEM_FLAG_TRUE_RESIDUAL) != 0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   cofem_status s = COFEM_OK;
   hipError_t e = hipGetDevice(&c->device);

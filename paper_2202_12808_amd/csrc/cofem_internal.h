@@ -38,6 +38,8 @@ struct CgScalars {
   int32_t n_clamped;      // M-step floor hits of the last M-step
   int32_t numeric_error;  // set when a CG scalar is not finite
   uint32_t counter[4];    // last-block tickets (self-resetting)
+  double true_res[kMaxCols];  // ||b_c - A x_c||^2 of the last solve (float64 sums)
+  double true_ratio;          // sqrt(sum_c true_res[c]) / nB
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -301,6 +303,20 @@ __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
   }
 }
 
+// Finishes the true-residual check: ||b_c - A x_c||^2 per column (in shared
+// memory) and the joint ratio sqrt(sum_c ...) / ||B||_F.
+__device__ __forceinline__ void finish_true_resid(CgScalars* st, const double* res) {
+  const int nc = st->kp + 1;
+  if ((int)threadIdx.x < nc) st->true_res[threadIdx.x] = res[threadIdx.x];
+  if (threadIdx.x == 0) {
+    const double nB = st->nB;
+    double sum = 0.0;
+    for (int c = 0; c < nc; ++c) sum += res[c];
+    if (!isfinite(sum)) st->numeric_error = 1;
+    st->true_ratio = nB > 0.0 ? sqrt(sum) / nB : 0.0;
+  }
+}
+
 // ------------------------------------------------------------ host launchers
 // Dense problem geometry.  Np and Dp are N and D padded to multiples of 64.
 // Probe-column state uses the blocked-4 layout: element (d, c) of a Dp x 32
@@ -343,6 +359,11 @@ hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const f
 hipError_t dense_to_colmajor(const DenseDims& dd, int K, const float* Xb, float* out, hipStream_t s);
 hipError_t dense_from_colmajor(const DenseDims& dd, int K, const float* in, float* Xb, hipStream_t s);
 int dense_update_blocks(const DenseDims& dd);
+// ||B - Q||^2 per column with B regenerated (probes of EM iteration t, b0) and
+// Q = A X from the operator passes (blocked-4 probe block + float64 column).
+hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
+                            const float* Q, const double* qm, double* parts, uint32_t* cnts,
+                            CgScalars* st, hipStream_t s);
 
 struct ConvDims {
   int H, W, ks;      // square odd kernel side
@@ -372,6 +393,8 @@ hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const
 hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void* Q, double* xm,
                        double* rm, double* pm, const double* qm, const ConvReduce& red,
                        CgScalars* st, hipStream_t s);
+hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const double* b0, const void* Q,
+                           const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s);
 hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
                       float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
                       hipStream_t s);

@@ -39,7 +39,7 @@ __device__ __forceinline__ int wrap(int x, int n) {
 
 // One (tile, column) of the fused operator pass, in precision T.
 template <int KS, typename T>
-__device__ __forceinline__ void conv_tile(const float* __restrict__ taps, int H, int W, int tu0,
+__device__ __forceinline__ void conv_tile(const float* __restrict__ sTaps, int H, int W, int tu0,
                                           int tv0, const T* __restrict__ P,
                                           const T* __restrict__ R,
                                           const float* __restrict__ alpha, T beta,
@@ -62,7 +62,9 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ taps, int H,
     T out[kRB];
 #pragma unroll
     for (int r = 0; r < kRB; ++r) out[r] = T(0);
-#pragma unroll
+    // one column of taps per step (not unrolled): the taps come from LDS, so
+    // registers hold a strip and RB sums, not all KS*KS taps
+#pragma unroll 1
     for (int b = 0; b < KS; ++b) {
       // rows i0 + r - a + 2c for r in [0, RB), a in [0, KS)
       T strip[kRB + KS - 1];
@@ -70,7 +72,7 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ taps, int H,
       for (int q = 0; q < kRB + KS - 1; ++q) strip[q] = sP[(i0 + q) * G::spW + (j - b + 2 * c)];
 #pragma unroll
       for (int a = 0; a < KS; ++a) {
-        const T h = (T)taps[a * KS + b];
+        const T h = (T)sTaps[a * KS + b];
 #pragma unroll
         for (int r = 0; r < kRB; ++r) out[r] += h * strip[r - a + KS - 1];
       }
@@ -87,14 +89,14 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ taps, int H,
     T out[kRB];
 #pragma unroll
     for (int r = 0; r < kRB; ++r) out[r] = T(0);
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < KS; ++b) {
       T strip[kRB + KS - 1];
 #pragma unroll
       for (int q = 0; q < kRB + KS - 1; ++q) strip[q] = sT[(i0 + q) * G::stW + j + b];
 #pragma unroll
       for (int a = 0; a < KS; ++a) {
-        const T h = (T)taps[a * KS + b];
+        const T h = (T)sTaps[a * KS + b];
 #pragma unroll
         for (int r = 0; r < kRB; ++r) out[r] += h * strip[r + a];
       }
@@ -129,16 +131,18 @@ __global__ __launch_bounds__(256) void k_conv_pass(
   if (!apply_only && st->stop) return;
   using G = ConvGeom<KS>;
   __shared__ double sbuf[G::spH * G::spW + G::stH * G::stW];
+  __shared__ float sTaps[KS * KS];  // visible after the first barrier of conv_tile
+  if (threadIdx.x < KS * KS) sTaps[threadIdx.x] = taps[threadIdx.x];
   const int col = blockIdx.z;
   const int tu0 = blockIdx.y * kTile, tv0 = blockIdx.x * kTile;
   double dots[3];
   if (col == K) {
-    conv_tile<KS, double>(taps, H, W, tu0, tv0, pm, rm, alpha, beta, qm, sbuf,
+    conv_tile<KS, double>(sTaps, H, W, tu0, tv0, pm, rm, alpha, beta, qm, sbuf,
                           sbuf + G::spH * G::spW, dots);
   } else {
     TP* sb = reinterpret_cast<TP*>(sbuf);
     const int64_t off = (int64_t)col * ldD;
-    conv_tile<KS, TP>(taps, H, W, tu0, tv0, P + off, R + off, alpha, (TP)beta, Q + off, sb,
+    conv_tile<KS, TP>(sTaps, H, W, tu0, tv0, P + off, R + off, alpha, (TP)beta, Q + off, sb,
                       sb + G::spH * G::spW, dots);
   }
   if (apply_only) return;
@@ -343,6 +347,54 @@ hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void
     hipLaunchKernelGGL(k_conv_update<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K,
                        static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P),
                        static_cast<const float*>(Q), xm, rm, pm, qm, red, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ true residual (final check of a solve)
+// ||b_c - q_c||^2 per column with q = A x from an operator pass over X and B
+// regenerated: probes of EM iteration t (Eq. 7) and b0 for the mean column.
+template <typename TP>
+__global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD, int K, uint64_t seed,
+                                                         int t, const double* __restrict__ b0,
+                                                         const TP* __restrict__ Q,
+                                                         const double* __restrict__ qm, ConvReduce red,
+                                                         CgScalars* st) {
+  const int col = blockIdx.y;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  if (col == K) {
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const double e = b0[d] - qm[d];
+      acc += e * e;
+    }
+  } else {
+    const TP* q = Q + (int64_t)col * ldD;
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const double e = (double)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d) - (double)q[d];
+      acc += e * e;
+    }
+  }
+  __shared__ double shm[8];
+  __shared__ double mine[1], tot[kMaxCols];
+  const double tot_b = block_sum(acc, shm);
+  if (threadIdx.x == 0) mine[0] = tot_b;
+  __syncthreads();
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col,
+                          K + 1, 1, mine, tot))
+    return;
+  finish_true_resid(st, tot);
+}
+
+hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const double* b0, const void* Q,
+                           const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s) {
+  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_true_resid<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+                       static_cast<const double*>(Q), qm, red, st);
+  else
+    hipLaunchKernelGGL(k_conv_true_resid<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+                       static_cast<const float*>(Q), qm, red, st);
   return hipGetLastError();
 }
 

@@ -594,6 +594,51 @@ hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const
   return hipGetLastError();
 }
 
+// ------------------------------------------------ true residual (final check of a solve)
+// ||b_c - q_c||^2 per column, float64 sums, with q = A x from the operator
+// passes applied to X and B regenerated: probes of EM iteration t (Eq. 7) in
+// rows d < D, zero in the padding rows, and b0 for the mean column.
+__global__ __launch_bounds__(256) void k_dense_true_resid(int64_t D, int64_t Dp, uint64_t seed, int t, int K,
+                                                          const double* __restrict__ b0,
+                                                          const float* __restrict__ Q,
+                                                          const double* __restrict__ qm,
+                                                          double* __restrict__ parts, uint32_t* cnts,
+                                                          CgScalars* st) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  const int c = threadIdx.x & 31;  // gstride is a multiple of 32: fixed column per thread
+  double acc = 0.0;
+  for (int64_t e4 = gtid; e4 < Dp * 8; e4 += gstride) {
+    const float4 q = reinterpret_cast<const float4*>(Q)[e4];
+    const int64_t d0 = (e4 >> 5) * 4;
+    const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t d = d0 + i;
+      const double b = (c < K && d < D) ? (double)probe_sign(seed, (uint32_t)t, (uint32_t)c, (uint64_t)d) : 0.0;
+      const double e = b - (double)qv[i];
+      acc += e * e;
+    }
+  }
+  double accm = 0.0;
+  for (int64_t d = gtid; d < Dp; d += gstride) {
+    const double e = b0[d] - qm[d];
+    accm += e * e;
+  }
+  __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
+  dense_block_sums(acc, accm, mine);
+  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, kDenseKP + 1, mine, tot)) return;
+  finish_true_resid(st, tot);
+}
+
+hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
+                            const float* Q, const double* qm, double* parts, uint32_t* cnts,
+                            CgScalars* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_true_resid, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed,
+                     t, K, b0, Q, qm, parts, cnts, st);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
 __global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, int t, int K,
                                                      const float* __restrict__ X,

@@ -261,6 +261,45 @@ def test_conv_256x256_k7_fp32_error_floor(torch_dev):
     assert errs[1] < 1e-3 and errs[2] < 1e-3
 
 
+# ------------------------------------------------------------------ true residual
+@pytest.mark.parametrize("kind", ["dense", "conv"])
+def test_true_residual_matches_float64_recomputation(torch_dev, kind):
+    # ||B - A X||_F / ||B||_F reported by the solver (one operator pass over X,
+    # float64 sums) against the same quantity formed on the CPU in float64 from
+    # the GPU's own X, its alpha and B regenerated from the oracle's probes
+    torch = torch_dev
+    if kind == "dense":
+        p, make = synth.dense_256x1024(0), _dense_ctx
+    else:
+        p = synth.conv_problem(48, 40, 7, rho=0.02, beta=100.0, K=6, tol=1e-5, max_iter=400, seed=3,
+                               law="laplace", name="conv_48x40_k7")
+        make = _conv_ctx
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with make(torch, p) as g:
+        g.em_step(2)
+        alpha = g.posterior()[2].cpu().numpy().astype(np.float64)
+        st = g.em_step(1)[0]
+        X, m = g.solution()
+    X = X.cpu().numpy().astype(np.float64).T
+    m = m.cpu().numpy()
+    B = np.concatenate([O.rademacher_probes(p.seed, st["t"], p.K, p.D), b0[:, None]], axis=1)
+    A = O.cofem_oracle.make_apply_A(op, p.beta, alpha)
+    ref = np.linalg.norm(B - A(np.concatenate([X, m[:, None]], axis=1))) / np.linalg.norm(B)
+    _say(kind, "true residual gpu", st["rel_resid_true"], "cpu float64", ref, "recursive", st["rel_resid"],
+         "cg", st["cg_iters"])
+    # the GPU's A X carries float32 rounding in the probe columns (~1e-7 of ||B||)
+    assert abs(st["rel_resid_true"] - ref) <= 0.02 * ref + 3e-7
+
+
+def test_true_residual_off_reports_minus_one(torch_dev):
+    torch = torch_dev
+    p = synth.dense_problem(64, 128, nnz=5, beta=100.0, K=4, tol=1e-5, seed=1)
+    with _dense_ctx(torch, p, true_residual=False) as g:
+        st = g.em_step(1)[0]
+    assert st["rel_resid_true"] == -1.0
+
+
 # ------------------------------------------------------------------ closed form
 @pytest.mark.parametrize("kind", ["dense", "conv"])
 def test_identity_dictionary_closed_form(torch_dev, kind):
