@@ -288,8 +288,17 @@ def test_true_residual_matches_float64_recomputation(torch_dev, kind):
     ref = np.linalg.norm(B - A(np.concatenate([X, m[:, None]], axis=1))) / np.linalg.norm(B)
     _say(kind, "true residual gpu", st["rel_resid_true"], "cpu float64", ref, "recursive", st["rel_resid"],
          "cg", st["cg_iters"])
-    # the GPU's A X carries float32 rounding in the probe columns (~1e-7 of ||B||)
-    assert abs(st["rel_resid_true"] - ref) <= 0.02 * ref + 3e-7
+    # The GPU forms A X for the probe columns from float32 operands with float32
+    # MFMA sums, so its residual carries an absolute error of order
+    # u32 * beta * ||Phi||_2^2 * ||X_probes||_F (u32 = 2^-24), here ~1e-6 of ||B||_F;
+    # the float64 mean column adds nothing comparable.
+    if kind == "dense":
+        phi_norm = np.linalg.norm(p.phi.astype(np.float64), 2)
+    else:
+        phi_norm = np.abs(p.taps.astype(np.float64)).sum()  # ||h||_1 bounds ||Phi||_2
+    floor = 2.0 ** -24 * p.beta * phi_norm ** 2 * np.linalg.norm(X) / np.linalg.norm(B)
+    _say("float32 product floor", floor)
+    assert abs(st["rel_resid_true"] - ref) <= 0.02 * ref + floor
 
 
 def test_true_residual_off_reports_minus_one(torch_dev):
