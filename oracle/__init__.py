@@ -12,10 +12,12 @@ from .cofem_oracle import (  # noqa: F401
     cg_solve,
     cofem,
     cofem_estep,
+    cofem_estep_ir,
     diag_estimate,
     diag_estimate_ratio,
     exact_estep,
     exact_em,
+    ir_solve,
     loglik,
     loglik_direct,
     mstep,

@@ -244,6 +244,53 @@ def true_relative_residual(apply_A, X: np.ndarray, B: np.ndarray) -> float:
 
 
 # ---------------------------------------------------------------------------
+# Mixed-precision form of the solve (not in the paper): classical iterative
+# refinement (Wilkinson 1963; Moler 1967) around the CG solve of Sec. 3.2.  The
+# outer residual B - A X uses the problem's own operator; every inner
+# correction solve A_in D = R uses a lower-precision operator (for example
+# Phi rounded to bfloat16) and stops at a relative tolerance tol_in of its own
+# right-hand side.  The outer loop stops on the true residual.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class IRInfo:
+    sweeps: list        # inner CG iterations of each correction solve
+    iters: int          # total inner iterations
+    converged: bool     # true ratio below tol at exit
+    rel_resid: float    # ||B - A X||_F / ||B||_F at exit
+    history: list       # the true ratio before each sweep (and at exit)
+
+
+def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
+             max_iter: int, max_sweeps: int, fixed_inner=None):
+    """Iterative refinement: X = 0, R = B; while ||R||_F/||B||_F >= tol (and
+    fewer than ``max_iter`` inner iterations and ``max_sweeps`` sweeps so far):
+    D = CG(apply_A_inner, R, tol_in, remaining budget); X += D; R = B - A X.
+    With ``fixed_inner`` (a list of counts) exactly those sweeps run, each for
+    exactly its count."""
+    B = np.asarray(B, dtype=np.float64)
+    X = np.zeros_like(B)
+    R = B.copy()
+    nB = float(np.linalg.norm(B))
+    sweeps, hist = [], []
+    total = 0
+    while True:
+        ratio = float(np.linalg.norm(R)) / nB if nB > 0.0 else 0.0
+        hist.append(ratio)
+        if fixed_inner is not None:
+            if len(sweeps) == len(fixed_inner):
+                break
+        elif ratio < tol or total >= max_iter or len(sweeps) >= max_sweeps:
+            break
+        n = None if fixed_inner is None else int(fixed_inner[len(sweeps)])
+        Dx, info = cg_solve(apply_A_inner, R, tol_in, max_iter - total, fixed_iters=n)
+        X += Dx
+        total += info.iters
+        sweeps.append(info.iters)
+        R = B - apply_A(X)
+    return X, IRInfo(sweeps, total, ratio < tol, ratio, hist)
+
+
+# ---------------------------------------------------------------------------
 # Simplified E-step, diagonal estimate and M-step (Sec. 3.1, Algorithm 1)
 # ---------------------------------------------------------------------------
 def diag_estimate(P: np.ndarray, X: np.ndarray) -> np.ndarray:
@@ -291,6 +338,23 @@ def cofem_estep(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
     mu = X[:, K].copy()
     s = diag_estimate(P, X[:, :K])
     return EStepResult(mu=mu, s=s, X=X, P=P, cg=info)
+
+
+def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
+                   tol: float, tol_in: float, max_iter: int, max_sweeps: int, seed: int, t: int,
+                   fixed_inner=None):
+    """The E-step of Algorithm 1 with the solve done by ``ir_solve``: outer
+    residual with ``op`` (the problem's Phi), inner corrections with
+    ``op_inner`` (a lower-precision Phi).  Returns (EStepResult, IRInfo)."""
+    D = op.D
+    P = rademacher_probes(seed, t, K, D)
+    B = np.concatenate([P, np.asarray(b0, np.float64)[:, None]], axis=1)
+    X, info = ir_solve(make_apply_A(op, beta, alpha), make_apply_A(op_inner, beta, alpha), B, tol,
+                       tol_in, max_iter, max_sweeps, fixed_inner)
+    mu = X[:, K].copy()
+    s = diag_estimate(P, X[:, :K])
+    cg = CGInfo(info.iters, info.converged, info.rel_resid, info.history)
+    return EStepResult(mu=mu, s=s, X=X, P=P, cg=cg), info
 
 
 @dataclasses.dataclass

@@ -1,0 +1,99 @@
+"""Pins of the oracle's iterative-refinement solve (the mixed-precision form).
+
+Iterative refinement is not in the paper; the oracle follows the classical
+scheme (outer residual with the problem's operator, inner CG corrections with a
+lower-precision one).  Pinned here against: plain CG when the inner operator is
+exact, the Cholesky solution within the tolerance, the true residual at exit,
+monotone residual decrease for a contraction, and replay with fixed counts.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.cofem_oracle import make_apply_A, ir_solve
+
+
+def _spd_problem(D=120, N=60, beta=50.0, seed=0, K=3):
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((N, D)) / np.sqrt(N)
+    alpha = np.exp(rng.uniform(-1.0, 2.0, D))
+    B = np.concatenate([np.where(rng.random((D, K)) < 0.5, -1.0, 1.0), rng.standard_normal((D, 1)) * 30.0],
+                       axis=1)
+    A = beta * phi.T @ phi + np.diag(alpha)
+    return phi, alpha, beta, A, B
+
+
+def _bf16(x):
+    # round-to-nearest-even to bfloat16 on the float32 value (test-side helper)
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_ir_with_exact_inner_operator_is_one_cg_solve():
+    phi, alpha, beta, A, B = _spd_problem()
+    op = O.DenseOperator(phi)
+    apply_A = make_apply_A(op, beta, alpha)
+    X, info = ir_solve(apply_A, apply_A, B, tol=1e-6, tol_in=1e-9, max_iter=400, max_sweeps=10)
+    Xc, ci = O.cg_solve(apply_A, B, 1e-9, 400)
+    assert info.sweeps == [ci.iters]
+    np.testing.assert_allclose(X, Xc, rtol=0, atol=1e-12 * np.abs(Xc).max())
+
+
+def test_ir_bf16_inner_reaches_true_tolerance_and_cholesky_solution():
+    phi, alpha, beta, A, B = _spd_problem(seed=1)
+    op, opb = O.DenseOperator(phi), O.DenseOperator(_bf16(phi))
+    tol = 1e-9
+    X, info = ir_solve(make_apply_A(op, beta, alpha), make_apply_A(opb, beta, alpha), B, tol=tol,
+                       tol_in=1e-2, max_iter=2000, max_sweeps=50)
+    assert info.converged and len(info.sweeps) >= 2
+    assert O.true_relative_residual(make_apply_A(op, beta, alpha), X, B) < tol
+    Xe = np.linalg.solve(A, B)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(X - Xe) / np.linalg.norm(Xe) < kappa * tol
+    # the same run against the bf16 system instead converges to a different
+    # solution: the outer residual really uses the full operator
+    Xb = np.linalg.solve(beta * _bf16(phi).T @ _bf16(phi) + np.diag(alpha), B)
+    assert np.linalg.norm(Xb - Xe) / np.linalg.norm(Xe) > 100 * np.linalg.norm(X - Xe) / np.linalg.norm(Xe)
+
+
+def test_ir_true_residual_decreases_each_sweep_for_a_contraction():
+    phi, alpha, beta, A, B = _spd_problem(seed=2)
+    op, opb = O.DenseOperator(phi), O.DenseOperator(_bf16(phi))
+    X, info = ir_solve(make_apply_A(op, beta, alpha), make_apply_A(opb, beta, alpha), B, tol=1e-10,
+                       tol_in=1e-3, max_iter=4000, max_sweeps=40)
+    h = info.history
+    assert all(b < a for a, b in zip(h[:-1], h[1:]))
+    assert h[-1] == pytest.approx(info.rel_resid)
+
+
+def test_ir_fixed_counts_replay_a_free_run():
+    phi, alpha, beta, A, B = _spd_problem(seed=3)
+    op, opb = O.DenseOperator(phi), O.DenseOperator(_bf16(phi))
+    a, ab = make_apply_A(op, beta, alpha), make_apply_A(opb, beta, alpha)
+    X1, i1 = ir_solve(a, ab, B, tol=1e-7, tol_in=1e-2, max_iter=400, max_sweeps=10)
+    X2, i2 = ir_solve(a, ab, B, tol=0.0, tol_in=0.5, max_iter=0, max_sweeps=0, fixed_inner=i1.sweeps)
+    assert i2.sweeps == i1.sweeps
+    np.testing.assert_array_equal(X1, X2)
+
+
+def test_ir_zero_rhs_and_budget():
+    phi, alpha, beta, A, B = _spd_problem(seed=4)
+    op = O.DenseOperator(phi)
+    a = make_apply_A(op, beta, alpha)
+    X, info = ir_solve(a, a, np.zeros_like(B), tol=1e-6, tol_in=1e-2, max_iter=100, max_sweeps=5)
+    assert info.sweeps == [] and not X.any()
+    X, info = ir_solve(a, a, B, tol=1e-30, tol_in=1e-1, max_iter=7, max_sweeps=100)
+    assert info.iters <= 7 and not info.converged
+
+
+def test_estep_ir_matches_plain_estep_when_inner_is_exact():
+    phi, alpha, beta, A, B = _spd_problem(seed=5, K=4)
+    op = O.DenseOperator(phi)
+    b0 = B[:, -1]
+    e_ir, info = O.cofem_estep_ir(op, op, b0, beta, alpha, 4, 1e-8, 1e-12, 400, 10, seed=9, t=2)
+    e = O.cofem_estep(op, b0, beta, alpha, 4, 1e-12, 400, seed=9, t=2)
+    assert len(info.sweeps) == 1
+    np.testing.assert_allclose(e_ir.mu, e.mu, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(e_ir.s, e.s, rtol=1e-12, atol=1e-15)
