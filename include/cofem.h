@@ -56,7 +56,15 @@ enum { COFEM_F32 = 0, COFEM_BF16 = 1 };
  *                   in float64;
  *  COFEM_PREC_FP64  every column in float64 (convolution dictionaries only in
  *                   this build) -- for ill-conditioned solves whose float32
- *                   probe iterates drift from a float64 reference. */
+ *                   probe iterates drift from a float64 reference;
+ *  COFEM_PREC_BF16_IR  mixed-precision form (dense only): each E-step solve
+ *                   is an iterative refinement whose inner CG solves use Phi
+ *                   rounded once to bfloat16 (matrix cores, float32 sums) and
+ *                   whose outer residual B - A X uses the float32 Phi with
+ *                   float64 sums; it stops when that true residual ratio is
+ *                   below cg_tol (the cap U bounds the inner iterations in
+ *                   total).  Not in the paper: a precision form layered on
+ *                   the solve of Sec. 3.2. */
 enum { COFEM_PREC_FP32 = 0, COFEM_PREC_BF16_IR = 1, COFEM_PREC_FP64 = 2 };
 /* cofem_params.stop_rule */
 enum { COFEM_STOP_FROBENIUS = 0 };
@@ -118,6 +126,10 @@ typedef struct cofem_params {
   double alpha_max;
   int32_t flags;
   int32_t poll_interval;
+  /* COFEM_PREC_BF16_IR only: relative tolerance of each inner solve (0 selects
+   * 1e-2) and the maximum number of refinement sweeps per E-step (0 selects 20) */
+  double ir_inner_tol;
+  int32_t ir_max_sweeps;
 } cofem_params;
 
 /* Per-EM-iteration statistics returned by cofem_em_step (host struct). */
@@ -129,7 +141,8 @@ typedef struct cofem_iter_stats {
   double rel_resid;    /* recursive ||R||_F / ||B||_F at exit */
   double ms;           /* wall time of this EM iteration (device events) */
   double rel_resid_true; /* ||B - A X||_F / ||B||_F at exit, float64 sums
-                            (COFEM_FLAG_TRUE_RESIDUAL), else -1 */
+                            (COFEM_FLAG_TRUE_RESIDUAL or COFEM_PREC_BF16_IR), else -1 */
+  int32_t ir_sweeps;     /* refinement sweeps (COFEM_PREC_BF16_IR), else 0 */
 } cofem_iter_stats;
 
 typedef struct cofem_ctx cofem_ctx;
@@ -169,7 +182,8 @@ cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha
 cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t);
 
 /* n > 0: every CG solve runs exactly n iterations, ignoring cg_tol (the cap is
- * raised to n); n == 0 restores the stop test.  For step-by-step comparisons. */
+ * raised to n); n == 0 restores the stop test.  For step-by-step comparisons.
+ * COFEM_ERR_UNSUPPORTED under COFEM_PREC_BF16_IR (use cofem_get_ir_sweeps). */
 cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n);
 
 /*
@@ -178,6 +192,21 @@ cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n);
  * mean: device float64, length D.  Either pointer nullable.
  */
 cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, double* mean);
+
+/*
+ * COFEM_PREC_BF16_IR only: the inner CG iteration count of each refinement
+ * sweep of the last E-step.  Writes min(n, capacity) counts to counts (host)
+ * and the number of sweeps n to *n (host).
+ */
+cofem_status cofem_get_ir_sweeps(cofem_ctx* ctx, int32_t* counts, int32_t capacity, int32_t* n);
+
+/*
+ * COFEM_PREC_BF16_IR only: applies the inner operator A~ = beta Phi~^T Phi~ +
+ * diag(alpha), Phi~ = Phi rounded to bfloat16 (nearest, ties to even), with
+ * the inner kernels; arguments as cofem_apply_A.  For operator tests.
+ */
+cofem_status cofem_apply_A_lowp(cofem_ctx* ctx, int32_t problem, const float* v_probes,
+                                const double* v_mean, float* q_probes, double* q_mean);
 
 /*
  * Applies A = beta Phi^T Phi + diag(alpha) of `problem` with the context's

@@ -251,6 +251,9 @@ def true_relative_residual(apply_A, X: np.ndarray, B: np.ndarray) -> float:
 # Phi rounded to bfloat16) and stops at a relative tolerance tol_in of its own
 # right-hand side.  The outer loop stops on the true residual.
 # ---------------------------------------------------------------------------
+IR_STALL = 3  # sweeps in a row without halving the best true residual
+
+
 @dataclasses.dataclass
 class IRInfo:
     sweeps: list        # inner CG iterations of each correction solve
@@ -263,7 +266,10 @@ class IRInfo:
 def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
              max_iter: int, max_sweeps: int, fixed_inner=None):
     """Iterative refinement: X = 0, R = B; while ||R||_F/||B||_F >= tol (and
-    fewer than ``max_iter`` inner iterations and ``max_sweeps`` sweeps so far):
+    fewer than ``max_iter`` inner iterations and ``max_sweeps`` sweeps so far,
+    and fewer than IR_STALL sweeps in a row failed to halve the best ratio --
+    the true residual of refinement need not fall monotonically, and once it
+    stalls its evaluation has reached its rounding floor):
     D = CG(apply_A_inner, R, tol_in, remaining budget); X += D; R = B - A X.
     With ``fixed_inner`` (a list of counts) exactly those sweeps run, each for
     exactly its count."""
@@ -273,13 +279,21 @@ def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
     nB = float(np.linalg.norm(B))
     sweeps, hist = [], []
     total = 0
+    best, stall = None, 0
     while True:
         ratio = float(np.linalg.norm(R)) / nB if nB > 0.0 else 0.0
         hist.append(ratio)
+        if best is None:
+            best = ratio
+        elif ratio < 0.5 * best:
+            best, stall = ratio, 0
+        else:
+            stall += 1
         if fixed_inner is not None:
             if len(sweeps) == len(fixed_inner):
                 break
-        elif ratio < tol or total >= max_iter or len(sweeps) >= max_sweeps:
+        elif (ratio < tol or total >= max_iter or len(sweeps) >= max_sweeps
+              or stall >= IR_STALL):
             break
         n = None if fixed_inner is None else int(fixed_inner[len(sweeps)])
         Dx, info = cg_solve(apply_A_inner, R, tol_in, max_iter - total, fixed_iters=n)

@@ -56,12 +56,14 @@ class cofem_problem(ctypes.Structure):
 class cofem_params(ctypes.Structure):
     _fields_ = [("beta", c_double), ("K", c_int32), ("cg_tol", c_double), ("cg_max_iter", c_int32),
                 ("seed", c_uint64), ("precision", c_int32), ("stop_rule", c_int32),
-                ("alpha_max", c_double), ("flags", c_int32), ("poll_interval", c_int32)]
+                ("alpha_max", c_double), ("flags", c_int32), ("poll_interval", c_int32),
+                ("ir_inner_tol", c_double), ("ir_max_sweeps", c_int32)]
 
 
 class cofem_iter_stats(ctypes.Structure):
     _fields_ = [("t", c_int32), ("cg_iters", c_int32), ("converged", c_int32), ("n_clamped", c_int32),
-                ("rel_resid", c_double), ("ms", c_double), ("rel_resid_true", c_double)]
+                ("rel_resid", c_double), ("ms", c_double), ("rel_resid_true", c_double),
+                ("ir_sweeps", c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +82,8 @@ _SIGNATURES = {
     "cofem_probe_signs": (c_int32, [c_uint64, c_int32, c_int32, c_int64, c_void_p, c_void_p]),
     "cofem_time_operator": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float)]),
     "cofem_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
+    "cofem_get_ir_sweeps": (c_int32, [c_void_p, POINTER(c_int32), c_int32, POINTER(c_int32)]),
+    "cofem_apply_A_lowp": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cofem_get_kernel_timing": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(c_int64)]),
     "cofem_destroy": (None, [c_void_p]),
     "cofem_last_error": (c_char_p, [c_void_p]),
@@ -162,6 +166,11 @@ def cofem_apply_A(ctx, v_probes, v_mean, q_probes, q_mean, problem: int = 0):
                                 _ptr(q_mean)), ctx)
 
 
+def cofem_apply_A_lowp(ctx, v_probes, v_mean, q_probes, q_mean, problem: int = 0):
+    _check(load().cofem_apply_A_lowp(ctx, problem, _ptr(v_probes), _ptr(v_mean), _ptr(q_probes),
+                                     _ptr(q_mean)), ctx)
+
+
 def cofem_probe_signs(seed: int, t: int, K: int, D: int, out, stream=None):
     _check(load().cofem_probe_signs(seed, t, K, D, _ptr(out), _stream(stream)))
 
@@ -173,6 +182,13 @@ def cofem_time_operator(ctx, reps: int):
 
 
 KERNEL_SLOTS = ("pass1", "pass2", "update", "init", "mstep", "check")  # COFEM_KT_* order
+
+
+def cofem_get_ir_sweeps(ctx):
+    counts = (c_int32 * 256)()
+    n = c_int32(0)
+    _check(load().cofem_get_ir_sweeps(ctx, counts, 256, ctx and ctypes.byref(n)), ctx)
+    return [int(counts[i]) for i in range(min(n.value, 256))]
 
 
 def cofem_set_kernel_timing(ctx, enable: bool):
@@ -213,12 +229,13 @@ class CoFEM:
 
     @staticmethod
     def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0, precision="fp32",
-                true_residual=True):
+                true_residual=True, ir_inner_tol=0.0, ir_max_sweeps=0):
         flags = COFEM_FLAG_TRUE_RESIDUAL if true_residual else 0
         return cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
                             seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=_PRECISIONS[precision],
                             stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max), flags=flags,
-                            poll_interval=int(poll_interval))
+                            poll_interval=int(poll_interval), ir_inner_tol=float(ir_inner_tol),
+                            ir_max_sweeps=int(ir_max_sweeps))
 
     @classmethod
     def dense(cls, phi, y, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
@@ -282,14 +299,20 @@ class CoFEM:
     def set_fixed_cg_iters(self, n):
         cofem_set_fixed_cg_iters(self.ctx, n)
 
-    def apply_A(self, v_probes, v_mean):
+    def apply_A(self, v_probes, v_mean, lowp=False):
+        """A v (or, with lowp, the bfloat16-dictionary operator of the
+        mixed-precision form) for K probe columns (K x D) and the mean column."""
         import torch
         v_probes = v_probes.to(device=self.device, dtype=torch.float32).contiguous()
         v_mean = v_mean.to(device=self.device, dtype=torch.float64).contiguous()
         q = torch.empty_like(v_probes)
         qm = torch.empty_like(v_mean)
-        cofem_apply_A(self.ctx, v_probes, v_mean, q, qm)
+        (cofem_apply_A_lowp if lowp else cofem_apply_A)(self.ctx, v_probes, v_mean, q, qm)
         return q, qm
+
+    def ir_sweeps(self):
+        """Inner CG counts of the refinement sweeps of the last E-step."""
+        return cofem_get_ir_sweeps(self.ctx)
 
     def time_operator(self, reps=20):
         return cofem_time_operator(self.ctx, reps)

@@ -35,6 +35,14 @@ struct cofem_ctx {
   int prev_iters = 0;
   int precision = COFEM_PREC_FP32;
   bool true_resid = false;
+  // mixed-precision form (COFEM_PREC_BF16_IR): inner tolerance, sweep cap,
+  // bfloat16 copies of Phi, the accumulated solution and the last sweep counts
+  double tol_in = 1e-2;
+  int max_sweeps = 20;
+  uint16_t *phiA16 = nullptr, *phiB16 = nullptr;
+  float* Xt = nullptr;
+  double* xtm = nullptr;
+  std::vector<int32_t> sweeps;
   bool has_solution = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -140,7 +148,7 @@ void destroy_ctx(cofem_ctx* c) {
 cofem_status push_controls(cofem_ctx* c) {
   CgScalars h;
   memset(&h, 0, sizeof(h));
-  h.tol = c->tol;
+  h.tol = c->precision == COFEM_PREC_BF16_IR ? c->tol_in : c->tol;
   h.limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
   h.fixed = c->fixed_iters > 0 ? 1 : 0;
   h.kp = c->KP;
@@ -178,7 +186,12 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
       dd.ring = rg;
     }
   }
+  dd.S1h = dense16_split(dd.Np / 64, dd.Dp / 16);
+  dd.S2h = dense16_split(dd.Dp / 64, dd.Np / 16);
   c->KP = kDenseKP;
+  const bool lowp = c->precision == COFEM_PREC_BF16_IR;
+  const int s1 = lowp && dd.S1h > dd.S1 ? dd.S1h : dd.S1;
+  const int s2 = lowp && dd.S2h > dd.S2 ? dd.S2h : dd.S2;
 
   const size_t blk = (size_t)dd.Dp * kDenseKP;
   COFEM_TRY(alloc(c, &c->phiA, (size_t)dd.Np * dd.Dp));
@@ -205,14 +218,22 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, kDenseKP + 1));
   COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, kDenseKP + 1));
   COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 32, 3 * (kDenseKP + 1)));
-  COFEM_TRY(alloc(c, &c->Wpart, (size_t)(dd.S1 > 1 ? dd.S1 : 0) * dd.Np * kDenseKP));
-  COFEM_TRY(alloc(c, &c->wmpart, (size_t)(dd.S1 > 1 ? dd.S1 : 0) * dd.Np));
-  COFEM_TRY(alloc(c, &c->Qpart, (size_t)(dd.S2 > 1 ? dd.S2 : 0) * dd.Dp * kDenseKP));
-  COFEM_TRY(alloc(c, &c->qmpart, (size_t)(dd.S2 > 1 ? dd.S2 : 0) * dd.Dp));
+  COFEM_TRY(alloc(c, &c->Wpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np * kDenseKP));
+  COFEM_TRY(alloc(c, &c->wmpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np));
+  COFEM_TRY(alloc(c, &c->Qpart, (size_t)(s2 > 1 ? s2 : 0) * dd.Dp * kDenseKP));
+  COFEM_TRY(alloc(c, &c->qmpart, (size_t)(s2 > 1 ? s2 : 0) * dd.Dp));
+  if (lowp) {
+    COFEM_TRY(alloc(c, &c->phiA16, (size_t)dd.Np * dd.Dp));
+    COFEM_TRY(alloc(c, &c->phiB16, (size_t)dd.Np * dd.Dp));
+    COFEM_TRY(alloc(c, &c->Xt, blk));
+    COFEM_TRY(alloc(c, &c->xtm, dd.Dp));
+  }
   COFEM_TRY(alloc(c, &c->cnt_split1, (size_t)(dd.Np / 32)));
   COFEM_TRY(alloc(c, &c->cnt_split2, (size_t)(dd.Dp / 32)));
 
   COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
+  if (lowp)
+    COFEM_HIP(c, dense_pack16(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA16, c->phiB16, c->stream));
   COFEM_HIP(c, dense_b0(static_cast<const float*>(p.phi), p.ld_phi, p.y, c->beta, dd, c->b0, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, dd.Dp, c->stream));
   return COFEM_OK;
@@ -281,8 +302,15 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->K < 1 || q->K > COFEM_MAX_K) return *why = "K must be in [1, 32]", COFEM_ERR_INVALID_ARG;
   if (!(q->cg_tol >= 0.0) || !isfinite(q->cg_tol)) return *why = "cg_tol must be >= 0", COFEM_ERR_INVALID_ARG;
   if (q->cg_max_iter < 0) return *why = "cg_max_iter must be >= 0", COFEM_ERR_INVALID_ARG;
-  if (q->precision != COFEM_PREC_FP32 && q->precision != COFEM_PREC_FP64)
-    return *why = "precision mode not built", COFEM_ERR_UNSUPPORTED;
+  if (q->precision != COFEM_PREC_FP32 && q->precision != COFEM_PREC_FP64 && q->precision != COFEM_PREC_BF16_IR)
+    return *why = "unknown precision mode", COFEM_ERR_INVALID_ARG;
+  if (q->precision == COFEM_PREC_BF16_IR) {
+    if (p->kind != COFEM_DENSE)
+      return *why = "COFEM_PREC_BF16_IR is built for dense dictionaries only", COFEM_ERR_UNSUPPORTED;
+    if (!(q->ir_inner_tol >= 0.0) || !(q->ir_inner_tol < 1.0))
+      return *why = "ir_inner_tol must be in [0, 1) (0 selects 1e-2)", COFEM_ERR_INVALID_ARG;
+    if (q->ir_max_sweeps < 0) return *why = "ir_max_sweeps must be >= 0", COFEM_ERR_INVALID_ARG;
+  }
   if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
     return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
   if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
@@ -348,10 +376,21 @@ cofem_status collect_times(cofem_ctx* c, int iters) {
   return COFEM_OK;
 }
 
-cofem_status run_cg_iterations(cofem_ctx* c, int n) {
+cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
   for (int i = 0; i < n; ++i) {
     const int it = c->cg_enq++;
-    if (c->kind == COFEM_DENSE) {
+    if (c->kind == COFEM_DENSE && lowp) {
+      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_HIP(c, dense16_pass1(c->dd, c->phiA16, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
+                                 c->cnt_split1, c->st, 0, c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
+      COFEM_HIP(c, dense16_pass2(c->dd, c->phiB16, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
+                                 c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
+                                 c->cnt_split2, c->st, 0, c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
+      COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
+                                c->cnts_upd, c->st, c->stream));
+    } else if (c->kind == COFEM_DENSE) {
       COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
       COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
                                c->cnt_split1, c->st, 0, c->stream));
@@ -402,7 +441,106 @@ cofem_status read_state(cofem_ctx* c) {
   return COFEM_OK;
 }
 
+// Mixed-precision E-step (COFEM_PREC_BF16_IR): iterative refinement.  X = 0,
+// R = B; each sweep solves A~ D = R by CG with the bfloat16 Phi to the inner
+// tolerance (relative to ||R||_F), adds D to X, and forms the outer residual
+// R = B - A X with the float32 Phi and float64 sums; the sweeps stop once
+// ||R||_F / ||B||_F < eps, after U inner iterations in total, or after
+// max_sweeps sweeps.  The M-step then reads the accumulated X.
+constexpr int kIrStall = 3;
+
+cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
+  const int t = c->t_next;
+  const DenseDims& dd = c->dd;
+  COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  c->kev_used = 0;
+  c->sweeps.clear();
+  COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
+  COFEM_HIP(c, dense_init(dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->parts_init,
+                          c->cnts_init, c->st, c->stream));
+  COFEM_HIP(c, fill_f32(c->Xt, 0.0f, dd.Dp * kDenseKP, c->stream));
+  COFEM_HIP(c, hipMemsetAsync(c->xtm, 0, sizeof(double) * dd.Dp, c->stream));
+  COFEM_TRY(read_state(c));
+  double outer = c->host_st->nB0 > 0.0 ? 1.0 : 0.0, best = outer;
+  int total = 0, stall = 0;
+  for (;;) {
+    // The true residual of refinement need not fall monotonically.  Stop at the
+    // tolerance, at the caps, or after kIrStall sweeps in a row without halving
+    // the best ratio so far (its float32 evaluation has reached its floor).
+    if (!c->sweeps.empty()) {
+      if (outer < 0.5 * best) {
+        best = outer;
+        stall = 0;
+      } else {
+        ++stall;
+      }
+    }
+    if (outer < c->tol || total >= c->U || (int)c->sweeps.size() >= c->max_sweeps || stall >= kIrStall) break;
+    // inner solve with the bfloat16 dictionary
+    c->cg_enq = 0;
+    int chunk = c->poll, enqueued = 0;
+    const int limit = c->U - total;
+    if (chunk > limit) chunk = limit;
+    for (;;) {
+      if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk, true));
+      enqueued += chunk;
+      COFEM_TRY(read_state(c));
+      if (c->host_st->stop) break;
+      if (enqueued > limit + 2) return fail(c, COFEM_ERR_DEVICE, "inner CG did not report completion");
+      chunk = c->poll;
+      if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
+    }
+    if (c->host_st->numeric_error)
+      return fail(c, COFEM_ERR_NUMERIC, "non-finite value in an inner CG scalar at EM iteration " + std::to_string(t));
+    const int n_in = c->host_st->iter;
+    COFEM_TRY(mark(c, -1, 0));
+    COFEM_TRY(collect_times(c, n_in));
+    total += n_in;
+    c->sweeps.push_back(n_in);
+    // outer residual with the float32 dictionary
+    COFEM_TRY(mark(c, COFEM_KT_CHECK, 0));
+    COFEM_HIP(c, dense_ir_accumulate(dd, c->Xt, c->X, c->xtm, c->xm, c->stream));
+    COFEM_HIP(c, dense_pass1(dd, c->phiA, c->Xt, c->xtm, c->Wpart, c->wmpart, c->W, c->wm, c->cnt_split1, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_pass2(dd, c->phiB, c->W, c->wm, c->Xt, c->xtm, c->R, c->rm, c->alpha, c->beta, c->Qpart,
+                             c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_ir_residual(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->X, c->R, c->P, c->xm, c->rm, c->pm,
+                                   c->parts_upd, c->cnts_upd, c->st, c->U - total, c->stream));
+    COFEM_TRY(mark(c, -1, 0));
+    COFEM_TRY(read_state(c));
+    COFEM_TRY(collect_times(c, 0));
+    if (c->host_st->numeric_error)
+      return fail(c, COFEM_ERR_NUMERIC, "non-finite outer residual at EM iteration " + std::to_string(t));
+    outer = c->host_st->true_ratio;
+  }
+  COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
+  COFEM_HIP(c, dense_mstep(dd, c->seed, t, c->K, c->Xt, c->xtm, c->alpha, c->alpha_max, c->mu, c->sdiag, c->st,
+                           c->stream));
+  COFEM_TRY(mark(c, -1, 0));
+  COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  COFEM_TRY(read_state(c));
+  COFEM_TRY(collect_times(c, 0));
+  c->has_solution = true;
+  c->prev_iters = total;
+  c->t_next = t + 1;
+  if (out) {
+    float ms = 0.0f;
+    COFEM_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    out->t = t;
+    out->cg_iters = total;
+    out->converged = outer < c->tol ? 1 : 0;
+    out->n_clamped = c->host_st->n_clamped;
+    out->rel_resid = outer;
+    out->ms = ms;
+    out->rel_resid_true = outer;
+    out->ir_sweeps = (int32_t)c->sweeps.size();
+  }
+  return COFEM_OK;
+}
+
 cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
+  if (c->precision == COFEM_PREC_BF16_IR) return em_iteration_ir(c, out);
   const int t = c->t_next;
   COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
   c->cg_enq = 0;
@@ -457,6 +595,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     out->rel_resid = c->host_st->ratio;
     out->ms = ms;
     out->rel_resid_true = c->true_resid ? c->host_st->true_ratio : -1.0;
+    out->ir_sweeps = 0;
   }
   return COFEM_OK;
 }
@@ -486,6 +625,8 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   c->poll = params->poll_interval > 0 ? params->poll_interval : 8;
   c->precision = params->precision;
   c->true_resid = (params->flags & COFEM_FLAG_TRUE_RESIDUAL) != 0;
+  c->tol_in = params->ir_inner_tol > 0.0 ? params->ir_inner_tol : 1e-2;
+  c->max_sweeps = params->ir_max_sweeps > 0 ? params->ir_max_sweeps : 20;
   c->stream = static_cast<hipStream_t>(hip_stream);
   cofem_status s = COFEM_OK;
   hipError_t e = hipGetDevice(&c->device);
@@ -549,6 +690,8 @@ cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t) {
 
 cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (ctx->precision == COFEM_PREC_BF16_IR)
+    return fail(ctx, COFEM_ERR_UNSUPPORTED, "fixed CG counts are not available under COFEM_PREC_BF16_IR");
   if (n < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "n must be >= 0");
   ctx->fixed_iters = n;
   ctx->prev_iters = n;
@@ -558,35 +701,46 @@ cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n) {
 cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, double* mean) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  const bool ir = ctx->precision == COFEM_PREC_BF16_IR;
   if (probes) {
     if (ctx->kind == COFEM_DENSE) {
-      COFEM_HIP(ctx, dense_to_colmajor(ctx->dd, ctx->K, ctx->X, probes, ctx->stream));
+      COFEM_HIP(ctx, dense_to_colmajor(ctx->dd, ctx->K, ir ? ctx->Xt : ctx->X, probes, ctx->stream));
     } else {
       COFEM_HIP(ctx, conv_probes_out(ctx->cd, ctx->vX, probes, ctx->stream));
     }
   }
   if (mean)
-    COFEM_HIP(ctx, hipMemcpyAsync(mean, ctx->xm, sizeof(double) * (size_t)ctx->D, hipMemcpyDeviceToDevice,
-                                  ctx->stream));
+    COFEM_HIP(ctx, hipMemcpyAsync(mean, ir ? ctx->xtm : ctx->xm, sizeof(double) * (size_t)ctx->D,
+                                  hipMemcpyDeviceToDevice, ctx->stream));
   return COFEM_OK;
 }
 
-cofem_status cofem_apply_A(cofem_ctx* ctx, int32_t problem, const float* v_probes, const double* v_mean,
-                           float* q_probes, double* q_mean) {
+static cofem_status apply_A_impl(cofem_ctx* ctx, int32_t problem, const float* v_probes, const double* v_mean,
+                                 float* q_probes, double* q_mean, bool lowp) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
   if (!v_probes || !v_mean || !q_probes || !q_mean) return fail(ctx, COFEM_ERR_INVALID_ARG, "null vector");
+  if (lowp && ctx->precision != COFEM_PREC_BF16_IR)
+    return fail(ctx, COFEM_ERR_UNSUPPORTED, "the low-precision operator exists only under COFEM_PREC_BF16_IR");
   const size_t Dm = sizeof(double) * (size_t)ctx->D;
   if (ctx->kind == COFEM_DENSE) {
     const DenseDims& dd = ctx->dd;
     COFEM_HIP(ctx, dense_from_colmajor(dd, ctx->K, v_probes, ctx->Vs, ctx->stream));
     COFEM_HIP(ctx, hipMemsetAsync(ctx->Vsm, 0, sizeof(double) * dd.Dp, ctx->stream));
     COFEM_HIP(ctx, hipMemcpyAsync(ctx->Vsm, v_mean, Dm, hipMemcpyDeviceToDevice, ctx->stream));
-    COFEM_HIP(ctx, dense_pass1(dd, ctx->phiA, ctx->Vs, ctx->Vsm, ctx->Wpart, ctx->wmpart, ctx->W, ctx->wm,
-                               ctx->cnt_split1, ctx->st, 1, ctx->stream));
-    COFEM_HIP(ctx, dense_pass2(dd, ctx->phiB, ctx->W, ctx->wm, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm,
-                               ctx->alpha, ctx->beta, ctx->Qpart, ctx->qmpart, ctx->Qs, ctx->Qsm,
-                               ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1, ctx->stream));
+    if (lowp) {
+      COFEM_HIP(ctx, dense16_pass1(dd, ctx->phiA16, ctx->Vs, ctx->Vsm, ctx->Wpart, ctx->wmpart, ctx->W, ctx->wm,
+                                   ctx->cnt_split1, ctx->st, 1, ctx->stream));
+      COFEM_HIP(ctx, dense16_pass2(dd, ctx->phiB16, ctx->W, ctx->wm, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm,
+                                   ctx->alpha, ctx->beta, ctx->Qpart, ctx->qmpart, ctx->Qs, ctx->Qsm,
+                                   ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1, ctx->stream));
+    } else {
+      COFEM_HIP(ctx, dense_pass1(dd, ctx->phiA, ctx->Vs, ctx->Vsm, ctx->Wpart, ctx->wmpart, ctx->W, ctx->wm,
+                                 ctx->cnt_split1, ctx->st, 1, ctx->stream));
+      COFEM_HIP(ctx, dense_pass2(dd, ctx->phiB, ctx->W, ctx->wm, ctx->Vs, ctx->Vsm, ctx->Vs, ctx->Vsm,
+                                 ctx->alpha, ctx->beta, ctx->Qpart, ctx->qmpart, ctx->Qs, ctx->Qsm,
+                                 ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1, ctx->stream));
+    }
     COFEM_HIP(ctx, dense_to_colmajor(dd, ctx->K, ctx->Qs, q_probes, ctx->stream));
   } else {
     const ConvDims& cd = ctx->cd;
@@ -598,6 +752,27 @@ cofem_status cofem_apply_A(cofem_ctx* ctx, int32_t problem, const float* v_probe
   }
   COFEM_HIP(ctx, hipMemcpyAsync(q_mean, ctx->Qsm, Dm, hipMemcpyDeviceToDevice, ctx->stream));
   COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_apply_A(cofem_ctx* ctx, int32_t problem, const float* v_probes, const double* v_mean,
+                           float* q_probes, double* q_mean) {
+  return apply_A_impl(ctx, problem, v_probes, v_mean, q_probes, q_mean, false);
+}
+
+cofem_status cofem_apply_A_lowp(cofem_ctx* ctx, int32_t problem, const float* v_probes, const double* v_mean,
+                                float* q_probes, double* q_mean) {
+  return apply_A_impl(ctx, problem, v_probes, v_mean, q_probes, q_mean, true);
+}
+
+cofem_status cofem_get_ir_sweeps(cofem_ctx* ctx, int32_t* counts, int32_t capacity, int32_t* n) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (!n || capacity < 0 || (capacity > 0 && !counts)) return fail(ctx, COFEM_ERR_INVALID_ARG, "bad output");
+  if (ctx->precision != COFEM_PREC_BF16_IR)
+    return fail(ctx, COFEM_ERR_UNSUPPORTED, "refinement sweeps exist only under COFEM_PREC_BF16_IR");
+  const int32_t m = (int32_t)ctx->sweeps.size();
+  for (int32_t i = 0; i < m && i < capacity; ++i) counts[i] = ctx->sweeps[i];
+  *n = m;
   return COFEM_OK;
 }
 

@@ -39,7 +39,8 @@ struct CgScalars {
   int32_t numeric_error;  // set when a CG scalar is not finite
   uint32_t counter[4];    // last-block tickets (self-resetting)
   double true_res[kMaxCols];  // ||b_c - A x_c||^2 of the last solve (float64 sums)
-  double true_ratio;          // sqrt(sum_c true_res[c]) / nB
+  double true_ratio;          // sqrt(sum_c true_res[c]) / nB0
+  double nB0;                 // ||B||_F of the E-step (nB is the current solve's reference)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -222,6 +223,24 @@ __device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts
   return true;
 }
 
+// ------------------------------------------------ per-block column sums (dense)
+// Thread tid owns probe column tid & 31 (acc) and a share of the mean column
+// (accm); leaves the block's 33 sums in out_sh (256-thread blocks).
+__device__ __forceinline__ void dense_block_sums(double acc, double accm, double* out_sh) {
+  __shared__ double sh[kThreads];
+  __shared__ double shm[8];
+  sh[threadIdx.x] = acc;
+  const double m = block_sum(accm, shm);  // synchronises
+  if (threadIdx.x < kDenseKP) {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < kThreads; t += kDenseKP) v += sh[t];
+    out_sh[threadIdx.x] = v;
+  } else if (threadIdx.x == kDenseKP) {
+    out_sh[kDenseKP] = m;
+  }
+  __syncthreads();
+}
+
 // The finish_* helpers run in the last block of a reduction, all threads,
 // with the per-column totals in shared memory.  Column c is handled by thread
 // c, so the loads of the scalar block are issued together (one round trip to
@@ -295,6 +314,7 @@ __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
     double sum = 0.0;
     for (int c = 0; c < nc; ++c) sum += rho[c];
     st->nB = sqrt(sum);
+    st->nB0 = sqrt(sum);
     st->ratio = sum > 0.0 ? 1.0 : 0.0;
     st->iter = 0;
     st->n_clamped = 0;
@@ -317,6 +337,33 @@ __device__ __forceinline__ void finish_true_resid(CgScalars* st, const double* r
   }
 }
 
+// Finishes the outer residual of an iterative-refinement sweep (||r_c||^2 in
+// shared memory): the next inner solve starts from R with reference norm
+// ||R||_F, a fresh iteration count and cap `limit`; true_ratio = ||R||_F/||B||_F.
+__device__ __forceinline__ void finish_ir_residual(CgScalars* st, const double* rho, int limit) {
+  const int nc = st->kp + 1;
+  if ((int)threadIdx.x < nc) {
+    st->rho[threadIdx.x] = rho[threadIdx.x];
+    st->true_res[threadIdx.x] = rho[threadIdx.x];
+    st->a[threadIdx.x] = 0.0;
+    st->b[threadIdx.x] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    const double nB0 = st->nB0;
+    double sum = 0.0;
+    for (int c = 0; c < nc; ++c) sum += rho[c];
+    const bool finite = isfinite(sum);
+    const double nr = sqrt(sum);
+    st->nB = nr;
+    st->true_ratio = nB0 > 0.0 ? nr / nB0 : 0.0;
+    st->ratio = sum > 0.0 ? 1.0 : 0.0;
+    st->iter = 0;
+    st->limit = limit;
+    if (!finite) st->numeric_error = 1;
+    st->stop = (sum == 0.0) || (limit <= 0) || !finite;
+  }
+}
+
 // ------------------------------------------------------------ host launchers
 // Dense problem geometry.  Np and Dp are N and D padded to multiples of 64.
 // Probe-column state uses the blocked-4 layout: element (d, c) of a Dp x 32
@@ -327,6 +374,7 @@ struct DenseDims {
   int64_t N, D, Np, Dp;
   int S1, S2;  // workgroups sharing one tile's reduction in pass 1 / pass 2
   int ring;    // outstanding 8-wide groups per wave (1, 2, 4 or 8)
+  int S1h, S2h;  // splits of the bfloat16 passes (two tiles per workgroup)
 };
 
 __host__ __device__ __forceinline__ int64_t blk4(int64_t d, int c) {
@@ -359,6 +407,23 @@ hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const f
 hipError_t dense_to_colmajor(const DenseDims& dd, int K, const float* Xb, float* out, hipStream_t s);
 hipError_t dense_from_colmajor(const DenseDims& dd, int K, const float* in, float* Xb, hipStream_t s);
 int dense_update_blocks(const DenseDims& dd);
+// bfloat16-dictionary passes of the mixed-precision form (kernels_dense_bf16.hip)
+hipError_t dense_pack16(const float* phi, int64_t ld, const DenseDims& dd, void* phiA16, void* phiB16,
+                        hipStream_t s);
+int dense16_split(int64_t pairs, int64_t groups);
+bool dense16_split_ok(int64_t groups, int splits);
+hipError_t dense16_pass1(const DenseDims& dd, const void* phiA16, const float* P, const double* pm,
+                         float* Wpart, double* wmpart, float* W, double* wm, uint32_t* cnts, CgScalars* st,
+                         int apply_only, hipStream_t s);
+hipError_t dense16_pass2(const DenseDims& dd, const void* phiB16, const float* W, const double* wm,
+                         const float* P, const double* pm, const float* R, const double* rm, const float* alpha,
+                         double beta, float* Qpart, double* qmpart, float* Q, double* qm, double* gpart,
+                         uint32_t* counter, uint32_t* split_cnts, CgScalars* st, int apply_only, hipStream_t s);
+hipError_t dense_ir_accumulate(const DenseDims& dd, float* Xt, const float* Xi, double* xtm, const double* xim,
+                               hipStream_t s);
+hipError_t dense_ir_residual(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0, const float* Q,
+                             const double* qm, float* Xi, float* R, float* P, double* xim, double* rm, double* pm,
+                             double* parts, uint32_t* cnts, CgScalars* st, int limit, hipStream_t s);
 // ||B - Q||^2 per column with B regenerated (probes of EM iteration t, b0) and
 // Q = A X from the operator passes (blocked-4 probe block + float64 column).
 hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,

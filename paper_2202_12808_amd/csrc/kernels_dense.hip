@@ -93,24 +93,6 @@ hipError_t dense_b0(const float* phi, int64_t ld, const float* y, double beta, c
   return hipGetLastError();
 }
 
-// ------------------------------------------------ per-block column sums
-// Thread tid owns probe column tid & 31 (acc) and a share of the mean column
-// (accm); leaves the block's 33 sums in out_sh (256-thread blocks).
-__device__ __forceinline__ void dense_block_sums(double acc, double accm, double* out_sh) {
-  __shared__ double sh[kThreads];
-  __shared__ double shm[8];
-  sh[threadIdx.x] = acc;
-  const double m = block_sum(accm, shm);  // synchronises
-  if (threadIdx.x < kDenseKP) {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < kThreads; t += kDenseKP) v += sh[t];
-    out_sh[threadIdx.x] = v;
-  } else if (threadIdx.x == kDenseKP) {
-    out_sh[kDenseKP] = m;
-  }
-  __syncthreads();
-}
-
 int dense_update_blocks(const DenseDims& dd) {
   const int64_t want = (dd.Dp * 8 + 4 * 256 - 1) / (4 * 256);
   return (int)(want < 1 ? 1 : (want > 256 ? 256 : want));

@@ -66,7 +66,12 @@ def _params(**kw):
     ({}, {"K": 33}, C.COFEM_ERR_INVALID_ARG),
     ({}, {"cg_tol": -1.0}, C.COFEM_ERR_INVALID_ARG),
     ({}, {"cg_max_iter": -1}, C.COFEM_ERR_INVALID_ARG),
-    ({}, {"precision": 7}, C.COFEM_ERR_UNSUPPORTED),
+    ({}, {"precision": 7}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"precision": C.COFEM_PREC_BF16_IR, "ir_inner_tol": 1.5}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"precision": C.COFEM_PREC_BF16_IR, "ir_max_sweeps": -1}, C.COFEM_ERR_INVALID_ARG),
+    ({"kind": C.COFEM_CONV2D_CIRC, "H": 4, "W": 4, "N": 16, "D": 16, "kh": 3, "kw": 3, "taps": 3},
+     {"precision": C.COFEM_PREC_BF16_IR}, C.COFEM_ERR_UNSUPPORTED),
+    ({}, {"precision": C.COFEM_PREC_FP64}, C.COFEM_ERR_UNSUPPORTED),
     ({"N": 0}, {}, C.COFEM_ERR_INVALID_ARG),
     ({"D": 0}, {}, C.COFEM_ERR_INVALID_ARG),
     ({"phi": None}, {}, C.COFEM_ERR_INVALID_ARG),

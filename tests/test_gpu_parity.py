@@ -103,6 +103,36 @@ def test_dense_apply_A(torch_dev, N, D, K):
     assert relerr(qm, A(vm)) < 1e-13
 
 
+@pytest.mark.parametrize("N,D,K", [(256, 1024, 20), (200, 700, 5), (1, 33, 1), (333, 129, 32), (4096, 2048, 32)])
+def test_dense_lowp_apply_A(torch_dev, N, D, K):
+    # inner operator of the mixed-precision form: A~ = beta Phi~^T Phi~ + diag(alpha)
+    # with Phi~ = bf16(Phi).  The float32 operand is carried as a bfloat16 head
+    # and tail (relative error <= 2^-17), the sums in float32: 2e-5 per column.
+    torch = torch_dev
+    _say("dense lowp apply_A", N, D, K)
+    p = synth.dense_problem(N, D, nnz=min(5, D), beta=123.0, K=K, tol=1e-6, seed=N + D)
+    rng = np.random.default_rng(8)
+    alpha = (10.0 ** rng.uniform(-2, 6, D)).astype(np.float32)
+    V = rng.standard_normal((D, K)).astype(np.float32)
+    vm = rng.standard_normal(D)
+    with _dense_ctx(torch, p, precision="bf16_ir") as g:
+        g.set_alpha(torch.from_numpy(alpha))
+        q, qm = g.apply_A(torch.from_numpy(V.T.copy()), torch.from_numpy(vm), lowp=True)
+        q = q.cpu().numpy().T
+        qm = qm.cpu().numpy()
+        q32, _ = g.apply_A(torch.from_numpy(V.T.copy()), torch.from_numpy(vm))
+        q32 = q32.cpu().numpy().T
+    opb = O.DenseOperator(synth.round_to_bf16(p.phi).astype(np.float64))
+    A = O.cofem_oracle.make_apply_A(opb, p.beta, alpha.astype(np.float64))
+    ref = A(V.astype(np.float64))
+    for k in range(K):
+        assert relerr(q[:, k], ref[:, k]) < 2e-5, k
+    assert relerr(qm, A(vm)) < 1e-13
+    # the float32 operator of the same context is still the problem's own
+    A32 = O.cofem_oracle.make_apply_A(_oracle_op(p), p.beta, alpha.astype(np.float64))
+    assert relerr(q32[:, 0], A32(V[:, :1].astype(np.float64))[:, 0]) < 2e-6
+
+
 @pytest.mark.parametrize("H,W,k,K", [(32, 32, 7, 4), (40, 37, 7, 3), (64, 48, 9, 16), (13, 70, 3, 2),
                                      (5, 9, 5, 1), (33, 33, 1, 2), (256, 256, 7, 16)])
 def test_conv_apply_A(torch_dev, H, W, k, K):
@@ -259,6 +289,72 @@ def test_conv_256x256_k7_fp32_error_floor(torch_dev):
     _say("conv_256x256_k7 fp32 floor: cg", stats["cg_iters"], "relerr mu/s/(1/alpha)", errs)
     assert errs[0] < STEP_TOL
     assert errs[1] < 1e-3 and errs[2] < 1e-3
+
+
+# ------------------------------------------------------------------ mixed precision
+def _ir_step_parity(torch, p, t_free, label, tol_in=1e-2):
+    """Free-run the bf16-IR form t_free EM iterations, then one teacher-forced
+    step: the oracle's iterative refinement (outer operator Phi, inner
+    operator bf16(Phi)) replays the GPU's sweeps with its inner counts."""
+    op = _oracle_op(p)
+    opb = O.DenseOperator(synth.round_to_bf16(p.phi).astype(np.float64))
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _dense_ctx(torch, p, precision="bf16_ir", ir_inner_tol=tol_in) as g:
+        if t_free:
+            g.em_step(t_free)
+        alpha = g.posterior()[2].cpu().numpy().astype(np.float64)
+        st = g.em_step(1)[0]
+        sweeps = g.ir_sweeps()
+        mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    assert st["ir_sweeps"] == len(sweeps) and sum(sweeps) == st["cg_iters"]
+    e, info = O.cofem_estep_ir(op, opb, b0, p.beta, alpha, p.K, p.tol, tol_in, p.max_iter, 20, p.seed, st["t"],
+                               fixed_inner=sweeps)
+    a_ref, _ = O.mstep(e.mu, e.s)
+    errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / a_new, 1.0 / a_ref))
+    _say(label, "t", st["t"], "sweeps", sweeps, "gpu outer ratio", st["rel_resid"], "oracle", info.rel_resid,
+         "relerr mu/s/(1/alpha)", errs)
+    # The GPU evaluates the outer residual with float32 products, whose
+    # rounding floor is ~ u32 * beta * ||Phi||_2^2 * ||X||_F / ||B||_F; the
+    # refinement stops there (stagnation) when that floor lies above eps.
+    floor = (2.0 ** -24 * p.beta * np.linalg.norm(p.phi.astype(np.float64), 2) ** 2
+             * np.linalg.norm(e.X) / np.linalg.norm(np.concatenate([e.P, b0[:, None]], axis=1)))
+    _say("outer float32 floor", floor)
+    assert st["rel_resid"] < max(p.tol, floor)
+    assert info.rel_resid <= st["rel_resid"] * 1.5
+    assert all(err < STEP_TOL for err in errs), errs
+    return e
+
+
+@pytest.mark.parametrize("t_free", [0, 5])
+def test_dense_256x1024_bf16_ir_step_parity(torch_dev, t_free):
+    _ir_step_parity(torch_dev, synth.dense_256x1024(0), t_free, f"dense_256x1024 bf16-IR t_free={t_free}")
+
+
+def test_dense_ragged_bf16_ir_step_parity(torch_dev):
+    p = synth.dense_problem(300, 777, nnz=9, beta=500.0, K=7, tol=1e-6, seed=11)
+    _ir_step_parity(torch_dev, p, 2, "dense_300x777 bf16-IR", tol_in=1e-3)
+
+
+def test_bf16_ir_solution_matches_float64_solve(torch_dev):
+    # the refined solution solves the float32 problem (not the bf16 one): mu of
+    # the first E-step against a Cholesky solve of A mu = b0 in float64, within
+    # the bound kappa(A) * eps that the outer stop rule implies
+    torch = torch_dev
+    p = synth.dense_256x1024(0)
+    with _dense_ctx(torch, p, precision="bf16_ir") as g:
+        st = g.em_step(1)[0]
+        X, m = g.solution()
+    m = m.cpu().numpy()
+    phi = p.phi.astype(np.float64)
+    A = p.beta * phi.T @ phi + np.eye(p.D)
+    mu_exact = np.linalg.solve(A, p.beta * phi.T @ p.y.astype(np.float64))
+    phib = synth.round_to_bf16(p.phi).astype(np.float64)
+    mu_bf16 = np.linalg.solve(p.beta * phib.T @ phib + np.eye(p.D), p.beta * phi.T @ p.y.astype(np.float64))
+    err, err_b = relerr(m, mu_exact), relerr(mu_bf16, mu_exact)
+    _say("bf16-IR first step: relerr mu vs float64 solve", err, "(bf16 system's own solution:", err_b, ")",
+         "sweeps", st["ir_sweeps"])
+    assert err < np.linalg.cond(A) * p.tol
+    assert err < 0.1 * err_b
 
 
 # ------------------------------------------------------------------ true residual

@@ -97,3 +97,24 @@ def test_estep_ir_matches_plain_estep_when_inner_is_exact():
     assert len(info.sweeps) == 1
     np.testing.assert_allclose(e_ir.mu, e.mu, rtol=1e-12, atol=0)
     np.testing.assert_allclose(e_ir.s, e.s, rtol=1e-12, atol=1e-15)
+
+
+def test_ir_stops_after_three_stalled_sweeps():
+    # an inner operator so far from A that refinement cannot contract (A/5:
+    # every correction overshoots, R -> -4 R): the loop ends after IR_STALL
+    # sweeps without halving the best ratio
+    phi, alpha, beta, A, B = _spd_problem(seed=6)
+    op = O.DenseOperator(phi)
+    a = make_apply_A(op, beta, alpha)
+    bad = make_apply_A(op, 0.2 * beta, 0.2 * alpha)
+    X, info = ir_solve(a, bad, B, tol=1e-12, tol_in=1e-6, max_iter=10000, max_sweeps=100)
+    h = info.history
+    assert not info.converged and len(info.sweeps) < 100
+    best = h[0]
+    stall = 0
+    for r in h[1:]:
+        if r < 0.5 * best:
+            best, stall = r, 0
+        else:
+            stall += 1
+    assert stall == 3 and len(info.sweeps) == 3
