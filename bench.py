@@ -39,23 +39,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(p, which):
-    """Bytes one launch must move at minimum: the dictionary once plus the
-    skinny operands it is contracted with (K probe columns float32, the mean
-    column float64)."""
+def algorithmic_bytes(p, which, phi_bytes=4):
+    """Bytes one launch must move at minimum: the dictionary once (4 bytes an
+    entry in float32, 2 in bfloat16) plus the skinny operands it is contracted
+    with (K probe columns float32, the mean column float64)."""
     K, N, D = p.K, p.N, p.D
     col = 4 * K + 8
     if p.kind == "dense":
         if which == "pass1":   # W = Phi P: Phi, P in, W out
-            return 4 * N * D + D * col + N * col
+            return phi_bytes * N * D + D * col + N * col
         # pass 2: Phi, W in; P, R, alpha in; Q out
-        return 4 * N * D + N * col + 3 * D * col + 4 * D
+        return phi_bytes * N * D + N * col + 3 * D * col + 4 * D
     # conv fused pass: P, R, alpha in; Q out (taps negligible)
     return 3 * D * col + 4 * D
 
 
 KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "update": "k_dense_update"},
+                "dense_bf16_ir": {"pass1": "k_dense16_pass1", "pass2": "k_dense16_pass2", "update": "k_dense_update"},
                 "conv": {"pass1": "k_conv_pass", "update": "k_conv_update"}}
+FORMS = {"fp32": "fp32 probes + fp64 mean column",
+         "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column)"}
 KERNEL_SOURCES = {"dense": ("paper_2202_12808_amd/csrc/kernels_dense.hip", "paper_2202_12808_amd/csrc/cofem_internal.h"),
                   "conv": ("paper_2202_12808_amd/csrc/kernels_conv.hip", "paper_2202_12808_amd/csrc/cofem_internal.h")}
 
@@ -105,6 +108,15 @@ def main():
                     help="time the steps without the per-launch events (roofline from cofem_time_operator)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (counter calibration)")
+    ap.add_argument("--form", default="fp32", choices=sorted(FORMS),
+                    help="solver form timed for the headline value (bf16_ir: dense only)")
+    ap.add_argument("--ir-inner-tol", type=float, default=0.0,
+                    help="bf16_ir: relative tolerance of each inner solve (0: the library default, 0.1)")
+    ap.add_argument("--oracle-trajectory", action="store_true",
+                    help="also run the float64 oracle for the whole T_em trajectory (minutes of host time) "
+                         "and report each form's NMSE of mu_T against it")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="dense: do not also time the other form on the same inputs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -128,13 +140,20 @@ def main():
     log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} beta={p.beta} tol={p.tol} U={p.max_iter} "
         f"T_em={T_em} (inputs generated in {time.perf_counter() - t_gen:.1f}s)")
 
+    if args.form != "fp32" and p.kind != "dense":
+        print("--form bf16_ir is built for dense dictionaries only", file=sys.stderr, flush=True)
+        sys.exit(2)
     y = torch.from_numpy(p.y).to(dev)
-    if p.kind == "dense":
-        phi = torch.from_numpy(p.phi).to(dev)
-        g = CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
-    else:
+    phi = torch.from_numpy(p.phi).to(dev) if p.kind == "dense" else None
+
+    def make(form):
+        if p.kind == "dense":
+            return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, precision=form,
+                               ir_inner_tol=args.ir_inner_tol)
         taps = torch.from_numpy(p.taps).to(dev)
-        g = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+        return CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+
+    g = make(args.form)
     ones = torch.ones(p.D, dtype=torch.float32, device=dev)
     if args.calibration_copy_mib > 0:
         n = args.calibration_copy_mib << 18
@@ -155,6 +174,7 @@ def main():
     g.set_alpha(ones)
     g.set_iteration(1)
     first = g.em_step(1)[0]
+    first_sweeps = g.ir_sweeps() if args.form == "bf16_ir" else None
     mu1, s1, a1 = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
 
     for w in range(args.warmup):
@@ -181,7 +201,8 @@ def main():
 
     # roofline of the dominant operator kernel: mean launch time inside the
     # timed solves (events recorded by the library on its stream)
-    names = KERNEL_NAMES[p.kind]
+    names = KERNEL_NAMES["dense_bf16_ir" if args.form == "bf16_ir" else p.kind]
+    phi_bytes = 2 if args.form == "bf16_ir" else 4
     ops = [k for k in ("pass1", "pass2") if k in names]
     if not args.no_kernel_timing:
         kt = g.kernel_timing()
@@ -196,7 +217,7 @@ def main():
         total, launches = dict(per), {k: args.timing_reps for k in ops}
         source = "cofem_time_operator back-to-back launches"
     dom = max(ops, key=lambda k: total[k])
-    nbytes = algorithmic_bytes(p, dom)
+    nbytes = algorithmic_bytes(p, dom, phi_bytes)
     achieved = nbytes / (per[dom] * 1e-3) / 1e9
     traffic = stored_traffic(p.kind, names[dom], p.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -207,6 +228,70 @@ def main():
     log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak); per-launch us "
         + ", ".join(f"{names[k]} {per[k] * 1e3:.1f}" for k in per))
+
+    # the other form on the same inputs (dense): throughput and how far its
+    # final mu lies from this form's
+    forms = None
+    mu_T2 = None
+    mean_cg_fp32 = mean_cg if args.form == "fp32" else None
+    if p.kind == "dense" and not args.no_compare:
+        other = "bf16_ir" if args.form == "fp32" else "fp32"
+        g2 = make(other)
+        for w in range(max(args.warmup, 1)):
+            g2.set_alpha(ones)
+            g2.set_iteration(1)
+            g2.em_step(T_em)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            g2.set_alpha(ones)
+            g2.set_iteration(1)
+            st2 = g2.em_step(T_em)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t1
+        mu_T2 = g2.posterior()[0].cpu().numpy().astype(np.float64)
+        cg2 = [x["cg_iters"] for x in st2]
+        if other == "fp32":
+            mean_cg_fp32 = float(np.mean(cg2))
+        ref_mu = mu_T if args.form == "fp32" else mu_T2
+        oth_mu = mu_T2 if args.form == "fp32" else mu_T
+        forms = {
+            args.form: {"value": round(value, 4), "cg_iters_per_em_mean": round(mean_cg, 2)},
+            other: {"value": round(args.steps * T_em / el2, 4), "cg_iters_per_em_mean": round(float(np.mean(cg2)), 2),
+                    "nrmse_vs_truth": round(float(np.linalg.norm(mu_T2 - p.z) / np.linalg.norm(p.z)), 6)},
+            "nmse_bf16_ir_vs_fp32_mu_T": float(np.sum((oth_mu - ref_mu) ** 2) / np.sum(ref_mu ** 2)),
+        }
+        if other == "bf16_ir" or args.form == "bf16_ir":
+            sw = [x["ir_sweeps"] for x in (st2 if other == "bf16_ir" else stats)]
+            forms["bf16_ir"]["ir_sweeps_per_em_mean"] = round(float(np.mean(sw)), 2)
+        log(f"other form {other}: {forms[other]['value']:.3f} EM it/s; NMSE(mu_T) between forms "
+            f"{forms['nmse_bf16_ir_vs_fp32_mu_T']:.3e}")
+        g2.close()
+
+    traj = None
+    if args.oracle_trajectory:
+        import oracle as O
+        op_t = (O.DenseOperator(p.phi.astype(np.float64)) if p.kind == "dense"
+                else O.ConvOperator(p.taps.astype(np.float64), p.H, p.W))
+        # two float64 trajectories: the oracle at the workload's tolerance (the
+        # plain form's twin) and a tight-tolerance reference (eps / 1000, cap
+        # 3U) that neither form's stopping point is privileged against
+        tt0 = time.perf_counter()
+        res = O.cofem(op_t, p.y, p.beta, T_em, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+        tight = O.cofem(op_t, p.y, p.beta, T_em, p.K, tol=p.tol * 1e-3, max_iter=3 * p.max_iter, seed=p.seed)
+        tt = time.perf_counter() - tt0
+
+        def nmse(m, ref):
+            return float(np.sum((m - ref.mu) ** 2) / np.sum(ref.mu ** 2))
+        mus = {args.form: mu_T}
+        if mu_T2 is not None:
+            mus["bf16_ir" if args.form == "fp32" else "fp32"] = mu_T2
+        traj = {"T_em": T_em, "host_seconds": round(tt, 1),
+                "nmse_vs_oracle": {k: nmse(m, res) for k, m in mus.items()},
+                "nmse_vs_tight_oracle": {k: nmse(m, tight) for k, m in mus.items()},
+                "oracle_vs_tight_oracle": nmse(res.mu, tight)}
+        log(f"oracle trajectories ({tt:.0f}s): NMSE of mu_T vs oracle {traj['nmse_vs_oracle']}; "
+            f"vs tight oracle {traj['nmse_vs_tight_oracle']}; oracle itself vs tight {traj['oracle_vs_tight_oracle']:.3e}")
 
     cpu = None
     parity = None
@@ -224,21 +309,32 @@ def main():
         n1 = first["cg_iters"]
         tc0 = time.perf_counter()
         b0 = p.beta * op.apply_t(p.y.astype(np.float64))
-        e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1,
-                          fixed_iters=n1)
+        if args.form == "bf16_ir":
+            # the oracle's refinement replays the GPU's sweeps (inner operator bf16(Phi))
+            opb = O.DenseOperator(synth.round_to_bf16(p.phi).astype(np.float64))
+            e, _ = O.cofem_estep_ir(op, opb, b0, p.beta, np.ones(p.D), p.K, p.tol, args.ir_inner_tol or 0.1,
+                                    p.max_iter, 20, p.seed, 1, fixed_inner=first_sweeps)
+            n_ops = n1 + 2 * len(first_sweeps)  # inner iterations + outer residuals (2 operator halves each)
+        else:
+            e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1,
+                              fixed_iters=n1)
+            n_ops = n1
         a_ref, _ = O.mstep(e.mu, e.s)
         t_sample = time.perf_counter() - tc0
-        per_cg = t_sample / max(n1, 1)
-        cpu_em_per_s = 1.0 / (per_cg * mean_cg)
+        per_cg = t_sample / max(n_ops, 1)
+        scale_cg = mean_cg_fp32 if mean_cg_fp32 is not None else mean_cg
+        cpu_em_per_s = 1.0 / (per_cg * scale_cg)
         cpu = {"value": round(cpu_em_per_s, 5), "unit": "EM it/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"first E-step + M-step of {p.name} at {n1} CG iterations took {t_sample:.2f}s "
-                         f"on the host; scaled by the GPU run's mean of {mean_cg:.1f} CG iterations "
-                         f"per EM iteration"}
+               "sample": f"first E-step + M-step of {p.name} ({n_ops} operator applications) took "
+                         f"{t_sample:.2f}s on the host; scaled to the plain float32 GPU run's mean of "
+                         f"{scale_cg:.1f} CG iterations per EM iteration"}
 
         def rel(a, b):
             return float(np.linalg.norm(a - b) / np.linalg.norm(b))
         parity = {"step": 1, "cg_iters": n1, "relerr_mu": rel(mu1, e.mu), "relerr_s": rel(s1, e.s),
                   "relerr_alpha": rel(a1, a_ref), "nmse_mu": rel(mu1, e.mu) ** 2}
+        if first_sweeps is not None:
+            parity["ir_sweeps"] = first_sweeps
         log(f"cpu oracle: {cpu_em_per_s:.4f} EM it/s on {threads} threads; parity {parity}")
 
     out = {
@@ -252,14 +348,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16+f32" if args.form == "bf16_ir" else "f32",
         "data": "synthetic",
         "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
-                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": "fp32 probes + fp64 mean column",
+                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": FORMS[args.form],
                    "cg_iters_per_em_mean": round(mean_cg, 2), "nrmse_vs_truth": round(nrmse, 6)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "forms": forms,
+        "oracle_trajectory": traj,
     }
     print(json.dumps(out), flush=True)
     g.close()

@@ -74,7 +74,12 @@ enum {
   /* After each CG solve, form the true residual ||B - A X||_F / ||B||_F with
    * one more operator application over X and float64 sums (reported in
    * cofem_iter_stats.rel_resid_true; costs one CG iteration's operator). */
-  COFEM_FLAG_TRUE_RESIDUAL = 1
+  COFEM_FLAG_TRUE_RESIDUAL = 1,
+  /* Batched form: launch each chunk of CG iterations directly instead of
+   * replaying the captured graph (same kernels, same results). */
+  COFEM_FLAG_EAGER = 2,
+  /* Use the batched form (bfloat16 dictionaries) even for n_problems == 1. */
+  COFEM_FLAG_BATCHED = 4
 };
 
 /* Maximum number of probe vectors K per problem. */
@@ -127,7 +132,8 @@ typedef struct cofem_params {
   int32_t flags;
   int32_t poll_interval;
   /* COFEM_PREC_BF16_IR only: relative tolerance of each inner solve (0 selects
-   * 1e-2) and the maximum number of refinement sweeps per E-step (0 selects 20) */
+   * 0.1, the cheapest setting measured on a 4096 x 16384 problem) and the
+   * maximum number of refinement sweeps per E-step (0 selects 20) */
   double ir_inner_tol;
   int32_t ir_max_sweeps;
 } cofem_params;
@@ -148,12 +154,23 @@ typedef struct cofem_iter_stats {
 typedef struct cofem_ctx cofem_ctx;
 
 /*
- * Creates a context for `n_problems` problems (this build: n_problems == 1)
- * with alpha = 1 (Algorithm 1, first line) and the next EM iteration t = 1.
- * Allocates device memory for the packed dictionary and the CG state
- * (dense: 2 packed float32 copies of Phi plus 4 D x 32 float32 blocks;
- * conv: 5 (K) x D float32 blocks), computes beta Phi^T y, and synchronises
- * `hip_stream` before returning.  *out receives the context.
+ * Creates a context for `n_problems` problems with alpha = 1 (Algorithm 1,
+ * first line) and the next EM iteration t = 1.  Allocates device memory for
+ * the packed dictionary and the CG state (dense: 2 packed float32 copies of
+ * Phi plus 4 D x 32 float32 blocks; conv: 5 (K) x D float32 blocks),
+ * computes beta Phi^T y, and synchronises `hip_stream` before returning.
+ * *out receives the context.
+ *
+ * Batched form (n_problems > 1, phi_dtype == COFEM_BF16, or
+ * COFEM_FLAG_BATCHED): independent
+ * dense problems sharing beta, K, cg_tol, U; problem i draws its probes with
+ * seed + i.  Each Phi_i is rounded to bfloat16 at init (or given in
+ * bfloat16) and that bfloat16 matrix is the problem; CG runs in float32
+ * with the float64 mean column, all problems' blocks in the same grouped
+ * launches, one captured HIP graph replayed per chunk of CG iterations until
+ * every problem has stopped.  An autotuner picks the workgroup budget of the
+ * grouped passes at init (cofem_batch_plan).  Needs precision
+ * COFEM_PREC_FP32 and no COFEM_FLAG_TRUE_RESIDUAL.
  */
 cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems,
                         const cofem_params* params, void* hip_stream, cofem_ctx** out);
@@ -162,7 +179,8 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems,
  * Runs `n_iters` EM iterations of Algorithm 1 (E-step by CG, diagonal
  * estimate, M-step).  Synchronises the stream at the end of every EM
  * iteration (the host reads the CG stop flag).  `stats` (host, nullable)
- * receives n_iters entries.
+ * receives n_iters entries, or n_iters * n_problems for a batched context
+ * (entry it * n_problems + i for problem i).
  */
 cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats);
 
@@ -235,6 +253,18 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
  * conv  -> {fused stencil pass, 0, 0}.  Leaves the solver state unchanged.
  */
 cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out);
+
+/*
+ * Batched form (cofem_init with n_problems > 1, or a COFEM_BF16 dictionary):
+ * the autotuner's choice.  *target_wgs: workgroups per operator pass that the
+ * grouped launches were planned for (the fastest of 256, 512, 1024, 2048 in
+ * a timed trial at init); candidate_ms[4]: the measured ms of one pass-1 +
+ * pass-2 pair for each candidate (0 if not tried); splits1/splits2[i]:
+ * reduction splits of problem i in pass 1 / pass 2.  Host pointers, each
+ * nullable.  COFEM_ERR_UNSUPPORTED for a single-problem context.
+ */
+cofem_status cofem_batch_plan(cofem_ctx* ctx, int32_t* target_wgs, float* candidate_ms, int32_t* splits1,
+                              int32_t* splits2);
 
 /* Kernel slots of cofem_get_kernel_timing. */
 enum {

@@ -33,6 +33,8 @@ COFEM_PREC_BF16_IR = 1
 COFEM_PREC_FP64 = 2
 COFEM_STOP_FROBENIUS = 0
 COFEM_FLAG_TRUE_RESIDUAL = 1
+COFEM_FLAG_EAGER = 2
+COFEM_FLAG_BATCHED = 4
 _PRECISIONS = {"fp32": COFEM_PREC_FP32, "bf16_ir": COFEM_PREC_BF16_IR, "fp64": COFEM_PREC_FP64}
 COFEM_MAX_K = 32
 
@@ -82,6 +84,8 @@ _SIGNATURES = {
     "cofem_probe_signs": (c_int32, [c_uint64, c_int32, c_int32, c_int64, c_void_p, c_void_p]),
     "cofem_time_operator": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float)]),
     "cofem_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
+    "cofem_batch_plan": (c_int32, [c_void_p, POINTER(c_int32), POINTER(ctypes.c_float), POINTER(c_int32),
+                                   POINTER(c_int32)]),
     "cofem_get_ir_sweeps": (c_int32, [c_void_p, POINTER(c_int32), c_int32, POINTER(c_int32)]),
     "cofem_apply_A_lowp": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cofem_get_kernel_timing": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(c_int64)]),
@@ -135,10 +139,31 @@ def cofem_init(problem: cofem_problem, params: cofem_params, stream=None):
     return ctx
 
 
-def cofem_em_step(ctx, n_iters: int):
-    stats = (cofem_iter_stats * max(n_iters, 1))()
+def cofem_em_step(ctx, n_iters: int, n_problems: int = 1):
+    """Per-iteration statistics: a list of n_iters dicts, or for a batched
+    context a list of n_iters lists of n_problems dicts."""
+    stats = (cofem_iter_stats * max(n_iters * n_problems, 1))()
     _check(load().cofem_em_step(ctx, n_iters, stats), ctx)
-    return [stats[i].as_dict() for i in range(n_iters)]
+    if n_problems == 1:
+        return [stats[i].as_dict() for i in range(n_iters)]
+    return [[stats[i * n_problems + j].as_dict() for j in range(n_problems)] for i in range(n_iters)]
+
+
+def cofem_init_batch(problems, params: cofem_params, stream=None):
+    arr = (cofem_problem * len(problems))(*problems)
+    ctx = c_void_p()
+    _check(load().cofem_init(arr, len(problems), ctypes.byref(params), _stream(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def cofem_batch_plan(ctx, n_problems: int):
+    target = c_int32(0)
+    ms = (ctypes.c_float * 4)()
+    s1 = (c_int32 * n_problems)()
+    s2 = (c_int32 * n_problems)()
+    _check(load().cofem_batch_plan(ctx, ctypes.byref(target), ms, s1, s2), ctx)
+    return {"target_wgs": target.value, "candidate_ms": [float(v) for v in ms],
+            "splits1": list(s1), "splits2": list(s2)}
 
 
 def cofem_posterior(ctx, mu=None, s=None, alpha=None, problem: int = 0):
@@ -338,4 +363,87 @@ class CoFEM:
         return self
 
     def __exit__(self, *exc):
+        self.close()
+
+
+class CoFEMBatch:
+    """Many independent dense problems solved together (the batched form):
+    bfloat16-rounded dictionaries, plain CG, grouped launches replayed from a
+    captured graph.  problems: list of (phi[N_i, D_i] float32 cuda, y[N_i]
+    float32 cuda); problem i uses probe seed `seed + i`."""
+
+    def __init__(self, problems, beta, K, tol=1e-5, max_iter=400, seed=0, alpha_max=1e10, eager=False,
+                 stream=None):
+        import torch
+        keep, probs = [], []
+        for phi, y in problems:
+            if phi.dtype != torch.float32 or y.dtype != torch.float32 or not phi.is_cuda or not y.is_cuda:
+                raise CofemError(COFEM_ERR_INVALID_ARG, "phi and y must be float32 GPU tensors")
+            phi, y = phi.contiguous(), y.contiguous()
+            keep += [phi, y]
+            N, D = phi.shape
+            probs.append(cofem_problem(kind=COFEM_DENSE, N=N, D=D, phi=phi.data_ptr(), ld_phi=D,
+                                       phi_dtype=COFEM_F32,
+                                       H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr()))
+        self.n = len(probs)
+        self.D = [int(p.D) for p in probs]
+        self.K = int(K)
+        self.device = problems[0][0].device
+        self._keep = keep
+        params = cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
+                              seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=COFEM_PREC_FP32,
+                              stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max),
+                              flags=COFEM_FLAG_BATCHED | (COFEM_FLAG_EAGER if eager else 0), poll_interval=0,
+                              ir_inner_tol=0.0,
+                              ir_max_sweeps=0)
+        with torch.cuda.device(self.device):
+            self.ctx = cofem_init_batch(probs, params, stream)
+
+    def em_step(self, n_iters=1):
+        return cofem_em_step(self.ctx, n_iters, self.n)
+
+    def posterior(self, i):
+        import torch
+        mu = torch.empty(self.D[i], dtype=torch.float32, device=self.device)
+        s = torch.empty_like(mu)
+        alpha = torch.empty_like(mu)
+        cofem_posterior(self.ctx, mu, s, alpha, problem=i)
+        torch.cuda.synchronize(self.device)
+        return mu, s, alpha
+
+    def set_alpha(self, i, alpha):
+        import torch
+        alpha = alpha.to(device=self.device, dtype=torch.float32).contiguous()
+        cofem_set_alpha(self.ctx, alpha, problem=i)
+        torch.cuda.synchronize(self.device)
+
+    def set_iteration(self, t):
+        cofem_set_iteration(self.ctx, t)
+
+    def solution(self, i):
+        import torch
+        X = torch.empty((self.K, self.D[i]), dtype=torch.float32, device=self.device)
+        m = torch.empty(self.D[i], dtype=torch.float64, device=self.device)
+        cofem_get_solution(self.ctx, X, m, problem=i)
+        torch.cuda.synchronize(self.device)
+        return X, m
+
+    def plan(self):
+        return cofem_batch_plan(self.ctx, self.n)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            cofem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
         self.close()

@@ -16,14 +16,40 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace cofem;
 
+// Host side of the batched form (n_problems > 1 or a bfloat16 dictionary):
+// per-problem descriptors and buffers, the grouped launches' work lists, and
+// the captured graph of a chunk of CG iterations.
+struct BatchHost {
+  int n = 0;
+  std::vector<cofem::BatchProblem> probs;  // device pointers, host copy
+  std::vector<cofem::DenseDims> dims;
+  cofem::BatchProblem* d_probs = nullptr;
+  cofem::BatchItem *d_items1 = nullptr, *d_items2 = nullptr, *d_itemsv = nullptr;
+  int n1 = 0, n2 = 0, nv = 0;
+  int32_t* d_running = nullptr;
+  int32_t* h_running = nullptr;    // pinned
+  cofem::CgScalars* h_st = nullptr;  // pinned, n entries
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool eager = false;
+  int chunk = 8;
+  int target = 0;                 // chosen workgroups per pass (autotuner)
+  float cand_ms[4] = {0.f, 0.f, 0.f, 0.f};
+  static constexpr int kCandidates[4] = {256, 512, 1024, 2048};
+  static constexpr int kSmax = 8;
+};
+
 struct cofem_ctx {
   int kind = COFEM_DENSE;
+  BatchHost* batch = nullptr;
   int64_t N = 0, D = 0;
   int K = 0, KP = 0;
   double beta = 1.0, tol = 1e-5, alpha_max = 1e10;
@@ -35,9 +61,10 @@ struct cofem_ctx {
   int prev_iters = 0;
   int precision = COFEM_PREC_FP32;
   bool true_resid = false;
+  int flags = 0;
   // mixed-precision form (COFEM_PREC_BF16_IR): inner tolerance, sweep cap,
   // bfloat16 copies of Phi, the accumulated solution and the last sweep counts
-  double tol_in = 1e-2;
+  double tol_in = 0.1;
   int max_sweeps = 20;
   uint16_t *phiA16 = nullptr, *phiB16 = nullptr;
   float* Xt = nullptr;
@@ -141,11 +168,20 @@ void destroy_ctx(cofem_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
+  if (BatchHost* b = c->batch) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->h_running) (void)hipHostFree(b->h_running);
+    if (b->h_st) (void)hipHostFree(b->h_st);
+    delete b;
+  }
   delete c;
 }
 
 // Writes the solver controls (cap, tolerance, sizes) into the device scalars.
 cofem_status push_controls(cofem_ctx* c) {
+  const int n = c->batch ? c->batch->n : 1;
   CgScalars h;
   memset(&h, 0, sizeof(h));
   h.tol = c->precision == COFEM_PREC_BF16_IR ? c->tol_in : c->tol;
@@ -154,7 +190,8 @@ cofem_status push_controls(cofem_ctx* c) {
   h.kp = c->KP;
   h.k = c->K;
   h.stop = 1;
-  COFEM_HIP(c, hipMemcpyAsync(c->st, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+  for (int i = 0; i < n; ++i)
+    COFEM_HIP(c, hipMemcpyAsync(c->st + i, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
   COFEM_HIP(c, hipStreamSynchronize(c->stream));
   return COFEM_OK;
 }
@@ -233,8 +270,8 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
 
   COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
   if (lowp)
-    COFEM_HIP(c, dense_pack16(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA16, c->phiB16, c->stream));
-  COFEM_HIP(c, dense_b0(static_cast<const float*>(p.phi), p.ld_phi, p.y, c->beta, dd, c->b0, c->stream));
+    COFEM_HIP(c, dense_pack16(p.phi, kDictF32ToBf16, p.ld_phi, dd, c->phiA16, c->phiB16, c->stream));
+  COFEM_HIP(c, dense_b0(p.phi, kDictF32, p.ld_phi, p.y, c->beta, dd, c->b0, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, dd.Dp, c->stream));
   return COFEM_OK;
 }
@@ -292,12 +329,261 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   return COFEM_OK;
 }
 
+// Work lists of the grouped launches for a total of about `target`
+// workgroups per pass, shared among the problems in proportion to their
+// dictionary size (the splits of each problem within its LDS staging bound).
+void batch_plan(BatchHost* b, int target, std::vector<BatchItem>* it1, std::vector<BatchItem>* it2,
+                std::vector<BatchItem>* itv) {
+  double work = 0.0;
+  for (const DenseDims& d : b->dims) work += (double)d.Np * (double)d.Dp;
+  auto splits = [&](int64_t pairs, int64_t groups, double share) {
+    int64_t s = (int64_t)ceil(target * share / (double)pairs);
+    int64_t most = groups / 64;  // at least eight 16-wide groups per wave
+    if (most > BatchHost::kSmax) most = BatchHost::kSmax;
+    if (s > most) s = most;
+    const int64_t least = (groups + 255) / 256;  // LDS staging bound of the mean operand
+    if (s < least) s = least;
+    return (int)(s < 1 ? 1 : s);
+  };
+  // largest problems first, so the long work items start early
+  std::vector<int> order(b->n);
+  for (int i = 0; i < b->n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) {
+    return (double)b->dims[x].Np * b->dims[x].Dp > (double)b->dims[y].Np * b->dims[y].Dp;
+  });
+  it1->clear();
+  it2->clear();
+  itv->clear();
+  for (int i : order) {
+    const DenseDims& d = b->dims[i];
+    BatchProblem& p = b->probs[i];
+    const double share = (double)d.Np * (double)d.Dp / work;
+    p.S1 = splits(d.Np / 64, d.Dp / 16, share);
+    p.S2 = splits(d.Dp / 64, d.Np / 16, share);
+    for (int a = 0; a < p.npairs1; ++a)
+      for (int sp = 0; sp < p.S1; ++sp) it1->push_back(BatchItem{i, a, sp, 0});
+    for (int a = 0; a < p.npairs2; ++a)
+      for (int sp = 0; sp < p.S2; ++sp) it2->push_back(BatchItem{i, a, sp, 0});
+    for (int a = 0; a < p.nvec; ++a) itv->push_back(BatchItem{i, a, 0, 0});
+  }
+}
+
+cofem_status batch_upload(cofem_ctx* c, const std::vector<BatchItem>& it1, const std::vector<BatchItem>& it2,
+                          const std::vector<BatchItem>& itv) {
+  BatchHost* b = c->batch;
+  COFEM_HIP(c, hipMemcpyAsync(b->d_probs, b->probs.data(), sizeof(BatchProblem) * b->n, hipMemcpyHostToDevice,
+                              c->stream));
+  COFEM_HIP(c, hipMemcpyAsync(b->d_items1, it1.data(), sizeof(BatchItem) * it1.size(), hipMemcpyHostToDevice,
+                              c->stream));
+  COFEM_HIP(c, hipMemcpyAsync(b->d_items2, it2.data(), sizeof(BatchItem) * it2.size(), hipMemcpyHostToDevice,
+                              c->stream));
+  COFEM_HIP(c, hipMemcpyAsync(b->d_itemsv, itv.data(), sizeof(BatchItem) * itv.size(), hipMemcpyHostToDevice,
+                              c->stream));
+  COFEM_HIP(c, hipStreamSynchronize(c->stream));
+  b->n1 = (int)it1.size();
+  b->n2 = (int)it2.size();
+  b->nv = (int)itv.size();
+  return COFEM_OK;
+}
+
+// One CG iteration of every problem: the two grouped operator passes and the
+// grouped update (blocks of stopped problems return at once).
+cofem_status batch_cg_iteration(cofem_ctx* c, hipStream_t s) {
+  BatchHost* b = c->batch;
+  COFEM_HIP(c, batch_pass1(b->d_items1, b->n1, b->d_probs, 0, s));
+  COFEM_HIP(c, batch_pass2(b->d_items2, b->n2, b->d_probs, c->beta, 0, s));
+  COFEM_HIP(c, batch_update(b->d_itemsv, b->nv, b->d_probs, s));
+  return COFEM_OK;
+}
+
+cofem_status init_batch(cofem_ctx* c, const cofem_problem* problems, int n) {
+  BatchHost* b = new (std::nothrow) BatchHost();
+  if (!b) return fail(c, COFEM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->batch = b;
+  b->n = n;
+  b->probs.resize(n);
+  b->dims.resize(n);
+  c->KP = kDenseKP;
+  b->eager = (c->flags & COFEM_FLAG_EAGER) != 0;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_running), sizeof(int32_t)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_st), sizeof(CgScalars) * n) != hipSuccess)
+    return fail(c, COFEM_ERR_DEVICE, "pinned allocation failed");
+  for (int i = 0; i < n; ++i) {
+    const cofem_problem& q = problems[i];
+    DenseDims& d = b->dims[i];
+    d.N = q.N;
+    d.D = q.D;
+    d.Np = round_up(q.N, 64);
+    d.Dp = round_up(q.D, 64);
+    d.S1 = d.S2 = 1;
+    d.S1h = d.S2h = 1;
+    d.ring = 4;
+    BatchProblem& p = b->probs[i];
+    memset(&p, 0, sizeof(p));
+    p.N = d.N;
+    p.D = d.D;
+    p.Np = d.Np;
+    p.Dp = d.Dp;
+    p.npairs1 = (int32_t)(d.Np / 64);
+    p.npairs2 = (int32_t)(d.Dp / 64);
+    p.nvec = dense_update_blocks(d);
+    p.seed = c->seed + (uint64_t)i;
+    const size_t blk = (size_t)d.Dp * kDenseKP;
+    uint16_t *a16 = nullptr, *b16 = nullptr;
+    double* b0 = nullptr;
+    COFEM_TRY(alloc(c, &a16, (size_t)d.Np * d.Dp));
+    COFEM_TRY(alloc(c, &b16, (size_t)d.Np * d.Dp));
+    COFEM_TRY(alloc(c, &b0, d.Dp));
+    p.phiA16 = a16;
+    p.phiB16 = b16;
+    p.b0 = b0;
+    COFEM_TRY(alloc(c, &p.alpha, d.Dp));
+    COFEM_TRY(alloc(c, &p.mu, d.Dp));
+    COFEM_TRY(alloc(c, &p.sdiag, d.Dp));
+    COFEM_TRY(alloc(c, &p.X, blk));
+    COFEM_TRY(alloc(c, &p.R, blk));
+    COFEM_TRY(alloc(c, &p.P, blk));
+    COFEM_TRY(alloc(c, &p.Q, blk));
+    COFEM_TRY(alloc(c, &p.W, (size_t)d.Np * kDenseKP));
+    COFEM_TRY(alloc(c, &p.xm, d.Dp));
+    COFEM_TRY(alloc(c, &p.rm, d.Dp));
+    COFEM_TRY(alloc(c, &p.pm, d.Dp));
+    COFEM_TRY(alloc(c, &p.qm, d.Dp));
+    COFEM_TRY(alloc(c, &p.wm, d.Np));
+    COFEM_TRY(alloc(c, &p.Wpart, (size_t)BatchHost::kSmax * d.Np * kDenseKP));
+    COFEM_TRY(alloc(c, &p.wmpart, (size_t)BatchHost::kSmax * d.Np));
+    COFEM_TRY(alloc(c, &p.Qpart, (size_t)BatchHost::kSmax * d.Dp * kDenseKP));
+    COFEM_TRY(alloc(c, &p.qmpart, (size_t)BatchHost::kSmax * d.Dp));
+    COFEM_TRY(alloc(c, &p.cnt_split1, (size_t)p.npairs1));
+    COFEM_TRY(alloc(c, &p.cnt_split2, (size_t)p.npairs2));
+    COFEM_TRY(alloc_tree(c, &p.parts_init, &p.cnts_init, p.nvec, kDenseKP + 1));
+    COFEM_TRY(alloc_tree(c, &p.parts_upd, &p.cnts_upd, p.nvec, kDenseKP + 1));
+    COFEM_TRY(alloc_tree(c, &p.parts_pass, &p.cnts_pass, p.npairs2, 3 * (kDenseKP + 1)));
+    p.st = c->st + i;
+    const int kind = q.phi_dtype == COFEM_BF16 ? kDictBf16 : kDictF32ToBf16;
+    COFEM_HIP(c, dense_pack16(q.phi, kind, q.ld_phi, d, a16, b16, c->stream));
+    COFEM_HIP(c, dense_b0(q.phi, kind, q.ld_phi, q.y, c->beta, d, b0, c->stream));
+    COFEM_HIP(c, fill_f32(p.alpha, 1.0f, d.Dp, c->stream));
+  }
+  COFEM_TRY(alloc(c, &b->d_probs, (size_t)n));
+  COFEM_TRY(alloc(c, &b->d_running, 1));
+  // work lists sized for the largest candidate
+  std::vector<BatchItem> it1, it2, itv;
+  size_t m1 = 0, m2 = 0;
+  for (int target : BatchHost::kCandidates) {
+    batch_plan(b, target, &it1, &it2, &itv);
+    m1 = std::max(m1, it1.size());
+    m2 = std::max(m2, it2.size());
+  }
+  COFEM_TRY(alloc(c, &b->d_items1, m1));
+  COFEM_TRY(alloc(c, &b->d_items2, m2));
+  COFEM_TRY(alloc(c, &b->d_itemsv, itv.size()));
+  COFEM_HIP(c, hipStreamSynchronize(c->stream));
+
+  // autotuner: time the grouped operator passes (apply only, on the zeroed
+  // state) for each candidate workgroup budget; keep the fastest
+  int forced = 0;
+  if (const char* e = getenv("COFEM_BATCH_TARGET")) forced = atoi(e);
+  float best = -1.f;
+  for (int k = 0; k < 4; ++k) {
+    const int target = BatchHost::kCandidates[k];
+    if (forced > 0 && target != forced) continue;
+    batch_plan(b, target, &it1, &it2, &itv);
+    COFEM_TRY(batch_upload(c, it1, it2, itv));
+    for (int w = 0; w < 2; ++w) {
+      COFEM_HIP(c, batch_pass1(b->d_items1, b->n1, b->d_probs, 1, c->stream));
+      COFEM_HIP(c, batch_pass2(b->d_items2, b->n2, b->d_probs, c->beta, 1, c->stream));
+    }
+    COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r) {
+      COFEM_HIP(c, batch_pass1(b->d_items1, b->n1, b->d_probs, 1, c->stream));
+      COFEM_HIP(c, batch_pass2(b->d_items2, b->n2, b->d_probs, c->beta, 1, c->stream));
+    }
+    COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+    COFEM_HIP(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    COFEM_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    b->cand_ms[k] = ms / reps;
+    if (best < 0.f || b->cand_ms[k] < best) {
+      best = b->cand_ms[k];
+      b->target = target;
+    }
+  }
+  if (b->target == 0) b->target = BatchHost::kCandidates[1];
+  batch_plan(b, b->target, &it1, &it2, &itv);
+  COFEM_TRY(batch_upload(c, it1, it2, itv));
+
+  // graph of one chunk of CG iterations plus the running-problem count
+  if (!b->eager) {
+    COFEM_HIP(c, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    COFEM_HIP(c, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    cofem_status st = COFEM_OK;
+    for (int i = 0; i < b->chunk && st == COFEM_OK; ++i) st = batch_cg_iteration(c, b->cap);
+    if (st == COFEM_OK && batch_running(b->d_probs, b->n, b->d_running, b->cap) != hipSuccess)
+      st = fail(c, COFEM_ERR_DEVICE, "graph capture: running-count launch failed");
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != COFEM_OK) return st;
+    if (e != hipSuccess) return fail(c, COFEM_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    COFEM_HIP(c, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  return COFEM_OK;
+}
+
+cofem_status em_iteration_batch(cofem_ctx* c, cofem_iter_stats* out) {
+  BatchHost* b = c->batch;
+  const int t = c->t_next;
+  COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  COFEM_HIP(c, batch_init(b->d_itemsv, b->nv, b->d_probs, t, c->K, c->stream));
+  const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
+  int enqueued = 0;
+  for (;;) {
+    if (b->exec) {
+      COFEM_HIP(c, hipGraphLaunch(b->exec, c->stream));
+    } else {
+      for (int i = 0; i < b->chunk; ++i) COFEM_TRY(batch_cg_iteration(c, c->stream));
+      COFEM_HIP(c, batch_running(b->d_probs, b->n, b->d_running, c->stream));
+    }
+    enqueued += b->chunk;
+    COFEM_HIP(c, hipMemcpyAsync(b->h_running, b->d_running, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    COFEM_HIP(c, hipStreamSynchronize(c->stream));
+    if (*b->h_running == 0) break;
+    if (enqueued > limit + b->chunk)
+      return fail(c, COFEM_ERR_DEVICE, "batched CG did not report completion after the iteration cap");
+  }
+  COFEM_HIP(c, batch_mstep(b->d_itemsv, b->nv, b->d_probs, t, c->K, c->alpha_max, c->stream));
+  COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  COFEM_HIP(c, hipMemcpyAsync(b->h_st, c->st, sizeof(CgScalars) * b->n, hipMemcpyDeviceToHost, c->stream));
+  COFEM_HIP(c, hipStreamSynchronize(c->stream));
+  float ms = 0.0f;
+  COFEM_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  for (int i = 0; i < b->n; ++i)
+    if (b->h_st[i].numeric_error)
+      return fail(c, COFEM_ERR_NUMERIC, "non-finite CG scalar in problem " + std::to_string(i) +
+                                            " at EM iteration " + std::to_string(t));
+  c->has_solution = true;
+  c->t_next = t + 1;
+  if (out) {
+    for (int i = 0; i < b->n; ++i) {
+      const CgScalars& h = b->h_st[i];
+      out[i].t = t;
+      out[i].cg_iters = h.iter;
+      out[i].converged = h.ratio < c->tol ? 1 : 0;
+      out[i].n_clamped = h.n_clamped;
+      out[i].rel_resid = h.ratio;
+      out[i].ms = ms;
+      out[i].rel_resid_true = -1.0;
+      out[i].ir_sweeps = 0;
+    }
+  }
+  return COFEM_OK;
+}
+
 cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, std::string* why) {
   if (!p || !q) return *why = "null problem or params", COFEM_ERR_INVALID_ARG;
-  if (n != 1) {
-    *why = "n_problems must be 1 in this build";
-    return n < 1 ? COFEM_ERR_INVALID_ARG : COFEM_ERR_UNSUPPORTED;
-  }
+  if (n < 1) return *why = "n_problems must be >= 1", COFEM_ERR_INVALID_ARG;
   if (!(q->beta > 0.0) || !isfinite(q->beta)) return *why = "beta must be positive and finite", COFEM_ERR_INVALID_ARG;
   if (q->K < 1 || q->K > COFEM_MAX_K) return *why = "K must be in [1, 32]", COFEM_ERR_INVALID_ARG;
   if (!(q->cg_tol >= 0.0) || !isfinite(q->cg_tol)) return *why = "cg_tol must be >= 0", COFEM_ERR_INVALID_ARG;
@@ -314,6 +600,24 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
     return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
   if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
+  if (n > 1 || p->phi_dtype == COFEM_BF16 || (q->flags & COFEM_FLAG_BATCHED)) {
+    // batched form: dense problems whose bfloat16 dictionary is the problem
+    if (q->precision != COFEM_PREC_FP32)
+      return *why = "the batched form runs plain CG (precision COFEM_PREC_FP32)", COFEM_ERR_UNSUPPORTED;
+    if (q->flags & COFEM_FLAG_TRUE_RESIDUAL)
+      return *why = "COFEM_FLAG_TRUE_RESIDUAL is not built for the batched form", COFEM_ERR_UNSUPPORTED;
+    for (int32_t i = 0; i < n; ++i) {
+      const cofem_problem& b = p[i];
+      if (b.kind != COFEM_DENSE) return *why = "the batched form takes dense problems", COFEM_ERR_UNSUPPORTED;
+      if (b.N < 1 || b.D < 1) return *why = "N and D must be >= 1", COFEM_ERR_INVALID_ARG;
+      if (!b.phi || !b.y) return *why = "phi or y is null", COFEM_ERR_INVALID_ARG;
+      if (b.ld_phi < b.D) return *why = "ld_phi < D", COFEM_ERR_INVALID_ARG;
+      if (b.phi_dtype != COFEM_F32 && b.phi_dtype != COFEM_BF16)
+        return *why = "phi_dtype must be COFEM_F32 or COFEM_BF16", COFEM_ERR_INVALID_ARG;
+      if (b.N > (int64_t)1 << 24 || b.D > (int64_t)1 << 24) return *why = "N or D too large", COFEM_ERR_INVALID_ARG;
+    }
+    return COFEM_OK;
+  }
   if (!p->y) return *why = "y is null", COFEM_ERR_INVALID_ARG;
   if (p->kind == COFEM_DENSE) {
     if (p->N < 1 || p->D < 1) return *why = "N and D must be >= 1", COFEM_ERR_INVALID_ARG;
@@ -540,6 +844,7 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
 }
 
 cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
+  if (c->batch) return em_iteration_batch(c, out);
   if (c->precision == COFEM_PREC_BF16_IR) return em_iteration_ir(c, out);
   const int t = c->t_next;
   COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
@@ -625,7 +930,8 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   c->poll = params->poll_interval > 0 ? params->poll_interval : 8;
   c->precision = params->precision;
   c->true_resid = (params->flags & COFEM_FLAG_TRUE_RESIDUAL) != 0;
-  c->tol_in = params->ir_inner_tol > 0.0 ? params->ir_inner_tol : 1e-2;
+  c->flags = params->flags;
+  c->tol_in = params->ir_inner_tol > 0.0 ? params->ir_inner_tol : 0.1;
   c->max_sweeps = params->ir_max_sweeps > 0 ? params->ir_max_sweeps : 20;
   c->stream = static_cast<hipStream_t>(hip_stream);
   cofem_status s = COFEM_OK;
@@ -636,8 +942,10 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   if (e != hipSuccess) {
     s = fail(c, COFEM_ERR_DEVICE, std::string("HIP set-up: ") + hipGetErrorString(e));
   }
-  if (s == COFEM_OK) s = alloc(c, &c->st, 1);
-  if (s == COFEM_OK) s = (p.kind == COFEM_DENSE) ? init_dense(c, p) : init_conv(c, p);
+  const bool batched = n_problems > 1 || p.phi_dtype == COFEM_BF16 || (params->flags & COFEM_FLAG_BATCHED);
+  if (s == COFEM_OK) s = alloc(c, &c->st, (size_t)n_problems);
+  if (s == COFEM_OK)
+    s = batched ? init_batch(c, problems, n_problems) : (p.kind == COFEM_DENSE) ? init_dense(c, p) : init_conv(c, p);
   if (s == COFEM_OK) s = push_controls(c);
   if (s == COFEM_OK) {
     e = hipStreamSynchronize(c->stream);
@@ -657,27 +965,40 @@ cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* st
   if (n_iters < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "n_iters < 0");
   for (int i = 0; i < n_iters; ++i) {
     if (ctx->t_next >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
-    COFEM_TRY(em_iteration(ctx, stats ? &stats[i] : nullptr));
+    const int np = ctx->batch ? ctx->batch->n : 1;
+    COFEM_TRY(em_iteration(ctx, stats ? &stats[(size_t)i * np] : nullptr));
   }
   return COFEM_OK;
 }
 
 cofem_status cofem_posterior(cofem_ctx* ctx, int32_t problem, float* mu, float* s, float* alpha) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
-  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
-  const size_t bytes = sizeof(float) * (size_t)ctx->D;
-  if (mu) COFEM_HIP(ctx, hipMemcpyAsync(mu, ctx->mu, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-  if (s) COFEM_HIP(ctx, hipMemcpyAsync(s, ctx->sdiag, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-  if (alpha) COFEM_HIP(ctx, hipMemcpyAsync(alpha, ctx->alpha, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  const int np = ctx->batch ? ctx->batch->n : 1;
+  if (problem < 0 || problem >= np) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  const float *pmu = ctx->mu, *ps = ctx->sdiag, *pa = ctx->alpha;
+  int64_t D = ctx->D;
+  if (ctx->batch) {
+    const BatchProblem& p = ctx->batch->probs[problem];
+    pmu = p.mu;
+    ps = p.sdiag;
+    pa = p.alpha;
+    D = p.D;
+  }
+  const size_t bytes = sizeof(float) * (size_t)D;
+  if (mu) COFEM_HIP(ctx, hipMemcpyAsync(mu, pmu, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (s) COFEM_HIP(ctx, hipMemcpyAsync(s, ps, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (alpha) COFEM_HIP(ctx, hipMemcpyAsync(alpha, pa, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   return COFEM_OK;
 }
 
 cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
-  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  const int np = ctx->batch ? ctx->batch->n : 1;
+  if (problem < 0 || problem >= np) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
   if (!alpha) return fail(ctx, COFEM_ERR_INVALID_ARG, "alpha is null");
-  COFEM_HIP(ctx, hipMemcpyAsync(ctx->alpha, alpha, sizeof(float) * (size_t)ctx->D, hipMemcpyDeviceToDevice,
-                                ctx->stream));
+  float* dst = ctx->batch ? ctx->batch->probs[problem].alpha : ctx->alpha;
+  const int64_t D = ctx->batch ? ctx->batch->probs[problem].D : ctx->D;
+  COFEM_HIP(ctx, hipMemcpyAsync(dst, alpha, sizeof(float) * (size_t)D, hipMemcpyDeviceToDevice, ctx->stream));
   return COFEM_OK;
 }
 
@@ -700,6 +1021,14 @@ cofem_status cofem_set_fixed_cg_iters(cofem_ctx* ctx, int32_t n) {
 
 cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, double* mean) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (ctx->batch) {
+    if (problem < 0 || problem >= ctx->batch->n) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+    const BatchProblem& p = ctx->batch->probs[problem];
+    if (probes) COFEM_HIP(ctx, dense_to_colmajor(ctx->batch->dims[problem], ctx->K, p.X, probes, ctx->stream));
+    if (mean)
+      COFEM_HIP(ctx, hipMemcpyAsync(mean, p.xm, sizeof(double) * (size_t)p.D, hipMemcpyDeviceToDevice, ctx->stream));
+    return COFEM_OK;
+  }
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
   const bool ir = ctx->precision == COFEM_PREC_BF16_IR;
   if (probes) {
@@ -720,6 +1049,7 @@ static cofem_status apply_A_impl(cofem_ctx* ctx, int32_t problem, const float* v
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
   if (!v_probes || !v_mean || !q_probes || !q_mean) return fail(ctx, COFEM_ERR_INVALID_ARG, "null vector");
+  if (ctx->batch) return fail(ctx, COFEM_ERR_UNSUPPORTED, "operator application is not built for the batched form");
   if (lowp && ctx->precision != COFEM_PREC_BF16_IR)
     return fail(ctx, COFEM_ERR_UNSUPPORTED, "the low-precision operator exists only under COFEM_PREC_BF16_IR");
   const size_t Dm = sizeof(double) * (size_t)ctx->D;
@@ -790,6 +1120,7 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
 cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (reps < 1 || !ms_out) return fail(ctx, COFEM_ERR_INVALID_ARG, "reps < 1 or ms_out null");
+  if (ctx->batch) return fail(ctx, COFEM_ERR_UNSUPPORTED, "use cofem_batch_plan for the batched form");
   // Each pass is launched `reps` times back to back between one pair of
   // events, as the CG loop issues them, so the average is the kernel's
   // duration plus the dispatch gap, not the latency of an isolated launch.
@@ -841,6 +1172,21 @@ cofem_status cofem_get_kernel_timing(cofem_ctx* ctx, double* ms_total, int64_t* 
   for (int i = 0; i < COFEM_KT_SLOTS; ++i) {
     ms_total[i] = ctx->kt_ms[i];
     launches[i] = ctx->kt_n[i];
+  }
+  return COFEM_OK;
+}
+
+cofem_status cofem_batch_plan(cofem_ctx* ctx, int32_t* target_wgs, float* candidate_ms, int32_t* splits1,
+                              int32_t* splits2) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (!ctx->batch) return fail(ctx, COFEM_ERR_UNSUPPORTED, "not a batched context");
+  const BatchHost* b = ctx->batch;
+  if (target_wgs) *target_wgs = b->target;
+  if (candidate_ms)
+    for (int k = 0; k < 4; ++k) candidate_ms[k] = b->cand_ms[k];
+  for (int i = 0; i < b->n; ++i) {
+    if (splits1) splits1[i] = b->probs[i].S1;
+    if (splits2) splits2[i] = b->probs[i].S2;
   }
   return COFEM_OK;
 }

@@ -44,6 +44,24 @@ struct CgScalars {
 };
 
 // ---------------------------------------------------------------- device helpers
+// float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Dictionary element i as stored by the caller: kind 0 float32, 1 float32 to
+// be rounded to bfloat16 (the bfloat16 value is the problem), 2 bfloat16 bits.
+enum { kDictF32 = 0, kDictF32ToBf16 = 1, kDictBf16 = 2 };
+__device__ __forceinline__ uint32_t dict_bf16_bits(const void* phi, int kind, int64_t i) {
+  if (kind == kDictBf16) return static_cast<const uint16_t*>(phi)[i];
+  return bf16_rne_bits(static_cast<const float*>(phi)[i]);
+}
+__device__ __forceinline__ float dict_value(const void* phi, int kind, int64_t i) {
+  if (kind == kDictF32) return static_cast<const float*>(phi)[i];
+  return __uint_as_float(dict_bf16_bits(phi, kind, i) << 16);
+}
+
 __device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -383,7 +401,7 @@ __host__ __device__ __forceinline__ int64_t blk4(int64_t d, int c) {
 
 hipError_t dense_pack(const float* phi, int64_t ld, const DenseDims& dd, float* phiA, float* phiB,
                       hipStream_t s);
-hipError_t dense_b0(const float* phi, int64_t ld, const float* y, double beta, const DenseDims& dd,
+hipError_t dense_b0(const void* phi, int dict_kind, int64_t ld, const float* y, double beta, const DenseDims& dd,
                     double* b0, hipStream_t s);
 hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
                       float* X, float* R, float* P, double* xm, double* rm, double* pm,
@@ -408,8 +426,8 @@ hipError_t dense_to_colmajor(const DenseDims& dd, int K, const float* Xb, float*
 hipError_t dense_from_colmajor(const DenseDims& dd, int K, const float* in, float* Xb, hipStream_t s);
 int dense_update_blocks(const DenseDims& dd);
 // bfloat16-dictionary passes of the mixed-precision form (kernels_dense_bf16.hip)
-hipError_t dense_pack16(const float* phi, int64_t ld, const DenseDims& dd, void* phiA16, void* phiB16,
-                        hipStream_t s);
+hipError_t dense_pack16(const void* phi, int dict_kind, int64_t ld, const DenseDims& dd, void* phiA16,
+                        void* phiB16, hipStream_t s);
 int dense16_split(int64_t pairs, int64_t groups);
 bool dense16_split_ok(int64_t groups, int splits);
 hipError_t dense16_pass1(const DenseDims& dd, const void* phiA16, const float* P, const double* pm,
@@ -470,5 +488,40 @@ hipError_t probe_signs_colmajor(uint64_t seed, int t, int K, int64_t D, float* o
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
 
 int conv_update_blocks(const ConvDims& cd);
+
+// ------------------------------------------------------------ batched form
+// Many independent dense problems (bfloat16 dictionaries, plain CG) advanced
+// together: every grouped launch covers all problems' blocks, each block
+// reading its (problem, a, b) work item and the problem's descriptor.
+struct BatchProblem {
+  int64_t N, D, Np, Dp;
+  int32_t S1, S2;          // reduction splits of pass 1 / pass 2
+  int32_t npairs1, npairs2;  // Np / 64, Dp / 64 (two tiles per workgroup)
+  int32_t nvec;            // blocks of the vector kernels (init, update, M-step)
+  int32_t pad;
+  uint64_t seed;           // probe seed of this problem
+  const void* phiA16;
+  const void* phiB16;
+  const double* b0;
+  float* alpha;
+  float *X, *R, *P, *Q, *W, *Wpart, *Qpart;
+  double *xm, *rm, *pm, *qm, *wm, *wmpart, *qmpart;
+  uint32_t *cnt_split1, *cnt_split2;
+  double *parts_init, *parts_upd, *parts_pass;
+  uint32_t *cnts_init, *cnts_upd, *cnts_pass;
+  float *mu, *sdiag;
+  CgScalars* st;
+};
+struct BatchItem {
+  int32_t prob, a, b, pad;  // pass kernels: a = tile pair, b = split; vector kernels: a = block
+};
+hipError_t batch_pass1(const BatchItem* items, int n, const BatchProblem* probs, int apply_only, hipStream_t s);
+hipError_t batch_pass2(const BatchItem* items, int n, const BatchProblem* probs, double beta, int apply_only,
+                       hipStream_t s);
+hipError_t batch_init(const BatchItem* items, int n, const BatchProblem* probs, int t, int K, hipStream_t s);
+hipError_t batch_update(const BatchItem* items, int n, const BatchProblem* probs, hipStream_t s);
+hipError_t batch_mstep(const BatchItem* items, int n, const BatchProblem* probs, int t, int K, double alpha_max,
+                       hipStream_t s);
+hipError_t batch_running(const BatchProblem* probs, int n, int32_t* out, hipStream_t s);
 
 }  // namespace cofem

@@ -76,19 +76,20 @@ hipError_t dense_pack(const float* phi, int64_t ld, const DenseDims& dd, float* 
 }
 
 // ------------------------------------------------- b0 = beta Phi^T y (Eq. 5)
-__global__ void k_dense_b0(const float* __restrict__ phi, int64_t ld, const float* __restrict__ y,
+// (the dictionary as the problem defines it: float32, or its bfloat16 rounding)
+__global__ void k_dense_b0(const void* __restrict__ phi, int kind, int64_t ld, const float* __restrict__ y,
                            double beta, int64_t N, int64_t D, int64_t Dp, double* __restrict__ b0) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= Dp) return;
   double acc = 0.0;
   if (d < D)
-    for (int64_t n = 0; n < N; ++n) acc = fma((double)phi[n * ld + d], (double)y[n], acc);
+    for (int64_t n = 0; n < N; ++n) acc = fma((double)dict_value(phi, kind, n * ld + d), (double)y[n], acc);
   b0[d] = beta * acc;
 }
 
-hipError_t dense_b0(const float* phi, int64_t ld, const float* y, double beta, const DenseDims& dd,
+hipError_t dense_b0(const void* phi, int kind, int64_t ld, const float* y, double beta, const DenseDims& dd,
                     double* b0, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_b0, dim3((unsigned)((dd.Dp + 255) / 256)), dim3(256), 0, s, phi, ld, y,
+  hipLaunchKernelGGL(k_dense_b0, dim3((unsigned)((dd.Dp + 255) / 256)), dim3(256), 0, s, phi, kind, ld, y,
                      beta, dd.N, dd.D, dd.Dp, b0);
   return hipGetLastError();
 }
@@ -99,7 +100,7 @@ int dense_update_blocks(const DenseDims& dd) {
 }
 
 // ------------------------------------------------ initial residual R = P = B (Eq. 7)
-__global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint64_t seed, int t,
+__device__ __forceinline__ void dense_init_body(int64_t blk, int64_t nblk, int64_t D, int64_t Dp, uint64_t seed, int t,
                                                     int K, const double* __restrict__ b0,
                                                     float* __restrict__ X, float* __restrict__ R,
                                                     float* __restrict__ P, double* __restrict__ xm,
@@ -107,8 +108,8 @@ __global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint6
                                                     double* __restrict__ pm,
                                                     double* __restrict__ parts, uint32_t* cnts,
                                                     CgScalars* st) {
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
   double acc = 0.0;
   for (int64_t e4 = gtid; e4 < Dp * 8; e4 += gstride) {
@@ -134,8 +135,19 @@ __global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint6
   }
   __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
   dense_block_sums(acc, accm, mine);
-  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, kDenseKP + 1, mine, tot)) return;
+  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + 1, mine, tot)) return;
   finish_init(st, tot);
+}
+
+__global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint64_t seed, int t,
+                                                    int K, const double* __restrict__ b0,
+                                                    float* __restrict__ X, float* __restrict__ R,
+                                                    float* __restrict__ P, double* __restrict__ xm,
+                                                    double* __restrict__ rm,
+                                                    double* __restrict__ pm,
+                                                    double* __restrict__ parts, uint32_t* cnts,
+                                                    CgScalars* st) {
+  dense_init_body(blockIdx.x, gridDim.x, D, Dp, seed, t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st);
 }
 
 hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
@@ -515,7 +527,7 @@ bool dense_split_ok(int64_t groups, int splits) {
 
 // ------------------------------------------------ CG update
 // x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2 and the stop test.
-__global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restrict__ X,
+__device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int64_t Dp, float* __restrict__ X,
                                                       float* __restrict__ R, float* __restrict__ P,
                                                       const float* __restrict__ Q,
                                                       double* __restrict__ xm,
@@ -525,8 +537,8 @@ __global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restr
                                                       double* __restrict__ parts, uint32_t* cnts,
                                                       CgScalars* st) {
   if (st->stop) return;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
   const float a = (float)st->a[c], b = (float)st->b[c];
   const double am = st->a[kDenseKP], bmm = st->b[kDenseKP];
@@ -564,8 +576,20 @@ __global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restr
   }
   __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
   dense_block_sums(acc, accm, mine);
-  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, kDenseKP + 1, mine, tot)) return;
+  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + 1, mine, tot)) return;
   finish_update(st, tot);
+}
+
+__global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restrict__ X,
+                                                      float* __restrict__ R, float* __restrict__ P,
+                                                      const float* __restrict__ Q,
+                                                      double* __restrict__ xm,
+                                                      double* __restrict__ rm,
+                                                      double* __restrict__ pm,
+                                                      const double* __restrict__ qm,
+                                                      double* __restrict__ parts, uint32_t* cnts,
+                                                      CgScalars* st) {
+  dense_update_body(blockIdx.x, gridDim.x, Dp, X, R, P, Q, xm, rm, pm, qm, parts, cnts, st);
 }
 
 hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
@@ -622,14 +646,14 @@ hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, co
 }
 
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
-__global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, int t, int K,
+__device__ __forceinline__ void dense_mstep_body(int64_t blk, int64_t nblk, int64_t D, uint64_t seed, int t, int K,
                                                      const float* __restrict__ X,
                                                      const double* __restrict__ xm,
                                                      float* __restrict__ alpha, double alpha_max,
                                                      float* __restrict__ mu,
                                                      float* __restrict__ sdiag, CgScalars* st) {
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)nblk * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
   double clamped = 0.0;
   for (int64_t d = gtid; d < D; d += gstride) {
@@ -647,6 +671,15 @@ __global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, i
   __shared__ double shm[8];
   const double tot = block_sum(clamped, shm);
   if (threadIdx.x == 0 && tot > 0.0) atomicAdd(&st->n_clamped, (int)tot);
+}
+
+__global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, int t, int K,
+                                                     const float* __restrict__ X,
+                                                     const double* __restrict__ xm,
+                                                     float* __restrict__ alpha, double alpha_max,
+                                                     float* __restrict__ mu,
+                                                     float* __restrict__ sdiag, CgScalars* st) {
+  dense_mstep_body(blockIdx.x, gridDim.x, D, seed, t, K, X, xm, alpha, alpha_max, mu, sdiag, st);
 }
 
 hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,
@@ -688,6 +721,66 @@ hipError_t dense_from_colmajor(const DenseDims& dd, int K, const float* in, floa
   const int64_t tot = dd.Dp * kDenseKP;
   hipLaunchKernelGGL(k_col_to_blk4, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, dd.D, dd.Dp,
                      K, in, Xb);
+  return hipGetLastError();
+}
+
+}  // namespace cofem
+
+namespace cofem {
+
+// ------------------------------------------------ batched form: grouped vector kernels
+// Work item a = block index within the problem (p.nvec blocks per problem).
+__global__ __launch_bounds__(256) void k_batch_init(const BatchItem* __restrict__ items,
+                                                    const BatchProblem* __restrict__ probs, int t, int K) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProblem& p = probs[it.prob];
+  dense_init_body(it.a, p.nvec, p.D, p.Dp, p.seed, t, K, p.b0, p.X, p.R, p.P, p.xm, p.rm, p.pm, p.parts_init,
+                  p.cnts_init, p.st);
+}
+
+__global__ __launch_bounds__(256) void k_batch_update(const BatchItem* __restrict__ items,
+                                                      const BatchProblem* __restrict__ probs) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProblem& p = probs[it.prob];
+  dense_update_body(it.a, p.nvec, p.Dp, p.X, p.R, p.P, p.Q, p.xm, p.rm, p.pm, p.qm, p.parts_upd, p.cnts_upd, p.st);
+}
+
+__global__ __launch_bounds__(256) void k_batch_mstep(const BatchItem* __restrict__ items,
+                                                     const BatchProblem* __restrict__ probs, int t, int K,
+                                                     double alpha_max) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProblem& p = probs[it.prob];
+  dense_mstep_body(it.a, p.nvec, p.D, p.seed, t, K, p.X, p.xm, p.alpha, alpha_max, p.mu, p.sdiag, p.st);
+}
+
+// Number of problems whose solve has not stopped (one block).
+__global__ __launch_bounds__(256) void k_batch_running(const BatchProblem* __restrict__ probs, int n,
+                                                       int32_t* __restrict__ out) {
+  __shared__ double shm[8];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += probs[i].st->stop ? 0.0 : 1.0;
+  const double tot = block_sum(v, shm);
+  if (threadIdx.x == 0) out[0] = (int32_t)tot;
+}
+
+hipError_t batch_init(const BatchItem* items, int n, const BatchProblem* probs, int t, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init, dim3((unsigned)n), dim3(256), 0, s, items, probs, t, K);
+  return hipGetLastError();
+}
+
+hipError_t batch_update(const BatchItem* items, int n, const BatchProblem* probs, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_update, dim3((unsigned)n), dim3(256), 0, s, items, probs);
+  return hipGetLastError();
+}
+
+hipError_t batch_mstep(const BatchItem* items, int n, const BatchProblem* probs, int t, int K, double alpha_max,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_mstep, dim3((unsigned)n), dim3(256), 0, s, items, probs, t, K, alpha_max);
+  return hipGetLastError();
+}
+
+hipError_t batch_running(const BatchProblem* probs, int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_running, dim3(1), dim3(256), 0, s, probs, n, out);
   return hipGetLastError();
 }
 

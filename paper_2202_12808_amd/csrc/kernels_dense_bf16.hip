@@ -26,12 +26,6 @@ namespace cofem {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-
 __device__ __forceinline__ float bf16_lo_as_float(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi_as_float(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
@@ -39,7 +33,7 @@ __device__ __forceinline__ float bf16_hi_as_float(uint32_t w) { return __uint_as
 // phiA16 chunk (t, g), t = 32-row tile, g = 16-column group, at (t * G + g) * 64
 // (uint4 units): lane l holds bf16(Phi[32 t + l%32][16 g + 8 (l/32) + s]),
 // s = 0..7, element s in the low (s even) or high half of word s/2.
-__global__ void k_pack_a16(const float* __restrict__ phi, int64_t ld, int64_t N, int64_t D, int64_t G,
+__global__ void k_pack_a16(const void* __restrict__ phi, int kind, int64_t ld, int64_t N, int64_t D, int64_t G,
                            int64_t tiles, uint4* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tiles * G * 64) return;
@@ -52,8 +46,8 @@ __global__ void k_pack_a16(const float* __restrict__ phi, int64_t ld, int64_t N,
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t d = d0 + 2 * q;
-    const uint32_t lo = (n < N && d < D) ? bf16_rne_bits(phi[n * ld + d]) : 0u;
-    const uint32_t hi = (n < N && d + 1 < D) ? bf16_rne_bits(phi[n * ld + d + 1]) : 0u;
+    const uint32_t lo = (n < N && d < D) ? dict_bf16_bits(phi, kind, n * ld + d) : 0u;
+    const uint32_t hi = (n < N && d + 1 < D) ? dict_bf16_bits(phi, kind, n * ld + d + 1) : 0u;
     w[q] = lo | (hi << 16);
   }
   out[idx] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -61,7 +55,7 @@ __global__ void k_pack_a16(const float* __restrict__ phi, int64_t ld, int64_t N,
 
 // phiB16 chunk (t, g), t = 32-coordinate tile, g = 16-row group:
 // lane l holds bf16(Phi[16 g + 8 (l/32) + s][32 t + l%32]), s = 0..7.
-__global__ void k_pack_b16(const float* __restrict__ phi, int64_t ld, int64_t N, int64_t D, int64_t G2,
+__global__ void k_pack_b16(const void* __restrict__ phi, int kind, int64_t ld, int64_t N, int64_t D, int64_t G2,
                            int64_t tiles, uint4* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tiles * G2 * 64) return;
@@ -74,22 +68,22 @@ __global__ void k_pack_b16(const float* __restrict__ phi, int64_t ld, int64_t N,
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t n = n0 + 2 * q;
-    const uint32_t lo = (n < N && d < D) ? bf16_rne_bits(phi[n * ld + d]) : 0u;
-    const uint32_t hi = (n + 1 < N && d < D) ? bf16_rne_bits(phi[(n + 1) * ld + d]) : 0u;
+    const uint32_t lo = (n < N && d < D) ? dict_bf16_bits(phi, kind, n * ld + d) : 0u;
+    const uint32_t hi = (n + 1 < N && d < D) ? dict_bf16_bits(phi, kind, (n + 1) * ld + d) : 0u;
     w[q] = lo | (hi << 16);
   }
   out[idx] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-hipError_t dense_pack16(const float* phi, int64_t ld, const DenseDims& dd, void* phiA16, void* phiB16,
+hipError_t dense_pack16(const void* phi, int kind, int64_t ld, const DenseDims& dd, void* phiA16, void* phiB16,
                         hipStream_t s) {
   const int64_t G = dd.Dp / 16, tilesA = dd.Np / 32;
   const int64_t totA = tilesA * G * 64;
-  hipLaunchKernelGGL(k_pack_a16, dim3((unsigned)((totA + 255) / 256)), dim3(256), 0, s, phi, ld, dd.N, dd.D,
+  hipLaunchKernelGGL(k_pack_a16, dim3((unsigned)((totA + 255) / 256)), dim3(256), 0, s, phi, kind, ld, dd.N, dd.D,
                      G, tilesA, static_cast<uint4*>(phiA16));
   const int64_t G2 = dd.Np / 16, tilesB = dd.Dp / 32;
   const int64_t totB = tilesB * G2 * 64;
-  hipLaunchKernelGGL(k_pack_b16, dim3((unsigned)((totB + 255) / 256)), dim3(256), 0, s, phi, ld, dd.N, dd.D,
+  hipLaunchKernelGGL(k_pack_b16, dim3((unsigned)((totB + 255) / 256)), dim3(256), 0, s, phi, kind, ld, dd.N, dd.D,
                      G2, tilesB, static_cast<uint4*>(phiB16));
   return hipGetLastError();
 }
@@ -305,14 +299,13 @@ constexpr int kG16Waves = 8;
 
 // ------------------------------------------------ inner pass 1: W = Phi~ P
 template <int RING>
-__global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass1(
-    const uint4* __restrict__ phiA, int64_t G, int64_t gps, int nsplit, int64_t Np,
+__device__ __forceinline__ void dense16_pass1_body(
+    int64_t pair, int split, const uint4* __restrict__ phiA, int64_t G, int64_t gps, int nsplit, int64_t Np,
     const float* __restrict__ P, const double* __restrict__ pm, float* __restrict__ Wpart,
     double* __restrict__ wmpart, float* __restrict__ W, double* __restrict__ wm,
     uint32_t* __restrict__ cnts, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
-  const int64_t pair = blockIdx.x;  // tiles 2 pair, 2 pair + 1
-  const int split = blockIdx.y;
+  // tiles 2 pair and 2 pair + 1, reduction split `split` of `nsplit`
   const int64_t g0 = split * gps;
   const int64_t g1 = (g0 + gps < G) ? g0 + gps : G;
   floatx16 acc[2];
@@ -331,19 +324,27 @@ __global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass1(
   if (ee < 32) wm[row0 + 32 * tt + ee] = vm;
 }
 
+template <int RING>
+__global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass1(
+    const uint4* __restrict__ phiA, int64_t G, int64_t gps, int nsplit, int64_t Np,
+    const float* __restrict__ P, const double* __restrict__ pm, float* __restrict__ Wpart,
+    double* __restrict__ wmpart, float* __restrict__ W, double* __restrict__ wm,
+    uint32_t* __restrict__ cnts, CgScalars* __restrict__ st, int apply_only) {
+  dense16_pass1_body<RING>(blockIdx.x, blockIdx.y, phiA, G, gps, nsplit, Np, P, pm, Wpart, wmpart, W, wm, cnts,
+                           st, apply_only);
+}
+
 // ------------------------------------------------ inner pass 2: Q = beta Phi~^T W + alpha P, dots
 template <int RING>
-__global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass2(
-    const uint4* __restrict__ phiB, int64_t G2, int64_t gps, int nsplit, int64_t Dp,
-    const float* __restrict__ W, const double* __restrict__ wm, const float* __restrict__ P,
+__device__ __forceinline__ void dense16_pass2_body(
+    int64_t pair, int split, int64_t npairs, const uint4* __restrict__ phiB, int64_t G2, int64_t gps, int nsplit,
+    int64_t Dp, const float* __restrict__ W, const double* __restrict__ wm, const float* __restrict__ P,
     const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
     const float* __restrict__ alpha, double beta, float* __restrict__ Qpart, double* __restrict__ qmpart,
     float* __restrict__ Q, double* __restrict__ qm, double* __restrict__ parts, uint32_t* __restrict__ cnts,
     uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
   constexpr int nc = kDenseKP + 1;
-  const int64_t pair = blockIdx.x;
-  const int split = blockIdx.y;
   const int64_t g0 = split * gps;
   const int64_t g1 = (g0 + gps < G2) ? g0 + gps : G2;
   floatx16 acc[2];
@@ -408,8 +409,20 @@ __global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass2(
     mine[kind * nc + kDenseKP] = sacc;
   }
   __syncthreads();
-  if (!tree_reduce(parts, cnts, pair, gridDim.x, 3 * nc, mine, tot)) return;
+  if (!tree_reduce(parts, cnts, pair, npairs, 3 * nc, mine, tot)) return;
   finish_step(st, tot);
+}
+
+template <int RING>
+__global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass2(
+    const uint4* __restrict__ phiB, int64_t G2, int64_t gps, int nsplit, int64_t Dp,
+    const float* __restrict__ W, const double* __restrict__ wm, const float* __restrict__ P,
+    const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
+    const float* __restrict__ alpha, double beta, float* __restrict__ Qpart, double* __restrict__ qmpart,
+    float* __restrict__ Q, double* __restrict__ qm, double* __restrict__ parts, uint32_t* __restrict__ cnts,
+    uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only) {
+  dense16_pass2_body<RING>(blockIdx.x, blockIdx.y, gridDim.x, phiB, G2, gps, nsplit, Dp, W, wm, P, pm, R, rm, alpha,
+                           beta, Qpart, qmpart, Q, qm, parts, cnts, split_cnts, st, apply_only);
 }
 
 // Splits of a low-precision pass: ~256 workgroups of two tiles each (one
@@ -531,6 +544,50 @@ hipError_t dense_ir_residual(const DenseDims& dd, uint64_t seed, int t, int K, c
                              double* parts, uint32_t* cnts, CgScalars* st, int limit, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_ir_residual, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed, t, K,
                      b0, Q, qm, Xi, R, P, xim, rm, pm, parts, cnts, st, limit);
+  return hipGetLastError();
+}
+
+}  // namespace cofem
+
+namespace cofem {
+
+// ------------------------------------------------ batched form: grouped passes
+// One launch covers every problem's (tile pair, split) work items; a block
+// reads its item and its problem's descriptor and runs the single-problem
+// pass body on them (the problem's own stop flag, counters and tree).
+__global__ __launch_bounds__(64 * kG16Waves) void k_batch_pass1(const BatchItem* __restrict__ items,
+                                                                const BatchProblem* __restrict__ probs,
+                                                                int apply_only) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProblem& p = probs[it.prob];
+  const int64_t G = p.Dp / 16;
+  const int64_t gps = (G + p.S1 - 1) / p.S1;
+  dense16_pass1_body<4>(it.a, it.b, static_cast<const uint4*>(p.phiA16), G, gps, p.S1, p.Np, p.P, p.pm, p.Wpart,
+                        p.wmpart, p.W, p.wm, p.cnt_split1, p.st, apply_only);
+}
+
+__global__ __launch_bounds__(64 * kG16Waves) void k_batch_pass2(const BatchItem* __restrict__ items,
+                                                                const BatchProblem* __restrict__ probs, double beta,
+                                                                int apply_only) {
+  const BatchItem it = items[blockIdx.x];
+  const BatchProblem& p = probs[it.prob];
+  const int64_t G2 = p.Np / 16;
+  const int64_t gps = (G2 + p.S2 - 1) / p.S2;
+  dense16_pass2_body<4>(it.a, it.b, p.npairs2, static_cast<const uint4*>(p.phiB16), G2, gps, p.S2, p.Dp, p.W, p.wm,
+                        p.P, p.pm, p.R, p.rm, p.alpha, beta, p.Qpart, p.qmpart, p.Q, p.qm, p.parts_pass, p.cnts_pass,
+                        p.cnt_split2, p.st, apply_only);
+}
+
+hipError_t batch_pass1(const BatchItem* items, int n, const BatchProblem* probs, int apply_only, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_pass1, dim3((unsigned)n), dim3(64 * kG16Waves), 0, s, items, probs, apply_only);
+  return hipGetLastError();
+}
+
+hipError_t batch_pass2(const BatchItem* items, int n, const BatchProblem* probs, double beta, int apply_only,
+                       hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_pass2, dim3((unsigned)n), dim3(64 * kG16Waves), 0, s, items, probs, beta, apply_only);
   return hipGetLastError();
 }
 

@@ -508,3 +508,83 @@ def test_runs_are_bit_reproducible(torch_dev, kind):
     assert outs[0][0] == outs[1][0]
     for a, b in zip(outs[0][1], outs[1][1]):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ batched form
+def _batch_problems(sizes, seed=0):
+    # the batched workload's recipe at small sizes: N_i = D_i / 4, 2% nonzeros,
+    # beta 1e3, K 16, eps 1e-5; the bfloat16 rounding of Phi_i is the problem
+    return [synth.dense_problem(D // 4, D, rho=0.02, beta=1e3, K=16, tol=1e-5, max_iter=400, seed=seed * 1000 + i,
+                                name=f"batch_{i}")
+            for i, D in enumerate(sizes)]
+
+
+def _batch_ctx(torch, probs, **kw):
+    from paper_2202_12808_amd.cofem import CoFEMBatch
+    p0 = probs[0]
+    return CoFEMBatch([(torch.from_numpy(p.phi).cuda(), torch.from_numpy(p.y).cuda()) for p in probs],
+                      p0.beta, p0.K, tol=p0.tol, max_iter=p0.max_iter, seed=7, **kw)
+
+
+@pytest.mark.parametrize("t_free", [0, 3])
+def test_batch_step_parity_per_problem(torch_dev, t_free):
+    # every problem of a ragged batch against the oracle on its own bf16(Phi_i),
+    # probes seeded 7 + i, teacher-forced alpha, oracle at the GPU's CG count
+    torch = torch_dev
+    sizes = [256, 1000, 512, 1536, 300 * 4]
+    probs = _batch_problems(sizes)
+    _say("batch step parity sizes", sizes, "t_free", t_free)
+    with _batch_ctx(torch, probs) as g:
+        if t_free:
+            g.em_step(t_free)
+        alphas = [g.posterior(i)[2].cpu().numpy().astype(np.float64) for i in range(len(probs))]
+        stats = g.em_step(1)[0]
+        post = [[x.cpu().numpy().astype(np.float64) for x in g.posterior(i)] for i in range(len(probs))]
+        plan = g.plan()
+    _say("plan", plan)
+    assert plan["target_wgs"] in (256, 512, 1024, 2048)
+    for i, p in enumerate(probs):
+        op = O.DenseOperator(synth.round_to_bf16(p.phi).astype(np.float64))
+        b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+        st = stats[i]
+        e = O.cofem_estep(op, b0, p.beta, alphas[i], p.K, p.tol, p.max_iter, 7 + i, st["t"],
+                          fixed_iters=st["cg_iters"])
+        a_ref, _ = O.mstep(e.mu, e.s)
+        mu, s, a = post[i]
+        errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / a, 1.0 / a_ref))
+        _say("problem", i, "D", p.D, "cg", st["cg_iters"], "relerr", errs)
+        assert st["converged"] == 1 or st["cg_iters"] == p.max_iter
+        assert all(err < STEP_TOL for err in errs), (i, errs)
+
+
+def test_batch_graph_replays_equal_eager_launches(torch_dev):
+    # the captured graph (replayed many times per E-step, with eager init and
+    # M-step kernels and host synchronisations between replays) gives the
+    # same bits as launching the same kernels directly
+    torch = torch_dev
+    probs = _batch_problems([512, 768, 1024], seed=2)
+    outs = []
+    for eager in (False, True):
+        with _batch_ctx(torch, probs, eager=eager) as g:
+            st = g.em_step(4)
+            outs.append(([x["cg_iters"] for it in st for x in it],
+                         [[x.cpu().numpy() for x in g.posterior(i)] for i in range(len(probs))]))
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1], outs[1][1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_batch_of_one_matches_batch_member(torch_dev):
+    # a problem solved alone in the batched form equals the same problem
+    # inside a larger batch (same seed index 0): grouping changes nothing
+    torch = torch_dev
+    probs = _batch_problems([640, 1024], seed=3)
+    with _batch_ctx(torch, probs[:1]) as g1:
+        g1.em_step(2)
+        solo = [x.cpu().numpy() for x in g1.posterior(0)]
+    with _batch_ctx(torch, probs) as g2:
+        g2.em_step(2)
+        both = [x.cpu().numpy() for x in g2.posterior(0)]
+    for x, y in zip(solo, both):
+        assert np.array_equal(x, y)
