@@ -250,6 +250,7 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
  * issues it).  Writes the mean per-launch time in milliseconds, dispatch gaps
  * included, of each kernel to ms_out (host, 3 entries):
  * dense -> {pass 1 (W = Phi P), pass 2 (Q = beta Phi^T W + alpha P), 0};
+ * batched -> {grouped pass 1, grouped pass 2 over all problems, 0};
  * conv  -> {fused stencil pass, 0, 0}.  Leaves the solver state unchanged.
  */
 cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out);

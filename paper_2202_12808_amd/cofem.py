@@ -431,6 +431,9 @@ class CoFEMBatch:
     def plan(self):
         return cofem_batch_plan(self.ctx, self.n)
 
+    def time_operator(self, reps=10):
+        return cofem_time_operator(self.ctx, reps)
+
     def close(self):
         if getattr(self, "ctx", None):
             cofem_destroy(self.ctx)

@@ -1120,7 +1120,26 @@ cofem_status cofem_probe_signs(uint64_t seed, int32_t t, int32_t K, int64_t D, f
 cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (reps < 1 || !ms_out) return fail(ctx, COFEM_ERR_INVALID_ARG, "reps < 1 or ms_out null");
-  if (ctx->batch) return fail(ctx, COFEM_ERR_UNSUPPORTED, "use cofem_batch_plan for the batched form");
+  if (BatchHost* b = ctx->batch) {
+    // grouped passes over every problem, apply only, back to back
+    float ms[2] = {0.f, 0.f};
+    for (int k = 0; k < 2; ++k) {
+      auto launch = [&]() {
+        return k == 0 ? batch_pass1(b->d_items1, b->n1, b->d_probs, 1, ctx->stream)
+                      : batch_pass2(b->d_items2, b->n2, b->d_probs, ctx->beta, 1, ctx->stream);
+      };
+      COFEM_HIP(ctx, launch());
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+      for (int r = 0; r < reps; ++r) COFEM_HIP(ctx, launch());
+      COFEM_HIP(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+      COFEM_HIP(ctx, hipEventSynchronize(ctx->ev1));
+      COFEM_HIP(ctx, hipEventElapsedTime(&ms[k], ctx->ev0, ctx->ev1));
+    }
+    ms_out[0] = ms[0] / (float)reps;
+    ms_out[1] = ms[1] / (float)reps;
+    ms_out[2] = 0.f;
+    return COFEM_OK;
+  }
   // Each pass is launched `reps` times back to back between one pair of
   // events, as the CG loop issues them, so the average is the kernel's
   // duration plus the dispatch gap, not the latency of an isolated launch.
