@@ -6,6 +6,14 @@ Algorithm 1 from alpha = 1 (E-step by multi-right-hand-side CG, diagonal
 estimate, M-step), on inputs already resident in HBM.  The reported value is
 EM iterations per second over the timed steps.
 
+Forms (dense workloads): the headline is the mixed-precision form (bf16
+dictionary in the inner CG solves, iterative refinement on the float32
+dictionary's true residual); the plain float32 CG form is timed on the same
+inputs and reported under "forms", with the NMSE between the two final mu.
+`--oracle-trajectory` also runs the float64 oracle over the whole trajectory
+(at the workload's tolerance and at 1/1000 of it) and reports each form's
+NMSE against both.  `--workload batched_64` runs the 64-problem batched form.
+
 Besides the throughput line the JSON carries:
   roofline      the dominant operator kernel's achieved HBM bandwidth
                 (algorithmic bytes per launch / mean launch time, from HIP
@@ -226,8 +234,9 @@ def main():
                     help="time the steps without the per-launch events (roofline from cofem_time_operator)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="first run 3 plain device copies of this many MiB (counter calibration)")
-    ap.add_argument("--form", default="fp32", choices=sorted(FORMS),
-                    help="solver form timed for the headline value (bf16_ir: dense only)")
+    ap.add_argument("--form", default=None, choices=sorted(FORMS),
+                    help="solver form timed for the headline value (default: bf16_ir for dense workloads, "
+                         "fp32 for conv)")
     ap.add_argument("--ir-inner-tol", type=float, default=0.0,
                     help="bf16_ir: relative tolerance of each inner solve (0: the library default, 0.1)")
     ap.add_argument("--oracle-trajectory", action="store_true",
@@ -261,6 +270,8 @@ def main():
     log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} beta={p.beta} tol={p.tol} U={p.max_iter} "
         f"T_em={T_em} (inputs generated in {time.perf_counter() - t_gen:.1f}s)")
 
+    if args.form is None:
+        args.form = "bf16_ir" if p.kind == "dense" else "fp32"
     if args.form != "fp32" and p.kind != "dense":
         print("--form bf16_ir is built for dense dictionaries only", file=sys.stderr, flush=True)
         sys.exit(2)
