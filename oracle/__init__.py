@@ -13,6 +13,7 @@ from .cofem_oracle import (  # noqa: F401
     cofem,
     cofem_estep,
     cofem_estep_ir,
+    cofem_estep_pcg,
     diag_estimate,
     diag_estimate_ratio,
     exact_estep,
@@ -21,6 +22,7 @@ from .cofem_oracle import (  # noqa: F401
     loglik,
     loglik_direct,
     mstep,
+    pcg_solve,
     rademacher_probes,
     splitmix64_mix,
     splitmix64_stream,

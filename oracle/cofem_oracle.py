@@ -236,6 +236,50 @@ def cg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int,
     return X, CGInfo(it, ratio < tol, ratio, hist)
 
 
+def pcg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int, minv: Optional[np.ndarray] = None,
+              X0: Optional[np.ndarray] = None, fixed_iters: Optional[int] = None):
+    """Preconditioned CG from a starting block (not in the paper: the learned
+    and warm-started forms).  M^-1 = diag(minv) (a length-D positive vector,
+    the same for every column; None is the identity), X0 the starting block
+    (None is zero).  Column c: r = b - A x0, z = M^-1 r, p = z,
+    rho = r^T z; per step a = rho / (p^T A p), x += a p, r -= a q,
+    z = M^-1 r, rho' = r^T z, p = z + (rho'/rho) p.  The stop test is the
+    solve's own (Sec. 3.2): sqrt(sum_c ||r_c||^2) / ||B||_F < tol on the
+    recursively updated (unpreconditioned) residual, checked before every
+    iteration, or the cap."""
+    B = np.asarray(B, dtype=np.float64)
+    X = np.zeros_like(B) if X0 is None else np.asarray(X0, dtype=np.float64).copy()
+    m = np.ones(B.shape[0]) if minv is None else np.asarray(minv, dtype=np.float64)
+    R = B - apply_A(X) if X0 is not None else B.copy()
+    Z = m[:, None] * R
+    P = Z.copy()
+    rho = np.einsum("dc,dc->c", R, Z)
+    nB = float(np.linalg.norm(B))
+    hist = []
+    if nB == 0.0:
+        return X, CGInfo(0, True, 0.0, hist)
+    limit = fixed_iters if fixed_iters is not None else max_iter
+    it = 0
+    while it < limit:
+        ratio = float(np.linalg.norm(R)) / nB
+        hist.append(ratio)
+        if fixed_iters is None and ratio < tol:
+            break
+        Q = apply_A(P)
+        gam = np.einsum("dc,dc->c", P, Q)
+        a = np.divide(rho, gam, out=np.zeros_like(rho), where=gam != 0.0)
+        X += a * P
+        R -= a * Q
+        Z = m[:, None] * R
+        rho_new = np.einsum("dc,dc->c", R, Z)
+        b = np.divide(rho_new, rho, out=np.zeros_like(rho), where=rho != 0.0)
+        P = Z + b * P
+        rho = rho_new
+        it += 1
+    ratio = float(np.linalg.norm(R)) / nB
+    return X, CGInfo(it, ratio < tol, ratio, hist)
+
+
 def true_relative_residual(apply_A, X: np.ndarray, B: np.ndarray) -> float:
     """||B - A X||_F / ||B||_F evaluated directly (the stop test of Sec. 3.2)."""
     R = np.asarray(B, dtype=np.float64) - apply_A(np.asarray(X, dtype=np.float64))
@@ -369,6 +413,26 @@ def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray,
     s = diag_estimate(P, X[:, :K])
     cg = CGInfo(info.iters, info.converged, info.rel_resid, info.history)
     return EStepResult(mu=mu, s=s, X=X, P=P, cg=cg), info
+
+
+def cofem_estep_pcg(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int, tol: float, max_iter: int,
+                    seed: int, t: int, minv=None, mu0=None, d0=None, fixed_iters=None) -> EStepResult:
+    """The E-step of Algorithm 1 solved by ``pcg_solve``: M^-1 = diag(minv);
+    starting block X0 = [d0 (.) p_1 .. d0 (.) p_K | mu0] (a warm start for
+    the probe solves x_k ~ Sigma p_k from a diagonal estimate d0, and for mu);
+    None entries start from zero."""
+    D = op.D
+    P = rademacher_probes(seed, t, K, D)
+    B = np.concatenate([P, np.asarray(b0, np.float64)[:, None]], axis=1)
+    X0 = None
+    if mu0 is not None or d0 is not None:
+        X0 = np.zeros_like(B)
+        if d0 is not None:
+            X0[:, :K] = np.asarray(d0, np.float64)[:, None] * P
+        if mu0 is not None:
+            X0[:, K] = np.asarray(mu0, np.float64)
+    X, info = pcg_solve(make_apply_A(op, beta, alpha), B, tol, max_iter, minv, X0, fixed_iters)
+    return EStepResult(mu=X[:, K].copy(), s=diag_estimate(P, X[:, :K]), X=X, P=P, cg=info)
 
 
 @dataclasses.dataclass
