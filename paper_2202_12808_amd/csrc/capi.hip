@@ -70,6 +70,15 @@ struct cofem_ctx {
   float* Xt = nullptr;
   double* xtm = nullptr;
   std::vector<int32_t> sweeps;
+  // warm-started / preconditioned / learned forms (conv): M^-1 and the start
+  float* minv = nullptr;
+  float* d0 = nullptr;
+  double* mu0 = nullptr;
+  const float* active_minv = nullptr;
+  // predictor hook (learned form): fills d0 (probe start scale and M^-1) and
+  // mu0 (mean start) for the next E-step from the context's current state
+  cofem_status (*predictor)(cofem_ctx*, void*, float*, double*) = nullptr;
+  void* predictor_user = nullptr;
   bool has_solution = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -296,6 +305,9 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->alpha, cd.ldD));
   COFEM_TRY(alloc(c, &c->mu, cd.ldD));
   COFEM_TRY(alloc(c, &c->sdiag, cd.ldD));
+  COFEM_TRY(alloc(c, &c->minv, cd.ldD));
+  COFEM_TRY(alloc(c, &c->d0, cd.ldD));
+  COFEM_TRY(alloc(c, &c->mu0, cd.ldD));
   void** blocks[6] = {&c->vX, &c->vR, &c->vP, &c->vQ, &c->vVs, &c->vQs};
   for (void** b : blocks) {
     if (cd.fp64) {
@@ -318,7 +330,7 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   const int64_t nupd = conv_update_blocks(cd), ntiles = (int64_t)cd.tilesX * cd.tilesY;
   ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
   const int64_t nblks[3] = {nupd, nupd, ntiles};
-  const int nvs[3] = {1, 1, 3};
+  const int nvs[3] = {1, 3, 3};  // the preconditioned update reduces two values, its start three
   for (int i = 0; i < 3; ++i) {
     COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], nvs[i], ncols));
     COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * 3));
@@ -600,6 +612,9 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
     return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
   if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI)) && (n != 1 || p->kind != COFEM_CONV2D_CIRC))
+    return *why = "warm starts and the Jacobi preconditioner are built for convolution dictionaries",
+           COFEM_ERR_UNSUPPORTED;
   if (n > 1 || p->phi_dtype == COFEM_BF16 || (q->flags & COFEM_FLAG_BATCHED)) {
     // batched form: dense problems whose bfloat16 dictionary is the problem
     if (q->precision != COFEM_PREC_FP32)
@@ -680,6 +695,49 @@ cofem_status collect_times(cofem_ctx* c, int iters) {
   return COFEM_OK;
 }
 
+// Conv solves that start from a block X0 and/or use a diagonal preconditioner:
+// COFEM_FLAG_WARM_PREV (X0 = [max(s_prev, 0) (.) p_k | mu_prev]),
+// COFEM_FLAG_JACOBI (M^-1 = 1/diag(A)), or a predictor set by the caller.
+bool conv_pcg(const cofem_ctx* c) {
+  return c->kind == COFEM_CONV2D_CIRC && (c->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI) || c->predictor);
+}
+
+cofem_status conv_start_pcg(cofem_ctx* c, int t) {
+  const ConvDims& cd = c->cd;
+  const float* d0 = nullptr;
+  const double* mu0 = nullptr;
+  bool start = false;
+  c->active_minv = nullptr;
+  if (c->predictor && c->has_solution) {
+    // learned: X0 = [d (.) p_k | mu_hat], M^-1 = diag(d) from the network
+    COFEM_TRY(c->predictor(c, c->predictor_user, c->d0, c->mu0));
+    d0 = c->d0;
+    mu0 = c->mu0;
+    c->active_minv = c->d0;
+    start = true;
+  } else {
+    if (c->flags & COFEM_FLAG_JACOBI) {
+      COFEM_HIP(c, conv_jacobi(cd, c->taps, c->beta, c->alpha, c->minv, c->stream));
+      c->active_minv = c->minv;
+    }
+    if ((c->flags & COFEM_FLAG_WARM_PREV) && c->has_solution) {
+      d0 = c->sdiag;  // clamped at zero by conv_start
+      start = true;
+    }
+  }
+  if (start) {
+    COFEM_HIP(c, conv_start(cd, c->seed, t, d0, mu0, c->vX, c->xm, c->stream));
+    COFEM_HIP(c, conv_pass(cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm, c->red_pass,
+                           c->st, 1, c->stream));
+    COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, c->vQs, c->Qsm, c->vX, c->vR, c->vP, c->xm,
+                               c->rm, c->pm, c->red_pass, c->st, c->stream));
+  } else {
+    COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, nullptr, nullptr, c->vX, c->vR, c->vP, c->xm,
+                               c->rm, c->pm, c->red_pass, c->st, c->stream));
+  }
+  return COFEM_OK;
+}
+
 cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
   for (int i = 0; i < n; ++i) {
     const int it = c->cg_enq++;
@@ -705,6 +763,13 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
+    } else if (conv_pcg(c)) {
+      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
+                             c->red_pass, c->st, 0, c->stream, c->active_minv));
+      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
+      COFEM_HIP(c, conv_update_pcg(c->cd, c->active_minv, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm,
+                                   c->red_upd, c->st, c->stream));
     } else {
       COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
       COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
@@ -854,9 +919,12 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_init(c->dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm,
                             c->parts_init, c->cnts_init, c->st, c->stream));
-  else
+  else if (conv_pcg(c)) {
+    COFEM_TRY(conv_start_pcg(c, t));
+  } else {
     COFEM_HIP(c, conv_init(c->cd, c->seed, t, c->b0, c->vX, c->vR, c->vP, c->xm, c->rm, c->pm, c->red_init,
                            c->st, c->stream));
+  }
   const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
   // First chunk: the previous solve's count (CG counts drift slowly across EM
   // iterations), then `poll`-sized chunks until the device flag says stop.

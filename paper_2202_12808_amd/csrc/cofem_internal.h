@@ -341,6 +341,56 @@ __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
   }
 }
 
+// Finishes the start of a preconditioned solve: per column r^T z, ||r||^2 and
+// ||b||^2 in shared memory (laid out value-major, ncols each).
+__device__ __forceinline__ void finish_init_pcg(CgScalars* st, const double* v, int ncols) {
+  if ((int)threadIdx.x < ncols) {
+    st->rho[threadIdx.x] = v[threadIdx.x];
+    st->a[threadIdx.x] = 0.0;
+    st->b[threadIdx.x] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    const int limit = st->limit, fixed = st->fixed;
+    const double tol = st->tol;
+    double rr = 0.0, bb = 0.0, rz = 0.0;
+    for (int c = 0; c < ncols; ++c) {
+      rz += v[c];
+      rr += v[ncols + c];
+      bb += v[2 * ncols + c];
+    }
+    const bool finite = isfinite(rz) && isfinite(rr) && isfinite(bb);
+    const double nB = sqrt(bb);
+    st->nB = nB;
+    st->nB0 = nB;
+    st->ratio = nB > 0.0 ? sqrt(rr) / nB : 0.0;
+    st->iter = 0;
+    st->n_clamped = 0;
+    st->numeric_error = finite ? 0 : 1;
+    st->stop = (bb == 0.0) || (limit <= 0) || (!fixed && st->ratio < tol) || !finite;
+  }
+}
+
+// Finishes a preconditioned update: per column rho' = r^T z and ||r||^2 (the
+// stop test is on the unpreconditioned residual).
+__device__ __forceinline__ void finish_update_pcg(CgScalars* st, const double* v, int ncols) {
+  if ((int)threadIdx.x < ncols) st->rho[threadIdx.x] = v[threadIdx.x];
+  if (threadIdx.x == 0) {
+    const double nB = st->nB, tol = st->tol;
+    const int it = st->iter + 1, limit = st->limit, fixed = st->fixed;
+    double rr = 0.0, rz = 0.0;
+    for (int c = 0; c < ncols; ++c) {
+      rz += v[c];
+      rr += v[ncols + c];
+    }
+    const bool finite = isfinite(rr) && isfinite(rz);
+    if (!finite) st->numeric_error = 1;
+    const double ratio = nB > 0.0 ? sqrt(rr) / nB : 0.0;
+    st->ratio = ratio;
+    st->iter = it;
+    st->stop = (it >= limit) || (!fixed && ratio < tol) || !finite;
+  }
+}
+
 // Finishes the true-residual check: ||b_c - A x_c||^2 per column (in shared
 // memory) and the joint ratio sqrt(sum_c ...) / ||B||_F.
 __device__ __forceinline__ void finish_true_resid(CgScalars* st, const double* res) {
@@ -472,7 +522,19 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
                      CgScalars* st, hipStream_t s);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
-                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s);
+                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,
+                     const float* minv = nullptr);
+// preconditioned CG from a starting block (warm-started and learned forms)
+hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double* b0, const float* minv,
+                         const void* Qx, const double* qxm, void* X, void* R, void* P, double* xm, double* rm,
+                         double* pm, const ConvReduce& red, CgScalars* st, hipStream_t s);
+hipError_t conv_update_pcg(const ConvDims& cd, const float* minv, void* X, void* R, void* P, const void* Q,
+                           double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
+                           CgScalars* st, hipStream_t s);
+hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
+                      double* xm, hipStream_t s);
+hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const float* alpha, float* minv,
+                       hipStream_t s);
 hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void* Q, double* xm,
                        double* rm, double* pm, const double* qm, const ConvReduce& red,
                        CgScalars* st, hipStream_t s);

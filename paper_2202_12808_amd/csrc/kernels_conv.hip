@@ -43,6 +43,7 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ sTaps, int H
                                           int tv0, const T* __restrict__ P,
                                           const T* __restrict__ R,
                                           const float* __restrict__ alpha, T beta,
+                                          const float* __restrict__ minv,
                                           T* __restrict__ Q, T* sP, T* sT, double dots[3]) {
   using G = ConvGeom<KS>;
   constexpr int c = G::c;
@@ -111,9 +112,12 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ sTaps, int H
         const T q = beta * out[r] + (T)alpha[idx] * p;
         Q[idx] = q;
         const double qd = (double)q;
+        // with a diagonal preconditioner the step's dots are weighted by it:
+        // delta = r^T M^-1 q, eta = q^T M^-1 q
+        const double mq = minv ? (double)minv[idx] * qd : qd;
         g += (double)p * qd;
-        dl += (double)R[idx] * qd;
-        et += qd * qd;
+        dl += (double)R[idx] * mq;
+        et += qd * mq;
       }
     }
   }
@@ -126,8 +130,8 @@ template <int KS, typename TP>
 __global__ __launch_bounds__(256) void k_conv_pass(
     const float* __restrict__ taps, int H, int W, int64_t ldD, int K, const TP* __restrict__ P,
     const double* __restrict__ pm, const TP* __restrict__ R, const double* __restrict__ rm,
-    const float* __restrict__ alpha, double beta, TP* __restrict__ Q, double* __restrict__ qm,
-    ConvReduce red, CgScalars* __restrict__ st, int apply_only) {
+    const float* __restrict__ alpha, double beta, const float* __restrict__ minv, TP* __restrict__ Q,
+    double* __restrict__ qm, ConvReduce red, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
   using G = ConvGeom<KS>;
   __shared__ double sbuf[G::spH * G::spW + G::stH * G::stW];
@@ -137,12 +141,12 @@ __global__ __launch_bounds__(256) void k_conv_pass(
   const int tu0 = blockIdx.y * kTile, tv0 = blockIdx.x * kTile;
   double dots[3];
   if (col == K) {
-    conv_tile<KS, double>(sTaps, H, W, tu0, tv0, pm, rm, alpha, beta, qm, sbuf,
+    conv_tile<KS, double>(sTaps, H, W, tu0, tv0, pm, rm, alpha, beta, minv, qm, sbuf,
                           sbuf + G::spH * G::spW, dots);
   } else {
     TP* sb = reinterpret_cast<TP*>(sbuf);
     const int64_t off = (int64_t)col * ldD;
-    conv_tile<KS, TP>(sTaps, H, W, tu0, tv0, P + off, R + off, alpha, (TP)beta, Q + off, sb,
+    conv_tile<KS, TP>(sTaps, H, W, tu0, tv0, P + off, R + off, alpha, (TP)beta, minv, Q + off, sb,
                       sb + G::spH * G::spW, dots);
   }
   if (apply_only) return;
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(256) void k_conv_pass(
 template <typename TP>
 static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const void* P,
                                    const double* pm, const void* R, const double* rm,
-                                   const float* alpha, double beta, void* Q, double* qm,
+                                   const float* alpha, double beta, const float* minv, void* Q, double* qm,
                                    const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
   const dim3 grid(cd.tilesX, cd.tilesY, cd.K + 1);
   const TP* Pt = static_cast<const TP*>(P);
@@ -177,7 +181,7 @@ static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const 
 #define COFEM_CONV_CASE(KS)                                                                           \
   case KS:                                                                                            \
     hipLaunchKernelGGL((k_conv_pass<KS, TP>), grid, dim3(256), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K, Pt, \
-                       pm, Rt, rm, alpha, beta, Qt, qm, red, st, apply_only);                         \
+                       pm, Rt, rm, alpha, beta, minv, Qt, qm, red, st, apply_only);                   \
     break;
   switch (cd.ks) {
     COFEM_CONV_CASE(1)
@@ -194,10 +198,11 @@ static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const 
 
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
-                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
+                     double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,
+                     const float* minv) {
   if (cd.fp64)
-    return launch_conv_pass<double>(cd, taps, P, pm, R, rm, alpha, beta, Q, qm, red, st, apply_only, s);
-  return launch_conv_pass<float>(cd, taps, P, pm, R, rm, alpha, beta, Q, qm, red, st, apply_only, s);
+    return launch_conv_pass<double>(cd, taps, P, pm, R, rm, alpha, beta, minv, Q, qm, red, st, apply_only, s);
+  return launch_conv_pass<float>(cd, taps, P, pm, R, rm, alpha, beta, minv, Q, qm, red, st, apply_only, s);
 }
 
 // ------------------------------------------------ b0 = beta Phi^T y (Eq. 5), float64
@@ -347,6 +352,197 @@ hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void
     hipLaunchKernelGGL(k_conv_update<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K,
                        static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P),
                        static_cast<const float*>(Q), xm, rm, pm, qm, red, st);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ preconditioned CG from a starting block
+// (warm-started and learned forms).  M^-1 = diag(minv) for every column (null:
+// identity).  With a start X0 (already in X / xm) and Q = A X0 from an
+// operator pass: R = B - Q; without one: R = B, X = 0.  Then Z = M^-1 R,
+// P = Z; per column rho = r^T z, ||r||^2 (the stop test's) and ||b||^2.
+template <typename TP>
+__global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, int K, uint64_t seed, int t,
+                                                       const double* __restrict__ b0, const float* __restrict__ minv,
+                                                       const TP* __restrict__ Qx, const double* __restrict__ qxm,
+                                                       TP* __restrict__ X, TP* __restrict__ R, TP* __restrict__ P,
+                                                       double* __restrict__ xm, double* __restrict__ rm,
+                                                       double* __restrict__ pm, ConvReduce red, CgScalars* st) {
+  const int col = blockIdx.y;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  if (col == K) {
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const double b = b0[d];
+      const double r = qxm ? b - qxm[d] : b;
+      const double z = minv ? (double)minv[d] * r : r;
+      rm[d] = r;
+      pm[d] = z;
+      if (!qxm) xm[d] = 0.0;
+      rz += r * z;
+      rr += r * r;
+      bb += b * b;
+    }
+  } else {
+    const int64_t off = (int64_t)col * ldD;
+    for (int64_t d = gtid; d < D; d += gstride) {
+      const TP b = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d);
+      const TP r = Qx ? b - Qx[off + d] : b;
+      const TP z = minv ? (TP)minv[d] * r : r;
+      R[off + d] = r;
+      P[off + d] = z;
+      if (!Qx) X[off + d] = TP(0);
+      rz += (double)r * (double)z;
+      rr += (double)r * (double)r;
+      bb += 1.0;
+    }
+  }
+  __shared__ double shm[8];
+  __shared__ double mine[3], tot[3 * kMaxCols];
+  const double v0 = block_sum(rz, shm);
+  const double v1 = block_sum(rr, shm);
+  const double v2 = block_sum(bb, shm);
+  if (threadIdx.x == 0) {
+    mine[0] = v0;
+    mine[1] = v1;
+    mine[2] = v2;
+  }
+  __syncthreads();
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col, K + 1, 3, mine,
+                          tot))
+    return;
+  finish_init_pcg(st, tot, K + 1);
+}
+
+hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double* b0, const float* minv,
+                         const void* Qx, const double* qxm, void* X, void* R, void* P, double* xm, double* rm,
+                         double* pm, const ConvReduce& red, CgScalars* st, hipStream_t s) {
+  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_init_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0, minv,
+                       static_cast<const double*>(Qx), qxm, static_cast<double*>(X), static_cast<double*>(R),
+                       static_cast<double*>(P), xm, rm, pm, red, st);
+  else
+    hipLaunchKernelGGL(k_conv_init_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0, minv,
+                       static_cast<const float*>(Qx), qxm, static_cast<float*>(X), static_cast<float*>(R),
+                       static_cast<float*>(P), xm, rm, pm, red, st);
+  return hipGetLastError();
+}
+
+// x += a p ; r -= a q ; z = M^-1 r ; p <- z + b p ; rho' = r^T z, ||r||^2.
+template <typename T>
+__device__ __forceinline__ void conv_update_pcg_column(int64_t D, T* __restrict__ X, T* __restrict__ R,
+                                                       T* __restrict__ P, const T* __restrict__ Q,
+                                                       const float* __restrict__ minv, T a, T b, double* rz,
+                                                       double* rr) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t d = gtid; d < D; d += gstride) {
+    const T p = P[d];
+    X[d] = fma(a, p, X[d]);
+    const T r = fma(-a, Q[d], R[d]);
+    R[d] = r;
+    const T z = minv ? (T)minv[d] * r : r;
+    P[d] = fma(b, p, z);
+    s0 += (double)r * (double)z;
+    s1 += (double)r * (double)r;
+  }
+  *rz = s0;
+  *rr = s1;
+}
+
+template <typename TP>
+__global__ __launch_bounds__(256) void k_conv_update_pcg(int64_t D, int64_t ldD, int K, const float* __restrict__ minv,
+                                                         TP* __restrict__ X, TP* __restrict__ R, TP* __restrict__ P,
+                                                         const TP* __restrict__ Q, double* __restrict__ xm,
+                                                         double* __restrict__ rm, double* __restrict__ pm,
+                                                         const double* __restrict__ qm, ConvReduce red,
+                                                         CgScalars* st) {
+  if (st->stop) return;
+  const int col = blockIdx.y;
+  double rz, rr;
+  if (col == K) {
+    conv_update_pcg_column<double>(D, xm, rm, pm, qm, minv, st->a[K], st->b[K], &rz, &rr);
+  } else {
+    const int64_t off = (int64_t)col * ldD;
+    conv_update_pcg_column<TP>(D, X + off, R + off, P + off, Q + off, minv, (TP)st->a[col], (TP)st->b[col], &rz,
+                               &rr);
+  }
+  __shared__ double shm[8];
+  __shared__ double mine[2], tot[2 * kMaxCols];
+  const double v0 = block_sum(rz, shm);
+  const double v1 = block_sum(rr, shm);
+  if (threadIdx.x == 0) {
+    mine[0] = v0;
+    mine[1] = v1;
+  }
+  __syncthreads();
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col, K + 1, 2, mine,
+                          tot))
+    return;
+  finish_update_pcg(st, tot, K + 1);
+}
+
+hipError_t conv_update_pcg(const ConvDims& cd, const float* minv, void* X, void* R, void* P, const void* Q,
+                           double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
+                           CgScalars* st, hipStream_t s) {
+  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_update_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, minv,
+                       static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P),
+                       static_cast<const double*>(Q), xm, rm, pm, qm, red, st);
+  else
+    hipLaunchKernelGGL(k_conv_update_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, minv,
+                       static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P),
+                       static_cast<const float*>(Q), xm, rm, pm, qm, red, st);
+  return hipGetLastError();
+}
+
+// Starting block X0 = [max(d0, 0) (.) p_1 .. max(d0, 0) (.) p_K | mu0] (d0 null:
+// zero probe columns; mu0 null: keep xm as it is, the previous solve's mean
+// column).
+template <typename TP>
+__global__ void k_conv_start(int64_t D, int64_t ldD, int K, uint64_t seed, int t, const float* __restrict__ d0,
+                             const double* __restrict__ mu0, TP* __restrict__ X, double* __restrict__ xm) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D * (K + 1)) return;
+  const int64_t k = idx / D, d = idx - (idx / D) * D;
+  if (k == K) {
+    if (mu0) xm[d] = mu0[d];
+  } else {
+    const float dv = d0 ? fmaxf(d0[d], 0.0f) : 0.0f;
+    X[k * ldD + d] = (TP)(dv * probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)d));
+  }
+}
+
+hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
+                      double* xm, hipStream_t s) {
+  const int64_t tot = cd.D * (cd.K + 1);
+  const dim3 grid((unsigned)((tot + 255) / 256));
+  if (cd.fp64)
+    hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, d0, mu0,
+                       static_cast<double*>(X), xm);
+  else
+    hipLaunchKernelGGL(k_conv_start<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, d0, mu0,
+                       static_cast<float*>(X), xm);
+  return hipGetLastError();
+}
+
+// Jacobi: minv_j = 1 / (beta ||h||^2 + alpha_j) (every column of Phi has norm ||h||).
+__global__ void k_conv_jacobi(int64_t D, const float* __restrict__ taps, int ntaps, double beta,
+                              const float* __restrict__ alpha, float* __restrict__ minv) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= D) return;
+  double hh = 0.0;
+  for (int i = 0; i < ntaps; ++i) hh += (double)taps[i] * (double)taps[i];
+  minv[d] = (float)(1.0 / (beta * hh + (double)alpha[d]));
+}
+
+hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const float* alpha, float* minv,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_jacobi, dim3((unsigned)((cd.D + 255) / 256)), dim3(256), 0, s, cd.D, taps,
+                     cd.ks * cd.ks, beta, alpha, minv);
   return hipGetLastError();
 }
 

@@ -588,3 +588,51 @@ def test_batch_of_one_matches_batch_member(torch_dev):
         both = [x.cpu().numpy() for x in g2.posterior(0)]
     for x, y in zip(solo, both):
         assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------------ warm start / preconditioner
+@pytest.mark.parametrize("mode", ["jacobi", "warm", "both"])
+def test_conv_pcg_step_parity(torch_dev, mode):
+    # the warm-started / Jacobi-preconditioned solve against the oracle's PCG
+    # from the same start (the GPU's previous mean and clamped diagonal
+    # estimate) with the same float32 M^-1, at the GPU's iteration count
+    torch = torch_dev
+    p = synth.conv_problem(64, 48, 7, rho=0.02, beta=100.0, K=6, tol=1e-5, max_iter=400, seed=3, law="laplace",
+                           name="conv_64x48_k7")
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    kw = {"jacobi": mode in ("jacobi", "both"), "warm_start": mode in ("warm", "both")}
+    with _conv_ctx(torch, p, **kw) as g:
+        g.em_step(3)
+        _, s_prev, alpha = [x.cpu().numpy() for x in g.posterior()]
+        _, mu_prev = g.solution()
+        mu_prev = mu_prev.cpu().numpy()
+        st = g.em_step(1)[0]
+        mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    hh = float(np.sum(p.taps.astype(np.float64) ** 2))
+    minv = (1.0 / (p.beta * hh + alpha.astype(np.float64))).astype(np.float32).astype(np.float64)
+    e = O.cofem_estep_pcg(op, b0, p.beta, alpha.astype(np.float64), p.K, p.tol, p.max_iter, p.seed, st["t"],
+                          minv=minv if kw["jacobi"] else None,
+                          mu0=mu_prev if kw["warm_start"] else None,
+                          d0=np.maximum(s_prev.astype(np.float64), 0.0) if kw["warm_start"] else None,
+                          fixed_iters=st["cg_iters"])
+    a_ref, _ = O.mstep(e.mu, e.s)
+    errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / a_new, 1.0 / a_ref))
+    _say("conv pcg", mode, "t", st["t"], "cg", st["cg_iters"], "relerr", errs)
+    assert st["converged"] == 1 or st["cg_iters"] == p.max_iter
+    assert all(err < STEP_TOL for err in errs), errs
+
+
+def test_conv_warm_jacobi_needs_fewer_iterations(torch_dev):
+    # the non-learned control on an ill-conditioned conv problem: over EM
+    # iterations 2..6 the warm-started Jacobi solve takes fewer CG iterations
+    # than the cold unpreconditioned one (same stop rule)
+    torch = torch_dev
+    p = synth.conv_problem(96, 96, 7, rho=0.02, beta=1e3, K=8, tol=1e-5, max_iter=400, seed=4, law="laplace",
+                           name="conv_96x96_k7")
+    counts = {}
+    for name, kw in (("plain", {}), ("warm+jacobi", {"jacobi": True, "warm_start": True})):
+        with _conv_ctx(torch, p, **kw) as g:
+            counts[name] = [x["cg_iters"] for x in g.em_step(6)]
+    _say("cg counts", counts)
+    assert sum(counts["warm+jacobi"][1:]) < sum(counts["plain"][1:])
