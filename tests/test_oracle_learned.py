@@ -1,0 +1,66 @@
+"""Pins of the oracle of the learned start/preconditioner network: the hand
+backward pass against central finite differences of the loss, the 3x3
+circular convolution against a direct double loop, and the zero network's
+prediction (the previous mean and the Jacobi diagonal)."""
+import numpy as np
+
+from oracle import learned as L
+
+
+def _sample(H=7, W=6, seed=0, channels=(4, 5, 3, 2)):
+    rng = np.random.default_rng(seed)
+    theta = rng.standard_normal(L.n_params(channels)) * 0.4
+    feats = rng.standard_normal((channels[0], H, W))
+    mu_p = rng.standard_normal((H, W))
+    d = np.exp(rng.uniform(0, 3, (H, W)))
+    aux = np.stack([mu_p, d])
+    targets = np.stack([mu_p * rng.uniform(0.5, 1.5, (H, W)), np.exp(rng.uniform(-1, 1, (H, W))) / d])
+    return theta, feats, aux, targets, channels
+
+
+def test_conv3_matches_direct_loop():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((3, 5, 4))
+    w = rng.standard_normal((2, 3, 3, 3))
+    b = rng.standard_normal(2)
+    out = L.conv3(x, w, b)
+    H, W = 5, 4
+    ref = np.zeros((2, H, W))
+    for co in range(2):
+        for u in range(H):
+            for v in range(W):
+                acc = b[co]
+                for ci in range(3):
+                    for ky in range(3):
+                        for kx in range(3):
+                            acc += w[co, ci, ky, kx] * x[ci, (u + ky - 1) % H, (v + kx - 1) % W]
+                ref[co, u, v] = acc
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_backward_matches_finite_differences():
+    theta, feats, aux, targets, ch = _sample()
+    Lv, g = L.backward(theta, feats, aux, targets, ch)
+    assert np.isclose(Lv, L.loss(theta, feats, aux, targets, ch))
+    rng = np.random.default_rng(2)
+    idx = rng.choice(theta.size, 40, replace=False)
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (L.loss(tp, feats, aux, targets, ch) - L.loss(tm, feats, aux, targets, ch)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_zero_network_predicts_previous_mean_and_jacobi():
+    H, W = 6, 5
+    rng = np.random.default_rng(3)
+    alpha = np.exp(rng.uniform(-2, 8, H * W))
+    mu = rng.standard_normal(H * W)
+    s = np.exp(rng.uniform(-5, 0, H * W))
+    feats, aux = L.features(alpha, mu, s, 100.0, 0.8, H, W)
+    out, _ = L.forward(np.zeros(L.n_params()), feats)
+    mu_hat, d_hat = L.predict(out, aux)
+    np.testing.assert_allclose(mu_hat, mu.reshape(H, W))
+    np.testing.assert_allclose(d_hat, 1.0 / (100.0 * 0.8 + alpha.reshape(H, W)))
