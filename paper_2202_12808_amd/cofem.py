@@ -86,6 +86,16 @@ _SIGNATURES = {
     "cofem_probe_signs": (c_int32, [c_uint64, c_int32, c_int32, c_int64, c_void_p, c_void_p]),
     "cofem_time_operator": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float)]),
     "cofem_set_kernel_timing": (c_int32, [c_void_p, c_int32]),
+    "cofem_net_num_params": (c_int64, []),
+    "cofem_net_create": (c_int32, [c_int32, c_int32, c_uint64, c_void_p, POINTER(c_void_p)]),
+    "cofem_net_destroy": (None, [c_void_p]),
+    "cofem_net_set_params": (c_int32, [c_void_p, c_void_p, c_int64]),
+    "cofem_net_get_params": (c_int32, [c_void_p, c_void_p, c_int64]),
+    "cofem_net_forward": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "cofem_net_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p]),
+    "cofem_net_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, POINTER(c_double)]),
+    "cofem_features": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cofem_set_predictor": (c_int32, [c_void_p, c_void_p]),
     "cofem_batch_plan": (c_int32, [c_void_p, POINTER(c_int32), POINTER(ctypes.c_float), POINTER(c_int32),
                                    POINTER(c_int32)]),
     "cofem_get_ir_sweeps": (c_int32, [c_void_p, POINTER(c_int32), c_int32, POINTER(c_int32)]),
@@ -345,6 +355,18 @@ class CoFEM:
     def time_operator(self, reps=20):
         return cofem_time_operator(self.ctx, reps)
 
+    def features(self, net):
+        """(feats [4, H*W], aux [2, H*W]) of the next E-step (convolution only)."""
+        import torch
+        feats = torch.empty((4, self.D), dtype=torch.float32, device=self.device)
+        aux = torch.empty((2, self.D), dtype=torch.float32, device=self.device)
+        _check(load().cofem_features(self.ctx, net.net, _ptr(feats), _ptr(aux)), self.ctx)
+        return feats, aux
+
+    def set_predictor(self, net):
+        _check(load().cofem_set_predictor(self.ctx, net.net if net is not None else None), self.ctx)
+        self._predictor = net
+
     def set_kernel_timing(self, enable=True):
         cofem_set_kernel_timing(self.ctx, enable)
 
@@ -453,3 +475,61 @@ class CoFEMBatch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class CoFEMNet:
+    """The learned form's network (convolution dictionaries): trained and run
+    by the library's own kernels on H x W images."""
+
+    def __init__(self, H, W, seed=0, stream=None):
+        self.H, self.W = int(H), int(W)
+        self.net = c_void_p()
+        _check(load().cofem_net_create(self.H, self.W, int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream),
+                                       ctypes.byref(self.net)))
+
+    @staticmethod
+    def num_params():
+        return int(load().cofem_net_num_params())
+
+    def set_params(self, theta):
+        import numpy as np
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(load().cofem_net_set_params(self.net, theta.ctypes.data_as(c_void_p), theta.size))
+
+    def get_params(self):
+        import numpy as np
+        theta = np.empty(self.num_params(), dtype=np.float32)
+        _check(load().cofem_net_get_params(self.net, theta.ctypes.data_as(c_void_p), theta.size))
+        return theta
+
+    def forward(self, feats):
+        import torch
+        out = torch.empty((2, self.H * self.W), dtype=torch.float32, device=feats.device)
+        _check(load().cofem_net_forward(self.net, _ptr(feats.contiguous()), _ptr(out)))
+        return out
+
+    def loss_grad(self, feats, aux, targets):
+        import numpy as np
+        loss = c_double(0.0)
+        g = np.empty(self.num_params(), dtype=np.float32)
+        _check(load().cofem_net_loss_grad(self.net, _ptr(feats.contiguous()), _ptr(aux.contiguous()),
+                                          _ptr(targets.contiguous()), ctypes.byref(loss),
+                                          g.ctypes.data_as(c_void_p)))
+        return loss.value, g
+
+    def train_step(self, feats, aux, targets, lr=1e-3):
+        loss = c_double(0.0)
+        _check(load().cofem_net_train_step(self.net, _ptr(feats), _ptr(aux), _ptr(targets), float(lr),
+                                           ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "net", None) and self.net.value:
+            load().cofem_net_destroy(self.net)
+            self.net = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -129,6 +129,8 @@ namespace {
 
 thread_local std::string g_err;
 
+cofem_status predictor_hook(cofem_ctx* c, void* user, float* d0, double* mu0);
+
 cofem_status fail(cofem_ctx* c, cofem_status s, const std::string& msg) {
   if (c) c->err = msg;
   g_err = msg;
@@ -1278,6 +1280,30 @@ cofem_status cofem_batch_plan(cofem_ctx* ctx, int32_t* target_wgs, float* candid
   return COFEM_OK;
 }
 
+cofem_status cofem_features(cofem_ctx* ctx, cofem_net* net, float* feats, float* aux) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (!net || !feats || !aux) return fail(ctx, COFEM_ERR_INVALID_ARG, "null net or output");
+  if (ctx->kind != COFEM_CONV2D_CIRC || ctx->batch)
+    return fail(ctx, COFEM_ERR_UNSUPPORTED, "features exist for convolution dictionaries only");
+  if (net_height(net) != ctx->cd.H || net_width(net) != ctx->cd.W)
+    return fail(ctx, COFEM_ERR_INVALID_ARG, "the net's image size differs from the problem's");
+  COFEM_TRY(net_features(net, ctx->alpha, ctx->xm, ctx->sdiag, ctx->taps, ctx->cd.ks * ctx->cd.ks, ctx->beta, feats,
+                         aux, ctx->stream));
+  COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_set_predictor(cofem_ctx* ctx, cofem_net* net) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (ctx->kind != COFEM_CONV2D_CIRC || ctx->batch)
+    return fail(ctx, COFEM_ERR_UNSUPPORTED, "the learned form is built for convolution dictionaries");
+  if (net && (net_height(net) != ctx->cd.H || net_width(net) != ctx->cd.W))
+    return fail(ctx, COFEM_ERR_INVALID_ARG, "the net's image size differs from the problem's");
+  ctx->predictor = net ? predictor_hook : nullptr;
+  ctx->predictor_user = net;
+  return COFEM_OK;
+}
+
 void cofem_destroy(cofem_ctx* ctx) { destroy_ctx(ctx); }
 
 const char* cofem_last_error(const cofem_ctx* ctx) {
@@ -1298,3 +1324,16 @@ const char* cofem_status_string(cofem_status s) {
 }
 
 }  // extern "C"
+
+namespace {
+
+cofem_status predictor_hook(cofem_ctx* c, void* user, float* d0, double* mu0) {
+  return net_predict(static_cast<cofem_net*>(user), c->alpha, c->xm, c->sdiag, c->taps, c->cd.ks * c->cd.ks,
+                     c->beta, d0, mu0, c->stream);
+}
+
+}  // namespace
+
+namespace cofem {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace cofem

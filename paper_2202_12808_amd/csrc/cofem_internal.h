@@ -9,6 +9,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include "cofem.h"
+
+#include <string>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -585,5 +588,14 @@ hipError_t batch_update(const BatchItem* items, int n, const BatchProblem* probs
 hipError_t batch_mstep(const BatchItem* items, int n, const BatchProblem* probs, int t, int K, double alpha_max,
                        hipStream_t s);
 hipError_t batch_running(const BatchProblem* probs, int n, int32_t* out, hipStream_t s);
+
+// ------------------------------------------------------------ learned form
+void set_last_error(const std::string& msg);
+cofem_status net_predict(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
+                         const float* taps, int ntaps, double beta, float* d0, double* mu0, hipStream_t s);
+cofem_status net_features(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
+                          const float* taps, int ntaps, double beta, float* feats, float* aux, hipStream_t s);
+int net_height(const cofem_net* n);
+int net_width(const cofem_net* n);
 
 }  // namespace cofem

@@ -636,3 +636,138 @@ def test_conv_warm_jacobi_needs_fewer_iterations(torch_dev):
             counts[name] = [x["cg_iters"] for x in g.em_step(6)]
     _say("cg counts", counts)
     assert sum(counts["warm+jacobi"][1:]) < sum(counts["plain"][1:])
+
+
+# ------------------------------------------------------------------ learned form
+def _net_sample(torch, H, W, seed=0):
+    rng = np.random.default_rng(seed)
+    from oracle import learned as OL
+    theta = (rng.standard_normal(OL.n_params()) * 0.15).astype(np.float32)
+    feats = rng.standard_normal((4, H, W)).astype(np.float32)
+    mu_p = rng.standard_normal((H, W)).astype(np.float32)
+    d = np.exp(rng.uniform(0, 3, (H, W))).astype(np.float32)
+    aux = np.stack([mu_p, d])
+    tg = np.stack([mu_p * rng.uniform(0.5, 1.5, (H, W)), np.exp(rng.uniform(-1, 1, (H, W))) / d]).astype(np.float32)
+    return theta, feats, aux, tg
+
+
+def test_net_forward_and_gradients_match_oracle(torch_dev):
+    # the training kernels (forward, loss, backward through the four circular
+    # 3x3 layers) against the float64 oracle whose backward is pinned by finite
+    # differences; 20 x 18 covers partial 16 x 16 tiles and the wrap-around
+    torch = torch_dev
+    from oracle import learned as OL
+    from paper_2202_12808_amd.cofem import CoFEMNet
+    H, W = 20, 18
+    theta, feats, aux, tg = _net_sample(torch, H, W)
+    net = CoFEMNet(H, W)
+    net.set_params(theta)
+    t = lambda a: torch.from_numpy(a.reshape(a.shape[0], H * W)).cuda()  # noqa: E731
+    out = net.forward(t(feats)).cpu().numpy().reshape(2, H, W)
+    ref_out, _ = OL.forward(theta.astype(np.float64), feats.astype(np.float64))
+    assert relerr(out, ref_out) < 1e-5
+    loss, g = net.loss_grad(t(feats), t(aux), t(tg))
+    ref_loss, ref_g = OL.backward(theta.astype(np.float64), feats.astype(np.float64), aux.astype(np.float64),
+                                  tg.astype(np.float64))
+    _say("net loss gpu", loss, "oracle", ref_loss, "grad relerr", relerr(g, ref_g))
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert relerr(g, ref_g) < 1e-4
+    # per layer, so that no small layer hides behind a large one
+    k = 0
+    for ws, bs in OL.param_shapes():
+        n = int(np.prod(ws)) + int(np.prod(bs))
+        assert relerr(g[k:k + n], ref_g[k:k + n]) < 1e-4
+        k += n
+    net.close()
+
+
+def _small_conv(seed=0, H=64, W=64):
+    return synth.conv_problem(H, W, 7, rho=0.02, beta=1e3, K=8, tol=1e-5, max_iter=400, seed=seed,
+                              law="laplace", name=f"conv_{H}x{W}_k7")
+
+
+def test_features_match_oracle(torch_dev):
+    torch = torch_dev
+    from oracle import learned as OL
+    from paper_2202_12808_amd.cofem import CoFEMNet
+    p = _small_conv(5, 40, 36)
+    net = CoFEMNet(p.H, p.W)
+    with _conv_ctx(torch, p, jacobi=True, warm_start=True) as g:
+        g.em_step(2)
+        _, s, alpha = [x.cpu().numpy() for x in g.posterior()]
+        _, mu = g.solution()
+        feats, aux = [x.cpu().numpy() for x in g.features(net)]
+    hh = float(np.sum(p.taps.astype(np.float64) ** 2))
+    rf, ra = OL.features(alpha, mu.cpu().numpy(), s, p.beta, hh, p.H, p.W)
+    assert relerr(feats.reshape(4, p.H, p.W), rf) < 1e-6
+    assert relerr(aux.reshape(2, p.H, p.W), ra) < 1e-6
+    net.close()
+
+
+def test_learned_step_parity(torch_dev):
+    # a solve started from the network's prediction with its preconditioner,
+    # against the oracle's PCG from the oracle network's prediction on the
+    # same state (same parameters), at the GPU's iteration count
+    torch = torch_dev
+    from oracle import learned as OL
+    from paper_2202_12808_amd.cofem import CoFEMNet
+    p = _small_conv(6, 48, 40)
+    rng = np.random.default_rng(4)
+    theta = (rng.standard_normal(OL.n_params()) * 0.05).astype(np.float32)
+    net = CoFEMNet(p.H, p.W)
+    net.set_params(theta)
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _conv_ctx(torch, p) as g:
+        g.set_predictor(net)
+        g.em_step(2)
+        _, s_prev, alpha = [x.cpu().numpy() for x in g.posterior()]
+        _, mu_prev = g.solution()
+        mu_prev = mu_prev.cpu().numpy()
+        st = g.em_step(1)[0]
+        mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    hh = float(np.sum(p.taps.astype(np.float64) ** 2))
+    f, aux = OL.features(alpha, mu_prev, s_prev, p.beta, hh, p.H, p.W)
+    out, _ = OL.forward(theta.astype(np.float64), f)
+    mu_hat, d_hat = OL.predict(out, aux)
+    d_hat = d_hat.ravel().astype(np.float32).astype(np.float64)
+    e = O.cofem_estep_pcg(op, b0, p.beta, alpha.astype(np.float64), p.K, p.tol, p.max_iter, p.seed, st["t"],
+                          minv=d_hat, mu0=mu_hat.ravel(), d0=d_hat, fixed_iters=st["cg_iters"])
+    a_ref, _ = O.mstep(e.mu, e.s)
+    errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / a_new, 1.0 / a_ref))
+    _say("learned step t", st["t"], "cg", st["cg_iters"], "relerr", errs)
+    assert st["converged"] == 1
+    assert all(err < STEP_TOL for err in errs), errs
+    net.close()
+
+
+def test_training_reduces_loss_and_cg_iterations(torch_dev):
+    # trained on EM iterates of three training seeds, evaluated on a fourth:
+    # the loss falls, and from the second EM iteration on the learned solve
+    # needs fewer CG iterations than the plain one (same stop rule); the
+    # non-learned control (previous iterate + Jacobi) is reported beside it
+    torch = torch_dev
+    from paper_2202_12808_amd import learned as LD
+    from paper_2202_12808_amd.cofem import CoFEMNet
+    H = W = 64
+    net = CoFEMNet(H, W, seed=1)
+    mk = lambda sd: _conv_ctx(torch, _small_conv(100 + sd, H, W), jacobi=True, warm_start=True)  # noqa: E731
+    samples = LD.collect_samples(mk, [0, 1, 2], 8, net)
+    before = LD.mean_loss(net, samples)
+    hist = LD.train(net, samples, epochs=40, lr=2e-3)
+    after = LD.mean_loss(net, samples)
+    _say("training loss", before, "->", after, "epochs", [round(h, 4) for h in hist[::8]])
+    assert after < 0.8 * before
+    p = _small_conv(7, H, W)
+    counts, mus = {}, {}
+    for name in ("plain", "control", "learned"):
+        kw = {"jacobi": True, "warm_start": True} if name == "control" else {}
+        with _conv_ctx(torch, p, **kw) as g:
+            if name == "learned":
+                g.set_predictor(net)
+            counts[name] = [x["cg_iters"] for x in g.em_step(8)]
+            mus[name] = g.posterior()[0].cpu().numpy().astype(np.float64)
+    _say("cg counts", counts, "nmse of mu_T vs plain",
+         {k: float(np.sum((m - mus["plain"]) ** 2) / np.sum(mus["plain"] ** 2)) for k, m in mus.items()})
+    assert sum(counts["learned"][1:]) < sum(counts["plain"][1:])
+    net.close()
