@@ -66,8 +66,13 @@ KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "u
                 "dense_bf16_ir": {"pass1": "k_dense16_pass1", "pass2": "k_dense16_pass2", "update": "k_dense_update"},
                 "conv": {"pass1": "k_conv_pass", "update": "k_conv_update"}}
 FORMS = {"fp32": "fp32 probes + fp64 mean column",
-         "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column)"}
+         "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column)",
+         "control": "fp32 CG started from the previous mean and diagonal estimate, Jacobi-preconditioned",
+         "learned": "fp32 CG started from a learned prediction with its learned diagonal preconditioner"}
+CONV_FORMS = ("fp32", "control", "learned")
 KERNEL_SOURCES = {"dense": ("paper_2202_12808_amd/csrc/kernels_dense.hip", "paper_2202_12808_amd/csrc/cofem_internal.h"),
+                  "dense_bf16_ir": ("paper_2202_12808_amd/csrc/kernels_dense_bf16.hip",
+                                    "paper_2202_12808_amd/csrc/cofem_internal.h"),
                   "conv": ("paper_2202_12808_amd/csrc/kernels_conv.hip", "paper_2202_12808_amd/csrc/cofem_internal.h")}
 
 
@@ -100,6 +105,44 @@ def stored_traffic(kind, kernel, workload):
         return float(fields["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=8, epochs=30, lr=2e-3):
+    """Trains the learned form's network on EM iterates of `seeds` (disjoint
+    from the evaluation seed) at train_size^2 with the workload's kernel law,
+    beta, K and tolerance (warm-started Jacobi solves give the targets), then
+    returns a network of the workload's image size with those parameters."""
+    import torch
+
+    from paper_2202_12808_amd import learned as LD
+    from paper_2202_12808_amd import synth
+    from paper_2202_12808_amd.cofem import CoFEM, CoFEMNet
+
+    t0 = time.perf_counter()
+    hs = min(train_size, p.H)
+    ws = min(train_size, p.W)
+    small = CoFEMNet(hs, ws, seed=7)
+
+    def mk(sd):
+        q = synth.conv_problem(hs, ws, p.taps.shape[0], rho=float(round(p.z.astype(bool).mean(), 4)), beta=p.beta,
+                               K=p.K, tol=p.tol, max_iter=p.max_iter, seed=sd, name="train")
+        return CoFEM.conv(torch.from_numpy(q.taps).to(dev), torch.from_numpy(q.y).to(dev), q.H, q.W, q.beta, q.K,
+                          tol=q.tol, max_iter=q.max_iter, seed=sd, jacobi=True, warm_start=True)
+
+    samples = LD.collect_samples(mk, seeds, em_iters, small)
+    before = LD.mean_loss(small, samples)
+    hist = LD.train(small, samples, epochs=epochs, lr=lr)
+    after = LD.mean_loss(small, samples)
+    net = small
+    if (hs, ws) != (p.H, p.W):
+        net = CoFEMNet(p.H, p.W)
+        net.set_params(small.get_params())
+        small.close()
+    info = {"train_image": [hs, ws], "seeds": list(seeds), "samples": len(samples), "epochs": epochs,
+            "loss_before": round(before, 6), "loss_after": round(after, 6),
+            "seconds": round(time.perf_counter() - t0, 2)}
+    log(f"learned predictor trained: {info}")
+    return net, info
 
 
 def run_batched(args):
@@ -271,19 +314,29 @@ def main():
         f"T_em={T_em} (inputs generated in {time.perf_counter() - t_gen:.1f}s)")
 
     if args.form is None:
-        args.form = "bf16_ir" if p.kind == "dense" else "fp32"
-    if args.form != "fp32" and p.kind != "dense":
-        print("--form bf16_ir is built for dense dictionaries only", file=sys.stderr, flush=True)
+        args.form = "bf16_ir" if p.kind == "dense" else "learned"
+    if (args.form == "bf16_ir" and p.kind != "dense") or (args.form in ("control", "learned") and p.kind == "dense"):
+        print(f"--form {args.form} is not built for this dictionary kind", file=sys.stderr, flush=True)
         sys.exit(2)
     y = torch.from_numpy(p.y).to(dev)
     phi = torch.from_numpy(p.phi).to(dev) if p.kind == "dense" else None
+
+    net = None
+    train_info = None
+    if p.kind == "conv" and (args.form == "learned" or not args.no_compare):
+        net, train_info = train_predictor(p, dev)
 
     def make(form):
         if p.kind == "dense":
             return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, precision=form,
                                ir_inner_tol=args.ir_inner_tol)
         taps = torch.from_numpy(p.taps).to(dev)
-        return CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
+        ctl = form == "control"
+        c = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, jacobi=ctl,
+                       warm_start=ctl)
+        if form == "learned":
+            c.set_predictor(net)
+        return c
 
     g = make(args.form)
     ones = torch.ones(p.D, dtype=torch.float32, device=dev)
@@ -351,7 +404,7 @@ def main():
     dom = max(ops, key=lambda k: total[k])
     nbytes = algorithmic_bytes(p, dom, phi_bytes)
     achieved = nbytes / (per[dom] * 1e-3) / 1e9
-    traffic = stored_traffic(p.kind, names[dom], p.name)
+    traffic = stored_traffic("dense_bf16_ir" if args.form == "bf16_ir" else p.kind, names[dom], p.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[dom],
                 "bytes_per_launch": nbytes, "ms_per_launch": round(per[dom], 5), "timing": source,
@@ -366,6 +419,29 @@ def main():
     forms = None
     mu_T2 = None
     mean_cg_fp32 = mean_cg if args.form == "fp32" else None
+    if p.kind == "conv" and not args.no_compare:
+        forms = {args.form: {"value": round(value, 4), "cg_iters_per_em": cg_counts}}
+        mus = {args.form: mu_T}
+        for other in CONV_FORMS:
+            if other == args.form:
+                continue
+            g2 = make(other)
+            g2.set_alpha(ones)
+            g2.set_iteration(1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st2 = g2.em_step(T_em)
+            torch.cuda.synchronize()
+            el2 = time.perf_counter() - t1
+            mus[other] = g2.posterior()[0].cpu().numpy().astype(np.float64)
+            forms[other] = {"value": round(T_em / el2, 4), "cg_iters_per_em": [x["cg_iters"] for x in st2]}
+            if other == "fp32":
+                mean_cg_fp32 = float(np.mean(forms[other]["cg_iters_per_em"]))
+            log(f"form {other}: {forms[other]['value']:.3f} EM it/s; CG per EM {forms[other]['cg_iters_per_em']}")
+            g2.close()
+        ref = mus["fp32"]
+        forms["nmse_mu_T_vs_fp32"] = {k: float(np.sum((m - ref) ** 2) / np.sum(ref ** 2)) for k, m in mus.items()}
+        forms["training"] = train_info
     if p.kind == "dense" and not args.no_compare:
         other = "bf16_ir" if args.form == "fp32" else "fp32"
         g2 = make(other)
