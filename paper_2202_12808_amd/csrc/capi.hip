@@ -211,7 +211,7 @@ cofem_status push_controls(cofem_ctx* c) {
 cofem_status alloc_tree(cofem_ctx* c, double** parts, uint32_t** cnts, int64_t nblk, int ncols,
                         int regions = 1) {
   COFEM_TRY(alloc(c, parts, (size_t)(tree_rows(nblk) * ncols * regions)));
-  COFEM_TRY(alloc(c, cnts, (size_t)(tree_counters(nblk) * regions)));
+  COFEM_TRY(alloc(c, cnts, (size_t)(tree_counters(nblk) * regions * kCounterStride)));
   return COFEM_OK;
 }
 
@@ -276,8 +276,8 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
     COFEM_TRY(alloc(c, &c->Xt, blk));
     COFEM_TRY(alloc(c, &c->xtm, dd.Dp));
   }
-  COFEM_TRY(alloc(c, &c->cnt_split1, (size_t)(dd.Np / 32)));
-  COFEM_TRY(alloc(c, &c->cnt_split2, (size_t)(dd.Dp / 32)));
+  COFEM_TRY(alloc(c, &c->cnt_split1, (size_t)(dd.Np / 32 * kCounterStride)));
+  COFEM_TRY(alloc(c, &c->cnt_split2, (size_t)(dd.Dp / 32 * kCounterStride)));
 
   COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
   if (lowp)
@@ -295,8 +295,8 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   cd.D = (int64_t)p.H * p.W;
   cd.ldD = round_up(cd.D, 256);
   cd.K = c->K;
-  cd.tilesX = (p.W + 31) / 32;
-  cd.tilesY = (p.H + 31) / 32;
+  cd.tilesX = (p.W + kConvTile - 1) / kConvTile;
+  cd.tilesY = (p.H + kConvTile - 1) / kConvTile;
   c->KP = c->K;
   cd.fp64 = c->precision == COFEM_PREC_FP64 ? 1 : 0;
   const size_t blk = (size_t)cd.ldD * c->K;
@@ -329,9 +329,10 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->Vsm, cd.ldD));
   COFEM_TRY(alloc(c, &c->Qsm, cd.ldD));
   const int ncols = c->K + 1;
-  const int64_t nupd = conv_update_blocks(cd), ntiles = (int64_t)cd.tilesX * cd.tilesY;
+  const int64_t nupd = conv_update_blocks(cd), npass = conv_pass_blocks(cd);
   ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
-  const int64_t nblks[3] = {nupd, nupd, ntiles};
+  // red_pass also serves the start of a preconditioned solve (nupd blocks)
+  const int64_t nblks[3] = {nupd, nupd, npass > nupd ? npass : nupd};
   const int nvs[3] = {1, 3, 3};  // the preconditioned update reduces two values, its start three
   for (int i = 0; i < 3; ++i) {
     COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], nvs[i], ncols));
@@ -468,8 +469,8 @@ cofem_status init_batch(cofem_ctx* c, const cofem_problem* problems, int n) {
     COFEM_TRY(alloc(c, &p.wmpart, (size_t)BatchHost::kSmax * d.Np));
     COFEM_TRY(alloc(c, &p.Qpart, (size_t)BatchHost::kSmax * d.Dp * kDenseKP));
     COFEM_TRY(alloc(c, &p.qmpart, (size_t)BatchHost::kSmax * d.Dp));
-    COFEM_TRY(alloc(c, &p.cnt_split1, (size_t)p.npairs1));
-    COFEM_TRY(alloc(c, &p.cnt_split2, (size_t)p.npairs2));
+    COFEM_TRY(alloc(c, &p.cnt_split1, (size_t)(p.npairs1 * kCounterStride)));
+    COFEM_TRY(alloc(c, &p.cnt_split2, (size_t)(p.npairs2 * kCounterStride)));
     COFEM_TRY(alloc_tree(c, &p.parts_init, &p.cnts_init, p.nvec, kDenseKP + 1));
     COFEM_TRY(alloc_tree(c, &p.parts_upd, &p.cnts_upd, p.nvec, kDenseKP + 1));
     COFEM_TRY(alloc_tree(c, &p.parts_pass, &p.cnts_pass, p.npairs2, 3 * (kDenseKP + 1)));

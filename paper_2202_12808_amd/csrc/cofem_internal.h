@@ -95,6 +95,13 @@ __device__ __forceinline__ void store_agent(T* p, T v) {
 // thread waits for its own stores to complete before the barrier, so the
 // ticket increment is ordered after all of the block's partials without a
 // device-wide cache write-back per block.
+// Ticket counters are spaced one 256-byte line apart (kCounterStride uint32
+// slots): device-scope atomics on counters that share a line serialise at the
+// memory side, and a reduction's level-one counters are hit by up to 32
+// workgroups at once.  Arrays of counters are allocated and indexed with this
+// stride.
+constexpr int kCounterStride = 64;
+
 __device__ __forceinline__ bool last_block_ticket(uint32_t* counter, uint32_t total) {
   __shared__ bool s_last;
   __builtin_amdgcn_s_waitcnt(0);
@@ -122,43 +129,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh /* >= 8 doubles
   return r;
 }
 
-// Deterministic last-block total out_sh[c] = sum_b part[b * ncols + c] over
-// b < nblk, c < ncols (ncols <= blockDim.x); loads are issued eight at a time.
-__device__ __forceinline__ void total_partials(const double* part, int nblk, int ncols,
-                                               double* out_sh) {
-  __shared__ double red[512];
-  const int nt = blockDim.x;
-  const int tpc = nt / ncols;
-  const int c = threadIdx.x / tpc, j = threadIdx.x - c * tpc;
-  double v = 0.0;
-  if (c < ncols) {
-    int b = j;
-    for (; b + 7 * tpc < nblk; b += 8 * tpc) {
-      double t[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) t[i] = load_agent(&part[(int64_t)(b + i * tpc) * ncols + c]);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v += t[i];
-    }
-    for (; b < nblk; b += tpc) v += load_agent(&part[(int64_t)b * ncols + c]);
-  }
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x < ncols) {
-    double s = 0.0;
-    for (int i = 0; i < tpc; ++i) s += red[threadIdx.x * tpc + i];
-    out_sh[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
 // Deterministic tree reduction of per-block partial vectors across a grid.
 // Every block calls it with its own ncols values in shared memory (`mine`,
 // ncols <= blockDim.x); blocks are grouped 32 at a time per level, and the last
 // block of each group sums the group (in index order) and moves up a level.
 // Returns true in the single block that ends with the totals in `out_sh`.
 // `parts` holds tree_rows(nblk) rows of ncols doubles and `cnts`
-// tree_counters(nblk) zero-initialised counters (left zero on exit).
+// tree_counters(nblk) zero-initialised counters, kCounterStride slots apart
+// (left zero on exit).
 __host__ __device__ __forceinline__ int64_t tree_rows(int64_t n) {
   int64_t rows = n;
   while (n > 1) {
@@ -192,7 +170,7 @@ __device__ __forceinline__ bool tree_reduce(double* parts, uint32_t* cnts, int64
     const int64_t g = idx / 32;
     const int64_t base = g * 32;
     const int gs = (int)((n - base) < 32 ? (n - base) : 32);
-    if (!last_block_ticket(&c[g], (uint32_t)gs)) return false;
+    if (!last_block_ticket(&c[g * kCounterStride], (uint32_t)gs)) return false;
     double v = 0.0;
     if (tid < ncols) {
       // all (up to 32) loads in flight at once, summed in block order
@@ -203,7 +181,7 @@ __device__ __forceinline__ bool tree_reduce(double* parts, uint32_t* cnts, int64
       for (int u = 0; u < 32; ++u)
         if (u < gs) v += t[u];
     }
-    if (tid == 0) store_agent(&c[g], 0u);
+    if (tid == 0) store_agent(&c[g * kCounterStride], 0u);
     const int64_t ng = (n + 31) / 32;
     if (ng == 1) {
       if (tid < ncols) out_sh[tid] = v;
@@ -212,7 +190,7 @@ __device__ __forceinline__ bool tree_reduce(double* parts, uint32_t* cnts, int64
     }
     double* pn = p + n * ncols;
     if (tid < ncols) store_agent(&pn[g * ncols + tid], v);
-    c += ng;
+    c += ng * kCounterStride;
     p = pn;
     idx = g;
     n = ng;
@@ -227,11 +205,11 @@ __device__ __forceinline__ bool tree_reduce(double* parts, uint32_t* cnts, int64
 // The last of those returns true with every total in out_sh[v * ncols + col].
 __device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts, double* colsum,
                                                    uint32_t* cnt_cols, int64_t blk, int64_t nblk,
-                                                   int col, int ncols, int nv, const double* mine,
-                                                   double* out_sh) {
+                                                   int64_t nblk_alloc, int col, int ncols, int nv,
+                                                   const double* mine, double* out_sh) {
   __shared__ double coltot[8];
-  double* p = parts + (int64_t)col * tree_rows(nblk) * nv;
-  uint32_t* c = cnts + (int64_t)col * tree_counters(nblk);
+  double* p = parts + (int64_t)col * tree_rows(nblk_alloc) * nv;
+  uint32_t* c = cnts + (int64_t)col * tree_counters(nblk_alloc) * kCounterStride;
   if (!tree_reduce(p, c, blk, nblk, nv, mine, coltot)) return false;
   if (threadIdx.x < nv) store_agent(&colsum[col * nv + threadIdx.x], coltot[threadIdx.x]);
   if (!last_block_ticket(cnt_cols, (uint32_t)ncols)) return false;
@@ -242,6 +220,12 @@ __device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts
   if (threadIdx.x == 0) store_agent(cnt_cols, 0u);
   __syncthreads();
   return true;
+}
+__device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts, double* colsum,
+                                                   uint32_t* cnt_cols, int64_t blk, int64_t nblk,
+                                                   int col, int ncols, int nv, const double* mine,
+                                                   double* out_sh) {
+  return column_tree_reduce(parts, cnts, colsum, cnt_cols, blk, nblk, nblk, col, ncols, nv, mine, out_sh);
 }
 
 // ------------------------------------------------ per-block column sums (dense)
@@ -268,24 +252,46 @@ __device__ __forceinline__ void dense_block_sums(double acc, double accm, double
 // device-coherent memory, not one per column); column sums are formed by
 // thread 0 from shared memory in column order.
 
+// The scalars that the finishing block of a CG kernel reads, loaded by every
+// block at kernel start (they do not change during the kernel), so the last
+// block's finish costs no further memory round trip.
+struct CgCtl {
+  double rho;  // st->rho[threadIdx.x] in threads < nc, else 0
+  double nB, tol;
+  int nc, iter, limit, fixed;
+};
+__device__ __forceinline__ CgCtl load_cg_ctl(const CgScalars* st) {
+  CgCtl c;
+  c.nc = st->kp + 1;
+  c.rho = (int)threadIdx.x < c.nc ? st->rho[threadIdx.x] : 0.0;
+  c.nB = st->nB;
+  c.tol = st->tol;
+  c.iter = st->iter;
+  c.limit = st->limit;
+  c.fixed = st->fixed;
+  return c;
+}
+
 // Finishes a CG update: the new ||r_c||^2 for columns 0..kp.  Applies the stop
 // test of the solve (joint Frobenius ratio of the recursive residual, or the
 // cap).
-__device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho) {
-  const int nc = st->kp + 1;
+__device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho, const CgCtl& k) {
+  const int nc = k.nc;
   if ((int)threadIdx.x < nc) st->rho[threadIdx.x] = new_rho[threadIdx.x];
   if (threadIdx.x == 0) {
-    const double nB = st->nB, tol = st->tol;
-    const int it = st->iter + 1, limit = st->limit, fixed = st->fixed;
+    const int it = k.iter + 1;
     double sum = 0.0;
     for (int c = 0; c < nc; ++c) sum += new_rho[c];
     const bool finite = isfinite(sum);
     if (!finite) st->numeric_error = 1;
-    const double ratio = nB > 0.0 ? sqrt(sum) / nB : 0.0;
+    const double ratio = k.nB > 0.0 ? sqrt(sum) / k.nB : 0.0;
     st->ratio = ratio;
     st->iter = it;
-    st->stop = (it >= limit) || (!fixed && ratio < tol) || !finite;
+    st->stop = (it >= k.limit) || (!k.fixed && ratio < k.tol) || !finite;
   }
+}
+__device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho) {
+  finish_update(st, new_rho, load_cg_ctl(st));
 }
 
 // Finishes a step-length computation from the three dot products of the
@@ -295,15 +301,15 @@ __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_r
 //   b_c = ||r_c - a_c q_c||^2 / rho_c = (rho_c - 2 a_c del_c + a_c^2 eta_c) / rho_c
 // (the same value Hestenes-Stiefel CG forms after the residual update; known
 // here one kernel earlier so the update kernel can also form p <- r + b p).
-__device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
+__device__ __forceinline__ void finish_step(CgScalars* st, const double* dots, const CgCtl& k) {
   __shared__ int s_bad;
-  const int nc = st->kp + 1;
+  const int nc = k.nc;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   const int c = threadIdx.x;
   if (c < nc) {
     const double g = dots[c], dl = dots[nc + c], et = dots[2 * nc + c];
-    const double rho = st->rho[c];
+    const double rho = k.rho;
     const double a = (g != 0.0) ? rho / g : 0.0;
     st->gam[c] = g;
     st->del[c] = dl;
@@ -319,6 +325,9 @@ __device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
     st->numeric_error = 1;
     st->stop = 1;
   }
+}
+__device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
+  finish_step(st, dots, load_cg_ctl(st));
 }
 
 // Finishes the initial residual R = B: rho_c = ||b_c||^2 (in shared memory).
@@ -501,11 +510,13 @@ hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, co
                             const float* Q, const double* qm, double* parts, uint32_t* cnts,
                             CgScalars* st, hipStream_t s);
 
+constexpr int kConvTile = 64;  // output tile side of the fused conv operator pass
+
 struct ConvDims {
   int H, W, ks;      // square odd kernel side
   int64_t D, ldD;    // D = H*W, ldD = D rounded up to 256
   int K;             // probe columns (column-major blocks of ldD elements)
-  int tilesX, tilesY;
+  int tilesX, tilesY;  // kConvTile x kConvTile output tiles
   int fp64;          // probe columns in float64 (else float32)
 };
 
@@ -523,6 +534,7 @@ struct ConvReduce {
 hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, void* X, void* R,
                      void* P, double* xm, double* rm, double* pm, const ConvReduce& red,
                      CgScalars* st, hipStream_t s);
+int64_t conv_pass_blocks(const ConvDims& cd);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,

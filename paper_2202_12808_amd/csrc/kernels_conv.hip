@@ -20,105 +20,225 @@
 
 namespace cofem {
 
-constexpr int kTile = 32;  // output tile side
-constexpr int kRB = 4;     // rows per thread (register blocking)
-
-template <int KS>
-struct ConvGeom {
-  static constexpr int c = (KS - 1) / 2;
-  static constexpr int stH = ((kTile + 2 * c + kRB - 1) / kRB) * kRB;  // rows of the Phi p buffer
-  static constexpr int stW = kTile + 2 * c;
-  static constexpr int spH = stH + 2 * c;  // rows of the p buffer
-  static constexpr int spW = kTile + 4 * c;
-};
-
 __device__ __forceinline__ int wrap(int x, int n) {
   x %= n;
   return x < 0 ? x + n : x;
 }
 
-// One (tile, column) of the fused operator pass, in precision T.
-template <int KS, typename T>
-__device__ __forceinline__ void conv_tile(const float* __restrict__ sTaps, int H, int W, int tu0,
-                                          int tv0, const T* __restrict__ P,
-                                          const T* __restrict__ R,
+// Geometry of one fused pass over a TILE x TILE output tile with KS x KS taps
+// (c = (KS-1)/2).  Stage 1 forms t = Phi p on the tile plus a c halo (TR x TR,
+// rounded up to 4x4 blocks) from p staged with a 2c halo (SPH x SPW); stage 2
+// forms Phi^T t on the tile.  Each thread computes 4x4 output blocks; a block
+// reads KS+3 rows of XW values (KS+3 rounded up to whole float4s).
+template <int KS, int TILE>
+struct ConvGeom {
+  static constexpr int c = (KS - 1) / 2;
+  static constexpr int TR = ((TILE + 2 * c + 3) / 4) * 4;
+  static constexpr int XW = ((KS + 3 + 3) / 4) * 4;
+  static constexpr int SPH = TR + 2 * c;
+  static constexpr int SPW = TR + XW - 4;
+  static constexpr int NB1 = (TR / 4) * (TR / 4);
+  static constexpr int NB2 = (TILE / 4) * (TILE / 4);
+  static constexpr int LDS = SPH * SPW + TR * TR;  // values
+};
+
+// Taps of the 4x4 blocks, read from LDS as broadcasts.  Each input row uses
+// at most 4 tap rows (4 KS values), which stay in registers for that row;
+// fence() is an empty asm that the compiler must assume changes the (zero)
+// index offset, so tap reads of later rows are neither merged with nor
+// hoisted above earlier ones (keeping all KS*KS taps live would crowd out the
+// accumulators and the double-buffered input rows).
+template <typename T>
+struct Taps {
+  const T* s;
+  int off = 0;  // always 0; laundered by fence() (the pointer itself is not, so
+                // the compiler still sees an LDS address and emits ds_read)
+  __device__ __forceinline__ explicit Taps(const T* p) : s(p) {}
+  __device__ __forceinline__ T operator()(int i) const { return s[i + off]; }
+  __device__ __forceinline__ void fence() { asm volatile("" : "+v"(off)); }
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void lds_row(const T* src, T (&x)[N]) {
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int q = 0; q < N / 4; ++q) {
+      const float4 v = reinterpret_cast<const float4*>(src)[q];
+      x[4 * q] = v.x;
+      x[4 * q + 1] = v.y;
+      x[4 * q + 2] = v.z;
+      x[4 * q + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) {
+      const double2 v = reinterpret_cast<const double2*>(src)[q];
+      x[2 * q] = v.x;
+      x[2 * q + 1] = v.y;
+    }
+  }
+}
+
+// One output tile of one column of the fused operator pass, in precision T:
+// q = beta Phi^T (Phi p) + alpha (.) p on the tile, written to Q, and the
+// thread's parts of gam = p^T q, del = r^T M^-1 q, eta = q^T M^-1 q.
+// `near` (uniform): every staged coordinate is within one period of the
+// image, so wrapping is a compare and an add.
+template <int KS, int TILE, typename T, typename TapsT>
+__device__ __forceinline__ void conv_tile(TapsT h, int H, int W, int tu0, int tv0, bool near,
+                                          const T* __restrict__ P, const T* __restrict__ R,
                                           const float* __restrict__ alpha, T beta,
-                                          const float* __restrict__ minv,
-                                          T* __restrict__ Q, T* sP, T* sT, double dots[3]) {
-  using G = ConvGeom<KS>;
+                                          const float* __restrict__ minv, T* __restrict__ Q, T* sP, T* sT,
+                                          double dots[3]) {
+  using G = ConvGeom<KS, TILE>;
   constexpr int c = G::c;
   const int tid = threadIdx.x;
-  // stage 0: p on the tile plus a 2c halo (circular wrap)
-  for (int e = tid; e < G::spH * G::spW; e += kThreads) {
-    const int i = e / G::spW, j = e - (e / G::spW) * G::spW;
-    const int u = wrap(tu0 - 2 * c + i, H), v = wrap(tv0 - 2 * c + j, W);
-    sP[e] = P[(int64_t)u * W + v];
-  }
-  __syncthreads();
-  // stage 1: t = Phi p on the tile plus a c halo
-  constexpr int nStrips = G::stH / kRB;
-  for (int item = tid; item < nStrips * G::stW; item += kThreads) {
-    const int j = item % G::stW;
-    const int i0 = (item / G::stW) * kRB;
-    T out[kRB];
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) out[r] = T(0);
-    // one column of taps per step (not unrolled): the taps come from LDS, so
-    // registers hold a strip and RB sums, not all KS*KS taps
-#pragma unroll 1
-    for (int b = 0; b < KS; ++b) {
-      // rows i0 + r - a + 2c for r in [0, RB), a in [0, KS)
-      T strip[kRB + KS - 1];
-#pragma unroll
-      for (int q = 0; q < kRB + KS - 1; ++q) strip[q] = sP[(i0 + q) * G::spW + (j - b + 2 * c)];
-#pragma unroll
-      for (int a = 0; a < KS; ++a) {
-        const T h = (T)sTaps[a * KS + b];
-#pragma unroll
-        for (int r = 0; r < kRB; ++r) out[r] += h * strip[r - a + KS - 1];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kRB; ++r) sT[(i0 + r) * G::stW + j] = out[r];
-  }
-  __syncthreads();
-  // stage 2: q = beta Phi^T t + alpha p on the tile
-  double g = 0.0, dl = 0.0, et = 0.0;
+  // stage 0: p on the tile plus a 2c halo (circular wrap).  Every load of
+  // the thread is issued before the first LDS store, so the staging costs
+  // about one memory latency, not one per element.
   {
-    const int j = tid % kTile;
-    const int i0 = (tid / kTile) * kRB;
-    T out[kRB];
+    constexpr int N0 = G::SPH * G::SPW, PER = (N0 + kThreads - 1) / kThreads;
+    T pv[PER];
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) out[r] = T(0);
-#pragma unroll 1
-    for (int b = 0; b < KS; ++b) {
-      T strip[kRB + KS - 1];
-#pragma unroll
-      for (int q = 0; q < kRB + KS - 1; ++q) strip[q] = sT[(i0 + q) * G::stW + j + b];
-#pragma unroll
-      for (int a = 0; a < KS; ++a) {
-        const T h = (T)sTaps[a * KS + b];
-#pragma unroll
-        for (int r = 0; r < kRB; ++r) out[r] += h * strip[r + a];
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * kThreads;
+      if (e < N0) {
+        const int i = e / G::SPW, j = e - (e / G::SPW) * G::SPW;
+        int u = tu0 - 2 * c + i, v = tv0 - 2 * c + j;
+        if (near) {
+          u = u < 0 ? u + H : (u >= H ? u - H : u);
+          v = v < 0 ? v + W : (v >= W ? v - W : v);
+        } else {
+          u = wrap(u, H);
+          v = wrap(v, W);
+        }
+        pv[k] = P[(int64_t)u * W + v];
       }
     }
-    const int v = tv0 + j;
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) {
-      const int u = tu0 + i0 + r;
-      if (u < H && v < W) {
-        const int64_t idx = (int64_t)u * W + v;
-        const T p = sP[(i0 + r + 2 * c) * G::spW + j + 2 * c];
-        const T q = beta * out[r] + (T)alpha[idx] * p;
-        Q[idx] = q;
-        const double qd = (double)q;
-        // with a diagonal preconditioner the step's dots are weighted by it:
-        // delta = r^T M^-1 q, eta = q^T M^-1 q
-        const double mq = minv ? (double)minv[idx] * qd : qd;
-        g += (double)p * qd;
-        dl += (double)R[idx] * mq;
-        et += qd * mq;
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * kThreads;
+      if (e < N0) sP[e] = pv[k];
+    }
+  }
+  __syncthreads();
+  // stage 1: t = Phi p on the tile plus a c halo, 4x4 blocks:
+  //   t(i, j) = sum_{a,b} h[a][b] sP(i - a + 2c, j - b + 2c)
+  for (int item = tid; item < G::NB1; item += kThreads) {
+    const int bi = item / (G::TR / 4), bj = item - (item / (G::TR / 4)) * (G::TR / 4);
+    T acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) acc[r][cc] = T(0);
+    // rows are double-buffered: row q + 1 is read from LDS while row q is
+    // used; the scheduling barrier keeps later rows' loads from being hoisted
+    // (which would hold every row in registers at once)
+    const T* src1 = sP + (4 * bi) * G::SPW + 4 * bj;
+    T x[2][G::XW];
+    lds_row(src1, x[0]);
+#pragma unroll
+    for (int q = 0; q < KS + 3; ++q) {  // input row 4 bi + q
+      h.fence();
+      if (q + 1 < KS + 3) lds_row(src1 + (q + 1) * G::SPW, x[(q + 1) & 1]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = r + 2 * c - q;
+        if (a < 0 || a >= KS) continue;
+#pragma unroll
+        for (int b = 0; b < KS; ++b) {
+          const T hv = h(a * KS + b);
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[r][cc] = fma(hv, x[q & 1][cc + 2 * c - b], acc[r][cc]);
+        }
       }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      T* dst = sT + (4 * bi + r) * G::TR + 4 * bj;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) dst[cc] = acc[r][cc];
+    }
+  }
+  __syncthreads();
+  // stage 2: q = beta Phi^T t + alpha p on the tile, 4x4 blocks:
+  //   (Phi^T t)(i, j) = sum_{a,b} h[a][b] t(i + a, j + b)
+  double g = 0.0, dl = 0.0, et = 0.0;
+  const int bi2 = tid / (TILE / 4), bj2 = tid - (tid / (TILE / 4)) * (TILE / 4);
+  T acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) acc[r][cc] = T(0);
+  if (tid < G::NB2) {
+    const int bi = bi2, bj = bj2;
+    const T* src2 = sT + (4 * bi) * G::TR + 4 * bj;
+    T x[2][G::XW];
+    lds_row(src2, x[0]);
+#pragma unroll
+    for (int q = 0; q < KS + 3; ++q) {  // t row 4 bi + q
+      h.fence();
+      if (q + 1 < KS + 3) lds_row(src2 + (q + 1) * G::TR, x[(q + 1) & 1]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = q - r;
+        if (a < 0 || a >= KS) continue;
+#pragma unroll
+        for (int b = 0; b < KS; ++b) {
+          const T hv = h(a * KS + b);
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[r][cc] = fma(hv, x[q & 1][cc + b], acc[r][cc]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();  // every thread is done reading t
+  if (tid < G::NB2) {
+    T* dst = sT + (4 * bi2) * TILE + 4 * bj2;  // Phi^T t of the tile, TILE x TILE
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) dst[r * TILE + cc] = acc[r][cc];
+  }
+  __syncthreads();
+  // epilogue, one output per thread per step (coalesced rows):
+  // q = beta Phi^T t + alpha p, and the dots.  The steps' loads are issued
+  // in groups of 8 before their uses.
+  constexpr int PER2 = TILE * TILE / kThreads, GRP = PER2 < 8 ? PER2 : 8;
+#pragma unroll
+  for (int k0 = 0; k0 < PER2; k0 += GRP) {
+    float al[GRP], mv[GRP];
+    T rv[GRP];
+    int64_t ix[GRP];
+    bool ok[GRP];
+#pragma unroll
+    for (int k = 0; k < GRP; ++k) {
+      const int e = tid + (k0 + k) * kThreads;
+      const int i = e / TILE, j = e - (e / TILE) * TILE;
+      const int u = tu0 + i, v = tv0 + j;
+      ok[k] = u < H && v < W;
+      ix[k] = (int64_t)u * W + v;
+      al[k] = ok[k] ? alpha[ix[k]] : 0.0f;
+      rv[k] = ok[k] ? R[ix[k]] : T(0);
+      mv[k] = (ok[k] && minv) ? minv[ix[k]] : 1.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < GRP; ++k) {
+      if (!ok[k]) continue;
+      const int e = tid + (k0 + k) * kThreads;
+      const int i = e / TILE, j = e - (e / TILE) * TILE;
+      const T p = sP[(i + 2 * c) * G::SPW + j + 2 * c];
+      const T q = beta * sT[e] + (T)al[k] * p;
+      Q[ix[k]] = q;
+      const double qd = (double)q;
+      // with a diagonal preconditioner the step's dots are weighted by it:
+      // delta = r^T M^-1 q, eta = q^T M^-1 q (mv = 1 without one)
+      const double mq = (double)mv[k] * qd;
+      g += (double)p * qd;
+      dl += (double)rv[k] * mq;
+      et += qd * mq;
     }
   }
   dots[0] = g;
@@ -126,28 +246,82 @@ __device__ __forceinline__ void conv_tile(const float* __restrict__ sTaps, int H
   dots[2] = et;
 }
 
+// Grid: x = 64 x 64 tile (in an order that gives each XCD a contiguous band
+// of tiles, so halo rows shared by neighbouring tiles stay in one L2),
+// z = column part.  z < 4: quadrant z of the float64 mean column; then S
+// parts per probe column (S = 1 for float columns, 4 quadrants in the float64
+// mode).  Column k's partial dots come from ntiles * S_k workgroups.
 template <int KS, typename TP>
-__global__ __launch_bounds__(256) void k_conv_pass(
-    const float* __restrict__ taps, int H, int W, int64_t ldD, int K, const TP* __restrict__ P,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_pass(
+    const float* __restrict__ taps, int H, int W, int64_t ldD, int K, int tilesX, const TP* __restrict__ P,
     const double* __restrict__ pm, const TP* __restrict__ R, const double* __restrict__ rm,
     const float* __restrict__ alpha, double beta, const float* __restrict__ minv, TP* __restrict__ Q,
-    double* __restrict__ qm, ConvReduce red, CgScalars* __restrict__ st, int apply_only) {
+    double* __restrict__ qm, ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
-  using G = ConvGeom<KS>;
-  __shared__ double sbuf[G::spH * G::spW + G::stH * G::stW];
-  __shared__ float sTaps[KS * KS];  // visible after the first barrier of conv_tile
-  if (threadIdx.x < KS * KS) sTaps[threadIdx.x] = taps[threadIdx.x];
-  const int col = blockIdx.z;
-  const int tu0 = blockIdx.y * kTile, tv0 = blockIdx.x * kTile;
-  double dots[3];
-  if (col == K) {
-    conv_tile<KS, double>(sTaps, H, W, tu0, tv0, pm, rm, alpha, beta, minv, qm, sbuf,
-                          sbuf + G::spH * G::spW, dots);
+  const CgCtl ctl = load_cg_ctl(st);
+  using G64 = ConvGeom<KS, kConvTile>;
+  using G32 = ConvGeom<KS, kConvTile / 2>;
+  constexpr int kS = sizeof(TP) == 8 ? 4 : 1;  // parts per probe column
+  // float64 columns (the mean, and every column in the float64 mode) take
+  // 32 x 32 quadrants; float columns 64 x 64 tiles
+  constexpr size_t kBytes = kS == 4 ? G32::LDS * sizeof(double)
+                                    : (G64::LDS * sizeof(float) > G32::LDS * sizeof(double) ? G64::LDS * sizeof(float)
+                                                                                             : G32::LDS * sizeof(double));
+  __shared__ __align__(16) unsigned char sbuf[kBytes];
+  __shared__ double sTapsD[KS * KS];
+  __shared__ float sTapsF[KS * KS];
+  if (threadIdx.x < KS * KS) {
+    sTapsD[threadIdx.x] = (double)taps[threadIdx.x];
+    sTapsF[threadIdx.x] = taps[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t ntiles = gridDim.x;
+  int64_t tile = blockIdx.x;
+  if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
+  const int ty = (int)(tile / tilesX), tx = (int)(tile - (tile / tilesX) * tilesX);
+  const int z = blockIdx.z;
+  int col, part, nparts;
+  if (z < 4) {
+    col = K;
+    part = z;
+    nparts = 4;
   } else {
-    TP* sb = reinterpret_cast<TP*>(sbuf);
+    col = (z - 4) / kS;
+    part = (z - 4) - col * kS;
+    nparts = kS;
+  }
+  int tu0 = ty * kConvTile, tv0 = tx * kConvTile;
+  double dots[3];
+  dots[0] = dots[1] = dots[2] = 0.0;
+  if (nparts == 4) {  // a float64 quadrant
+    tu0 += (part >> 1) * (kConvTile / 2);
+    tv0 += (part & 1) * (kConvTile / 2);
+  }
+  if (tu0 >= H || tv0 >= W) {
+    // a quadrant past the image edge: no outputs, zero dots (it still
+    // arrives at the reduction)
+  } else if (nparts == 4) {
+    const bool near = H >= G32::TR && W >= G32::SPW - 2 * G32::c;
+    double* sb = reinterpret_cast<double*>(sbuf);
+    Taps<double> hd(sTapsD);
+    if (col == K) {
+      conv_tile<KS, kConvTile / 2, double>(hd, H, W, tu0, tv0, near, pm, rm, alpha, beta, minv, qm, sb,
+                                           sb + G32::SPH * G32::SPW, dots);
+    } else {
+      const int64_t off = (int64_t)col * ldD;
+      conv_tile<KS, kConvTile / 2, double>(hd, H, W, tu0, tv0, near, reinterpret_cast<const double*>(P) + off,
+                                           reinterpret_cast<const double*>(R) + off, alpha, beta, minv,
+                                           reinterpret_cast<double*>(Q) + off, sb, sb + G32::SPH * G32::SPW,
+                                           dots);
+    }
+  } else if constexpr (kS == 1) {  // a float column's 64 x 64 tile
+    const bool near = H >= G64::TR && W >= G64::SPW - 2 * G64::c;
+    float* sb = reinterpret_cast<float*>(sbuf);
+    Taps<float> hf(sTapsF);
     const int64_t off = (int64_t)col * ldD;
-    conv_tile<KS, TP>(sTaps, H, W, tu0, tv0, P + off, R + off, alpha, (TP)beta, minv, Q + off, sb,
-                      sb + G::spH * G::spW, dots);
+    conv_tile<KS, kConvTile, float>(hf, H, W, tu0, tv0, near, reinterpret_cast<const float*>(P) + off,
+                                    reinterpret_cast<const float*>(R) + off, alpha, (float)beta, minv,
+                                    reinterpret_cast<float*>(Q) + off, sb, sb + G64::SPH * G64::SPW, dots);
   }
   if (apply_only) return;
   __shared__ double shm[8];
@@ -161,12 +335,10 @@ __global__ __launch_bounds__(256) void k_conv_pass(
     mine[2] = te;
   }
   __syncthreads();
-  const int64_t ntiles = (int64_t)gridDim.x * gridDim.y;
-  const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, tile, ntiles, col, K + 1, 3,
-                          mine, tot))
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, tile * nparts + part, ntiles * nparts,
+                          nblk_alloc, col, K + 1, 3, mine, tot))
     return;
-  finish_step(st, tot);
+  finish_step(st, tot, ctl);
 }
 
 template <typename TP>
@@ -174,14 +346,16 @@ static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const 
                                    const double* pm, const void* R, const double* rm,
                                    const float* alpha, double beta, const float* minv, void* Q, double* qm,
                                    const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
-  const dim3 grid(cd.tilesX, cd.tilesY, cd.K + 1);
+  constexpr int kS = sizeof(TP) == 8 ? 4 : 1;
+  const dim3 grid((unsigned)(cd.tilesX * cd.tilesY), 1, (unsigned)(4 + cd.K * kS));
   const TP* Pt = static_cast<const TP*>(P);
   const TP* Rt = static_cast<const TP*>(R);
   TP* Qt = static_cast<TP*>(Q);
-#define COFEM_CONV_CASE(KS)                                                                           \
-  case KS:                                                                                            \
-    hipLaunchKernelGGL((k_conv_pass<KS, TP>), grid, dim3(256), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K, Pt, \
-                       pm, Rt, rm, alpha, beta, minv, Qt, qm, red, st, apply_only);                   \
+  const int64_t nblk_alloc = conv_pass_blocks(cd);
+#define COFEM_CONV_CASE(KS)                                                                             \
+  case KS:                                                                                              \
+    hipLaunchKernelGGL((k_conv_pass<KS, TP>), grid, dim3(kThreads), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K,  \
+                       cd.tilesX, Pt, pm, Rt, rm, alpha, beta, minv, Qt, qm, red, nblk_alloc, st, apply_only); \
     break;
   switch (cd.ks) {
     COFEM_CONV_CASE(1)
@@ -204,6 +378,10 @@ hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const
     return launch_conv_pass<double>(cd, taps, P, pm, R, rm, alpha, beta, minv, Q, qm, red, st, apply_only, s);
   return launch_conv_pass<float>(cd, taps, P, pm, R, rm, alpha, beta, minv, Q, qm, red, st, apply_only, s);
 }
+
+// Workgroups whose partial dots one column of the operator pass may reduce
+// (the reduction workspace is sized for this many per column).
+int64_t conv_pass_blocks(const ConvDims& cd) { return 4 * (int64_t)cd.tilesX * cd.tilesY; }
 
 // ------------------------------------------------ b0 = beta Phi^T y (Eq. 5), float64
 __global__ void k_conv_b0(const float* __restrict__ taps, int ks, int H, int W, int64_t ldD,
@@ -293,22 +471,59 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
 
 // ------------------------------------------------ CG update
 // x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2 and the stop test.
+// One column of the update: x += a p; r -= a q; z = M^-1 r (z = r without
+// a preconditioner); p <- z + b p; returns r^T z and r^T r.  Each thread
+// takes four elements per round, all loaded before any is used (one memory
+// latency per round instead of one per element); the sums run in the same
+// element order as a one-element loop.
+template <typename T>
+__device__ __forceinline__ void conv_update_col(int64_t D, T* __restrict__ X, T* __restrict__ R,
+                                                T* __restrict__ P, const T* __restrict__ Q,
+                                                const float* __restrict__ minv, T a, T b, double* rz, double* rr) {
+  constexpr int U = 4;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t d0 = gtid; d0 < D; d0 += U * gstride) {
+    T pv[U], xv[U], rv[U], qv[U];
+    float mv[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t d = d0 + k * gstride;
+      if (d < D) {
+        pv[k] = P[d];
+        xv[k] = X[d];
+        rv[k] = R[d];
+        qv[k] = Q[d];
+        mv[k] = minv ? minv[d] : 1.0f;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int64_t d = d0 + k * gstride;
+      if (d < D) {
+        X[d] = fma(a, pv[k], xv[k]);
+        const T r = fma(-a, qv[k], rv[k]);
+        R[d] = r;
+        const T z = minv ? (T)mv[k] * r : r;
+        P[d] = fma(b, pv[k], z);
+        s0 += (double)r * (double)z;
+        s1 += (double)r * (double)r;
+      }
+    }
+  }
+  *rz = s0;
+  *rr = s1;
+}
+
+// x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2
 template <typename T>
 __device__ __forceinline__ double conv_update_column(int64_t D, T* __restrict__ X, T* __restrict__ R,
                                                      T* __restrict__ P, const T* __restrict__ Q,
                                                      T a, T b) {
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
-  double acc = 0.0;
-  for (int64_t d = gtid; d < D; d += gstride) {
-    const T p = P[d];
-    X[d] = fma(a, p, X[d]);
-    const T r = fma(-a, Q[d], R[d]);
-    R[d] = r;
-    P[d] = fma(b, p, r);
-    acc += (double)r * (double)r;
-  }
-  return acc;
+  double rz, rr;
+  conv_update_col<T>(D, X, R, P, Q, nullptr, a, b, &rz, &rr);
+  return rr;
 }
 
 template <typename TP>
@@ -435,21 +650,7 @@ __device__ __forceinline__ void conv_update_pcg_column(int64_t D, T* __restrict_
                                                        T* __restrict__ P, const T* __restrict__ Q,
                                                        const float* __restrict__ minv, T a, T b, double* rz,
                                                        double* rr) {
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t d = gtid; d < D; d += gstride) {
-    const T p = P[d];
-    X[d] = fma(a, p, X[d]);
-    const T r = fma(-a, Q[d], R[d]);
-    R[d] = r;
-    const T z = minv ? (T)minv[d] * r : r;
-    P[d] = fma(b, p, z);
-    s0 += (double)r * (double)z;
-    s1 += (double)r * (double)r;
-  }
-  *rz = s0;
-  *rr = s1;
+  conv_update_col<T>(D, X, R, P, Q, minv, a, b, rz, rr);
 }
 
 template <typename TP>

@@ -372,7 +372,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass1(
   double vm;
   wg_reduce32<kGemmWaves>(acc, accm, &v, &vm);
   const int64_t row0 = tile * 32;
-  if (!split_reduce32(nsplit, split, row0, Np, Wpart, wmpart, &cnts[tile], &v, &vm)) return;
+  if (!split_reduce32(nsplit, split, row0, Np, Wpart, wmpart, &cnts[tile * kCounterStride], &v, &vm)) return;
   if (threadIdx.x < 256) reinterpret_cast<float4*>(W)[tile_f4(row0, threadIdx.x)] = v;
   if (threadIdx.x < 32) wm[row0 + threadIdx.x] = vm;
 }
@@ -410,6 +410,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
     double* __restrict__ parts, uint32_t* __restrict__ cnts, uint32_t* __restrict__ split_cnts,
     CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
+  const CgCtl ctl = load_cg_ctl(st);
   constexpr int nc = kDenseKP + 1;
   const int64_t tile = blockIdx.x;
   const int split = blockIdx.y;
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
   double vm;
   wg_reduce32<kGemmWaves>(acc, accm, &v, &vm);
   const int64_t d0 = tile * 32;
-  if (!split_reduce32(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[tile], &v, &vm)) return;
+  if (!split_reduce32(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[tile * kCounterStride], &v, &vm)) return;
 
   __shared__ double sdots[3][256];
   __shared__ double mine[3 * nc], tot[3 * nc];
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
   }
   __syncthreads();
   if (!tree_reduce(parts, cnts, tile, gridDim.x, 3 * nc, mine, tot)) return;
-  finish_step(st, tot);
+  finish_step(st, tot, ctl);
 }
 
 hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, const double* wm,
@@ -536,48 +537,74 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
                                                       const double* __restrict__ qm,
                                                       double* __restrict__ parts, uint32_t* cnts,
                                                       CgScalars* st) {
-  if (st->stop) return;
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
+  const int64_t n4 = Dp * 8;
+  // Elements go two per round, both rounds' loads issued before any use.  The
+  // first round's state is loaded together with the scalars and the stop flag
+  // (all in bounds), so the flag's latency hides under the data's; the flag
+  // only decides whether anything is written.
+  float4 x[2], r[2], p[2], q[2];
+  auto load2 = [&](int64_t e4) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t e = e4 + u * gstride;
+      if (e < n4) {
+        x[u] = reinterpret_cast<float4*>(X)[e];
+        r[u] = reinterpret_cast<float4*>(R)[e];
+        p[u] = reinterpret_cast<float4*>(P)[e];
+        q[u] = reinterpret_cast<const float4*>(Q)[e];
+      }
+    }
+  };
+  load2(gtid);
+  const CgCtl ctl = load_cg_ctl(st);
+  const int stop = st->stop;
   const float a = (float)st->a[c], b = (float)st->b[c];
   const double am = st->a[kDenseKP], bmm = st->b[kDenseKP];
+  if (stop) return;
   double acc = 0.0;
-  for (int64_t e4 = gtid; e4 < Dp * 8; e4 += gstride) {
-    float4 x = reinterpret_cast<float4*>(X)[e4];
-    float4 r = reinterpret_cast<float4*>(R)[e4];
-    float4 p = reinterpret_cast<float4*>(P)[e4];
-    const float4 q = reinterpret_cast<const float4*>(Q)[e4];
-    x.x = fmaf(a, p.x, x.x);
-    x.y = fmaf(a, p.y, x.y);
-    x.z = fmaf(a, p.z, x.z);
-    x.w = fmaf(a, p.w, x.w);
-    r.x = fmaf(-a, q.x, r.x);
-    r.y = fmaf(-a, q.y, r.y);
-    r.z = fmaf(-a, q.z, r.z);
-    r.w = fmaf(-a, q.w, r.w);
-    p.x = fmaf(b, p.x, r.x);
-    p.y = fmaf(b, p.y, r.y);
-    p.z = fmaf(b, p.z, r.z);
-    p.w = fmaf(b, p.w, r.w);
-    reinterpret_cast<float4*>(X)[e4] = x;
-    reinterpret_cast<float4*>(R)[e4] = r;
-    reinterpret_cast<float4*>(P)[e4] = p;
-    acc += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+  for (int64_t e4 = gtid; e4 < n4; e4 += 2 * gstride) {
+    if (e4 != gtid) load2(e4);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t e = e4 + u * gstride;
+      if (e < n4) {
+        float4 xv = x[u], rv = r[u], pv = p[u];
+        const float4 qv = q[u];
+        xv.x = fmaf(a, pv.x, xv.x);
+        xv.y = fmaf(a, pv.y, xv.y);
+        xv.z = fmaf(a, pv.z, xv.z);
+        xv.w = fmaf(a, pv.w, xv.w);
+        rv.x = fmaf(-a, qv.x, rv.x);
+        rv.y = fmaf(-a, qv.y, rv.y);
+        rv.z = fmaf(-a, qv.z, rv.z);
+        rv.w = fmaf(-a, qv.w, rv.w);
+        pv.x = fmaf(b, pv.x, rv.x);
+        pv.y = fmaf(b, pv.y, rv.y);
+        pv.z = fmaf(b, pv.z, rv.z);
+        pv.w = fmaf(b, pv.w, rv.w);
+        reinterpret_cast<float4*>(X)[e] = xv;
+        reinterpret_cast<float4*>(R)[e] = rv;
+        reinterpret_cast<float4*>(P)[e] = pv;
+        acc += (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z + (double)rv.w * rv.w;
+      }
+    }
   }
   double accm = 0.0;
   for (int64_t d = gtid; d < Dp; d += gstride) {
-    const double p = pm[d];
-    xm[d] = fma(am, p, xm[d]);
-    const double r = fma(-am, qm[d], rm[d]);
-    rm[d] = r;
-    pm[d] = fma(bmm, p, r);
-    accm += r * r;
+    const double pv = pm[d];
+    xm[d] = fma(am, pv, xm[d]);
+    const double rv = fma(-am, qm[d], rm[d]);
+    rm[d] = rv;
+    pm[d] = fma(bmm, pv, rv);
+    accm += rv * rv;
   }
   __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
   dense_block_sums(acc, accm, mine);
   if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + 1, mine, tot)) return;
-  finish_update(st, tot);
+  finish_update(st, tot, ctl);
 }
 
 __global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restrict__ X,

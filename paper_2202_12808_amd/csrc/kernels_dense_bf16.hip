@@ -318,7 +318,7 @@ __device__ __forceinline__ void dense16_pass1_body(
   double vm = 0.0;
   wg_reduce_x2<kG16Waves>(acc, accm, &v, &vm);
   const int64_t row0 = pair * 64;
-  if (!split_reduce_x2(nsplit, split, row0, Np, Wpart, wmpart, &cnts[pair], &v, &vm)) return;
+  if (!split_reduce_x2(nsplit, split, row0, Np, Wpart, wmpart, &cnts[pair * kCounterStride], &v, &vm)) return;
   const int tt = threadIdx.x >> 8, ee = threadIdx.x & 255;
   reinterpret_cast<float4*>(W)[tile_f4_16(row0 + 32 * tt, ee)] = v;
   if (ee < 32) wm[row0 + 32 * tt + ee] = vm;
@@ -344,6 +344,7 @@ __device__ __forceinline__ void dense16_pass2_body(
     float* __restrict__ Q, double* __restrict__ qm, double* __restrict__ parts, uint32_t* __restrict__ cnts,
     uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
+  const CgCtl ctl = load_cg_ctl(st);
   constexpr int nc = kDenseKP + 1;
   const int64_t g0 = split * gps;
   const int64_t g1 = (g0 + gps < G2) ? g0 + gps : G2;
@@ -357,7 +358,7 @@ __device__ __forceinline__ void dense16_pass2_body(
   double vm = 0.0;
   wg_reduce_x2<kG16Waves>(acc, accm, &v, &vm);
   const int64_t d0 = pair * 64;
-  if (!split_reduce_x2(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[pair], &v, &vm)) return;
+  if (!split_reduce_x2(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[pair * kCounterStride], &v, &vm)) return;
 
   __shared__ double sdots[3][512];
   __shared__ double smean[3][64];
@@ -410,7 +411,7 @@ __device__ __forceinline__ void dense16_pass2_body(
   }
   __syncthreads();
   if (!tree_reduce(parts, cnts, pair, npairs, 3 * nc, mine, tot)) return;
-  finish_step(st, tot);
+  finish_step(st, tot, ctl);
 }
 
 template <int RING>
