@@ -68,7 +68,7 @@ KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "u
 FORMS = {"fp32": "fp32 probes + fp64 mean column",
          "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column)",
          "control": "fp32 CG started from the previous mean and diagonal estimate, Jacobi-preconditioned",
-         "learned": "fp32 CG started from a learned prediction with its learned diagonal preconditioner"}
+         "learned": "fp32 CG started from a learned prediction, Jacobi-preconditioned"}
 CONV_FORMS = ("fp32", "control", "learned")
 KERNEL_SOURCES = {"dense": ("paper_2202_12808_amd/csrc/kernels_dense.hip", "paper_2202_12808_amd/csrc/cofem_internal.h"),
                   "dense_bf16_ir": ("paper_2202_12808_amd/csrc/kernels_dense_bf16.hip",

@@ -1,13 +1,13 @@
-"""Float64 CPU oracle of the learned warm start and diagonal preconditioner.
+"""Float64 CPU oracle of the learned warm start.
 
 TEST INFRASTRUCTURE ONLY: used by ``tests/`` (gradient checks of the GPU
 training kernels); never by the HIP product path.
 
 This part is not in the paper.  It is a small fully convolutional network on
 the image grid of a convolution dictionary.  From the state before EM
-iteration t, it predicts a start for the CG solve of that E-step and a
-diagonal preconditioner.  The solve's own stop rule then judges the
-prediction (Sec. 3.2).
+iteration t, it predicts a start for the CG solve of that E-step, which runs
+preconditioned by the Jacobi diagonal of A.  The solve's own stop rule then
+judges the prediction (Sec. 3.2).
 
 Definitions (shared with the GPU kernels by specification, not by code):
 
@@ -17,17 +17,19 @@ Definitions (shared with the GPU kernels by specification, not by code):
     f1 = mu_{t-1} / rms(mu_{t-1})          (rms over the image; 1 if it is 0)
     f2 = log(clip(s_{t-1} d, 1e-3, 1e3)) / 3
     f3 = log(d / (beta ||h||^2)) / 10
-  aux (2 channels): mu_{t-1}, d.
+  aux (3 channels): mu_{t-1}, d, sb = clip(s_{t-1} d, 0.05, 20).
 * network: four 3x3 convolutions with circular padding, 4 -> 32 -> 32 -> 32 -> 2
   channels, ReLU after the first three; out[co][u][v] = b[co] +
   sum_{ci,ky,kx} w[co][ci][ky][kx] x[ci][(u+ky-1) mod H][(v+kx-1) mod W].
-* prediction: mu_hat = mu_{t-1} (1 + tanh(o0)),  d_hat = exp(clip(o1, -10, 10)) / d;
-  the solve starts from X0 = [d_hat (.) p_k | mu_hat] with M^-1 = diag(d_hat).
-  All-zero output gives mu_hat = mu_{t-1} and d_hat = 1/d (the Jacobi
-  diagonal).
+* prediction: mu_hat = mu_{t-1} (1 + tanh(o0)),  d_hat = exp(clip(o1, -10, 10)) sb / d;
+  the solve starts from X0 = [d_hat (.) p_k | mu_hat] with M^-1 = 1/d (the
+  Jacobi diagonal; d_hat estimates diag(Sigma), which as a preconditioner
+  needs more iterations).  All-zero output gives mu_hat = mu_{t-1} and
+  d_hat = clip(s_{t-1} d, 0.05, 20) / d, i.e. the previous iterate, the
+  non-learned warm start: the network learns corrections to it.
 * loss against the E-step's result (mu_t, s_t):
     L = sum (mu_hat - mu_t)^2 / sum mu_t^2
-        + LAMBDA_D * mean (o1 - log(clip(s_t d, 0.05, 20)))^2.
+        + LAMBDA_D * mean (o1 - log(clip(s_t d, 0.05, 20) / sb))^2.
 * parameters, flattened: for each layer w (Cout x Cin x 3 x 3, row-major),
   then b (Cout).
 
@@ -78,7 +80,7 @@ def conv3(x, w, b):
 
 
 def features(alpha, mu_prev, s_prev, beta, hh, H, W):
-    """(feats [4,H,W], aux [2,H,W]) from the state before an E-step."""
+    """(feats [4,H,W], aux [3,H,W]) from the state before an E-step."""
     alpha = np.asarray(alpha, np.float64).reshape(H, W)
     mu = np.asarray(mu_prev, np.float64).reshape(H, W)
     s = np.asarray(s_prev, np.float64).reshape(H, W)
@@ -87,7 +89,7 @@ def features(alpha, mu_prev, s_prev, beta, hh, H, W):
     rms = rms if rms > 0.0 else 1.0
     f = np.stack([alpha / d, mu / rms, np.log(np.clip(s * d, 1e-3, 1e3)) / 3.0,
                   np.log(d / (beta * hh)) / 10.0])
-    return f, np.stack([mu, d])
+    return f, np.stack([mu, d, np.clip(s * d, 0.05, 20.0)])
 
 
 def forward(theta, feats, channels=CHANNELS):
@@ -104,21 +106,21 @@ def forward(theta, feats, channels=CHANNELS):
 
 
 def predict(out, aux):
-    """(mu_hat, d_hat) from the network output and aux = [mu_prev, d]."""
+    """(mu_hat, d_hat) from the network output and aux = [mu_prev, d, sb]."""
     mu_hat = aux[0] * (1.0 + np.tanh(out[0]))
-    d_hat = np.exp(np.clip(out[1], -10.0, 10.0)) / aux[1]
+    d_hat = np.exp(np.clip(out[1], -10.0, 10.0)) * aux[2] / aux[1]
     return mu_hat, d_hat
 
 
 def loss_and_grad_out(out, aux, targets):
     """Loss L and dL/d(out) for targets = [mu_t, s_t]."""
-    mu_p, d = aux
+    mu_p, d, sb = aux
     mu_t, s_t = targets
     th = np.tanh(out[0])
     e = mu_p * (1.0 + th) - mu_t
     nrm = float(np.sum(mu_t * mu_t))
     nrm = nrm if nrm > 0.0 else 1.0
-    tgt = np.log(np.clip(s_t * d, 0.05, 20.0))
+    tgt = np.log(np.clip(s_t * d, 0.05, 20.0) / sb)
     r = out[1] - tgt
     n = out[0].size
     L = float(np.sum(e * e)) / nrm + LAMBDA_D * float(np.mean(r * r))

@@ -92,6 +92,7 @@ _SIGNATURES = {
     "cofem_net_set_params": (c_int32, [c_void_p, c_void_p, c_int64]),
     "cofem_net_get_params": (c_int32, [c_void_p, c_void_p, c_int64]),
     "cofem_net_forward": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "cofem_net_forward_bf16": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "cofem_net_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "cofem_net_train_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float, POINTER(c_double)]),
     "cofem_features": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -356,10 +357,10 @@ class CoFEM:
         return cofem_time_operator(self.ctx, reps)
 
     def features(self, net):
-        """(feats [4, H*W], aux [2, H*W]) of the next E-step (convolution only)."""
+        """(feats [4, H*W], aux [3, H*W]) of the next E-step (convolution only)."""
         import torch
         feats = torch.empty((4, self.D), dtype=torch.float32, device=self.device)
-        aux = torch.empty((2, self.D), dtype=torch.float32, device=self.device)
+        aux = torch.empty((3, self.D), dtype=torch.float32, device=self.device)
         _check(load().cofem_features(self.ctx, net.net, _ptr(feats), _ptr(aux)), self.ctx)
         return feats, aux
 
@@ -506,6 +507,13 @@ class CoFEMNet:
         import torch
         out = torch.empty((2, self.H * self.W), dtype=torch.float32, device=feats.device)
         _check(load().cofem_net_forward(self.net, _ptr(feats.contiguous()), _ptr(out)))
+        return out
+
+    def forward_bf16(self, feats):
+        """The predictor's forward pass (bfloat16 MFMA, float32 accumulation)."""
+        import torch
+        out = torch.empty((2, self.H * self.W), dtype=torch.float32, device=feats.device)
+        _check(load().cofem_net_forward_bf16(self.net, _ptr(feats.contiguous()), _ptr(out)))
         return out
 
     def loss_grad(self, feats, aux, targets):

@@ -712,11 +712,16 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
   bool start = false;
   c->active_minv = nullptr;
   if (c->predictor && c->has_solution) {
-    // learned: X0 = [d (.) p_k | mu_hat], M^-1 = diag(d) from the network
+    // learned: X0 = [d (.) p_k | mu_hat] from the network, M^-1 = Jacobi.
+    // (The network's diagonal estimate d tracks diag(Sigma); as a
+    // preconditioner it, and blends of it with the Jacobi diagonal, need more
+    // iterations than the Jacobi diagonal, most of all right after the first
+    // M-step, so it serves only as the probe columns' start.)
     COFEM_TRY(c->predictor(c, c->predictor_user, c->d0, c->mu0));
+    COFEM_HIP(c, conv_jacobi(cd, c->taps, c->beta, c->alpha, c->minv, c->stream));
     d0 = c->d0;
     mu0 = c->mu0;
-    c->active_minv = c->d0;
+    c->active_minv = c->minv;
     start = true;
   } else {
     if (c->flags & COFEM_FLAG_JACOBI) {

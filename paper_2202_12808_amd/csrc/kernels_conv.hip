@@ -50,12 +50,16 @@ struct ConvGeom {
 // accumulators and the double-buffered input rows).
 template <typename T>
 struct Taps {
-  const T* s;
-  int off = 0;  // always 0; laundered by fence() (the pointer itself is not, so
-                // the compiler still sees an LDS address and emits ds_read)
-  __device__ __forceinline__ explicit Taps(const T* p) : s(p) {}
-  __device__ __forceinline__ T operator()(int i) const { return s[i + off]; }
-  __device__ __forceinline__ void fence() { asm volatile("" : "+v"(off)); }
+  typedef __attribute__((address_space(3))) const T* lds_ptr;
+  lds_ptr s;     // the taps in LDS (an LDS-typed pointer, so reads stay ds_read)
+  lds_ptr base;  // s laundered by fence(): one address register per input
+                 // row, the row's tap reads use immediate offsets from it
+  __device__ __forceinline__ explicit Taps(const T* p) : s((lds_ptr)p), base((lds_ptr)p) {}
+  __device__ __forceinline__ T operator()(int i) const { return base[i]; }
+  __device__ __forceinline__ void fence() {
+    base = s;
+    asm volatile("" : "+v"(base));
+  }
 };
 
 template <typename T, int N>

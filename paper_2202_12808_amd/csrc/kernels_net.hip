@@ -1,10 +1,10 @@
-// Learned warm start and diagonal preconditioner for convolution
-// dictionaries (the learned form; not in the paper).  A small fully
-// convolutional network on the image grid, trained on the GPU by the kernels
-// below.  Before EM iteration t it reads the state: alpha_t, the previous mean
-// and the previous diagonal estimate.  It predicts a start for that E-step's
-// CG solve and a diagonal M^-1; the solve's unchanged stop rule (Sec. 3.2)
-// then corrects and judges the prediction.
+// Learned warm start for convolution dictionaries (the learned form; not in
+// the paper).  A small fully convolutional network on the image grid, trained
+// on the GPU by the kernels below.  Before EM iteration t it reads the state:
+// alpha_t, the previous mean and the previous diagonal estimate.  It predicts
+// a start for that E-step's CG solve (run with the Jacobi preconditioner); the
+// solve's unchanged stop rule (Sec. 3.2) then corrects and judges the
+// prediction.
 //
 // Definitions (features, network, prediction, loss):
 //   d = beta ||h||^2 + alpha (the diagonal of A); features
@@ -13,9 +13,12 @@
 //   four 3x3 convolutions with circular padding, 4 -> 32 -> 32 -> 32 -> 2
 //   channels, ReLU after the first three,
 //     out[co][u][v] = b[co] + sum w[co][ci][ky][kx] x[ci][(u+ky-1) mod H][(v+kx-1) mod W];
-//   mu_hat = mu_prev (1 + tanh o0), d_hat = exp(clip(o1, -10, 10)) / d;
+//   with sb = clip(s_prev d, 0.05, 20):
+//   mu_hat = mu_prev (1 + tanh o0), d_hat = exp(clip(o1, -10, 10)) sb / d;
 //   loss = sum (mu_hat - mu_t)^2 / sum mu_t^2
-//          + 0.1 mean (o1 - log(clip(s_t d, 0.05, 20)))^2.
+//          + 0.1 mean (o1 - log(clip(s_t d, 0.05, 20) / sb))^2.
+// The untrained network (zero last layer) reproduces the previous iterate,
+// so training learns corrections to the non-learned warm start.
 // Activations are channel-major float32 images; sums of the loss and of the
 // weight gradients are deterministic (fixed-order partials).
 #include "cofem.h"
@@ -108,6 +111,108 @@ static hipError_t net_conv3(const float* in, int cin, const float* w, const floa
     hipLaunchKernelGGL(k_net_conv3<2>, dim3(gx, gy, (unsigned)((cout + 1) / 2)), dim3(256), 0, s, in, cin, w, b, out,
                        cout, H, W, relu, mask);
   return hipGetLastError();
+}
+
+// ------------------------------------------------ inference on bfloat16 MFMA
+// The predictor's forward pass, one layer per launch, as implicit GEMMs on
+// v_mfma_f32_32x32x16_bf16: for a row segment of 32 pixels,
+//   out[co][pixel] = b[co] + sum_k Wk[co][k] X[k][pixel],
+// k = tap * CP + ci (tap = 3 ky + kx, channels padded to CP = 8 or 32), K
+// padded to a multiple of 16 with zero weights, output channels padded to 32
+// with zero weights.  Weights and activations are rounded to bfloat16 (RNE);
+// products accumulate in float32; activations stay float32 in HBM.  A
+// workgroup stages a 16 x 32 pixel tile plus a one-pixel circular halo in LDS
+// as bfloat16, pixel-major with CP channels per pixel, so a lane's eight
+// consecutive k are one 16-byte LDS read (the B operand); each wave holds the
+// layer's whole weight matrix in registers (the A operand: lane l has output
+// channel l % 32, k = 16 s + 8 (l / 32) .. +7 of step s) and computes 4 rows.
+constexpr int kMR = 16;  // tile rows (4 per wave)
+constexpr int kMC = 32;  // tile columns: one MFMA column block
+
+template <int CP>
+struct MfmaGeom {
+  static constexpr int KP = ((9 * CP + 15) / 16) * 16;  // padded reduction length
+  static constexpr int NS = KP / 16;                      // MFMA steps
+};
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// wb[co][k] = bf16(w[co][ci][ky][kx]) for co < cout, tap = 3 ky + kx < 9,
+// ci < cin (k = tap CP + ci); zero elsewhere; 32 rows of KP.
+__global__ void k_net_pack_bf16(const float* __restrict__ w, int cin, int cout, int CP, int KP,
+                                uint16_t* __restrict__ wb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 32 * KP) return;
+  const int co = idx / KP, k = idx - (idx / KP) * KP;
+  const int tap = k / CP, ci = k - (k / CP) * CP;
+  const float v = (co < cout && tap < 9 && ci < cin) ? w[((int64_t)co * cin + ci) * 9 + tap] : 0.0f;
+  wb[idx] = (uint16_t)bf16_rne_bits(v);
+}
+
+template <int CP>
+__global__ __launch_bounds__(256) void k_net_conv3_mfma(const float* __restrict__ in, int cin,
+                                                        const uint16_t* __restrict__ wb, const float* __restrict__ b,
+                                                        float* __restrict__ out, int cout, int H, int W, int relu) {
+  using G = MfmaGeom<CP>;
+  constexpr int SW = kMC + 2, NPIX = (kMR + 2) * SW, NOCT = CP / 8;
+  __shared__ __align__(16) uint16_t s_x[NPIX * CP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int v0 = blockIdx.x * kMC, u0 = blockIdx.y * kMR;
+  const int64_t HW = (int64_t)H * W;
+  uint4 a[G::NS];
+#pragma unroll
+  for (int st = 0; st < G::NS; ++st)
+    a[st] = *reinterpret_cast<const uint4*>(wb + (lane & 31) * G::KP + 16 * st + 8 * (lane >> 5));
+  // stage: each item is one pixel's octet of channels (8 loads, one 16-byte store)
+  for (int e = threadIdx.x; e < NPIX * NOCT; e += blockDim.x) {
+    const int o = e / NPIX, pix = e - (e / NPIX) * NPIX;
+    const int i = pix / SW, j = pix - (pix / SW) * SW;
+    const int64_t src = (int64_t)nwrap(u0 + i - 1, H) * W + nwrap(v0 + j - 1, W);
+    uint32_t wd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c0 = 8 * o + 2 * q;
+      const uint32_t lo = c0 < cin ? bf16_rne_bits(in[(int64_t)c0 * HW + src]) : 0u;
+      const uint32_t hi = c0 + 1 < cin ? bf16_rne_bits(in[(int64_t)(c0 + 1) * HW + src]) : 0u;
+      wd[q] = lo | (hi << 16);
+    }
+    *reinterpret_cast<uint4*>(s_x + pix * CP + 8 * o) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+  }
+  __syncthreads();
+  const int j = lane & 31, h = lane >> 5;
+  const int v = v0 + j;
+#pragma unroll 1
+  for (int r = 0; r < kMR / 4; ++r) {
+    const int i = wave * (kMR / 4) + r;  // tile row
+    floatx16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int st = 0; st < G::NS; ++st) {
+      const int k0 = 16 * st + 8 * h;
+      int tap = k0 / CP;
+      const int ci0 = k0 - tap * CP;
+      if (tap >= 9) tap = 0;  // padding k: zero weights, any staged value
+      const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+      const uint4 bx = *reinterpret_cast<const uint4*>(s_x + ((i + ky) * SW + j + kx) * CP + ci0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[st]),
+                                                    __builtin_bit_cast(bf16x8, bx), acc, 0, 0, 0);
+    }
+    const int u = u0 + i;
+    if (u < H && v < W) {
+      const int64_t pxo = (int64_t)u * W + v;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int co = 8 * (q >> 2) + 4 * h + (q & 3);  // row of the 32 x 32 result
+        if (co < cout) {
+          float o = acc[q] + b[co];
+          if (relu) o = fmaxf(o, 0.0f);
+          out[(int64_t)co * HW + pxo] = o;
+        }
+      }
+    }
+  }
 }
 
 // wt[ci][co][ky][kx] = w[co][ci][2-ky][2-kx]: the backward data pass is the
@@ -219,13 +324,13 @@ __global__ __launch_bounds__(256) void k_net_loss_grad(const float* __restrict__
   double a = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += (int64_t)gridDim.x * blockDim.x) {
     const double o0 = out[p], o1 = out[HW + p];
-    const double mp = aux[p], d = aux[HW + p];
+    const double mp = aux[p], d = aux[HW + p], sb = aux[2 * HW + p];
     const double mt = tgt[p], st = tgt[HW + p];
     const double th = tanh(o0);
     const double e = mp * (1.0 + th) - mt;
     double sd = st * d;
     sd = sd < 0.05 ? 0.05 : (sd > 20.0 ? 20.0 : sd);
-    const double r = o1 - log(sd);
+    const double r = o1 - log(sd / sb);
     a += e * e / nr + kNetLambdaD * r * r / (double)HW;
     g[p] = (float)(2.0 * e * mp * (1.0 - th * th) / nr);
     g[HW + p] = (float)(2.0 * kNetLambdaD * r / (double)HW);
@@ -278,9 +383,12 @@ __global__ void k_net_features(const float* __restrict__ alpha, const double* __
   feats[3 * HW + p] = (float)(log(d / bh) / 10.0);
   aux[p] = (float)mu[p];
   aux[HW + p] = (float)d;
+  double sb = (double)s[p] * d;
+  sb = sb < 0.05 ? 0.05 : (sb > 20.0 ? 20.0 : sb);
+  aux[2 * HW + p] = (float)sb;
 }
 
-// mu0 = mu_prev (1 + tanh o0) (float64, from the exact previous mean), d0 = exp(clip(o1)) / d
+// mu0 = mu_prev (1 + tanh o0) (float64, from the exact previous mean), d0 = exp(clip(o1)) sb / d
 __global__ void k_net_predict(const float* __restrict__ out, const double* __restrict__ mu_prev,
                               const float* __restrict__ aux, int64_t HW, float* __restrict__ d0,
                               double* __restrict__ mu0) {
@@ -290,7 +398,7 @@ __global__ void k_net_predict(const float* __restrict__ out, const double* __res
   double o1 = out[HW + p];
   o1 = o1 < -10.0 ? -10.0 : (o1 > 10.0 ? 10.0 : o1);
   mu0[p] = mu_prev[p] * (1.0 + tanh(o0));
-  d0[p] = (float)(exp(o1) / (double)aux[HW + p]);
+  d0[p] = (float)(exp(o1) * (double)aux[2 * HW + p] / (double)aux[HW + p]);
 }
 
 }  // namespace cofem
@@ -306,6 +414,7 @@ struct cofem_net {
   float* act[kNetLayers + 1] = {};  // act[0] = features, act[4] = output
   float *g0 = nullptr, *g1 = nullptr, *wt = nullptr, *wpart = nullptr;
   float *feats = nullptr, *aux = nullptr;  // predictor scratch
+  uint16_t* wbf = nullptr;                 // bfloat16 weights of the MFMA forward pass
   double *dpart = nullptr, *dscal = nullptr;
   int step = 0;
   int nred = 0;  // blocks of the reductions
@@ -355,7 +464,7 @@ int64_t layer_offset(int l) {
 
 // He-normal initial weights (std sqrt(2 / (9 cin))), zero biases, and a
 // last layer of zeros: the untrained network predicts the previous mean and
-// the Jacobi diagonal.  Normals from a counter-based SplitMix64 stream
+// the previous diagonal estimate (clipped).  Normals from a counter-based SplitMix64 stream
 // (Box-Muller), seeded by `seed`.
 void net_init_host(std::vector<float>& th, uint64_t seed) {
   uint64_t ctr = 0;
@@ -386,6 +495,36 @@ cofem_status net_forward_impl(cofem_net* n, const float* feats) {
     const float* b = w + (int64_t)kNetCh[l + 1] * kNetCh[l] * 9;
     NET_HIP(net_conv3(x, kNetCh[l], w, b, n->act[l + 1], kNetCh[l + 1], n->H, n->W, l + 1 < kNetLayers ? 1 : 0,
                       nullptr, n->stream));
+    x = n->act[l + 1];
+  }
+  return COFEM_OK;
+}
+
+// The forward pass on bfloat16 MFMA (inference): weights packed per layer,
+// then one implicit-GEMM launch per layer into act[1..4].
+cofem_status net_forward_bf16_impl(cofem_net* n, const float* feats) {
+  const float* x = feats;
+  int64_t off = 0;
+  for (int l = 0; l < kNetLayers; ++l) {
+    const int ci = kNetCh[l], co = kNetCh[l + 1];
+    const int64_t o = layer_offset(l);
+    const float* w = n->theta + o;
+    const float* bias = w + (int64_t)co * ci * 9;
+    const int CP = ci <= 8 ? 8 : 32;
+    const int KP = CP == 8 ? MfmaGeom<8>::KP : MfmaGeom<32>::KP;
+    uint16_t* wb = n->wbf + off;
+    off += 32 * KP;
+    hipLaunchKernelGGL(k_net_pack_bf16, dim3((unsigned)((32 * KP + 255) / 256)), dim3(256), 0, n->stream, w, ci, co,
+                       CP, KP, wb);
+    const dim3 grid((unsigned)((n->W + kMC - 1) / kMC), (unsigned)((n->H + kMR - 1) / kMR));
+    const int relu = l + 1 < kNetLayers ? 1 : 0;
+    if (CP == 8)
+      hipLaunchKernelGGL(k_net_conv3_mfma<8>, grid, dim3(256), 0, n->stream, x, ci, wb, bias, n->act[l + 1], co, n->H,
+                         n->W, relu);
+    else
+      hipLaunchKernelGGL(k_net_conv3_mfma<32>, grid, dim3(256), 0, n->stream, x, ci, wb, bias, n->act[l + 1], co,
+                         n->H, n->W, relu);
+    NET_HIP(hipGetLastError());
     x = n->act[l + 1];
   }
   return COFEM_OK;
@@ -430,8 +569,8 @@ cofem_status net_loss_grad_impl(cofem_net* n, const float* feats, const float* a
 namespace cofem {
 
 // Predictor of the learned form: from the solver state (alpha, the previous
-// float64 mean and the previous diagonal estimate) fills the start scale /
-// preconditioner d0 and the mean start mu0 for the next E-step.
+// float64 mean and the previous diagonal estimate) fills the probe columns'
+// start scale d0 and the mean start mu0 for the next E-step.
 cofem_status net_predict(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
                          const float* taps, int ntaps, double beta, float* d0, double* mu0, hipStream_t s) {
   const int nb = n->nred;
@@ -443,7 +582,7 @@ cofem_status net_predict(cofem_net* n, const float* alpha, const double* mu_prev
   NET_HIP(hipGetLastError());
   hipStream_t keep = n->stream;
   n->stream = s;
-  const cofem_status st = net_forward_impl(n, n->feats);
+  const cofem_status st = net_forward_bf16_impl(n, n->feats);
   n->stream = keep;
   if (st != COFEM_OK) return st;
   hipLaunchKernelGGL(k_net_predict, dim3(g), dim3(256), 0, s, n->act[kNetLayers], mu_prev, n->aux, n->HW, d0, mu0);
@@ -501,7 +640,8 @@ cofem_status cofem_net_create(int32_t H, int32_t W, uint64_t seed, void* hip_str
   A(&n->wt, (size_t)kNetMaxC * kNetMaxC * 9);
   A(&n->wpart, (size_t)kNetWgBlocks * (kNetMaxC * kNetMaxC * 9 + kNetMaxC));
   A(&n->feats, (size_t)4 * n->HW);
-  A(&n->aux, (size_t)2 * n->HW);
+  A(&n->aux, (size_t)3 * n->HW);
+  A(&n->wbf, (size_t)32 * (MfmaGeom<8>::KP + (kNetLayers - 1) * MfmaGeom<32>::KP));
   A(&n->dpart, (size_t)n->nred);
   A(&n->dscal, 4);
   if (s == COFEM_OK) {
@@ -541,6 +681,14 @@ cofem_status cofem_net_get_params(cofem_net* n, float* host_params, int64_t coun
 cofem_status cofem_net_forward(cofem_net* n, const float* feats, float* out) {
   if (!n || !feats || !out) return net_fail(COFEM_ERR_INVALID_ARG, "null argument");
   if (cofem_status s = net_forward_impl(n, feats)) return s;
+  NET_HIP(hipMemcpyAsync(out, n->act[kNetLayers], sizeof(float) * 2 * n->HW, hipMemcpyDeviceToDevice, n->stream));
+  NET_HIP(hipStreamSynchronize(n->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_net_forward_bf16(cofem_net* n, const float* feats, float* out) {
+  if (!n || !feats || !out) return net_fail(COFEM_ERR_INVALID_ARG, "null argument");
+  if (cofem_status s = net_forward_bf16_impl(n, feats)) return s;
   NET_HIP(hipMemcpyAsync(out, n->act[kNetLayers], sizeof(float) * 2 * n->HW, hipMemcpyDeviceToDevice, n->stream));
   NET_HIP(hipStreamSynchronize(n->stream));
   return COFEM_OK;

@@ -646,7 +646,8 @@ def _net_sample(torch, H, W, seed=0):
     feats = rng.standard_normal((4, H, W)).astype(np.float32)
     mu_p = rng.standard_normal((H, W)).astype(np.float32)
     d = np.exp(rng.uniform(0, 3, (H, W))).astype(np.float32)
-    aux = np.stack([mu_p, d])
+    sb = np.exp(rng.uniform(-2, 2, (H, W))).astype(np.float32)
+    aux = np.stack([mu_p, d, sb])
     tg = np.stack([mu_p * rng.uniform(0.5, 1.5, (H, W)), np.exp(rng.uniform(-1, 1, (H, W))) / d]).astype(np.float32)
     return theta, feats, aux, tg
 
@@ -681,6 +682,53 @@ def test_net_forward_and_gradients_match_oracle(torch_dev):
     net.close()
 
 
+def _bf16_forward_bound(theta, feats):
+    """Elementwise first-order bound on |bf16 MFMA forward - exact forward|.
+
+    Each layer rounds its weights and inputs to bfloat16 (relative error at
+    most u = 2^-9 each) and accumulates in float32 (at most K * 2^-24 relative
+    to sum |w||x|, K = 9 Cin <= 288).  With e the bound on the input error
+    (e = 0 for the features), the output error is at most
+        2u |W| * (|X| + e) + |W| * e + 288 * 2^-24 |W| * |X|
+    (* the circular 3x3 correlation, |.| elementwise); ReLU is 1-Lipschitz so
+    the bound carries through it.  Second-order terms (u^2) are absorbed by
+    the 5% margin the caller adds."""
+    from oracle import learned as OL
+    layers = OL.unflatten(np.asarray(theta, np.float64))
+    x = np.asarray(feats, np.float64)
+    e = np.zeros_like(x)
+    u = 2.0 ** -9
+    for i, (w, b) in enumerate(layers):
+        aw = np.abs(w)
+        zero = np.zeros_like(b)
+        wx = OL.conv3(np.abs(x), aw, zero)
+        e = 2 * u * (wx + OL.conv3(e, aw, zero)) + OL.conv3(e, aw, zero) + 288 * 2.0 ** -24 * wx
+        z = OL.conv3(x, w, b)
+        x = np.maximum(z, 0.0) if i + 1 < len(layers) else z
+    return x, e
+
+
+def test_net_bf16_forward_within_rounding_bound(torch_dev):
+    # the predictor's bfloat16 MFMA forward pass against the float64 oracle
+    # network, elementwise within the first-order bfloat16 rounding bound;
+    # 37 x 45 covers partial 16 x 32 tiles and the wrap-around, and both
+    # channel paddings (4 -> 8 inputs, 2 -> 32 outputs)
+    torch = torch_dev
+    from paper_2202_12808_amd.cofem import CoFEMNet
+    H, W = 37, 45
+    theta, feats, _, _ = _net_sample(torch, H, W, seed=3)
+    net = CoFEMNet(H, W)
+    net.set_params(theta)
+    out = net.forward_bf16(torch.from_numpy(feats.reshape(4, H * W)).cuda()).cpu().numpy().reshape(2, H, W)
+    ref, bound = _bf16_forward_bound(theta.astype(np.float64), feats.astype(np.float64))
+    err = np.abs(out.astype(np.float64) - ref)
+    _say("bf16 forward: max err", float(err.max()), "max bound", float(bound.max()), "relerr", relerr(out, ref),
+         "max err/bound", float(np.max(err / (bound + 1e-30))))
+    assert np.all(err <= 1.05 * bound + 1e-7)
+    assert relerr(out, ref) < 3e-2  # norm-wise, for the record
+    net.close()
+
+
 def _small_conv(seed=0, H=64, W=64):
     return synth.conv_problem(H, W, 7, rho=0.02, beta=1e3, K=8, tol=1e-5, max_iter=400, seed=seed,
                               law="laplace", name=f"conv_{H}x{W}_k7")
@@ -700,14 +748,14 @@ def test_features_match_oracle(torch_dev):
     hh = float(np.sum(p.taps.astype(np.float64) ** 2))
     rf, ra = OL.features(alpha, mu.cpu().numpy(), s, p.beta, hh, p.H, p.W)
     assert relerr(feats.reshape(4, p.H, p.W), rf) < 1e-6
-    assert relerr(aux.reshape(2, p.H, p.W), ra) < 1e-6
+    assert relerr(aux.reshape(3, p.H, p.W), ra) < 1e-6
     net.close()
 
 
 def test_learned_step_parity(torch_dev):
-    # a solve started from the network's prediction with its preconditioner,
-    # against the oracle's PCG from the oracle network's prediction on the
-    # same state (same parameters), at the GPU's iteration count
+    # a solve started from the network's prediction (Jacobi preconditioner),
+    # against the oracle's PCG started from the same prediction, at the GPU's
+    # iteration count
     torch = torch_dev
     from oracle import learned as OL
     from paper_2202_12808_amd.cofem import CoFEMNet
@@ -724,15 +772,21 @@ def test_learned_step_parity(torch_dev):
         _, s_prev, alpha = [x.cpu().numpy() for x in g.posterior()]
         _, mu_prev = g.solution()
         mu_prev = mu_prev.cpu().numpy()
+        # the predictor's input and bfloat16 forward pass (pinned against the
+        # oracle network by test_features_match_oracle and by the rounding bound
+        # of test_net_bf16_forward_within_rounding_bound)
+        feats, aux = g.features(net)
+        out = net.forward_bf16(feats).cpu().numpy().astype(np.float64).reshape(2, p.H, p.W)
+        aux = aux.cpu().numpy().astype(np.float64).reshape(3, p.H, p.W)
         st = g.em_step(1)[0]
         mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
     hh = float(np.sum(p.taps.astype(np.float64) ** 2))
-    f, aux = OL.features(alpha, mu_prev, s_prev, p.beta, hh, p.H, p.W)
-    out, _ = OL.forward(theta.astype(np.float64), f)
+    aux[0] = mu_prev.reshape(p.H, p.W)  # the start scales the exact float64 mean
     mu_hat, d_hat = OL.predict(out, aux)
     d_hat = d_hat.ravel().astype(np.float32).astype(np.float64)
+    minv = (1.0 / (p.beta * hh + alpha.astype(np.float64))).astype(np.float32).astype(np.float64)
     e = O.cofem_estep_pcg(op, b0, p.beta, alpha.astype(np.float64), p.K, p.tol, p.max_iter, p.seed, st["t"],
-                          minv=d_hat, mu0=mu_hat.ravel(), d0=d_hat, fixed_iters=st["cg_iters"])
+                          minv=minv, mu0=mu_hat.ravel(), d0=d_hat, fixed_iters=st["cg_iters"])
     a_ref, _ = O.mstep(e.mu, e.s)
     errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / a_new, 1.0 / a_ref))
     _say("learned step t", st["t"], "cg", st["cg_iters"], "relerr", errs)

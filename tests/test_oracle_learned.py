@@ -1,7 +1,7 @@
 """Pins of the oracle of the learned start/preconditioner network: the hand
 backward pass against central finite differences of the loss, the 3x3
 circular convolution against a direct double loop, and the zero network's
-prediction (the previous mean and the Jacobi diagonal)."""
+prediction (the previous mean and the previous diagonal estimate)."""
 import numpy as np
 
 from oracle import learned as L
@@ -13,7 +13,7 @@ def _sample(H=7, W=6, seed=0, channels=(4, 5, 3, 2)):
     feats = rng.standard_normal((channels[0], H, W))
     mu_p = rng.standard_normal((H, W))
     d = np.exp(rng.uniform(0, 3, (H, W)))
-    aux = np.stack([mu_p, d])
+    aux = np.stack([mu_p, d, np.exp(rng.uniform(-2, 2, (H, W)))])
     targets = np.stack([mu_p * rng.uniform(0.5, 1.5, (H, W)), np.exp(rng.uniform(-1, 1, (H, W))) / d])
     return theta, feats, aux, targets, channels
 
@@ -53,14 +53,20 @@ def test_backward_matches_finite_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
 
 
-def test_zero_network_predicts_previous_mean_and_jacobi():
+def test_zero_network_predicts_previous_mean_and_diagonal():
+    # the untrained network (zero last layer) reproduces the non-learned warm
+    # start: mu_prev, and s_prev wherever s_prev d lies in [0.05, 20]
     H, W = 6, 5
     rng = np.random.default_rng(3)
     alpha = np.exp(rng.uniform(-2, 8, H * W))
     mu = rng.standard_normal(H * W)
-    s = np.exp(rng.uniform(-5, 0, H * W))
+    d = 100.0 * 0.8 + alpha
+    s = np.exp(rng.uniform(-1.5, 1.5, H * W)) / d
+    s[:3] = [1e-4 / d[0], -1.0 / d[1], 50.0 / d[2]]  # below, negative, above the clip
     feats, aux = L.features(alpha, mu, s, 100.0, 0.8, H, W)
     out, _ = L.forward(np.zeros(L.n_params()), feats)
     mu_hat, d_hat = L.predict(out, aux)
     np.testing.assert_allclose(mu_hat, mu.reshape(H, W))
-    np.testing.assert_allclose(d_hat, 1.0 / (100.0 * 0.8 + alpha.reshape(H, W)))
+    ref = s.copy()
+    ref[:3] = [0.05 / d[0], 0.05 / d[1], 20.0 / d[2]]
+    np.testing.assert_allclose(d_hat, ref.reshape(H, W), rtol=1e-14)
