@@ -107,7 +107,7 @@ def stored_traffic(kind, kernel, workload):
         return None
 
 
-def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=8, epochs=30, lr=2e-3):
+def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=None, epochs=20, lr=1e-3):
     """Trains the learned form's network on EM iterates of `seeds` (disjoint
     from the evaluation seed) at train_size^2 with the workload's kernel law,
     beta, K and tolerance (warm-started Jacobi solves give the targets), then
@@ -129,7 +129,9 @@ def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=8
         return CoFEM.conv(torch.from_numpy(q.taps).to(dev), torch.from_numpy(q.y).to(dev), q.H, q.W, q.beta, q.K,
                           tol=q.tol, max_iter=q.max_iter, seed=sd, jacobi=True, warm_start=True)
 
-    samples = LD.collect_samples(mk, seeds, em_iters, small)
+    # every EM iteration of the workload's run: late iterations, where the
+    # previous iterate is already a good start, must be learned too
+    samples = LD.collect_samples(mk, seeds, em_iters or p.T_em, small)
     before = LD.mean_loss(small, samples)
     hist = LD.train(small, samples, epochs=epochs, lr=lr)
     after = LD.mean_loss(small, samples)
@@ -138,7 +140,8 @@ def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=8
         net = CoFEMNet(p.H, p.W)
         net.set_params(small.get_params())
         small.close()
-    info = {"train_image": [hs, ws], "seeds": list(seeds), "samples": len(samples), "epochs": epochs,
+    info = {"train_image": [hs, ws], "seeds": list(seeds), "em_iters": em_iters or p.T_em,
+            "samples": len(samples), "epochs": epochs,
             "loss_before": round(before, 6), "loss_after": round(after, 6),
             "seconds": round(time.perf_counter() - t0, 2)}
     log(f"learned predictor trained: {info}")

@@ -284,15 +284,19 @@ cofem_status cofem_batch_plan(cofem_ctx* ctx, int32_t* target_wgs, float* candid
  * The solve's stop rule is unchanged (Sec. 3.2), so the prediction only
  * changes how many iterations are needed.
  *
- * Features (4 channels, float32, channel-major H x W images), with the diagonal
- * d = beta ||h||^2 + alpha of A: alpha/d; mu_prev / rms(mu_prev);
- * log(clip(s_prev d, 1e-3, 1e3)) / 3; log(d / (beta ||h||^2)) / 10.
+ * Features (5 channels, float32, channel-major H x W images), with the diagonal
+ * d = beta ||h||^2 + alpha of A and d_prev from the previous E-step's alpha:
+ * alpha/d; mu_prev / rms(mu_prev); log(clip(s_prev d, 1e-3, 1e3)) / 3;
+ * log(d / (beta ||h||^2)) / 10; clip(log(d_prev / d), -10, 10) / 10.
  * aux (3 channels): mu_prev, d, sb = clip(s_prev d, 0.05, 20).  Network: four
- * 3x3 circular convolutions, 4 -> 32 -> 32 -> 32 -> 2 channels, ReLU after
+ * 3x3 circular convolutions, 5 -> 32 -> 32 -> 32 -> 2 channels, ReLU after
  * the first three.  Prediction: mu_hat = mu_prev (1 + tanh o0),
  * d_hat = exp(clip(o1, -10, 10)) sb / d.
- * Loss against an E-step's (mu_t, s_t) (targets, 2 channels):
- * sum (mu_hat - mu_t)^2 / sum mu_t^2 + 0.1 mean (o1 - log(clip(s_t d, 0.05, 20) / sb))^2.
+ * Loss against an E-step's (mu_t, s_t) (targets, 2 channels), each term relative
+ * to the untrained network's (the previous iterate's), with
+ * tgt = log(clip(s_t d, 0.05, 20) / sb) and f = 1e-4:
+ * sum (mu_hat - mu_t)^2 / (sum (mu_prev - mu_t)^2 + f sum mu_t^2)
+ * + 0.1 sum (o1 - tgt)^2 / (sum tgt^2 + f H W).
  * Parameters (float32): for each layer w (Cout x Cin x 3 x 3), then b (Cout).
  * All device pointers below are float32 images of the net's H x W grid.
  */
@@ -312,19 +316,19 @@ void cofem_net_destroy(cofem_net* net);
 cofem_status cofem_net_set_params(cofem_net* net, const float* host_params, int64_t count);
 cofem_status cofem_net_get_params(cofem_net* net, float* host_params, int64_t count);
 
-/* out (2 channels) = network(feats (4 channels)) in float32 (the training
+/* out (2 channels) = network(feats (5 channels)) in float32 (the training
  * kernels' forward pass); synchronises. */
 cofem_status cofem_net_forward(cofem_net* net, const float* feats, float* out);
 
 /* The same forward pass as the predictor runs it (inference): each 3x3 layer
  * an implicit GEMM on bfloat16 MFMA (v_mfma_f32_32x32x16_bf16), weights and
  * activations rounded to bfloat16 (round to nearest even), float32
- * accumulation and float32 activations in memory.  feats (4 images) in, out
+ * accumulation and float32 activations in memory.  feats (5 images) in, out
  * (2 images) written; synchronises.  COFEM_ERR_INVALID_ARG for a null
  * pointer. */
 cofem_status cofem_net_forward_bf16(cofem_net* net, const float* feats, float* out);
 
-/* Loss and its gradient for one sample (feats 4, aux 3, targets 2 channels);
+/* Loss and its gradient for one sample (feats 5, aux 3, targets 2 channels);
  * *loss (host, nullable) and host_grad (host, cofem_net_num_params() floats,
  * nullable).  Synchronises. */
 cofem_status cofem_net_loss_grad(cofem_net* net, const float* feats, const float* aux, const float* targets,
@@ -336,8 +340,8 @@ cofem_status cofem_net_train_step(cofem_net* net, const float* feats, const floa
                                   float lr, double* loss);
 
 /* The features and aux channels of the context's next E-step (from its alpha,
- * last mean and last diagonal estimate), written to device buffers of 4 and 3
- * images; `net` (same H x W) lends its reduction scratch.  Synchronises. */
+ * previous alpha, last mean and last diagonal estimate), written to device
+ * buffers of 5 and 3 images; `net` (same H x W) lends its reduction scratch.  Synchronises. */
 cofem_status cofem_features(cofem_ctx* ctx, cofem_net* net, float* feats, float* aux);
 
 /* Attaches `net` as the predictor of a convolution context (NULL detaches):

@@ -11,14 +11,16 @@ judges the prediction (Sec. 3.2).
 
 Definitions (shared with the GPU kernels by specification, not by code):
 
-* features (4 channels) from alpha_t, mu_{t-1}, s_{t-1}, with the diagonal
-  d = beta ||h||^2 + alpha_t of A:
+* features (5 channels) from alpha_t, alpha_{t-1}, mu_{t-1}, s_{t-1}, with the
+  diagonal d = beta ||h||^2 + alpha_t of A (d_prev likewise from alpha_{t-1}):
     f0 = alpha_t / d
     f1 = mu_{t-1} / rms(mu_{t-1})          (rms over the image; 1 if it is 0)
     f2 = log(clip(s_{t-1} d, 1e-3, 1e3)) / 3
     f3 = log(d / (beta ||h||^2)) / 10
+    f4 = clip(log(d_prev / d), -10, 10) / 10   (how far the last M-step moved A;
+         mu_t - mu_{t-1} solves A_t e = (alpha_{t-1} - alpha_t) mu_{t-1})
   aux (3 channels): mu_{t-1}, d, sb = clip(s_{t-1} d, 0.05, 20).
-* network: four 3x3 convolutions with circular padding, 4 -> 32 -> 32 -> 32 -> 2
+* network: four 3x3 convolutions with circular padding, 5 -> 32 -> 32 -> 32 -> 2
   channels, ReLU after the first three; out[co][u][v] = b[co] +
   sum_{ci,ky,kx} w[co][ci][ky][kx] x[ci][(u+ky-1) mod H][(v+kx-1) mod W].
 * prediction: mu_hat = mu_{t-1} (1 + tanh(o0)),  d_hat = exp(clip(o1, -10, 10)) sb / d;
@@ -27,9 +29,11 @@ Definitions (shared with the GPU kernels by specification, not by code):
   needs more iterations).  All-zero output gives mu_hat = mu_{t-1} and
   d_hat = clip(s_{t-1} d, 0.05, 20) / d, i.e. the previous iterate, the
   non-learned warm start: the network learns corrections to it.
-* loss against the E-step's result (mu_t, s_t):
-    L = sum (mu_hat - mu_t)^2 / sum mu_t^2
-        + LAMBDA_D * mean (o1 - log(clip(s_t d, 0.05, 20) / sb))^2.
+* loss against the E-step's result (mu_t, s_t), each term relative to the
+  untrained network's (the previous iterate's), with tgt = log(clip(s_t d,
+  0.05, 20) / sb) and f = NORM_FLOOR:
+    L = sum (mu_hat - mu_t)^2 / (sum (mu_{t-1} - mu_t)^2 + f sum mu_t^2)
+        + LAMBDA_D * sum (o1 - tgt)^2 / (sum tgt^2 + f HW).
 * parameters, flattened: for each layer w (Cout x Cin x 3 x 3, row-major),
   then b (Cout).
 
@@ -40,8 +44,9 @@ from __future__ import annotations
 
 import numpy as np
 
-CHANNELS = (4, 32, 32, 32, 2)
+CHANNELS = (5, 32, 32, 32, 2)
 LAMBDA_D = 0.1
+NORM_FLOOR = 1e-4  # changes below 1% of the mean count as converged (bounds the weights)
 
 
 def param_shapes(channels=CHANNELS):
@@ -79,16 +84,19 @@ def conv3(x, w, b):
     return out
 
 
-def features(alpha, mu_prev, s_prev, beta, hh, H, W):
-    """(feats [4,H,W], aux [3,H,W]) from the state before an E-step."""
+def features(alpha, mu_prev, s_prev, beta, hh, H, W, alpha_prev=None):
+    """(feats [5,H,W], aux [3,H,W]) from the state before an E-step
+    (alpha_prev: the previous E-step's alpha; None means unchanged)."""
     alpha = np.asarray(alpha, np.float64).reshape(H, W)
+    ap = alpha if alpha_prev is None else np.asarray(alpha_prev, np.float64).reshape(H, W)
     mu = np.asarray(mu_prev, np.float64).reshape(H, W)
     s = np.asarray(s_prev, np.float64).reshape(H, W)
     d = beta * hh + alpha
     rms = float(np.sqrt(np.mean(mu * mu)))
     rms = rms if rms > 0.0 else 1.0
     f = np.stack([alpha / d, mu / rms, np.log(np.clip(s * d, 1e-3, 1e3)) / 3.0,
-                  np.log(d / (beta * hh)) / 10.0])
+                  np.log(d / (beta * hh)) / 10.0,
+                  np.clip(np.log((beta * hh + ap) / d), -10.0, 10.0) / 10.0])
     return f, np.stack([mu, d, np.clip(s * d, 0.05, 20.0)])
 
 
@@ -113,18 +121,22 @@ def predict(out, aux):
 
 
 def loss_and_grad_out(out, aux, targets):
-    """Loss L and dL/d(out) for targets = [mu_t, s_t]."""
+    """Loss L and dL/d(out) for targets = [mu_t, s_t].  Each term is
+    normalised by the same term of the untrained network (the non-learned
+    warm start), so L < 1 + LAMBDA_D means a better start than the previous
+    iterate, in early and late EM iterations alike."""
     mu_p, d, sb = aux
     mu_t, s_t = targets
     th = np.tanh(out[0])
     e = mu_p * (1.0 + th) - mu_t
-    nrm = float(np.sum(mu_t * mu_t))
-    nrm = nrm if nrm > 0.0 else 1.0
-    tgt = np.log(np.clip(s_t * d, 0.05, 20.0) / sb)
-    r = out[1] - tgt
     n = out[0].size
-    L = float(np.sum(e * e)) / nrm + LAMBDA_D * float(np.mean(r * r))
-    g = np.stack([2.0 * e * mu_p * (1.0 - th * th) / nrm, 2.0 * LAMBDA_D * r / n])
+    nrm_mu = float(np.sum((mu_p - mu_t) ** 2)) + NORM_FLOOR * float(np.sum(mu_t * mu_t))
+    nrm_mu = nrm_mu if nrm_mu > 0.0 else 1.0
+    tgt = np.log(np.clip(s_t * d, 0.05, 20.0) / sb)
+    nrm_d = float(np.sum(tgt * tgt)) + NORM_FLOOR * n
+    r = out[1] - tgt
+    L = float(np.sum(e * e)) / nrm_mu + LAMBDA_D * float(np.sum(r * r)) / nrm_d
+    g = np.stack([2.0 * e * mu_p * (1.0 - th * th) / nrm_mu, 2.0 * LAMBDA_D * r / nrm_d])
     return L, g
 
 

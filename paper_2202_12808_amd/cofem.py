@@ -357,9 +357,9 @@ class CoFEM:
         return cofem_time_operator(self.ctx, reps)
 
     def features(self, net):
-        """(feats [4, H*W], aux [3, H*W]) of the next E-step (convolution only)."""
+        """(feats [5, H*W], aux [3, H*W]) of the next E-step (convolution only)."""
         import torch
-        feats = torch.empty((4, self.D), dtype=torch.float32, device=self.device)
+        feats = torch.empty((5, self.D), dtype=torch.float32, device=self.device)
         aux = torch.empty((3, self.D), dtype=torch.float32, device=self.device)
         _check(load().cofem_features(self.ctx, net.net, _ptr(feats), _ptr(aux)), self.ctx)
         return feats, aux

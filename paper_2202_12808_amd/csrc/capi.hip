@@ -92,6 +92,7 @@ struct cofem_ctx {
   // solve state
   double* b0 = nullptr;
   float* alpha = nullptr;
+  float* alpha_prev = nullptr;  // conv: the alpha of the last E-step (learned form's features)
   float *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
   double *xm = nullptr, *rm = nullptr, *pm = nullptr, *qm = nullptr;
   // conv probe blocks (float or double per the precision mode)
@@ -305,6 +306,7 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
                               c->stream));
   COFEM_TRY(alloc(c, &c->b0, cd.ldD));
   COFEM_TRY(alloc(c, &c->alpha, cd.ldD));
+  COFEM_TRY(alloc(c, &c->alpha_prev, cd.ldD));
   COFEM_TRY(alloc(c, &c->mu, cd.ldD));
   COFEM_TRY(alloc(c, &c->sdiag, cd.ldD));
   COFEM_TRY(alloc(c, &c->minv, cd.ldD));
@@ -341,6 +343,7 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   }
   COFEM_HIP(c, conv_b0(cd, c->taps, p.y, c->beta, c->b0, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
+  COFEM_HIP(c, fill_f32(c->alpha_prev, 1.0f, cd.ldD, c->stream));
   return COFEM_OK;
 }
 
@@ -956,9 +959,13 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
                              c->sdiag, c->st, c->stream));
-  else
+  else {
+    // the learned form's features see how far this M-step moves alpha
+    COFEM_HIP(c, hipMemcpyAsync(c->alpha_prev, c->alpha, sizeof(float) * c->cd.D, hipMemcpyDeviceToDevice,
+                                c->stream));
     COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
                             c->st, c->stream));
+  }
   COFEM_TRY(mark(c, -1, 0));
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
   COFEM_TRY(read_state(c));
@@ -1293,8 +1300,8 @@ cofem_status cofem_features(cofem_ctx* ctx, cofem_net* net, float* feats, float*
     return fail(ctx, COFEM_ERR_UNSUPPORTED, "features exist for convolution dictionaries only");
   if (net_height(net) != ctx->cd.H || net_width(net) != ctx->cd.W)
     return fail(ctx, COFEM_ERR_INVALID_ARG, "the net's image size differs from the problem's");
-  COFEM_TRY(net_features(net, ctx->alpha, ctx->xm, ctx->sdiag, ctx->taps, ctx->cd.ks * ctx->cd.ks, ctx->beta, feats,
-                         aux, ctx->stream));
+  COFEM_TRY(net_features(net, ctx->alpha, ctx->alpha_prev, ctx->xm, ctx->sdiag, ctx->taps, ctx->cd.ks * ctx->cd.ks,
+                         ctx->beta, feats, aux, ctx->stream));
   COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return COFEM_OK;
 }
@@ -1334,8 +1341,8 @@ const char* cofem_status_string(cofem_status s) {
 namespace {
 
 cofem_status predictor_hook(cofem_ctx* c, void* user, float* d0, double* mu0) {
-  return net_predict(static_cast<cofem_net*>(user), c->alpha, c->xm, c->sdiag, c->taps, c->cd.ks * c->cd.ks,
-                     c->beta, d0, mu0, c->stream);
+  return net_predict(static_cast<cofem_net*>(user), c->alpha, c->alpha_prev, c->xm, c->sdiag, c->taps,
+                     c->cd.ks * c->cd.ks, c->beta, d0, mu0, c->stream);
 }
 
 }  // namespace

@@ -603,10 +603,12 @@ hipError_t batch_running(const BatchProblem* probs, int n, int32_t* out, hipStre
 
 // ------------------------------------------------------------ learned form
 void set_last_error(const std::string& msg);
-cofem_status net_predict(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
-                         const float* taps, int ntaps, double beta, float* d0, double* mu0, hipStream_t s);
-cofem_status net_features(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
-                          const float* taps, int ntaps, double beta, float* feats, float* aux, hipStream_t s);
+cofem_status net_predict(cofem_net* n, const float* alpha, const float* alpha_prev, const double* mu_prev,
+                         const float* s_prev, const float* taps, int ntaps, double beta, float* d0, double* mu0,
+                         hipStream_t s);
+cofem_status net_features(cofem_net* n, const float* alpha, const float* alpha_prev, const double* mu_prev,
+                          const float* s_prev, const float* taps, int ntaps, double beta, float* feats, float* aux,
+                          hipStream_t s);
 int net_height(const cofem_net* n);
 int net_width(const cofem_net* n);
 

@@ -9,14 +9,17 @@
 // Definitions (features, network, prediction, loss):
 //   d = beta ||h||^2 + alpha (the diagonal of A); features
 //     f0 = alpha / d, f1 = mu_prev / rms(mu_prev),
-//     f2 = log(clip(s_prev d, 1e-3, 1e3)) / 3, f3 = log(d / (beta ||h||^2)) / 10;
-//   four 3x3 convolutions with circular padding, 4 -> 32 -> 32 -> 32 -> 2
+//     f2 = log(clip(s_prev d, 1e-3, 1e3)) / 3, f3 = log(d / (beta ||h||^2)) / 10,
+//     f4 = clip(log(d_prev / d), -10, 10) / 10 (d_prev from the previous E-step's alpha);
+//   four 3x3 convolutions with circular padding, 5 -> 32 -> 32 -> 32 -> 2
 //   channels, ReLU after the first three,
 //     out[co][u][v] = b[co] + sum w[co][ci][ky][kx] x[ci][(u+ky-1) mod H][(v+kx-1) mod W];
 //   with sb = clip(s_prev d, 0.05, 20):
 //   mu_hat = mu_prev (1 + tanh o0), d_hat = exp(clip(o1, -10, 10)) sb / d;
-//   loss = sum (mu_hat - mu_t)^2 / sum mu_t^2
-//          + 0.1 mean (o1 - log(clip(s_t d, 0.05, 20) / sb))^2.
+//   with tgt = log(clip(s_t d, 0.05, 20) / sb), each term relative to the
+//   untrained network's (the previous iterate's) and f = 1e-4:
+//   loss = sum (mu_hat - mu_t)^2 / (sum (mu_prev - mu_t)^2 + f sum mu_t^2)
+//          + 0.1 sum (o1 - tgt)^2 / (sum tgt^2 + f HW).
 // The untrained network (zero last layer) reproduces the previous iterate,
 // so training learns corrections to the non-learned warm start.
 // Activations are channel-major float32 images; sums of the loss and of the
@@ -34,9 +37,10 @@
 namespace cofem {
 
 constexpr int kNetLayers = 4;
-constexpr int kNetCh[kNetLayers + 1] = {4, 32, 32, 32, 2};
+constexpr int kNetCh[kNetLayers + 1] = {5, 32, 32, 32, 2};
 constexpr int kNetMaxC = 32;
 constexpr double kNetLambdaD = 0.1;
+constexpr double kNetNormFloor = 1e-4;  // changes below 1% of the mean count as converged
 constexpr int kNT = 16;               // pixel tile side
 constexpr int kNHalo = kNT + 2;       // tile plus a one-pixel halo
 constexpr int kNetWgBlocks = 256;     // blocks of the weight-gradient kernel
@@ -150,13 +154,21 @@ __global__ void k_net_pack_bf16(const float* __restrict__ w, int cin, int cout, 
   wb[idx] = (uint16_t)bf16_rne_bits(v);
 }
 
-template <int CP>
-__global__ __launch_bounds__(256) void k_net_conv3_mfma(const float* __restrict__ in, int cin,
+// IN_BF: the input is the previous layer's bfloat16 output, pixel-major with
+// 32 channels per pixel (else float32 channel-major images, converted while
+// staged).  OUT_BF: the output is written that way for the next layer (else
+// float32 channel-major images).  Bias and ReLU are applied in float32 before
+// the rounding, so the values match rounding at the next layer's input.
+template <int CP, bool IN_BF, bool OUT_BF>
+__global__ __launch_bounds__(256) void k_net_conv3_mfma(const void* __restrict__ in_, int cin,
                                                         const uint16_t* __restrict__ wb, const float* __restrict__ b,
-                                                        float* __restrict__ out, int cout, int H, int W, int relu) {
+                                                        void* __restrict__ out_, int cout, int H, int W, int relu) {
   using G = MfmaGeom<CP>;
-  constexpr int SW = kMC + 2, NPIX = (kMR + 2) * SW, NOCT = CP / 8;
+  constexpr int SW = kMC + 2, NPIX = (kMR + 2) * SW, NOCT = CP / 8, ITEMS = NPIX * NOCT;
   __shared__ __align__(16) uint16_t s_x[NPIX * CP];
+  // per-wave staging of one output row (32 pixels x 32 channels) so that the
+  // bfloat16 output leaves as contiguous 16-byte stores
+  __shared__ __align__(16) uint16_t s_o[OUT_BF ? 4 : 1][OUT_BF ? kMC * 32 : 8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int v0 = blockIdx.x * kMC, u0 = blockIdx.y * kMR;
   const int64_t HW = (int64_t)H * W;
@@ -164,20 +176,43 @@ __global__ __launch_bounds__(256) void k_net_conv3_mfma(const float* __restrict_
 #pragma unroll
   for (int st = 0; st < G::NS; ++st)
     a[st] = *reinterpret_cast<const uint4*>(wb + (lane & 31) * G::KP + 16 * st + 8 * (lane >> 5));
-  // stage: each item is one pixel's octet of channels (8 loads, one 16-byte store)
-  for (int e = threadIdx.x; e < NPIX * NOCT; e += blockDim.x) {
-    const int o = e / NPIX, pix = e - (e / NPIX) * NPIX;
-    const int i = pix / SW, j = pix - (pix / SW) * SW;
-    const int64_t src = (int64_t)nwrap(u0 + i - 1, H) * W + nwrap(v0 + j - 1, W);
-    uint32_t wd[4];
+  // stage: each item is one pixel's octet of channels (one 16-byte LDS store);
+  // items go in groups of 5 per thread with all their loads issued first
+  constexpr int PER = (ITEMS + kThreads - 1) / kThreads, GRP = 5;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c0 = 8 * o + 2 * q;
-      const uint32_t lo = c0 < cin ? bf16_rne_bits(in[(int64_t)c0 * HW + src]) : 0u;
-      const uint32_t hi = c0 + 1 < cin ? bf16_rne_bits(in[(int64_t)(c0 + 1) * HW + src]) : 0u;
-      wd[q] = lo | (hi << 16);
+  for (int k0 = 0; k0 < PER; k0 += GRP) {
+    uint4 vals[GRP];
+#pragma unroll
+    for (int k = 0; k < GRP; ++k) {
+      const int e = threadIdx.x + (k0 + k) * kThreads;
+      if (k0 + k < PER && e < ITEMS) {
+        const int o = e / NPIX, pix = e - (e / NPIX) * NPIX;
+        const int i = pix / SW, j = pix - (pix / SW) * SW;
+        const int64_t src = (int64_t)nwrap(u0 + i - 1, H) * W + nwrap(v0 + j - 1, W);
+        if constexpr (IN_BF) {
+          vals[k] = reinterpret_cast<const uint4*>(in_)[src * NOCT + o];
+        } else {
+          const float* in = static_cast<const float*>(in_);
+          uint32_t wd[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c0 = 8 * o + 2 * q;
+            const uint32_t lo = c0 < cin ? bf16_rne_bits(in[(int64_t)c0 * HW + src]) : 0u;
+            const uint32_t hi = c0 + 1 < cin ? bf16_rne_bits(in[(int64_t)(c0 + 1) * HW + src]) : 0u;
+            wd[q] = lo | (hi << 16);
+          }
+          vals[k] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+        }
+      }
     }
-    *reinterpret_cast<uint4*>(s_x + pix * CP + 8 * o) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+#pragma unroll
+    for (int k = 0; k < GRP; ++k) {
+      const int e = threadIdx.x + (k0 + k) * kThreads;
+      if (k0 + k < PER && e < ITEMS) {
+        const int o = e / NPIX, pix = e - (e / NPIX) * NPIX;
+        *reinterpret_cast<uint4*>(s_x + pix * CP + 8 * o) = vals[k];
+      }
+    }
   }
   __syncthreads();
   const int j = lane & 31, h = lane >> 5;
@@ -200,15 +235,50 @@ __global__ __launch_bounds__(256) void k_net_conv3_mfma(const float* __restrict_
                                                     __builtin_bit_cast(bf16x8, bx), acc, 0, 0, 0);
     }
     const int u = u0 + i;
-    if (u < H && v < W) {
-      const int64_t pxo = (int64_t)u * W + v;
+    // row of the 32 x 32 result held in acc[q]: 8 (q / 4) + 4 h + q % 4
+    if constexpr (OUT_BF) {
+      uint16_t* so = s_o[wave];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int co = 8 * (q >> 2) + 4 * h + (q & 3);  // row of the 32 x 32 result
-        if (co < cout) {
-          float o = acc[q] + b[co];
-          if (relu) o = fmaxf(o, 0.0f);
-          out[(int64_t)co * HW + pxo] = o;
+      for (int g = 0; g < 4; ++g) {
+        uint32_t wd[2];
+#pragma unroll
+        for (int hq = 0; hq < 2; ++hq) {
+          uint32_t bits[2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const int q = 4 * g + 2 * hq + t, co = 8 * g + 4 * h + 2 * hq + t;
+            float o = co < cout ? acc[q] + b[co] : 0.0f;
+            if (relu) o = fmaxf(o, 0.0f);
+            bits[t] = bf16_rne_bits(o);
+          }
+          wd[hq] = bits[0] | (bits[1] << 16);
+        }
+        *reinterpret_cast<uint2*>(so + j * 32 + 8 * g + 4 * h) = make_uint2(wd[0], wd[1]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (u < H) {
+        uint16_t* out = static_cast<uint16_t*>(out_);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int idx = lane + 64 * t, pix = idx >> 2, oct = idx & 3;  // 16-byte pieces of the row
+          if (v0 + pix < W)
+            *reinterpret_cast<uint4*>(out + ((int64_t)u * W + v0 + pix) * 32 + 8 * oct) =
+                *reinterpret_cast<const uint4*>(so + pix * 32 + 8 * oct);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    } else if (u < H && v < W) {
+      const int64_t pxo = (int64_t)u * W + v;
+      {
+        float* out = static_cast<float*>(out_);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int co = 8 * (q >> 2) + 4 * h + (q & 3);
+          if (co < cout) {
+            float o = acc[q] + b[co];
+            if (relu) o = fmaxf(o, 0.0f);
+            out[(int64_t)co * HW + pxo] = o;
+          }
         }
       }
     }
@@ -300,27 +370,54 @@ __device__ __forceinline__ void net_block_partial(double v, double* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void k_net_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
+// out[0] = sum of part[0..n): one block of 256 threads, thread t summing
+// part[t], part[t + 256], ... in order, then a fixed-shape block reduction
+// (deterministic; every load in flight at once instead of a serial chain)
+__global__ __launch_bounds__(256) void k_net_finish_sum(const double* __restrict__ part, int n,
+                                                        double* __restrict__ out) {
+  __shared__ double shm[8];
   double a = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a += (double)x[i] * (double)x[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
+  const double t = block_sum(a, shm);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// Block partials of the loss normalisers: sum (mu_prev - mu_t)^2 into part,
+// sum mu_t^2 into part + nblk, sum tgt^2 into part + 2 nblk, with
+// tgt = log(clip(s_t d, 0.05, 20) / sb).
+__global__ __launch_bounds__(256) void k_net_loss_norms(const float* __restrict__ aux, const float* __restrict__ tgt,
+                                                        int64_t HW, double* __restrict__ part) {
+  double a = 0.0, m = 0.0, t = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += (int64_t)gridDim.x * blockDim.x) {
+    const double mp = aux[p], d = aux[HW + p], sb = aux[2 * HW + p];
+    const double mt = tgt[p], st = tgt[HW + p];
+    double sd = st * d;
+    sd = sd < 0.05 ? 0.05 : (sd > 20.0 ? 20.0 : sd);
+    const double lt = log(sd / sb);
+    a += (mp - mt) * (mp - mt);
+    m += mt * mt;
+    t += lt * lt;
+  }
   net_block_partial(a, part);
+  net_block_partial(m, part + gridDim.x);
+  net_block_partial(t, part + 2 * gridDim.x);
 }
 
-// out[0] = sum of part[0..n) in order (one thread)
-__global__ void k_net_finish_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
+// nrm[0] = sum (mu_prev - mu_t)^2 + f sum mu_t^2, nrm[1] = sum tgt^2 + f HW
+// from the three finished sums s[0..2] (f = kNetNormFloor); one thread
+__global__ void k_net_finish_norms(const double* __restrict__ s3, int64_t HW, double* __restrict__ nrm) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double a = 0.0;
-  for (int i = 0; i < n; ++i) a += part[i];
-  out[0] = a;
+  double a = s3[0] + kNetNormFloor * s3[1];
+  nrm[0] = a > 0.0 ? a : 1.0;
+  nrm[1] = s3[2] + kNetNormFloor * (double)HW;
 }
 
-// g = dL/d(out) and block partials of L (the normalisation sum mu_t^2 in nrm[0])
+// g = dL/d(out) and block partials of L (the normalisers in nrm[0..1])
 __global__ __launch_bounds__(256) void k_net_loss_grad(const float* __restrict__ out, const float* __restrict__ aux,
                                                        const float* __restrict__ tgt, int64_t HW,
                                                        const double* __restrict__ nrm, float* __restrict__ g,
                                                        double* __restrict__ part) {
-  const double nr = nrm[0] > 0.0 ? nrm[0] : 1.0;
+  const double nr = nrm[0], nd = nrm[1];
   double a = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += (int64_t)gridDim.x * blockDim.x) {
     const double o0 = out[p], o1 = out[HW + p];
@@ -331,9 +428,9 @@ __global__ __launch_bounds__(256) void k_net_loss_grad(const float* __restrict__
     double sd = st * d;
     sd = sd < 0.05 ? 0.05 : (sd > 20.0 ? 20.0 : sd);
     const double r = o1 - log(sd / sb);
-    a += e * e / nr + kNetLambdaD * r * r / (double)HW;
+    a += e * e / nr + kNetLambdaD * r * r / nd;
     g[p] = (float)(2.0 * e * mp * (1.0 - th * th) / nr);
-    g[HW + p] = (float)(2.0 * kNetLambdaD * r / (double)HW);
+    g[HW + p] = (float)(2.0 * kNetLambdaD * r / nd);
   }
   net_block_partial(a, part);
 }
@@ -363,7 +460,8 @@ __global__ __launch_bounds__(256) void k_net_mu_sumsq(const double* __restrict__
   net_block_partial(a, part);
 }
 
-__global__ void k_net_features(const float* __restrict__ alpha, const double* __restrict__ mu,
+__global__ void k_net_features(const float* __restrict__ alpha, const float* __restrict__ alpha_prev,
+                               const double* __restrict__ mu,
                                const float* __restrict__ s, const float* __restrict__ taps, int ntaps, double beta,
                                int64_t HW, const double* __restrict__ musq, float* __restrict__ feats,
                                float* __restrict__ aux) {
@@ -381,6 +479,9 @@ __global__ void k_net_features(const float* __restrict__ alpha, const double* __
   feats[HW + p] = (float)(mu[p] / rms);
   feats[2 * HW + p] = (float)(log(sd) / 3.0);
   feats[3 * HW + p] = (float)(log(d / bh) / 10.0);
+  double lr = log((bh + (double)alpha_prev[p]) / d);
+  lr = lr < -10.0 ? -10.0 : (lr > 10.0 ? 10.0 : lr);
+  feats[4 * HW + p] = (float)(lr / 10.0);
   aux[p] = (float)mu[p];
   aux[HW + p] = (float)d;
   double sb = (double)s[p] * d;
@@ -415,6 +516,7 @@ struct cofem_net {
   float *g0 = nullptr, *g1 = nullptr, *wt = nullptr, *wpart = nullptr;
   float *feats = nullptr, *aux = nullptr;  // predictor scratch
   uint16_t* wbf = nullptr;                 // bfloat16 weights of the MFMA forward pass
+  uint16_t* actb[2] = {};                  // its bfloat16 activations, pixel-major, 32 channels
   double *dpart = nullptr, *dscal = nullptr;
   int step = 0;
   int nred = 0;  // blocks of the reductions
@@ -503,29 +605,32 @@ cofem_status net_forward_impl(cofem_net* n, const float* feats) {
 // The forward pass on bfloat16 MFMA (inference): weights packed per layer,
 // then one implicit-GEMM launch per layer into act[1..4].
 cofem_status net_forward_bf16_impl(cofem_net* n, const float* feats) {
-  const float* x = feats;
   int64_t off = 0;
+  const dim3 grid((unsigned)((n->W + kMC - 1) / kMC), (unsigned)((n->H + kMR - 1) / kMR));
   for (int l = 0; l < kNetLayers; ++l) {
     const int ci = kNetCh[l], co = kNetCh[l + 1];
     const int64_t o = layer_offset(l);
     const float* w = n->theta + o;
     const float* bias = w + (int64_t)co * ci * 9;
-    const int CP = ci <= 8 ? 8 : 32;
+    const int CP = l == 0 ? 8 : 32;
     const int KP = CP == 8 ? MfmaGeom<8>::KP : MfmaGeom<32>::KP;
     uint16_t* wb = n->wbf + off;
     off += 32 * KP;
     hipLaunchKernelGGL(k_net_pack_bf16, dim3((unsigned)((32 * KP + 255) / 256)), dim3(256), 0, n->stream, w, ci, co,
                        CP, KP, wb);
-    const dim3 grid((unsigned)((n->W + kMC - 1) / kMC), (unsigned)((n->H + kMR - 1) / kMR));
-    const int relu = l + 1 < kNetLayers ? 1 : 0;
-    if (CP == 8)
-      hipLaunchKernelGGL(k_net_conv3_mfma<8>, grid, dim3(256), 0, n->stream, x, ci, wb, bias, n->act[l + 1], co, n->H,
-                         n->W, relu);
+    // layer 0: float32 features -> bf16 act; 1, 2: bf16 -> bf16; 3: bf16 -> float32 output
+    uint16_t* ping = n->actb[l & 1];
+    const uint16_t* pong = n->actb[(l + 1) & 1];
+    if (l == 0)
+      hipLaunchKernelGGL((k_net_conv3_mfma<8, false, true>), grid, dim3(256), 0, n->stream, feats, ci, wb, bias, ping,
+                         co, n->H, n->W, 1);
+    else if (l + 1 < kNetLayers)
+      hipLaunchKernelGGL((k_net_conv3_mfma<32, true, true>), grid, dim3(256), 0, n->stream, pong, ci, wb, bias, ping,
+                         co, n->H, n->W, 1);
     else
-      hipLaunchKernelGGL(k_net_conv3_mfma<32>, grid, dim3(256), 0, n->stream, x, ci, wb, bias, n->act[l + 1], co,
-                         n->H, n->W, relu);
+      hipLaunchKernelGGL((k_net_conv3_mfma<32, true, false>), grid, dim3(256), 0, n->stream, pong, ci, wb, bias,
+                         n->act[kNetLayers], co, n->H, n->W, 0);
     NET_HIP(hipGetLastError());
-    x = n->act[l + 1];
   }
   return COFEM_OK;
 }
@@ -534,11 +639,14 @@ cofem_status net_forward_bf16_impl(cofem_net* n, const float* feats) {
 cofem_status net_loss_grad_impl(cofem_net* n, const float* feats, const float* aux, const float* tgt) {
   if (cofem_status s = net_forward_impl(n, feats)) return s;
   const int nb = n->nred;
-  hipLaunchKernelGGL(k_net_sumsq, dim3(nb), dim3(256), 0, n->stream, tgt, n->HW, n->dpart);
-  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(64), 0, n->stream, n->dpart, nb, n->dscal);
+  // dscal: [1] loss, [3..5] the three normaliser sums, [6..7] the normalisers
+  hipLaunchKernelGGL(k_net_loss_norms, dim3(nb), dim3(256), 0, n->stream, aux, tgt, n->HW, n->dpart);
+  for (int i = 0; i < 3; ++i)
+    hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(256), 0, n->stream, n->dpart + i * nb, nb, n->dscal + 3 + i);
+  hipLaunchKernelGGL(k_net_finish_norms, dim3(1), dim3(64), 0, n->stream, n->dscal + 3, n->HW, n->dscal + 6);
   hipLaunchKernelGGL(k_net_loss_grad, dim3(nb), dim3(256), 0, n->stream, n->act[kNetLayers], aux, tgt, n->HW,
-                     n->dscal, n->g0, n->dpart);
-  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(64), 0, n->stream, n->dpart, nb, n->dscal + 1);
+                     n->dscal + 6, n->g0, n->dpart);
+  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(256), 0, n->stream, n->dpart, nb, n->dscal + 1);
   NET_HIP(hipGetLastError());
   float* g = n->g0;
   float* gn = n->g1;
@@ -571,14 +679,15 @@ namespace cofem {
 // Predictor of the learned form: from the solver state (alpha, the previous
 // float64 mean and the previous diagonal estimate) fills the probe columns'
 // start scale d0 and the mean start mu0 for the next E-step.
-cofem_status net_predict(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
-                         const float* taps, int ntaps, double beta, float* d0, double* mu0, hipStream_t s) {
+cofem_status net_predict(cofem_net* n, const float* alpha, const float* alpha_prev, const double* mu_prev,
+                         const float* s_prev, const float* taps, int ntaps, double beta, float* d0, double* mu0,
+                         hipStream_t s) {
   const int nb = n->nred;
   hipLaunchKernelGGL(k_net_mu_sumsq, dim3(nb), dim3(256), 0, s, mu_prev, n->HW, n->dpart);
-  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(64), 0, s, n->dpart, nb, n->dscal + 2);
+  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(256), 0, s, n->dpart, nb, n->dscal + 2);
   const unsigned g = (unsigned)((n->HW + 255) / 256);
-  hipLaunchKernelGGL(k_net_features, dim3(g), dim3(256), 0, s, alpha, mu_prev, s_prev, taps, ntaps, beta, n->HW,
-                     n->dscal + 2, n->feats, n->aux);
+  hipLaunchKernelGGL(k_net_features, dim3(g), dim3(256), 0, s, alpha, alpha_prev, mu_prev, s_prev, taps, ntaps, beta,
+                     n->HW, n->dscal + 2, n->feats, n->aux);
   NET_HIP(hipGetLastError());
   hipStream_t keep = n->stream;
   n->stream = s;
@@ -590,13 +699,14 @@ cofem_status net_predict(cofem_net* n, const float* alpha, const double* mu_prev
   return COFEM_OK;
 }
 
-cofem_status net_features(cofem_net* n, const float* alpha, const double* mu_prev, const float* s_prev,
-                          const float* taps, int ntaps, double beta, float* feats, float* aux, hipStream_t s) {
+cofem_status net_features(cofem_net* n, const float* alpha, const float* alpha_prev, const double* mu_prev,
+                          const float* s_prev, const float* taps, int ntaps, double beta, float* feats, float* aux,
+                          hipStream_t s) {
   const int nb = n->nred;
   hipLaunchKernelGGL(k_net_mu_sumsq, dim3(nb), dim3(256), 0, s, mu_prev, n->HW, n->dpart);
-  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(64), 0, s, n->dpart, nb, n->dscal + 2);
-  hipLaunchKernelGGL(k_net_features, dim3((unsigned)((n->HW + 255) / 256)), dim3(256), 0, s, alpha, mu_prev, s_prev,
-                     taps, ntaps, beta, n->HW, n->dscal + 2, feats, aux);
+  hipLaunchKernelGGL(k_net_finish_sum, dim3(1), dim3(256), 0, s, n->dpart, nb, n->dscal + 2);
+  hipLaunchKernelGGL(k_net_features, dim3((unsigned)((n->HW + 255) / 256)), dim3(256), 0, s, alpha, alpha_prev,
+                     mu_prev, s_prev, taps, ntaps, beta, n->HW, n->dscal + 2, feats, aux);
   NET_HIP(hipGetLastError());
   return COFEM_OK;
 }
@@ -639,11 +749,13 @@ cofem_status cofem_net_create(int32_t H, int32_t W, uint64_t seed, void* hip_str
   A(&n->g1, (size_t)kNetMaxC * n->HW);
   A(&n->wt, (size_t)kNetMaxC * kNetMaxC * 9);
   A(&n->wpart, (size_t)kNetWgBlocks * (kNetMaxC * kNetMaxC * 9 + kNetMaxC));
-  A(&n->feats, (size_t)4 * n->HW);
+  A(&n->feats, (size_t)kNetCh[0] * n->HW);
   A(&n->aux, (size_t)3 * n->HW);
   A(&n->wbf, (size_t)32 * (MfmaGeom<8>::KP + (kNetLayers - 1) * MfmaGeom<32>::KP));
-  A(&n->dpart, (size_t)n->nred);
-  A(&n->dscal, 4);
+  A(&n->actb[0], (size_t)32 * n->HW);
+  A(&n->actb[1], (size_t)32 * n->HW);
+  A(&n->dpart, (size_t)3 * n->nred);
+  A(&n->dscal, 8);
   if (s == COFEM_OK) {
     std::vector<float> th((size_t)n->np);
     net_init_host(th, seed);

@@ -70,3 +70,20 @@ def test_zero_network_predicts_previous_mean_and_diagonal():
     ref = s.copy()
     ref[:3] = [0.05 / d[0], 0.05 / d[1], 20.0 / d[2]]
     np.testing.assert_allclose(d_hat, ref.reshape(H, W), rtol=1e-14)
+
+
+def test_untrained_network_loss_is_one_per_term():
+    # each loss term is normalised by the untrained network's own error, so a
+    # zero network scores A / (A + f M) + LAMBDA_D T / (T + f n): 1 + LAMBDA_D
+    # up to the normaliser floor f (A = sum (mu_prev - mu_t)^2, M = sum mu_t^2,
+    # T = sum of the squared log targets, n pixels)
+    theta, feats, aux, targets, ch = _sample()
+    theta = np.zeros_like(theta)
+    Lv = L.loss(theta, feats, aux, targets, ch)
+    mu_p, d, sb = aux
+    A = np.sum((mu_p - targets[0]) ** 2)
+    M = np.sum(targets[0] ** 2)
+    T = np.sum(np.log(np.clip(targets[1] * d, 0.05, 20.0) / sb) ** 2)
+    f, n = L.NORM_FLOOR, mu_p.size
+    assert abs(Lv - (A / (A + f * M) + L.LAMBDA_D * T / (T + f * n))) < 1e-12, Lv
+    assert abs(Lv - (1.0 + L.LAMBDA_D)) < 0.01
