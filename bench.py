@@ -15,12 +15,14 @@ inputs and reported under "forms", with the NMSE between the two final mu.
 NMSE against both.  `--workload batched_64` runs the 64-problem batched form.
 
 Besides the throughput line the JSON carries:
-  roofline      the dominant operator kernel's achieved HBM bandwidth
-                (algorithmic bytes per launch / mean launch time, from HIP
-                events the library records on its stream before every launch
-                during the timed steps) against the 8 TB/s MI355X peak, and
-                the counter-measured HBM bytes per launch when a stored
-                rocprofv3 summary matches the current kernel source;
+  roofline      the dominant operator kernel against its roofline: dense
+                passes by HBM (algorithmic bytes per launch / mean launch
+                time, from HIP events the library records on its stream before
+                every launch during the timed steps) against 8 TB/s, with the
+                counter-measured HBM bytes per launch when a stored rocprofv3
+                summary matches the current kernel source; the conv stencil
+                pass by the fp32 vector ALU (its stencil flops per launch /
+                mean launch time) against 157.3 TFLOP/s;
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the
                 first E-step, its CG iteration count fixed to the GPU's),
                 scaled to EM iterations per second with the GPU's mean CG count;
@@ -41,6 +43,19 @@ if ROOT not in sys.path:
 
 METRIC = "EM iters/sec at fixed NMSE vs FP64 oracle; bf16+learned vs plain FP32 CG"
 HBM_PEAK_GBS = 8000.0
+# MI355X fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2
+# (packed FP32) x 2.4 GHz.  The library is built without packed FP32
+# instructions, so its own issue ceiling is half of this (78.6 TFLOP/s).
+FP32_VALU_PEAK_TFS = 157.3
+
+
+def algorithmic_flops(p, which):
+    """Flops one launch of the fused conv operator pass must do: the k x k
+    stencil of Phi and of Phi^T (one FMA per tap each) on every pixel of the
+    K + 1 columns.  The halo recomputation and the alpha/dot epilogue are not
+    counted."""
+    k = p.taps.shape[0]
+    return 2 * 2 * k * k * p.D * (p.K + 1)
 
 
 def log(*a):
@@ -58,13 +73,14 @@ def algorithmic_bytes(p, which, phi_bytes=4):
             return phi_bytes * N * D + D * col + N * col
         # pass 2: Phi, W in; P, R, alpha in; Q out
         return phi_bytes * N * D + N * col + 3 * D * col + 4 * D
-    # conv fused pass: P, R, alpha in; Q out (taps negligible)
-    return 3 * D * col + 4 * D
+    # conv fused iteration: p, r, q, x and alpha in; x, r, p, q out (taps
+    # negligible; the halo re-reads are not counted)
+    return 8 * D * col + 4 * D
 
 
 KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "update": "k_dense_update"},
                 "dense_bf16_ir": {"pass1": "k_dense16_pass1", "pass2": "k_dense16_pass2", "update": "k_dense_update"},
-                "conv": {"pass1": "k_conv_pass", "update": "k_conv_update"}}
+                "conv": {"pass1": "k_conv_fused"}}
 FORMS = {"fp32": "fp32 probes + fp64 mean column",
          "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column)",
          "control": "fp32 CG started from the previous mean and diagonal estimate, Jacobi-preconditioned",
@@ -406,16 +422,28 @@ def main():
         source = "cofem_time_operator back-to-back launches"
     dom = max(ops, key=lambda k: total[k])
     nbytes = algorithmic_bytes(p, dom, phi_bytes)
-    achieved = nbytes / (per[dom] * 1e-3) / 1e9
+    gbs = nbytes / (per[dom] * 1e-3) / 1e9
     traffic = stored_traffic("dense_bf16_ir" if args.form == "bf16_ir" else p.kind, names[dom], p.name)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[dom],
-                "bytes_per_launch": nbytes, "ms_per_launch": round(per[dom], 5), "timing": source,
-                "kernels": {names[k]: {"ms_per_launch": round(per[k], 5), "launches": launches[k]}
-                            for k in per}}
-    log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
-        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak); per-launch us "
-        + ", ".join(f"{names[k]} {per[k] * 1e3:.1f}" for k in per))
+    if p.kind == "conv":
+        # the fused stencil pass is bound by the vector ALU (2 k^2 FMAs per
+        # pixel and column against a few bytes), not by HBM
+        nflops = algorithmic_flops(p, dom)
+        achieved = nflops / (per[dom] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP32_VALU_PEAK_TFS, 4), "traffic": traffic, "kernel": names[dom],
+                    "flops_per_launch": nflops, "bytes_per_launch": nbytes, "hbm_gbs": round(gbs, 1),
+                    "ms_per_launch": round(per[dom], 5), "timing": source}
+        log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.2f} TFLOP/s "
+            f"({100 * achieved / FP32_VALU_PEAK_TFS:.1f}% of the fp32 vector peak), {gbs:.0f} GB/s")
+    else:
+        achieved = gbs
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[dom],
+                    "bytes_per_launch": nbytes, "ms_per_launch": round(per[dom], 5), "timing": source}
+        log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
+            f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
+    roofline["kernels"] = {names[k]: {"ms_per_launch": round(per[k], 5), "launches": launches[k]} for k in per}
+    log("per-launch us " + ", ".join(f"{names[k]} {per[k] * 1e3:.1f}" for k in per))
 
     # the other form on the same inputs (dense): throughput and how far its
     # final mu lies from this form's

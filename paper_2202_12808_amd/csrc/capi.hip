@@ -97,6 +97,9 @@ struct cofem_ctx {
   double *xm = nullptr, *rm = nullptr, *pm = nullptr, *qm = nullptr;
   // conv probe blocks (float or double per the precision mode)
   void *vX = nullptr, *vR = nullptr, *vP = nullptr, *vQ = nullptr, *vVs = nullptr, *vQs = nullptr;
+  // conv: the second buffer set of p, r, q (fused iterations alternate sets)
+  void *vP2 = nullptr, *vR2 = nullptr, *vQ2 = nullptr;
+  double *pm2 = nullptr, *rm2 = nullptr, *qm2 = nullptr;
   // scratch for apply_A
   float *Vs = nullptr, *Qs = nullptr;
   double *Vsm = nullptr, *Qsm = nullptr;
@@ -312,7 +315,7 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->minv, cd.ldD));
   COFEM_TRY(alloc(c, &c->d0, cd.ldD));
   COFEM_TRY(alloc(c, &c->mu0, cd.ldD));
-  void** blocks[6] = {&c->vX, &c->vR, &c->vP, &c->vQ, &c->vVs, &c->vQs};
+  void** blocks[9] = {&c->vX, &c->vR, &c->vP, &c->vQ, &c->vVs, &c->vQs, &c->vP2, &c->vR2, &c->vQ2};
   for (void** b : blocks) {
     if (cd.fp64) {
       double* q = nullptr;
@@ -328,6 +331,9 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->rm, cd.ldD));
   COFEM_TRY(alloc(c, &c->pm, cd.ldD));
   COFEM_TRY(alloc(c, &c->qm, cd.ldD));
+  COFEM_TRY(alloc(c, &c->rm2, cd.ldD));
+  COFEM_TRY(alloc(c, &c->pm2, cd.ldD));
+  COFEM_TRY(alloc(c, &c->qm2, cd.ldD));
   COFEM_TRY(alloc(c, &c->Vsm, cd.ldD));
   COFEM_TRY(alloc(c, &c->Qsm, cd.ldD));
   const int ncols = c->K + 1;
@@ -335,10 +341,10 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
   // red_pass also serves the start of a preconditioned solve (nupd blocks)
   const int64_t nblks[3] = {nupd, nupd, npass > nupd ? npass : nupd};
-  const int nvs[3] = {1, 3, 3};  // the preconditioned update reduces two values, its start three
+  const int nvs[3] = {1, 3, 5};  // the preconditioned start reduces three values, a fused iteration five
   for (int i = 0; i < 3; ++i) {
     COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], nvs[i], ncols));
-    COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * 3));
+    COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
     COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
   }
   COFEM_HIP(c, conv_b0(cd, c->taps, p.y, c->beta, c->b0, c->stream));
@@ -774,20 +780,21 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
-    } else if (conv_pcg(c)) {
-      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
-      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
-                             c->red_pass, c->st, 0, c->stream, c->active_minv));
-      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
-      COFEM_HIP(c, conv_update_pcg(c->cd, c->active_minv, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm,
-                                   c->red_upd, c->st, c->stream));
     } else {
+      // conv: the first launch of a solve is the operator pass on the start
+      // direction (set 0); each later one a fused iteration, the previous
+      // update applied while staging, reading set (it - 1) % 2 and writing
+      // set it % 2 (so a solve needs one launch more than it has updates)
+      const float* minv = conv_pcg(c) ? c->active_minv : nullptr;
+      const ConvState sets[2] = {{c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm},
+                                 {c->vP2, c->vR2, c->vQ2, c->pm2, c->rm2, c->qm2}};
       COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
-      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
-                             c->red_pass, c->st, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
-      COFEM_HIP(c, conv_update(c->cd, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm, c->red_upd,
-                               c->st, c->stream));
+      if (it == 0)
+        COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
+                               c->red_pass, c->st, 0, c->stream, minv));
+      else
+        COFEM_HIP(c, conv_fused(c->cd, c->taps, sets[(it - 1) & 1], sets[it & 1], c->vX, c->xm, c->alpha, c->beta,
+                                minv, c->red_pass, c->st, c->stream));
     }
   }
   return COFEM_OK;
@@ -936,10 +943,12 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     COFEM_HIP(c, conv_init(c->cd, c->seed, t, c->b0, c->vX, c->vR, c->vP, c->xm, c->rm, c->pm, c->red_init,
                            c->st, c->stream));
   }
-  const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
+  // launches per solve: conv needs one more than its updates (the first
+  // operator pass)
+  const int limit = (c->fixed_iters > 0 ? c->fixed_iters : c->U) + (c->kind == COFEM_CONV2D_CIRC ? 1 : 0);
   // First chunk: the previous solve's count (CG counts drift slowly across EM
   // iterations), then `poll`-sized chunks until the device flag says stop.
-  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 : c->poll;
+  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 + (c->kind == COFEM_CONV2D_CIRC ? 1 : 0) : c->poll;
   if (chunk > limit) chunk = limit;
   int enqueued = 0;
   for (;;) {
@@ -969,7 +978,8 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   COFEM_TRY(mark(c, -1, 0));
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
   COFEM_TRY(read_state(c));
-  COFEM_TRY(collect_times(c, c->host_st->iter));
+  // (a conv solve of n updates has n + 1 working launches)
+  COFEM_TRY(collect_times(c, c->host_st->iter + (c->kind == COFEM_CONV2D_CIRC ? 1 : 0)));
   c->has_solution = true;
   c->prev_iters = c->host_st->iter;
   c->t_next = t + 1;

@@ -330,6 +330,50 @@ __device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
   finish_step(st, dots, load_cg_ctl(st));
 }
 
+// Finishes a fused conv iteration (an update followed by an operator pass):
+// v holds, per column (nc values each), rho' = r^T z, r^T r, gam, del, eta.
+// The update's part: rho <- rho', the iteration count and the stop test on
+// sqrt(sum r^T r) / ||B||_F (as finish_update_pcg); then, for the next
+// update, a = rho'/gam and b = (rho' - 2 a del + a^2 eta)/rho' (as
+// finish_step).
+__device__ __forceinline__ void finish_fused(CgScalars* st, const double* v, int nc, const CgCtl& k) {
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) {
+    const int it = k.iter + 1;
+    double rr = 0.0, rz = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      rz += v[c];
+      rr += v[nc + c];
+    }
+    const bool finite = isfinite(rr) && isfinite(rz);
+    const double ratio = k.nB > 0.0 ? sqrt(rr) / k.nB : 0.0;
+    st->ratio = ratio;
+    st->iter = it;
+    s_bad = finite ? 0 : 1;
+    st->stop = (it >= k.limit) || (!k.fixed && ratio < k.tol) || !finite;
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < nc) {
+    const double rho = v[c], g = v[2 * nc + c], dl = v[3 * nc + c], et = v[4 * nc + c];
+    st->rho[c] = rho;
+    const double a = (g != 0.0) ? rho / g : 0.0;
+    st->gam[c] = g;
+    st->del[c] = dl;
+    st->eta[c] = et;
+    st->a[c] = a;
+    double rn = rho - 2.0 * a * dl + a * a * et;
+    if (rn < 0.0) rn = 0.0;
+    st->b[c] = (rho != 0.0) ? rn / rho : 0.0;
+    if (!(isfinite(g) && isfinite(dl) && isfinite(et))) s_bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_bad) {
+    st->numeric_error = 1;
+    st->stop = 1;
+  }
+}
+
 // Finishes the initial residual R = B: rho_c = ||b_c||^2 (in shared memory).
 __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
   const int nc = st->kp + 1;
@@ -535,6 +579,15 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
                      void* P, double* xm, double* rm, double* pm, const ConvReduce& red,
                      CgScalars* st, hipStream_t s);
 int64_t conv_pass_blocks(const ConvDims& cd);
+// One of the two buffer sets of the conv CG direction, residual and operator
+// product (probe columns of the context's type, mean column float64).
+struct ConvState {
+  void *P, *R, *Q;
+  double *pm, *rm, *qm;
+};
+hipError_t conv_fused(const ConvDims& cd, const float* taps, const ConvState& s0, const ConvState& s1, void* X,
+                      double* xm, const float* alpha, double beta, const float* minv, const ConvReduce& red,
+                      CgScalars* st, hipStream_t s);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,
@@ -543,16 +596,10 @@ hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const
 hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double* b0, const float* minv,
                          const void* Qx, const double* qxm, void* X, void* R, void* P, double* xm, double* rm,
                          double* pm, const ConvReduce& red, CgScalars* st, hipStream_t s);
-hipError_t conv_update_pcg(const ConvDims& cd, const float* minv, void* X, void* R, void* P, const void* Q,
-                           double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
-                           CgScalars* st, hipStream_t s);
 hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
                       double* xm, hipStream_t s);
 hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const float* alpha, float* minv,
                        hipStream_t s);
-hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void* Q, double* xm,
-                       double* rm, double* pm, const double* qm, const ConvReduce& red,
-                       CgScalars* st, hipStream_t s);
 hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const double* b0, const void* Q,
                            const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s);
 hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,

@@ -4,14 +4,16 @@
 // dictionary with a fast apply, Sec. 1 and Sec. 3.2 of arXiv 2202.12808):
 //   (Phi z)[u, v]   = sum_{a,b} h[a,b] z[(u - a + c) mod H, (v - b + c) mod W]
 //   (Phi^T w)[u, v] = sum_{a,b} h[a,b] w[(u + a - c) mod H, (v + b - c) mod W]
-// with c = (ks - 1)/2.  One CG iteration's operator application
+// with c = (ks - 1)/2.  The operator application
 //   q = beta Phi^T (Phi p) + alpha (.) p
-// runs as a single pass per 32x32 output tile and column: the tile of p with
-// a 2c halo is staged in LDS, Phi p is formed on the tile with a c halo in a
-// second LDS buffer, and Phi^T of that gives q on the tile.  Each output row
-// strip of 4 pixels is register-blocked against a column of taps.  The pass
-// also forms gam = p^T q, del = r^T q and eta = q^T q; the update kernel then
-// does x += a p, r -= a q and p <- r + b p in one sweep.
+// runs as a single pass per output tile and column: the tile of p with a 2c
+// halo is staged in LDS, Phi p is formed on the tile with a c halo in a
+// second LDS buffer, and Phi^T of that gives q on the tile, each thread
+// computing 4x4 output blocks.  The pass also forms gam = p^T q,
+// del = r^T M^-1 q and eta = q^T M^-1 q.  The first CG iteration of a solve
+// is that pass alone; each later one is a fused launch that applies the
+// previous update (x += a p, r -= a q, p <- M^-1 r + b p) while it stages p
+// and then runs the pass, so the state is streamed once per iteration.
 //
 // State layout: probe columns are column-major images (column k at k * ldD,
 // pixel j = u * W + v) of type TP (float, or double in the float64 mode); the
@@ -83,24 +85,98 @@ __device__ __forceinline__ void lds_row(const T* src, T (&x)[N]) {
   }
 }
 
+// The CG update that a fused iteration applies while it stages p: the
+// previous iteration's p, r and q (read: a neighbouring tile's halo reads
+// them too, so the new r and p go to the other buffer of a pair), x updated in
+// place, the new r and p written for the tile's own pixels, and the step
+// scalars of the column.
+template <typename T>
+struct FusedUpd {
+  const T* P0;
+  const T* R0;
+  const T* Q0;
+  T* X;
+  T* P1;
+  T* R1;
+  T a, b;
+};
+
 // One output tile of one column of the fused operator pass, in precision T:
 // q = beta Phi^T (Phi p) + alpha (.) p on the tile, written to Q, and the
 // thread's parts of gam = p^T q, del = r^T M^-1 q, eta = q^T M^-1 q.
 // `near` (uniform): every staged coordinate is within one period of the
 // image, so wrapping is a compare and an add.
-template <int KS, int TILE, typename T, typename TapsT>
+// FUSED: p is not read but formed while staging from the previous
+// iteration's state (`fu`): r' = r - a q, z = M^-1 r', p' = z + b p (the
+// textbook CG update's arithmetic), with x += a p, r' and p' written and
+// dots[3..4] = r'^T z, r'^T r' summed for the tile's own pixels; R and P are
+// then unused and the epilogue's r is r' recomputed from fu.R0 and fu.Q0.
+template <int KS, int TILE, typename T, typename TapsT, bool FUSED = false>
 __device__ __forceinline__ void conv_tile(TapsT h, int H, int W, int tu0, int tv0, bool near,
                                           const T* __restrict__ P, const T* __restrict__ R,
                                           const float* __restrict__ alpha, T beta,
                                           const float* __restrict__ minv, T* __restrict__ Q, T* sP, T* sT,
-                                          double dots[3]) {
+                                          double* dots, const FusedUpd<T>* fu = nullptr) {
   using G = ConvGeom<KS, TILE>;
   constexpr int c = G::c;
   const int tid = threadIdx.x;
   // stage 0: p on the tile plus a 2c halo (circular wrap).  Every load of
   // the thread is issued before the first LDS store, so the staging costs
   // about one memory latency, not one per element.
-  {
+  if constexpr (FUSED) {
+    constexpr int N0 = G::SPH * G::SPW, PER = (N0 + kThreads - 1) / kThreads, GRP = 4;
+    const T a = fu->a, b = fu->b;
+    double rz = 0.0, rr = 0.0;
+#pragma unroll
+    for (int k0 = 0; k0 < PER; k0 += GRP) {
+      T p0[GRP], r0[GRP], q0[GRP], x0[GRP];
+      float mv[GRP];
+      int64_t ix[GRP];
+      bool ok[GRP], own[GRP];
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+        const int e = tid + (k0 + k) * kThreads;
+        ok[k] = k0 + k < PER && e < N0;
+        own[k] = false;
+        if (ok[k]) {
+          const int i = e / G::SPW, j = e - (e / G::SPW) * G::SPW;
+          int u = tu0 - 2 * c + i, v = tv0 - 2 * c + j;
+          // the tile's own pixels: unwrapped, inside the tile and the image
+          own[k] = i >= 2 * c && i < 2 * c + TILE && j >= 2 * c && j < 2 * c + TILE && u < H && v < W;
+          if (near) {
+            u = u < 0 ? u + H : (u >= H ? u - H : u);
+            v = v < 0 ? v + W : (v >= W ? v - W : v);
+          } else {
+            u = wrap(u, H);
+            v = wrap(v, W);
+          }
+          ix[k] = (int64_t)u * W + v;
+          p0[k] = fu->P0[ix[k]];
+          r0[k] = fu->R0[ix[k]];
+          q0[k] = fu->Q0[ix[k]];
+          mv[k] = minv ? minv[ix[k]] : 1.0f;
+          if (own[k]) x0[k] = fu->X[ix[k]];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < GRP; ++k) {
+        if (!ok[k]) continue;
+        const T r1 = fma(-a, q0[k], r0[k]);
+        const T z = minv ? (T)mv[k] * r1 : r1;
+        const T p1 = fma(b, p0[k], z);
+        sP[tid + (k0 + k) * kThreads] = p1;
+        if (own[k]) {
+          fu->X[ix[k]] = fma(a, p0[k], x0[k]);
+          fu->R1[ix[k]] = r1;
+          fu->P1[ix[k]] = p1;
+          rz += (double)r1 * (double)z;
+          rr += (double)r1 * (double)r1;
+        }
+      }
+    }
+    dots[3] = rz;
+    dots[4] = rr;
+  } else {
     constexpr int N0 = G::SPH * G::SPW, PER = (N0 + kThreads - 1) / kThreads;
     T pv[PER];
 #pragma unroll
@@ -225,7 +301,10 @@ __device__ __forceinline__ void conv_tile(TapsT h, int H, int W, int tu0, int tv
       ok[k] = u < H && v < W;
       ix[k] = (int64_t)u * W + v;
       al[k] = ok[k] ? alpha[ix[k]] : 0.0f;
-      rv[k] = ok[k] ? R[ix[k]] : T(0);
+      if constexpr (FUSED)  // r' = r - a q, the value the staging wrote
+        rv[k] = ok[k] ? fma(-fu->a, fu->Q0[ix[k]], fu->R0[ix[k]]) : T(0);
+      else
+        rv[k] = ok[k] ? R[ix[k]] : T(0);
       mv[k] = (ok[k] && minv) ? minv[ix[k]] : 1.0f;
     }
 #pragma unroll
@@ -343,6 +422,156 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                           nblk_alloc, col, K + 1, 3, mine, tot))
     return;
   finish_step(st, tot, ctl);
+}
+
+// ------------------------------------------------ fused CG iteration
+// One launch per CG iteration after the first: the update of the previous
+// iteration (x += a p, r -= a q, z = M^-1 r, p = z + b p) applied while p is
+// staged, then the operator pass on the new p, with the update's r^T z and
+// r^T r and the pass's gam, del, eta reduced together.  Its finish applies
+// the stop test on ||r||_F and, if the solve goes on, sets the next step's a
+// and b -- the same arithmetic and decisions as a separate update followed by
+// a pass, with the update's stream of the state overlapped with the
+// stencil's arithmetic (a solve's last launch computes one operator product
+// that is not used).  p, r, q alternate between two buffers (a tile's halo
+// reads its neighbours' old values while they write their new ones); x is
+// updated in place.  The grid is the operator pass's.
+template <int KS, typename TP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_fused(
+    const float* __restrict__ taps, int H, int W, int64_t ldD, int K, int tilesX, const TP* __restrict__ P0,
+    const TP* __restrict__ R0, const TP* __restrict__ Q0, TP* __restrict__ X, TP* __restrict__ P1,
+    TP* __restrict__ R1, TP* __restrict__ Q1, const double* __restrict__ pm0, const double* __restrict__ rm0,
+    const double* __restrict__ qm0, double* __restrict__ xm, double* __restrict__ pm1, double* __restrict__ rm1,
+    double* __restrict__ qm1, const float* __restrict__ alpha, double beta, const float* __restrict__ minv,
+    ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st) {
+  if (st->stop) return;
+  const CgCtl ctl = load_cg_ctl(st);
+  using G64 = ConvGeom<KS, kConvTile>;
+  using G32 = ConvGeom<KS, kConvTile / 2>;
+  constexpr int kS = sizeof(TP) == 8 ? 4 : 1;  // parts per probe column
+  constexpr size_t kBytes = kS == 4 ? G32::LDS * sizeof(double)
+                                    : (G64::LDS * sizeof(float) > G32::LDS * sizeof(double) ? G64::LDS * sizeof(float)
+                                                                                             : G32::LDS * sizeof(double));
+  __shared__ __align__(16) unsigned char sbuf[kBytes];
+  __shared__ double sTapsD[KS * KS];
+  __shared__ float sTapsF[KS * KS];
+  if (threadIdx.x < KS * KS) {
+    sTapsD[threadIdx.x] = (double)taps[threadIdx.x];
+    sTapsF[threadIdx.x] = taps[threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t ntiles = gridDim.x;
+  int64_t tile = blockIdx.x;
+  if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
+  const int ty = (int)(tile / tilesX), tx = (int)(tile - (tile / tilesX) * tilesX);
+  const int z = blockIdx.z;
+  int col, part, nparts;
+  if (z < 4) {
+    col = K;
+    part = z;
+    nparts = 4;
+  } else {
+    col = (z - 4) / kS;
+    part = (z - 4) - col * kS;
+    nparts = kS;
+  }
+  int tu0 = ty * kConvTile, tv0 = tx * kConvTile;
+  double dots[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (nparts == 4) {
+    tu0 += (part >> 1) * (kConvTile / 2);
+    tv0 += (part & 1) * (kConvTile / 2);
+  }
+  if (tu0 >= H || tv0 >= W) {
+    // a quadrant past the image edge: no pixels, zero sums
+  } else if (nparts == 4) {
+    const bool near = H >= G32::TR && W >= G32::SPW - 2 * G32::c;
+    double* sb = reinterpret_cast<double*>(sbuf);
+    Taps<double> hd(sTapsD);
+    const double a = st->a[col], b = st->b[col];
+    if (col == K) {
+      const FusedUpd<double> fu{pm0, rm0, qm0, xm, pm1, rm1, a, b};
+      conv_tile<KS, kConvTile / 2, double, Taps<double>, true>(hd, H, W, tu0, tv0, near, nullptr, nullptr, alpha,
+                                                               beta, minv, qm1, sb, sb + G32::SPH * G32::SPW, dots,
+                                                               &fu);
+    } else {
+      const int64_t off = (int64_t)col * ldD;
+      const double* dP0 = reinterpret_cast<const double*>(P0) + off;
+      const double* dR0 = reinterpret_cast<const double*>(R0) + off;
+      const double* dQ0 = reinterpret_cast<const double*>(Q0) + off;
+      const FusedUpd<double> fu{dP0, dR0, dQ0, reinterpret_cast<double*>(X) + off,
+                                reinterpret_cast<double*>(P1) + off, reinterpret_cast<double*>(R1) + off, a, b};
+      conv_tile<KS, kConvTile / 2, double, Taps<double>, true>(hd, H, W, tu0, tv0, near, nullptr, nullptr, alpha,
+                                                               beta, minv, reinterpret_cast<double*>(Q1) + off, sb,
+                                                               sb + G32::SPH * G32::SPW, dots, &fu);
+    }
+  } else if constexpr (kS == 1) {  // a float column's 64 x 64 tile
+    const bool near = H >= G64::TR && W >= G64::SPW - 2 * G64::c;
+    float* sb = reinterpret_cast<float*>(sbuf);
+    Taps<float> hf(sTapsF);
+    const int64_t off = (int64_t)col * ldD;
+    const FusedUpd<float> fu{reinterpret_cast<const float*>(P0) + off, reinterpret_cast<const float*>(R0) + off,
+                             reinterpret_cast<const float*>(Q0) + off, reinterpret_cast<float*>(X) + off,
+                             reinterpret_cast<float*>(P1) + off, reinterpret_cast<float*>(R1) + off,
+                             (float)st->a[col], (float)st->b[col]};
+    conv_tile<KS, kConvTile, float, Taps<float>, true>(hf, H, W, tu0, tv0, near, nullptr, nullptr, alpha,
+                                                       (float)beta, minv, reinterpret_cast<float*>(Q1) + off, sb,
+                                                       sb + G64::SPH * G64::SPW, dots, &fu);
+  }
+  __shared__ double shm[8];
+  __shared__ double mine[5], tot[5 * kMaxCols];
+  // r^T z, r^T r, gam, del, eta
+  const double v0 = block_sum(dots[3], shm);
+  const double v1 = block_sum(dots[4], shm);
+  const double v2 = block_sum(dots[0], shm);
+  const double v3 = block_sum(dots[1], shm);
+  const double v4 = block_sum(dots[2], shm);
+  if (threadIdx.x == 0) {
+    mine[0] = v0;
+    mine[1] = v1;
+    mine[2] = v2;
+    mine[3] = v3;
+    mine[4] = v4;
+  }
+  __syncthreads();
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, tile * nparts + part, ntiles * nparts,
+                          nblk_alloc, col, K + 1, 5, mine, tot))
+    return;
+  finish_fused(st, tot, K + 1, ctl);
+}
+
+template <typename TP>
+static hipError_t launch_conv_fused(const ConvDims& cd, const float* taps, const ConvState& s0, const ConvState& s1,
+                                    void* X, double* xm, const float* alpha, double beta, const float* minv,
+                                    const ConvReduce& red, CgScalars* st, hipStream_t s) {
+  constexpr int kS = sizeof(TP) == 8 ? 4 : 1;
+  const dim3 grid((unsigned)(cd.tilesX * cd.tilesY), 1, (unsigned)(4 + cd.K * kS));
+  const int64_t nblk_alloc = conv_pass_blocks(cd);
+#define COFEM_FUSED_CASE(KS)                                                                                    \
+  case KS:                                                                                                      \
+    hipLaunchKernelGGL((k_conv_fused<KS, TP>), grid, dim3(kThreads), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K,        \
+                       cd.tilesX, static_cast<const TP*>(s0.P), static_cast<const TP*>(s0.R),                     \
+                       static_cast<const TP*>(s0.Q), static_cast<TP*>(X), static_cast<TP*>(s1.P),                  \
+                       static_cast<TP*>(s1.R), static_cast<TP*>(s1.Q), s0.pm, s0.rm, s0.qm, xm, s1.pm, s1.rm,      \
+                       s1.qm, alpha, beta, minv, red, nblk_alloc, st);                                            \
+    break;
+  switch (cd.ks) {
+    COFEM_FUSED_CASE(1)
+    COFEM_FUSED_CASE(3)
+    COFEM_FUSED_CASE(5)
+    COFEM_FUSED_CASE(7)
+    COFEM_FUSED_CASE(9)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef COFEM_FUSED_CASE
+  return hipGetLastError();
+}
+
+hipError_t conv_fused(const ConvDims& cd, const float* taps, const ConvState& s0, const ConvState& s1, void* X,
+                      double* xm, const float* alpha, double beta, const float* minv, const ConvReduce& red,
+                      CgScalars* st, hipStream_t s) {
+  if (cd.fp64) return launch_conv_fused<double>(cd, taps, s0, s1, X, xm, alpha, beta, minv, red, st, s);
+  return launch_conv_fused<float>(cd, taps, s0, s1, X, xm, alpha, beta, minv, red, st, s);
 }
 
 template <typename TP>
@@ -473,107 +702,6 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
   return hipGetLastError();
 }
 
-// ------------------------------------------------ CG update
-// x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2 and the stop test.
-// One column of the update: x += a p; r -= a q; z = M^-1 r (z = r without
-// a preconditioner); p <- z + b p; returns r^T z and r^T r.  Each thread
-// takes four elements per round, all loaded before any is used (one memory
-// latency per round instead of one per element); the sums run in the same
-// element order as a one-element loop.
-template <typename T>
-__device__ __forceinline__ void conv_update_col(int64_t D, T* __restrict__ X, T* __restrict__ R,
-                                                T* __restrict__ P, const T* __restrict__ Q,
-                                                const float* __restrict__ minv, T a, T b, double* rz, double* rr) {
-  constexpr int U = 4;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t d0 = gtid; d0 < D; d0 += U * gstride) {
-    T pv[U], xv[U], rv[U], qv[U];
-    float mv[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int64_t d = d0 + k * gstride;
-      if (d < D) {
-        pv[k] = P[d];
-        xv[k] = X[d];
-        rv[k] = R[d];
-        qv[k] = Q[d];
-        mv[k] = minv ? minv[d] : 1.0f;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int64_t d = d0 + k * gstride;
-      if (d < D) {
-        X[d] = fma(a, pv[k], xv[k]);
-        const T r = fma(-a, qv[k], rv[k]);
-        R[d] = r;
-        const T z = minv ? (T)mv[k] * r : r;
-        P[d] = fma(b, pv[k], z);
-        s0 += (double)r * (double)z;
-        s1 += (double)r * (double)r;
-      }
-    }
-  }
-  *rz = s0;
-  *rr = s1;
-}
-
-// x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2
-template <typename T>
-__device__ __forceinline__ double conv_update_column(int64_t D, T* __restrict__ X, T* __restrict__ R,
-                                                     T* __restrict__ P, const T* __restrict__ Q,
-                                                     T a, T b) {
-  double rz, rr;
-  conv_update_col<T>(D, X, R, P, Q, nullptr, a, b, &rz, &rr);
-  return rr;
-}
-
-template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_update(int64_t D, int64_t ldD, int K,
-                                                     TP* __restrict__ X, TP* __restrict__ R,
-                                                     TP* __restrict__ P, const TP* __restrict__ Q,
-                                                     double* __restrict__ xm,
-                                                     double* __restrict__ rm,
-                                                     double* __restrict__ pm,
-                                                     const double* __restrict__ qm, ConvReduce red,
-                                                     CgScalars* st) {
-  if (st->stop) return;
-  const int col = blockIdx.y;
-  double acc;
-  if (col == K) {
-    acc = conv_update_column<double>(D, xm, rm, pm, qm, st->a[K], st->b[K]);
-  } else {
-    const int64_t off = (int64_t)col * ldD;
-    acc = conv_update_column<TP>(D, X + off, R + off, P + off, Q + off, (TP)st->a[col], (TP)st->b[col]);
-  }
-  __shared__ double shm[8];
-  __shared__ double mine[1], tot[kMaxCols];
-  const double tot_b = block_sum(acc, shm);
-  if (threadIdx.x == 0) mine[0] = tot_b;
-  __syncthreads();
-  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col,
-                          K + 1, 1, mine, tot))
-    return;
-  finish_update(st, tot);
-}
-
-hipError_t conv_update(const ConvDims& cd, void* X, void* R, void* P, const void* Q, double* xm,
-                       double* rm, double* pm, const double* qm, const ConvReduce& red,
-                       CgScalars* st, hipStream_t s) {
-  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
-  if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_update<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K,
-                       static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P),
-                       static_cast<const double*>(Q), xm, rm, pm, qm, red, st);
-  else
-    hipLaunchKernelGGL(k_conv_update<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K,
-                       static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P),
-                       static_cast<const float*>(Q), xm, rm, pm, qm, red, st);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------ preconditioned CG from a starting block
 // (warm-started and learned forms).  M^-1 = diag(minv) for every column (null:
 // identity).  With a start X0 (already in X / xm) and Q = A X0 from an
@@ -649,60 +777,7 @@ hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double*
 }
 
 // x += a p ; r -= a q ; z = M^-1 r ; p <- z + b p ; rho' = r^T z, ||r||^2.
-template <typename T>
-__device__ __forceinline__ void conv_update_pcg_column(int64_t D, T* __restrict__ X, T* __restrict__ R,
-                                                       T* __restrict__ P, const T* __restrict__ Q,
-                                                       const float* __restrict__ minv, T a, T b, double* rz,
-                                                       double* rr) {
-  conv_update_col<T>(D, X, R, P, Q, minv, a, b, rz, rr);
-}
 
-template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_update_pcg(int64_t D, int64_t ldD, int K, const float* __restrict__ minv,
-                                                         TP* __restrict__ X, TP* __restrict__ R, TP* __restrict__ P,
-                                                         const TP* __restrict__ Q, double* __restrict__ xm,
-                                                         double* __restrict__ rm, double* __restrict__ pm,
-                                                         const double* __restrict__ qm, ConvReduce red,
-                                                         CgScalars* st) {
-  if (st->stop) return;
-  const int col = blockIdx.y;
-  double rz, rr;
-  if (col == K) {
-    conv_update_pcg_column<double>(D, xm, rm, pm, qm, minv, st->a[K], st->b[K], &rz, &rr);
-  } else {
-    const int64_t off = (int64_t)col * ldD;
-    conv_update_pcg_column<TP>(D, X + off, R + off, P + off, Q + off, minv, (TP)st->a[col], (TP)st->b[col], &rz,
-                               &rr);
-  }
-  __shared__ double shm[8];
-  __shared__ double mine[2], tot[2 * kMaxCols];
-  const double v0 = block_sum(rz, shm);
-  const double v1 = block_sum(rr, shm);
-  if (threadIdx.x == 0) {
-    mine[0] = v0;
-    mine[1] = v1;
-  }
-  __syncthreads();
-  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col, K + 1, 2, mine,
-                          tot))
-    return;
-  finish_update_pcg(st, tot, K + 1);
-}
-
-hipError_t conv_update_pcg(const ConvDims& cd, const float* minv, void* X, void* R, void* P, const void* Q,
-                           double* xm, double* rm, double* pm, const double* qm, const ConvReduce& red,
-                           CgScalars* st, hipStream_t s) {
-  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
-  if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_update_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, minv,
-                       static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P),
-                       static_cast<const double*>(Q), xm, rm, pm, qm, red, st);
-  else
-    hipLaunchKernelGGL(k_conv_update_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, minv,
-                       static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P),
-                       static_cast<const float*>(Q), xm, rm, pm, qm, red, st);
-  return hipGetLastError();
-}
 
 // Starting block X0 = [max(d0, 0) (.) p_1 .. max(d0, 0) (.) p_K | mu0] (d0 null:
 // zero probe columns; mu0 null: keep xm as it is, the previous solve's mean
