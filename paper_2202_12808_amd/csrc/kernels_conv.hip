@@ -124,7 +124,7 @@ __device__ __forceinline__ void conv_tile(TapsT h, int H, int W, int tu0, int tv
   // the thread is issued before the first LDS store, so the staging costs
   // about one memory latency, not one per element.
   if constexpr (FUSED) {
-    constexpr int N0 = G::SPH * G::SPW, PER = (N0 + kThreads - 1) / kThreads, GRP = 4;
+    constexpr int N0 = G::SPH * G::SPW, PER = (N0 + kThreads - 1) / kThreads, GRP = 7;
     const T a = fu->a, b = fu->b;
     double rz = 0.0, rr = 0.0;
 #pragma unroll
