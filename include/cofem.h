@@ -48,7 +48,7 @@ typedef enum cofem_status {
 } cofem_status;
 
 /* cofem_problem.kind */
-enum { COFEM_DENSE = 0, COFEM_CONV2D_CIRC = 1 };
+enum { COFEM_DENSE = 0, COFEM_CONV2D_CIRC = 1, COFEM_DCT_MASK = 2 };
 /* cofem_problem.phi_dtype */
 enum { COFEM_F32 = 0, COFEM_BF16 = 1 };
 /* cofem_params.precision:
@@ -105,9 +105,19 @@ enum {
  *   taps    device, kh x kw float32, row-major; kh == kw, odd, 1..9;
  *   (Phi z)[u, v] = sum_{a,b} taps[a, b] * z[(u - a + ch) mod H, (v - b + cw) mod W],
  *   ch = (kh - 1) / 2, cw = (kw - 1) / 2; Phi^T is the matching correlation.
+ * kind == COFEM_DCT_MASK (the structured dictionary of Sec. 4: an inverse DCT
+ * followed by an undersampling mask):
+ *   D = 2^p with 12 <= p <= 20; 1 <= N <= D;
+ *   rows    device, N int32: the observed samples, distinct, in [0, D);
+ *   (Phi z)_i = (C^T z)[rows[i]] with C the orthonormal DCT-II matrix,
+ *   C[k, n] = c_k cos(pi (2n + 1) k / 2D), c_0 = sqrt(1/D), c_k = sqrt(2/D),
+ *   so C^T is the inverse DCT and Phi Phi^T = I_N.  Precision COFEM_PREC_FP32
+ *   only.  rows is copied to the host once to check it (COFEM_ERR_INVALID_ARG
+ *   when an index repeats or is out of range).
  * y         device, N float32.
- * phi, taps and y are read during cofem_init only (the library keeps its own
- * packed copy of Phi and the vector beta Phi^T y); the caller keeps ownership.
+ * phi, taps, rows and y are read during cofem_init only (the library keeps its
+ * own packed copy of Phi or the mask, and the vector beta Phi^T y); the caller
+ * keeps ownership.
  */
 typedef struct cofem_problem {
   int32_t kind;
@@ -119,6 +129,7 @@ typedef struct cofem_problem {
   int32_t H, W, kh, kw;
   const float* taps;
   const float* y;
+  const int32_t* rows;
 } cofem_problem;
 
 /*

@@ -8,6 +8,7 @@ HIP package: the two share no code, table or constant generator.
 from .cofem_oracle import (  # noqa: F401
     ALPHA_MAX_DEFAULT,
     ConvOperator,
+    DctMaskOperator,
     DenseOperator,
     cg_solve,
     cofem,

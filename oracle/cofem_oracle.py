@@ -23,6 +23,9 @@ Readings of the paper taken here (each is also a row of the design notes):
   alpha <- 1 / max(mu^2 + s, 1/alpha_max).  Exact EM never hits the floor.
 * The structured dictionary is a 2D circular convolution with an odd k x k
   kernel centred at ((kh-1)/2, (kw-1)/2); N = D = H*W; pixel index j = u*W + v.
+* The DCT dictionary of Sec. 4 is Phi = S C^T with C the orthonormal DCT-II
+  matrix (C^T is the inverse DCT) over a length-D signal and S the selection
+  of N distinct observed samples (``DctMaskOperator``).
 
 Pins: every function here is checked in ``tests/test_oracle_*.py`` against
 closed forms, brute force, textbook factorizations or the published SplitMix64
@@ -156,6 +159,58 @@ class ConvOperator:
 
     def column_norms_sq(self) -> np.ndarray:
         return np.full(self.D, float(np.sum(self.taps * self.taps)))
+
+
+class DctMaskOperator:
+    """Inverse DCT followed by an undersampling mask (the structured dictionary
+    of Sec. 4, "Structured Dictionary"): Phi = S C^T in R^{N x D}.
+
+    C is the D x D orthonormal DCT-II matrix,
+        C[k, n] = c_k cos(pi (2n + 1) k / (2D)),  c_0 = sqrt(1/D), c_k = sqrt(2/D),
+    so C^T (the orthonormal DCT-III) is the inverse DCT, and S keeps the N
+    observed samples ``rows`` (distinct indices into the length-D signal):
+    (Phi z)_i = (C^T z)[rows[i]].  z holds DCT coefficients.  The paper fixes
+    neither the DCT type, its normalisation nor how the samples are chosen;
+    with the orthonormal type II, Phi Phi^T = I_N.  apply / apply_t call
+    scipy.fft's idct / dct (a library transform: the definition above, in
+    O(D log D)), one call for all columns.
+    """
+
+    def __init__(self, rows: np.ndarray, D: int):
+        rows = np.asarray(rows, dtype=np.int64)
+        self.D = int(D)
+        if rows.ndim != 1 or rows.size == 0 or rows.min() < 0 or rows.max() >= self.D:
+            raise ValueError("rows must be indices into [0, D)")
+        if np.unique(rows).size != rows.size:
+            raise ValueError("rows must be distinct")
+        self.rows = rows
+        self.N = rows.size
+
+    def apply(self, v: np.ndarray) -> np.ndarray:
+        import scipy.fft as sf
+
+        v = np.asarray(v, dtype=np.float64)
+        return sf.idct(v, type=2, norm="ortho", axis=0)[self.rows]
+
+    def apply_t(self, w: np.ndarray) -> np.ndarray:
+        import scipy.fft as sf
+
+        w = np.asarray(w, dtype=np.float64)
+        full = np.zeros((self.D,) + w.shape[1:])
+        full[self.rows] = w
+        return sf.dct(full, type=2, norm="ortho", axis=0)
+
+    def column_norms_sq(self) -> np.ndarray:
+        """||Phi e_k||^2 = sum over observed samples n of C[k, n]^2, from the
+        cosine definition (O(N D): small problems)."""
+        k = np.arange(self.D, dtype=np.float64)[:, None]
+        c2 = np.full(self.D, 2.0 / self.D)
+        c2[0] = 1.0 / self.D
+        out = np.zeros(self.D)
+        for lo in range(0, self.N, 1024):
+            n = self.rows[lo:lo + 1024].astype(np.float64)[None, :]
+            out += np.sum(np.cos(np.pi * (2.0 * n + 1.0) * k / (2.0 * self.D)) ** 2, axis=1)
+        return c2 * out
 
 
 _POOL = None

@@ -26,6 +26,7 @@ COFEM_ERR_UNSUPPORTED = 5
 
 COFEM_DENSE = 0
 COFEM_CONV2D_CIRC = 1
+COFEM_DCT_MASK = 2
 COFEM_F32 = 0
 COFEM_BF16 = 1
 COFEM_PREC_FP32 = 0
@@ -54,7 +55,8 @@ _STATUS_NAMES = {0: "COFEM_OK", 1: "COFEM_ERR_INVALID_ARG", 2: "COFEM_ERR_OUT_OF
 class cofem_problem(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("N", c_int64), ("D", c_int64), ("phi", c_void_p),
                 ("ld_phi", c_int64), ("phi_dtype", c_int32), ("H", c_int32), ("W", c_int32),
-                ("kh", c_int32), ("kw", c_int32), ("taps", c_void_p), ("y", c_void_p)]
+                ("kh", c_int32), ("kw", c_int32), ("taps", c_void_p), ("y", c_void_p),
+                ("rows", c_void_p)]
 
 
 class cofem_params(ctypes.Structure):
@@ -252,6 +254,7 @@ class CoFEM:
 
     dense:  CoFEM.dense(phi[N, D] float32 cuda, y[N] float32 cuda, beta, K, ...)
     conv:   CoFEM.conv(taps[k, k] float32 cuda, y[H*W] float32 cuda, H, W, beta, K, ...)
+    dct:    CoFEM.dct(rows[N] int32 cuda, y[N] float32 cuda, D, beta, K, ...)
     """
 
     def __init__(self, problem: cofem_problem, params: cofem_params, keep, device, stream=None):
@@ -300,6 +303,20 @@ class CoFEM:
                              phi_dtype=COFEM_F32, H=H, W=W, kh=th, kw=tw, taps=taps.data_ptr(),
                              y=y.data_ptr())
         return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (taps, y), taps.device)
+
+    @classmethod
+    def dct(cls, rows, y, D, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
+        """Inverse DCT of a length-D coefficient vector followed by the N
+        observed samples `rows` (distinct indices into [0, D))."""
+        import torch
+        if rows.dtype != torch.int32 or y.dtype != torch.float32 or not rows.is_cuda or not y.is_cuda:
+            raise CofemError(COFEM_ERR_INVALID_ARG, "rows must be an int32 and y a float32 GPU tensor")
+        rows = rows.contiguous()
+        y = y.contiguous()
+        N = rows.numel()
+        prob = cofem_problem(kind=COFEM_DCT_MASK, N=N, D=int(D), phi=None, ld_phi=0, phi_dtype=COFEM_F32,
+                             H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr(), rows=rows.data_ptr())
+        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (rows, y), rows.device)
 
     def em_step(self, n_iters=1):
         return cofem_em_step(self.ctx, n_iters)

@@ -84,6 +84,10 @@ struct cofem_ctx {
   int device = 0;
   DenseDims dd{};
   ConvDims cd{};
+  // DCT dictionary: transform geometry and buffers (the CG state uses the conv
+  // fields, in the row order of cd.perm)
+  DctDims xd{};
+  DctBuffers xb{};
   std::vector<void*> allocs;
   // dictionary
   float* phiA = nullptr;
@@ -350,6 +354,79 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   COFEM_HIP(c, conv_b0(cd, c->taps, p.y, c->beta, c->b0, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha_prev, 1.0f, cd.ldD, c->stream));
+  return COFEM_OK;
+}
+
+cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
+  int l = 0;
+  while ((int64_t(1) << l) < p.D) ++l;
+  DctDims& xd = c->xd;
+  xd.D = p.D;
+  xd.l1 = (l + 1) / 2;
+  xd.l2 = l / 2;
+  xd.K = c->K;
+  xd.npairs = (c->K + 1) / 2;
+  xd.units = (1 << xd.l1) / 2 + 1;
+  ConvDims& cd = c->cd;
+  cd.H = 1;
+  cd.W = (int)p.D;
+  cd.ks = 1;
+  cd.D = p.D;
+  cd.ldD = p.D;
+  cd.K = c->K;
+  cd.fp64 = 0;
+  cd.perm = xd.l1 | (xd.l2 << 8);
+  c->KP = c->K;
+  // the observed samples must be distinct and in range (checked once, here)
+  {
+    std::vector<int32_t> hr((size_t)p.N);
+    COFEM_HIP(c, hipMemcpyAsync(hr.data(), p.rows, sizeof(int32_t) * (size_t)p.N, hipMemcpyDeviceToHost, c->stream));
+    COFEM_HIP(c, hipStreamSynchronize(c->stream));
+    std::vector<uint8_t> seen((size_t)p.D, 0);
+    for (int32_t r : hr) {
+      if (r < 0 || r >= p.D) return fail(c, COFEM_ERR_INVALID_ARG, "rows holds an index outside [0, D)");
+      if (seen[(size_t)r]) return fail(c, COFEM_ERR_INVALID_ARG, "rows holds a repeated index");
+      seen[(size_t)r] = 1;
+    }
+  }
+  const size_t D = (size_t)p.D, blk = D * (size_t)c->K;
+  const int N1 = 1 << xd.l1, N2 = 1 << xd.l2;
+  COFEM_TRY(alloc(c, &c->b0, D));
+  COFEM_TRY(alloc(c, &c->alpha, D));
+  COFEM_TRY(alloc(c, &c->mu, D));
+  COFEM_TRY(alloc(c, &c->sdiag, D));
+  void** blocks[6] = {&c->vX, &c->vR, &c->vP, &c->vQ, &c->vVs, &c->vQs};
+  for (void** b : blocks) {
+    float* q = nullptr;
+    COFEM_TRY(alloc(c, &q, blk));
+    *b = q;
+  }
+  double** vecs[6] = {&c->xm, &c->rm, &c->pm, &c->qm, &c->Vsm, &c->Qsm};
+  for (double** v : vecs) COFEM_TRY(alloc(c, v, D));
+  float *Wf = nullptr, *tw1f = nullptr, *tw2f = nullptr;
+  double *Wd = nullptr, *mk = nullptr, *vb = nullptr, *tw1d = nullptr, *tw2d = nullptr, *rr = nullptr;
+  COFEM_TRY(alloc(c, &Wf, 2 * D * (size_t)xd.npairs));
+  COFEM_TRY(alloc(c, &Wd, 2 * D));
+  COFEM_TRY(alloc(c, &mk, D));
+  COFEM_TRY(alloc(c, &vb, D));
+  COFEM_TRY(alloc(c, &tw1f, (size_t)2 * N1));
+  COFEM_TRY(alloc(c, &tw2f, (size_t)2 * N2));
+  COFEM_TRY(alloc(c, &tw1d, (size_t)2 * N1));
+  COFEM_TRY(alloc(c, &tw2d, (size_t)2 * N2));
+  COFEM_TRY(alloc(c, &rr, (size_t)(c->K + 1) * xd.units));
+  c->xb = DctBuffers{Wf, Wd, mk, tw1f, tw2f, tw1d, tw2d, rr};
+  const int ncols = c->K + 1;
+  ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
+  const int64_t nupd = conv_update_blocks(cd);
+  const int64_t nblks[3] = {nupd, nupd, xd.units};
+  const int nvs[3] = {1, 1, 5};  // init and true residual one value per column; an iteration up to five
+  for (int i = 0; i < 3; ++i) {
+    COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], nvs[i], ncols));
+    COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
+    COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
+  }
+  COFEM_HIP(c, dct_setup(xd, p.rows, p.N, p.y, c->beta, mk, vb, tw1f, tw2f, tw1d, tw2d, c->xb, c->b0, c->stream));
+  COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
   return COFEM_OK;
 }
 
@@ -659,11 +736,22 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
     if (p->kh < 1 || p->kh > 9 || p->kh % 2 == 0) return *why = "kernel side must be odd, 1..9", COFEM_ERR_INVALID_ARG;
     if (p->N != (int64_t)p->H * p->W || p->D != p->N) return *why = "conv needs N == D == H*W", COFEM_ERR_INVALID_ARG;
     if ((int64_t)p->H * p->W > (int64_t)1 << 30) return *why = "image too large", COFEM_ERR_INVALID_ARG;
+  } else if (p->kind == COFEM_DCT_MASK) {
+    if (p->D < ((int64_t)1 << 12) || p->D > ((int64_t)1 << 20) || (p->D & (p->D - 1)) != 0)
+      return *why = "the DCT dictionary needs D = 2^p, 12 <= p <= 20", COFEM_ERR_UNSUPPORTED;
+    if (p->N < 1 || p->N > p->D) return *why = "the DCT dictionary needs 1 <= N <= D", COFEM_ERR_INVALID_ARG;
+    if (!p->rows) return *why = "rows is null", COFEM_ERR_INVALID_ARG;
+    if (q->precision != COFEM_PREC_FP32)
+      return *why = "the DCT dictionary runs precision COFEM_PREC_FP32", COFEM_ERR_UNSUPPORTED;
   } else {
     return *why = "unknown dictionary kind", COFEM_ERR_INVALID_ARG;
   }
   return COFEM_OK;
 }
+
+// Dictionaries whose CG iterations fold the previous update into the first
+// launch: a solve of n updates takes n + 1 iterations' launches.
+bool folded_update(const cofem_ctx* c) { return c->kind == COFEM_CONV2D_CIRC || c->kind == COFEM_DCT_MASK; }
 
 // Kernel timing: an event is recorded before every launch (and one after the
 // last); launch i lasts from event i to event i + 1, dispatch gap included.
@@ -780,6 +868,19 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
+    } else if (c->kind == COFEM_DCT_MASK) {
+      // DCT: the first iteration of a solve is the operator on the start
+      // direction; each later one folds the previous update into its first
+      // launch (state updated in place: no launch reads another row's state)
+      const int fused = it > 0 ? 1 : 0;
+      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_HIP(c, dct_rows_in(c->xd, c->xb, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm, c->st, fused, 0,
+                               c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
+      COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 0, c->stream));
+      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
+      COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm, c->alpha, c->red_pass,
+                                c->st, fused, 0, c->stream));
     } else {
       // conv: the first launch of a solve is the operator pass on the start
       // direction (set 0); each later one a fused iteration, the previous
@@ -815,8 +916,16 @@ cofem_status true_residual(cofem_ctx* c, int t) {
     COFEM_HIP(c, dense_true_resid(c->dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->parts_upd, c->cnts_upd,
                                   c->st, c->stream));
   } else {
-    COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm,
-                           c->red_pass, c->st, 1, c->stream));
+    if (c->kind == COFEM_DCT_MASK) {
+      COFEM_HIP(c, dct_rows_in(c->xd, c->xb, nullptr, nullptr, c->vX, nullptr, nullptr, nullptr, c->xm, nullptr,
+                               c->st, 0, 1, c->stream));
+      COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 1, c->stream));
+      COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vX, nullptr, c->vQs, c->xm, nullptr, c->Qsm, c->alpha, c->red_pass,
+                                c->st, 0, 1, c->stream));
+    } else {
+      COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm,
+                             c->red_pass, c->st, 1, c->stream));
+    }
     COFEM_HIP(c, conv_true_resid(c->cd, c->seed, t, c->b0, c->vQs, c->Qsm, c->red_upd, c->st, c->stream));
   }
   return COFEM_OK;
@@ -945,10 +1054,10 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   }
   // launches per solve: conv needs one more than its updates (the first
   // operator pass)
-  const int limit = (c->fixed_iters > 0 ? c->fixed_iters : c->U) + (c->kind == COFEM_CONV2D_CIRC ? 1 : 0);
+  const int limit = (c->fixed_iters > 0 ? c->fixed_iters : c->U) + (folded_update(c) ? 1 : 0);
   // First chunk: the previous solve's count (CG counts drift slowly across EM
   // iterations), then `poll`-sized chunks until the device flag says stop.
-  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 + (c->kind == COFEM_CONV2D_CIRC ? 1 : 0) : c->poll;
+  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 + (folded_update(c) ? 1 : 0) : c->poll;
   if (chunk > limit) chunk = limit;
   int enqueued = 0;
   for (;;) {
@@ -970,8 +1079,9 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
                              c->sdiag, c->st, c->stream));
   else {
     // the learned form's features see how far this M-step moves alpha
-    COFEM_HIP(c, hipMemcpyAsync(c->alpha_prev, c->alpha, sizeof(float) * c->cd.D, hipMemcpyDeviceToDevice,
-                                c->stream));
+    if (c->alpha_prev)
+      COFEM_HIP(c, hipMemcpyAsync(c->alpha_prev, c->alpha, sizeof(float) * c->cd.D, hipMemcpyDeviceToDevice,
+                                  c->stream));
     COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
                             c->st, c->stream));
   }
@@ -979,7 +1089,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
   COFEM_TRY(read_state(c));
   // (a conv solve of n updates has n + 1 working launches)
-  COFEM_TRY(collect_times(c, c->host_st->iter + (c->kind == COFEM_CONV2D_CIRC ? 1 : 0)));
+  COFEM_TRY(collect_times(c, c->host_st->iter + (folded_update(c) ? 1 : 0)));
   c->has_solution = true;
   c->prev_iters = c->host_st->iter;
   c->t_next = t + 1;
@@ -1038,7 +1148,10 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   const bool batched = n_problems > 1 || p.phi_dtype == COFEM_BF16 || (params->flags & COFEM_FLAG_BATCHED);
   if (s == COFEM_OK) s = alloc(c, &c->st, (size_t)n_problems);
   if (s == COFEM_OK)
-    s = batched ? init_batch(c, problems, n_problems) : (p.kind == COFEM_DENSE) ? init_dense(c, p) : init_conv(c, p);
+    s = batched                       ? init_batch(c, problems, n_problems)
+        : (p.kind == COFEM_DENSE)     ? init_dense(c, p)
+        : (p.kind == COFEM_DCT_MASK) ? init_dct(c, p)
+                                      : init_conv(c, p);
   if (s == COFEM_OK) s = push_controls(c);
   if (s == COFEM_OK) {
     e = hipStreamSynchronize(c->stream);
@@ -1077,6 +1190,13 @@ cofem_status cofem_posterior(cofem_ctx* ctx, int32_t problem, float* mu, float* 
     pa = p.alpha;
     D = p.D;
   }
+  if (ctx->kind == COFEM_DCT_MASK) {
+    // state order -> natural coefficient order
+    if (mu) COFEM_HIP(ctx, perm_out_f32(ctx->cd, pmu, mu, ctx->stream));
+    if (s) COFEM_HIP(ctx, perm_out_f32(ctx->cd, ps, s, ctx->stream));
+    if (alpha) COFEM_HIP(ctx, perm_out_f32(ctx->cd, pa, alpha, ctx->stream));
+    return COFEM_OK;
+  }
   const size_t bytes = sizeof(float) * (size_t)D;
   if (mu) COFEM_HIP(ctx, hipMemcpyAsync(mu, pmu, bytes, hipMemcpyDeviceToDevice, ctx->stream));
   if (s) COFEM_HIP(ctx, hipMemcpyAsync(s, ps, bytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1091,7 +1211,10 @@ cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha
   if (!alpha) return fail(ctx, COFEM_ERR_INVALID_ARG, "alpha is null");
   float* dst = ctx->batch ? ctx->batch->probs[problem].alpha : ctx->alpha;
   const int64_t D = ctx->batch ? ctx->batch->probs[problem].D : ctx->D;
-  COFEM_HIP(ctx, hipMemcpyAsync(dst, alpha, sizeof(float) * (size_t)D, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->kind == COFEM_DCT_MASK)
+    COFEM_HIP(ctx, perm_in_f32(ctx->cd, alpha, dst, ctx->stream));
+  else
+    COFEM_HIP(ctx, hipMemcpyAsync(dst, alpha, sizeof(float) * (size_t)D, hipMemcpyDeviceToDevice, ctx->stream));
   return COFEM_OK;
 }
 
@@ -1131,7 +1254,9 @@ cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, 
       COFEM_HIP(ctx, conv_probes_out(ctx->cd, ctx->vX, probes, ctx->stream));
     }
   }
-  if (mean)
+  if (mean && ctx->kind == COFEM_DCT_MASK)
+    COFEM_HIP(ctx, perm_out_f64(ctx->cd, ctx->xm, mean, ctx->stream));
+  else if (mean)
     COFEM_HIP(ctx, hipMemcpyAsync(mean, ir ? ctx->xtm : ctx->xm, sizeof(double) * (size_t)ctx->D,
                                   hipMemcpyDeviceToDevice, ctx->stream));
   return COFEM_OK;
@@ -1165,6 +1290,19 @@ static cofem_status apply_A_impl(cofem_ctx* ctx, int32_t problem, const float* v
                                  ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1, ctx->stream));
     }
     COFEM_HIP(ctx, dense_to_colmajor(dd, ctx->K, ctx->Qs, q_probes, ctx->stream));
+  } else if (ctx->kind == COFEM_DCT_MASK) {
+    const ConvDims& cd = ctx->cd;
+    COFEM_HIP(ctx, conv_probes_in(cd, v_probes, ctx->vVs, ctx->stream));
+    COFEM_HIP(ctx, perm_in_f64(cd, v_mean, ctx->Vsm, ctx->stream));
+    COFEM_HIP(ctx, dct_rows_in(ctx->xd, ctx->xb, nullptr, nullptr, ctx->vVs, nullptr, nullptr, nullptr, ctx->Vsm,
+                               nullptr, ctx->st, 0, 1, ctx->stream));
+    COFEM_HIP(ctx, dct_mid(ctx->xd, ctx->xb, ctx->st, 1, ctx->stream));
+    COFEM_HIP(ctx, dct_rows_out(ctx->xd, ctx->xb, ctx->vVs, nullptr, ctx->vQs, ctx->Vsm, nullptr, ctx->Qsm,
+                                ctx->alpha, ctx->red_pass, ctx->st, 0, 1, ctx->stream));
+    COFEM_HIP(ctx, conv_probes_out(cd, ctx->vQs, q_probes, ctx->stream));
+    COFEM_HIP(ctx, perm_out_f64(cd, ctx->Qsm, q_mean, ctx->stream));
+    COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return COFEM_OK;
   } else {
     const ConvDims& cd = ctx->cd;
     COFEM_HIP(ctx, conv_probes_in(cd, v_probes, ctx->vVs, ctx->stream));
@@ -1259,6 +1397,18 @@ cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
                                         ctx->parts_pass, ctx->cnts_pass, ctx->cnt_split2, ctx->st, 1,
                                         ctx->stream); },
                &ms_out[1]);
+  } else if (ctx->kind == COFEM_DCT_MASK) {
+    const DctDims& xd = ctx->xd;
+    const DctBuffers& xb = ctx->xb;
+    rc = timed([&] { return dct_rows_in(xd, xb, nullptr, nullptr, ctx->vP, nullptr, nullptr, nullptr, ctx->pm,
+                                        nullptr, ctx->st, 0, 1, ctx->stream); },
+               &ms_out[0]);
+    if (rc != COFEM_OK) return rc;
+    rc = timed([&] { return dct_mid(xd, xb, ctx->st, 1, ctx->stream); }, &ms_out[1]);
+    if (rc != COFEM_OK) return rc;
+    rc = timed([&] { return dct_rows_out(xd, xb, ctx->vP, nullptr, ctx->vQs, ctx->pm, nullptr, ctx->Qsm,
+                                         ctx->alpha, ctx->red_pass, ctx->st, 0, 1, ctx->stream); },
+               &ms_out[2]);
   } else {
     rc = timed([&] { return conv_pass(ctx->cd, ctx->taps, ctx->vP, ctx->pm, ctx->vR, ctx->rm, ctx->alpha,
                                       ctx->beta, ctx->vQs, ctx->Qsm, ctx->red_pass, ctx->st, 1, ctx->stream); },

@@ -562,7 +562,17 @@ struct ConvDims {
   int K;             // probe columns (column-major blocks of ldD elements)
   int tilesX, tilesY;  // kConvTile x kConvTile output tiles
   int fp64;          // probe columns in float64 (else float32)
+  // element order of the state vectors: 0 = natural; otherwise l1 | (l2 << 8)
+  // for the DCT dictionary's row-major order of coefficient k = k1 + 2^l1 k2
+  // at position k1 2^l2 + k2 (perm_nat maps a position to k)
+  int perm;
 };
+
+__host__ __device__ __forceinline__ int64_t perm_nat(int perm, int64_t pos) {
+  if (perm == 0) return pos;
+  const int l1 = perm & 0xFF, l2 = perm >> 8;
+  return (pos >> l2) + ((pos & ((int64_t(1) << l2) - 1)) << l1);
+}
 
 hipError_t conv_b0(const ConvDims& cd, const float* taps, const float* y, double beta, double* b0,
                    hipStream_t s);
@@ -612,6 +622,57 @@ hipError_t probe_signs_colmajor(uint64_t seed, int t, int K, int64_t D, float* o
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
 
 int conv_update_blocks(const ConvDims& cd);
+// element-order conversions of the state (cd.perm) to and from the caller's
+// natural order: float vectors, float64 vectors
+hipError_t perm_out_f32(const ConvDims& cd, const float* src, float* dst, hipStream_t s);
+hipError_t perm_in_f32(const ConvDims& cd, const float* src, float* dst, hipStream_t s);
+hipError_t perm_out_f64(const ConvDims& cd, const double* src, double* dst, hipStream_t s);
+hipError_t perm_in_f64(const ConvDims& cd, const double* src, double* dst, hipStream_t s);
+
+// ------------------------------------------------------------ DCT dictionary
+// Phi = S C^T: the orthonormal inverse DCT of a length-D coefficient vector,
+// then N observed samples.  A v = beta C S^T S C^T v + alpha v runs as one
+// complex FFT sandwich per pair of float columns (and one for the float64
+// mean column): D = N1 N2 in the four-step order, three launches per CG
+// iteration: rows of the state (length-N2 transforms, with the previous CG
+// update folded in), then groups of the intermediate (length-N1 inverse and
+// forward transforms around the mask), then rows again (forward, the
+// operator's output and the CG dot products).  State vectors are in the row
+// order of ConvDims::perm.
+struct DctDims {
+  int64_t D;
+  int l1, l2;      // N1 = 2^l1 rows, N2 = 2^l2 columns (l1 = ceil(p/2))
+  int K;           // probe columns
+  int npairs;      // ceil(K/2) float column pairs
+  int units;       // N1/2 + 1 row units (a row and its mirror row)
+  int gf, gd;      // groups per middle-launch tile: float pairs, float64 column
+};
+struct DctBuffers {
+  float* Wf;             // npairs x D complex float intermediates
+  double* Wd;            // D complex double intermediate (mean column)
+  const double* mk;      // mask values beta/D or 0, middle-launch order
+  const float* tw1f;     // e^{2 pi i j / N1}, j < N1 (float complex)
+  const float* tw2f;     // e^{2 pi i j / N2}
+  const double* tw1d;
+  const double* tw2d;
+  double* rr;            // per (column, row unit): ||r||^2 of the folded update
+};
+// Set-up: mask values and the zero-filled scaled data for b0, twiddle tables,
+// then b0 = beta Phi^T y (float64, state order).  rows: device int32 [N].
+hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const float* y, double beta, double* mk,
+                     double* vb, float* tw1f, float* tw2f, double* tw1d, double* tw2d, const DctBuffers& b,
+                     double* b0, hipStream_t s);
+// One CG iteration is dct_rows_in, dct_mid, dct_rows_out.  fused = 0: Q = A P with the pass's
+// dot products (first iteration of a solve); fused = 1: the previous update
+// (x += a p, r -= a q, p = r + b p, in place) folded into the first launch,
+// then Q = A P; apply_only: Q = A P with no reduction and no stop check.
+hipError_t dct_rows_in(const DctDims& dd, const DctBuffers& b, void* X, void* R, void* P, const void* Q, double* xm,
+                       double* rm, double* pm, const double* qm, CgScalars* st, int fused, int apply_only,
+                       hipStream_t s);
+hipError_t dct_mid(const DctDims& dd, const DctBuffers& b, CgScalars* st, int apply_only, hipStream_t s);
+hipError_t dct_rows_out(const DctDims& dd, const DctBuffers& b, const void* P, const void* R, void* Q,
+                        const double* pm, const double* rm, double* qm, const float* alpha, const ConvReduce& red,
+                        CgScalars* st, int fused, int apply_only, hipStream_t s);
 
 // ------------------------------------------------------------ batched form
 // Many independent dense problems (bfloat16 dictionaries, plain CG) advanced

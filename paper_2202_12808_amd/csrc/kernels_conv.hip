@@ -648,7 +648,7 @@ int conv_update_blocks(const ConvDims& cd) {
 
 // ------------------------------------------------ initial residual R = P = B (Eq. 7)
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K, uint64_t seed,
+__global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K, int perm, uint64_t seed,
                                                    int t, const double* __restrict__ b0,
                                                    TP* __restrict__ X, TP* __restrict__ R,
                                                    TP* __restrict__ P, double* __restrict__ xm,
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K
   } else {
     const int64_t off = (int64_t)col * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const TP v = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d);
+      const TP v = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)perm_nat(perm, d));
       R[off + d] = v;
       P[off + d] = v;
       X[off + d] = TP(0);
@@ -692,11 +692,11 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
                      CgScalars* st, hipStream_t s) {
   const dim3 grid(conv_update_blocks(cd), cd.K + 1);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_init<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_init<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
                        static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P), xm,
                        rm, pm, red, st);
   else
-    hipLaunchKernelGGL(k_conv_init<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_init<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
                        static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P), xm, rm,
                        pm, red, st);
   return hipGetLastError();
@@ -830,7 +830,7 @@ hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const
 // ||b_c - q_c||^2 per column with q = A x from an operator pass over X and B
 // regenerated: probes of EM iteration t (Eq. 7) and b0 for the mean column.
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD, int K, uint64_t seed,
+__global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD, int K, int perm, uint64_t seed,
                                                          int t, const double* __restrict__ b0,
                                                          const TP* __restrict__ Q,
                                                          const double* __restrict__ qm, ConvReduce red,
@@ -847,7 +847,8 @@ __global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD,
   } else {
     const TP* q = Q + (int64_t)col * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const double e = (double)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d) - (double)q[d];
+      const double e =
+          (double)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)perm_nat(perm, d)) - (double)q[d];
       acc += e * e;
     }
   }
@@ -866,17 +867,17 @@ hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const doubl
                            const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s) {
   const dim3 grid(conv_update_blocks(cd), cd.K + 1);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_true_resid<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_true_resid<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
                        static_cast<const double*>(Q), qm, red, st);
   else
-    hipLaunchKernelGGL(k_conv_true_resid<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_true_resid<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
                        static_cast<const float*>(Q), qm, red, st);
   return hipGetLastError();
 }
 
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, uint64_t seed,
+__global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, int perm, uint64_t seed,
                                                     int t, const TP* __restrict__ X,
                                                     const double* __restrict__ xm,
                                                     float* __restrict__ alpha, double alpha_max,
@@ -888,8 +889,9 @@ __global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int 
   double clamped = 0.0;
   for (int64_t d = gtid; d < D; d += gstride) {
     double acc = 0.0;
+    const uint64_t dn = (uint64_t)perm_nat(perm, d);
     for (int k = 0; k < K; ++k)
-      acc += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)d) * (double)X[(int64_t)k * ldD + d];
+      acc += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, dn) * (double)X[(int64_t)k * ldD + d];
     const double s = acc / (double)K;
     const double m = xm[d];
     const double den = m * m + s;
@@ -909,33 +911,38 @@ hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, c
   const int64_t want = (cd.D + 255) / 256;
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t,
+    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t,
                        static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, st);
   else
-    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t,
+    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t,
                        static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, st);
   return hipGetLastError();
 }
 
 // ------------------------------------------------ strided copies between the caller's
-// float32 D x K blocks and the probe state (float or double, leading dimension ldD)
-template <typename TS, typename TD>
-__global__ void k_copy_cols(int64_t D, int K, const TS* __restrict__ src, int64_t lds,
+// float32 D x K blocks (natural order) and the probe state (float or double,
+// leading dimension ldD, element order cd.perm)
+template <typename TS, typename TD, bool OUT>
+__global__ void k_copy_cols(int64_t D, int K, int perm, const TS* __restrict__ src, int64_t lds,
                             TD* __restrict__ dst, int64_t ldd) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= D * K) return;
-  const int64_t k = idx / D, d = idx % D;
-  dst[k * ldd + d] = (TD)src[k * lds + d];
+  const int64_t k = idx / D, d = idx % D;  // d: state position
+  const int64_t n = perm_nat(perm, d);
+  if (OUT)
+    dst[k * ldd + n] = (TD)src[k * lds + d];
+  else
+    dst[k * ldd + d] = (TD)src[k * lds + n];
 }
 
 hipError_t conv_probes_out(const ConvDims& cd, const void* X, float* out, hipStream_t s) {
   const int64_t tot = cd.D * cd.K;
   const dim3 grid((unsigned)((tot + 255) / 256));
   if (cd.fp64)
-    hipLaunchKernelGGL((k_copy_cols<double, float>), grid, dim3(256), 0, s, cd.D, cd.K,
+    hipLaunchKernelGGL((k_copy_cols<double, float, true>), grid, dim3(256), 0, s, cd.D, cd.K, cd.perm,
                        static_cast<const double*>(X), cd.ldD, out, cd.D);
   else
-    hipLaunchKernelGGL((k_copy_cols<float, float>), grid, dim3(256), 0, s, cd.D, cd.K,
+    hipLaunchKernelGGL((k_copy_cols<float, float, true>), grid, dim3(256), 0, s, cd.D, cd.K, cd.perm,
                        static_cast<const float*>(X), cd.ldD, out, cd.D);
   return hipGetLastError();
 }
@@ -944,12 +951,44 @@ hipError_t conv_probes_in(const ConvDims& cd, const float* in, void* X, hipStrea
   const int64_t tot = cd.D * cd.K;
   const dim3 grid((unsigned)((tot + 255) / 256));
   if (cd.fp64)
-    hipLaunchKernelGGL((k_copy_cols<float, double>), grid, dim3(256), 0, s, cd.D, cd.K, in, cd.D,
+    hipLaunchKernelGGL((k_copy_cols<float, double, false>), grid, dim3(256), 0, s, cd.D, cd.K, cd.perm, in, cd.D,
                        static_cast<double*>(X), cd.ldD);
   else
-    hipLaunchKernelGGL((k_copy_cols<float, float>), grid, dim3(256), 0, s, cd.D, cd.K, in, cd.D,
+    hipLaunchKernelGGL((k_copy_cols<float, float, false>), grid, dim3(256), 0, s, cd.D, cd.K, cd.perm, in, cd.D,
                        static_cast<float*>(X), cd.ldD);
   return hipGetLastError();
+}
+
+// single vectors between the state order and the natural order
+template <typename T, bool OUT>
+__global__ void k_perm_vec(int64_t D, int perm, const T* __restrict__ src, T* __restrict__ dst) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= D) return;
+  const int64_t n = perm_nat(perm, d);
+  if (OUT)
+    dst[n] = src[d];
+  else
+    dst[d] = src[n];
+}
+
+template <typename T, bool OUT>
+static hipError_t perm_vec(const ConvDims& cd, const T* src, T* dst, hipStream_t s) {
+  if (cd.D == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_perm_vec<T, OUT>), dim3((unsigned)((cd.D + 255) / 256)), dim3(256), 0, s, cd.D, cd.perm,
+                     src, dst);
+  return hipGetLastError();
+}
+hipError_t perm_out_f32(const ConvDims& cd, const float* src, float* dst, hipStream_t s) {
+  return perm_vec<float, true>(cd, src, dst, s);
+}
+hipError_t perm_in_f32(const ConvDims& cd, const float* src, float* dst, hipStream_t s) {
+  return perm_vec<float, false>(cd, src, dst, s);
+}
+hipError_t perm_out_f64(const ConvDims& cd, const double* src, double* dst, hipStream_t s) {
+  return perm_vec<double, true>(cd, src, dst, s);
+}
+hipError_t perm_in_f64(const ConvDims& cd, const double* src, double* dst, hipStream_t s) {
+  return perm_vec<double, false>(cd, src, dst, s);
 }
 
 // ------------------------------------------------ probes for tests; fills

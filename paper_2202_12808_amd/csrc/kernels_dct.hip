@@ -1,0 +1,692 @@
+// Inverse-DCT-with-undersampling dictionary (Sec. 4, structured dictionary):
+// Phi = S C^T, C the orthonormal DCT-II matrix, S the selection of N observed
+// samples.  The CG operator A v = beta C S^T S C^T v + alpha v runs as complex
+// FFTs of length D = N1 N2 in the four-step order, three launches per CG
+// iteration, every transform done by one wavefront in LDS.
+//
+// The DCT through a complex FFT (Makhoul's reordering).  Let sigma(n) = 2n for
+// n < D/2 and 2(D-1-n)+1 above: the signal sample held at FFT index n.  For a
+// pair (u, w) of real coefficient vectors, with u^ = u except u^_0 = sqrt(2) u_0
+// and u^_D = 0,
+//   Z_k = e^{i pi k / 2D} [(u^_k + w^_{D-k}) + i (w^_k - u^_{D-k})]
+// is Hermitian-symmetric in each of its two real parts, so its inverse FFT is
+// sqrt(2D) (C^T u + i C^T w), reordered by sigma.  Scaling every observed index
+// by beta/D (the mask) and taking the forward FFT Z' gives, per column,
+//   (beta C S^T S C^T u)_k = c_k Re(e^{-i pi k / 2D} (Z'_k + conj Z'_{D-k}) / 2)
+// and the same with (Z'_k - conj Z'_{D-k}) / 2i for w, c_0 = 1/sqrt 2, c_k = 1.
+// The float64 mean column runs alone (w = 0).
+//
+// Four-step order: coefficient k = k1 + N1 k2 is stored at position k1 N2 + k2
+// (rows of length N2); FFT index n = n2 + N2 n1.  The inverse FFT is a length-N2
+// transform along each row, a twiddle e^{2 pi i n2 k1 / D}, then a length-N1
+// transform across rows for each n2; the forward FFT walks the same steps
+// backwards.  Launch 1 (rows in) forms Z and the row transforms; launch 2
+// (middle) the two cross-row transforms around the mask, in place on tiles of
+// the intermediate; launch 3 (rows out) the forward row transforms, the output
+// per column and the CG dot products.  Row k1 pairs with row N1 - k1 (the
+// mirror index D - k), so both rows are one workgroup's.
+#include "cofem_internal.h"
+
+namespace cofem {
+
+namespace {
+
+template <typename T>
+struct Cx {
+  T x, y;
+};
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * (SIGN i)
+template <int SIGN, typename T>
+__device__ __forceinline__ Cx<T> rot90(Cx<T> a) {
+  return SIGN > 0 ? Cx<T>{-a.y, a.x} : Cx<T>{a.y, -a.x};
+}
+
+__device__ __forceinline__ void sin_cos_pi(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sin_cos_pi(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// e^{SIGN 2 pi i m / D}, m < D; two_over_d = 2/D (D a power of two, so the
+// argument m (2/D) is exact)
+template <int SIGN, typename T>
+__device__ __forceinline__ Cx<T> unit_root(int64_t m, T two_over_d) {
+  T s, c;
+  sin_cos_pi((T)m * two_over_d, &s, &c);
+  return {c, SIGN > 0 ? s : -s};
+}
+
+// Lanes of one wavefront exchange data through LDS between the phases of a
+// transform.  The hardware completes a wavefront's LDS operations in order,
+// but the compiler reasons per lane and may forward a lane's own earlier store
+// or move accesses across a phase; this fence (no instruction at wavefront
+// scope) keeps every LDS access on its side.
+__device__ __forceinline__ void lds_wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// ---- small DFTs in registers (sign SIGN of the exponent)
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft2(Cx<T>& a, Cx<T>& b) {
+  const Cx<T> t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft4(Cx<T>& x0, Cx<T>& x1, Cx<T>& x2, Cx<T>& x3) {
+  const Cx<T> t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3), t3 = rot90<SIGN>(csub(x1, x3));
+  x0 = cadd(t0, t2);
+  x2 = csub(t0, t2);
+  x1 = cadd(t1, t3);
+  x3 = csub(t1, t3);
+}
+template <int SIGN, typename T, int R>
+__device__ __forceinline__ void dft(Cx<T>* v) {
+  if constexpr (R == 2) {
+    dft2<SIGN>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<SIGN>(v[0], v[1], v[2], v[3]);
+  } else {
+    static_assert(R == 8, "radix 2, 4 or 8");
+    // even and odd halves, then the eighth roots of unity
+    dft4<SIGN>(v[0], v[2], v[4], v[6]);
+    dft4<SIGN>(v[1], v[3], v[5], v[7]);
+    const T h = (T)0.70710678118654752440;
+    const Cx<T> o1{(v[3].x - SIGN * v[3].y) * h, (v[3].y + SIGN * v[3].x) * h};
+    const Cx<T> o2 = rot90<SIGN>(v[5]);
+    const Cx<T> o3{(-v[7].x - SIGN * v[7].y) * h, (-v[7].y + SIGN * v[7].x) * h};
+    const Cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+  }
+}
+
+// One radix-R Stockham stage of a length-L transform held in LDS, by one
+// wavefront, in place: butterfly j (< L/R) reads elements j + m L/R, applies
+// the twiddles of its sub-transform (span NS) and a radix-R DFT, and writes
+// elements (j / NS) NS R + j % NS + m NS.  Every load of the stage is issued
+// before its first store (fenced), and a wavefront's LDS operations complete
+// in order, so the stage needs no second buffer.  tw: e^{2 pi i j / L}, j < L.
+template <typename T, int L, int R, int NS, int SIGN>
+__device__ __forceinline__ void fft_stage(Cx<T>* buf, const Cx<T>* __restrict__ tw, int lane) {
+  constexpr int NB = L / R;
+  constexpr int PER = NB >= 64 ? NB / 64 : 1;
+  Cx<T> v[PER][R];
+  lds_wave_fence();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lane + 64 * i;
+    if (NB >= 64 || j < NB) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[i][m] = buf[j + m * NB];
+    }
+  }
+  lds_wave_fence();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lane + 64 * i;
+    if (NB >= 64 || j < NB) {
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
+        constexpr int step = L / (NS * R);
+#pragma unroll
+        for (int m = 1; m < R; ++m) {
+          Cx<T> w = tw[k * m * step];
+          if (SIGN < 0) w.y = -w.y;
+          v[i][m] = cmul(v[i][m], w);
+        }
+      }
+      dft<SIGN, T, R>(v[i]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) buf[base + m * NS] = v[i][m];
+    }
+  }
+  lds_wave_fence();
+}
+
+// A whole transform (radix 8 first, then one stage of 2 or 4 if needed),
+// natural order in and out, unnormalised.
+template <typename T, int L, int NS, int SIGN>
+__device__ __forceinline__ void fft_stages(Cx<T>* buf, const Cx<T>* __restrict__ tw, int lane) {
+  if constexpr (NS < L) {
+    constexpr int R = (L / NS) >= 8 ? 8 : (L / NS);
+    fft_stage<T, L, R, NS, SIGN>(buf, tw, lane);
+    fft_stages<T, L, NS * R, SIGN>(buf, tw, lane);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ const Cx<T>* as_cx(const T* p) {
+  return reinterpret_cast<const Cx<T>*>(p);
+}
+
+// Row unit u: rows u and (N1 - u) mod N1 (one row when they coincide).  The
+// mirror of coefficient k = row + N1 e (k != 0), the index D - k, sits in row
+// (N1 - row) mod N1 at column (N2 - e) mod N2 for row 0, else N2 - 1 - e.
+struct RowUnit {
+  int rowA, rowB;
+  bool single;
+};
+__device__ __forceinline__ RowUnit row_unit(int u, int N1) {
+  RowUnit r;
+  r.rowA = u;
+  r.rowB = (N1 - u) & (N1 - 1);
+  r.single = r.rowA == r.rowB;
+  return r;
+}
+__device__ __forceinline__ int mirror_col(int row, int e, int N2) { return row == 0 ? ((N2 - e) & (N2 - 1)) : (N2 - 1 - e); }
+
+// ---------------------------------------------------------------- launch 1
+// Column pointers of one slot: NC = 2 float probe columns (the second may be
+// absent when K is odd) or NC = 1 float64 mean column.
+template <typename T, int NC>
+struct SlotCols {
+  int col[NC];
+  bool valid[NC];
+};
+
+template <typename T, int NC, int L2>
+__device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers& b, const SlotCols<T, NC>& sc,
+                                             T* const* Xc, T* const* Rc, T* const* Pc, const T* const* Qc,
+                                             const CgScalars* st, int fused, Cx<T>* Wslot, const Cx<T>* tw2,
+                                             unsigned char* smem, double* rr) {
+  const int N1 = 1 << dd.l1;
+  const RowUnit ru = row_unit(blockIdx.x, N1);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = w == 0 ? ru.rowA : ru.rowB;
+  const bool active = (w == 0) || !ru.single;
+  T* sp = reinterpret_cast<T*>(smem);                                     // [2][NC][L2] real inputs
+  Cx<T>* sz = reinterpret_cast<Cx<T>*>(smem + 2 * NC * L2 * sizeof(T));  // [2][L2] complex rows
+  if (active) {
+    T a[NC], bb[NC];
+    if (fused) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        a[c] = sc.valid[c] ? (T)st->a[sc.col[c]] : T(0);
+        bb[c] = sc.valid[c] ? (T)st->b[sc.col[c]] : T(0);
+      }
+    }
+    for (int e = lane; e < L2; e += 64) {
+      const int64_t pos = (int64_t)row * L2 + e;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T p = T(0);
+        if (sc.valid[c]) {
+          if (fused) {
+            // the previous CG update, folded in: x += a p, r -= a q, p = r + b p
+            const T p0 = Pc[c][pos], r0 = Rc[c][pos], q0 = Qc[c][pos], x0 = Xc[c][pos];
+            const T r1 = r0 - a[c] * q0;
+            p = r1 + bb[c] * p0;
+            Xc[c][pos] = x0 + a[c] * p0;
+            Rc[c][pos] = r1;
+            Pc[c][pos] = p;
+            rr[c] += (double)r1 * (double)r1;
+          } else {
+            p = Pc[c][pos];
+          }
+        }
+        sp[(w * NC + c) * L2 + e] = p;
+      }
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  const int64_t D = dd.D;
+  const T half_over_d = T(0.5) / (T)D, two_over_d = T(2) / (T)D;
+  const T rt2 = (T)1.41421356237309504880;
+  Cx<T>* zr = sz + w * L2;
+  for (int e = lane; e < L2; e += 64) {
+    const int64_t k = row + ((int64_t)e << dd.l1);
+    T u = sp[(w * NC + 0) * L2 + e], um = T(0);
+    T v = T(0), vm = T(0);
+    if (NC == 2) v = sp[(w * NC + 1) * L2 + e];
+    if (k == 0) {
+      u *= rt2;
+      v *= rt2;
+    } else {
+      const int mrow = (N1 - row) & (N1 - 1);
+      const int mw = (mrow == ru.rowA) ? 0 : 1;
+      const int me = mirror_col(row, e, L2);
+      um = sp[(mw * NC + 0) * L2 + me];
+      if (NC == 2) vm = sp[(mw * NC + 1) * L2 + me];
+    }
+    T s, c;
+    sin_cos_pi((T)k * half_over_d, &s, &c);
+    const Cx<T> g{u + vm, v - um};
+    zr[e] = cmul(Cx<T>{c, s}, g);
+  }
+  fft_stages<T, L2, 1, +1>(zr, tw2, lane);
+  for (int e = lane; e < L2; e += 64) {
+    const int64_t m = ((int64_t)e * row) & (D - 1);
+    Wslot[(int64_t)row * L2 + e] = cmul(zr[e], unit_root<+1, T>(m, two_over_d));
+  }
+}
+
+template <int L2>
+__global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, float* X, float* R, float* P,
+                                                     const float* Q, double* xm, double* rm, double* pm,
+                                                     const double* qm, CgScalars* st, int fused, int apply_only) {
+  if (!apply_only && st->stop) return;
+  constexpr size_t kF = 2 * 2 * L2 * sizeof(float) + 2 * L2 * sizeof(Cx<float>);
+  constexpr size_t kD = 2 * 1 * L2 * sizeof(double) + 2 * L2 * sizeof(Cx<double>);
+  __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
+  __shared__ double shm[8];
+  const int slot = blockIdx.y;
+  const int64_t ld = dd.D;
+  const bool do_rr = fused && !apply_only;
+  if (slot < dd.npairs) {
+    SlotCols<float, 2> sc;
+    float *Xc[2], *Rc[2], *Pc[2];
+    const float* Qc[2];
+    for (int c = 0; c < 2; ++c) {
+      sc.col[c] = 2 * slot + c;
+      sc.valid[c] = sc.col[c] < dd.K;
+      const int64_t off = (int64_t)(sc.valid[c] ? sc.col[c] : 0) * ld;
+      Xc[c] = X + off;
+      Rc[c] = R + off;
+      Pc[c] = P + off;
+      Qc[c] = Q + off;
+    }
+    double rr[2] = {0.0, 0.0};
+    rows_in_body<float, 2, L2>(dd, b, sc, Xc, Rc, Pc, Qc, st, fused, reinterpret_cast<Cx<float>*>(b.Wf) + slot * ld,
+                               as_cx(b.tw2f), smem, rr);
+    if (do_rr) {
+      for (int c = 0; c < 2; ++c) {
+        const double t = block_sum(rr[c], shm);
+        if (threadIdx.x == 0 && sc.valid[c]) b.rr[(int64_t)sc.col[c] * dd.units + blockIdx.x] = t;
+      }
+    }
+  } else {
+    SlotCols<double, 1> sc;
+    sc.col[0] = dd.K;
+    sc.valid[0] = true;
+    double* Xc[1] = {xm};
+    double* Rc[1] = {rm};
+    double* Pc[1] = {pm};
+    const double* Qc[1] = {qm};
+    double rr[1] = {0.0};
+    rows_in_body<double, 1, L2>(dd, b, sc, Xc, Rc, Pc, Qc, st, fused, reinterpret_cast<Cx<double>*>(b.Wd),
+                                as_cx(b.tw2d), smem, rr);
+    if (do_rr) {
+      const double t = block_sum(rr[0], shm);
+      if (threadIdx.x == 0) b.rr[(int64_t)dd.K * dd.units + blockIdx.x] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launch 2
+// A tile of G consecutive n2 columns of the N1 x N2 intermediate (all rows):
+// per column, the inverse length-N1 transform (giving the signal in FFT order
+// n = n2 + N2 n1), the mask, the forward transform, the twiddle
+// e^{-2 pi i n2 k1 / D}; written back in place.  b0 mode: the tile starts
+// from the real vector vb (middle-launch order) and runs the forward half only.
+template <typename T, int G, int L1>
+__device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const double* __restrict__ mk,
+                                         const double* __restrict__ vb, const Cx<T>* tw1, int tile,
+                                         unsigned char* smem) {
+  constexpr int LP = L1 + 1;  // padded group stride
+  const int N2 = 1 << dd.l2;
+  const int64_t D = dd.D;
+  const int g0 = tile * G;
+  const T two_over_d = T(2) / (T)D;
+  Cx<T>* s = reinterpret_cast<Cx<T>*>(smem);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  if (vb) {
+    for (int e = tid; e < G * L1; e += blockDim.x) {
+      const int j = e / L1, n1 = e - (e / L1) * L1;
+      s[j * LP + n1] = Cx<T>{(T)vb[(int64_t)(g0 + j) * L1 + n1], T(0)};
+    }
+  } else {
+    for (int e = tid; e < G * L1; e += blockDim.x) {
+      const int j = e % G, k1 = e / G;
+      s[j * LP + k1] = W[(int64_t)k1 * N2 + g0 + j];
+    }
+  }
+  __syncthreads();
+  for (int j = w; j < G; j += (int)(blockDim.x >> 6)) {
+    Cx<T>* buf = s + j * LP;
+    const int n2 = g0 + j;
+    if (!vb) {
+      fft_stages<T, L1, 1, +1>(buf, tw1, lane);
+      for (int n1 = lane; n1 < L1; n1 += 64) {
+        const T m = (T)mk[(int64_t)n2 * L1 + n1];
+        buf[n1] = Cx<T>{buf[n1].x * m, buf[n1].y * m};
+      }
+    }
+    fft_stages<T, L1, 1, -1>(buf, tw1, lane);
+    for (int k1 = lane; k1 < L1; k1 += 64) {
+      const int64_t m = ((int64_t)n2 * k1) & (D - 1);
+      buf[k1] = cmul(buf[k1], unit_root<-1, T>(m, two_over_d));
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < G * L1; e += blockDim.x) {
+    const int j = e % G, k1 = e / G;
+    W[(int64_t)k1 * N2 + g0 + j] = s[j * LP + k1];
+  }
+}
+
+template <int L1>
+struct MidGeom {
+  static constexpr int GF = (8192 / L1) < 16 ? (8192 / L1) : 16;
+  static constexpr int GD = (4096 / L1) < 8 ? (4096 / L1) : 8;
+  static constexpr size_t LDS_F = (size_t)GF * (L1 + 1) * sizeof(Cx<float>);
+  static constexpr size_t LDS_D = (size_t)GD * (L1 + 1) * sizeof(Cx<double>);
+  static constexpr size_t LDS = LDS_F > LDS_D ? LDS_F : LDS_D;
+};
+
+template <int L1>
+__global__ __launch_bounds__(256) void k_dct_mid(DctDims dd, DctBuffers b, const double* vb, CgScalars* st,
+                                                 int apply_only) {
+  if (!apply_only && st->stop) return;
+  using G = MidGeom<L1>;
+  __shared__ __align__(16) unsigned char smem[G::LDS];
+  const int N2 = 1 << dd.l2;
+  const int ftiles = vb ? 0 : dd.npairs * (N2 / G::GF);
+  const int blk = blockIdx.x;
+  if (blk < ftiles) {
+    const int slot = blk / (N2 / G::GF), tile = blk - slot * (N2 / G::GF);
+    mid_body<float, G::GF, L1>(dd, reinterpret_cast<Cx<float>*>(b.Wf) + (int64_t)slot * dd.D, b.mk, nullptr,
+                               as_cx(b.tw1f), tile, smem);
+  } else {
+    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd), b.mk, vb, as_cx(b.tw1d), blk - ftiles,
+                                smem);
+  }
+}
+
+// ---------------------------------------------------------------- launch 3
+// Forward row transforms, then per coefficient the operator's output, q = out
+// + alpha p (or b0), and the dot products of the pass.
+template <typename T, int NC, int L2>
+__device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Wslot, const Cx<T>* tw2,
+                                              const SlotCols<T, NC>& sc, const T* const* Pc, const T* const* Rc,
+                                              T* const* Qc, const float* __restrict__ alpha, double* b0,
+                                              bool dots, unsigned char* smem, double (*acc)[3]) {
+  const int N1 = 1 << dd.l1;
+  const RowUnit ru = row_unit(blockIdx.x, N1);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = w == 0 ? ru.rowA : ru.rowB;
+  const bool active = (w == 0) || !ru.single;
+  Cx<T>* sz = reinterpret_cast<Cx<T>*>(smem);  // [2][L2]
+  Cx<T>* zr = sz + w * L2;
+  if (active) {
+    for (int e = lane; e < L2; e += 64) zr[e] = Wslot[(int64_t)row * L2 + e];
+    fft_stages<T, L2, 1, -1>(zr, tw2, lane);
+  }
+  __syncthreads();
+  if (!active) return;
+  const T half_over_d = T(0.5) / (T)dd.D;
+  const T rh = (T)0.70710678118654752440;
+  for (int e = lane; e < L2; e += 64) {
+    const int64_t k = row + ((int64_t)e << dd.l1);
+    const Cx<T> z = zr[e];
+    Cx<T> zm = z;
+    if (k != 0) {
+      const int mrow = (N1 - row) & (N1 - 1);
+      const int mw = (mrow == ru.rowA) ? 0 : 1;
+      zm = sz[mw * L2 + mirror_col(row, e, L2)];
+    }
+    T s, c;
+    sin_cos_pi((T)k * half_over_d, &s, &c);
+    const T ck = k == 0 ? rh : T(1);
+    // (z + conj zm) / 2 and (z - conj zm) / 2i
+    const Cx<T> v1{(z.x + zm.x) * T(0.5), (z.y - zm.y) * T(0.5)};
+    const Cx<T> v2{(z.y + zm.y) * T(0.5), (zm.x - z.x) * T(0.5)};
+    T out[2];
+    out[0] = ck * (c * v1.x + s * v1.y);
+    out[1] = ck * (c * v2.x + s * v2.y);
+    const int64_t pos = (int64_t)row * L2 + e;
+    if (b0) {
+      b0[pos] = (double)out[0];
+      continue;
+    }
+    const T al = (T)alpha[pos];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      if (!sc.valid[cc]) continue;
+      const T p = Pc[cc][pos];
+      const T q = out[cc] + al * p;
+      Qc[cc][pos] = q;
+      if (dots) {
+        const T r = Rc[cc][pos];
+        acc[cc][0] += (double)p * (double)q;
+        acc[cc][1] += (double)r * (double)q;
+        acc[cc][2] += (double)q * (double)q;
+      }
+    }
+  }
+}
+
+template <int L2>
+__global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, const float* P, const float* R,
+                                                      float* Q, const double* pm, const double* rm, double* qm,
+                                                      const float* alpha, double* b0, ConvReduce red,
+                                                      CgScalars* st, int fused, int apply_only) {
+  if (!apply_only && st->stop) return;
+  const CgCtl ctl = apply_only ? CgCtl{} : load_cg_ctl(st);
+  constexpr size_t kF = 2 * L2 * sizeof(Cx<float>);
+  constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);
+  __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
+  const int slot = b0 ? dd.npairs : blockIdx.y;
+  const int64_t ld = dd.D;
+  const bool dots = !apply_only;
+  double acc[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  int cols[2] = {0, 0};
+  bool valid[2] = {false, false};
+  if (slot < dd.npairs) {
+    SlotCols<float, 2> sc;
+    const float *Pc[2], *Rc[2];
+    float* Qc[2];
+    for (int c = 0; c < 2; ++c) {
+      sc.col[c] = 2 * slot + c;
+      sc.valid[c] = sc.col[c] < dd.K;
+      cols[c] = sc.col[c];
+      valid[c] = sc.valid[c];
+      const int64_t off = (int64_t)(sc.valid[c] ? sc.col[c] : 0) * ld;
+      Pc[c] = P + off;
+      Rc[c] = R + off;
+      Qc[c] = Q + off;
+    }
+    rows_out_body<float, 2, L2>(dd, reinterpret_cast<const Cx<float>*>(b.Wf) + slot * ld, as_cx(b.tw2f), sc, Pc,
+                                Rc, Qc, alpha, nullptr, dots, smem, acc);
+  } else {
+    SlotCols<double, 1> sc;
+    sc.col[0] = dd.K;
+    sc.valid[0] = true;
+    cols[0] = dd.K;
+    valid[0] = true;
+    const double* Pc[1] = {pm};
+    const double* Rc[1] = {rm};
+    double* Qc[1] = {qm};
+    rows_out_body<double, 1, L2>(dd, reinterpret_cast<const Cx<double>*>(b.Wd), as_cx(b.tw2d), sc, Pc, Rc, Qc,
+                                 alpha, b0, dots, smem, acc);
+  }
+  if (!dots) return;
+  __shared__ double shm[8];
+  __shared__ double mine[2][5], tot[5 * kMaxCols];
+  const int nv = fused ? 5 : 3;
+  for (int c = 0; c < 2; ++c) {
+    const double g = block_sum(acc[c][0], shm);
+    const double dl = block_sum(acc[c][1], shm);
+    const double et = block_sum(acc[c][2], shm);
+    if (threadIdx.x == 0) {
+      if (fused) {
+        const double r2 = valid[c] ? b.rr[(int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
+        mine[c][0] = r2;  // r^T z = r^T r (no preconditioner)
+        mine[c][1] = r2;
+        mine[c][2] = g;
+        mine[c][3] = dl;
+        mine[c][4] = et;
+      } else {
+        mine[c][0] = g;
+        mine[c][1] = dl;
+        mine[c][2] = et;
+      }
+    }
+  }
+  __syncthreads();
+  bool last = false;
+  for (int c = 0; c < 2; ++c) {
+    if (!valid[c]) continue;
+    if (column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, dd.units, dd.units,
+                           cols[c], dd.K + 1, nv, mine[c], tot))
+      last = true;
+  }
+  if (!last) return;
+  if (fused)
+    finish_fused(st, tot, dd.K + 1, ctl);
+  else
+    finish_step(st, tot, ctl);
+}
+
+// ---------------------------------------------------------------- set-up
+// Twiddle tables e^{2 pi i j / L} for the two transform lengths.
+__global__ void k_dct_tables(int N1, int N2, float* tw1f, float* tw2f, double* tw1d, double* tw2d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N1) {
+    double s, c;
+    sincospi(2.0 * j / N1, &s, &c);
+    tw1d[2 * j] = c;
+    tw1d[2 * j + 1] = s;
+    tw1f[2 * j] = (float)c;
+    tw1f[2 * j + 1] = (float)s;
+  }
+  if (j < N2) {
+    double s, c;
+    sincospi(2.0 * j / N2, &s, &c);
+    tw2d[2 * j] = c;
+    tw2d[2 * j + 1] = s;
+    tw2f[2 * j] = (float)c;
+    tw2f[2 * j + 1] = (float)s;
+  }
+}
+
+// Observed sample j sits at FFT index n = j/2 (j even) or D-1-(j-1)/2 (odd),
+// n = n2 + N2 n1, which the middle launch reads at n2 N1 + n1: there the mask
+// value beta/D and the data term beta sqrt(2/D) y_i.
+__global__ void k_dct_scatter(int64_t D, int l1, int l2, const int32_t* __restrict__ rows, int64_t N,
+                              const float* __restrict__ y, double mval, double yscale, double* __restrict__ mk,
+                              double* __restrict__ vb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t j = rows[i];
+  const int64_t n = (j & 1) == 0 ? j / 2 : D - 1 - (j - 1) / 2;
+  const int64_t n2 = n & ((int64_t(1) << l2) - 1), n1 = n >> l2;
+  const int64_t idx = (n2 << l1) + n1;
+  mk[idx] = mval;
+  vb[idx] = yscale * (double)y[i];
+}
+
+}  // namespace
+
+#define COFEM_DCT_SWITCH(LEN, CALL) \
+  switch (LEN) {                    \
+    case 64:                        \
+      CALL(64);                     \
+      break;                        \
+    case 128:                       \
+      CALL(128);                    \
+      break;                        \
+    case 256:                       \
+      CALL(256);                    \
+      break;                        \
+    case 512:                       \
+      CALL(512);                    \
+      break;                        \
+    case 1024:                      \
+      CALL(1024);                   \
+      break;                        \
+    default:                        \
+      return hipErrorInvalidValue;  \
+  }
+
+hipError_t dct_rows_in(const DctDims& dd, const DctBuffers& b, void* X, void* R, void* P, const void* Q, double* xm,
+                       double* rm, double* pm, const double* qm, CgScalars* st, int fused, int apply_only,
+                       hipStream_t s) {
+  const dim3 grid((unsigned)dd.units, (unsigned)(dd.npairs + 1));
+#define COFEM_ROWS_IN(L)                                                                                         \
+  hipLaunchKernelGGL(k_dct_rows_in<L>, grid, dim3(128), 0, s, dd, b, static_cast<float*>(X), static_cast<float*>(R), \
+                     static_cast<float*>(P), static_cast<const float*>(Q), xm, rm, pm, qm, st, fused, apply_only)
+  COFEM_DCT_SWITCH(1 << dd.l2, COFEM_ROWS_IN)
+#undef COFEM_ROWS_IN
+  return hipGetLastError();
+}
+
+static hipError_t launch_mid(const DctDims& dd, const DctBuffers& b, const double* vb, CgScalars* st, int apply_only,
+                             hipStream_t s) {
+  const int N2 = 1 << dd.l2;
+#define COFEM_MID(L)                                                                                     \
+  {                                                                                                      \
+    const int nb = (vb ? 0 : dd.npairs * (N2 / MidGeom<L>::GF)) + N2 / MidGeom<L>::GD;                 \
+    hipLaunchKernelGGL(k_dct_mid<L>, dim3((unsigned)nb), dim3(256), 0, s, dd, b, vb, st, apply_only); \
+  }
+  COFEM_DCT_SWITCH(1 << dd.l1, COFEM_MID)
+#undef COFEM_MID
+  return hipGetLastError();
+}
+
+hipError_t dct_mid(const DctDims& dd, const DctBuffers& b, CgScalars* st, int apply_only, hipStream_t s) {
+  return launch_mid(dd, b, nullptr, st, apply_only, s);
+}
+
+static hipError_t launch_rows_out(const DctDims& dd, const DctBuffers& b, const void* P, const void* R, void* Q,
+                                  const double* pm, const double* rm, double* qm, const float* alpha, double* b0,
+                                  const ConvReduce& red, CgScalars* st, int fused, int apply_only, hipStream_t s) {
+  const dim3 grid((unsigned)dd.units, b0 ? 1u : (unsigned)(dd.npairs + 1));
+#define COFEM_ROWS_OUT(L)                                                                                     \
+  hipLaunchKernelGGL(k_dct_rows_out<L>, grid, dim3(128), 0, s, dd, b, static_cast<const float*>(P),             \
+                     static_cast<const float*>(R), static_cast<float*>(Q), pm, rm, qm, alpha, b0, red, st, fused, \
+                     apply_only)
+  COFEM_DCT_SWITCH(1 << dd.l2, COFEM_ROWS_OUT)
+#undef COFEM_ROWS_OUT
+  return hipGetLastError();
+}
+
+hipError_t dct_rows_out(const DctDims& dd, const DctBuffers& b, const void* P, const void* R, void* Q,
+                        const double* pm, const double* rm, double* qm, const float* alpha, const ConvReduce& red,
+                        CgScalars* st, int fused, int apply_only, hipStream_t s) {
+  return launch_rows_out(dd, b, P, R, Q, pm, rm, qm, alpha, nullptr, red, st, fused, apply_only, s);
+}
+
+hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const float* y, double beta, double* mk,
+                     double* vb, float* tw1f, float* tw2f, double* tw1d, double* tw2d, const DctBuffers& b,
+                     double* b0, hipStream_t s) {
+  const int N1 = 1 << dd.l1, N2 = 1 << dd.l2;
+  const int nt = N1 > N2 ? N1 : N2;
+  hipLaunchKernelGGL(k_dct_tables, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, N1, N2, tw1f, tw2f, tw1d,
+                     tw2d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(mk, 0, sizeof(double) * (size_t)dd.D, s);
+  if (e == hipSuccess) e = hipMemsetAsync(vb, 0, sizeof(double) * (size_t)dd.D, s);
+  if (e != hipSuccess) return e;
+  if (N > 0) {
+    hipLaunchKernelGGL(k_dct_scatter, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, dd.D, dd.l1, dd.l2, rows,
+                       N, y, beta / (double)dd.D, beta * sqrt(2.0 / (double)dd.D), mk, vb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // b0 = beta C S^T y: the forward half of the middle launch on vb, then the
+  // output rows of the float64 column
+  e = launch_mid(dd, b, vb, nullptr, 1, s);
+  if (e != hipSuccess) return e;
+  const ConvReduce none{};
+  return launch_rows_out(dd, b, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, b0, none, nullptr, 0,
+                         1, s);
+}
+
+}  // namespace cofem

@@ -17,6 +17,13 @@ precision beta known):
                         beta = 1e4; K = 16; eps 1e-5; U = 400; T_em = 30.
 * ``conv_1024x1024_k9`` same law, 9x9 taps, 1024x1024 image; 1% nonzeros
                         N(0,1); beta = 1e4; K = 16; eps 1e-5; U = 400; T_em = 30.
+* ``dct_4096``          inverse DCT (orthonormal DCT-III) of length D = 4096
+                        followed by N = D/4 samples uniform without replacement;
+                        4% nonzero N(0,1) coefficients; beta = 4e4 (noise sigma
+                        0.005, the paper's dense setting; the DCT runs state
+                        none); K = 20; eps 1e-5; U = 400; T_em = 30.
+* ``dct_262144``        the same law at D = 2^18 with 10% nonzeros (the
+                        high-dimensional DCT runs of Sec. 4).
 * ``batched_64``        64 dense problems, D_i = 4*U{256..4096}, N_i = D_i/4,
                         Phi iid N(0, 1/N_i) rounded to bfloat16; 2% nonzeros
                         N(0,1); beta = 1e3; K = 16; eps 1e-5; U = 400; T_em = 30.
@@ -36,7 +43,7 @@ import numpy as np
 
 @dataclasses.dataclass
 class Problem:
-    kind: str                      # "dense" | "conv"
+    kind: str                      # "dense" | "conv" | "dct"
     N: int
     D: int
     y: np.ndarray                  # float32 (N,)
@@ -49,6 +56,7 @@ class Problem:
     seed: int
     phi: Optional[np.ndarray] = None    # float32 (N, D), row-major
     taps: Optional[np.ndarray] = None   # float32 (kh, kw)
+    rows: Optional[np.ndarray] = None   # int32 (N,) observed samples (DCT dictionary)
     H: int = 0
     W: int = 0
     name: str = ""
@@ -117,6 +125,27 @@ def conv_problem(H, W, k, *, rho, beta, K, tol, max_iter=400, T_em=30, seed=0,
                    taps=taps, H=H, W=W, name=name)
 
 
+def _inverse_dct_f64(z):
+    """Forward model for data synthesis only: the orthonormal inverse DCT
+    (scipy's DCT-III) of the coefficient vector."""
+    import scipy.fft as sf
+
+    return sf.idct(np.asarray(z, np.float64), type=2, norm="ortho")
+
+
+def dct_problem(D, *, rho, beta, K, tol, max_iter=400, T_em=30, seed=0, name="") -> Problem:
+    """Phi = inverse DCT followed by the selection of N = D/4 samples drawn
+    uniformly without replacement (sorted); z* has round(rho D) N(0,1)
+    coefficients; y = Phi z* + N(0, 1/beta) noise."""
+    rng = np.random.default_rng(seed)
+    N = D // 4
+    rows = np.sort(rng.choice(D, size=N, replace=False)).astype(np.int32)
+    z = _sparse_signal(rng, D, _nnz(rho, D), "normal")
+    clean = _inverse_dct_f64(z)[rows]
+    y = (clean + rng.standard_normal(N) / math.sqrt(beta)).astype(np.float32)
+    return Problem("dct", N, D, y, z, float(beta), K, tol, max_iter, T_em, seed, rows=rows, name=name)
+
+
 def round_to_bf16(x: np.ndarray) -> np.ndarray:
     """float32 -> nearest bfloat16 (ties to even), returned as float32."""
     x = np.ascontiguousarray(x, dtype=np.float32)
@@ -145,6 +174,16 @@ def conv_256x256_k7(seed=0):
 def conv_1024x1024_k9(seed=0):
     return conv_problem(1024, 1024, 9, rho=0.01, beta=1e4, K=16, tol=1e-5, max_iter=400,
                         T_em=30, seed=seed, law="normal", name="conv_1024x1024_k9")
+
+
+def dct_4096(seed=0):
+    return dct_problem(4096, rho=0.04, beta=4e4, K=20, tol=1e-5, max_iter=400, T_em=30, seed=seed,
+                       name="dct_4096")
+
+
+def dct_262144(seed=0):
+    return dct_problem(262144, rho=0.1, beta=4e4, K=20, tol=1e-5, max_iter=400, T_em=30, seed=seed,
+                       name="dct_262144")
 
 
 def batched_sizes(seed=0, count=64):

@@ -1,0 +1,191 @@
+"""GPU parity of the DCT dictionary (inverse DCT + undersampling mask, Sec. 4)
+through the C ABI against the FP64 oracle.
+
+The operator runs as float32 complex FFTs for the probe columns (a length-D
+transform's rounding error grows like u32 log2 D, u32 = 2^-24) and float64
+FFTs for the mean column.  Step parity uses the same bar as the other
+dictionaries: norm-wise relative error 1e-4 on mu, s and 1/alpha after one
+E-step + M-step from the GPU's alpha, the oracle running the GPU's CG count.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2202_12808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-4
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2202_12808_amd import cofem as C
+    C.load()  # fails loudly when the library is missing
+    return torch
+
+
+def relerr(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _ctx(torch, p, **kw):
+    from paper_2202_12808_amd.cofem import CoFEM
+    rows = torch.from_numpy(p.rows.astype(np.int32)).cuda()
+    y = torch.from_numpy(p.y).cuda()
+    return CoFEM.dct(rows, y, p.D, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, **kw)
+
+
+def _op(p):
+    return O.DctMaskOperator(p.rows, p.D)
+
+
+@pytest.mark.parametrize("D,K,N", [(4096, 20, 1024), (8192, 5, 3000), (65536, 1, 16384), (16384, 32, 4096),
+                                   (1 << 20, 2, 1 << 18), (4096, 3, 4096)])
+def test_dct_apply_A(torch_dev, D, K, N):
+    torch = torch_dev
+    _say("dct apply_A", D, K, N)
+    rng = np.random.default_rng(D + K)
+    rows = np.sort(rng.choice(D, N, replace=False)).astype(np.int32)
+    p = synth.Problem("dct", N, D, rng.standard_normal(N).astype(np.float32), np.zeros(D), 321.0, K, 1e-6, 400, 30,
+                      1, rows=rows)
+    alpha = (10.0 ** rng.uniform(-2, 4, D)).astype(np.float32)
+    V = rng.standard_normal((D, K)).astype(np.float32)
+    vm = rng.standard_normal(D)
+    with _ctx(torch, p) as g:
+        g.set_alpha(torch.from_numpy(alpha))
+        q, qm = g.apply_A(torch.from_numpy(V.T.copy()), torch.from_numpy(vm))
+        q = q.cpu().numpy().T
+        qm = qm.cpu().numpy()
+    op = _op(p)
+    A = O.cofem_oracle.make_apply_A(op, p.beta, alpha.astype(np.float64))
+    ref = A(V.astype(np.float64))
+    # the dictionary part alone, so the alpha term cannot hide an error in it
+    PtP = p.beta * op.apply_t(op.apply(V.astype(np.float64)))
+    errs = [relerr(q[:, c] - alpha * V[:, c], PtP[:, c]) for c in range(K)]
+    _say("float columns: relerr of beta Phi^T Phi v max", max(errs), "of A v max",
+         max(relerr(q[:, c], ref[:, c]) for c in range(K)), "mean column", relerr(qm, A(vm)))
+    bound = 8 * 2.0 ** -24 * np.log2(D)
+    assert max(errs) < bound
+    for c in range(K):
+        assert relerr(q[:, c], ref[:, c]) < bound
+    mref = p.beta * op.apply_t(op.apply(vm))
+    assert relerr(qm - alpha.astype(np.float64) * vm, mref) < 1e-13
+
+
+def _step_parity(torch, p, t_free, label):
+    op = _op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _ctx(torch, p) as g:
+        if t_free:
+            g.em_step(t_free)
+        alpha = g.posterior()[2].cpu().numpy()
+        stats = g.em_step(1)[0]
+        mu, s, alpha_new = [x.cpu().numpy() for x in g.posterior()]
+    n, t = stats["cg_iters"], stats["t"]
+    assert t == t_free + 1
+    e = O.cofem_estep(op, b0, p.beta, alpha.astype(np.float64), p.K, p.tol, p.max_iter, p.seed, t, fixed_iters=n)
+    a_ref, _ = O.mstep(e.mu, e.s)
+    errs = (relerr(mu, e.mu), relerr(s, e.s), relerr(1.0 / alpha_new.astype(np.float64), 1.0 / a_ref))
+    _say(label, "t", t, "cg", n, "relerr mu/s/(1/alpha)", errs, "oracle ratio at that count", e.cg.rel_resid)
+    assert stats["converged"] == 1 or n == p.max_iter
+    assert all(err < STEP_TOL for err in errs), errs
+
+
+@pytest.mark.parametrize("t_free", [0, 5])
+def test_dct_4096_step_parity(torch_dev, t_free):
+    _step_parity(torch_dev, synth.dct_4096(0), t_free, f"dct_4096 t_free={t_free}")
+
+
+def test_dct_odd_exponent_odd_K_step_parity(torch_dev):
+    # D = 2^13 (rows of 64, 128 rows), K odd (the last float pair half empty)
+    p = synth.dct_problem(8192, rho=0.03, beta=2e3, K=7, tol=1e-6, seed=5, name="dct_8192")
+    _step_parity(torch_dev, p, 2, "dct_8192 K=7")
+
+
+def test_dct_262144_step_parity(torch_dev):
+    # the high-dimensional workload at its full size, first E-step
+    _step_parity(torch_dev, synth.dct_262144(0), 0, "dct_262144")
+
+
+def test_dct_full_mask_closed_form(torch_dev):
+    # every sample observed: Phi = C^T is orthonormal, A = (beta + alpha) I, so
+    # the first solve takes one CG iteration and mu = beta C y / (beta + alpha),
+    # s = 1 / (beta + alpha) for every K
+    torch = torch_dev
+    D = 4096
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(D).astype(np.float32)
+    p = synth.Problem("dct", D, D, y, np.zeros(D), 50.0, 4, 1e-7, 200, 3, 3, rows=np.arange(D, dtype=np.int32))
+    with _ctx(torch, p) as g:
+        st = g.em_step(3)
+        mu, s, alpha = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    assert st[0]["cg_iters"] == 1
+    c = O.DctMaskOperator(np.arange(D), D).apply_t(y.astype(np.float64))
+    a = np.ones(D)
+    for _ in range(3):
+        m_ref = p.beta * c / (p.beta + a)
+        v_ref = 1.0 / (p.beta + a)
+        a = 1.0 / (m_ref * m_ref + v_ref)
+    assert relerr(mu, m_ref) < 1e-6
+    assert relerr(s, v_ref) < 1e-6
+    assert relerr(alpha, a) < 1e-6
+
+
+def test_dct_true_residual_matches_float64_recomputation(torch_dev):
+    torch = torch_dev
+    p = synth.dct_4096(1)
+    op = _op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _ctx(torch, p) as g:
+        g.em_step(2)
+        alpha = g.posterior()[2].cpu().numpy().astype(np.float64)
+        st = g.em_step(1)[0]
+        X, m = g.solution()
+    X = X.cpu().numpy().astype(np.float64).T
+    m = m.cpu().numpy()
+    B = np.concatenate([O.rademacher_probes(p.seed, st["t"], p.K, p.D), b0[:, None]], axis=1)
+    A = O.cofem_oracle.make_apply_A(op, p.beta, alpha)
+    ref = np.linalg.norm(B - A(np.concatenate([X, m[:, None]], axis=1))) / np.linalg.norm(B)
+    # float32 transforms of the probe columns: an absolute error of order
+    # u32 log2(D) beta ||X_probes||_F (||Phi||_2 = 1)
+    floor = 8 * 2.0 ** -24 * np.log2(p.D) * p.beta * np.linalg.norm(X) / np.linalg.norm(B)
+    _say("dct true residual gpu", st["rel_resid_true"], "cpu float64", ref, "floor", floor, "cg", st["cg_iters"])
+    assert abs(st["rel_resid_true"] - ref) <= 0.02 * ref + floor
+
+
+def test_dct_runs_are_bit_reproducible(torch_dev):
+    torch = torch_dev
+    p = synth.dct_problem(16384, rho=0.05, beta=4e4, K=20, tol=1e-5, seed=4)
+    outs = []
+    for _ in range(2):
+        with _ctx(torch, p) as g:
+            st = g.em_step(4)
+            outs.append(([x["cg_iters"] for x in st], [x.cpu().numpy() for x in g.posterior()]))
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("D,rows,code", [(4096, [1, 5, 5], "INVALID_ARG"), (4096, [0, 4096], "INVALID_ARG"),
+                                         (5000, [1, 2], "UNSUPPORTED"), (2048, [1, 2], "UNSUPPORTED")])
+def test_dct_rejects_bad_problems(torch_dev, D, rows, code):
+    torch = torch_dev
+    from paper_2202_12808_amd import cofem as C
+    r = torch.tensor(rows, dtype=torch.int32, device="cuda")
+    y = torch.ones(len(rows), dtype=torch.float32, device="cuda")
+    with pytest.raises(C.CofemError) as ei:
+        C.CoFEM.dct(r, y, D, 10.0, 4)
+    assert getattr(C, "COFEM_ERR_" + code) == ei.value.status
