@@ -97,6 +97,7 @@ struct cofem_ctx {
   double* b0 = nullptr;
   float* alpha = nullptr;
   float* alpha_prev = nullptr;  // conv: the alpha of the last E-step (learned form's features)
+  double* dct_cn = nullptr;     // DCT: ||Phi e_k||^2 (state order), for the Jacobi preconditioner
   float *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
   double *xm = nullptr, *rm = nullptr, *pm = nullptr, *qm = nullptr;
   // conv probe blocks (float or double per the precision mode)
@@ -404,7 +405,8 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   double** vecs[6] = {&c->xm, &c->rm, &c->pm, &c->qm, &c->Vsm, &c->Qsm};
   for (double** v : vecs) COFEM_TRY(alloc(c, v, D));
   float *Wf = nullptr, *tw1f = nullptr, *tw2f = nullptr;
-  double *Wd = nullptr, *mk = nullptr, *vb = nullptr, *tw1d = nullptr, *tw2d = nullptr, *rr = nullptr;
+  double *Wd = nullptr, *vb = nullptr, *tw1d = nullptr, *tw2d = nullptr, *rr = nullptr;
+  uint8_t* mk = nullptr;
   COFEM_TRY(alloc(c, &Wf, 2 * D * (size_t)xd.npairs));
   COFEM_TRY(alloc(c, &Wd, 2 * D));
   COFEM_TRY(alloc(c, &mk, D));
@@ -413,19 +415,27 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &tw2f, (size_t)2 * N2));
   COFEM_TRY(alloc(c, &tw1d, (size_t)2 * N1));
   COFEM_TRY(alloc(c, &tw2d, (size_t)2 * N2));
-  COFEM_TRY(alloc(c, &rr, (size_t)(c->K + 1) * xd.units));
-  c->xb = DctBuffers{Wf, Wd, mk, tw1f, tw2f, tw1d, tw2d, rr};
+  COFEM_TRY(alloc(c, &rr, (size_t)2 * (c->K + 1) * xd.units));
+  COFEM_TRY(alloc(c, &c->minv, D));
+  COFEM_TRY(alloc(c, &c->dct_cn, D));
+  c->xb = DctBuffers{Wf, Wd, mk, c->beta / (double)p.D, tw1f, tw2f, tw1d, tw2d, rr};
   const int ncols = c->K + 1;
   ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
   const int64_t nupd = conv_update_blocks(cd);
   const int64_t nblks[3] = {nupd, nupd, xd.units};
-  const int nvs[3] = {1, 1, 5};  // init and true residual one value per column; an iteration up to five
+  // init one value per column; the preconditioned start (and the true
+  // residual) up to three per column; an iteration up to five per column
+  const int nvs[3] = {1, 3, 5};
   for (int i = 0; i < 3; ++i) {
-    COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], nvs[i], ncols));
+    // the iteration's tree runs per column slot (a float pair or the mean
+    // column) with regions of 2 * nv values
+    const int regions = i == 2 ? xd.npairs + 1 : ncols;
+    COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], i == 2 ? 2 * nvs[i] : nvs[i], regions));
     COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
     COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
   }
-  COFEM_HIP(c, dct_setup(xd, p.rows, p.N, p.y, c->beta, mk, vb, tw1f, tw2f, tw1d, tw2d, c->xb, c->b0, c->stream));
+  COFEM_HIP(c, dct_setup(xd, p.rows, p.N, p.y, c->beta, mk, vb, tw1f, tw2f, tw1d, tw2d, c->xb, c->b0,
+                         (c->flags & COFEM_FLAG_JACOBI) ? c->dct_cn : nullptr, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
   return COFEM_OK;
 }
@@ -701,8 +711,9 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
     return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
   if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
-  if ((q->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI)) && (n != 1 || p->kind != COFEM_CONV2D_CIRC))
-    return *why = "warm starts and the Jacobi preconditioner are built for convolution dictionaries",
+  if ((q->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI)) &&
+      (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
+    return *why = "warm starts and the Jacobi preconditioner are built for convolution and DCT dictionaries",
            COFEM_ERR_UNSUPPORTED;
   if (n > 1 || p->phi_dtype == COFEM_BF16 || (q->flags & COFEM_FLAG_BATCHED)) {
     // batched form: dense problems whose bfloat16 dictionary is the problem
@@ -799,7 +810,31 @@ cofem_status collect_times(cofem_ctx* c, int iters) {
 // COFEM_FLAG_WARM_PREV (X0 = [max(s_prev, 0) (.) p_k | mu_prev]),
 // COFEM_FLAG_JACOBI (M^-1 = 1/diag(A)), or a predictor set by the caller.
 bool conv_pcg(const cofem_ctx* c) {
-  return c->kind == COFEM_CONV2D_CIRC && (c->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI) || c->predictor);
+  return (c->kind == COFEM_CONV2D_CIRC || c->kind == COFEM_DCT_MASK) &&
+         (c->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI) || c->predictor);
+}
+
+// Q = A X into the scratch blocks (no reduction, no stop check).
+cofem_status apply_to_scratch(cofem_ctx* c, void* X, double* xm) {
+  if (c->kind == COFEM_DCT_MASK) {
+    COFEM_HIP(c, dct_rows_in(c->xd, c->xb, nullptr, nullptr, X, nullptr, nullptr, nullptr, xm, nullptr, nullptr,
+                             c->st, 0, 1, c->stream));
+    COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 1, c->stream));
+    COFEM_HIP(c, dct_rows_out(c->xd, c->xb, X, nullptr, c->vQs, xm, nullptr, c->Qsm, c->alpha, nullptr, c->red_pass,
+                              c->st, 0, 1, c->stream));
+  } else {
+    COFEM_HIP(c, conv_pass(c->cd, c->taps, X, xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm, c->red_pass,
+                           c->st, 1, c->stream));
+  }
+  return COFEM_OK;
+}
+
+cofem_status pcg_jacobi(cofem_ctx* c) {
+  if (c->kind == COFEM_DCT_MASK)
+    COFEM_HIP(c, dct_jacobi(c->xd, c->dct_cn, c->beta, c->alpha, c->minv, c->stream));
+  else
+    COFEM_HIP(c, conv_jacobi(c->cd, c->taps, c->beta, c->alpha, c->minv, c->stream));
+  return COFEM_OK;
 }
 
 cofem_status conv_start_pcg(cofem_ctx* c, int t) {
@@ -815,14 +850,14 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
     // iterations than the Jacobi diagonal, most of all right after the first
     // M-step, so it serves only as the probe columns' start.)
     COFEM_TRY(c->predictor(c, c->predictor_user, c->d0, c->mu0));
-    COFEM_HIP(c, conv_jacobi(cd, c->taps, c->beta, c->alpha, c->minv, c->stream));
+    COFEM_TRY(pcg_jacobi(c));
     d0 = c->d0;
     mu0 = c->mu0;
     c->active_minv = c->minv;
     start = true;
   } else {
     if (c->flags & COFEM_FLAG_JACOBI) {
-      COFEM_HIP(c, conv_jacobi(cd, c->taps, c->beta, c->alpha, c->minv, c->stream));
+      COFEM_TRY(pcg_jacobi(c));
       c->active_minv = c->minv;
     }
     if ((c->flags & COFEM_FLAG_WARM_PREV) && c->has_solution) {
@@ -830,15 +865,17 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
       start = true;
     }
   }
+  // the start's column reduction (conv_update_blocks blocks, three values per
+  // column): conv sizes red_pass for it, the DCT dictionary red_upd
+  const ConvReduce& rs = c->kind == COFEM_DCT_MASK ? c->red_upd : c->red_pass;
   if (start) {
     COFEM_HIP(c, conv_start(cd, c->seed, t, d0, mu0, c->vX, c->xm, c->stream));
-    COFEM_HIP(c, conv_pass(cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm, c->red_pass,
-                           c->st, 1, c->stream));
+    COFEM_TRY(apply_to_scratch(c, c->vX, c->xm));
     COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, c->vQs, c->Qsm, c->vX, c->vR, c->vP, c->xm,
-                               c->rm, c->pm, c->red_pass, c->st, c->stream));
+                               c->rm, c->pm, rs, c->st, c->stream));
   } else {
     COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, nullptr, nullptr, c->vX, c->vR, c->vP, c->xm,
-                               c->rm, c->pm, c->red_pass, c->st, c->stream));
+                               c->rm, c->pm, rs, c->st, c->stream));
   }
   return COFEM_OK;
 }
@@ -874,13 +911,13 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       // launch (state updated in place: no launch reads another row's state)
       const int fused = it > 0 ? 1 : 0;
       COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
-      COFEM_HIP(c, dct_rows_in(c->xd, c->xb, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm, c->st, fused, 0,
-                               c->stream));
+      COFEM_HIP(c, dct_rows_in(c->xd, c->xb, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm,
+                               conv_pcg(c) ? c->active_minv : nullptr, c->st, fused, 0, c->stream));
       COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 0, c->stream));
       COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
-      COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm, c->alpha, c->red_pass,
-                                c->st, fused, 0, c->stream));
+      COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm, c->alpha,
+                                conv_pcg(c) ? c->active_minv : nullptr, c->red_pass, c->st, fused, 0, c->stream));
     } else {
       // conv: the first launch of a solve is the operator pass on the start
       // direction (set 0); each later one a fused iteration, the previous
@@ -918,10 +955,10 @@ cofem_status true_residual(cofem_ctx* c, int t) {
   } else {
     if (c->kind == COFEM_DCT_MASK) {
       COFEM_HIP(c, dct_rows_in(c->xd, c->xb, nullptr, nullptr, c->vX, nullptr, nullptr, nullptr, c->xm, nullptr,
-                               c->st, 0, 1, c->stream));
+                               nullptr, c->st, 0, 1, c->stream));
       COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 1, c->stream));
-      COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vX, nullptr, c->vQs, c->xm, nullptr, c->Qsm, c->alpha, c->red_pass,
-                                c->st, 0, 1, c->stream));
+      COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vX, nullptr, c->vQs, c->xm, nullptr, c->Qsm, c->alpha, nullptr,
+                                c->red_pass, c->st, 0, 1, c->stream));
     } else {
       COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm,
                              c->red_pass, c->st, 1, c->stream));
@@ -1295,10 +1332,10 @@ static cofem_status apply_A_impl(cofem_ctx* ctx, int32_t problem, const float* v
     COFEM_HIP(ctx, conv_probes_in(cd, v_probes, ctx->vVs, ctx->stream));
     COFEM_HIP(ctx, perm_in_f64(cd, v_mean, ctx->Vsm, ctx->stream));
     COFEM_HIP(ctx, dct_rows_in(ctx->xd, ctx->xb, nullptr, nullptr, ctx->vVs, nullptr, nullptr, nullptr, ctx->Vsm,
-                               nullptr, ctx->st, 0, 1, ctx->stream));
+                               nullptr, nullptr, ctx->st, 0, 1, ctx->stream));
     COFEM_HIP(ctx, dct_mid(ctx->xd, ctx->xb, ctx->st, 1, ctx->stream));
     COFEM_HIP(ctx, dct_rows_out(ctx->xd, ctx->xb, ctx->vVs, nullptr, ctx->vQs, ctx->Vsm, nullptr, ctx->Qsm,
-                                ctx->alpha, ctx->red_pass, ctx->st, 0, 1, ctx->stream));
+                                ctx->alpha, nullptr, ctx->red_pass, ctx->st, 0, 1, ctx->stream));
     COFEM_HIP(ctx, conv_probes_out(cd, ctx->vQs, q_probes, ctx->stream));
     COFEM_HIP(ctx, perm_out_f64(cd, ctx->Qsm, q_mean, ctx->stream));
     COFEM_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1401,13 +1438,13 @@ cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
     const DctDims& xd = ctx->xd;
     const DctBuffers& xb = ctx->xb;
     rc = timed([&] { return dct_rows_in(xd, xb, nullptr, nullptr, ctx->vP, nullptr, nullptr, nullptr, ctx->pm,
-                                        nullptr, ctx->st, 0, 1, ctx->stream); },
+                                        nullptr, nullptr, ctx->st, 0, 1, ctx->stream); },
                &ms_out[0]);
     if (rc != COFEM_OK) return rc;
     rc = timed([&] { return dct_mid(xd, xb, ctx->st, 1, ctx->stream); }, &ms_out[1]);
     if (rc != COFEM_OK) return rc;
     rc = timed([&] { return dct_rows_out(xd, xb, ctx->vP, nullptr, ctx->vQs, ctx->pm, nullptr, ctx->Qsm,
-                                         ctx->alpha, ctx->red_pass, ctx->st, 0, 1, ctx->stream); },
+                                         ctx->alpha, nullptr, ctx->red_pass, ctx->st, 0, 1, ctx->stream); },
                &ms_out[2]);
   } else {
     rc = timed([&] { return conv_pass(ctx->cd, ctx->taps, ctx->vP, ctx->pm, ctx->vR, ctx->rm, ctx->alpha,

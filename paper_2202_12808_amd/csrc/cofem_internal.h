@@ -650,29 +650,36 @@ struct DctDims {
 struct DctBuffers {
   float* Wf;             // npairs x D complex float intermediates
   double* Wd;            // D complex double intermediate (mean column)
-  const double* mk;      // mask values beta/D or 0, middle-launch order
+  const uint8_t* mk;     // mask: 1 where the sample is observed, middle-launch order
+  double mval;           // the mask's scale beta/D
   const float* tw1f;     // e^{2 pi i j / N1}, j < N1 (float complex)
   const float* tw2f;     // e^{2 pi i j / N2}
   const double* tw1d;
   const double* tw2d;
-  double* rr;            // per (column, row unit): ||r||^2 of the folded update
+  double* rr;            // per (column, row unit): r^T z, then (second half) r^T r of the folded update
 };
-// Set-up: mask values and the zero-filled scaled data for b0, twiddle tables,
-// then b0 = beta Phi^T y (float64, state order).  rows: device int32 [N].
-hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const float* y, double beta, double* mk,
+// Set-up: mask bytes and the zero-filled scaled data for b0, twiddle tables,
+// then b0 = beta Phi^T y (float64, state order) and, if cn is not null, the
+// squared column norms ||Phi e_k||^2 (state order).  rows: device int32 [N].
+hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const float* y, double beta, uint8_t* mk,
                      double* vb, float* tw1f, float* tw2f, double* tw1d, double* tw2d, const DctBuffers& b,
-                     double* b0, hipStream_t s);
+                     double* b0, double* cn, hipStream_t s);
+// Jacobi preconditioner minv = 1 / (beta cn + alpha), state order.
+hipError_t dct_jacobi(const DctDims& dd, const double* cn, double beta, const float* alpha, float* minv,
+                      hipStream_t s);
 // One CG iteration is dct_rows_in, dct_mid, dct_rows_out.  fused = 0: Q = A P with the pass's
 // dot products (first iteration of a solve); fused = 1: the previous update
 // (x += a p, r -= a q, p = r + b p, in place) folded into the first launch,
 // then Q = A P; apply_only: Q = A P with no reduction and no stop check.
+// minv (null: none) preconditions the folded update: z = M^-1 r, p = z + b p.
 hipError_t dct_rows_in(const DctDims& dd, const DctBuffers& b, void* X, void* R, void* P, const void* Q, double* xm,
-                       double* rm, double* pm, const double* qm, CgScalars* st, int fused, int apply_only,
-                       hipStream_t s);
+                       double* rm, double* pm, const double* qm, const float* minv, CgScalars* st, int fused,
+                       int apply_only, hipStream_t s);
 hipError_t dct_mid(const DctDims& dd, const DctBuffers& b, CgScalars* st, int apply_only, hipStream_t s);
+// minv (null: none) weights the pass's dots r^T M^-1 q and q^T M^-1 q.
 hipError_t dct_rows_out(const DctDims& dd, const DctBuffers& b, const void* P, const void* R, void* Q,
-                        const double* pm, const double* rm, double* qm, const float* alpha, const ConvReduce& red,
-                        CgScalars* st, int fused, int apply_only, hipStream_t s);
+                        const double* pm, const double* rm, double* qm, const float* alpha, const float* minv,
+                        const ConvReduce& red, CgScalars* st, int fused, int apply_only, hipStream_t s);
 
 // ------------------------------------------------------------ batched form
 // Many independent dense problems (bfloat16 dictionaries, plain CG) advanced

@@ -708,7 +708,7 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
 // operator pass: R = B - Q; without one: R = B, X = 0.  Then Z = M^-1 R,
 // P = Z; per column rho = r^T z, ||r||^2 (the stop test's) and ||b||^2.
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, int K, uint64_t seed, int t,
+__global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, int K, int perm, uint64_t seed, int t,
                                                        const double* __restrict__ b0, const float* __restrict__ minv,
                                                        const TP* __restrict__ Qx, const double* __restrict__ qxm,
                                                        TP* __restrict__ X, TP* __restrict__ R, TP* __restrict__ P,
@@ -733,7 +733,7 @@ __global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, i
   } else {
     const int64_t off = (int64_t)col * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const TP b = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)d);
+      const TP b = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)perm_nat(perm, d));
       const TP r = Qx ? b - Qx[off + d] : b;
       const TP z = minv ? (TP)minv[d] * r : r;
       R[off + d] = r;
@@ -766,24 +766,21 @@ hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double*
                          double* pm, const ConvReduce& red, CgScalars* st, hipStream_t s) {
   const dim3 grid(conv_update_blocks(cd), cd.K + 1);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_init_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0, minv,
+    hipLaunchKernelGGL(k_conv_init_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0, minv,
                        static_cast<const double*>(Qx), qxm, static_cast<double*>(X), static_cast<double*>(R),
                        static_cast<double*>(P), xm, rm, pm, red, st);
   else
-    hipLaunchKernelGGL(k_conv_init_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, b0, minv,
+    hipLaunchKernelGGL(k_conv_init_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0, minv,
                        static_cast<const float*>(Qx), qxm, static_cast<float*>(X), static_cast<float*>(R),
                        static_cast<float*>(P), xm, rm, pm, red, st);
   return hipGetLastError();
 }
 
-// x += a p ; r -= a q ; z = M^-1 r ; p <- z + b p ; rho' = r^T z, ||r||^2.
-
-
 // Starting block X0 = [max(d0, 0) (.) p_1 .. max(d0, 0) (.) p_K | mu0] (d0 null:
 // zero probe columns; mu0 null: keep xm as it is, the previous solve's mean
 // column).
 template <typename TP>
-__global__ void k_conv_start(int64_t D, int64_t ldD, int K, uint64_t seed, int t, const float* __restrict__ d0,
+__global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, uint64_t seed, int t, const float* __restrict__ d0,
                              const double* __restrict__ mu0, TP* __restrict__ X, double* __restrict__ xm) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= D * (K + 1)) return;
@@ -792,7 +789,7 @@ __global__ void k_conv_start(int64_t D, int64_t ldD, int K, uint64_t seed, int t
     if (mu0) xm[d] = mu0[d];
   } else {
     const float dv = d0 ? fmaxf(d0[d], 0.0f) : 0.0f;
-    X[k * ldD + d] = (TP)(dv * probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)d));
+    X[k * ldD + d] = (TP)(dv * probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d)));
   }
 }
 
@@ -801,10 +798,10 @@ hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0,
   const int64_t tot = cd.D * (cd.K + 1);
   const dim3 grid((unsigned)((tot + 255) / 256));
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, d0, mu0,
+    hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, d0, mu0,
                        static_cast<double*>(X), xm);
   else
-    hipLaunchKernelGGL(k_conv_start<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, d0, mu0,
+    hipLaunchKernelGGL(k_conv_start<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, d0, mu0,
                        static_cast<float*>(X), xm);
   return hipGetLastError();
 }

@@ -202,15 +202,15 @@ struct SlotCols {
 template <typename T, int NC, int L2>
 __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers& b, const SlotCols<T, NC>& sc,
                                              T* const* Xc, T* const* Rc, T* const* Pc, const T* const* Qc,
-                                             const CgScalars* st, int fused, Cx<T>* Wslot, const Cx<T>* tw2,
-                                             unsigned char* smem, double* rr) {
+                                             const float* __restrict__ minv, const CgScalars* st, int fused,
+                                             Cx<T>* Wslot, const Cx<T>* tw2, unsigned char* smem, double* rz,
+                                             double* rr) {
   const int N1 = 1 << dd.l1;
   const RowUnit ru = row_unit(blockIdx.x, N1);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = w == 0 ? ru.rowA : ru.rowB;
   const bool active = (w == 0) || !ru.single;
-  T* sp = reinterpret_cast<T*>(smem);                                     // [2][NC][L2] real inputs
-  Cx<T>* sz = reinterpret_cast<Cx<T>*>(smem + 2 * NC * L2 * sizeof(T));  // [2][L2] complex rows
+  T* sp = reinterpret_cast<T*>(smem);  // [2][NC][L2] real inputs, then [2][L2] complex rows
   if (active) {
     T a[NC], bb[NC];
     if (fused) {
@@ -222,18 +222,22 @@ __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers
     }
     for (int e = lane; e < L2; e += 64) {
       const int64_t pos = (int64_t)row * L2 + e;
+      const T mi = (fused && minv) ? (T)minv[pos] : T(1);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         T p = T(0);
         if (sc.valid[c]) {
           if (fused) {
-            // the previous CG update, folded in: x += a p, r -= a q, p = r + b p
+            // the previous CG update, folded in: x += a p, r -= a q,
+            // z = M^-1 r, p = z + b p
             const T p0 = Pc[c][pos], r0 = Rc[c][pos], q0 = Qc[c][pos], x0 = Xc[c][pos];
             const T r1 = r0 - a[c] * q0;
-            p = r1 + bb[c] * p0;
+            const T z = mi * r1;
+            p = z + bb[c] * p0;
             Xc[c][pos] = x0 + a[c] * p0;
             Rc[c][pos] = r1;
             Pc[c][pos] = p;
+            rz[c] += (double)r1 * (double)z;
             rr[c] += (double)r1 * (double)r1;
           } else {
             p = Pc[c][pos];
@@ -244,31 +248,40 @@ __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers
     }
   }
   __syncthreads();
-  if (!active) return;
   const int64_t D = dd.D;
   const T half_over_d = T(0.5) / (T)D, two_over_d = T(2) / (T)D;
   const T rt2 = (T)1.41421356237309504880;
-  Cx<T>* zr = sz + w * L2;
-  for (int e = lane; e < L2; e += 64) {
-    const int64_t k = row + ((int64_t)e << dd.l1);
-    T u = sp[(w * NC + 0) * L2 + e], um = T(0);
-    T v = T(0), vm = T(0);
-    if (NC == 2) v = sp[(w * NC + 1) * L2 + e];
-    if (k == 0) {
-      u *= rt2;
-      v *= rt2;
-    } else {
-      const int mrow = (N1 - row) & (N1 - 1);
-      const int mw = (mrow == ru.rowA) ? 0 : 1;
-      const int me = mirror_col(row, e, L2);
-      um = sp[(mw * NC + 0) * L2 + me];
-      if (NC == 2) vm = sp[(mw * NC + 1) * L2 + me];
+  constexpr int PE = L2 / 64;  // elements per lane
+  Cx<T> z[PE];
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+      const int e = lane + 64 * i;
+      const int64_t k = row + ((int64_t)e << dd.l1);
+      T u = sp[(w * NC + 0) * L2 + e], um = T(0);
+      T v = T(0), vm = T(0);
+      if (NC == 2) v = sp[(w * NC + 1) * L2 + e];
+      if (k == 0) {
+        u *= rt2;
+        v *= rt2;
+      } else {
+        const int mrow = (N1 - row) & (N1 - 1);
+        const int mw = (mrow == ru.rowA) ? 0 : 1;
+        const int me = mirror_col(row, e, L2);
+        um = sp[(mw * NC + 0) * L2 + me];
+        if (NC == 2) vm = sp[(mw * NC + 1) * L2 + me];
+      }
+      T s, c;
+      sin_cos_pi((T)k * half_over_d, &s, &c);
+      z[i] = cmul(Cx<T>{c, s}, Cx<T>{u + vm, v - um});
     }
-    T s, c;
-    sin_cos_pi((T)k * half_over_d, &s, &c);
-    const Cx<T> g{u + vm, v - um};
-    zr[e] = cmul(Cx<T>{c, s}, g);
   }
+  // every wave has read the real inputs: the complex rows take their place
+  __syncthreads();
+  if (!active) return;
+  Cx<T>* zr = reinterpret_cast<Cx<T>*>(smem) + w * L2;
+#pragma unroll
+  for (int i = 0; i < PE; ++i) zr[lane + 64 * i] = z[i];
   fft_stages<T, L2, 1, +1>(zr, tw2, lane);
   for (int e = lane; e < L2; e += 64) {
     const int64_t m = ((int64_t)e * row) & (D - 1);
@@ -279,10 +292,12 @@ __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers
 template <int L2>
 __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, float* X, float* R, float* P,
                                                      const float* Q, double* xm, double* rm, double* pm,
-                                                     const double* qm, CgScalars* st, int fused, int apply_only) {
+                                                     const double* qm, const float* minv, CgScalars* st, int fused,
+                                                     int apply_only) {
   if (!apply_only && st->stop) return;
-  constexpr size_t kF = 2 * 2 * L2 * sizeof(float) + 2 * L2 * sizeof(Cx<float>);
-  constexpr size_t kD = 2 * 1 * L2 * sizeof(double) + 2 * L2 * sizeof(Cx<double>);
+  // the real inputs, then (in the same place) the complex rows
+  constexpr size_t kF = 2 * L2 * sizeof(Cx<float>);  // = 2 * 2 * L2 * sizeof(float)
+  constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);  // > 2 * 1 * L2 * sizeof(double)
   __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
   __shared__ double shm[8];
   const int slot = blockIdx.y;
@@ -301,13 +316,18 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
       Pc[c] = P + off;
       Qc[c] = Q + off;
     }
-    double rr[2] = {0.0, 0.0};
-    rows_in_body<float, 2, L2>(dd, b, sc, Xc, Rc, Pc, Qc, st, fused, reinterpret_cast<Cx<float>*>(b.Wf) + slot * ld,
-                               as_cx(b.tw2f), smem, rr);
+    double rz[2] = {0.0, 0.0}, rr[2] = {0.0, 0.0};
+    rows_in_body<float, 2, L2>(dd, b, sc, Xc, Rc, Pc, Qc, minv, st, fused,
+                               reinterpret_cast<Cx<float>*>(b.Wf) + slot * ld, as_cx(b.tw2f), smem, rz, rr);
     if (do_rr) {
+      const int64_t half = (int64_t)(dd.K + 1) * dd.units;
       for (int c = 0; c < 2; ++c) {
-        const double t = block_sum(rr[c], shm);
-        if (threadIdx.x == 0 && sc.valid[c]) b.rr[(int64_t)sc.col[c] * dd.units + blockIdx.x] = t;
+        const double tz = block_sum(rz[c], shm);
+        const double tr = block_sum(rr[c], shm);
+        if (threadIdx.x == 0 && sc.valid[c]) {
+          b.rr[(int64_t)sc.col[c] * dd.units + blockIdx.x] = tz;
+          b.rr[half + (int64_t)sc.col[c] * dd.units + blockIdx.x] = tr;
+        }
       }
     }
   } else {
@@ -318,12 +338,17 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
     double* Rc[1] = {rm};
     double* Pc[1] = {pm};
     const double* Qc[1] = {qm};
-    double rr[1] = {0.0};
-    rows_in_body<double, 1, L2>(dd, b, sc, Xc, Rc, Pc, Qc, st, fused, reinterpret_cast<Cx<double>*>(b.Wd),
-                                as_cx(b.tw2d), smem, rr);
+    double rz[1] = {0.0}, rr[1] = {0.0};
+    rows_in_body<double, 1, L2>(dd, b, sc, Xc, Rc, Pc, Qc, minv, st, fused, reinterpret_cast<Cx<double>*>(b.Wd),
+                                as_cx(b.tw2d), smem, rz, rr);
     if (do_rr) {
-      const double t = block_sum(rr[0], shm);
-      if (threadIdx.x == 0) b.rr[(int64_t)dd.K * dd.units + blockIdx.x] = t;
+      const int64_t half = (int64_t)(dd.K + 1) * dd.units;
+      const double tz = block_sum(rz[0], shm);
+      const double tr = block_sum(rr[0], shm);
+      if (threadIdx.x == 0) {
+        b.rr[(int64_t)dd.K * dd.units + blockIdx.x] = tz;
+        b.rr[half + (int64_t)dd.K * dd.units + blockIdx.x] = tr;
+      }
     }
   }
 }
@@ -335,7 +360,7 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
 // e^{-2 pi i n2 k1 / D}; written back in place.  b0 mode: the tile starts
 // from the real vector vb (middle-launch order) and runs the forward half only.
 template <typename T, int G, int L1>
-__device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const double* __restrict__ mk,
+__device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const uint8_t* __restrict__ mk, double mval,
                                          const double* __restrict__ vb, const Cx<T>* tw1, int tile,
                                          unsigned char* smem) {
   constexpr int LP = L1 + 1;  // padded group stride
@@ -343,7 +368,9 @@ __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const doub
   const int64_t D = dd.D;
   const int g0 = tile * G;
   const T two_over_d = T(2) / (T)D;
+  const T mv = (T)mval;
   Cx<T>* s = reinterpret_cast<Cx<T>*>(smem);
+  uint8_t* sm = smem + (size_t)G * LP * sizeof(Cx<T>);  // the tile's mask bytes, group-major
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   if (vb) {
     for (int e = tid; e < G * L1; e += blockDim.x) {
@@ -355,6 +382,9 @@ __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const doub
       const int j = e % G, k1 = e / G;
       s[j * LP + k1] = W[(int64_t)k1 * N2 + g0 + j];
     }
+    // the groups' mask bytes are contiguous: G * L1 bytes from group g0
+    const uint32_t* m4 = reinterpret_cast<const uint32_t*>(mk + (int64_t)g0 * L1);
+    for (int e = tid; e < G * L1 / 4; e += blockDim.x) reinterpret_cast<uint32_t*>(sm)[e] = m4[e];
   }
   __syncthreads();
   for (int j = w; j < G; j += (int)(blockDim.x >> 6)) {
@@ -363,7 +393,7 @@ __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const doub
     if (!vb) {
       fft_stages<T, L1, 1, +1>(buf, tw1, lane);
       for (int n1 = lane; n1 < L1; n1 += 64) {
-        const T m = (T)mk[(int64_t)n2 * L1 + n1];
+        const T m = sm[j * L1 + n1] ? mv : T(0);
         buf[n1] = Cx<T>{buf[n1].x * m, buf[n1].y * m};
       }
     }
@@ -384,8 +414,8 @@ template <int L1>
 struct MidGeom {
   static constexpr int GF = (8192 / L1) < 16 ? (8192 / L1) : 16;
   static constexpr int GD = (4096 / L1) < 8 ? (4096 / L1) : 8;
-  static constexpr size_t LDS_F = (size_t)GF * (L1 + 1) * sizeof(Cx<float>);
-  static constexpr size_t LDS_D = (size_t)GD * (L1 + 1) * sizeof(Cx<double>);
+  static constexpr size_t LDS_F = (size_t)GF * (L1 + 1) * sizeof(Cx<float>) + (size_t)GF * L1;
+  static constexpr size_t LDS_D = (size_t)GD * (L1 + 1) * sizeof(Cx<double>) + (size_t)GD * L1;
   static constexpr size_t LDS = LDS_F > LDS_D ? LDS_F : LDS_D;
 };
 
@@ -400,38 +430,59 @@ __global__ __launch_bounds__(256) void k_dct_mid(DctDims dd, DctBuffers b, const
   const int blk = blockIdx.x;
   if (blk < ftiles) {
     const int slot = blk / (N2 / G::GF), tile = blk - slot * (N2 / G::GF);
-    mid_body<float, G::GF, L1>(dd, reinterpret_cast<Cx<float>*>(b.Wf) + (int64_t)slot * dd.D, b.mk, nullptr,
-                               as_cx(b.tw1f), tile, smem);
+    mid_body<float, G::GF, L1>(dd, reinterpret_cast<Cx<float>*>(b.Wf) + (int64_t)slot * dd.D, b.mk, b.mval,
+                               nullptr, as_cx(b.tw1f), tile, smem);
   } else {
-    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd), b.mk, vb, as_cx(b.tw1d), blk - ftiles,
-                                smem);
+    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd), b.mk, b.mval, vb, as_cx(b.tw1d),
+                                blk - ftiles, smem);
   }
 }
 
 // ---------------------------------------------------------------- launch 3
 // Forward row transforms, then per coefficient the operator's output, q = out
-// + alpha p (or b0), and the dot products of the pass.
+// + alpha p (or b0), and the dot products of the pass.  The state the output
+// needs (p, r, alpha) is loaded before the transform, so its latency overlaps
+// the transform's.
 template <typename T, int NC, int L2>
 __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Wslot, const Cx<T>* tw2,
                                               const SlotCols<T, NC>& sc, const T* const* Pc, const T* const* Rc,
-                                              T* const* Qc, const float* __restrict__ alpha, double* b0,
-                                              bool dots, unsigned char* smem, double (*acc)[3]) {
+                                              T* const* Qc, const float* __restrict__ alpha,
+                                              const float* __restrict__ minv, double* b0, bool dots,
+                                              unsigned char* smem, double* acc /* [NC * 3] */) {
   const int N1 = 1 << dd.l1;
   const RowUnit ru = row_unit(blockIdx.x, N1);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = w == 0 ? ru.rowA : ru.rowB;
   const bool active = (w == 0) || !ru.single;
+  constexpr int PE = L2 / 64;
   Cx<T>* sz = reinterpret_cast<Cx<T>*>(smem);  // [2][L2]
   Cx<T>* zr = sz + w * L2;
+  T pv[NC][PE], rv[NC][PE], al[PE], mv[PE];
   if (active) {
-    for (int e = lane; e < L2; e += 64) zr[e] = Wslot[(int64_t)row * L2 + e];
+#pragma unroll
+    for (int i = 0; i < PE; ++i) zr[lane + 64 * i] = Wslot[(int64_t)row * L2 + lane + 64 * i];
+    if (!b0) {
+#pragma unroll
+      for (int i = 0; i < PE; ++i) {
+        const int64_t pos = (int64_t)row * L2 + lane + 64 * i;
+        al[i] = (T)alpha[pos];
+        mv[i] = (dots && minv) ? (T)minv[pos] : T(1);
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          pv[cc][i] = sc.valid[cc] ? Pc[cc][pos] : T(0);
+          rv[cc][i] = (sc.valid[cc] && dots) ? Rc[cc][pos] : T(0);
+        }
+      }
+    }
     fft_stages<T, L2, 1, -1>(zr, tw2, lane);
   }
   __syncthreads();
   if (!active) return;
   const T half_over_d = T(0.5) / (T)dd.D;
   const T rh = (T)0.70710678118654752440;
-  for (int e = lane; e < L2; e += 64) {
+#pragma unroll
+  for (int i = 0; i < PE; ++i) {
+    const int e = lane + 64 * i;
     const int64_t k = row + ((int64_t)e << dd.l1);
     const Cx<T> z = zr[e];
     Cx<T> zm = z;
@@ -454,28 +505,74 @@ __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Ws
       b0[pos] = (double)out[0];
       continue;
     }
-    const T al = (T)alpha[pos];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
       if (!sc.valid[cc]) continue;
-      const T p = Pc[cc][pos];
-      const T q = out[cc] + al * p;
+      const T p = pv[cc][i];
+      const T q = out[cc] + al[i] * p;
       Qc[cc][pos] = q;
       if (dots) {
-        const T r = Rc[cc][pos];
-        acc[cc][0] += (double)p * (double)q;
-        acc[cc][1] += (double)r * (double)q;
-        acc[cc][2] += (double)q * (double)q;
+        // with a diagonal preconditioner the step's dots are weighted by it:
+        // delta = r^T M^-1 q, eta = q^T M^-1 q (mv = 1 without one)
+        const double mq = (double)mv[i] * (double)q;
+        acc[cc * 3 + 0] += (double)p * (double)q;
+        acc[cc * 3 + 1] += (double)rv[cc][i] * mq;
+        acc[cc * 3 + 2] += (double)q * mq;
       }
     }
   }
 }
 
+// Block sums of N values at once (one exchange through LDS), left in out[].
+template <int N>
+__device__ __forceinline__ void block_sums(double* v, double (*sh)[N], double* out) {
+#pragma unroll
+  for (int n = 0; n < N; ++n)
+    for (int off = 32; off > 0; off >>= 1) v[n] += __shfl_xor(v[n], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int n = 0; n < N; ++n) sh[wave][n] = v[n];
+  __syncthreads();
+  if ((int)threadIdx.x < N) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// Reduction over the blocks of one column slot: one tree per slot carries all
+// of the slot's columns (nv values each; regions of tree_rows(units) * 2 nv
+// doubles); the block finishing a slot stores its columns' totals in colsum and
+// takes a ticket on cnt_cols; the last of those returns true with every total
+// in out_sh[v * ncols + col].
+__device__ __forceinline__ bool slot_tree_reduce(const ConvReduce& red, int slot, int nslots, int units,
+                                                 const int* cols, const bool* valid, int nc_slot, int ncols, int nv,
+                                                 const double* mine, double* out_sh) {
+  __shared__ double tslot[10];
+  double* p = red.parts + (int64_t)slot * tree_rows(units) * (2 * nv);
+  uint32_t* c = red.cnts + (int64_t)slot * tree_counters(units) * kCounterStride;
+  if (!tree_reduce(p, c, blockIdx.x, units, nc_slot * nv, mine, tslot)) return false;
+  if ((int)threadIdx.x < nc_slot * nv) {
+    const int cc = threadIdx.x / nv, v = threadIdx.x - (threadIdx.x / nv) * nv;
+    if (valid[cc]) store_agent(&red.colsum[cols[cc] * nv + v], tslot[threadIdx.x]);
+  }
+  if (!last_block_ticket(red.cnt_cols, (uint32_t)nslots)) return false;
+  for (int e = threadIdx.x; e < ncols * nv; e += blockDim.x) {
+    const int cc = e / nv, v = e - (e / nv) * nv;
+    out_sh[v * ncols + cc] = load_agent(&red.colsum[e]);
+  }
+  if (threadIdx.x == 0) store_agent(red.cnt_cols, 0u);
+  __syncthreads();
+  return true;
+}
+
 template <int L2>
 __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, const float* P, const float* R,
                                                       float* Q, const double* pm, const double* rm, double* qm,
-                                                      const float* alpha, double* b0, ConvReduce red,
-                                                      CgScalars* st, int fused, int apply_only) {
+                                                      const float* alpha, const float* minv, double* b0,
+                                                      ConvReduce red, CgScalars* st, int fused, int apply_only) {
   if (!apply_only && st->stop) return;
   const CgCtl ctl = apply_only ? CgCtl{} : load_cg_ctl(st);
   constexpr size_t kF = 2 * L2 * sizeof(Cx<float>);
@@ -484,10 +581,12 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
   const int slot = b0 ? dd.npairs : blockIdx.y;
   const int64_t ld = dd.D;
   const bool dots = !apply_only;
-  double acc[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int cols[2] = {0, 0};
   bool valid[2] = {false, false};
+  int nc_slot = 1;
   if (slot < dd.npairs) {
+    nc_slot = 2;
     SlotCols<float, 2> sc;
     const float *Pc[2], *Rc[2];
     float* Qc[2];
@@ -502,7 +601,7 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
       Qc[c] = Q + off;
     }
     rows_out_body<float, 2, L2>(dd, reinterpret_cast<const Cx<float>*>(b.Wf) + slot * ld, as_cx(b.tw2f), sc, Pc,
-                                Rc, Qc, alpha, nullptr, dots, smem, acc);
+                                Rc, Qc, alpha, minv, nullptr, dots, smem, acc);
   } else {
     SlotCols<double, 1> sc;
     sc.col[0] = dd.K;
@@ -513,40 +612,32 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
     const double* Rc[1] = {rm};
     double* Qc[1] = {qm};
     rows_out_body<double, 1, L2>(dd, reinterpret_cast<const Cx<double>*>(b.Wd), as_cx(b.tw2d), sc, Pc, Rc, Qc,
-                                 alpha, b0, dots, smem, acc);
+                                 alpha, minv, b0, dots, smem, acc);
   }
   if (!dots) return;
-  __shared__ double shm[8];
-  __shared__ double mine[2][5], tot[5 * kMaxCols];
+  __shared__ double sh[2][6], sums[6];
+  __shared__ double mine[10], tot[5 * kMaxCols];
+  block_sums<6>(acc, sh, sums);
   const int nv = fused ? 5 : 3;
-  for (int c = 0; c < 2; ++c) {
-    const double g = block_sum(acc[c][0], shm);
-    const double dl = block_sum(acc[c][1], shm);
-    const double et = block_sum(acc[c][2], shm);
-    if (threadIdx.x == 0) {
-      if (fused) {
-        const double r2 = valid[c] ? b.rr[(int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
-        mine[c][0] = r2;  // r^T z = r^T r (no preconditioner)
-        mine[c][1] = r2;
-        mine[c][2] = g;
-        mine[c][3] = dl;
-        mine[c][4] = et;
-      } else {
-        mine[c][0] = g;
-        mine[c][1] = dl;
-        mine[c][2] = et;
-      }
+  if (threadIdx.x < 2) {
+    const int c = threadIdx.x;
+    double* m = mine + c * nv;
+    if (fused) {
+      // the folded update's r^T z and r^T r, from the first launch
+      const int64_t half = (int64_t)(dd.K + 1) * dd.units;
+      m[0] = valid[c] ? b.rr[(int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
+      m[1] = valid[c] ? b.rr[half + (int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
+      m[2] = sums[c * 3 + 0];
+      m[3] = sums[c * 3 + 1];
+      m[4] = sums[c * 3 + 2];
+    } else {
+      m[0] = sums[c * 3 + 0];
+      m[1] = sums[c * 3 + 1];
+      m[2] = sums[c * 3 + 2];
     }
   }
   __syncthreads();
-  bool last = false;
-  for (int c = 0; c < 2; ++c) {
-    if (!valid[c]) continue;
-    if (column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, dd.units, dd.units,
-                           cols[c], dd.K + 1, nv, mine[c], tot))
-      last = true;
-  }
-  if (!last) return;
+  if (!slot_tree_reduce(red, slot, dd.npairs + 1, dd.units, cols, valid, nc_slot, dd.K + 1, nv, mine, tot)) return;
   if (fused)
     finish_fused(st, tot, dd.K + 1, ctl);
   else
@@ -577,9 +668,9 @@ __global__ void k_dct_tables(int N1, int N2, float* tw1f, float* tw2f, double* t
 
 // Observed sample j sits at FFT index n = j/2 (j even) or D-1-(j-1)/2 (odd),
 // n = n2 + N2 n1, which the middle launch reads at n2 N1 + n1: there the mask
-// value beta/D and the data term beta sqrt(2/D) y_i.
+// byte 1 (the launch scales by beta/D) and the data term beta sqrt(2/D) y_i.
 __global__ void k_dct_scatter(int64_t D, int l1, int l2, const int32_t* __restrict__ rows, int64_t N,
-                              const float* __restrict__ y, double mval, double yscale, double* __restrict__ mk,
+                              const float* __restrict__ y, double yscale, uint8_t* __restrict__ mk,
                               double* __restrict__ vb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -587,8 +678,34 @@ __global__ void k_dct_scatter(int64_t D, int l1, int l2, const int32_t* __restri
   const int64_t n = (j & 1) == 0 ? j / 2 : D - 1 - (j - 1) / 2;
   const int64_t n2 = n & ((int64_t(1) << l2) - 1), n1 = n >> l2;
   const int64_t idx = (n2 << l1) + n1;
-  mk[idx] = mval;
+  mk[idx] = 1;
   vb[idx] = yscale * (double)y[i];
+}
+
+// ||Phi e_k||^2 = c_k^2 sum over observed samples n of cos^2(pi (2n+1) k / 2D)
+//               = c_k^2 (N + sum_n cos(pi (2n+1) k / D)) / 2,
+// one coefficient per thread (state order), the cosines of exact arguments
+// ((2n+1) k mod 2D) / D in float, summed in float64.
+__global__ void k_dct_colnorm(int64_t D, int l1, int l2, const int32_t* __restrict__ rows, int64_t N,
+                              double* __restrict__ cn) {
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= D) return;
+  const int64_t k = perm_nat(l1 | (l2 << 8), pos);
+  const float inv_d = 1.0f / (float)D;
+  double acc = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t m = ((2 * (int64_t)rows[i] + 1) * k) & (2 * D - 1);
+    acc += (double)cospif((float)m * inv_d);
+  }
+  const double ck2 = (k == 0 ? 1.0 : 2.0) / (double)D;
+  cn[pos] = 0.5 * ck2 * ((double)N + acc);
+}
+
+// Jacobi: minv = 1 / (beta ||Phi e_k||^2 + alpha_k)
+__global__ void k_dct_jacobi(int64_t D, const double* __restrict__ cn, double beta, const float* __restrict__ alpha,
+                             float* __restrict__ minv) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d < D) minv[d] = (float)(1.0 / (beta * cn[d] + (double)alpha[d]));
 }
 
 }  // namespace
@@ -615,12 +732,12 @@ __global__ void k_dct_scatter(int64_t D, int l1, int l2, const int32_t* __restri
   }
 
 hipError_t dct_rows_in(const DctDims& dd, const DctBuffers& b, void* X, void* R, void* P, const void* Q, double* xm,
-                       double* rm, double* pm, const double* qm, CgScalars* st, int fused, int apply_only,
-                       hipStream_t s) {
+                       double* rm, double* pm, const double* qm, const float* minv, CgScalars* st, int fused,
+                       int apply_only, hipStream_t s) {
   const dim3 grid((unsigned)dd.units, (unsigned)(dd.npairs + 1));
 #define COFEM_ROWS_IN(L)                                                                                         \
   hipLaunchKernelGGL(k_dct_rows_in<L>, grid, dim3(128), 0, s, dd, b, static_cast<float*>(X), static_cast<float*>(R), \
-                     static_cast<float*>(P), static_cast<const float*>(Q), xm, rm, pm, qm, st, fused, apply_only)
+                     static_cast<float*>(P), static_cast<const float*>(Q), xm, rm, pm, qm, minv, st, fused, apply_only)
   COFEM_DCT_SWITCH(1 << dd.l2, COFEM_ROWS_IN)
 #undef COFEM_ROWS_IN
   return hipGetLastError();
@@ -644,39 +761,52 @@ hipError_t dct_mid(const DctDims& dd, const DctBuffers& b, CgScalars* st, int ap
 }
 
 static hipError_t launch_rows_out(const DctDims& dd, const DctBuffers& b, const void* P, const void* R, void* Q,
-                                  const double* pm, const double* rm, double* qm, const float* alpha, double* b0,
-                                  const ConvReduce& red, CgScalars* st, int fused, int apply_only, hipStream_t s) {
+                                  const double* pm, const double* rm, double* qm, const float* alpha,
+                                  const float* minv, double* b0, const ConvReduce& red, CgScalars* st, int fused,
+                                  int apply_only, hipStream_t s) {
   const dim3 grid((unsigned)dd.units, b0 ? 1u : (unsigned)(dd.npairs + 1));
 #define COFEM_ROWS_OUT(L)                                                                                     \
   hipLaunchKernelGGL(k_dct_rows_out<L>, grid, dim3(128), 0, s, dd, b, static_cast<const float*>(P),             \
-                     static_cast<const float*>(R), static_cast<float*>(Q), pm, rm, qm, alpha, b0, red, st, fused, \
-                     apply_only)
+                     static_cast<const float*>(R), static_cast<float*>(Q), pm, rm, qm, alpha, minv, b0, red, st,   \
+                     fused, apply_only)
   COFEM_DCT_SWITCH(1 << dd.l2, COFEM_ROWS_OUT)
 #undef COFEM_ROWS_OUT
   return hipGetLastError();
 }
 
 hipError_t dct_rows_out(const DctDims& dd, const DctBuffers& b, const void* P, const void* R, void* Q,
-                        const double* pm, const double* rm, double* qm, const float* alpha, const ConvReduce& red,
-                        CgScalars* st, int fused, int apply_only, hipStream_t s) {
-  return launch_rows_out(dd, b, P, R, Q, pm, rm, qm, alpha, nullptr, red, st, fused, apply_only, s);
+                        const double* pm, const double* rm, double* qm, const float* alpha, const float* minv,
+                        const ConvReduce& red, CgScalars* st, int fused, int apply_only, hipStream_t s) {
+  return launch_rows_out(dd, b, P, R, Q, pm, rm, qm, alpha, minv, nullptr, red, st, fused, apply_only, s);
 }
 
-hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const float* y, double beta, double* mk,
+hipError_t dct_jacobi(const DctDims& dd, const double* cn, double beta, const float* alpha, float* minv,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_dct_jacobi, dim3((unsigned)((dd.D + 255) / 256)), dim3(256), 0, s, dd.D, cn, beta, alpha, minv);
+  return hipGetLastError();
+}
+
+hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const float* y, double beta, uint8_t* mk,
                      double* vb, float* tw1f, float* tw2f, double* tw1d, double* tw2d, const DctBuffers& b,
-                     double* b0, hipStream_t s) {
+                     double* b0, double* cn, hipStream_t s) {
   const int N1 = 1 << dd.l1, N2 = 1 << dd.l2;
   const int nt = N1 > N2 ? N1 : N2;
   hipLaunchKernelGGL(k_dct_tables, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, N1, N2, tw1f, tw2f, tw1d,
                      tw2d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = hipMemsetAsync(mk, 0, sizeof(double) * (size_t)dd.D, s);
+  e = hipMemsetAsync(mk, 0, (size_t)dd.D, s);
   if (e == hipSuccess) e = hipMemsetAsync(vb, 0, sizeof(double) * (size_t)dd.D, s);
   if (e != hipSuccess) return e;
   if (N > 0) {
     hipLaunchKernelGGL(k_dct_scatter, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, dd.D, dd.l1, dd.l2, rows,
-                       N, y, beta / (double)dd.D, beta * sqrt(2.0 / (double)dd.D), mk, vb);
+                       N, y, beta * sqrt(2.0 / (double)dd.D), mk, vb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (cn) {
+    hipLaunchKernelGGL(k_dct_colnorm, dim3((unsigned)((dd.D + 255) / 256)), dim3(256), 0, s, dd.D, dd.l1, dd.l2, rows,
+                       N, cn);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -685,8 +815,8 @@ hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const fl
   e = launch_mid(dd, b, vb, nullptr, 1, s);
   if (e != hipSuccess) return e;
   const ConvReduce none{};
-  return launch_rows_out(dd, b, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, b0, none, nullptr, 0,
-                         1, s);
+  return launch_rows_out(dd, b, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, b0, none,
+                         nullptr, 0, 1, s);
 }
 
 }  // namespace cofem

@@ -189,3 +189,63 @@ def test_dct_rejects_bad_problems(torch_dev, D, rows, code):
     with pytest.raises(C.CofemError) as ei:
         C.CoFEM.dct(r, y, D, 10.0, 4)
     assert getattr(C, "COFEM_ERR_" + code) == ei.value.status
+
+
+@pytest.mark.parametrize("mode", ["jacobi", "warm", "both"])
+def test_dct_pcg_step_parity(torch_dev, mode):
+    # the warm-started / Jacobi-preconditioned solve against the oracle's PCG
+    # from the same start (the GPU's previous mean and clamped diagonal
+    # estimate) with M^-1 = 1/(beta ||Phi e_k||^2 + alpha_k) rounded to float32.
+    # A warm start's first residual B - A X0 cancels most of B, so the float32
+    # operator's rounding (relative u32 log2 D per output) is amplified in it:
+    # the bar is 1e-4 or 5x the spread of oracle runs whose operator outputs
+    # carry noise of that size, whichever is larger.
+    from tests.test_gpu_parity import _RoundingNoiseOp
+    torch = torch_dev
+    p = synth.dct_problem(8192, rho=0.05, beta=4e4, K=10, tol=1e-5, seed=6, name="dct_8192")
+    op = _op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    kw = {"jacobi": mode in ("jacobi", "both"), "warm_start": mode in ("warm", "both")}
+    with _ctx(torch, p, **kw) as g:
+        g.em_step(4)
+        _, s_prev, alpha = [x.cpu().numpy() for x in g.posterior()]
+        _, mu_prev = g.solution()
+        mu_prev = mu_prev.cpu().numpy()
+        st = g.em_step(1)[0]
+        mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    minv = (1.0 / (p.beta * op.column_norms_sq() + alpha.astype(np.float64))).astype(np.float32).astype(np.float64)
+
+    def run(o):
+        e = O.cofem_estep_pcg(o, b0, p.beta, alpha.astype(np.float64), p.K, p.tol, p.max_iter, p.seed, st["t"],
+                              minv=minv if kw["jacobi"] else None,
+                              mu0=mu_prev if kw["warm_start"] else None,
+                              d0=np.maximum(s_prev.astype(np.float64), 0.0) if kw["warm_start"] else None,
+                              fixed_iters=st["cg_iters"])
+        return e.mu, e.s, 1.0 / O.mstep(e.mu, e.s)[0]
+
+    ref = run(op)
+    spread = np.zeros(3)
+    for sd in (1, 2):
+        noisy = run(_RoundingNoiseOp(op, sd, rel=2.0 ** -24 * np.log2(p.D)))
+        spread = np.maximum(spread, [relerr(a, b) for a, b in zip(noisy, ref)])
+    errs = [relerr(a, b) for a, b in zip((mu, s, 1.0 / a_new), ref)]
+    _say("dct pcg", mode, "t", st["t"], "cg", st["cg_iters"], "relerr", errs, "float32-noise spread", spread)
+    assert st["converged"] == 1 or st["cg_iters"] == p.max_iter
+    for err, sp in zip(errs, spread):
+        assert err < max(STEP_TOL, 5.0 * sp), (errs, spread)
+
+
+def test_dct_warm_jacobi_reaches_the_tolerance_in_fewer_iterations(torch_dev):
+    # the high-dimensional workload: plain CG against the warm-started
+    # Jacobi-preconditioned form over the same EM iterations
+    torch = torch_dev
+    p = synth.dct_262144(0)
+    counts = {}
+    for name, kw in (("plain", {}), ("warm+jacobi", {"jacobi": True, "warm_start": True})):
+        with _ctx(torch, p, **kw) as g:
+            st = g.em_step(12)
+        counts[name] = [x["cg_iters"] for x in st]
+        assert all(x["converged"] == 1 for x in st[:6]), (name, counts[name])
+    _say("dct_262144 cg counts", counts)
+    assert sum(counts["warm+jacobi"]) < 0.6 * sum(counts["plain"])
+    assert all(c < p.max_iter for c in counts["warm+jacobi"])
