@@ -56,21 +56,26 @@ __device__ __forceinline__ Cx<T> rot90(Cx<T> a) {
 __device__ __forceinline__ void sin_cos_pi(float x, float* s, float* c) { sincospif(x, s, c); }
 __device__ __forceinline__ void sin_cos_pi(double x, double* s, double* c) { sincospi(x, s, c); }
 
-// e^{SIGN 2 pi i m / D}, m < D; two_over_d = 2/D (D a power of two, so the
-// argument m (2/D) is exact)
-template <int SIGN, typename T>
-__device__ __forceinline__ Cx<T> unit_root(int64_t m, T two_over_d) {
-  T s, c;
-  sin_cos_pi((T)m * two_over_d, &s, &c);
-  return {c, SIGN > 0 ? s : -s};
-}
-
 // Lanes of one wavefront exchange data through LDS between the phases of a
 // transform.  The hardware completes a wavefront's LDS operations in order,
 // but the compiler reasons per lane and may forward a lane's own earlier store
 // or move accesses across a phase; this fence (no instruction at wavefront
 // scope) keeps every LDS access on its side.
 __device__ __forceinline__ void lds_wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
+// e^{i pi (x0 + j dx)} for j = 0, 1, ...: one sincospi for the start and one for
+// the step, then a complex multiplication per element (a lane walks its
+// elements lane + 64 j of a transform; the recurrence adds about one rounding
+// per step, far below the transform's own rounding).
+template <typename T>
+struct RootWalk {
+  Cx<T> w, step;
+  __device__ __forceinline__ RootWalk(T x0, T dx) {
+    sin_cos_pi(x0, &w.y, &w.x);
+    sin_cos_pi(dx, &step.y, &step.x);
+  }
+  __device__ __forceinline__ void next() { w = cmul(w, step); }
+};
 
 // ---- small DFTs in registers (sign SIGN of the exponent)
 template <int SIGN, typename T>
@@ -254,6 +259,8 @@ __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers
   constexpr int PE = L2 / 64;  // elements per lane
   Cx<T> z[PE];
   if (active) {
+    // e^{i pi k / 2D} for k = row + N1 (lane + 64 i)
+    RootWalk<T> th((T)(row + ((int64_t)lane << dd.l1)) * half_over_d, (T)((int64_t)64 << dd.l1) * half_over_d);
 #pragma unroll
     for (int i = 0; i < PE; ++i) {
       const int e = lane + 64 * i;
@@ -271,9 +278,8 @@ __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers
         um = sp[(mw * NC + 0) * L2 + me];
         if (NC == 2) vm = sp[(mw * NC + 1) * L2 + me];
       }
-      T s, c;
-      sin_cos_pi((T)k * half_over_d, &s, &c);
-      z[i] = cmul(Cx<T>{c, s}, Cx<T>{u + vm, v - um});
+      z[i] = cmul(th.w, Cx<T>{u + vm, v - um});
+      th.next();
     }
   }
   // every wave has read the real inputs: the complex rows take their place
@@ -283,9 +289,13 @@ __device__ __forceinline__ void rows_in_body(const DctDims& dd, const DctBuffers
 #pragma unroll
   for (int i = 0; i < PE; ++i) zr[lane + 64 * i] = z[i];
   fft_stages<T, L2, 1, +1>(zr, tw2, lane);
-  for (int e = lane; e < L2; e += 64) {
-    const int64_t m = ((int64_t)e * row) & (D - 1);
-    Wslot[(int64_t)row * L2 + e] = cmul(zr[e], unit_root<+1, T>(m, two_over_d));
+  // e^{2 pi i n2 k1 / D} for n2 = lane + 64 i, k1 = row
+  RootWalk<T> tw((T)(((int64_t)lane * row) & (D - 1)) * two_over_d, (T)(((int64_t)64 * row) & (D - 1)) * two_over_d);
+#pragma unroll
+  for (int i = 0; i < PE; ++i) {
+    const int e = lane + 64 * i;
+    Wslot[(int64_t)row * L2 + e] = cmul(zr[e], tw.w);
+    tw.next();
   }
 }
 
@@ -300,7 +310,9 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
   constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);  // > 2 * 1 * L2 * sizeof(double)
   __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
   __shared__ double shm[8];
-  const int slot = blockIdx.y;
+  // the float64 mean column's blocks (the slowest) are dispatched first:
+  // grid row 0 is the mean column (slot npairs), rows 1.. the float pairs
+  const int slot = blockIdx.y == 0 ? dd.npairs : (int)blockIdx.y - 1;
   const int64_t ld = dd.D;
   const bool do_rr = fused && !apply_only;
   if (slot < dd.npairs) {
@@ -398,9 +410,13 @@ __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const uint
       }
     }
     fft_stages<T, L1, 1, -1>(buf, tw1, lane);
-    for (int k1 = lane; k1 < L1; k1 += 64) {
-      const int64_t m = ((int64_t)n2 * k1) & (D - 1);
-      buf[k1] = cmul(buf[k1], unit_root<-1, T>(m, two_over_d));
+    // e^{-2 pi i n2 k1 / D} for k1 = lane + 64 i
+    RootWalk<T> tw((T)(((int64_t)n2 * lane) & (D - 1)) * two_over_d, (T)(((int64_t)n2 * 64) & (D - 1)) * two_over_d);
+#pragma unroll
+    for (int i = 0; i < L1 / 64; ++i) {
+      const int k1 = lane + 64 * i;
+      buf[k1] = cmul(buf[k1], Cx<T>{tw.w.x, -tw.w.y});
+      tw.next();
     }
   }
   __syncthreads();
@@ -412,8 +428,8 @@ __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const uint
 
 template <int L1>
 struct MidGeom {
-  static constexpr int GF = (8192 / L1) < 16 ? (8192 / L1) : 16;
-  static constexpr int GD = (4096 / L1) < 8 ? (4096 / L1) : 8;
+  static constexpr int GF = (4096 / L1) < 16 ? (4096 / L1) : 16;
+  static constexpr int GD = (2048 / L1) < 8 ? (2048 / L1) : 8;
   static constexpr size_t LDS_F = (size_t)GF * (L1 + 1) * sizeof(Cx<float>) + (size_t)GF * L1;
   static constexpr size_t LDS_D = (size_t)GD * (L1 + 1) * sizeof(Cx<double>) + (size_t)GD * L1;
   static constexpr size_t LDS = LDS_F > LDS_D ? LDS_F : LDS_D;
@@ -426,15 +442,17 @@ __global__ __launch_bounds__(256) void k_dct_mid(DctDims dd, DctBuffers b, const
   using G = MidGeom<L1>;
   __shared__ __align__(16) unsigned char smem[G::LDS];
   const int N2 = 1 << dd.l2;
-  const int ftiles = vb ? 0 : dd.npairs * (N2 / G::GF);
+  // the float64 mean column's tiles (the slowest) come first in dispatch order
+  const int dtiles = N2 / G::GD;
   const int blk = blockIdx.x;
-  if (blk < ftiles) {
-    const int slot = blk / (N2 / G::GF), tile = blk - slot * (N2 / G::GF);
+  if (blk >= dtiles) {
+    const int f = blk - dtiles;
+    const int slot = f / (N2 / G::GF), tile = f - slot * (N2 / G::GF);
     mid_body<float, G::GF, L1>(dd, reinterpret_cast<Cx<float>*>(b.Wf) + (int64_t)slot * dd.D, b.mk, b.mval,
                                nullptr, as_cx(b.tw1f), tile, smem);
   } else {
-    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd), b.mk, b.mval, vb, as_cx(b.tw1d),
-                                blk - ftiles, smem);
+    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd), b.mk, b.mval, vb, as_cx(b.tw1d), blk,
+                                smem);
   }
 }
 
@@ -480,6 +498,8 @@ __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Ws
   if (!active) return;
   const T half_over_d = T(0.5) / (T)dd.D;
   const T rh = (T)0.70710678118654752440;
+  // e^{i pi k / 2D} for k = row + N1 (lane + 64 i)
+  RootWalk<T> th((T)(row + ((int64_t)lane << dd.l1)) * half_over_d, (T)((int64_t)64 << dd.l1) * half_over_d);
 #pragma unroll
   for (int i = 0; i < PE; ++i) {
     const int e = lane + 64 * i;
@@ -491,8 +511,8 @@ __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Ws
       const int mw = (mrow == ru.rowA) ? 0 : 1;
       zm = sz[mw * L2 + mirror_col(row, e, L2)];
     }
-    T s, c;
-    sin_cos_pi((T)k * half_over_d, &s, &c);
+    const T c = th.w.x, s = th.w.y;
+    th.next();
     const T ck = k == 0 ? rh : T(1);
     // (z + conj zm) / 2 and (z - conj zm) / 2i
     const Cx<T> v1{(z.x + zm.x) * T(0.5), (z.y - zm.y) * T(0.5)};
@@ -578,7 +598,7 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
   constexpr size_t kF = 2 * L2 * sizeof(Cx<float>);
   constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);
   __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
-  const int slot = b0 ? dd.npairs : blockIdx.y;
+  const int slot = (b0 || blockIdx.y == 0) ? dd.npairs : (int)blockIdx.y - 1;  // mean column first
   const int64_t ld = dd.D;
   const bool dots = !apply_only;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
