@@ -114,7 +114,14 @@ enum {
  *   so C^T is the inverse DCT and Phi Phi^T = I_N.  Precision COFEM_PREC_FP32
  *   only.  rows is copied to the host once to check it (COFEM_ERR_INVALID_ARG
  *   when an index repeats or is out of range).
- * y         device, N float32.
+ * y         device, N float32; with n_tasks = T > 1, T observation vectors of
+ *           N float32 each, task t at y + t N.
+ * n_tasks   0 or 1: one observation vector.  T > 1 (COFEM_DCT_MASK only, K + T
+ *           <= 64): multi-task SBL, the extension named in Sec. 5: T tasks share
+ *           alpha, the E-step solves A X = [p_1 .. p_K | beta Phi^T y_1 .. y_T]
+ *           (a float64 column per task), and the M-step is
+ *           alpha_j = 1 / max(mean_t mu_tj^2 + s_j, 1/alpha_max).
+ *           cofem_posterior then returns task 0's mean; cofem_get_means all.
  * phi, taps, rows and y are read during cofem_init only (the library keeps its
  * own packed copy of Phi or the mask, and the vector beta Phi^T y); the caller
  * keeps ownership.
@@ -130,6 +137,7 @@ typedef struct cofem_problem {
   const float* taps;
   const float* y;
   const int32_t* rows;
+  int32_t n_tasks;
 } cofem_problem;
 
 /*
@@ -214,6 +222,11 @@ cofem_status cofem_posterior(cofem_ctx* ctx, int32_t problem, float* mu, float* 
 /* Replaces alpha of `problem` (device float32, length D, all > 0): the next
  * E-step uses it.  Used for step-by-step comparison with a reference. */
 cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha);
+
+/* The posterior means of every task after the last E-step: mu device, T x D
+ * float64 (task t at mu + t D), natural coefficient order.  T = 1 for a
+ * single-task context (then mu is cofem_get_solution's mean column). */
+cofem_status cofem_get_means(cofem_ctx* ctx, int32_t problem, double* mu);
 
 /* Sets the EM iteration index t (>= 0, < 65536) whose probes the next E-step draws. */
 cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t);

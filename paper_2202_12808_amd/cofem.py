@@ -56,7 +56,7 @@ class cofem_problem(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("N", c_int64), ("D", c_int64), ("phi", c_void_p),
                 ("ld_phi", c_int64), ("phi_dtype", c_int32), ("H", c_int32), ("W", c_int32),
                 ("kh", c_int32), ("kw", c_int32), ("taps", c_void_p), ("y", c_void_p),
-                ("rows", c_void_p)]
+                ("rows", c_void_p), ("n_tasks", c_int32)]
 
 
 class cofem_params(ctypes.Structure):
@@ -84,6 +84,7 @@ _SIGNATURES = {
     "cofem_set_iteration": (c_int32, [c_void_p, c_int32]),
     "cofem_set_fixed_cg_iters": (c_int32, [c_void_p, c_int32]),
     "cofem_get_solution": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "cofem_get_means": (c_int32, [c_void_p, c_int32, c_void_p]),
     "cofem_apply_A": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cofem_probe_signs": (c_int32, [c_uint64, c_int32, c_int32, c_int64, c_void_p, c_void_p]),
     "cofem_time_operator": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float)]),
@@ -197,6 +198,10 @@ def cofem_set_fixed_cg_iters(ctx, n: int):
     _check(load().cofem_set_fixed_cg_iters(ctx, n), ctx)
 
 
+def cofem_get_means(ctx, mu, problem: int = 0):
+    _check(load().cofem_get_means(ctx, problem, _ptr(mu)), ctx)
+
+
 def cofem_get_solution(ctx, probes=None, mean=None, problem: int = 0):
     _check(load().cofem_get_solution(ctx, problem, _ptr(probes), _ptr(mean)), ctx)
 
@@ -307,16 +312,22 @@ class CoFEM:
     @classmethod
     def dct(cls, rows, y, D, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
         """Inverse DCT of a length-D coefficient vector followed by the N
-        observed samples `rows` (distinct indices into [0, D))."""
+        observed samples `rows` (distinct indices into [0, D)).  y: (N,) for
+        one task, or (T, N) for T tasks sharing alpha (multi-task SBL)."""
         import torch
         if rows.dtype != torch.int32 or y.dtype != torch.float32 or not rows.is_cuda or not y.is_cuda:
             raise CofemError(COFEM_ERR_INVALID_ARG, "rows must be an int32 and y a float32 GPU tensor")
         rows = rows.contiguous()
         y = y.contiguous()
         N = rows.numel()
+        T = 1 if y.dim() == 1 else int(y.shape[0])
+        if y.numel() != T * N:
+            raise CofemError(COFEM_ERR_INVALID_ARG, "y must be (N,) or (T, N)")
         prob = cofem_problem(kind=COFEM_DCT_MASK, N=N, D=int(D), phi=None, ld_phi=0, phi_dtype=COFEM_F32,
-                             H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr(), rows=rows.data_ptr())
-        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (rows, y), rows.device)
+                             H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr(), rows=rows.data_ptr(), n_tasks=T)
+        ctx = cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (rows, y), rows.device)
+        ctx.T = T
+        return ctx
 
     def em_step(self, n_iters=1):
         return cofem_em_step(self.ctx, n_iters)
@@ -337,6 +348,14 @@ class CoFEM:
         cofem_get_solution(self.ctx, X, m)
         torch.cuda.synchronize(self.device)
         return X, m
+
+    def means(self):
+        """(T, D) float64: every task's posterior mean after the last E-step."""
+        import torch
+        m = torch.empty((getattr(self, "T", 1), self.D), dtype=torch.float64, device=self.device)
+        cofem_get_means(self.ctx, m)
+        torch.cuda.synchronize(self.device)
+        return m
 
     def set_alpha(self, alpha):
         alpha = alpha.to(device=self.device, dtype=self.dtype_f32()).contiguous()

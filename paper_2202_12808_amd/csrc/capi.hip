@@ -52,6 +52,7 @@ struct cofem_ctx {
   BatchHost* batch = nullptr;
   int64_t N = 0, D = 0;
   int K = 0, KP = 0;
+  int NT = 1;  // mean columns: tasks sharing alpha
   double beta = 1.0, tol = 1e-5, alpha_max = 1e10;
   int U = 400;
   uint64_t seed = 0;
@@ -209,6 +210,7 @@ cofem_status push_controls(cofem_ctx* c) {
   h.fixed = c->fixed_iters > 0 ? 1 : 0;
   h.kp = c->KP;
   h.k = c->K;
+  h.nt = c->NT;
   h.stop = 1;
   for (int i = 0; i < n; ++i)
     COFEM_HIP(c, hipMemcpyAsync(c->st + i, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
@@ -308,6 +310,7 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   cd.tilesY = (p.H + kConvTile - 1) / kConvTile;
   c->KP = c->K;
   cd.fp64 = c->precision == COFEM_PREC_FP64 ? 1 : 0;
+  cd.nt = 1;
   const size_t blk = (size_t)cd.ldD * c->K;
   COFEM_TRY(alloc(c, &c->taps, (size_t)p.kh * p.kw));
   COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
@@ -368,6 +371,8 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   xd.K = c->K;
   xd.npairs = (c->K + 1) / 2;
   xd.units = (1 << xd.l1) / 2 + 1;
+  xd.nt = c->NT;
+  xd.ntd = (c->NT + 1) / 2;
   ConvDims& cd = c->cd;
   cd.H = 1;
   cd.W = (int)p.D;
@@ -377,6 +382,7 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   cd.K = c->K;
   cd.fp64 = 0;
   cd.perm = xd.l1 | (xd.l2 << 8);
+  cd.nt = c->NT;
   c->KP = c->K;
   // the observed samples must be distinct and in range (checked once, here)
   {
@@ -390,9 +396,9 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
       seen[(size_t)r] = 1;
     }
   }
-  const size_t D = (size_t)p.D, blk = D * (size_t)c->K;
+  const size_t D = (size_t)p.D, blk = D * (size_t)c->K, DT = D * (size_t)c->NT;
   const int N1 = 1 << xd.l1, N2 = 1 << xd.l2;
-  COFEM_TRY(alloc(c, &c->b0, D));
+  COFEM_TRY(alloc(c, &c->b0, DT));
   COFEM_TRY(alloc(c, &c->alpha, D));
   COFEM_TRY(alloc(c, &c->mu, D));
   COFEM_TRY(alloc(c, &c->sdiag, D));
@@ -403,23 +409,23 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
     *b = q;
   }
   double** vecs[6] = {&c->xm, &c->rm, &c->pm, &c->qm, &c->Vsm, &c->Qsm};
-  for (double** v : vecs) COFEM_TRY(alloc(c, v, D));
+  for (double** v : vecs) COFEM_TRY(alloc(c, v, DT));  // one column per task
   float *Wf = nullptr, *tw1f = nullptr, *tw2f = nullptr;
   double *Wd = nullptr, *vb = nullptr, *tw1d = nullptr, *tw2d = nullptr, *rr = nullptr;
   uint8_t* mk = nullptr;
   COFEM_TRY(alloc(c, &Wf, 2 * D * (size_t)xd.npairs));
-  COFEM_TRY(alloc(c, &Wd, 2 * D));
+  COFEM_TRY(alloc(c, &Wd, 2 * D * (size_t)xd.ntd));
   COFEM_TRY(alloc(c, &mk, D));
-  COFEM_TRY(alloc(c, &vb, D));
+  COFEM_TRY(alloc(c, &vb, DT));
   COFEM_TRY(alloc(c, &tw1f, (size_t)2 * N1));
   COFEM_TRY(alloc(c, &tw2f, (size_t)2 * N2));
   COFEM_TRY(alloc(c, &tw1d, (size_t)2 * N1));
   COFEM_TRY(alloc(c, &tw2d, (size_t)2 * N2));
-  COFEM_TRY(alloc(c, &rr, (size_t)2 * (c->K + 1) * xd.units));
+  COFEM_TRY(alloc(c, &rr, (size_t)2 * (c->K + c->NT) * xd.units));
   COFEM_TRY(alloc(c, &c->minv, D));
   COFEM_TRY(alloc(c, &c->dct_cn, D));
   c->xb = DctBuffers{Wf, Wd, mk, c->beta / (double)p.D, tw1f, tw2f, tw1d, tw2d, rr};
-  const int ncols = c->K + 1;
+  const int ncols = c->K + c->NT;
   ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
   const int64_t nupd = conv_update_blocks(cd);
   const int64_t nblks[3] = {nupd, nupd, xd.units};
@@ -429,7 +435,7 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   for (int i = 0; i < 3; ++i) {
     // the iteration's tree runs per column slot (a float pair or the mean
     // column) with regions of 2 * nv values
-    const int regions = i == 2 ? xd.npairs + 1 : ncols;
+    const int regions = i == 2 ? xd.npairs + xd.ntd : ncols;
     COFEM_TRY(alloc_tree(c, &reds[i]->parts, &reds[i]->cnts, nblks[i], i == 2 ? 2 * nvs[i] : nvs[i], regions));
     COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
     COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
@@ -715,6 +721,9 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
       (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
     return *why = "warm starts and the Jacobi preconditioner are built for convolution and DCT dictionaries",
            COFEM_ERR_UNSUPPORTED;
+  for (int32_t i = 0; i < n; ++i)
+    if (p[i].n_tasks > 1 && (n != 1 || p[i].kind != COFEM_DCT_MASK))
+      return *why = "several tasks (n_tasks > 1) are built for one DCT-dictionary problem", COFEM_ERR_UNSUPPORTED;
   if (n > 1 || p->phi_dtype == COFEM_BF16 || (q->flags & COFEM_FLAG_BATCHED)) {
     // batched form: dense problems whose bfloat16 dictionary is the problem
     if (q->precision != COFEM_PREC_FP32)
@@ -748,6 +757,8 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
     if (p->N != (int64_t)p->H * p->W || p->D != p->N) return *why = "conv needs N == D == H*W", COFEM_ERR_INVALID_ARG;
     if ((int64_t)p->H * p->W > (int64_t)1 << 30) return *why = "image too large", COFEM_ERR_INVALID_ARG;
   } else if (p->kind == COFEM_DCT_MASK) {
+    if (p->n_tasks < 0 || q->K + (p->n_tasks > 1 ? p->n_tasks : 1) > kMaxCols)
+      return *why = "n_tasks must be >= 0 with K + n_tasks <= 64", COFEM_ERR_INVALID_ARG;
     if (p->D < ((int64_t)1 << 12) || p->D > ((int64_t)1 << 20) || (p->D & (p->D - 1)) != 0)
       return *why = "the DCT dictionary needs D = 2^p, 12 <= p <= 20", COFEM_ERR_UNSUPPORTED;
     if (p->N < 1 || p->N > p->D) return *why = "the DCT dictionary needs 1 <= N <= D", COFEM_ERR_INVALID_ARG;
@@ -1159,6 +1170,7 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   if (!c) return fail(nullptr, COFEM_ERR_OUT_OF_MEMORY, "host allocation failed");
   const cofem_problem& p = problems[0];
   c->kind = p.kind;
+  c->NT = p.n_tasks > 1 ? p.n_tasks : 1;  // validated: several tasks only for the DCT dictionary
   c->N = p.N;
   c->D = p.D;
   c->K = params->K;
@@ -1252,6 +1264,19 @@ cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha
     COFEM_HIP(ctx, perm_in_f32(ctx->cd, alpha, dst, ctx->stream));
   else
     COFEM_HIP(ctx, hipMemcpyAsync(dst, alpha, sizeof(float) * (size_t)D, hipMemcpyDeviceToDevice, ctx->stream));
+  return COFEM_OK;
+}
+
+cofem_status cofem_get_means(cofem_ctx* ctx, int32_t problem, double* mu) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (!mu) return fail(ctx, COFEM_ERR_INVALID_ARG, "mu is null");
+  if (ctx->batch || ctx->precision == COFEM_PREC_BF16_IR || ctx->kind != COFEM_DCT_MASK) {
+    // one task: the mean column of the solution
+    return cofem_get_solution(ctx, problem, nullptr, mu);
+  }
+  if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
+  for (int t = 0; t < ctx->NT; ++t)
+    COFEM_HIP(ctx, perm_out_f64(ctx->cd, ctx->xm + (size_t)t * ctx->D, mu + (size_t)t * ctx->D, ctx->stream));
   return COFEM_OK;
 }
 

@@ -36,8 +36,9 @@ struct CgScalars {
   int32_t stop;           // 1 once the solve is finished (kernels then no-op)
   int32_t limit;          // iteration cap
   int32_t fixed;          // 1: ignore tol, run exactly `limit` iterations
-  int32_t kp;             // probe slots; mean column index
+  int32_t kp;             // probe slots; index of the first mean column
   int32_t k;              // real probes
+  int32_t nt;             // mean columns (tasks sharing alpha; 1 for one task)
   int32_t n_clamped;      // M-step floor hits of the last M-step
   int32_t numeric_error;  // set when a CG scalar is not finite
   uint32_t counter[4];    // last-block tickets (self-resetting)
@@ -262,7 +263,7 @@ struct CgCtl {
 };
 __device__ __forceinline__ CgCtl load_cg_ctl(const CgScalars* st) {
   CgCtl c;
-  c.nc = st->kp + 1;
+  c.nc = st->kp + st->nt;
   c.rho = (int)threadIdx.x < c.nc ? st->rho[threadIdx.x] : 0.0;
   c.nB = st->nB;
   c.tol = st->tol;
@@ -376,7 +377,7 @@ __device__ __forceinline__ void finish_fused(CgScalars* st, const double* v, int
 
 // Finishes the initial residual R = B: rho_c = ||b_c||^2 (in shared memory).
 __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
-  const int nc = st->kp + 1;
+  const int nc = st->kp + st->nt;
   if ((int)threadIdx.x < nc) {
     st->rho[threadIdx.x] = rho[threadIdx.x];
     st->b[threadIdx.x] = 0.0;
@@ -450,7 +451,7 @@ __device__ __forceinline__ void finish_update_pcg(CgScalars* st, const double* v
 // Finishes the true-residual check: ||b_c - A x_c||^2 per column (in shared
 // memory) and the joint ratio sqrt(sum_c ...) / ||B||_F.
 __device__ __forceinline__ void finish_true_resid(CgScalars* st, const double* res) {
-  const int nc = st->kp + 1;
+  const int nc = st->kp + st->nt;
   if ((int)threadIdx.x < nc) st->true_res[threadIdx.x] = res[threadIdx.x];
   if (threadIdx.x == 0) {
     const double nB = st->nB;
@@ -465,7 +466,7 @@ __device__ __forceinline__ void finish_true_resid(CgScalars* st, const double* r
 // shared memory): the next inner solve starts from R with reference norm
 // ||R||_F, a fresh iteration count and cap `limit`; true_ratio = ||R||_F/||B||_F.
 __device__ __forceinline__ void finish_ir_residual(CgScalars* st, const double* rho, int limit) {
-  const int nc = st->kp + 1;
+  const int nc = st->kp + st->nt;
   if ((int)threadIdx.x < nc) {
     st->rho[threadIdx.x] = rho[threadIdx.x];
     st->true_res[threadIdx.x] = rho[threadIdx.x];
@@ -566,6 +567,8 @@ struct ConvDims {
   // for the DCT dictionary's row-major order of coefficient k = k1 + 2^l1 k2
   // at position k1 2^l2 + k2 (perm_nat maps a position to k)
   int perm;
+  // float64 mean columns (tasks sharing alpha), blocks of ldD after xm etc.
+  int nt;
 };
 
 __host__ __device__ __forceinline__ int64_t perm_nat(int perm, int64_t pos) {
@@ -644,12 +647,13 @@ struct DctDims {
   int l1, l2;      // N1 = 2^l1 rows, N2 = 2^l2 columns (l1 = ceil(p/2))
   int K;           // probe columns
   int npairs;      // ceil(K/2) float column pairs
+  int nt, ntd;     // float64 mean columns (tasks) and their pairs ceil(nt/2)
   int units;       // N1/2 + 1 row units (a row and its mirror row)
   int gf, gd;      // groups per middle-launch tile: float pairs, float64 column
 };
 struct DctBuffers {
   float* Wf;             // npairs x D complex float intermediates
-  double* Wd;            // D complex double intermediate (mean column)
+  double* Wd;            // ntd x D complex double intermediates (mean column pairs)
   const uint8_t* mk;     // mask: 1 where the sample is observed, middle-launch order
   double mval;           // the mask's scale beta/D
   const float* tw1f;     // e^{2 pi i j / N1}, j < N1 (float complex)

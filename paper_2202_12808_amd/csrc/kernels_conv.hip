@@ -648,7 +648,7 @@ int conv_update_blocks(const ConvDims& cd) {
 
 // ------------------------------------------------ initial residual R = P = B (Eq. 7)
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K, int perm, uint64_t seed,
+__global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed,
                                                    int t, const double* __restrict__ b0,
                                                    TP* __restrict__ X, TP* __restrict__ R,
                                                    TP* __restrict__ P, double* __restrict__ xm,
@@ -658,12 +658,13 @@ __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   double acc = 0.0;
-  if (col == K) {
+  if (col >= K) {  // mean column col - K
+    const int64_t mo = (int64_t)(col - K) * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const double b = b0[d];
-      rm[d] = b;
-      pm[d] = b;
-      xm[d] = 0.0;
+      const double b = b0[mo + d];
+      rm[mo + d] = b;
+      pm[mo + d] = b;
+      xm[mo + d] = 0.0;
       acc += b * b;
     }
   } else {
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K
   if (threadIdx.x == 0) mine[0] = tot_b;
   __syncthreads();
   if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col,
-                          K + 1, 1, mine, tot))
+                          K + nt, 1, mine, tot))
     return;
   finish_init(st, tot);
 }
@@ -690,13 +691,13 @@ __global__ __launch_bounds__(256) void k_conv_init(int64_t D, int64_t ldD, int K
 hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0, void* X, void* R,
                      void* P, double* xm, double* rm, double* pm, const ConvReduce& red,
                      CgScalars* st, hipStream_t s) {
-  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  const dim3 grid(conv_update_blocks(cd), cd.K + cd.nt);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_init<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_init<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, b0,
                        static_cast<double*>(X), static_cast<double*>(R), static_cast<double*>(P), xm,
                        rm, pm, red, st);
   else
-    hipLaunchKernelGGL(k_conv_init<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_init<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, b0,
                        static_cast<float*>(X), static_cast<float*>(R), static_cast<float*>(P), xm, rm,
                        pm, red, st);
   return hipGetLastError();
@@ -708,7 +709,8 @@ hipError_t conv_init(const ConvDims& cd, uint64_t seed, int t, const double* b0,
 // operator pass: R = B - Q; without one: R = B, X = 0.  Then Z = M^-1 R,
 // P = Z; per column rho = r^T z, ||r||^2 (the stop test's) and ||b||^2.
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, int K, int perm, uint64_t seed, int t,
+__global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed,
+                                                       int t,
                                                        const double* __restrict__ b0, const float* __restrict__ minv,
                                                        const TP* __restrict__ Qx, const double* __restrict__ qxm,
                                                        TP* __restrict__ X, TP* __restrict__ R, TP* __restrict__ P,
@@ -718,14 +720,15 @@ __global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, i
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   double rz = 0.0, rr = 0.0, bb = 0.0;
-  if (col == K) {
+  if (col >= K) {  // mean column col - K
+    const int64_t mo = (int64_t)(col - K) * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const double b = b0[d];
-      const double r = qxm ? b - qxm[d] : b;
+      const double b = b0[mo + d];
+      const double r = qxm ? b - qxm[mo + d] : b;
       const double z = minv ? (double)minv[d] * r : r;
-      rm[d] = r;
-      pm[d] = z;
-      if (!qxm) xm[d] = 0.0;
+      rm[mo + d] = r;
+      pm[mo + d] = z;
+      if (!qxm) xm[mo + d] = 0.0;
       rz += r * z;
       rr += r * r;
       bb += b * b;
@@ -755,22 +758,24 @@ __global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, i
     mine[2] = v2;
   }
   __syncthreads();
-  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col, K + 1, 3, mine,
+  if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col, K + nt, 3, mine,
                           tot))
     return;
-  finish_init_pcg(st, tot, K + 1);
+  finish_init_pcg(st, tot, K + nt);
 }
 
 hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double* b0, const float* minv,
                          const void* Qx, const double* qxm, void* X, void* R, void* P, double* xm, double* rm,
                          double* pm, const ConvReduce& red, CgScalars* st, hipStream_t s) {
-  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  const dim3 grid(conv_update_blocks(cd), cd.K + cd.nt);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_init_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0, minv,
+    hipLaunchKernelGGL(k_conv_init_pcg<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, b0,
+                       minv,
                        static_cast<const double*>(Qx), qxm, static_cast<double*>(X), static_cast<double*>(R),
                        static_cast<double*>(P), xm, rm, pm, red, st);
   else
-    hipLaunchKernelGGL(k_conv_init_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0, minv,
+    hipLaunchKernelGGL(k_conv_init_pcg<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, b0,
+                       minv,
                        static_cast<const float*>(Qx), qxm, static_cast<float*>(X), static_cast<float*>(R),
                        static_cast<float*>(P), xm, rm, pm, red, st);
   return hipGetLastError();
@@ -780,13 +785,14 @@ hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double*
 // zero probe columns; mu0 null: keep xm as it is, the previous solve's mean
 // column).
 template <typename TP>
-__global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, uint64_t seed, int t, const float* __restrict__ d0,
-                             const double* __restrict__ mu0, TP* __restrict__ X, double* __restrict__ xm) {
+__global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed, int t,
+                             const float* __restrict__ d0, const double* __restrict__ mu0, TP* __restrict__ X,
+                             double* __restrict__ xm) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= D * (K + 1)) return;
+  if (idx >= D * (K + nt)) return;
   const int64_t k = idx / D, d = idx - (idx / D) * D;
-  if (k == K) {
-    if (mu0) xm[d] = mu0[d];
+  if (k >= K) {  // mean column k - K
+    if (mu0) xm[(k - K) * ldD + d] = mu0[(k - K) * ldD + d];
   } else {
     const float dv = d0 ? fmaxf(d0[d], 0.0f) : 0.0f;
     X[k * ldD + d] = (TP)(dv * probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d)));
@@ -795,13 +801,13 @@ __global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, uint64_t s
 
 hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
                       double* xm, hipStream_t s) {
-  const int64_t tot = cd.D * (cd.K + 1);
+  const int64_t tot = cd.D * (cd.K + cd.nt);
   const dim3 grid((unsigned)((tot + 255) / 256));
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, d0, mu0,
+    hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, d0, mu0,
                        static_cast<double*>(X), xm);
   else
-    hipLaunchKernelGGL(k_conv_start<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, d0, mu0,
+    hipLaunchKernelGGL(k_conv_start<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, d0, mu0,
                        static_cast<float*>(X), xm);
   return hipGetLastError();
 }
@@ -827,7 +833,7 @@ hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const
 // ||b_c - q_c||^2 per column with q = A x from an operator pass over X and B
 // regenerated: probes of EM iteration t (Eq. 7) and b0 for the mean column.
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD, int K, int perm, uint64_t seed,
+__global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed,
                                                          int t, const double* __restrict__ b0,
                                                          const TP* __restrict__ Q,
                                                          const double* __restrict__ qm, ConvReduce red,
@@ -836,9 +842,10 @@ __global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD,
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   double acc = 0.0;
-  if (col == K) {
+  if (col >= K) {  // mean column col - K
+    const int64_t mo = (int64_t)(col - K) * ldD;
     for (int64_t d = gtid; d < D; d += gstride) {
-      const double e = b0[d] - qm[d];
+      const double e = b0[mo + d] - qm[mo + d];
       acc += e * e;
     }
   } else {
@@ -855,26 +862,26 @@ __global__ __launch_bounds__(256) void k_conv_true_resid(int64_t D, int64_t ldD,
   if (threadIdx.x == 0) mine[0] = tot_b;
   __syncthreads();
   if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, blockIdx.x, gridDim.x, col,
-                          K + 1, 1, mine, tot))
+                          K + nt, 1, mine, tot))
     return;
   finish_true_resid(st, tot);
 }
 
 hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const double* b0, const void* Q,
                            const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s) {
-  const dim3 grid(conv_update_blocks(cd), cd.K + 1);
+  const dim3 grid(conv_update_blocks(cd), cd.K + cd.nt);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_true_resid<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_true_resid<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, b0,
                        static_cast<const double*>(Q), qm, red, st);
   else
-    hipLaunchKernelGGL(k_conv_true_resid<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t, b0,
+    hipLaunchKernelGGL(k_conv_true_resid<float>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, b0,
                        static_cast<const float*>(Q), qm, red, st);
   return hipGetLastError();
 }
 
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, int perm, uint64_t seed,
+__global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed,
                                                     int t, const TP* __restrict__ X,
                                                     const double* __restrict__ xm,
                                                     float* __restrict__ alpha, double alpha_max,
@@ -891,7 +898,16 @@ __global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int 
       acc += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, dn) * (double)X[(int64_t)k * ldD + d];
     const double s = acc / (double)K;
     const double m = xm[d];
-    const double den = m * m + s;
+    // tasks sharing alpha: the mean of their squared means
+    double m2 = m * m;
+    if (nt > 1) {
+      for (int j = 1; j < nt; ++j) {
+        const double mj = xm[(int64_t)j * ldD + d];
+        m2 += mj * mj;
+      }
+      m2 /= (double)nt;
+    }
+    const double den = m2 + s;
     if (!(den >= floor_v)) clamped += 1.0;
     alpha[d] = (float)(1.0 / (den >= floor_v ? den : floor_v));
     mu[d] = (float)m;
@@ -908,10 +924,10 @@ hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, c
   const int64_t want = (cd.D + 255) / 256;
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t,
+    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
                        static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, st);
   else
-    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, seed, t,
+    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
                        static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, st);
   return hipGetLastError();
 }

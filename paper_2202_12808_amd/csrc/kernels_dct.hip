@@ -310,12 +310,15 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
   constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);  // > 2 * 1 * L2 * sizeof(double)
   __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
   __shared__ double shm[8];
-  // the float64 mean column's blocks (the slowest) are dispatched first:
-  // grid row 0 is the mean column (slot npairs), rows 1.. the float pairs
-  const int slot = blockIdx.y == 0 ? dd.npairs : (int)blockIdx.y - 1;
+  // grid rows 0 .. ntd-1: the float64 mean-column pairs (the slowest blocks,
+  // dispatched first); then the float probe pairs
   const int64_t ld = dd.D;
   const bool do_rr = fused && !apply_only;
-  if (slot < dd.npairs) {
+  int cols[2];
+  bool valid[2];
+  double rz[2] = {0.0, 0.0}, rr[2] = {0.0, 0.0};
+  if ((int)blockIdx.y >= dd.ntd) {
+    const int slot = (int)blockIdx.y - dd.ntd;
     SlotCols<float, 2> sc;
     float *Xc[2], *Rc[2], *Pc[2];
     const float* Qc[2];
@@ -327,39 +330,39 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
       Rc[c] = R + off;
       Pc[c] = P + off;
       Qc[c] = Q + off;
+      cols[c] = sc.col[c];
+      valid[c] = sc.valid[c];
     }
-    double rz[2] = {0.0, 0.0}, rr[2] = {0.0, 0.0};
     rows_in_body<float, 2, L2>(dd, b, sc, Xc, Rc, Pc, Qc, minv, st, fused,
                                reinterpret_cast<Cx<float>*>(b.Wf) + slot * ld, as_cx(b.tw2f), smem, rz, rr);
-    if (do_rr) {
-      const int64_t half = (int64_t)(dd.K + 1) * dd.units;
-      for (int c = 0; c < 2; ++c) {
-        const double tz = block_sum(rz[c], shm);
-        const double tr = block_sum(rr[c], shm);
-        if (threadIdx.x == 0 && sc.valid[c]) {
-          b.rr[(int64_t)sc.col[c] * dd.units + blockIdx.x] = tz;
-          b.rr[half + (int64_t)sc.col[c] * dd.units + blockIdx.x] = tr;
-        }
-      }
-    }
   } else {
-    SlotCols<double, 1> sc;
-    sc.col[0] = dd.K;
-    sc.valid[0] = true;
-    double* Xc[1] = {xm};
-    double* Rc[1] = {rm};
-    double* Pc[1] = {pm};
-    const double* Qc[1] = {qm};
-    double rz[1] = {0.0}, rr[1] = {0.0};
-    rows_in_body<double, 1, L2>(dd, b, sc, Xc, Rc, Pc, Qc, minv, st, fused, reinterpret_cast<Cx<double>*>(b.Wd),
-                                as_cx(b.tw2d), smem, rz, rr);
-    if (do_rr) {
-      const int64_t half = (int64_t)(dd.K + 1) * dd.units;
-      const double tz = block_sum(rz[0], shm);
-      const double tr = block_sum(rr[0], shm);
-      if (threadIdx.x == 0) {
-        b.rr[(int64_t)dd.K * dd.units + blockIdx.x] = tz;
-        b.rr[half + (int64_t)dd.K * dd.units + blockIdx.x] = tr;
+    const int j = blockIdx.y;  // tasks 2j, 2j + 1
+    SlotCols<double, 2> sc;
+    double *Xc[2], *Rc[2], *Pc[2];
+    const double* Qc[2];
+    for (int c = 0; c < 2; ++c) {
+      const int t = 2 * j + c;
+      sc.col[c] = dd.K + t;
+      sc.valid[c] = t < dd.nt;
+      const int64_t off = (int64_t)(sc.valid[c] ? t : 0) * ld;
+      Xc[c] = xm + off;
+      Rc[c] = rm + off;
+      Pc[c] = pm + off;
+      Qc[c] = qm + off;
+      cols[c] = sc.col[c];
+      valid[c] = sc.valid[c];
+    }
+    rows_in_body<double, 2, L2>(dd, b, sc, Xc, Rc, Pc, Qc, minv, st, fused,
+                                reinterpret_cast<Cx<double>*>(b.Wd) + j * ld, as_cx(b.tw2d), smem, rz, rr);
+  }
+  if (do_rr) {
+    const int64_t half = (int64_t)(dd.K + dd.nt) * dd.units;
+    for (int c = 0; c < 2; ++c) {
+      const double tz = block_sum(rz[c], shm);
+      const double tr = block_sum(rr[c], shm);
+      if (threadIdx.x == 0 && valid[c]) {
+        b.rr[(int64_t)cols[c] * dd.units + blockIdx.x] = tz;
+        b.rr[half + (int64_t)cols[c] * dd.units + blockIdx.x] = tr;
       }
     }
   }
@@ -373,8 +376,8 @@ __global__ __launch_bounds__(128) void k_dct_rows_in(DctDims dd, DctBuffers b, f
 // from the real vector vb (middle-launch order) and runs the forward half only.
 template <typename T, int G, int L1>
 __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const uint8_t* __restrict__ mk, double mval,
-                                         const double* __restrict__ vb, const Cx<T>* tw1, int tile,
-                                         unsigned char* smem) {
+                                         const double* __restrict__ vb, const double* __restrict__ vb_im,
+                                         const Cx<T>* tw1, int tile, unsigned char* smem) {
   constexpr int LP = L1 + 1;  // padded group stride
   const int N2 = 1 << dd.l2;
   const int64_t D = dd.D;
@@ -387,7 +390,8 @@ __device__ __forceinline__ void mid_body(const DctDims& dd, Cx<T>* W, const uint
   if (vb) {
     for (int e = tid; e < G * L1; e += blockDim.x) {
       const int j = e / L1, n1 = e - (e / L1) * L1;
-      s[j * LP + n1] = Cx<T>{(T)vb[(int64_t)(g0 + j) * L1 + n1], T(0)};
+      const int64_t i = (int64_t)(g0 + j) * L1 + n1;
+      s[j * LP + n1] = Cx<T>{(T)vb[i], vb_im ? (T)vb_im[i] : T(0)};
     }
   } else {
     for (int e = tid; e < G * L1; e += blockDim.x) {
@@ -442,17 +446,21 @@ __global__ __launch_bounds__(256) void k_dct_mid(DctDims dd, DctBuffers b, const
   using G = MidGeom<L1>;
   __shared__ __align__(16) unsigned char smem[G::LDS];
   const int N2 = 1 << dd.l2;
-  // the float64 mean column's tiles (the slowest) come first in dispatch order
-  const int dtiles = N2 / G::GD;
+  // the float64 mean-column pairs' tiles (the slowest) come first in
+  // dispatch order; b0 mode (vb set) runs only those
+  const int dper = N2 / G::GD;
   const int blk = blockIdx.x;
-  if (blk >= dtiles) {
-    const int f = blk - dtiles;
+  if (blk >= dd.ntd * dper) {
+    const int f = blk - dd.ntd * dper;
     const int slot = f / (N2 / G::GF), tile = f - slot * (N2 / G::GF);
     mid_body<float, G::GF, L1>(dd, reinterpret_cast<Cx<float>*>(b.Wf) + (int64_t)slot * dd.D, b.mk, b.mval,
-                               nullptr, as_cx(b.tw1f), tile, smem);
+                               nullptr, nullptr, as_cx(b.tw1f), tile, smem);
   } else {
-    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd), b.mk, b.mval, vb, as_cx(b.tw1d), blk,
-                                smem);
+    const int j = blk / dper, tile = blk - j * dper;  // tasks 2j, 2j + 1
+    const double* re = vb ? vb + (int64_t)(2 * j) * dd.D : nullptr;
+    const double* im = (vb && 2 * j + 1 < dd.nt) ? vb + (int64_t)(2 * j + 1) * dd.D : nullptr;
+    mid_body<double, G::GD, L1>(dd, reinterpret_cast<Cx<double>*>(b.Wd) + (int64_t)j * dd.D, b.mk, b.mval, re, im,
+                                as_cx(b.tw1d), tile, smem);
   }
 }
 
@@ -465,7 +473,7 @@ template <typename T, int NC, int L2>
 __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Wslot, const Cx<T>* tw2,
                                               const SlotCols<T, NC>& sc, const T* const* Pc, const T* const* Rc,
                                               T* const* Qc, const float* __restrict__ alpha,
-                                              const float* __restrict__ minv, double* b0, bool dots,
+                                              const float* __restrict__ minv, bool b0, bool dots,
                                               unsigned char* smem, double* acc /* [NC * 3] */) {
   const int N1 = 1 << dd.l1;
   const RowUnit ru = row_unit(blockIdx.x, N1);
@@ -521,8 +529,10 @@ __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Ws
     out[0] = ck * (c * v1.x + s * v1.y);
     out[1] = ck * (c * v2.x + s * v2.y);
     const int64_t pos = (int64_t)row * L2 + e;
-    if (b0) {
-      b0[pos] = (double)out[0];
+    if (b0) {  // set-up: the columns' b0 (Qc points into it)
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc)
+        if (sc.valid[cc]) Qc[cc][pos] = out[cc];
       continue;
     }
 #pragma unroll
@@ -598,15 +608,17 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
   constexpr size_t kF = 2 * L2 * sizeof(Cx<float>);
   constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);
   __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
-  const int slot = (b0 || blockIdx.y == 0) ? dd.npairs : (int)blockIdx.y - 1;  // mean column first
+  // grid rows 0 .. ntd-1: the float64 mean-column pairs (dispatched first);
+  // then the float probe pairs.  Reduction slots: float pairs 0 .. npairs-1,
+  // mean pairs npairs .. npairs+ntd-1.  b0 mode: the mean pairs only.
   const int64_t ld = dd.D;
   const bool dots = !apply_only;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int cols[2] = {0, 0};
   bool valid[2] = {false, false};
-  int nc_slot = 1;
-  if (slot < dd.npairs) {
-    nc_slot = 2;
+  int slot;
+  if (!b0 && (int)blockIdx.y >= dd.ntd) {
+    slot = (int)blockIdx.y - dd.ntd;
     SlotCols<float, 2> sc;
     const float *Pc[2], *Rc[2];
     float* Qc[2];
@@ -621,18 +633,26 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
       Qc[c] = Q + off;
     }
     rows_out_body<float, 2, L2>(dd, reinterpret_cast<const Cx<float>*>(b.Wf) + slot * ld, as_cx(b.tw2f), sc, Pc,
-                                Rc, Qc, alpha, minv, nullptr, dots, smem, acc);
+                                Rc, Qc, alpha, minv, false, dots, smem, acc);
   } else {
-    SlotCols<double, 1> sc;
-    sc.col[0] = dd.K;
-    sc.valid[0] = true;
-    cols[0] = dd.K;
-    valid[0] = true;
-    const double* Pc[1] = {pm};
-    const double* Rc[1] = {rm};
-    double* Qc[1] = {qm};
-    rows_out_body<double, 1, L2>(dd, reinterpret_cast<const Cx<double>*>(b.Wd), as_cx(b.tw2d), sc, Pc, Rc, Qc,
-                                 alpha, minv, b0, dots, smem, acc);
+    const int j = blockIdx.y;  // tasks 2j, 2j + 1
+    slot = dd.npairs + j;
+    SlotCols<double, 2> sc;
+    const double *Pc[2], *Rc[2];
+    double* Qc[2];
+    for (int c = 0; c < 2; ++c) {
+      const int t = 2 * j + c;
+      sc.col[c] = dd.K + t;
+      sc.valid[c] = t < dd.nt;
+      cols[c] = sc.col[c];
+      valid[c] = sc.valid[c];
+      const int64_t off = (int64_t)(sc.valid[c] ? t : 0) * ld;
+      Pc[c] = pm + off;
+      Rc[c] = rm + off;
+      Qc[c] = b0 ? b0 + off : qm + off;
+    }
+    rows_out_body<double, 2, L2>(dd, reinterpret_cast<const Cx<double>*>(b.Wd) + j * ld, as_cx(b.tw2d), sc, Pc, Rc,
+                                 Qc, alpha, minv, b0 != nullptr, dots, smem, acc);
   }
   if (!dots) return;
   __shared__ double sh[2][6], sums[6];
@@ -644,7 +664,7 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
     double* m = mine + c * nv;
     if (fused) {
       // the folded update's r^T z and r^T r, from the first launch
-      const int64_t half = (int64_t)(dd.K + 1) * dd.units;
+      const int64_t half = (int64_t)(dd.K + dd.nt) * dd.units;
       m[0] = valid[c] ? b.rr[(int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
       m[1] = valid[c] ? b.rr[half + (int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
       m[2] = sums[c * 3 + 0];
@@ -657,9 +677,10 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
     }
   }
   __syncthreads();
-  if (!slot_tree_reduce(red, slot, dd.npairs + 1, dd.units, cols, valid, nc_slot, dd.K + 1, nv, mine, tot)) return;
+  if (!slot_tree_reduce(red, slot, dd.npairs + dd.ntd, dd.units, cols, valid, 2, dd.K + dd.nt, nv, mine, tot))
+    return;
   if (fused)
-    finish_fused(st, tot, dd.K + 1, ctl);
+    finish_fused(st, tot, dd.K + dd.nt, ctl);
   else
     finish_step(st, tot, ctl);
 }
@@ -689,17 +710,18 @@ __global__ void k_dct_tables(int N1, int N2, float* tw1f, float* tw2f, double* t
 // Observed sample j sits at FFT index n = j/2 (j even) or D-1-(j-1)/2 (odd),
 // n = n2 + N2 n1, which the middle launch reads at n2 N1 + n1: there the mask
 // byte 1 (the launch scales by beta/D) and the data term beta sqrt(2/D) y_i.
-__global__ void k_dct_scatter(int64_t D, int l1, int l2, const int32_t* __restrict__ rows, int64_t N,
+__global__ void k_dct_scatter(int64_t D, int l1, int l2, const int32_t* __restrict__ rows, int64_t N, int nt,
                               const float* __restrict__ y, double yscale, uint8_t* __restrict__ mk,
                               double* __restrict__ vb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N * nt) return;
+  const int64_t task = g / N, i = g - (g / N) * N;  // y is task-major: y[task N + i]
   const int64_t j = rows[i];
   const int64_t n = (j & 1) == 0 ? j / 2 : D - 1 - (j - 1) / 2;
   const int64_t n2 = n & ((int64_t(1) << l2) - 1), n1 = n >> l2;
   const int64_t idx = (n2 << l1) + n1;
   mk[idx] = 1;
-  vb[idx] = yscale * (double)y[i];
+  vb[task * D + idx] = yscale * (double)y[task * N + i];
 }
 
 // ||Phi e_k||^2 = c_k^2 sum over observed samples n of cos^2(pi (2n+1) k / 2D)
@@ -754,7 +776,7 @@ __global__ void k_dct_jacobi(int64_t D, const double* __restrict__ cn, double be
 hipError_t dct_rows_in(const DctDims& dd, const DctBuffers& b, void* X, void* R, void* P, const void* Q, double* xm,
                        double* rm, double* pm, const double* qm, const float* minv, CgScalars* st, int fused,
                        int apply_only, hipStream_t s) {
-  const dim3 grid((unsigned)dd.units, (unsigned)(dd.npairs + 1));
+  const dim3 grid((unsigned)dd.units, (unsigned)(dd.npairs + dd.ntd));
 #define COFEM_ROWS_IN(L)                                                                                         \
   hipLaunchKernelGGL(k_dct_rows_in<L>, grid, dim3(128), 0, s, dd, b, static_cast<float*>(X), static_cast<float*>(R), \
                      static_cast<float*>(P), static_cast<const float*>(Q), xm, rm, pm, qm, minv, st, fused, apply_only)
@@ -768,7 +790,7 @@ static hipError_t launch_mid(const DctDims& dd, const DctBuffers& b, const doubl
   const int N2 = 1 << dd.l2;
 #define COFEM_MID(L)                                                                                     \
   {                                                                                                      \
-    const int nb = (vb ? 0 : dd.npairs * (N2 / MidGeom<L>::GF)) + N2 / MidGeom<L>::GD;                 \
+    const int nb = (vb ? 0 : dd.npairs * (N2 / MidGeom<L>::GF)) + dd.ntd * (N2 / MidGeom<L>::GD);      \
     hipLaunchKernelGGL(k_dct_mid<L>, dim3((unsigned)nb), dim3(256), 0, s, dd, b, vb, st, apply_only); \
   }
   COFEM_DCT_SWITCH(1 << dd.l1, COFEM_MID)
@@ -784,7 +806,7 @@ static hipError_t launch_rows_out(const DctDims& dd, const DctBuffers& b, const 
                                   const double* pm, const double* rm, double* qm, const float* alpha,
                                   const float* minv, double* b0, const ConvReduce& red, CgScalars* st, int fused,
                                   int apply_only, hipStream_t s) {
-  const dim3 grid((unsigned)dd.units, b0 ? 1u : (unsigned)(dd.npairs + 1));
+  const dim3 grid((unsigned)dd.units, b0 ? (unsigned)dd.ntd : (unsigned)(dd.npairs + dd.ntd));
 #define COFEM_ROWS_OUT(L)                                                                                     \
   hipLaunchKernelGGL(k_dct_rows_out<L>, grid, dim3(128), 0, s, dd, b, static_cast<const float*>(P),             \
                      static_cast<const float*>(R), static_cast<float*>(Q), pm, rm, qm, alpha, minv, b0, red, st,   \
@@ -816,11 +838,11 @@ hipError_t dct_setup(const DctDims& dd, const int32_t* rows, int64_t N, const fl
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(mk, 0, (size_t)dd.D, s);
-  if (e == hipSuccess) e = hipMemsetAsync(vb, 0, sizeof(double) * (size_t)dd.D, s);
+  if (e == hipSuccess) e = hipMemsetAsync(vb, 0, sizeof(double) * (size_t)dd.D * dd.nt, s);
   if (e != hipSuccess) return e;
   if (N > 0) {
-    hipLaunchKernelGGL(k_dct_scatter, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, dd.D, dd.l1, dd.l2, rows,
-                       N, y, beta * sqrt(2.0 / (double)dd.D), mk, vb);
+    hipLaunchKernelGGL(k_dct_scatter, dim3((unsigned)((N * dd.nt + 255) / 256)), dim3(256), 0, s, dd.D, dd.l1, dd.l2,
+                       rows, N, dd.nt, y, beta * sqrt(2.0 / (double)dd.D), mk, vb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
