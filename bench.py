@@ -323,9 +323,16 @@ def run_dct(args):
     torch.cuda.set_device(dev)
     t_gen = time.perf_counter()
     p = synth.WORKLOADS[args.workload](0)
+    if args.tasks > 1:
+        # the same dictionary law, beta, K and tolerance with T tasks sharing
+        # alpha (a shared support, independent values per task)
+        p = synth.dct_multitask(p.D, args.tasks, rho=float(np.count_nonzero(p.z)) / p.D, beta=p.beta, K=p.K,
+                                tol=p.tol, max_iter=p.max_iter, T_em=p.T_em, seed=0,
+                                name=f"{p.name}_tasks{args.tasks}")
     T_em = args.em_iters or p.T_em
-    log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} beta={p.beta} tol={p.tol} U={p.max_iter} "
-        f"T_em={T_em} nnz={int(np.count_nonzero(p.z))} (inputs generated in {time.perf_counter() - t_gen:.1f}s)")
+    log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} tasks={p.tasks} beta={p.beta} tol={p.tol} U={p.max_iter} "
+        f"T_em={T_em} nnz={int(np.count_nonzero(p.z)) // p.tasks} "
+        f"(inputs generated in {time.perf_counter() - t_gen:.1f}s)")
     if args.form is None:
         args.form = "control"
     if args.form not in ("fp32", "control"):
@@ -358,6 +365,12 @@ def run_dct(args):
 
     nz = np.linalg.norm(p.z)
 
+    def estimate(c):
+        # every task's mean (T x D), or the one mean (D)
+        if p.tasks > 1:
+            return c.means().cpu().numpy()
+        return c.posterior()[0].cpu().numpy().astype(np.float64)
+
     def time_to_target(c, target=0.02):
         # one EM iteration at a time from alpha = 1, summing the library's
         # per-iteration event times (host NRMSE not counted)
@@ -367,7 +380,7 @@ def run_dct(args):
         for it in range(2 * T_em):
             st = c.em_step(1)[0]
             t_ms += st["ms"]
-            e = float(np.linalg.norm(c.posterior()[0].cpu().numpy().astype(np.float64) - p.z) / nz)
+            e = float(np.linalg.norm(estimate(c) - p.z) / nz)
             trace.append(round(e, 5))
             if e <= target:
                 reached = {"em_iters": it + 1, "ms": round(t_ms, 3)}
@@ -379,6 +392,8 @@ def run_dct(args):
     gp = make("fp32")
     first = gp.em_step(1)[0]
     mu1, s1, a1 = [x.cpu().numpy().astype(np.float64) for x in gp.posterior()]
+    if p.tasks > 1:
+        mu1 = gp.means().cpu().numpy().T
     gp.close()
     for w in range(args.warmup):
         st = one_step(g)
@@ -394,8 +409,7 @@ def run_dct(args):
     cg_counts = [x["cg_iters"] for x in stats]
     mean_cg = float(np.mean(cg_counts))
     value = args.steps * T_em / elapsed
-    mu_T = g.posterior()[0].cpu().numpy().astype(np.float64)
-    nrmse = float(np.linalg.norm(mu_T - p.z) / nz)
+    nrmse = float(np.linalg.norm(estimate(g) - p.z) / nz)
     log(f"{value:.3f} EM it/s; CG iterations per EM iteration: mean {mean_cg:.1f}, min {min(cg_counts)}, "
         f"max {max(cg_counts)}; NRMSE vs ground truth {nrmse:.4f}")
 
@@ -437,9 +451,8 @@ def run_dct(args):
         st2 = one_step(g2)
         torch.cuda.synchronize()
         el2 = time.perf_counter() - t1
-        mu2 = g2.posterior()[0].cpu().numpy().astype(np.float64)
         forms[other] = {"value": round(T_em / el2, 4), "cg_iters_per_em": [x["cg_iters"] for x in st2],
-                        "nrmse_vs_truth": round(float(np.linalg.norm(mu2 - p.z) / nz), 6),
+                        "nrmse_vs_truth": round(float(np.linalg.norm(estimate(g2) - p.z) / nz), 6),
                         "time_to_nrmse": time_to_target(g2)}
         log(f"form {other}: {forms[other]['value']:.3f} EM it/s; CG per EM {forms[other]['cg_iters_per_em']}; "
             f"NRMSE {forms[other]['nrmse_vs_truth']}; time to NRMSE 0.02 {forms[other]['time_to_nrmse']['reached']}")
@@ -453,17 +466,20 @@ def run_dct(args):
             threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count()])
         except Exception:
             threads = os.cpu_count()
+        from oracle import multitask as OM
         op = O.DctMaskOperator(p.rows, p.D)
         n1 = first["cg_iters"]
         tc0 = time.perf_counter()
-        b0 = p.beta * op.apply_t(p.y.astype(np.float64))
-        e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1, fixed_iters=n1)
-        a_ref, _ = O.mstep(e.mu, e.s)
+        b0 = p.beta * op.apply_t(np.asarray(p.y, np.float64).reshape(p.tasks, p.N).T)
+        e = OM.cofem_estep_mt(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1, fixed_iters=n1)
+        a_ref, _ = OM.mstep_mt(e.mu, e.s)
+        if p.tasks == 1:
+            e.mu = e.mu[:, 0]
         t_sample = time.perf_counter() - tc0
         # the first E-step converges in very few iterations; time a few more
         # operator applications for a stable cost per CG iteration
         A = O.cofem_oracle.make_apply_A(op, p.beta, np.ones(p.D))
-        V = np.ones((p.D, p.K + 1))
+        V = np.ones((p.D, p.K + p.tasks))
         reps = 10
         tc1 = time.perf_counter()
         for _ in range(reps):
@@ -472,7 +488,7 @@ def run_dct(args):
         cpu = {"value": round(1.0 / (per_cg * mean_cg), 5), "unit": "EM it/s", "cores": int(threads),
                "kind": "oracle",
                "sample": f"first E-step + M-step of {p.name} ({n1} CG iterations) took {t_sample:.2f}s on the "
-                         f"host; {reps} operator applications on all {p.K + 1} columns took {per_cg * 1e3:.1f} ms "
+                         f"host; {reps} operator applications on all {p.K + p.tasks} columns took {per_cg * 1e3:.1f} ms "
                          f"each; scaled to this form's mean of {mean_cg:.1f} CG iterations per EM iteration"}
 
         def rel(a, b):
@@ -485,8 +501,8 @@ def run_dct(args):
         "metric": METRIC, "value": round(value, 4), "unit": "EM it/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
-                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": FORMS_DCT[args.form],
+        "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "tasks": p.tasks, "beta": p.beta,
+                   "cg_tol": p.tol, "cg_max_iter": p.max_iter, "T_em": T_em, "form": FORMS_DCT[args.form],
                    "cg_iters_per_em_mean": round(mean_cg, 2), "nrmse_vs_truth": round(nrmse, 6)},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "forms": forms,
     }
@@ -503,6 +519,8 @@ def main():
                     choices=["dense_4096x16384", "dense_256x1024", "conv_256x256_k7", "conv_1024x1024_k9",
                              "batched_64", "dct_4096", "dct_262144"])
     ap.add_argument("--em-iters", type=int, default=0, help="EM iterations per step (default: workload's)")
+    ap.add_argument("--tasks", type=int, default=1,
+                    help="DCT workloads: T > 1 tasks sharing alpha (multi-task SBL)")
     ap.add_argument("--timing-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
