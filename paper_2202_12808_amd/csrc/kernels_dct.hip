@@ -465,6 +465,7 @@ __global__ __launch_bounds__(256) void k_dct_mid(DctDims dd, DctBuffers b, const
 }
 
 // ---------------------------------------------------------------- launch 3
+constexpr int kOutUnits = 2;  // row units per workgroup of the output launch
 // Forward row transforms, then per coefficient the operator's output, q = out
 // + alpha p (or b0), and the dot products of the pass.  The state the output
 // needs (p, r, alpha) is loaded before the transform, so its latency overlaps
@@ -475,19 +476,26 @@ __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Ws
                                               T* const* Qc, const float* __restrict__ alpha,
                                               const float* __restrict__ minv, bool b0, bool dots,
                                               unsigned char* smem, double* acc /* [NC * 3] */) {
+  // a workgroup holds kOutUnits row units, two wavefronts each
   const int N1 = 1 << dd.l1;
-  const RowUnit ru = row_unit(blockIdx.x, N1);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int u = blockIdx.x * kOutUnits + (int)(threadIdx.x >> 7);
+  const RowUnit ru = row_unit(u < dd.units ? u : 0, N1);
+  const int w = (threadIdx.x >> 6) & 1, lane = threadIdx.x & 63;
   const int row = w == 0 ? ru.rowA : ru.rowB;
-  const bool active = (w == 0) || !ru.single;
+  const bool active = u < dd.units && ((w == 0) || !ru.single);
+  smem += (threadIdx.x >> 7) * 2 * L2 * sizeof(Cx<T>);
   constexpr int PE = L2 / 64;
   Cx<T>* sz = reinterpret_cast<Cx<T>*>(smem);  // [2][L2]
   Cx<T>* zr = sz + w * L2;
+  // float columns: p, r, alpha and M^-1 loaded before the transform; the
+  // float64 mean columns load them at use (their registers would cut the
+  // launch's occupancy)
+  constexpr bool kPre = sizeof(T) == 4;
   T pv[NC][PE], rv[NC][PE], al[PE], mv[PE];
   if (active) {
 #pragma unroll
     for (int i = 0; i < PE; ++i) zr[lane + 64 * i] = Wslot[(int64_t)row * L2 + lane + 64 * i];
-    if (!b0) {
+    if (kPre && !b0) {
 #pragma unroll
       for (int i = 0; i < PE; ++i) {
         const int64_t pos = (int64_t)row * L2 + lane + 64 * i;
@@ -535,18 +543,21 @@ __device__ __forceinline__ void rows_out_body(const DctDims& dd, const Cx<T>* Ws
         if (sc.valid[cc]) Qc[cc][pos] = out[cc];
       continue;
     }
+    const T ali = kPre ? al[i] : (T)alpha[pos];
+    const T mvi = kPre ? mv[i] : ((dots && minv) ? (T)minv[pos] : T(1));
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
       if (!sc.valid[cc]) continue;
-      const T p = pv[cc][i];
-      const T q = out[cc] + al[i] * p;
+      const T p = kPre ? pv[cc][i] : Pc[cc][pos];
+      const T q = out[cc] + ali * p;
       Qc[cc][pos] = q;
       if (dots) {
         // with a diagonal preconditioner the step's dots are weighted by it:
         // delta = r^T M^-1 q, eta = q^T M^-1 q (mv = 1 without one)
-        const double mq = (double)mv[i] * (double)q;
+        const T r = kPre ? rv[cc][i] : Rc[cc][pos];
+        const double mq = (double)mvi * (double)q;
         acc[cc * 3 + 0] += (double)p * (double)q;
-        acc[cc * 3 + 1] += (double)rv[cc][i] * mq;
+        acc[cc * 3 + 1] += (double)r * mq;
         acc[cc * 3 + 2] += (double)q * mq;
       }
     }
@@ -573,17 +584,17 @@ __device__ __forceinline__ void block_sums(double* v, double (*sh)[N], double* o
 }
 
 // Reduction over the blocks of one column slot: one tree per slot carries all
-// of the slot's columns (nv values each; regions of tree_rows(units) * 2 nv
+// of the slot's columns (nv values each; regions of tree_rows(nblk_alloc) * 2 nv
 // doubles); the block finishing a slot stores its columns' totals in colsum and
 // takes a ticket on cnt_cols; the last of those returns true with every total
 // in out_sh[v * ncols + col].
-__device__ __forceinline__ bool slot_tree_reduce(const ConvReduce& red, int slot, int nslots, int units,
-                                                 const int* cols, const bool* valid, int nc_slot, int ncols, int nv,
-                                                 const double* mine, double* out_sh) {
+__device__ __forceinline__ bool slot_tree_reduce(const ConvReduce& red, int slot, int nslots, int nblk,
+                                                 int64_t nblk_alloc, const int* cols, const bool* valid, int nc_slot,
+                                                 int ncols, int nv, const double* mine, double* out_sh) {
   __shared__ double tslot[10];
-  double* p = red.parts + (int64_t)slot * tree_rows(units) * (2 * nv);
-  uint32_t* c = red.cnts + (int64_t)slot * tree_counters(units) * kCounterStride;
-  if (!tree_reduce(p, c, blockIdx.x, units, nc_slot * nv, mine, tslot)) return false;
+  double* p = red.parts + (int64_t)slot * tree_rows(nblk_alloc) * (2 * nv);
+  uint32_t* c = red.cnts + (int64_t)slot * tree_counters(nblk_alloc) * kCounterStride;
+  if (!tree_reduce(p, c, blockIdx.x, nblk, nc_slot * nv, mine, tslot)) return false;
   if ((int)threadIdx.x < nc_slot * nv) {
     const int cc = threadIdx.x / nv, v = threadIdx.x - (threadIdx.x / nv) * nv;
     if (valid[cc]) store_agent(&red.colsum[cols[cc] * nv + v], tslot[threadIdx.x]);
@@ -599,7 +610,7 @@ __device__ __forceinline__ bool slot_tree_reduce(const ConvReduce& red, int slot
 }
 
 template <int L2>
-__global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, const float* P, const float* R,
+__global__ __launch_bounds__(128 * kOutUnits) void k_dct_rows_out(DctDims dd, DctBuffers b, const float* P, const float* R,
                                                       float* Q, const double* pm, const double* rm, double* qm,
                                                       const float* alpha, const float* minv, double* b0,
                                                       ConvReduce red, CgScalars* st, int fused, int apply_only) {
@@ -607,7 +618,7 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
   const CgCtl ctl = apply_only ? CgCtl{} : load_cg_ctl(st);
   constexpr size_t kF = 2 * L2 * sizeof(Cx<float>);
   constexpr size_t kD = 2 * L2 * sizeof(Cx<double>);
-  __shared__ __align__(16) unsigned char smem[kF > kD ? kF : kD];
+  __shared__ __align__(16) unsigned char smem[kOutUnits * (kF > kD ? kF : kD)];
   // grid rows 0 .. ntd-1: the float64 mean-column pairs (dispatched first);
   // then the float probe pairs.  Reduction slots: float pairs 0 .. npairs-1,
   // mean pairs npairs .. npairs+ntd-1.  b0 mode: the mean pairs only.
@@ -655,7 +666,7 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
                                  Qc, alpha, minv, b0 != nullptr, dots, smem, acc);
   }
   if (!dots) return;
-  __shared__ double sh[2][6], sums[6];
+  __shared__ double sh[2 * kOutUnits][6], sums[6];
   __shared__ double mine[10], tot[5 * kMaxCols];
   block_sums<6>(acc, sh, sums);
   const int nv = fused ? 5 : 3;
@@ -663,10 +674,19 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
     const int c = threadIdx.x;
     double* m = mine + c * nv;
     if (fused) {
-      // the folded update's r^T z and r^T r, from the first launch
+      // the folded update's r^T z and r^T r over this workgroup's row units,
+      // from the first launch
       const int64_t half = (int64_t)(dd.K + dd.nt) * dd.units;
-      m[0] = valid[c] ? b.rr[(int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
-      m[1] = valid[c] ? b.rr[half + (int64_t)cols[c] * dd.units + blockIdx.x] : 0.0;
+      double z2 = 0.0, r2 = 0.0;
+      for (int i = 0; i < kOutUnits; ++i) {
+        const int uu = blockIdx.x * kOutUnits + i;
+        if (valid[c] && uu < dd.units) {
+          z2 += b.rr[(int64_t)cols[c] * dd.units + uu];
+          r2 += b.rr[half + (int64_t)cols[c] * dd.units + uu];
+        }
+      }
+      m[0] = z2;
+      m[1] = r2;
       m[2] = sums[c * 3 + 0];
       m[3] = sums[c * 3 + 1];
       m[4] = sums[c * 3 + 2];
@@ -677,7 +697,8 @@ __global__ __launch_bounds__(128) void k_dct_rows_out(DctDims dd, DctBuffers b, 
     }
   }
   __syncthreads();
-  if (!slot_tree_reduce(red, slot, dd.npairs + dd.ntd, dd.units, cols, valid, 2, dd.K + dd.nt, nv, mine, tot))
+  if (!slot_tree_reduce(red, slot, dd.npairs + dd.ntd, (int)gridDim.x, dd.units, cols, valid, 2, dd.K + dd.nt, nv,
+                        mine, tot))
     return;
   if (fused)
     finish_fused(st, tot, dd.K + dd.nt, ctl);
@@ -806,9 +827,9 @@ static hipError_t launch_rows_out(const DctDims& dd, const DctBuffers& b, const 
                                   const double* pm, const double* rm, double* qm, const float* alpha,
                                   const float* minv, double* b0, const ConvReduce& red, CgScalars* st, int fused,
                                   int apply_only, hipStream_t s) {
-  const dim3 grid((unsigned)dd.units, b0 ? (unsigned)dd.ntd : (unsigned)(dd.npairs + dd.ntd));
+  const dim3 grid((unsigned)((dd.units + kOutUnits - 1) / kOutUnits), b0 ? (unsigned)dd.ntd : (unsigned)(dd.npairs + dd.ntd));
 #define COFEM_ROWS_OUT(L)                                                                                     \
-  hipLaunchKernelGGL(k_dct_rows_out<L>, grid, dim3(128), 0, s, dd, b, static_cast<const float*>(P),             \
+  hipLaunchKernelGGL(k_dct_rows_out<L>, grid, dim3(128 * kOutUnits), 0, s, dd, b, static_cast<const float*>(P),  \
                      static_cast<const float*>(R), static_cast<float*>(Q), pm, rm, qm, alpha, minv, b0, red, st,   \
                      fused, apply_only)
   COFEM_DCT_SWITCH(1 << dd.l2, COFEM_ROWS_OUT)
