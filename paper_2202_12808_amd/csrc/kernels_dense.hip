@@ -94,9 +94,13 @@ hipError_t dense_b0(const void* phi, int kind, int64_t ld, const float* y, doubl
   return hipGetLastError();
 }
 
+// Blocks of 256 threads for the vector kernels: enough that each thread has
+// kVecChunks float4 chunks of the probe block, so the update's loads go out in
+// one round (a second dependent round costs a full memory latency).
+constexpr int kVecChunks = 1;
 int dense_update_blocks(const DenseDims& dd) {
-  const int64_t want = (dd.Dp * 8 + 4 * 256 - 1) / (4 * 256);
-  return (int)(want < 1 ? 1 : (want > 256 ? 256 : want));
+  const int64_t want = (dd.Dp * 8 + kVecChunks * 256 - 1) / (kVecChunks * 256);
+  return (int)(want < 1 ? 1 : (want > 1024 ? 1024 : want));
 }
 
 // ------------------------------------------------ initial residual R = P = B (Eq. 7)
@@ -559,6 +563,14 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
     }
   };
   load2(gtid);
+  // this thread's first element of the float64 mean column, in the same round
+  double m_x = 0.0, m_r = 0.0, m_p = 0.0, m_q = 0.0;
+  if (gtid < Dp) {
+    m_x = xm[gtid];
+    m_r = rm[gtid];
+    m_p = pm[gtid];
+    m_q = qm[gtid];
+  }
   const CgCtl ctl = load_cg_ctl(st);
   const int stop = st->stop;
   const float a = (float)st->a[c], b = (float)st->b[c];
@@ -594,11 +606,16 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
   }
   double accm = 0.0;
   for (int64_t d = gtid; d < Dp; d += gstride) {
-    const double pv = pm[d];
-    xm[d] = fma(am, pv, xm[d]);
-    const double rv = fma(-am, qm[d], rm[d]);
+    if (d != gtid) {
+      m_x = xm[d];
+      m_r = rm[d];
+      m_p = pm[d];
+      m_q = qm[d];
+    }
+    xm[d] = fma(am, m_p, m_x);
+    const double rv = fma(-am, m_q, m_r);
     rm[d] = rv;
-    pm[d] = fma(bmm, pv, rv);
+    pm[d] = fma(bmm, m_p, rv);
     accm += rv * rv;
   }
   __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
