@@ -386,12 +386,20 @@ enum {
 };
 
 /*
- * Measurement support inside the solver itself.  enable != 0 makes every
- * following cofem_em_step record a HIP event on the context's stream before
- * each kernel launch (and one after the last), and resets the totals; 0 turns
- * the recording off.  A launch lasts from its event to the next one, so a
- * duration includes the dispatch gap.  CG launches enqueued after the solve
- * stopped (they return at once) are not counted.
+ * Measurement support inside the solver itself.  enable = n > 0 makes every
+ * following cofem_em_step record HIP events on the context's stream: one
+ * before each launch of every n-th CG iteration (counted over all solves since
+ * this call; n = 1 times them all) and of the set-up, check and M-step
+ * launches, and an end marker after the last launch of each timed stretch.
+ * The totals are reset; 0 turns the recording off, a negative n is
+ * COFEM_ERR_INVALID_ARG.  A launch lasts from its event to the next one, so a
+ * duration includes the dispatch gap.  Each event costs about a microsecond
+ * of stream time: n = 7 keeps the solver within a few percent of its untimed
+ * speed.  Choose n coprime to the polling chunk (8 iterations): the first
+ * launch after a host wait starts on an idle queue and runs a few
+ * microseconds longer, and a period aligned with the chunks would time only
+ * those.  CG launches enqueued after the solve stopped (they return at once)
+ * are not counted.
  */
 cofem_status cofem_set_kernel_timing(cofem_ctx* ctx, int32_t enable);
 

@@ -236,8 +236,9 @@ def cofem_get_ir_sweeps(ctx):
     return [int(counts[i]) for i in range(min(n.value, 256))]
 
 
-def cofem_set_kernel_timing(ctx, enable: bool):
-    _check(load().cofem_set_kernel_timing(ctx, 1 if enable else 0), ctx)
+def cofem_set_kernel_timing(ctx, enable):
+    """enable: False/0 off, True/1 every CG iteration, n > 1 every n-th."""
+    _check(load().cofem_set_kernel_timing(ctx, int(enable)), ctx)
 
 
 def cofem_get_kernel_timing(ctx):

@@ -124,8 +124,11 @@ struct cofem_ctx {
   // outputs of the last E-step / M-step
   float *mu = nullptr, *sdiag = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // optional per-kernel timing: one event before each launch of a solve
+  // optional per-kernel timing: one event before each timed launch, an end
+  // marker after the last; CG iterations timed every kt_every-th
   bool ktime = false;
+  int kt_every = 1;
+  int64_t kt_seq = 0;
   std::vector<hipEvent_t> kev;
   std::vector<int> kev_slot, kev_iter;  // kernel slot and CG iteration of launch i
   size_t kev_used = 0;
@@ -794,6 +797,19 @@ cofem_status mark(cofem_ctx* c, int slot, int iter) {
   return COFEM_OK;
 }
 
+// Closes the open timing interval with an end marker, so that host waits and
+// unsampled launches that follow are not charged to the last timed launch.
+cofem_status close_mark(cofem_ctx* c) {
+  if (!c->ktime || c->kev_used == 0 || c->kev_slot[c->kev_used - 1] < 0) return COFEM_OK;
+  return mark(c, -1, 0);
+}
+
+// Whether the next CG iteration is timed: every kt_every-th over the solver's
+// lifetime (1: all of them).
+bool sampled(cofem_ctx* c) { return c->ktime && (c->kt_seq++ % c->kt_every == 0); }
+
+cofem_status cg_mark(cofem_ctx* c, bool samp, int slot, int iter) { return samp ? mark(c, slot, iter) : COFEM_OK; }
+
 // Adds the recorded launches of a finished EM iteration to the totals.  CG
 // launches enqueued after the solve stopped (they return at once) are not
 // counted: `iters` is the solve's CG count.
@@ -892,28 +908,30 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
 }
 
 cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
+  COFEM_TRY(close_mark(c));
   for (int i = 0; i < n; ++i) {
     const int it = c->cg_enq++;
+    const bool samp = sampled(c);
     if (c->kind == COFEM_DENSE && lowp) {
-      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS1, it));
       COFEM_HIP(c, dense16_pass1(c->dd, c->phiA16, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
                                  c->cnt_split1, c->st, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dense16_pass2(c->dd, c->phiB16, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
                                  c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
                                  c->cnt_split2, c->st, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
     } else if (c->kind == COFEM_DENSE) {
-      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS1, it));
       COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
                                c->cnt_split1, c->st, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dense_pass2(c->dd, c->phiB, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
                                c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
                                c->cnt_split2, c->st, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
                                 c->cnts_upd, c->st, c->stream));
     } else if (c->kind == COFEM_DCT_MASK) {
@@ -921,12 +939,12 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       // direction; each later one folds the previous update into its first
       // launch (state updated in place: no launch reads another row's state)
       const int fused = it > 0 ? 1 : 0;
-      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS1, it));
       COFEM_HIP(c, dct_rows_in(c->xd, c->xb, c->vX, c->vR, c->vP, c->vQ, c->xm, c->rm, c->pm, c->qm,
                                conv_pcg(c) ? c->active_minv : nullptr, c->st, fused, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_PASS2, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 0, c->stream));
-      COFEM_TRY(mark(c, COFEM_KT_UPDATE, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm, c->alpha,
                                 conv_pcg(c) ? c->active_minv : nullptr, c->red_pass, c->st, fused, 0, c->stream));
     } else {
@@ -937,7 +955,7 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       const float* minv = conv_pcg(c) ? c->active_minv : nullptr;
       const ConvState sets[2] = {{c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm},
                                  {c->vP2, c->vR2, c->vQ2, c->pm2, c->rm2, c->qm2}};
-      COFEM_TRY(mark(c, COFEM_KT_PASS1, it));
+      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS1, it));
       if (it == 0)
         COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
                                c->red_pass, c->st, 0, c->stream, minv));
@@ -945,6 +963,8 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
         COFEM_HIP(c, conv_fused(c->cd, c->taps, sets[(it - 1) & 1], sets[it & 1], c->vX, c->xm, c->alpha, c->beta,
                                 minv, c->red_pass, c->st, c->stream));
     }
+    // close a sampled iteration unless the next one is sampled too
+    if (samp && !(i + 1 < n && c->kt_seq % c->kt_every == 0)) COFEM_TRY(close_mark(c));
   }
   return COFEM_OK;
 }
@@ -1481,7 +1501,10 @@ cofem_status cofem_time_operator(cofem_ctx* ctx, int32_t reps, float* ms_out) {
 
 cofem_status cofem_set_kernel_timing(cofem_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (enable < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "kernel timing period must be >= 0");
   ctx->ktime = enable != 0;
+  ctx->kt_every = enable > 0 ? enable : 1;
+  ctx->kt_seq = 0;
   ctx->kev_used = 0;
   for (int i = 0; i < COFEM_KT_SLOTS; ++i) {
     ctx->kt_ms[i] = 0.0;

@@ -510,6 +510,35 @@ def test_runs_are_bit_reproducible(torch_dev, kind):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("form", ["fp32", "bf16_ir"])
+def test_sampled_kernel_timing(torch_dev, form):
+    # timing every n-th CG iteration: about 1/n of the working launches are
+    # timed, their mean duration is of the same size as with every launch
+    # timed, and neither setting changes a bit of the results
+    torch = torch_dev
+    _say("sampled kernel timing", form)
+    p = synth.dense_problem(1000, 3000, nnz=30, beta=1e3, K=32, tol=1e-6, seed=4)
+    kw = {"precision": "bf16_ir", "ir_inner_tol": 0.1} if form == "bf16_ir" else {}
+    runs = []
+    for every in (1, 4):
+        with _dense_ctx(torch, p, **kw) as g:
+            g.set_kernel_timing(every)
+            st = g.em_step(4)
+            kt = g.kernel_timing()
+            runs.append(([x["cg_iters"] for x in st], [x.cpu().numpy() for x in g.posterior()], kt))
+    (c1, post1, kt1), (c4, post4, kt4) = runs
+    assert c1 == c4
+    for a, b in zip(post1, post4):
+        assert np.array_equal(a, b)
+    for slot in ("pass1", "pass2", "update"):
+        n1, n4 = kt1[slot][1], kt4[slot][1]
+        assert n1 >= 20 and n1 / 8 <= n4 <= n1 / 2, (slot, n1, n4)
+        m1, m4 = kt1[slot][0] / n1, kt4[slot][0] / n4
+        assert 0.0 < m4 < 3.0 * m1 and 0.0 < m1 < 3.0 * m4, (slot, m1, m4)
+    for slot in ("init", "mstep"):
+        assert kt4[slot][1] == kt1[slot][1] == 4
+
+
 # ------------------------------------------------------------------ batched form
 def _batch_problems(sizes, seed=0):
     # the batched workload's recipe at small sizes: N_i = D_i / 4, 2% nonzeros,
