@@ -124,6 +124,7 @@ struct cofem_ctx {
   // outputs of the last E-step / M-step
   float *mu = nullptr, *sdiag = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev_state = nullptr;  // completion of the state copy of a poll
   // optional per-kernel timing: one event before each timed launch, an end
   // marker after the last; CG iterations timed every kt_every-th
   bool ktime = false;
@@ -191,6 +192,7 @@ void destroy_ctx(cofem_ctx* c) {
   if (c->host_st) (void)hipHostFree(c->host_st);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev_state) (void)hipEventDestroy(c->ev_state);
   for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
   if (BatchHost* b = c->batch) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1005,6 +1007,23 @@ cofem_status read_state(cofem_ctx* c) {
   return COFEM_OK;
 }
 
+// A poll of a running solve: copies the state as it stands after the
+// iterations enqueued so far, then (if `ahead`) enqueues one more CG iteration
+// before waiting for the copy, so the GPU is not idle while the host reads the
+// flag.  After a stop that iteration returns at once.  Returns the number of
+// iterations it enqueued (0 or 1).
+cofem_status poll_state(cofem_ctx* c, bool ahead, bool lowp, int* extra) {
+  COFEM_HIP(c, hipMemcpyAsync(c->host_st, c->st, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+  COFEM_HIP(c, hipEventRecord(c->ev_state, c->stream));
+  *extra = 0;
+  if (ahead) {
+    COFEM_TRY(run_cg_iterations(c, 1, lowp));
+    *extra = 1;
+  }
+  COFEM_HIP(c, hipEventSynchronize(c->ev_state));
+  return COFEM_OK;
+}
+
 // Mixed-precision E-step (COFEM_PREC_BF16_IR): iterative refinement.  X = 0,
 // R = B; each sweep solves A~ D = R by CG with the bfloat16 Phi to the inner
 // tolerance (relative to ||R||_F), adds D to X, and forms the outer residual
@@ -1048,10 +1067,12 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
     for (;;) {
       if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk, true));
       enqueued += chunk;
-      COFEM_TRY(read_state(c));
+      int extra = 0;
+      COFEM_TRY(poll_state(c, enqueued < limit, true, &extra));
+      enqueued += extra;
       if (c->host_st->stop) break;
       if (enqueued > limit + 2) return fail(c, COFEM_ERR_DEVICE, "inner CG did not report completion");
-      chunk = c->poll;
+      chunk = c->poll - extra;
       if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
     }
     if (c->host_st->numeric_error)
@@ -1131,11 +1152,13 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   for (;;) {
     if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk));
     enqueued += chunk;
-    COFEM_TRY(read_state(c));
+    int extra = 0;
+    COFEM_TRY(poll_state(c, enqueued < limit, false, &extra));
+    enqueued += extra;
     if (c->host_st->stop) break;
     if (enqueued > limit + 2)
       return fail(c, COFEM_ERR_DEVICE, "CG did not report completion after the iteration cap");
-    chunk = c->poll;
+    chunk = c->poll - extra;
     if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
   }
   if (c->host_st->numeric_error)
@@ -1210,6 +1233,7 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_state, hipEventDisableTiming);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->host_st), sizeof(CgScalars));
   if (e != hipSuccess) {
     s = fail(c, COFEM_ERR_DEVICE, std::string("HIP set-up: ") + hipGetErrorString(e));
