@@ -44,7 +44,7 @@ typedef enum cofem_status {
   COFEM_ERR_OUT_OF_MEMORY = 2, /* device allocation failed (nothing leaked) */
   COFEM_ERR_DEVICE = 3,        /* a HIP runtime call failed; message has hipGetErrorString */
   COFEM_ERR_NUMERIC = 4,       /* NaN/Inf reached a CG scalar */
-  COFEM_ERR_UNSUPPORTED = 5    /* a valid request this build does not implement */
+  COFEM_ERR_UNSUPPORTED = 5    /* a valid request the library does not implement */
 } cofem_status;
 
 /* cofem_problem.kind */
@@ -54,8 +54,8 @@ enum { COFEM_F32 = 0, COFEM_BF16 = 1 };
 /* cofem_params.precision:
  *  COFEM_PREC_FP32  probe columns in float32 (float64 reductions), mean column
  *                   in float64;
- *  COFEM_PREC_FP64  every column in float64 (convolution dictionaries only in
- *                   this build) -- for ill-conditioned solves whose float32
+ *  COFEM_PREC_FP64  every column in float64 (convolution dictionaries only)
+ *                   -- for ill-conditioned solves whose float32
  *                   probe iterates drift from a float64 reference;
  *  COFEM_PREC_BF16_IR  mixed-precision form (dense only): each E-step solve
  *                   is an iterative refinement whose inner CG solves use Phi
