@@ -524,10 +524,11 @@ def main():
                     help="DCT workloads: T > 1 tasks sharing alpha (multi-task SBL)")
     ap.add_argument("--timing-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--timing-every", type=int, default=7,
-                    help="time the launches of every n-th CG iteration with HIP events (1: all; each event "
-                         "costs about a microsecond of stream time; 7 is coprime to the solver's 8-iteration "
-                         "polling chunks, so the timed iterations fall evenly on every chunk position)")
+    ap.add_argument("--timing-every", type=int, default=13,
+                    help="time the launches of every n-th CG iteration with HIP events (1: all; each timed "
+                         "iteration's four events cost a few microseconds of stream time; 13 is coprime to the "
+                         "solver's 8-iteration polling chunks, so the timed iterations fall evenly on every "
+                         "chunk position)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="time the steps without the per-launch events (roofline from cofem_time_operator)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,

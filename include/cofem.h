@@ -394,7 +394,7 @@ enum {
  * The totals are reset; 0 turns the recording off, a negative n is
  * COFEM_ERR_INVALID_ARG.  A launch lasts from its event to the next one, so a
  * duration includes the dispatch gap.  Each event costs about a microsecond
- * of stream time: n = 7 keeps the solver within a few percent of its untimed
+ * of stream time: n = 13 keeps the solver within a few percent of its untimed
  * speed.  Choose n coprime to the polling chunk (8 iterations): the first
  * launch after a host wait starts on an idle queue and runs a few
  * microseconds longer, and a period aligned with the chunks would time only
