@@ -537,6 +537,10 @@ def test_sampled_kernel_timing(torch_dev, form):
         assert 0.0 < m4 < 3.0 * m1 and 0.0 < m1 < 3.0 * m4, (slot, m1, m4)
     for slot in ("init", "mstep"):
         assert kt4[slot][1] == kt1[slot][1] == 4
+    from paper_2202_12808_amd.cofem import CofemError
+    with _dense_ctx(torch, p, **kw) as g:
+        with pytest.raises(CofemError):
+            g.set_kernel_timing(-1)
 
 
 # ------------------------------------------------------------------ batched form
