@@ -17,8 +17,9 @@ NMSE against both.  `--workload batched_64` runs the 64-problem batched form.
 Besides the throughput line the JSON carries:
   roofline      the dominant operator kernel against its roofline: dense
                 passes by HBM (algorithmic bytes per launch / mean launch
-                time, from HIP events the library records on its stream before
-                every launch during the timed steps) against 8 TB/s, with the
+                time, from HIP events the library records on its stream around
+                the launches of every n-th CG iteration during the timed steps,
+                --timing-every n) against 8 TB/s, with the
                 counter-measured HBM bytes per launch when a stored rocprofv3
                 summary matches the current kernel source; the conv stencil
                 pass by the fp32 vector ALU (its stencil flops per launch /
