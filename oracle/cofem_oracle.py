@@ -363,8 +363,8 @@ class IRInfo:
 
 
 def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
-             max_iter: int, max_sweeps: int, fixed_inner=None):
-    """Iterative refinement: X = 0, R = B; while ||R||_F/||B||_F >= tol (and
+             max_iter: int, max_sweeps: int, fixed_inner=None, X0: Optional[np.ndarray] = None):
+    """Iterative refinement: X = X0 (or 0), R = B - A X; while ||R||_F/||B||_F >= tol (and
     fewer than ``max_iter`` inner iterations and ``max_sweeps`` sweeps so far,
     and fewer than IR_STALL sweeps in a row failed to halve the best ratio --
     the true residual of refinement need not fall monotonically, and once it
@@ -373,8 +373,12 @@ def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
     With ``fixed_inner`` (a list of counts) exactly those sweeps run, each for
     exactly its count."""
     B = np.asarray(B, dtype=np.float64)
-    X = np.zeros_like(B)
-    R = B.copy()
+    if X0 is None:
+        X = np.zeros_like(B)
+        R = B.copy()
+    else:
+        X = np.array(X0, dtype=np.float64).reshape(B.shape)
+        R = B - apply_A(X)
     nB = float(np.linalg.norm(B))
     sweeps, hist = [], []
     total = 0
@@ -455,15 +459,24 @@ def cofem_estep(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
 
 def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
                    tol: float, tol_in: float, max_iter: int, max_sweeps: int, seed: int, t: int,
-                   fixed_inner=None):
+                   fixed_inner=None, mu0=None, d0=None):
     """The E-step of Algorithm 1 with the solve done by ``ir_solve``: outer
     residual with ``op`` (the problem's Phi), inner corrections with
-    ``op_inner`` (a lower-precision Phi).  Returns (EStepResult, IRInfo)."""
+    ``op_inner`` (a lower-precision Phi).  With mu0 / d0 the refinement starts
+    from X0 = [d0 (.) p_1 .. d0 (.) p_K | mu0] (the warm start of
+    ``cofem_estep_pcg``; None entries zero).  Returns (EStepResult, IRInfo)."""
     D = op.D
     P = rademacher_probes(seed, t, K, D)
     B = np.concatenate([P, np.asarray(b0, np.float64)[:, None]], axis=1)
+    X0 = None
+    if mu0 is not None or d0 is not None:
+        X0 = np.zeros_like(B)
+        if d0 is not None:
+            X0[:, :K] = np.asarray(d0, np.float64)[:, None] * P
+        if mu0 is not None:
+            X0[:, K] = np.asarray(mu0, np.float64)
     X, info = ir_solve(make_apply_A(op, beta, alpha), make_apply_A(op_inner, beta, alpha), B, tol,
-                       tol_in, max_iter, max_sweeps, fixed_inner)
+                       tol_in, max_iter, max_sweeps, fixed_inner, X0)
     mu = X[:, K].copy()
     s = diag_estimate(P, X[:, :K])
     cg = CGInfo(info.iters, info.converged, info.rel_resid, info.history)

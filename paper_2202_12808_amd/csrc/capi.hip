@@ -722,9 +722,12 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
     return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
   if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
-  if ((q->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI)) &&
-      (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
-    return *why = "warm starts and the Jacobi preconditioner are built for convolution and DCT dictionaries",
+  if ((q->flags & COFEM_FLAG_JACOBI) && (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
+    return *why = "the Jacobi preconditioner is built for convolution and DCT dictionaries", COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & COFEM_FLAG_WARM_PREV) &&
+      (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK &&
+                  !(p->kind == COFEM_DENSE && q->precision == COFEM_PREC_BF16_IR))))
+    return *why = "warm starts are built for convolution and DCT dictionaries and the dense COFEM_PREC_BF16_IR form",
            COFEM_ERR_UNSUPPORTED;
   for (int32_t i = 0; i < n; ++i)
     if (p[i].n_tasks > 1 && (n != 1 || p[i].kind != COFEM_DCT_MASK))
@@ -1041,10 +1044,27 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
   COFEM_HIP(c, dense_init(dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->parts_init,
                           c->cnts_init, c->st, c->stream));
-  COFEM_HIP(c, fill_f32(c->Xt, 0.0f, dd.Dp * kDenseKP, c->stream));
-  COFEM_HIP(c, hipMemsetAsync(c->xtm, 0, sizeof(double) * dd.Dp, c->stream));
+  const bool warm = (c->flags & COFEM_FLAG_WARM_PREV) && c->has_solution;
+  if (warm) {
+    // X0 = [max(s_prev, 0) (.) p_k | mu_prev] (Xt still holds the previous
+    // mean), then the first outer residual R = B - A X0 with the float32 Phi,
+    // which also sets up the first inner solve
+    COFEM_HIP(c, dense_warm_start(dd, c->seed, t, c->K, c->sdiag, c->Xt, c->stream));
+    COFEM_HIP(c, dense_pass1(dd, c->phiA, c->Xt, c->xtm, c->Wpart, c->wmpart, c->W, c->wm, c->cnt_split1, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_pass2(dd, c->phiB, c->W, c->wm, c->Xt, c->xtm, c->R, c->rm, c->alpha, c->beta, c->Qpart,
+                             c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_ir_residual(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->X, c->R, c->P, c->xm, c->rm, c->pm,
+                                   c->parts_upd, c->cnts_upd, c->st, c->U, c->stream));
+  } else {
+    COFEM_HIP(c, fill_f32(c->Xt, 0.0f, dd.Dp * kDenseKP, c->stream));
+    COFEM_HIP(c, hipMemsetAsync(c->xtm, 0, sizeof(double) * dd.Dp, c->stream));
+  }
   COFEM_TRY(read_state(c));
-  double outer = c->host_st->nB0 > 0.0 ? 1.0 : 0.0, best = outer;
+  if (warm && c->host_st->numeric_error)
+    return fail(c, COFEM_ERR_NUMERIC, "non-finite warm-start residual at EM iteration " + std::to_string(t));
+  double outer = warm ? c->host_st->true_ratio : (c->host_st->nB0 > 0.0 ? 1.0 : 0.0), best = outer;
   int total = 0, stall = 0;
   for (;;) {
     // The true residual of refinement need not fall monotonically.  Stop at the

@@ -544,6 +544,9 @@ hipError_t dense16_pass2(const DenseDims& dd, const void* phiB16, const float* W
                          const float* P, const double* pm, const float* R, const double* rm, const float* alpha,
                          double beta, float* Qpart, double* qmpart, float* Q, double* qm, double* gpart,
                          uint32_t* counter, uint32_t* split_cnts, CgScalars* st, int apply_only, hipStream_t s);
+// Xt's probe columns <- max(s_prev, 0) (.) p_k (EM iteration t); the mean column is kept
+hipError_t dense_warm_start(const DenseDims& dd, uint64_t seed, int t, int K, const float* sprev, float* Xt,
+                            hipStream_t s);
 hipError_t dense_ir_accumulate(const DenseDims& dd, float* Xt, const float* Xi, double* xtm, const double* xim,
                                hipStream_t s);
 hipError_t dense_ir_residual(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0, const float* Q,

@@ -469,6 +469,35 @@ hipError_t dense16_pass2(const DenseDims& dd, const void* phiB16, const float* W
 }
 
 // ------------------------------------------------ iterative refinement glue
+// Warm start of a refinement: the probe columns of Xt become
+// max(s_prev, 0) (.) p_k for the probes of EM iteration t (x_k ~ Sigma p_k from
+// the previous diagonal estimate); the float64 mean column keeps the previous
+// E-step's mean, which Xt still holds.
+__global__ __launch_bounds__(256) void k_dense_warm_start(int64_t D, int64_t Dp, uint64_t seed, int t, int K,
+                                                          const float* __restrict__ sprev, float* __restrict__ Xt) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e4 = gtid; e4 < Dp * 8; e4 += gstride) {
+    const int c = (int)(e4 & 31);
+    const int64_t d0 = (e4 >> 5) * 4;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t d = d0 + i;
+      v[i] = (d < D && c < K) ? fmaxf(sprev[d], 0.0f) * probe_sign(seed, (uint32_t)t, (uint32_t)c, (uint64_t)d)
+                              : 0.0f;
+    }
+    reinterpret_cast<float4*>(Xt)[e4] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+hipError_t dense_warm_start(const DenseDims& dd, uint64_t seed, int t, int K, const float* sprev, float* Xt,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_warm_start, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed, t, K,
+                     sprev, Xt);
+  return hipGetLastError();
+}
+
 // Xt += Xi over the blocked-4 probe block and the float64 mean column.
 __global__ __launch_bounds__(256) void k_dense_ir_accumulate(int64_t Dp, float* __restrict__ Xt,
                                                              const float* __restrict__ Xi,

@@ -118,3 +118,44 @@ def test_ir_stops_after_three_stalled_sweeps():
         else:
             stall += 1
     assert stall == 3 and len(info.sweeps) == 3
+
+
+def test_ir_warm_start_pins():
+    # X0 = 0 is the cold start; X0 = the exact solution needs no sweep; any
+    # other X0 converges to the same solution (the refinement corrects X0)
+    rng = np.random.default_rng(21)
+    N, D = 30, 50
+    phi = rng.standard_normal((N, D)) / np.sqrt(N)
+    alpha = rng.uniform(0.5, 4.0, D)
+    A = lambda X: 20.0 * phi.T @ (phi @ X) + alpha[:, None] * X
+    B = rng.standard_normal((D, 3))
+    X_ex = np.linalg.solve(20.0 * phi.T @ phi + np.diag(alpha), B)
+    cold, ic = O.ir_solve(A, A, B, 1e-10, 1e-2, 400, 20)
+    zero, iz = O.ir_solve(A, A, B, 1e-10, 1e-2, 400, 20, X0=np.zeros_like(B))
+    assert np.array_equal(cold, zero) and ic.sweeps == iz.sweeps
+    ex, ie = O.ir_solve(A, A, B, 1e-10, 1e-2, 400, 20, X0=X_ex)
+    assert ie.sweeps == [] and np.array_equal(ex, X_ex)
+    X0 = X_ex * (1.0 + 1e-3 * rng.standard_normal(B.shape))
+    w, iw = O.ir_solve(A, A, B, 1e-10, 1e-2, 400, 20, X0=X0)
+    assert iw.converged and np.allclose(w, X_ex, rtol=1e-8, atol=1e-10)
+    # a start near the solution saves sweeps against the cold start
+    assert len(iw.sweeps) < len(ic.sweeps)
+
+
+def test_estep_ir_warm_start_matches_pcg_warm_start():
+    # the same X0 = [d0 (.) p_k | mu0] in the refinement and in PCG; with the
+    # problem's own Phi as the inner operator both solve to the same X
+    rng = np.random.default_rng(22)
+    N, D, K = 24, 40, 4
+    phi = rng.standard_normal((N, D)) / np.sqrt(N)
+    op = O.DenseOperator(phi)
+    y = rng.standard_normal(N)
+    alpha = rng.uniform(0.5, 4.0, D)
+    b0 = 10.0 * op.apply_t(y)
+    mu0 = rng.standard_normal(D)
+    d0 = rng.uniform(0.0, 0.2, D)
+    e_ir, info = O.cofem_estep_ir(op, op, b0, 10.0, alpha, K, 1e-11, 1e-3, 400, 20, seed=5, t=3, mu0=mu0, d0=d0)
+    e_pcg = O.cofem_estep_pcg(op, b0, 10.0, alpha, K, 1e-11, 400, seed=5, t=3, mu0=mu0, d0=d0)
+    assert info.converged
+    assert np.allclose(e_ir.X, e_pcg.X, rtol=1e-8, atol=1e-10)
+
