@@ -537,6 +537,9 @@ def main():
     ap.add_argument("--form", default=None, choices=sorted(FORMS),
                     help="solver form timed for the headline value (default: bf16_ir for dense workloads, "
                          "fp32 for conv)")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="bf16_ir: start every E-step's refinement from zero instead of the previous mean and "
+                         "diagonal estimate")
     ap.add_argument("--ir-inner-tol", type=float, default=0.0,
                     help="bf16_ir: relative tolerance of each inner solve (0: the library default, 0.1)")
     ap.add_argument("--oracle-trajectory", action="store_true",
@@ -588,7 +591,7 @@ def main():
     def make(form):
         if p.kind == "dense":
             return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, precision=form,
-                               ir_inner_tol=args.ir_inner_tol)
+                               ir_inner_tol=args.ir_inner_tol, warm_start=(form == "bf16_ir" and not args.no_warm))
         taps = torch.from_numpy(p.taps).to(dev)
         ctl = form == "control"
         c = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, jacobi=ctl,
@@ -831,7 +834,9 @@ def main():
         "dtype": "bf16+f32" if args.form == "bf16_ir" else "f32",
         "data": "synthetic",
         "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
-                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": FORMS[args.form],
+                   "cg_max_iter": p.max_iter, "T_em": T_em,
+                   "form": FORMS[args.form] + (", each E-step warm-started from the previous mean and diagonal "
+                                               "estimate" if args.form == "bf16_ir" and not args.no_warm else ""),
                    "cg_iters_per_em_mean": round(mean_cg, 2), "nrmse_vs_truth": round(nrmse, 6)},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -80,11 +80,13 @@ enum {
   COFEM_FLAG_EAGER = 2,
   /* Use the batched form (bfloat16 dictionaries) even for n_problems == 1. */
   COFEM_FLAG_BATCHED = 4,
-  /* Convolution dictionaries, from the second E-step on: start each solve
-   * from X0 = [max(s_prev, 0) (.) p_k | mu_prev], the previous E-step's
-   * diagonal estimate and mean (not in the paper: a warm start). */
+  /* Convolution and DCT dictionaries, and dense ones under
+   * COFEM_PREC_BF16_IR, from the second E-step on: start each solve from
+   * X0 = [max(s_prev, 0) (.) p_k | mu_prev], the previous E-step's diagonal
+   * estimate and mean (not in the paper: a warm start).  The mixed-precision
+   * form starts its refinement there: the first outer residual is B - A X0. */
   COFEM_FLAG_WARM_PREV = 8,
-  /* Convolution dictionaries: diagonal (Jacobi) preconditioner
+  /* Convolution and DCT dictionaries: diagonal (Jacobi) preconditioner
    * M^-1 = 1 / (beta ||h||^2 + alpha), the inverse diagonal of A.  The stop
    * test stays the unpreconditioned one of Sec. 3.2. */
   COFEM_FLAG_JACOBI = 16
