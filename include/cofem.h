@@ -66,8 +66,19 @@ enum { COFEM_F32 = 0, COFEM_BF16 = 1 };
  *                   total).  Not in the paper: a precision form layered on
  *                   the solve of Sec. 3.2. */
 enum { COFEM_PREC_FP32 = 0, COFEM_PREC_BF16_IR = 1, COFEM_PREC_FP64 = 2 };
-/* cofem_params.stop_rule */
-enum { COFEM_STOP_FROBENIUS = 0 };
+/* cofem_params.stop_rule (the stop test of the CG solve, Sec. 3.2):
+ *  COFEM_STOP_FROBENIUS   the paper's joint test ||R||_F / ||B||_F < cg_tol on
+ *                         the recursively updated residual; every column runs
+ *                         the same number of iterations;
+ *  COFEM_STOP_PER_COLUMN  column c is finished once ||r_c|| < cg_tol ||b_c||
+ *                         (a zero column at once) and takes no further step
+ *                         (x_c, r_c frozen); the solve ends when every column
+ *                         is finished or at the cap.  Each column then meets
+ *                         its own relative tolerance (the mean column b0 is
+ *                         ~40..700 times larger than a probe column, so under
+ *                         the joint test the probes end less accurate).  Not
+ *                         with COFEM_PREC_BF16_IR. */
+enum { COFEM_STOP_FROBENIUS = 0, COFEM_STOP_PER_COLUMN = 1 };
 
 /* cofem_params.flags */
 enum {
@@ -178,17 +189,31 @@ typedef struct cofem_iter_stats {
   double rel_resid_true; /* ||B - A X||_F / ||B||_F at exit, float64 sums
                             (COFEM_FLAG_TRUE_RESIDUAL or COFEM_PREC_BF16_IR), else -1 */
   int32_t ir_sweeps;     /* refinement sweeps (COFEM_PREC_BF16_IR), else 0 */
+  double gamma_change;   /* relative change of the prior variances over this
+                            M-step, ||1/alpha_new - 1/alpha_old||_2 / ||1/alpha_new||_2
+                            (float64 sums; the EM stop test of cofem_em_run) */
 } cofem_iter_stats;
 
 typedef struct cofem_ctx cofem_ctx;
 
 /*
  * Creates a context for `n_problems` problems with alpha = 1 (Algorithm 1,
- * first line) and the next EM iteration t = 1.  Allocates device memory for
- * the packed dictionary and the CG state (dense: 2 packed float32 copies of
- * Phi plus 4 D x 32 float32 blocks; conv: 5 (K) x D float32 blocks),
- * computes beta Phi^T y, and synchronises `hip_stream` before returning.
- * *out receives the context.
+ * first line) and the next EM iteration t = 1, computes beta Phi^T y, and
+ * synchronises `hip_stream` before returning.  *out receives the context.
+ *
+ * Device memory (the packed dictionary and the CG state; dense: 2 packed
+ * float32 copies of Phi plus D x 32 float32 blocks; conv: (K) x D float32
+ * blocks) comes from one of two places:
+ *  - workspace == NULL (workspace_bytes 0): the library allocates it with
+ *    hipMalloc and frees it in cofem_destroy;
+ *  - workspace != NULL: device memory of workspace_bytes >= the size
+ *    cofem_workspace_size reports for the same problems and params, 256-byte
+ *    aligned, owned by the caller (e.g. a torch tensor): the context lays its
+ *    buffers out in it, allocates no device memory of its own and must be
+ *    destroyed before the workspace is freed.  A smaller workspace is
+ *    COFEM_ERR_OUT_OF_MEMORY, a misaligned one COFEM_ERR_INVALID_ARG.  The
+ *    results are the same bits as with library-allocated memory.
+ * (Host-side, the context still takes a few pinned bytes and HIP events.)
  *
  * Batched form (n_problems > 1, phi_dtype == COFEM_BF16, or
  * COFEM_FLAG_BATCHED): independent
@@ -202,7 +227,17 @@ typedef struct cofem_ctx cofem_ctx;
  * COFEM_PREC_FP32 and no COFEM_FLAG_TRUE_RESIDUAL.
  */
 cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems,
-                        const cofem_params* params, void* hip_stream, cofem_ctx** out);
+                        const cofem_params* params, void* hip_stream, void* workspace,
+                        size_t workspace_bytes, cofem_ctx** out);
+
+/*
+ * The device memory cofem_init needs for these problems and params, in bytes
+ * (*bytes, host), so that a caller can provide it as the workspace.  Validates
+ * the arguments as cofem_init does; touches no device and reads no device
+ * pointer.
+ */
+cofem_status cofem_workspace_size(const cofem_problem* problems, int32_t n_problems,
+                                  const cofem_params* params, size_t* bytes);
 
 /*
  * Runs `n_iters` EM iterations of Algorithm 1 (E-step by CG, diagonal
@@ -212,6 +247,19 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems,
  * (entry it * n_problems + i for problem i).
  */
 cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats);
+
+/*
+ * Runs EM iterations of Algorithm 1 as cofem_em_step does, but ends early after
+ * the first M-step whose gamma_change (the relative change of 1/alpha, see
+ * cofem_iter_stats) falls below em_tol: an EM-level stopping rule (the paper
+ * runs a fixed T_em; Sec. 4.2 times CoFEM to a target accuracy instead).  At
+ * most max_iters iterations; em_tol <= 0 never stops early.  A batched context
+ * stops when every problem's change is below em_tol.  stats (host, nullable)
+ * receives up to max_iters entries (times n_problems for a batched context),
+ * *n_done (host, nullable) the number of EM iterations run.
+ */
+cofem_status cofem_em_run(cofem_ctx* ctx, int32_t max_iters, double em_tol, cofem_iter_stats* stats,
+                          int32_t* n_done);
 
 /*
  * Copies Algorithm 1's return triple for problem `problem`: mu and s of the
@@ -230,8 +278,19 @@ cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha
  * single-task context (then mu is cofem_get_solution's mean column). */
 cofem_status cofem_get_means(cofem_ctx* ctx, int32_t problem, double* mu);
 
-/* Sets the EM iteration index t (>= 0, < 65536) whose probes the next E-step draws. */
+/* Sets the EM iteration index t (>= 0, < 65536) whose probes the next E-step
+ * draws.  The last E-step then no longer precedes the next one, so the
+ * previous mean and diagonal estimate are forgotten: the next solve starts
+ * from X = 0 (the warm, learned and mixed-precision warm starts resume from
+ * the E-step after it). */
 cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t);
+
+/* Restarts Algorithm 1 from its first line on the same problem: alpha = 1 for
+ * every problem, mu = s = 0, t = 1, and no previous solution (the next solve
+ * starts from X = 0, exactly as the first E-step of a new context does).
+ * Enqueued on the context's stream.  A failed cofem_em_step forgets the
+ * previous solution the same way (its iterates may be non-finite). */
+cofem_status cofem_restart(cofem_ctx* ctx);
 
 /* n > 0: every CG solve runs exactly n iterations, ignoring cg_tol (the cap is
  * raised to n); n == 0 restores the stop test.  For step-by-step comparisons.

@@ -8,6 +8,7 @@ HIP package: the two share no code, table or constant generator.
 from .cofem_oracle import (  # noqa: F401
     ALPHA_MAX_DEFAULT,
     ConvOperator,
+    ConvOperatorFFT,
     DctMaskOperator,
     DenseOperator,
     cg_solve,
@@ -19,9 +20,11 @@ from .cofem_oracle import (  # noqa: F401
     diag_estimate_ratio,
     exact_estep,
     exact_em,
+    gamma_change,
     ir_solve,
     loglik,
     loglik_direct,
+    make_apply_A,
     mstep,
     pcg_solve,
     rademacher_probes,

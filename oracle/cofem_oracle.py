@@ -161,6 +161,60 @@ class ConvOperator:
         return np.full(self.D, float(np.sum(self.taps * self.taps)))
 
 
+class ConvOperatorFFT:
+    """The circular convolution dictionary of ``ConvOperator`` applied through
+    the convolution theorem: with the taps placed on the H x W grid so that
+    tap (ch, cw) sits at the origin, Phi is multiplication of the 2D DFT by
+    the kernel's DFT h_hat, Phi^T by conj(h_hat), and Phi^T Phi (the only
+    product CG needs, Sec. 3.2) by |h_hat|^2 -- one forward and one inverse
+    real transform per column instead of two k x k stencils.  scipy.fft does
+    the transforms (a library FFT used as a step), over the host's threads.
+    """
+
+    def __init__(self, taps: np.ndarray, H: int, W: int):
+        import scipy.fft as sf
+
+        self.taps = np.asarray(taps, dtype=np.float64)
+        kh, kw = self.taps.shape
+        if kh % 2 == 0 or kw % 2 == 0:
+            raise ValueError("kernel sides must be odd")
+        self.H, self.W = int(H), int(W)
+        self.N = self.D = self.H * self.W
+        ch, cw = (kh - 1) // 2, (kw - 1) // 2
+        kern = np.zeros((self.H, self.W))
+        for a in range(kh):
+            for b in range(kw):
+                kern[(a - ch) % self.H, (b - cw) % self.W] += self.taps[a, b]
+        self.h_hat = sf.rfft2(kern)
+        self.gram_hat = (self.h_hat * np.conj(self.h_hat)).real
+        import os
+        self.workers = max(1, min(16, os.cpu_count() or 1))
+
+    def _filter(self, v, spec):
+        import scipy.fft as sf
+
+        v = np.asarray(v, dtype=np.float64)
+        one = v.ndim == 1
+        img = v.reshape(self.H, self.W, -1)
+        f = sf.rfft2(img, axes=(0, 1), workers=self.workers)
+        f *= spec[:, :, None]
+        out = sf.irfft2(f, s=(self.H, self.W), axes=(0, 1), workers=self.workers).reshape(self.D, -1)
+        return out[:, 0] if one else out
+
+    def apply(self, v: np.ndarray) -> np.ndarray:
+        return self._filter(v, self.h_hat)
+
+    def apply_t(self, w: np.ndarray) -> np.ndarray:
+        return self._filter(w, np.conj(self.h_hat))
+
+    def gram(self, v: np.ndarray) -> np.ndarray:
+        """Phi^T Phi v."""
+        return self._filter(v, self.gram_hat)
+
+    def column_norms_sq(self) -> np.ndarray:
+        return np.full(self.D, float(np.sum(self.taps ** 2)))
+
+
 class DctMaskOperator:
     """Inverse DCT followed by an undersampling mask (the structured dictionary
     of Sec. 4, "Structured Dictionary"): Phi = S C^T in R^{N x D}.
@@ -230,10 +284,13 @@ def make_apply_A(op, beta: float, alpha: np.ndarray) -> Callable[[np.ndarray], n
     """v -> A v with A = beta*Phi^T*Phi + diag(alpha) (Eq. 5, Eq. 7)."""
     alpha = np.asarray(alpha, dtype=np.float64)
 
+    gram = getattr(op, "gram", None)
+
     def apply_A(V):
         V = np.asarray(V, dtype=np.float64)
         av = alpha[:, None] * V if V.ndim == 2 else alpha * V
-        return beta * op.apply_t(op.apply(V)) + av
+        g = gram(V) if gram is not None else op.apply_t(op.apply(V))
+        return beta * g + av
 
     return apply_A
 
@@ -251,23 +308,30 @@ class CGInfo:
 
 
 def cg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int,
-             fixed_iters: Optional[int] = None):
+             fixed_iters: Optional[int] = None, stop_rule: str = "frobenius"):
     """Solve A X = B column by column with plain CG from X0 = 0.
 
     Column c keeps its own step a_c = rho_c / (p_c^T A p_c) and direction update
-    b_c = rho'_c / rho_c.  The whole block stops once
-    sqrt(sum_c rho_c) / ||B||_F < tol (rho_c = ||r_c||^2, recursive residual) or
-    after ``max_iter`` iterations.  With ``fixed_iters`` set, exactly that many
-    iterations run and the tolerance is ignored.  A column whose rho or
-    p^T A p is exactly zero takes a zero step.
+    b_c = rho'_c / rho_c.  With the default stop rule the whole block stops
+    once sqrt(sum_c rho_c) / ||B||_F < tol (rho_c = ||r_c||^2, recursive
+    residual) or after ``max_iter`` iterations.  With ``stop_rule =
+    "per_column"`` column c is finished once ||r_c|| / ||b_c|| < tol (a zero
+    column from the start): it takes no further step (a_c = 0, its x_c and r_c
+    stay as they are, its direction is reset to r_c), and the block stops when
+    every column is finished or at the cap.  With ``fixed_iters`` set, exactly
+    that many iterations run and the tolerance is ignored.  A column whose rho
+    or p^T A p is exactly zero takes a zero step.
     """
+    per_col = _check_stop_rule(stop_rule)
     B = np.asarray(B, dtype=np.float64)
     X = np.zeros_like(B)
     R = B.copy()
     P = R.copy()
     rho = np.einsum("dc,dc->c", R, R)
+    bb = rho.copy()
     nB = math.sqrt(float(rho.sum()))
     hist = []
+    done = np.zeros(B.shape[1], dtype=bool)
     if nB == 0.0:
         return X, CGInfo(0, True, 0.0, hist)
     limit = fixed_iters if fixed_iters is not None else max_iter
@@ -275,24 +339,41 @@ def cg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int,
     while it < limit:
         ratio = math.sqrt(float(rho.sum())) / nB
         hist.append(ratio)
-        if fixed_iters is None and ratio < tol:
-            break
+        if fixed_iters is None:
+            if per_col:
+                done |= (bb == 0.0) | (np.sqrt(rho) < tol * np.sqrt(bb))
+                if done.all():
+                    break
+            elif ratio < tol:
+                break
         Q = apply_A(P)
         gam = np.einsum("dc,dc->c", P, Q)
         a = np.divide(rho, gam, out=np.zeros_like(rho), where=gam != 0.0)
+        a[done] = 0.0
         X += a * P
         R -= a * Q
         rho_new = np.einsum("dc,dc->c", R, R)
         b = np.divide(rho_new, rho, out=np.zeros_like(rho), where=rho != 0.0)
+        b[done] = 0.0
         P = R + b * P
         rho = rho_new
         it += 1
     ratio = math.sqrt(float(rho.sum())) / nB
+    if per_col and fixed_iters is None:
+        done |= (bb == 0.0) | (np.sqrt(rho) < tol * np.sqrt(bb))
+        return X, CGInfo(it, bool(done.all()), ratio, hist)
     return X, CGInfo(it, ratio < tol, ratio, hist)
 
 
+def _check_stop_rule(stop_rule: str) -> bool:
+    if stop_rule not in ("frobenius", "per_column"):
+        raise ValueError(f"unknown stop rule {stop_rule!r}")
+    return stop_rule == "per_column"
+
+
 def pcg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int, minv: Optional[np.ndarray] = None,
-              X0: Optional[np.ndarray] = None, fixed_iters: Optional[int] = None):
+              X0: Optional[np.ndarray] = None, fixed_iters: Optional[int] = None,
+              stop_rule: str = "frobenius"):
     """Preconditioned CG from a starting block (not in the paper: the learned
     and warm-started forms).  M^-1 = diag(minv) (a length-D positive vector,
     the same for every column; None is the identity), X0 the starting block
@@ -301,7 +382,9 @@ def pcg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int, minv: Optional[
     z = M^-1 r, rho' = r^T z, p = z + (rho'/rho) p.  The stop test is the
     solve's own (Sec. 3.2): sqrt(sum_c ||r_c||^2) / ||B||_F < tol on the
     recursively updated (unpreconditioned) residual, checked before every
-    iteration, or the cap."""
+    iteration, or the cap; with ``stop_rule = "per_column"`` each column
+    stops on its own ||r_c|| / ||b_c|| < tol as in ``cg_solve``."""
+    per_col = _check_stop_rule(stop_rule)
     B = np.asarray(B, dtype=np.float64)
     X = np.zeros_like(B) if X0 is None else np.asarray(X0, dtype=np.float64).copy()
     m = np.ones(B.shape[0]) if minv is None else np.asarray(minv, dtype=np.float64)
@@ -309,8 +392,10 @@ def pcg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int, minv: Optional[
     Z = m[:, None] * R
     P = Z.copy()
     rho = np.einsum("dc,dc->c", R, Z)
+    bb = np.einsum("dc,dc->c", B, B)
     nB = float(np.linalg.norm(B))
     hist = []
+    done = np.zeros(B.shape[1], dtype=bool)
     if nB == 0.0:
         return X, CGInfo(0, True, 0.0, hist)
     limit = fixed_iters if fixed_iters is not None else max_iter
@@ -318,20 +403,30 @@ def pcg_solve(apply_A, B: np.ndarray, tol: float, max_iter: int, minv: Optional[
     while it < limit:
         ratio = float(np.linalg.norm(R)) / nB
         hist.append(ratio)
-        if fixed_iters is None and ratio < tol:
-            break
+        if fixed_iters is None:
+            if per_col:
+                done |= (bb == 0.0) | (np.sqrt(np.einsum("dc,dc->c", R, R)) < tol * np.sqrt(bb))
+                if done.all():
+                    break
+            elif ratio < tol:
+                break
         Q = apply_A(P)
         gam = np.einsum("dc,dc->c", P, Q)
         a = np.divide(rho, gam, out=np.zeros_like(rho), where=gam != 0.0)
+        a[done] = 0.0
         X += a * P
         R -= a * Q
         Z = m[:, None] * R
         rho_new = np.einsum("dc,dc->c", R, Z)
         b = np.divide(rho_new, rho, out=np.zeros_like(rho), where=rho != 0.0)
+        b[done] = 0.0
         P = Z + b * P
         rho = rho_new
         it += 1
     ratio = float(np.linalg.norm(R)) / nB
+    if per_col and fixed_iters is None:
+        done |= (bb == 0.0) | (np.sqrt(np.einsum("dc,dc->c", R, R)) < tol * np.sqrt(bb))
+        return X, CGInfo(it, bool(done.all()), ratio, hist)
     return X, CGInfo(it, ratio < tol, ratio, hist)
 
 
@@ -444,14 +539,14 @@ class EStepResult:
 
 def cofem_estep(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
                 tol: float, max_iter: int, seed: int, t: int,
-                fixed_iters: Optional[int] = None) -> EStepResult:
+                fixed_iters: Optional[int] = None, stop_rule: str = "frobenius") -> EStepResult:
     """One simplified E-step of Algorithm 1 at EM iteration t: draw probes,
     form B = [P | b0] (Eq. 7), solve A X = B by CG, read mu (last column) and
     s (Eq. 6)."""
     D = op.D
     P = rademacher_probes(seed, t, K, D)
     B = np.concatenate([P, np.asarray(b0, np.float64)[:, None]], axis=1)
-    X, info = cg_solve(make_apply_A(op, beta, alpha), B, tol, max_iter, fixed_iters)
+    X, info = cg_solve(make_apply_A(op, beta, alpha), B, tol, max_iter, fixed_iters, stop_rule)
     mu = X[:, K].copy()
     s = diag_estimate(P, X[:, :K])
     return EStepResult(mu=mu, s=s, X=X, P=P, cg=info)
@@ -484,7 +579,8 @@ def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray,
 
 
 def cofem_estep_pcg(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int, tol: float, max_iter: int,
-                    seed: int, t: int, minv=None, mu0=None, d0=None, fixed_iters=None) -> EStepResult:
+                    seed: int, t: int, minv=None, mu0=None, d0=None, fixed_iters=None,
+                    stop_rule: str = "frobenius") -> EStepResult:
     """The E-step of Algorithm 1 solved by ``pcg_solve``: M^-1 = diag(minv);
     starting block X0 = [d0 (.) p_1 .. d0 (.) p_K | mu0] (a warm start for
     the probe solves x_k ~ Sigma p_k from a diagonal estimate d0, and for mu);
@@ -499,7 +595,7 @@ def cofem_estep_pcg(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int, 
             X0[:, :K] = np.asarray(d0, np.float64)[:, None] * P
         if mu0 is not None:
             X0[:, K] = np.asarray(mu0, np.float64)
-    X, info = pcg_solve(make_apply_A(op, beta, alpha), B, tol, max_iter, minv, X0, fixed_iters)
+    X, info = pcg_solve(make_apply_A(op, beta, alpha), B, tol, max_iter, minv, X0, fixed_iters, stop_rule)
     return EStepResult(mu=X[:, K].copy(), s=diag_estimate(P, X[:, :K]), X=X, P=P, cg=info)
 
 
@@ -511,16 +607,32 @@ class CoFEMResult:
     stats: list
 
 
+def gamma_change(alpha_new: np.ndarray, alpha_old: np.ndarray) -> float:
+    """Relative change of the prior variances gamma = 1/alpha over one M-step,
+    ||gamma_new - gamma_old||_2 / ||gamma_new||_2: the EM-level convergence
+    measure of ``cofem``'s ``em_tol`` rule (not in the paper, which runs a
+    fixed T_em).  gamma rather than alpha: pruned coordinates sit at the
+    1/alpha_max floor of gamma, where their Monte-Carlo flicker is invisible,
+    while alpha itself would be dominated by them."""
+    gn = 1.0 / np.asarray(alpha_new, np.float64)
+    go = 1.0 / np.asarray(alpha_old, np.float64)
+    n = float(np.linalg.norm(gn))
+    return float(np.linalg.norm(gn - go)) / n if n > 0.0 else 0.0
+
+
 def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
           max_iter: int, seed: int, alpha_max: float = ALPHA_MAX_DEFAULT,
           alpha0: Optional[np.ndarray] = None, t0: int = 1,
-          fixed_iters=None) -> CoFEMResult:
+          fixed_iters=None, stop_rule: str = "frobenius",
+          em_tol: Optional[float] = None) -> CoFEMResult:
     """CovarianceFreeEM(y, Phi, beta, T_em, K) of Algorithm 1.
 
     alpha starts at 1 (or ``alpha0``); EM iterations are numbered t0, t0+1, ...
     (t selects the probe draw).  ``fixed_iters`` is None, an int, or a sequence
     giving the CG iteration count of each EM iteration.  Returns the final
     alpha together with mu and s of the last E-step, as Algorithm 1 does.
+    With ``em_tol`` the loop also ends after the first M-step whose
+    ``gamma_change`` is below em_tol (at most T_em iterations).
     """
     D = op.D
     alpha = np.ones(D) if alpha0 is None else np.asarray(alpha0, np.float64).copy()
@@ -530,11 +642,15 @@ def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
     for i in range(T_em):
         t = t0 + i
         fi = fixed_iters[i] if isinstance(fixed_iters, (list, tuple, np.ndarray)) else fixed_iters
-        e = cofem_estep(op, b0, beta, alpha, K, tol, max_iter, seed, t, fi)
+        e = cofem_estep(op, b0, beta, alpha, K, tol, max_iter, seed, t, fi, stop_rule)
         mu, s = e.mu, e.s
+        alpha_old = alpha
         alpha, n_clamped = mstep(mu, s, alpha_max)
+        change = gamma_change(alpha, alpha_old)
         stats.append({"t": t, "cg_iters": e.cg.iters, "converged": e.cg.converged,
-                      "rel_resid": e.cg.rel_resid, "n_clamped": n_clamped})
+                      "rel_resid": e.cg.rel_resid, "n_clamped": n_clamped, "gamma_change": change})
+        if em_tol is not None and change < em_tol:
+            break
     return CoFEMResult(alpha=alpha, mu=mu, s=s, stats=stats)
 
 

@@ -33,6 +33,8 @@ COFEM_PREC_FP32 = 0
 COFEM_PREC_BF16_IR = 1
 COFEM_PREC_FP64 = 2
 COFEM_STOP_FROBENIUS = 0
+COFEM_STOP_PER_COLUMN = 1
+_STOP_RULES = {"frobenius": COFEM_STOP_FROBENIUS, "per_column": COFEM_STOP_PER_COLUMN}
 COFEM_FLAG_TRUE_RESIDUAL = 1
 COFEM_FLAG_EAGER = 2
 COFEM_FLAG_BATCHED = 4
@@ -69,19 +71,23 @@ class cofem_params(ctypes.Structure):
 class cofem_iter_stats(ctypes.Structure):
     _fields_ = [("t", c_int32), ("cg_iters", c_int32), ("converged", c_int32), ("n_clamped", c_int32),
                 ("rel_resid", c_double), ("ms", c_double), ("rel_resid_true", c_double),
-                ("ir_sweeps", c_int32)]
+                ("ir_sweeps", c_int32), ("gamma_change", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _SIGNATURES = {
-    "cofem_init": (c_int32, [POINTER(cofem_problem), c_int32, POINTER(cofem_params), c_void_p,
-                             POINTER(c_void_p)]),
+    "cofem_init": (c_int32, [POINTER(cofem_problem), c_int32, POINTER(cofem_params), c_void_p, c_void_p,
+                             ctypes.c_size_t, POINTER(c_void_p)]),
+    "cofem_workspace_size": (c_int32, [POINTER(cofem_problem), c_int32, POINTER(cofem_params),
+                                       POINTER(ctypes.c_size_t)]),
     "cofem_em_step": (c_int32, [c_void_p, c_int32, POINTER(cofem_iter_stats)]),
+    "cofem_em_run": (c_int32, [c_void_p, c_int32, c_double, POINTER(cofem_iter_stats), POINTER(c_int32)]),
     "cofem_posterior": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "cofem_set_alpha": (c_int32, [c_void_p, c_int32, c_void_p]),
     "cofem_set_iteration": (c_int32, [c_void_p, c_int32]),
+    "cofem_restart": (c_int32, [c_void_p]),
     "cofem_set_fixed_cg_iters": (c_int32, [c_void_p, c_int32]),
     "cofem_get_solution": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "cofem_get_means": (c_int32, [c_void_p, c_int32, c_void_p]),
@@ -148,10 +154,23 @@ def _stream(stream):
 
 
 # --------------------------------------------------------- C-named wrappers
-def cofem_init(problem: cofem_problem, params: cofem_params, stream=None):
+def cofem_workspace_size(problems, params: cofem_params) -> int:
+    """Device bytes cofem_init needs for these problems (a list, or one)."""
+    if isinstance(problems, cofem_problem):
+        problems = [problems]
+    arr = (cofem_problem * len(problems))(*problems)
+    n = ctypes.c_size_t(0)
+    _check(load().cofem_workspace_size(arr, len(problems), ctypes.byref(params), ctypes.byref(n)))
+    return int(n.value)
+
+
+def cofem_init(problem: cofem_problem, params: cofem_params, stream=None, workspace=None):
+    """workspace: None (the library allocates) or a 256-byte aligned device
+    tensor of at least cofem_workspace_size bytes, kept alive by the caller."""
     ctx = c_void_p()
-    _check(load().cofem_init(ctypes.byref(problem), 1, ctypes.byref(params), _stream(stream),
-                             ctypes.byref(ctx)))
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().cofem_init(ctypes.byref(problem), 1, ctypes.byref(params), _stream(stream), _ptr(workspace),
+                             nbytes, ctypes.byref(ctx)))
     return ctx
 
 
@@ -165,10 +184,23 @@ def cofem_em_step(ctx, n_iters: int, n_problems: int = 1):
     return [[stats[i * n_problems + j].as_dict() for j in range(n_problems)] for i in range(n_iters)]
 
 
-def cofem_init_batch(problems, params: cofem_params, stream=None):
+def cofem_em_run(ctx, max_iters: int, em_tol: float, n_problems: int = 1):
+    """EM iterations until the relative change of 1/alpha falls below em_tol
+    (at most max_iters); statistics as cofem_em_step, one entry per iteration run."""
+    stats = (cofem_iter_stats * max(max_iters * n_problems, 1))()
+    n = c_int32(0)
+    _check(load().cofem_em_run(ctx, max_iters, float(em_tol), stats, ctypes.byref(n)), ctx)
+    if n_problems == 1:
+        return [stats[i].as_dict() for i in range(n.value)]
+    return [[stats[i * n_problems + j].as_dict() for j in range(n_problems)] for i in range(n.value)]
+
+
+def cofem_init_batch(problems, params: cofem_params, stream=None, workspace=None):
     arr = (cofem_problem * len(problems))(*problems)
     ctx = c_void_p()
-    _check(load().cofem_init(arr, len(problems), ctypes.byref(params), _stream(stream), ctypes.byref(ctx)))
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(load().cofem_init(arr, len(problems), ctypes.byref(params), _stream(stream), _ptr(workspace), nbytes,
+                             ctypes.byref(ctx)))
     return ctx
 
 
@@ -192,6 +224,10 @@ def cofem_set_alpha(ctx, alpha, problem: int = 0):
 
 def cofem_set_iteration(ctx, t: int):
     _check(load().cofem_set_iteration(ctx, t), ctx)
+
+
+def cofem_restart(ctx):
+    _check(load().cofem_restart(ctx), ctx)
 
 
 def cofem_set_fixed_cg_iters(ctx, n: int):
@@ -263,7 +299,8 @@ class CoFEM:
     dct:    CoFEM.dct(rows[N] int32 cuda, y[N] float32 cuda, D, beta, K, ...)
     """
 
-    def __init__(self, problem: cofem_problem, params: cofem_params, keep, device, stream=None):
+    def __init__(self, problem: cofem_problem, params: cofem_params, keep, device, stream=None,
+                 workspace=None):
         import torch
         self._keep = keep
         self.device = device
@@ -271,22 +308,30 @@ class CoFEM:
         self.K = int(params.K)
         self.params = params
         self.problem = problem
+        if workspace is True:
+            # a caller-owned workspace from torch, sized by the library
+            n = cofem_workspace_size(problem, params)
+            workspace = torch.empty(n + 256, dtype=torch.uint8, device=device)
+            off = (-workspace.data_ptr()) % 256
+            workspace = workspace[off:off + n]
+        self.workspace = workspace
         with torch.cuda.device(device):
-            self.ctx = cofem_init(problem, params, stream)
+            self.ctx = cofem_init(problem, params, stream, workspace)
 
     @staticmethod
     def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0, precision="fp32",
-                true_residual=True, ir_inner_tol=0.0, ir_max_sweeps=0, warm_start=False, jacobi=False):
+                true_residual=True, ir_inner_tol=0.0, ir_max_sweeps=0, warm_start=False, jacobi=False,
+                stop_rule="frobenius"):
         flags = ((COFEM_FLAG_TRUE_RESIDUAL if true_residual else 0) | (COFEM_FLAG_WARM_PREV if warm_start else 0)
                  | (COFEM_FLAG_JACOBI if jacobi else 0))
         return cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
                             seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=_PRECISIONS[precision],
-                            stop_rule=COFEM_STOP_FROBENIUS, alpha_max=float(alpha_max), flags=flags,
+                            stop_rule=_STOP_RULES[stop_rule], alpha_max=float(alpha_max), flags=flags,
                             poll_interval=int(poll_interval), ir_inner_tol=float(ir_inner_tol),
                             ir_max_sweeps=int(ir_max_sweeps))
 
     @classmethod
-    def dense(cls, phi, y, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
+    def dense(cls, phi, y, beta, K, tol=1e-5, max_iter=400, seed=0, workspace=None, **kw):
         import torch
         if phi.dtype != torch.float32 or y.dtype != torch.float32 or not phi.is_cuda or not y.is_cuda:
             raise CofemError(COFEM_ERR_INVALID_ARG, "phi and y must be float32 GPU tensors")
@@ -295,10 +340,11 @@ class CoFEM:
         N, D = phi.shape
         prob = cofem_problem(kind=COFEM_DENSE, N=N, D=D, phi=phi.data_ptr(), ld_phi=D,
                              phi_dtype=COFEM_F32, H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr())
-        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (phi, y), phi.device)
+        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (phi, y), phi.device,
+                   workspace=workspace)
 
     @classmethod
-    def conv(cls, taps, y, H, W, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
+    def conv(cls, taps, y, H, W, beta, K, tol=1e-5, max_iter=400, seed=0, workspace=None, **kw):
         import torch
         if taps.dtype != torch.float32 or y.dtype != torch.float32 or not taps.is_cuda or not y.is_cuda:
             raise CofemError(COFEM_ERR_INVALID_ARG, "taps and y must be float32 GPU tensors")
@@ -308,10 +354,11 @@ class CoFEM:
         prob = cofem_problem(kind=COFEM_CONV2D_CIRC, N=H * W, D=H * W, phi=None, ld_phi=0,
                              phi_dtype=COFEM_F32, H=H, W=W, kh=th, kw=tw, taps=taps.data_ptr(),
                              y=y.data_ptr())
-        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (taps, y), taps.device)
+        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (taps, y), taps.device,
+                   workspace=workspace)
 
     @classmethod
-    def dct(cls, rows, y, D, beta, K, tol=1e-5, max_iter=400, seed=0, **kw):
+    def dct(cls, rows, y, D, beta, K, tol=1e-5, max_iter=400, seed=0, workspace=None, **kw):
         """Inverse DCT of a length-D coefficient vector followed by the N
         observed samples `rows` (distinct indices into [0, D)).  y: (N,) for
         one task, or (T, N) for T tasks sharing alpha (multi-task SBL)."""
@@ -326,12 +373,17 @@ class CoFEM:
             raise CofemError(COFEM_ERR_INVALID_ARG, "y must be (N,) or (T, N)")
         prob = cofem_problem(kind=COFEM_DCT_MASK, N=N, D=int(D), phi=None, ld_phi=0, phi_dtype=COFEM_F32,
                              H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr(), rows=rows.data_ptr(), n_tasks=T)
-        ctx = cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (rows, y), rows.device)
+        ctx = cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (rows, y), rows.device,
+                  workspace=workspace)
         ctx.T = T
         return ctx
 
     def em_step(self, n_iters=1):
         return cofem_em_step(self.ctx, n_iters)
+
+    def em_run(self, max_iters, em_tol):
+        """EM iterations until the relative change of 1/alpha is below em_tol."""
+        return cofem_em_run(self.ctx, max_iters, em_tol)
 
     def posterior(self):
         import torch
@@ -371,6 +423,10 @@ class CoFEM:
 
     def set_iteration(self, t):
         cofem_set_iteration(self.ctx, t)
+
+    def restart(self):
+        """Algorithm 1 from its first line again: alpha = 1, t = 1, no previous solution."""
+        cofem_restart(self.ctx)
 
     def set_fixed_cg_iters(self, n):
         cofem_set_fixed_cg_iters(self.ctx, n)
@@ -436,7 +492,7 @@ class CoFEMBatch:
     float32 cuda); problem i uses probe seed `seed + i`."""
 
     def __init__(self, problems, beta, K, tol=1e-5, max_iter=400, seed=0, alpha_max=1e10, eager=False,
-                 stream=None):
+                 stream=None, workspace=None):
         import torch
         keep, probs = [], []
         for phi, y in problems:
@@ -459,11 +515,20 @@ class CoFEMBatch:
                               flags=COFEM_FLAG_BATCHED | (COFEM_FLAG_EAGER if eager else 0), poll_interval=0,
                               ir_inner_tol=0.0,
                               ir_max_sweeps=0)
+        if workspace is True:
+            n = cofem_workspace_size(probs, params)
+            workspace = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+            off = (-workspace.data_ptr()) % 256
+            workspace = workspace[off:off + n]
+        self.workspace = workspace
         with torch.cuda.device(self.device):
-            self.ctx = cofem_init_batch(probs, params, stream)
+            self.ctx = cofem_init_batch(probs, params, stream, workspace)
 
     def em_step(self, n_iters=1):
         return cofem_em_step(self.ctx, n_iters, self.n)
+
+    def em_run(self, max_iters, em_tol):
+        return cofem_em_run(self.ctx, max_iters, em_tol, self.n)
 
     def posterior(self, i):
         import torch
@@ -482,6 +547,9 @@ class CoFEMBatch:
 
     def set_iteration(self, t):
         cofem_set_iteration(self.ctx, t)
+
+    def restart(self):
+        cofem_restart(self.ctx)
 
     def solution(self, i):
         import torch

@@ -61,6 +61,7 @@ struct cofem_ctx {
   int fixed_iters = 0;
   int prev_iters = 0;
   int precision = COFEM_PREC_FP32;
+  bool per_col = false;  // COFEM_STOP_PER_COLUMN
   bool true_resid = false;
   int flags = 0;
   // mixed-precision form (COFEM_PREC_BF16_IR): inner tolerance, sweep cap,
@@ -90,6 +91,12 @@ struct cofem_ctx {
   DctDims xd{};
   DctBuffers xb{};
   std::vector<void*> allocs;
+  // device memory: a caller's workspace (sub-allocated in order, 256-byte
+  // aligned) or, when ws is null, one hipMalloc per buffer (allocs).  With
+  // `sizing` set nothing is allocated or launched: alloc only counts bytes.
+  char* ws = nullptr;
+  size_t ws_size = 0, ws_used = 0;
+  bool sizing = false;
   // dictionary
   float* phiA = nullptr;
   float* phiB = nullptr;
@@ -159,17 +166,35 @@ cofem_status fail(cofem_ctx* c, cofem_status s, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                         \
   } while (0)
 
+constexpr size_t kWsAlign = 256;
+
 template <typename T>
 cofem_status alloc(cofem_ctx* c, T** p, size_t count) {
   void* q = nullptr;
   const size_t bytes = (count == 0 ? 1 : count) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(c, e == hipErrorOutOfMemory ? COFEM_ERR_OUT_OF_MEMORY : COFEM_ERR_DEVICE,
-                "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  const size_t span = (bytes + kWsAlign - 1) / kWsAlign * kWsAlign;
+  if (c->sizing) {
+    // counting pass of cofem_workspace_size: a placeholder that is never used
+    c->ws_used += span;
+    *p = reinterpret_cast<T*>(kWsAlign);
+    return COFEM_OK;
   }
-  c->allocs.push_back(q);
+  hipError_t e = hipSuccess;
+  if (c->ws) {
+    if (c->ws_used + span > c->ws_size)
+      return fail(c, COFEM_ERR_OUT_OF_MEMORY,
+                  "workspace of " + std::to_string(c->ws_size) + " bytes is too small (cofem_workspace_size)");
+    q = c->ws + c->ws_used;
+    c->ws_used += span;
+  } else {
+    e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, e == hipErrorOutOfMemory ? COFEM_ERR_OUT_OF_MEMORY : COFEM_ERR_DEVICE,
+                  "hipMalloc of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    }
+    c->allocs.push_back(q);
+  }
   *p = static_cast<T*>(q);
   e = hipMemsetAsync(q, 0, bytes, c->stream);
   if (e != hipSuccess) return fail(c, COFEM_ERR_DEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
@@ -216,6 +241,7 @@ cofem_status push_controls(cofem_ctx* c) {
   h.kp = c->KP;
   h.k = c->K;
   h.nt = c->NT;
+  h.per_col = c->per_col ? 1 : 0;
   h.stop = 1;
   for (int i = 0; i < n; ++i)
     COFEM_HIP(c, hipMemcpyAsync(c->st + i, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
@@ -294,6 +320,7 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   }
   COFEM_TRY(alloc(c, &c->cnt_split1, (size_t)(dd.Np / 32 * kCounterStride)));
   COFEM_TRY(alloc(c, &c->cnt_split2, (size_t)(dd.Dp / 32 * kCounterStride)));
+  if (c->sizing) return COFEM_OK;
 
   COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
   if (lowp)
@@ -318,8 +345,6 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   cd.nt = 1;
   const size_t blk = (size_t)cd.ldD * c->K;
   COFEM_TRY(alloc(c, &c->taps, (size_t)p.kh * p.kw));
-  COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
-                              c->stream));
   COFEM_TRY(alloc(c, &c->b0, cd.ldD));
   COFEM_TRY(alloc(c, &c->alpha, cd.ldD));
   COFEM_TRY(alloc(c, &c->alpha_prev, cd.ldD));
@@ -360,6 +385,9 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
     COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
     COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
   }
+  if (c->sizing) return COFEM_OK;
+  COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
+                              c->stream));
   COFEM_HIP(c, conv_b0(cd, c->taps, p.y, c->beta, c->b0, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha_prev, 1.0f, cd.ldD, c->stream));
@@ -390,7 +418,7 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   cd.nt = c->NT;
   c->KP = c->K;
   // the observed samples must be distinct and in range (checked once, here)
-  {
+  if (!c->sizing) {
     std::vector<int32_t> hr((size_t)p.N);
     COFEM_HIP(c, hipMemcpyAsync(hr.data(), p.rows, sizeof(int32_t) * (size_t)p.N, hipMemcpyDeviceToHost, c->stream));
     COFEM_HIP(c, hipStreamSynchronize(c->stream));
@@ -445,6 +473,7 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
     COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
     COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
   }
+  if (c->sizing) return COFEM_OK;
   COFEM_HIP(c, dct_setup(xd, p.rows, p.N, p.y, c->beta, mk, vb, tw1f, tw2f, tw1d, tw2d, c->xb, c->b0,
                          (c->flags & COFEM_FLAG_JACOBI) ? c->dct_cn : nullptr, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
@@ -527,8 +556,8 @@ cofem_status init_batch(cofem_ctx* c, const cofem_problem* problems, int n) {
   b->dims.resize(n);
   c->KP = kDenseKP;
   b->eager = (c->flags & COFEM_FLAG_EAGER) != 0;
-  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_running), sizeof(int32_t)) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&b->h_st), sizeof(CgScalars) * n) != hipSuccess)
+  if (!c->sizing && (hipHostMalloc(reinterpret_cast<void**>(&b->h_running), sizeof(int32_t)) != hipSuccess ||
+                      hipHostMalloc(reinterpret_cast<void**>(&b->h_st), sizeof(CgScalars) * n) != hipSuccess))
     return fail(c, COFEM_ERR_DEVICE, "pinned allocation failed");
   for (int i = 0; i < n; ++i) {
     const cofem_problem& q = problems[i];
@@ -582,6 +611,7 @@ cofem_status init_batch(cofem_ctx* c, const cofem_problem* problems, int n) {
     COFEM_TRY(alloc_tree(c, &p.parts_upd, &p.cnts_upd, p.nvec, kDenseKP + 1));
     COFEM_TRY(alloc_tree(c, &p.parts_pass, &p.cnts_pass, p.npairs2, 3 * (kDenseKP + 1)));
     p.st = c->st + i;
+    if (c->sizing) continue;
     const int kind = q.phi_dtype == COFEM_BF16 ? kDictBf16 : kDictF32ToBf16;
     COFEM_HIP(c, dense_pack16(q.phi, kind, q.ld_phi, d, a16, b16, c->stream));
     COFEM_HIP(c, dense_b0(q.phi, kind, q.ld_phi, q.y, c->beta, d, b0, c->stream));
@@ -600,6 +630,7 @@ cofem_status init_batch(cofem_ctx* c, const cofem_problem* problems, int n) {
   COFEM_TRY(alloc(c, &b->d_items1, m1));
   COFEM_TRY(alloc(c, &b->d_items2, m2));
   COFEM_TRY(alloc(c, &b->d_itemsv, itv.size()));
+  if (c->sizing) return COFEM_OK;
   COFEM_HIP(c, hipStreamSynchronize(c->stream));
 
   // autotuner: time the grouped operator passes (apply only, on the zeroed
@@ -698,9 +729,20 @@ cofem_status em_iteration_batch(cofem_ctx* c, cofem_iter_stats* out) {
       out[i].ms = ms;
       out[i].rel_resid_true = -1.0;
       out[i].ir_sweeps = 0;
+      out[i].gamma_change = h.gamma_change;
+      if (c->per_col) out[i].converged = h.all_done;
     }
   }
   return COFEM_OK;
+}
+
+// Drops what a later E-step could start from (the warm and learned starts
+// read the previous E-step's mean and diagonal estimate) and the first
+// polling chunk's guess: the next E-step starts from X = 0 as the first
+// E-step of a fresh context does.
+void forget_solution(cofem_ctx* c) {
+  c->has_solution = false;
+  c->prev_iters = c->fixed_iters;
 }
 
 cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, std::string* why) {
@@ -721,7 +763,11 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   }
   if (q->precision == COFEM_PREC_FP64 && p->kind != COFEM_CONV2D_CIRC)
     return *why = "COFEM_PREC_FP64 is built for convolution dictionaries only", COFEM_ERR_UNSUPPORTED;
-  if (q->stop_rule != COFEM_STOP_FROBENIUS) return *why = "unknown stop rule", COFEM_ERR_UNSUPPORTED;
+  if (q->stop_rule != COFEM_STOP_FROBENIUS && q->stop_rule != COFEM_STOP_PER_COLUMN)
+    return *why = "unknown stop rule", COFEM_ERR_INVALID_ARG;
+  if (q->stop_rule == COFEM_STOP_PER_COLUMN && q->precision == COFEM_PREC_BF16_IR)
+    return *why = "COFEM_STOP_PER_COLUMN is not built for the refinement of COFEM_PREC_BF16_IR",
+           COFEM_ERR_UNSUPPORTED;
   if ((q->flags & COFEM_FLAG_JACOBI) && (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
     return *why = "the Jacobi preconditioner is built for convolution and DCT dictionaries", COFEM_ERR_UNSUPPORTED;
   if ((q->flags & COFEM_FLAG_WARM_PREV) &&
@@ -1120,8 +1166,8 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
     outer = c->host_st->true_ratio;
   }
   COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
-  COFEM_HIP(c, dense_mstep(dd, c->seed, t, c->K, c->Xt, c->xtm, c->alpha, c->alpha_max, c->mu, c->sdiag, c->st,
-                           c->stream));
+  COFEM_HIP(c, dense_mstep(dd, c->seed, t, c->K, c->Xt, c->xtm, c->alpha, c->alpha_max, c->mu, c->sdiag,
+                           c->parts_upd, c->cnts_upd, c->st, c->stream));
   COFEM_TRY(mark(c, -1, 0));
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
   COFEM_TRY(read_state(c));
@@ -1140,6 +1186,7 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
     out->ms = ms;
     out->rel_resid_true = outer;
     out->ir_sweeps = (int32_t)c->sweeps.size();
+    out->gamma_change = c->host_st->gamma_change;
   }
   return COFEM_OK;
 }
@@ -1187,14 +1234,14 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
-                             c->sdiag, c->st, c->stream));
+                             c->sdiag, c->parts_upd, c->cnts_upd, c->st, c->stream));
   else {
     // the learned form's features see how far this M-step moves alpha
     if (c->alpha_prev)
       COFEM_HIP(c, hipMemcpyAsync(c->alpha_prev, c->alpha, sizeof(float) * c->cd.D, hipMemcpyDeviceToDevice,
                                   c->stream));
     COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
-                            c->st, c->stream));
+                            c->red_upd, c->st, c->stream));
   }
   COFEM_TRY(mark(c, -1, 0));
   COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
@@ -1215,22 +1262,17 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     out->ms = ms;
     out->rel_resid_true = c->true_resid ? c->host_st->true_ratio : -1.0;
     out->ir_sweeps = 0;
+    out->gamma_change = c->host_st->gamma_change;
+    if (c->per_col) out->converged = c->host_st->all_done;
   }
   return COFEM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const cofem_params* params,
-                        void* hip_stream, cofem_ctx** out) {
-  if (!out) return fail(nullptr, COFEM_ERR_INVALID_ARG, "out is null");
-  std::string why;
-  cofem_status v = validate(problems, n_problems, params, &why);
-  if (v != COFEM_OK) return fail(nullptr, v, why);
+// A context holding the problem description and the solver controls (no
+// device state yet).
+cofem_ctx* new_ctx(const cofem_problem* problems, const cofem_params* params, void* hip_stream) {
   cofem_ctx* c = new (std::nothrow) cofem_ctx();
-  if (!c) return fail(nullptr, COFEM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  if (!c) return nullptr;
   const cofem_problem& p = problems[0];
   c->kind = p.kind;
   c->NT = p.n_tasks > 1 ? p.n_tasks : 1;  // validated: several tasks only for the DCT dictionary
@@ -1244,11 +1286,64 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   c->alpha_max = params->alpha_max > 0.0 ? params->alpha_max : 1e10;
   c->poll = params->poll_interval > 0 ? params->poll_interval : 8;
   c->precision = params->precision;
+  c->per_col = params->stop_rule == COFEM_STOP_PER_COLUMN;
   c->true_resid = (params->flags & COFEM_FLAG_TRUE_RESIDUAL) != 0;
   c->flags = params->flags;
   c->tol_in = params->ir_inner_tol > 0.0 ? params->ir_inner_tol : 0.1;
   c->max_sweeps = params->ir_max_sweeps > 0 ? params->ir_max_sweeps : 20;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  return c;
+}
+
+// Allocates (or, when sizing, counts) the device state of every problem and
+// sets it up.
+cofem_status init_state(cofem_ctx* c, const cofem_problem* problems, int32_t n_problems, const cofem_params* params) {
+  const cofem_problem& p = problems[0];
+  const bool batched = n_problems > 1 || p.phi_dtype == COFEM_BF16 || (params->flags & COFEM_FLAG_BATCHED);
+  COFEM_TRY(alloc(c, &c->st, (size_t)n_problems));
+  return batched                      ? init_batch(c, problems, n_problems)
+         : (p.kind == COFEM_DENSE)    ? init_dense(c, p)
+         : (p.kind == COFEM_DCT_MASK) ? init_dct(c, p)
+                                      : init_conv(c, p);
+}
+
+}  // namespace
+
+extern "C" {
+
+cofem_status cofem_workspace_size(const cofem_problem* problems, int32_t n_problems, const cofem_params* params,
+                                  size_t* bytes) {
+  if (!bytes) return fail(nullptr, COFEM_ERR_INVALID_ARG, "bytes is null");
+  std::string why;
+  cofem_status v = validate(problems, n_problems, params, &why);
+  if (v != COFEM_OK) return fail(nullptr, v, why);
+  cofem_ctx* c = new_ctx(problems, params, nullptr);
+  if (!c) return fail(nullptr, COFEM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->sizing = true;
+  const cofem_status s = init_state(c, problems, n_problems, params);
+  const size_t need = c->ws_used;
+  if (s != COFEM_OK) g_err = c->err;
+  delete c->batch;
+  delete c;  // nothing was allocated or launched
+  if (s != COFEM_OK) return s;
+  *bytes = need;
+  return COFEM_OK;
+}
+
+cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const cofem_params* params,
+                        void* hip_stream, void* workspace, size_t workspace_bytes, cofem_ctx** out) {
+  if (!out) return fail(nullptr, COFEM_ERR_INVALID_ARG, "out is null");
+  if (workspace && reinterpret_cast<uintptr_t>(workspace) % kWsAlign != 0)
+    return fail(nullptr, COFEM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (!workspace && workspace_bytes != 0)
+    return fail(nullptr, COFEM_ERR_INVALID_ARG, "workspace_bytes without a workspace");
+  std::string why;
+  cofem_status v = validate(problems, n_problems, params, &why);
+  if (v != COFEM_OK) return fail(nullptr, v, why);
+  cofem_ctx* c = new_ctx(problems, params, hip_stream);
+  if (!c) return fail(nullptr, COFEM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  c->ws = static_cast<char*>(workspace);
+  c->ws_size = workspace ? workspace_bytes : 0;
   cofem_status s = COFEM_OK;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
@@ -1258,13 +1353,7 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   if (e != hipSuccess) {
     s = fail(c, COFEM_ERR_DEVICE, std::string("HIP set-up: ") + hipGetErrorString(e));
   }
-  const bool batched = n_problems > 1 || p.phi_dtype == COFEM_BF16 || (params->flags & COFEM_FLAG_BATCHED);
-  if (s == COFEM_OK) s = alloc(c, &c->st, (size_t)n_problems);
-  if (s == COFEM_OK)
-    s = batched                       ? init_batch(c, problems, n_problems)
-        : (p.kind == COFEM_DENSE)     ? init_dense(c, p)
-        : (p.kind == COFEM_DCT_MASK) ? init_dct(c, p)
-                                      : init_conv(c, p);
+  if (s == COFEM_OK) s = init_state(c, problems, n_problems, params);
   if (s == COFEM_OK) s = push_controls(c);
   if (s == COFEM_OK) {
     e = hipStreamSynchronize(c->stream);
@@ -1285,8 +1374,38 @@ cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* st
   for (int i = 0; i < n_iters; ++i) {
     if (ctx->t_next >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
     const int np = ctx->batch ? ctx->batch->n : 1;
-    COFEM_TRY(em_iteration(ctx, stats ? &stats[(size_t)i * np] : nullptr));
+    const cofem_status s = em_iteration(ctx, stats ? &stats[(size_t)i * np] : nullptr);
+    if (s != COFEM_OK) {
+      // a failed E-step may leave non-finite iterates: no later solve starts there
+      forget_solution(ctx);
+      return s;
+    }
   }
+  return COFEM_OK;
+}
+
+cofem_status cofem_em_run(cofem_ctx* ctx, int32_t max_iters, double em_tol, cofem_iter_stats* stats,
+                          int32_t* n_done) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  if (max_iters < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "max_iters < 0");
+  if (!(em_tol == em_tol)) return fail(ctx, COFEM_ERR_INVALID_ARG, "em_tol is NaN");
+  const int np = ctx->batch ? ctx->batch->n : 1;
+  std::vector<cofem_iter_stats> one((size_t)np);
+  int done = 0;
+  for (int i = 0; i < max_iters; ++i) {
+    if (ctx->t_next >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
+    cofem_iter_stats* out = stats ? &stats[(size_t)i * np] : one.data();
+    const cofem_status s = em_iteration(ctx, out);
+    if (s != COFEM_OK) {
+      forget_solution(ctx);
+      return s;
+    }
+    ++done;
+    bool small = em_tol > 0.0;
+    for (int j = 0; j < np && small; ++j) small = out[j].gamma_change < em_tol;
+    if (small) break;
+  }
+  if (n_done) *n_done = done;
   return COFEM_OK;
 }
 
@@ -1348,6 +1467,29 @@ cofem_status cofem_set_iteration(cofem_ctx* ctx, int32_t t) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (t < 0 || t >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "t must be in [0, 65535]");
   ctx->t_next = t;
+  // the last solve no longer precedes the next E-step: start it cold
+  forget_solution(ctx);
+  return COFEM_OK;
+}
+
+cofem_status cofem_restart(cofem_ctx* ctx) {
+  if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
+  forget_solution(ctx);
+  ctx->t_next = 1;
+  ctx->prev_iters = ctx->fixed_iters;
+  if (BatchHost* b = ctx->batch) {
+    for (const BatchProblem& p : b->probs) {
+      COFEM_HIP(ctx, fill_f32(p.alpha, 1.0f, p.Dp, ctx->stream));
+      COFEM_HIP(ctx, fill_f32(p.mu, 0.0f, p.Dp, ctx->stream));
+      COFEM_HIP(ctx, fill_f32(p.sdiag, 0.0f, p.Dp, ctx->stream));
+    }
+    return COFEM_OK;
+  }
+  const int64_t n = ctx->kind == COFEM_DENSE ? ctx->dd.Dp : ctx->cd.ldD;
+  COFEM_HIP(ctx, fill_f32(ctx->alpha, 1.0f, n, ctx->stream));
+  if (ctx->alpha_prev) COFEM_HIP(ctx, fill_f32(ctx->alpha_prev, 1.0f, n, ctx->stream));
+  COFEM_HIP(ctx, fill_f32(ctx->mu, 0.0f, n, ctx->stream));
+  COFEM_HIP(ctx, fill_f32(ctx->sdiag, 0.0f, n, ctx->stream));
   return COFEM_OK;
 }
 

@@ -45,6 +45,14 @@ struct CgScalars {
   double true_res[kMaxCols];  // ||b_c - A x_c||^2 of the last solve (float64 sums)
   double true_ratio;          // sqrt(sum_c true_res[c]) / nB0
   double nB0;                 // ||B||_F of the E-step (nB is the current solve's reference)
+  // per-column stop rule (COFEM_STOP_PER_COLUMN): column c is finished once
+  // ||r_c|| < tol ||b_c|| and takes no further step; the solve stops when every
+  // column is finished (or at the cap)
+  int32_t per_col;            // 1: per-column rule, 0: joint Frobenius ratio
+  int32_t all_done;           // per-column rule: every column finished
+  int32_t done[kMaxCols];
+  double bb[kMaxCols];        // ||b_c||^2 of the solve's right-hand side
+  double gamma_change;        // M-step: ||1/alpha_new - 1/alpha_old|| / ||1/alpha_new||
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -258,19 +266,49 @@ __device__ __forceinline__ void dense_block_sums(double acc, double accm, double
 // block's finish costs no further memory round trip.
 struct CgCtl {
   double rho;  // st->rho[threadIdx.x] in threads < nc, else 0
+  double bb;   // per-column rule: st->bb[threadIdx.x] in threads < nc
   double nB, tol;
   int nc, iter, limit, fixed;
+  int per_col, done;  // done: st->done[threadIdx.x] (per-column rule)
 };
 __device__ __forceinline__ CgCtl load_cg_ctl(const CgScalars* st) {
   CgCtl c;
   c.nc = st->kp + st->nt;
-  c.rho = (int)threadIdx.x < c.nc ? st->rho[threadIdx.x] : 0.0;
+  const bool mine = (int)threadIdx.x < c.nc;
+  c.rho = mine ? st->rho[threadIdx.x] : 0.0;
   c.nB = st->nB;
   c.tol = st->tol;
   c.iter = st->iter;
   c.limit = st->limit;
   c.fixed = st->fixed;
+  c.per_col = st->per_col;
+  c.done = (c.per_col && mine) ? st->done[threadIdx.x] : 0;
+  c.bb = (c.per_col && mine) ? st->bb[threadIdx.x] : 0.0;
   return c;
+}
+
+// Per-column stop rule: thread c < nc decides whether its column is finished
+// after a residual norm ||r_c||^2 = rr (sticky: a finished column stays
+// finished), stores the flag, and the block learns whether all are finished.
+// Every thread of the block must call it.  Without the rule it returns false.
+__device__ __forceinline__ bool per_column_finish(CgScalars* st, const CgCtl& k, double rr, int* done_out) {
+  __shared__ int s_open;
+  if (!k.per_col) {
+    *done_out = 0;
+    return false;
+  }
+  if (threadIdx.x == 0) s_open = 0;
+  __syncthreads();
+  const int c = threadIdx.x;
+  int d = 0;
+  if (c < k.nc) {
+    d = k.done || (!k.fixed && (k.bb == 0.0 || sqrt(rr) < k.tol * sqrt(k.bb)));
+    st->done[c] = d;
+    if (!d) atomicAdd(&s_open, 1);
+  }
+  __syncthreads();
+  *done_out = d;
+  return s_open == 0;
 }
 
 // Finishes a CG update: the new ||r_c||^2 for columns 0..kp.  Applies the stop
@@ -279,6 +317,8 @@ __device__ __forceinline__ CgCtl load_cg_ctl(const CgScalars* st) {
 __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho, const CgCtl& k) {
   const int nc = k.nc;
   if ((int)threadIdx.x < nc) st->rho[threadIdx.x] = new_rho[threadIdx.x];
+  int mine_done;
+  const bool all = per_column_finish(st, k, (int)threadIdx.x < nc ? new_rho[threadIdx.x] : 0.0, &mine_done);
   if (threadIdx.x == 0) {
     const int it = k.iter + 1;
     double sum = 0.0;
@@ -288,7 +328,9 @@ __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_r
     const double ratio = k.nB > 0.0 ? sqrt(sum) / k.nB : 0.0;
     st->ratio = ratio;
     st->iter = it;
-    st->stop = (it >= k.limit) || (!k.fixed && ratio < k.tol) || !finite;
+    st->all_done = all ? 1 : 0;
+    const bool met = k.per_col ? all : (!k.fixed && ratio < k.tol);
+    st->stop = (it >= k.limit) || met || !finite;
   }
 }
 __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_rho) {
@@ -311,14 +353,15 @@ __device__ __forceinline__ void finish_step(CgScalars* st, const double* dots, c
   if (c < nc) {
     const double g = dots[c], dl = dots[nc + c], et = dots[2 * nc + c];
     const double rho = k.rho;
-    const double a = (g != 0.0) ? rho / g : 0.0;
+    // a finished column (per-column rule) takes no step
+    const double a = (g != 0.0 && !k.done) ? rho / g : 0.0;
     st->gam[c] = g;
     st->del[c] = dl;
     st->eta[c] = et;
     st->a[c] = a;
     double rn = rho - 2.0 * a * dl + a * a * et;
     if (rn < 0.0) rn = 0.0;
-    st->b[c] = (rho != 0.0) ? rn / rho : 0.0;
+    st->b[c] = (rho != 0.0 && !k.done) ? rn / rho : 0.0;
     if (!(isfinite(g) && isfinite(dl) && isfinite(et))) s_bad = 1;
   }
   __syncthreads();
@@ -339,6 +382,8 @@ __device__ __forceinline__ void finish_step(CgScalars* st, const double* dots) {
 // finish_step).
 __device__ __forceinline__ void finish_fused(CgScalars* st, const double* v, int nc, const CgCtl& k) {
   __shared__ int s_bad;
+  int mine_done;
+  const bool all = per_column_finish(st, k, (int)threadIdx.x < nc ? v[nc + threadIdx.x] : 0.0, &mine_done);
   if (threadIdx.x == 0) {
     const int it = k.iter + 1;
     double rr = 0.0, rz = 0.0;
@@ -350,22 +395,25 @@ __device__ __forceinline__ void finish_fused(CgScalars* st, const double* v, int
     const double ratio = k.nB > 0.0 ? sqrt(rr) / k.nB : 0.0;
     st->ratio = ratio;
     st->iter = it;
+    st->all_done = all ? 1 : 0;
     s_bad = finite ? 0 : 1;
-    st->stop = (it >= k.limit) || (!k.fixed && ratio < k.tol) || !finite;
+    const bool met = k.per_col ? all : (!k.fixed && ratio < k.tol);
+    st->stop = (it >= k.limit) || met || !finite;
   }
   __syncthreads();
   const int c = threadIdx.x;
   if (c < nc) {
     const double rho = v[c], g = v[2 * nc + c], dl = v[3 * nc + c], et = v[4 * nc + c];
     st->rho[c] = rho;
-    const double a = (g != 0.0) ? rho / g : 0.0;
+    // a finished column (per-column rule) takes no further step
+    const double a = (g != 0.0 && !mine_done) ? rho / g : 0.0;
     st->gam[c] = g;
     st->del[c] = dl;
     st->eta[c] = et;
     st->a[c] = a;
     double rn = rho - 2.0 * a * dl + a * a * et;
     if (rn < 0.0) rn = 0.0;
-    st->b[c] = (rho != 0.0) ? rn / rho : 0.0;
+    st->b[c] = (rho != 0.0 && !mine_done) ? rn / rho : 0.0;
     if (!(isfinite(g) && isfinite(dl) && isfinite(et))) s_bad = 1;
   }
   __syncthreads();
@@ -376,6 +424,27 @@ __device__ __forceinline__ void finish_fused(CgScalars* st, const double* v, int
 }
 
 // Finishes the initial residual R = B: rho_c = ||b_c||^2 (in shared memory).
+// Start-of-solve part of the per-column rule: thread c < nc records
+// ||b_c||^2 = bb and whether the column is finished already (||r_c||^2 = rr
+// at the start; a zero right-hand side is finished).  Returns (to every
+// thread) whether all columns are.
+__device__ __forceinline__ bool per_column_start(CgScalars* st, int nc, double rr, double bb) {
+  __shared__ int s_open;
+  const int per_col = st->per_col, fixed = st->fixed;
+  const double tol = st->tol;
+  if (threadIdx.x == 0) s_open = 0;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < nc) {
+    const int d = per_col && !fixed && (bb == 0.0 || sqrt(rr) < tol * sqrt(bb));
+    st->done[c] = d;
+    st->bb[c] = bb;
+    if (!d) atomicAdd(&s_open, 1);
+  }
+  __syncthreads();
+  return per_col && s_open == 0;
+}
+
 __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
   const int nc = st->kp + st->nt;
   if ((int)threadIdx.x < nc) {
@@ -383,6 +452,8 @@ __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
     st->b[threadIdx.x] = 0.0;
     st->a[threadIdx.x] = 0.0;
   }
+  const double own = (int)threadIdx.x < nc ? rho[threadIdx.x] : 0.0;
+  const bool all = per_column_start(st, nc, own, own);
   if (threadIdx.x == 0) {
     const int limit = st->limit, fixed = st->fixed;
     const double tol = st->tol;
@@ -393,8 +464,10 @@ __device__ __forceinline__ void finish_init(CgScalars* st, const double* rho) {
     st->ratio = sum > 0.0 ? 1.0 : 0.0;
     st->iter = 0;
     st->n_clamped = 0;
+    st->all_done = all ? 1 : 0;
     st->numeric_error = isfinite(sum) ? 0 : 1;
-    st->stop = (sum == 0.0) || (limit <= 0) || (!fixed && 1.0 < tol) || !isfinite(sum);
+    const bool met = st->per_col ? all : (!fixed && 1.0 < tol);
+    st->stop = (sum == 0.0) || (limit <= 0) || met || !isfinite(sum);
   }
 }
 
@@ -406,6 +479,9 @@ __device__ __forceinline__ void finish_init_pcg(CgScalars* st, const double* v, 
     st->a[threadIdx.x] = 0.0;
     st->b[threadIdx.x] = 0.0;
   }
+  const bool mine = (int)threadIdx.x < ncols;
+  const bool all = per_column_start(st, ncols, mine ? v[ncols + threadIdx.x] : 0.0,
+                                    mine ? v[2 * ncols + threadIdx.x] : 0.0);
   if (threadIdx.x == 0) {
     const int limit = st->limit, fixed = st->fixed;
     const double tol = st->tol;
@@ -422,29 +498,20 @@ __device__ __forceinline__ void finish_init_pcg(CgScalars* st, const double* v, 
     st->ratio = nB > 0.0 ? sqrt(rr) / nB : 0.0;
     st->iter = 0;
     st->n_clamped = 0;
+    st->all_done = all ? 1 : 0;
     st->numeric_error = finite ? 0 : 1;
-    st->stop = (bb == 0.0) || (limit <= 0) || (!fixed && st->ratio < tol) || !finite;
+    const bool met = st->per_col ? all : (!fixed && st->ratio < tol);
+    st->stop = (bb == 0.0) || (limit <= 0) || met || !finite;
   }
 }
 
-// Finishes a preconditioned update: per column rho' = r^T z and ||r||^2 (the
-// stop test is on the unpreconditioned residual).
-__device__ __forceinline__ void finish_update_pcg(CgScalars* st, const double* v, int ncols) {
-  if ((int)threadIdx.x < ncols) st->rho[threadIdx.x] = v[threadIdx.x];
+// Finishes the M-step's sums (in shared memory: floor hits, the squared
+// change of the prior variances 1/alpha, their squared norm): the clamp count
+// and the relative change ||1/alpha_new - 1/alpha_old|| / ||1/alpha_new||.
+__device__ __forceinline__ void finish_mstep(CgScalars* st, const double* v) {
   if (threadIdx.x == 0) {
-    const double nB = st->nB, tol = st->tol;
-    const int it = st->iter + 1, limit = st->limit, fixed = st->fixed;
-    double rr = 0.0, rz = 0.0;
-    for (int c = 0; c < ncols; ++c) {
-      rz += v[c];
-      rr += v[ncols + c];
-    }
-    const bool finite = isfinite(rr) && isfinite(rz);
-    if (!finite) st->numeric_error = 1;
-    const double ratio = nB > 0.0 ? sqrt(rr) / nB : 0.0;
-    st->ratio = ratio;
-    st->iter = it;
-    st->stop = (it >= limit) || (!fixed && ratio < tol) || !finite;
+    st->n_clamped = (int32_t)v[0];
+    st->gamma_change = v[2] > 0.0 ? sqrt(v[1]) / sqrt(v[2]) : 0.0;
   }
 }
 
@@ -526,9 +593,11 @@ hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const
                         uint32_t* cnts, CgScalars* st, hipStream_t s);
 int dense_split(int64_t tiles, int64_t groups);
 bool dense_split_ok(int64_t groups, int splits);
+// diagonal estimate and M-step; the update's reduction tree (parts, cnts)
+// serves its sums (clamp count, change of 1/alpha)
 hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,
                        const double* xm, float* alpha, double alpha_max, float* mu, float* sdiag,
-                       CgScalars* st, hipStream_t s);
+                       double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s);
 hipError_t dense_to_colmajor(const DenseDims& dd, int K, const float* Xb, float* out, hipStream_t s);
 hipError_t dense_from_colmajor(const DenseDims& dd, int K, const float* in, float* Xb, hipStream_t s);
 int dense_update_blocks(const DenseDims& dd);
@@ -619,7 +688,7 @@ hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const
 hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const double* b0, const void* Q,
                            const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s);
 hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
-                      float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
+                      float* alpha, double alpha_max, float* mu, float* sdiag, const ConvReduce& red, CgScalars* st,
                       hipStream_t s);
 hipError_t conv_probes_out(const ConvDims& cd, const void* X, float* out, hipStream_t s);
 hipError_t conv_probes_in(const ConvDims& cd, const float* in, void* X, hipStream_t s);

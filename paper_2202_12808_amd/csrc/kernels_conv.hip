@@ -886,11 +886,12 @@ __global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int 
                                                     const double* __restrict__ xm,
                                                     float* __restrict__ alpha, double alpha_max,
                                                     float* __restrict__ mu,
-                                                    float* __restrict__ sdiag, CgScalars* st) {
+                                                    float* __restrict__ sdiag, double* parts, uint32_t* cnts,
+                                                    CgScalars* st) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
-  double clamped = 0.0;
+  double clamped = 0.0, dg2 = 0.0, g2 = 0.0;
   for (int64_t d = gtid; d < D; d += gstride) {
     double acc = 0.0;
     const uint64_t dn = (uint64_t)perm_nat(perm, d);
@@ -909,26 +910,42 @@ __global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int 
     }
     const double den = m2 + s;
     if (!(den >= floor_v)) clamped += 1.0;
-    alpha[d] = (float)(1.0 / (den >= floor_v ? den : floor_v));
+    const float a_new = (float)(1.0 / (den >= floor_v ? den : floor_v));
+    // change of the prior variance 1/alpha as the stored (float32) alpha has it
+    const double g_new = 1.0 / (double)a_new, g_old = 1.0 / (double)alpha[d];
+    dg2 += (g_new - g_old) * (g_new - g_old);
+    g2 += g_new * g_new;
+    alpha[d] = a_new;
     mu[d] = (float)m;
     sdiag[d] = (float)s;
   }
   __shared__ double shm[8];
-  const double tot = block_sum(clamped, shm);
-  if (threadIdx.x == 0 && tot > 0.0) atomicAdd(&st->n_clamped, (int)tot);
+  __shared__ double mine[3], tot[3];
+  const double v0 = block_sum(clamped, shm);
+  const double v1 = block_sum(dg2, shm);
+  const double v2 = block_sum(g2, shm);
+  if (threadIdx.x == 0) {
+    mine[0] = v0;
+    mine[1] = v1;
+    mine[2] = v2;
+  }
+  __syncthreads();
+  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, 3, mine, tot)) return;
+  finish_mstep(st, tot);
 }
 
 hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
-                      float* alpha, double alpha_max, float* mu, float* sdiag, CgScalars* st,
+                      float* alpha, double alpha_max, float* mu, float* sdiag, const ConvReduce& red, CgScalars* st,
                       hipStream_t s) {
-  const int64_t want = (cd.D + 255) / 256;
-  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
+  // conv_update_blocks(cd) blocks: the first column region of the update's
+  // reduction workspace (three values per block) serves the M-step's sums
+  const unsigned blocks = (unsigned)conv_update_blocks(cd);
   if (cd.fp64)
     hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
-                       static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, st);
+                       static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st);
   else
     hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
-                       static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, st);
+                       static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st);
   return hipGetLastError();
 }
 

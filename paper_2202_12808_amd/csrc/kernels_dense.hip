@@ -695,11 +695,12 @@ __device__ __forceinline__ void dense_mstep_body(int64_t blk, int64_t nblk, int6
                                                      const double* __restrict__ xm,
                                                      float* __restrict__ alpha, double alpha_max,
                                                      float* __restrict__ mu,
-                                                     float* __restrict__ sdiag, CgScalars* st) {
+                                                     float* __restrict__ sdiag, double* parts, uint32_t* cnts,
+                                                     CgScalars* st) {
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
-  double clamped = 0.0;
+  double clamped = 0.0, dg2 = 0.0, g2 = 0.0;
   for (int64_t d = gtid; d < D; d += gstride) {
     double acc = 0.0;
     for (int k = 0; k < K; ++k)
@@ -708,13 +709,28 @@ __device__ __forceinline__ void dense_mstep_body(int64_t blk, int64_t nblk, int6
     const double m = xm[d];
     const double den = m * m + s;
     if (!(den >= floor_v)) clamped += 1.0;
-    alpha[d] = (float)(1.0 / (den >= floor_v ? den : floor_v));
+    const float a_new = (float)(1.0 / (den >= floor_v ? den : floor_v));
+    // change of the prior variance 1/alpha as the stored (float32) alpha has it
+    const double g_new = 1.0 / (double)a_new, g_old = 1.0 / (double)alpha[d];
+    dg2 += (g_new - g_old) * (g_new - g_old);
+    g2 += g_new * g_new;
+    alpha[d] = a_new;
     mu[d] = (float)m;
     sdiag[d] = (float)s;
   }
   __shared__ double shm[8];
-  const double tot = block_sum(clamped, shm);
-  if (threadIdx.x == 0 && tot > 0.0) atomicAdd(&st->n_clamped, (int)tot);
+  __shared__ double mine[3], tot[3];
+  const double v0 = block_sum(clamped, shm);
+  const double v1 = block_sum(dg2, shm);
+  const double v2 = block_sum(g2, shm);
+  if (threadIdx.x == 0) {
+    mine[0] = v0;
+    mine[1] = v1;
+    mine[2] = v2;
+  }
+  __syncthreads();
+  if (!tree_reduce(parts, cnts, blk, nblk, 3, mine, tot)) return;
+  finish_mstep(st, tot);
 }
 
 __global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, int t, int K,
@@ -722,17 +738,20 @@ __global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, i
                                                      const double* __restrict__ xm,
                                                      float* __restrict__ alpha, double alpha_max,
                                                      float* __restrict__ mu,
-                                                     float* __restrict__ sdiag, CgScalars* st) {
-  dense_mstep_body(blockIdx.x, gridDim.x, D, seed, t, K, X, xm, alpha, alpha_max, mu, sdiag, st);
+                                                     float* __restrict__ sdiag, double* parts, uint32_t* cnts,
+                                                     CgScalars* st) {
+  dense_mstep_body(blockIdx.x, gridDim.x, D, seed, t, K, X, xm, alpha, alpha_max, mu, sdiag, parts, cnts, st);
 }
 
 hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,
                        const double* xm, float* alpha, double alpha_max, float* mu, float* sdiag,
-                       CgScalars* st, hipStream_t s) {
-  const int64_t want = (dd.D + 255) / 256;
-  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+                       double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s) {
+  // at most dense_update_blocks(dd) blocks: the update's reduction tree
+  // (parts, cnts) serves the M-step's sums
+  const int64_t want = (dd.D + 255) / 256, cap = dense_update_blocks(dd);
+  const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
   hipLaunchKernelGGL(k_dense_mstep, dim3(blocks), dim3(256), 0, s, dd.D, seed, t, K, X, xm, alpha,
-                     alpha_max, mu, sdiag, st);
+                     alpha_max, mu, sdiag, parts, cnts, st);
   return hipGetLastError();
 }
 
@@ -794,7 +813,8 @@ __global__ __launch_bounds__(256) void k_batch_mstep(const BatchItem* __restrict
                                                      double alpha_max) {
   const BatchItem it = items[blockIdx.x];
   const BatchProblem& p = probs[it.prob];
-  dense_mstep_body(it.a, p.nvec, p.D, p.seed, t, K, p.X, p.xm, p.alpha, alpha_max, p.mu, p.sdiag, p.st);
+  dense_mstep_body(it.a, p.nvec, p.D, p.seed, t, K, p.X, p.xm, p.alpha, alpha_max, p.mu, p.sdiag, p.parts_upd,
+                   p.cnts_upd, p.st);
 }
 
 // Number of problems whose solve has not stopped (one block).

@@ -72,6 +72,8 @@ def _params(**kw):
     ({"kind": C.COFEM_CONV2D_CIRC, "H": 4, "W": 4, "N": 16, "D": 16, "kh": 3, "kw": 3, "taps": 3},
      {"precision": C.COFEM_PREC_BF16_IR}, C.COFEM_ERR_UNSUPPORTED),
     ({}, {"precision": C.COFEM_PREC_FP64}, C.COFEM_ERR_UNSUPPORTED),
+    ({}, {"stop_rule": 5}, C.COFEM_ERR_INVALID_ARG),
+    ({}, {"precision": C.COFEM_PREC_BF16_IR, "stop_rule": C.COFEM_STOP_PER_COLUMN}, C.COFEM_ERR_UNSUPPORTED),
     ({"N": 0}, {}, C.COFEM_ERR_INVALID_ARG),
     ({"D": 0}, {}, C.COFEM_ERR_INVALID_ARG),
     ({"phi": None}, {}, C.COFEM_ERR_INVALID_ARG),
@@ -89,7 +91,7 @@ def _params(**kw):
 ])
 def test_init_rejects_bad_arguments_without_device(lib, pkw, qkw, code):
     ctx = ctypes.c_void_p()
-    st = lib.cofem_init(ctypes.byref(_problem(**pkw)), 1, ctypes.byref(_params(**qkw)), None,
+    st = lib.cofem_init(ctypes.byref(_problem(**pkw)), 1, ctypes.byref(_params(**qkw)), None, None, 0,
                         ctypes.byref(ctx))
     assert st == code
     assert not ctx.value
@@ -98,16 +100,62 @@ def test_init_rejects_bad_arguments_without_device(lib, pkw, qkw, code):
 
 def test_init_rejects_batch_count(lib):
     ctx = ctypes.c_void_p()
-    assert lib.cofem_init(ctypes.byref(_problem()), 0, ctypes.byref(_params()), None,
+    assert lib.cofem_init(ctypes.byref(_problem()), 0, ctypes.byref(_params()), None, None, 0,
                           ctypes.byref(ctx)) == C.COFEM_ERR_INVALID_ARG
-    assert lib.cofem_init(None, 1, ctypes.byref(_params()), None,
+    assert lib.cofem_init(None, 1, ctypes.byref(_params()), None, None, 0,
                           ctypes.byref(ctx)) == C.COFEM_ERR_INVALID_ARG
-    assert lib.cofem_init(ctypes.byref(_problem()), 1, ctypes.byref(_params()), None,
+    assert lib.cofem_init(ctypes.byref(_problem()), 1, ctypes.byref(_params()), None, None, 0,
                           None) == C.COFEM_ERR_INVALID_ARG
+
+
+def test_init_workspace_arguments_checked_first(lib):
+    ctx = ctypes.c_void_p()
+    # a misaligned workspace, and a size without a workspace, are rejected
+    # before any device call
+    assert lib.cofem_init(ctypes.byref(_problem()), 1, ctypes.byref(_params()), None, 8, 1 << 20,
+                          ctypes.byref(ctx)) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_init(ctypes.byref(_problem()), 1, ctypes.byref(_params()), None, None, 1 << 20,
+                          ctypes.byref(ctx)) == C.COFEM_ERR_INVALID_ARG
+    assert not ctx.value
+
+
+def _ws(lib, prob, params, n=1):
+    arr = (C.cofem_problem * n)(*([prob] * n))
+    nbytes = ctypes.c_size_t(0)
+    st = lib.cofem_workspace_size(arr, n, ctypes.byref(params), ctypes.byref(nbytes))
+    return st, nbytes.value
+
+
+def test_workspace_size_without_device(lib):
+    # the sizing pass touches no device and no device pointer (phi and y are
+    # dummies here): dense needs at least the two packed float32 copies of Phi
+    # (N and D padded to multiples of 64) and the four D x 32 CG blocks
+    st, n1 = _ws(lib, _problem(N=100, D=300, ld_phi=300), _params())
+    assert st == C.COFEM_OK
+    Np, Dp = 128, 320
+    assert n1 >= 2 * 4 * Np * Dp + 4 * 4 * Dp * 32
+    st, n2 = _ws(lib, _problem(N=200, D=600, ld_phi=600), _params())
+    assert st == C.COFEM_OK and n2 > n1
+    # the mixed-precision form adds the two bfloat16 copies and the accumulated solution
+    st, n3 = _ws(lib, _problem(N=100, D=300, ld_phi=300), _params(precision=C.COFEM_PREC_BF16_IR))
+    assert st == C.COFEM_OK and n3 >= n1 + 2 * 2 * Np * Dp
+    # conv: K + 1 columns of images (float32 probes, float64 mean), several blocks
+    conv = _problem(kind=C.COFEM_CONV2D_CIRC, H=64, W=48, N=64 * 48, D=64 * 48, kh=7, kw=7, taps=3, phi=None)
+    st, nc = _ws(lib, conv, _params(K=8))
+    assert st == C.COFEM_OK and nc >= 4 * (4 * 8 + 8) * 64 * 48
+    # batched: more problems need more memory; bad arguments are still rejected
+    st, nb1 = _ws(lib, _problem(N=100, D=300, ld_phi=300), _params(), 2)
+    st2, nb2 = _ws(lib, _problem(N=100, D=300, ld_phi=300), _params(), 4)
+    assert st == st2 == C.COFEM_OK and nb2 > nb1
+    assert _ws(lib, _problem(), _params(beta=-1.0))[0] == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_workspace_size(ctypes.byref(_problem()), 1, ctypes.byref(_params()), None) == \
+        C.COFEM_ERR_INVALID_ARG
 
 
 def test_null_context_calls_fail_cleanly(lib):
     assert lib.cofem_em_step(None, 1, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_em_run(None, 1, 0.0, None, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_restart(None) == C.COFEM_ERR_INVALID_ARG
     assert lib.cofem_posterior(None, 0, None, None, None) == C.COFEM_ERR_INVALID_ARG
     assert lib.cofem_set_alpha(None, 0, None) == C.COFEM_ERR_INVALID_ARG
     assert lib.cofem_set_iteration(None, 1) == C.COFEM_ERR_INVALID_ARG

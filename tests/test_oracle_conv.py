@@ -93,3 +93,35 @@ def test_conv_column_norms():
     e = np.zeros(op.D)
     e[37] = 1.0
     assert np.isclose(np.sum(op.apply(e) ** 2), op.column_norms_sq()[37])
+
+
+@pytest.mark.parametrize("H,W,k", [(16, 16, 7), (9, 13, 3), (32, 20, 9), (5, 5, 5), (1, 8, 1)])
+def test_fft_operator_matches_direct_stencil(H, W, k):
+    # the convolution theorem route (ConvOperatorFFT) against the direct
+    # wrap-mode stencil, for Phi, Phi^T and Phi^T Phi, one and several columns
+    rng = np.random.default_rng(100 + H * W + k)
+    taps = rng.standard_normal((k, k))
+    direct = O.ConvOperator(taps, H, W)
+    fft = O.ConvOperatorFFT(taps, H, W)
+    z = rng.standard_normal((H * W, 3))
+    for fn in ("apply", "apply_t"):
+        ref = getattr(direct, fn)(z)
+        got = getattr(fft, fn)(z)
+        assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        assert np.allclose(getattr(fft, fn)(z[:, 1]), ref[:, 1], rtol=0, atol=1e-12 * np.abs(ref).max())
+    g = direct.apply_t(direct.apply(z))
+    assert np.allclose(fft.gram(z), g, rtol=0, atol=1e-12 * np.abs(g).max())
+    assert np.allclose(fft.column_norms_sq(), direct.column_norms_sq())
+
+
+def test_fft_operator_cofem_equals_direct_cofem():
+    # the E-step through the fast operator follows the direct one (same probes)
+    H, W, k = 24, 20, 7
+    rng = np.random.default_rng(7)
+    taps = rng.standard_normal((k, k))
+    taps /= np.linalg.norm(taps)
+    y = rng.standard_normal(H * W)
+    r1 = O.cofem(O.ConvOperator(taps, H, W), y, 50.0, 3, K=6, tol=1e-11, max_iter=800, seed=3)
+    r2 = O.cofem(O.ConvOperatorFFT(taps, H, W), y, 50.0, 3, K=6, tol=1e-11, max_iter=800, seed=3)
+    assert np.allclose(r1.mu, r2.mu, rtol=1e-8, atol=1e-12 * np.abs(r1.mu).max())
+    assert np.allclose(1.0 / r1.alpha, 1.0 / r2.alpha, rtol=1e-7)

@@ -87,3 +87,33 @@ def test_untrained_network_loss_is_one_per_term():
     f, n = L.NORM_FLOOR, mu_p.size
     assert abs(Lv - (A / (A + f * M) + L.LAMBDA_D * T / (T + f * n))) < 1e-12, Lv
     assert abs(Lv - (1.0 + L.LAMBDA_D)) < 0.01
+
+
+def test_features_hand_computed_2x2():
+    # a 2 x 2 grid worked by hand: beta ||h||^2 = 2 * 0.5 = 1, so d = 1 + alpha
+    # = [[2, 4], [8, 2]]; every clip bound is hit once
+    import math
+    alpha = np.array([1.0, 3.0, 7.0, 1.0])
+    alpha_prev = np.array([1.0, 1.0, 7.0, 15.0])      # d_prev = [[2, 2], [8, 16]]
+    mu = np.array([2.0, 0.0, -2.0, 0.0])              # rms = sqrt(8 / 4) = sqrt(2)
+    s = np.array([0.5, 1e-6, 0.25, 100.0])            # s d = [[1, 4e-6], [2, 200]]
+    f, aux = L.features(alpha, mu, s, 2.0, 0.5, 2, 2, alpha_prev=alpha_prev)
+    r2 = math.sqrt(2.0)
+    ln = math.log
+    want_f = [
+        [[0.5, 0.75], [0.875, 0.5]],                                # alpha / d
+        [[2.0 / r2, 0.0], [-2.0 / r2, 0.0]],                        # mu / rms
+        [[0.0, ln(1e-3) / 3.0], [ln(2.0) / 3.0, ln(200.0) / 3.0]],  # log clip(s d, 1e-3, 1e3) / 3
+        [[ln(2.0) / 10, ln(4.0) / 10], [ln(8.0) / 10, ln(2.0) / 10]],  # log(d / (beta ||h||^2)) / 10
+        [[0.0, ln(0.5) / 10], [0.0, ln(8.0) / 10]],                 # clip(log(d_prev / d)) / 10
+    ]
+    want_aux = [[[2.0, 0.0], [-2.0, 0.0]], [[2.0, 4.0], [8.0, 2.0]], [[1.0, 0.05], [2.0, 20.0]]]
+    np.testing.assert_allclose(f, np.array(want_f), rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(aux, np.array(want_aux), rtol=1e-14, atol=1e-15)
+    # the clip of log(d_prev / d) at +-10: a move of more than e^10
+    f2, _ = L.features(np.array([1e6]), np.array([1.0]), np.array([1.0]), 1.0, 1.0, 1, 1,
+                       alpha_prev=np.array([1e-9]))
+    assert f2[4, 0, 0] == -1.0
+    # a zero mean has rms 1 by definition (no division by zero)
+    f3, _ = L.features(alpha, np.zeros(4), s, 2.0, 0.5, 2, 2)
+    assert np.all(f3[1] == 0.0) and np.all(f3[4] == 0.0)

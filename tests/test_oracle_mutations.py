@@ -97,8 +97,8 @@ def test_mstep_without_s_is_caught(monkeypatch):
 def test_mean_from_wrong_column_is_caught(monkeypatch):
     orig = OC.cofem_estep
 
-    def bad(op, b0, beta, alpha, K, tol, max_iter, seed, t, fixed_iters=None):
-        e = orig(op, b0, beta, alpha, K, tol, max_iter, seed, t, fixed_iters)
+    def bad(op, b0, beta, alpha, K, tol, max_iter, seed, t, fixed_iters=None, stop_rule="frobenius"):
+        e = orig(op, b0, beta, alpha, K, tol, max_iter, seed, t, fixed_iters, stop_rule)
         e.mu = e.X[:, 0].copy()
         return e
     _patch(monkeypatch, "cofem_estep", bad)

@@ -286,3 +286,30 @@ def test_column_permutation_equivariance():
     X, _ = O.cg_solve(O.cofem_oracle.make_apply_A(op2, p.beta, alpha[perm]), B, 1e-13, 1000)
     assert np.allclose(X[:, 3], e.mu[perm], rtol=1e-9, atol=1e-12)
     assert np.allclose(O.diag_estimate(P, X[:, :3]), e.s[perm], rtol=1e-8, atol=1e-12)
+
+
+# ------------------------------------------------- EM-level stop (time to a target)
+def test_em_stop_rule_on_identity_closed_form():
+    # Phi = I: the EM map is scalar per coordinate, so the prior variances
+    # gamma_t = mu_t^2 + 1/(beta + alpha_{t-1}) are known in closed form for
+    # every t; the oracle must stop at the first t whose relative change
+    # ||gamma_t - gamma_{t-1}|| / ||gamma_t|| falls below em_tol, and report it
+    D, beta = 50, 40.0
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal(D) * np.where(rng.random(D) < 0.3, 3.0, 0.05)
+    seq = _identity_recursion(y, beta, np.ones(D), 200)
+    gam_prev = np.ones(D)
+    changes = []
+    for mu, var, a in seq:
+        g = mu * mu + var
+        changes.append(np.sqrt(np.sum((g - gam_prev) ** 2) / np.sum(g * g)))
+        gam_prev = g
+    for em_tol in (1e-2, 1e-3, 1e-5):
+        t_stop = next(i for i, c in enumerate(changes) if c < em_tol) + 1
+        r = O.cofem(O.DenseOperator(np.eye(D)), y, beta, 200, K=2, tol=1e-14, max_iter=50, seed=0,
+                    em_tol=em_tol)
+        assert len(r.stats) == t_stop, (em_tol, len(r.stats), t_stop)
+        assert np.allclose([st["gamma_change"] for st in r.stats], changes[:t_stop], rtol=1e-9)
+        assert np.allclose(r.alpha, seq[t_stop - 1][2], rtol=1e-10)
+    # without em_tol the loop runs T_em iterations
+    assert len(O.cofem(O.DenseOperator(np.eye(D)), y, beta, 7, K=2, tol=1e-14, max_iter=50, seed=0).stats) == 7
