@@ -240,6 +240,33 @@ cofem_status cofem_workspace_size(const cofem_problem* problems, int32_t n_probl
                                   const cofem_params* params, size_t* bytes);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one EM
+ * iteration of Algorithm 1 for one problem without a context and without any
+ * device or pinned allocation.  The same as cofem_init (library-allocated),
+ * cofem_set_alpha(alpha_in), cofem_set_iteration(t), cofem_em_step(1) and
+ * cofem_posterior(mu, s, alpha_out) followed by cofem_destroy, with the same
+ * kernels and the same bits, but every device buffer (packed dictionary, CG
+ * state, reduction partials and counters) laid out in a static array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends.  The layout is rebuilt (and cleared) on every call.
+ * problem, params: as cofem_init with n_problems = 1; precision
+ * COFEM_PREC_FP32 or COFEM_PREC_FP64, no batched form, no
+ * COFEM_FLAG_WARM_PREV (COFEM_ERR_UNSUPPORTED otherwise).  A problem whose
+ * layout exceeds the 64 MiB (cofem_workspace_size) is COFEM_ERR_INVALID_ARG.
+ * alpha_in: device float32, length D (all > 0); t: the EM iteration whose
+ * probes are drawn (0..65535); mu, s, alpha_out: device float32, length D,
+ * each nullable (alpha_out may equal alpha_in); stats: host, nullable (its
+ * ms is host wall time).  Work is enqueued on hip_stream and synchronised
+ * before returning.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.
+ */
+cofem_status cofem_em_step_static(const cofem_problem* problem, const cofem_params* params, const float* alpha_in,
+                                  int32_t t, float* mu, float* s, float* alpha_out, cofem_iter_stats* stats,
+                                  void* hip_stream);
+
+/*
  * Runs `n_iters` EM iterations of Algorithm 1 (E-step by CG, diagonal
  * estimate, M-step).  Synchronises the stream at the end of every EM
  * iteration (the host reads the CG stop flag).  `stats` (host, nullable)

@@ -84,6 +84,8 @@ _SIGNATURES = {
                                        POINTER(ctypes.c_size_t)]),
     "cofem_em_step": (c_int32, [c_void_p, c_int32, POINTER(cofem_iter_stats)]),
     "cofem_em_run": (c_int32, [c_void_p, c_int32, c_double, POINTER(cofem_iter_stats), POINTER(c_int32)]),
+    "cofem_em_step_static": (c_int32, [POINTER(cofem_problem), POINTER(cofem_params), c_void_p, c_int32, c_void_p,
+                                       c_void_p, c_void_p, POINTER(cofem_iter_stats), c_void_p]),
     "cofem_posterior": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "cofem_set_alpha": (c_int32, [c_void_p, c_int32, c_void_p]),
     "cofem_set_iteration": (c_int32, [c_void_p, c_int32]),
@@ -193,6 +195,16 @@ def cofem_em_run(ctx, max_iters: int, em_tol: float, n_problems: int = 1):
     if n_problems == 1:
         return [stats[i].as_dict() for i in range(n.value)]
     return [[stats[i * n_problems + j].as_dict() for j in range(n_problems)] for i in range(n.value)]
+
+
+def cofem_em_step_static(problem: cofem_problem, params: cofem_params, alpha_in, t: int, mu=None, s=None,
+                         alpha_out=None, stream=None):
+    """One EM iteration without a context or any device allocation (the
+    library's static scratch array); returns the iteration's statistics."""
+    st = cofem_iter_stats()
+    _check(load().cofem_em_step_static(ctypes.byref(problem), ctypes.byref(params), _ptr(alpha_in), int(t), _ptr(mu),
+                                       _ptr(s), _ptr(alpha_out), ctypes.byref(st), _stream(stream)))
+    return st.as_dict()
 
 
 def cofem_init_batch(problems, params: cofem_params, stream=None, workspace=None):

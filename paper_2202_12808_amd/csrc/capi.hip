@@ -17,6 +17,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -132,6 +134,7 @@ struct cofem_ctx {
   float *mu = nullptr, *sdiag = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t ev_state = nullptr;  // completion of the state copy of a poll
+  double t0_host = 0.0;           // host clock at the start of an EM iteration
   // optional per-kernel timing: one event before each timed launch, an end
   // marker after the last; CG iterations timed every kt_every-th
   bool ktime = false;
@@ -208,6 +211,31 @@ cofem_status alloc(cofem_ctx* c, T** p, size_t count) {
   } while (0)
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Per-EM-iteration timing: device events when the context has them, else the
+// host clock around the iteration (the allocation-free entry point creates
+// no events; it synchronises before reading the clock anyway).
+double host_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+cofem_status iter_start(cofem_ctx* c) {
+  c->t0_host = host_ms();
+  if (c->ev0) COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  return COFEM_OK;
+}
+cofem_status iter_end(cofem_ctx* c) {
+  if (c->ev1) COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  return COFEM_OK;
+}
+// After the stream has been synchronised past iter_end.
+cofem_status iter_ms(cofem_ctx* c, float* ms) {
+  if (c->ev0 && c->ev1) {
+    COFEM_HIP(c, hipEventElapsedTime(ms, c->ev0, c->ev1));
+  } else {
+    *ms = (float)(host_ms() - c->t0_host);
+  }
+  return COFEM_OK;
+}
 
 void destroy_ctx(cofem_ctx* c) {
   if (!c) return;
@@ -1063,13 +1091,16 @@ cofem_status read_state(cofem_ctx* c) {
 // iterations it enqueued (0 or 1).
 cofem_status poll_state(cofem_ctx* c, bool ahead, bool lowp, int* extra) {
   COFEM_HIP(c, hipMemcpyAsync(c->host_st, c->st, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
-  COFEM_HIP(c, hipEventRecord(c->ev_state, c->stream));
+  if (c->ev_state) COFEM_HIP(c, hipEventRecord(c->ev_state, c->stream));
   *extra = 0;
   if (ahead) {
     COFEM_TRY(run_cg_iterations(c, 1, lowp));
     *extra = 1;
   }
-  COFEM_HIP(c, hipEventSynchronize(c->ev_state));
+  if (c->ev_state)
+    COFEM_HIP(c, hipEventSynchronize(c->ev_state));
+  else
+    COFEM_HIP(c, hipStreamSynchronize(c->stream));
   return COFEM_OK;
 }
 
@@ -1084,7 +1115,7 @@ constexpr int kIrStall = 3;
 cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
   const int t = c->t_next;
   const DenseDims& dd = c->dd;
-  COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  COFEM_TRY(iter_start(c));
   c->kev_used = 0;
   c->sweeps.clear();
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
@@ -1169,7 +1200,7 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
   COFEM_HIP(c, dense_mstep(dd, c->seed, t, c->K, c->Xt, c->xtm, c->alpha, c->alpha_max, c->mu, c->sdiag,
                            c->parts_upd, c->cnts_upd, c->st, c->stream));
   COFEM_TRY(mark(c, -1, 0));
-  COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  COFEM_TRY(iter_end(c));
   COFEM_TRY(read_state(c));
   COFEM_TRY(collect_times(c, 0));
   c->has_solution = true;
@@ -1177,7 +1208,7 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
   c->t_next = t + 1;
   if (out) {
     float ms = 0.0f;
-    COFEM_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    COFEM_TRY(iter_ms(c, &ms));
     out->t = t;
     out->cg_iters = total;
     out->converged = outer < c->tol ? 1 : 0;
@@ -1195,7 +1226,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   if (c->batch) return em_iteration_batch(c, out);
   if (c->precision == COFEM_PREC_BF16_IR) return em_iteration_ir(c, out);
   const int t = c->t_next;
-  COFEM_HIP(c, hipEventRecord(c->ev0, c->stream));
+  COFEM_TRY(iter_start(c));
   c->cg_enq = 0;
   c->kev_used = 0;
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
@@ -1244,7 +1275,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
                             c->red_upd, c->st, c->stream));
   }
   COFEM_TRY(mark(c, -1, 0));
-  COFEM_HIP(c, hipEventRecord(c->ev1, c->stream));
+  COFEM_TRY(iter_end(c));
   COFEM_TRY(read_state(c));
   // (a conv solve of n updates has n + 1 working launches)
   COFEM_TRY(collect_times(c, c->host_st->iter + (folded_update(c) ? 1 : 0)));
@@ -1253,7 +1284,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   c->t_next = t + 1;
   if (out) {
     float ms = 0.0f;
-    COFEM_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    COFEM_TRY(iter_ms(c, &ms));
     out->t = t;
     out->cg_iters = c->host_st->iter;
     out->converged = c->host_st->ratio < c->tol ? 1 : 0;
@@ -1268,11 +1299,9 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   return COFEM_OK;
 }
 
-// A context holding the problem description and the solver controls (no
-// device state yet).
-cofem_ctx* new_ctx(const cofem_problem* problems, const cofem_params* params, void* hip_stream) {
-  cofem_ctx* c = new (std::nothrow) cofem_ctx();
-  if (!c) return nullptr;
+// The problem description and the solver controls of a context (no device
+// state yet).
+void setup_ctx(cofem_ctx* c, const cofem_problem* problems, const cofem_params* params, void* hip_stream) {
   const cofem_problem& p = problems[0];
   c->kind = p.kind;
   c->NT = p.n_tasks > 1 ? p.n_tasks : 1;  // validated: several tasks only for the DCT dictionary
@@ -1292,6 +1321,11 @@ cofem_ctx* new_ctx(const cofem_problem* problems, const cofem_params* params, vo
   c->tol_in = params->ir_inner_tol > 0.0 ? params->ir_inner_tol : 0.1;
   c->max_sweeps = params->ir_max_sweeps > 0 ? params->ir_max_sweeps : 20;
   c->stream = static_cast<hipStream_t>(hip_stream);
+}
+
+cofem_ctx* new_ctx(const cofem_problem* problems, const cofem_params* params, void* hip_stream) {
+  cofem_ctx* c = new (std::nothrow) cofem_ctx();
+  if (c) setup_ctx(c, problems, params, hip_stream);
   return c;
 }
 
@@ -1305,6 +1339,34 @@ cofem_status init_state(cofem_ctx* c, const cofem_problem* problems, int32_t n_p
          : (p.kind == COFEM_DENSE)    ? init_dense(c, p)
          : (p.kind == COFEM_DCT_MASK) ? init_dct(c, p)
                                       : init_conv(c, p);
+}
+
+// Device memory of the allocation-free entry point (cofem_em_step_static): a
+// file-scope array in the library's code object, kStaticScratchBytes on every
+// GPU the library runs on, held until the process ends.  Host code must not
+// pass `scratch` itself to a kernel or copy (on the host that name is only a
+// stand-in); its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and is kept in g_scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+cofem_status static_scratch(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(nullptr, COFEM_ERR_UNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, COFEM_ERR_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return COFEM_OK;
 }
 
 }  // namespace
@@ -1366,6 +1428,60 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   }
   *out = c;
   return COFEM_OK;
+}
+
+cofem_status cofem_em_step_static(const cofem_problem* problem, const cofem_params* params, const float* alpha_in,
+                                  int32_t t, float* mu, float* s, float* alpha_out, cofem_iter_stats* stats,
+                                  void* hip_stream) {
+  std::string why;
+  cofem_status v = validate(problem, 1, params, &why);
+  if (v != COFEM_OK) return fail(nullptr, v, why);
+  if (problem->phi_dtype != COFEM_F32 || (params->flags & (COFEM_FLAG_BATCHED | COFEM_FLAG_EAGER)))
+    return fail(nullptr, COFEM_ERR_UNSUPPORTED, "the allocation-free step takes one float32 problem (no batched form)");
+  if (params->precision == COFEM_PREC_BF16_IR)
+    return fail(nullptr, COFEM_ERR_UNSUPPORTED, "the allocation-free step runs COFEM_PREC_FP32 or COFEM_PREC_FP64");
+  if (params->flags & COFEM_FLAG_WARM_PREV)
+    return fail(nullptr, COFEM_ERR_UNSUPPORTED, "a single stateless step has no previous E-step to start from");
+  if (!alpha_in) return fail(nullptr, COFEM_ERR_INVALID_ARG, "alpha_in is null");
+  if (t < 0 || t >= (1 << 16)) return fail(nullptr, COFEM_ERR_INVALID_ARG, "t must be in [0, 65535]");
+  // the layout this problem needs, counted without touching the device
+  size_t need = 0;
+  {
+    cofem_ctx sz;
+    setup_ctx(&sz, problem, params, hip_stream);
+    sz.sizing = true;
+    const cofem_status st = init_state(&sz, problem, 1, params);
+    delete sz.batch;
+    sz.batch = nullptr;
+    if (st != COFEM_OK) return fail(nullptr, st, sz.err);
+    need = sz.ws_used;
+  }
+  if (need > kStaticScratchBytes)
+    return fail(nullptr, COFEM_ERR_INVALID_ARG,
+                "the problem needs " + std::to_string(need) + " bytes of device memory; the static scratch holds " +
+                    std::to_string(kStaticScratchBytes));
+  cofem_ctx c;
+  setup_ctx(&c, problem, params, hip_stream);
+  CgScalars host_state;  // pageable: the state reads are synchronous copies
+  c.host_st = &host_state;
+  COFEM_HIP(&c, hipGetDevice(&c.device));
+  COFEM_TRY(static_scratch(c.device, &c.ws));
+  c.ws_size = kStaticScratchBytes;
+  cofem_status st = init_state(&c, problem, 1, params);
+  if (st == COFEM_OK) st = push_controls(&c);
+  if (st == COFEM_OK) st = cofem_set_alpha(&c, 0, alpha_in);
+  if (st == COFEM_OK) {
+    c.t_next = t;
+    cofem_iter_stats local;
+    st = em_iteration(&c, stats ? stats : &local);
+  }
+  if (st == COFEM_OK) st = cofem_posterior(&c, 0, mu, s, alpha_out);
+  if (st == COFEM_OK) {
+    const hipError_t e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) st = fail(&c, COFEM_ERR_DEVICE, std::string("static step: ") + hipGetErrorString(e));
+  }
+  if (st != COFEM_OK) g_err = c.err;
+  return st;
 }
 
 cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats) {
