@@ -6,28 +6,30 @@ Algorithm 1 from alpha = 1 (E-step by multi-right-hand-side CG, diagonal
 estimate, M-step), on inputs already resident in HBM.  The reported value is
 EM iterations per second over the timed steps.
 
-Forms (dense workloads): the headline is the mixed-precision form (bf16
-dictionary in the inner CG solves, iterative refinement on the float32
-dictionary's true residual); the plain float32 CG form is timed on the same
-inputs and reported under "forms", with the NMSE between the two final mu.
-`--oracle-trajectory` also runs the float64 oracle over the whole trajectory
-(at the workload's tolerance and at 1/1000 of it) and reports each form's
-NMSE against both.  `--workload batched_64` runs the 64-problem batched form.
+Default workload: the 1024 x 1024 circular convolution with 9x9 taps (D =
+2^20, K = 16, beta = 1e4, eps = 1e-5, U = 400, T_em = 30).  The headline form
+is the learned start (a network trained on the GPU by the library's kernels
+on EM iterates of other seeds predicts each E-step's start; Jacobi-
+preconditioned CG from there); the non-learned control (the previous iterate
+as the start, Jacobi) and plain float32 CG are timed the same way under
+"forms".  Each form's mean after the first m EM iterations is compared with a
+float64 oracle run of the control's algorithm (NMSE, "oracle_trajectory");
+that run is the CPU sample too.  The same line carries, under "secondary",
+the dense 4096 x 16384 workload: bf16 refinement vs float32 CG, both warm-
+started, and float32 CG from zero.
 
 Besides the throughput line the JSON carries:
-  roofline      the dominant operator kernel against its roofline: dense
-                passes by HBM (algorithmic bytes per launch / mean launch
-                time, from HIP events the library records on its stream around
-                the launches of every n-th CG iteration during the timed steps,
-                --timing-every n) against 8 TB/s, with the
-                counter-measured HBM bytes per launch when a stored rocprofv3
-                summary matches the current kernel source; the conv stencil
-                pass by the fp32 vector ALU (its stencil flops per launch /
-                mean launch time) against 157.3 TFLOP/s;
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample (the
-                first E-step, its CG iteration count fixed to the GPU's),
-                scaled to EM iterations per second with the GPU's mean CG count;
-  parity        relative errors of that first GPU step against the oracle.
+  roofline      the dominant operator kernel against HBM: algorithmic bytes
+                per launch / mean launch time, the times from HIP events the
+                library records on its stream around the launches of every
+                n-th CG iteration during the timed steps (--timing-every n),
+                with the counter-measured HBM bytes per launch when a stored
+                rocprofv3 summary matches the current kernel source; for the
+                stencil also its flops against the fp32 vector ALU;
+  cpu_baseline  the float64 oracle timed on this host on a bounded sample,
+                scaled to EM iterations per second at the GPU run's CG counts
+                (with a one-thread figure and the host's CPU model);
+  parity        (dense) relative errors of the first GPU step vs the oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -37,6 +39,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -48,6 +52,7 @@ HBM_PEAK_GBS = 8000.0
 # (packed FP32) x 2.4 GHz.  The library is built without packed FP32
 # instructions, so its own issue ceiling is half of this (78.6 TFLOP/s).
 FP32_VALU_PEAK_TFS = 157.3
+FP32_VALU_ISSUE_TFS = 78.6
 
 
 def algorithmic_flops(p, which):
@@ -84,10 +89,12 @@ KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "u
                 "dense_bf16_ir": {"pass1": "k_dense16_pass1", "pass2": "k_dense16_pass2", "update": "k_dense_update"},
                 "conv": {"pass1": "k_conv_fused"}}
 FORMS = {"fp32": "fp32 probes + fp64 mean column",
-         "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column)",
+         "fp32_warm": "fp32 CG started from the previous mean and diagonal estimate (fp64 mean column)",
+         "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column), started from the "
+                    "previous mean and diagonal estimate",
          "control": "fp32 CG started from the previous mean and diagonal estimate, Jacobi-preconditioned",
          "learned": "fp32 CG started from a learned prediction, Jacobi-preconditioned"}
-CONV_FORMS = ("fp32", "control", "learned")
+DENSE_FORM_ORDER = ("bf16_ir", "fp32_warm", "fp32")
 FORMS_DCT = {"fp32": "inverse-DCT + mask dictionary, plain fp32 CG + fp64 mean column",
              "control": "inverse-DCT + mask dictionary, fp32 CG started from the previous mean and diagonal "
                         "estimate, Jacobi-preconditioned, fp64 mean column"}
@@ -512,55 +519,245 @@ def run_dct(args):
     g.close()
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dense_4096x16384",
-                    choices=["dense_4096x16384", "dense_256x1024", "conv_256x256_k7", "conv_1024x1024_k9",
-                             "batched_64", "dct_4096", "dct_262144"])
-    ap.add_argument("--em-iters", type=int, default=0, help="EM iterations per step (default: workload's)")
-    ap.add_argument("--tasks", type=int, default=1,
-                    help="DCT workloads: T > 1 tasks sharing alpha (multi-task SBL)")
-    ap.add_argument("--timing-reps", type=int, default=20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--timing-every", type=int, default=13,
-                    help="time the launches of every n-th CG iteration with HIP events (1: all; each timed "
-                         "iteration's four events cost a few microseconds of stream time; 13 is coprime to the "
-                         "solver's 8-iteration polling chunks, so the timed iterations fall evenly on every "
-                         "chunk position)")
-    ap.add_argument("--no-kernel-timing", action="store_true",
-                    help="time the steps without the per-launch events (roofline from cofem_time_operator)")
-    ap.add_argument("--calibration-copy-mib", type=int, default=0,
-                    help="first run 3 plain device copies of this many MiB (counter calibration)")
-    ap.add_argument("--form", default=None, choices=sorted(FORMS),
-                    help="solver form timed for the headline value (default: bf16_ir for dense workloads, "
-                         "fp32 for conv)")
-    ap.add_argument("--no-warm", action="store_true",
-                    help="bf16_ir: start every E-step's refinement from zero instead of the previous mean and "
-                         "diagonal estimate")
-    ap.add_argument("--ir-inner-tol", type=float, default=0.0,
-                    help="bf16_ir: relative tolerance of each inner solve (0: the library default, 0.1)")
-    ap.add_argument("--oracle-trajectory", action="store_true",
-                    help="also run the float64 oracle for the whole T_em trajectory (minutes of host time) "
-                         "and report each form's NMSE of mu_T against it")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="dense: do not also time the other form on the same inputs")
-    args = ap.parse_args()
+def cpu_info():
+    """Host CPU model and the number of cores this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
-              file=sys.stderr, flush=True)
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        return os.cpu_count()
+
+
+def nmse(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.sum((a - ref) ** 2) / np.sum(ref ** 2))
+
+
+CONV_FORM_ORDER = ("learned", "control", "fp32")
+
+
+def run_conv(args):
+    """The convolution dictionary (the metric's workload at 1024 x 1024, 9x9
+    taps).  A step is T_em EM iterations from alpha = 1 (cofem_restart).  The
+    headline form is the learned start; the non-learned control (previous
+    iterate + Jacobi) and plain float32 CG are timed the same way and
+    reported under "forms".  Every form's mean after the first m EM
+    iterations is compared with the float64 oracle run of the control's
+    algorithm over the same m iterations (its FFT route); that oracle run is
+    also the CPU sample."""
+    import torch
+
+    from paper_2202_12808_amd import synth
+    from paper_2202_12808_amd.cofem import CoFEM
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    p = synth.WORKLOADS[args.workload](0)
+    T_em = args.em_iters or p.T_em
+    m_ref = args.oracle_em_iters
+    log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} beta={p.beta} tol={p.tol} U={p.max_iter} T_em={T_em} "
+        f"(inputs generated in {time.perf_counter() - t_gen:.1f}s)")
+    form = args.form or "learned"
+    if form not in CONV_FORM_ORDER:
+        print(f"--form {form} is not built for the convolution dictionary", file=sys.stderr, flush=True)
         sys.exit(2)
+    taps = torch.from_numpy(p.taps).to(dev)
+    y = torch.from_numpy(p.y).to(dev)
+    net, train_info = train_predictor(p, dev)
 
-    if args.workload == "batched_64":
-        return run_batched(args)
-    if args.workload.startswith("dct"):
-        return run_dct(args)
+    def make(f):
+        ctl = f == "control"
+        c = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, jacobi=ctl,
+                       warm_start=ctl)
+        if f == "learned":
+            c.set_predictor(net)
+        return c
 
-    import numpy as np
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration: 3 copies of {4 * n} bytes")
+        del src, dst
+
+    def timed(f, kernel_timing):
+        g = make(f)
+        for _ in range(args.warmup):
+            g.restart()
+            g.em_step(T_em)
+        if kernel_timing:
+            g.set_kernel_timing(args.timing_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            g.restart()
+            st = g.em_step(T_em)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res = {"value": args.steps * T_em / el, "elapsed": el, "stats": st,
+               "mu_T": g.solution()[1].cpu().numpy()}
+        if kernel_timing:
+            res["kt"] = g.kernel_timing()
+            g.set_kernel_timing(0)
+        g.restart()
+        res["stats_m"] = g.em_step(m_ref)
+        res["mu_m"] = g.solution()[1].cpu().numpy()
+        g.close()
+        cg = [x["cg_iters"] for x in st]
+        log(f"form {f}: {res['value']:.3f} EM it/s over {args.steps} steps of {T_em} EM iterations; "
+            f"CG per EM {cg}")
+        return res
+
+    runs = {form: timed(form, not args.no_kernel_timing)}
+    if not args.no_compare:
+        for f in CONV_FORM_ORDER:
+            if f != form:
+                runs[f] = timed(f, False)
+    head = runs[form]
+    value, elapsed = head["value"], head["elapsed"]
+    cg_counts = [x["cg_iters"] for x in head["stats"]]
+
+    # roofline of the fused stencil iteration (the dominant kernel)
+    roofline = None
+    if "kt" in head:
+        kt = head["kt"]["pass1"]
+        ms = kt[0] / max(kt[1], 1)
+        nbytes = algorithmic_bytes(p, "pass1")
+        nflops = algorithmic_flops(p, "pass1")
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        tfs = nflops / (ms * 1e-3) / 1e12
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": stored_traffic("conv", "k_conv_fused", p.name), "kernel": "k_conv_fused",
+                    "bytes_per_launch": nbytes, "ms_per_launch": round(ms, 5), "launches": kt[1],
+                    "timing": f"HIP events around the launches of every {args.timing_every}-th CG iteration "
+                              "during the timed steps",
+                    "alu": {"flops_per_launch": nflops, "achieved_tflops": round(tfs, 2),
+                            "peak_issue_tflops": FP32_VALU_ISSUE_TFS, "frac_issue": round(tfs / FP32_VALU_ISSUE_TFS, 4),
+                            "peak_published_tflops": FP32_VALU_PEAK_TFS,
+                            "frac_published": round(tfs / FP32_VALU_PEAK_TFS, 4)}}
+        log(f"roofline: k_conv_fused {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of "
+            f"HBM), {tfs:.2f} TFLOP/s ({100 * tfs / FP32_VALU_ISSUE_TFS:.1f}% of the non-packed fp32 issue rate)")
+
+    # the float64 reference: the oracle run of the control's algorithm over
+    # the first m EM iterations (FFT route), also the CPU sample
+    traj = cpu = None
+    nz = np.linalg.norm(p.z)
+    forms = {}
+    for f, r in runs.items():
+        forms[f] = {"value": round(r["value"], 4), "cg_iters_per_em": [x["cg_iters"] for x in r["stats"]],
+                    "nrmse_vs_truth": round(float(np.linalg.norm(r["mu_T"] - p.z) / nz), 6)}
+    if "fp32" in runs:
+        ref = runs["fp32"]["mu_T"]
+        forms["nmse_mu_T_vs_fp32"] = {f: nmse(r["mu_T"], ref) for f, r in runs.items()}
+    forms["training"] = train_info
+    if not args.no_cpu_baseline:
+        import oracle as O
+        model, ncpu = cpu_info()
+        op = O.ConvOperatorFFT(p.taps.astype(np.float64), p.H, p.W)
+        y64 = p.y.astype(np.float64)
+        log(f"oracle reference: {m_ref} EM iterations of the control's algorithm on {op.workers} threads ...")
+        t0 = time.perf_counter()
+        ref = O.cofem(op, y64, p.beta, m_ref, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, warm_start=True,
+                      jacobi=True)
+        el = time.perf_counter() - t0
+        cg_or = [x["cg_iters"] for x in ref.stats]
+        # the per-EM-iteration work besides CG (probes, diagonal estimate, M-step)
+        t1 = time.perf_counter()
+        Pm = O.rademacher_probes(p.seed, 1, p.K, p.D)
+        O.mstep(ref.mu, O.diag_estimate(Pm, Pm))
+        c_em = time.perf_counter() - t1
+        c_cg = max(el - m_ref * c_em, 1e-9) / max(sum(cg_or), 1)
+        # one thread: two CG iterations of the first E-step
+        try:
+            from threadpoolctl import threadpool_limits
+        except Exception:
+            threadpool_limits = None
+        op1 = O.ConvOperatorFFT(p.taps.astype(np.float64), p.H, p.W)
+        op1.workers = 1
+        b0 = p.beta * op1.apply_t(y64)
+        ctx = threadpool_limits(1) if threadpool_limits else None
+        t2 = time.perf_counter()
+        if ctx:
+            with ctx:
+                O.cofem_estep(op1, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1, fixed_iters=2)
+        else:
+            O.cofem_estep(op1, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1, fixed_iters=2)
+        el1 = time.perf_counter() - t2
+        c_cg1 = max(el1 - c_em, 1e-9) / 2.0
+
+        def em_rate(per_cg, per_em):
+            return T_em / sum(per_cg * c + per_em for c in cg_counts)
+
+        cpu = {"value": round(em_rate(c_cg, c_em), 6), "unit": "EM it/s", "cores": int(op.workers), "kind": "oracle",
+               "sample": f"float64 oracle ({op.workers} FFT workers, {blas_threads()} BLAS threads) ran the first "
+                         f"{m_ref} EM iterations of the control's algorithm ({sum(cg_or)} CG iterations, "
+                         f"{cg_or}) in {el:.1f}s: {c_cg * 1e3:.0f} ms per CG iteration plus {c_em * 1e3:.0f} ms "
+                         f"per EM iteration (probes, diagonal estimate, M-step); scaled to the headline run's "
+                         f"{sum(cg_counts)} CG iterations over {T_em} EM iterations",
+               "first_m_em_per_s": round(m_ref / el, 6),
+               "one_thread": {"value": round(em_rate(c_cg1, c_em), 6), "ms_per_cg_iter": round(c_cg1 * 1e3, 1),
+                              "sample": "two CG iterations of the first E-step on one thread, scaled the same way"},
+               "host": {"cpu_model": model, "nproc": ncpu}}
+        traj = {"em_iters": m_ref, "reference": "float64 oracle, control's algorithm (warm start + Jacobi), "
+                                                "FFT route", "oracle_cg_iters": cg_or, "host_seconds": round(el, 1),
+                "nmse_mu_vs_oracle": {f: nmse(r["mu_m"], ref.mu) for f, r in runs.items()},
+                "cg_iters_gpu": {f: [x["cg_iters"] for x in r["stats_m"]] for f, r in runs.items()}}
+        log(f"cpu oracle: {cpu['value']:.5f} EM it/s ({c_cg * 1e3:.0f} ms per CG iteration on {op.workers} threads, "
+            f"{c_cg1 * 1e3:.0f} ms on one); NMSE of mu after {m_ref} EM iterations vs the oracle "
+            f"{traj['nmse_mu_vs_oracle']}")
+
+    secondary = None
+    if not args.no_secondary:
+        a2 = argparse.Namespace(**vars(args))
+        a2.workload, a2.form, a2.em_iters = "dense_4096x16384", None, 0
+        net.close()
+        torch.cuda.empty_cache()
+        secondary = run_dense(a2, emit=False)
+
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "EM it/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
+                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": form, "form_detail": FORMS[form],
+                   "cg_iters_per_em_mean": round(float(np.mean(cg_counts)), 2),
+                   "nrmse_vs_truth": forms[form]["nrmse_vs_truth"]},
+        "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "oracle_trajectory": traj,
+        "secondary": secondary,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_dense(args, emit=True):
+    """Dense workloads.  The headline form is the mixed-precision one
+    (bf16 dictionary in the inner CG solves, iterative refinement on the
+    float32 dictionary's true residual, each E-step started from the previous
+    mean and diagonal estimate); plain float32 CG started the same way
+    (fp32_warm) and from zero (fp32) are timed on the same inputs."""
     import torch
 
     from paper_2202_12808_amd import synth
@@ -574,278 +771,189 @@ def main():
     T_em = args.em_iters or p.T_em
     log(f"workload {p.name}: N={p.N} D={p.D} K={p.K} beta={p.beta} tol={p.tol} U={p.max_iter} "
         f"T_em={T_em} (inputs generated in {time.perf_counter() - t_gen:.1f}s)")
-
-    if args.form is None:
-        args.form = "bf16_ir" if p.kind == "dense" else "learned"
-    if (args.form == "bf16_ir" and p.kind != "dense") or (args.form in ("control", "learned") and p.kind == "dense"):
-        print(f"--form {args.form} is not built for this dictionary kind", file=sys.stderr, flush=True)
+    form = args.form or "bf16_ir"
+    if form not in DENSE_FORM_ORDER:
+        print(f"--form {form} is not built for dense dictionaries", file=sys.stderr, flush=True)
         sys.exit(2)
     y = torch.from_numpy(p.y).to(dev)
-    phi = torch.from_numpy(p.phi).to(dev) if p.kind == "dense" else None
+    phi = torch.from_numpy(p.phi).to(dev)
 
-    net = None
-    train_info = None
-    if p.kind == "conv" and (args.form == "learned" or not args.no_compare):
-        net, train_info = train_predictor(p, dev)
+    def make(f):
+        prec = "bf16_ir" if f == "bf16_ir" else "fp32"
+        warm = (f == "bf16_ir" and not args.no_warm) or f == "fp32_warm"
+        return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, precision=prec,
+                           ir_inner_tol=args.ir_inner_tol, warm_start=warm)
 
-    def make(form):
-        if p.kind == "dense":
-            return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, precision=form,
-                               ir_inner_tol=args.ir_inner_tol, warm_start=(form == "bf16_ir" and not args.no_warm))
-        taps = torch.from_numpy(p.taps).to(dev)
-        ctl = form == "control"
-        c = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, jacobi=ctl,
-                       warm_start=ctl)
-        if form == "learned":
-            c.set_predictor(net)
-        return c
-
-    g = make(args.form)
-    ones = torch.ones(p.D, dtype=torch.float32, device=dev)
-    if args.calibration_copy_mib > 0:
-        n = args.calibration_copy_mib << 18
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+    def timed(f, kernel_timing):
+        g = make(f)
+        for _ in range(max(args.warmup, 1)):
+            g.restart()
+            g.em_step(T_em)
+        if kernel_timing:
+            g.set_kernel_timing(args.timing_every)
         torch.cuda.synchronize()
-        log(f"calibration: 3 copies of {4 * n} bytes")
-        del src, dst
-
-    def one_step():
-        g.set_alpha(ones)
-        g.set_iteration(1)
-        return g.em_step(T_em)
-
-    # first E-step alone (for the parity and the CPU sample)
-    g.set_alpha(ones)
-    g.set_iteration(1)
-    first = g.em_step(1)[0]
-    first_sweeps = g.ir_sweeps() if args.form == "bf16_ir" else None
-    mu1, s1, a1 = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
-
-    for w in range(args.warmup):
-        st = one_step()
-        log(f"warmup {w + 1}/{args.warmup}: cg iters {sum(x['cg_iters'] for x in st)}")
-
-    g.set_kernel_timing(0 if args.no_kernel_timing else args.timing_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    all_stats = []
-    for k in range(args.steps):
-        all_stats.append(one_step())
-        log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stats = all_stats[-1]
-    cg_counts = [x["cg_iters"] for x in stats]
-    mean_cg = float(np.mean(cg_counts))
-    value = args.steps * T_em / elapsed
-    mu_T = g.posterior()[0].cpu().numpy().astype(np.float64)
-    nrmse = float(np.linalg.norm(mu_T - p.z) / np.linalg.norm(p.z))
-    log(f"{value:.3f} EM it/s; CG iterations per EM iteration: mean {mean_cg:.1f}, "
-        f"min {min(cg_counts)}, max {max(cg_counts)}; NRMSE vs ground truth {nrmse:.4f}")
-
-    # roofline of the dominant operator kernel: mean launch time inside the
-    # timed solves (events recorded by the library on its stream)
-    names = KERNEL_NAMES["dense_bf16_ir" if args.form == "bf16_ir" else p.kind]
-    phi_bytes = 2 if args.form == "bf16_ir" else 4
-    ops = [k for k in ("pass1", "pass2") if k in names]
-    if not args.no_kernel_timing:
-        kt = g.kernel_timing()
-        g.set_kernel_timing(False)
-        total = {k: kt[k][0] for k in names}
-        per = {k: kt[k][0] / max(kt[k][1], 1) for k in names}
-        launches = {k: kt[k][1] for k in names}
-        source = (f"HIP events around the launches of every {args.timing_every}-th CG iteration "
-                  "during the timed steps")
-    else:
-        ms = g.time_operator(args.timing_reps)
-        per = {k: ms[i] for i, k in enumerate(ops)}
-        total, launches = dict(per), {k: args.timing_reps for k in ops}
-        source = "cofem_time_operator back-to-back launches"
-    dom = max(ops, key=lambda k: total[k])
-    nbytes = algorithmic_bytes(p, dom, phi_bytes)
-    gbs = nbytes / (per[dom] * 1e-3) / 1e9
-    traffic = stored_traffic("dense_bf16_ir" if args.form == "bf16_ir" else p.kind, names[dom], p.name)
-    if p.kind == "conv":
-        # the fused stencil pass is bound by the vector ALU (2 k^2 FMAs per
-        # pixel and column against a few bytes), not by HBM
-        nflops = algorithmic_flops(p, dom)
-        achieved = nflops / (per[dom] * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VALU_PEAK_TFS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP32_VALU_PEAK_TFS, 4), "traffic": traffic, "kernel": names[dom],
-                    "flops_per_launch": nflops, "bytes_per_launch": nbytes, "hbm_gbs": round(gbs, 1),
-                    "ms_per_launch": round(per[dom], 5), "timing": source}
-        log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.2f} TFLOP/s "
-            f"({100 * achieved / FP32_VALU_PEAK_TFS:.1f}% of the fp32 vector peak), {gbs:.0f} GB/s")
-    else:
-        achieved = gbs
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": names[dom],
-                    "bytes_per_launch": nbytes, "ms_per_launch": round(per[dom], 5), "timing": source}
-        log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {achieved:.0f} GB/s "
-            f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
-    roofline["kernels"] = {names[k]: {"ms_per_launch": round(per[k], 5), "launches": launches[k]} for k in per}
-    log("per-launch us " + ", ".join(f"{names[k]} {per[k] * 1e3:.1f}" for k in per))
-
-    # the other form on the same inputs (dense): throughput and how far its
-    # final mu lies from this form's
-    forms = None
-    mu_T2 = None
-    mean_cg_fp32 = mean_cg if args.form == "fp32" else None
-    if p.kind == "conv" and not args.no_compare:
-        forms = {args.form: {"value": round(value, 4), "cg_iters_per_em": cg_counts}}
-        mus = {args.form: mu_T}
-        for other in CONV_FORMS:
-            if other == args.form:
-                continue
-            g2 = make(other)
-            g2.set_alpha(ones)
-            g2.set_iteration(1)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            st2 = g2.em_step(T_em)
-            torch.cuda.synchronize()
-            el2 = time.perf_counter() - t1
-            mus[other] = g2.posterior()[0].cpu().numpy().astype(np.float64)
-            forms[other] = {"value": round(T_em / el2, 4), "cg_iters_per_em": [x["cg_iters"] for x in st2]}
-            if other == "fp32":
-                mean_cg_fp32 = float(np.mean(forms[other]["cg_iters_per_em"]))
-            log(f"form {other}: {forms[other]['value']:.3f} EM it/s; CG per EM {forms[other]['cg_iters_per_em']}")
-            g2.close()
-        ref = mus["fp32"]
-        forms["nmse_mu_T_vs_fp32"] = {k: float(np.sum((m - ref) ** 2) / np.sum(ref ** 2)) for k, m in mus.items()}
-        forms["training"] = train_info
-    if p.kind == "dense" and not args.no_compare:
-        other = "bf16_ir" if args.form == "fp32" else "fp32"
-        g2 = make(other)
-        for w in range(max(args.warmup, 1)):
-            g2.set_alpha(ones)
-            g2.set_iteration(1)
-            g2.em_step(T_em)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        t0 = time.perf_counter()
         for k in range(args.steps):
-            g2.set_alpha(ones)
-            g2.set_iteration(1)
-            st2 = g2.em_step(T_em)
+            g.restart()
+            st = g.em_step(T_em)
         torch.cuda.synchronize()
-        el2 = time.perf_counter() - t1
-        mu_T2 = g2.posterior()[0].cpu().numpy().astype(np.float64)
-        cg2 = [x["cg_iters"] for x in st2]
-        if other == "fp32":
-            mean_cg_fp32 = float(np.mean(cg2))
-        ref_mu = mu_T if args.form == "fp32" else mu_T2
-        oth_mu = mu_T2 if args.form == "fp32" else mu_T
-        forms = {
-            args.form: {"value": round(value, 4), "cg_iters_per_em_mean": round(mean_cg, 2)},
-            other: {"value": round(args.steps * T_em / el2, 4), "cg_iters_per_em_mean": round(float(np.mean(cg2)), 2),
-                    "nrmse_vs_truth": round(float(np.linalg.norm(mu_T2 - p.z) / np.linalg.norm(p.z)), 6)},
-            "nmse_bf16_ir_vs_fp32_mu_T": float(np.sum((oth_mu - ref_mu) ** 2) / np.sum(ref_mu ** 2)),
-        }
-        if other == "bf16_ir" or args.form == "bf16_ir":
-            sw = [x["ir_sweeps"] for x in (st2 if other == "bf16_ir" else stats)]
-            forms["bf16_ir"]["ir_sweeps_per_em_mean"] = round(float(np.mean(sw)), 2)
-        log(f"other form {other}: {forms[other]['value']:.3f} EM it/s; NMSE(mu_T) between forms "
-            f"{forms['nmse_bf16_ir_vs_fp32_mu_T']:.3e}")
-        g2.close()
+        el = time.perf_counter() - t0
+        res = {"value": args.steps * T_em / el, "elapsed": el, "stats": st,
+               "mu_T": g.solution()[1].cpu().numpy()}
+        if kernel_timing:
+            res["kt"] = g.kernel_timing()
+            g.set_kernel_timing(0)
+        # the first E-step alone (parity and the CPU sample)
+        g.restart()
+        res["first"] = g.em_step(1)[0]
+        res["first_post"] = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+        res["first_sweeps"] = g.ir_sweeps() if f == "bf16_ir" else None
+        g.close()
+        cg = [x["cg_iters"] for x in st]
+        log(f"form {f}: {res['value']:.3f} EM it/s; CG per EM mean {np.mean(cg):.1f}")
+        return res
 
-    traj = None
-    if args.oracle_trajectory:
-        import oracle as O
-        op_t = (O.DenseOperator(p.phi.astype(np.float64)) if p.kind == "dense"
-                else O.ConvOperator(p.taps.astype(np.float64), p.H, p.W))
-        # two float64 trajectories: the oracle at the workload's tolerance (the
-        # plain form's twin) and a tight-tolerance reference (eps / 1000, cap
-        # 3U) that neither form's stopping point is privileged against
-        tt0 = time.perf_counter()
-        res = O.cofem(op_t, p.y, p.beta, T_em, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed)
-        tight = O.cofem(op_t, p.y, p.beta, T_em, p.K, tol=p.tol * 1e-3, max_iter=3 * p.max_iter, seed=p.seed)
-        tt = time.perf_counter() - tt0
+    runs = {form: timed(form, not args.no_kernel_timing)}
+    if not args.no_compare:
+        for f in DENSE_FORM_ORDER:
+            if f != form:
+                runs[f] = timed(f, False)
+    head = runs[form]
+    value, elapsed = head["value"], head["elapsed"]
+    cg_counts = [x["cg_iters"] for x in head["stats"]]
+    mean_cg = float(np.mean(cg_counts))
+    nz = np.linalg.norm(p.z)
 
-        def nmse(m, ref):
-            return float(np.sum((m - ref.mu) ** 2) / np.sum(ref.mu ** 2))
-        mus = {args.form: mu_T}
-        if mu_T2 is not None:
-            mus["bf16_ir" if args.form == "fp32" else "fp32"] = mu_T2
-        traj = {"T_em": T_em, "host_seconds": round(tt, 1),
-                "nmse_vs_oracle": {k: nmse(m, res) for k, m in mus.items()},
-                "nmse_vs_tight_oracle": {k: nmse(m, tight) for k, m in mus.items()},
-                "oracle_vs_tight_oracle": nmse(res.mu, tight)}
-        log(f"oracle trajectories ({tt:.0f}s): NMSE of mu_T vs oracle {traj['nmse_vs_oracle']}; "
-            f"vs tight oracle {traj['nmse_vs_tight_oracle']}; oracle itself vs tight {traj['oracle_vs_tight_oracle']:.3e}")
+    roofline = None
+    if "kt" in head:
+        names = KERNEL_NAMES["dense_bf16_ir" if form == "bf16_ir" else "dense"]
+        kt = head["kt"]
+        per = {k: kt[k][0] / max(kt[k][1], 1) for k in names}
+        dom = max(("pass1", "pass2"), key=lambda k: kt[k][0])
+        phi_bytes = 2 if form == "bf16_ir" else 4
+        nbytes = algorithmic_bytes(p, dom, phi_bytes)
+        gbs = nbytes / (per[dom] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": stored_traffic("dense_bf16_ir" if form == "bf16_ir" else "dense", names[dom], p.name),
+                    "kernel": names[dom], "bytes_per_launch": nbytes, "ms_per_launch": round(per[dom], 5),
+                    "timing": f"HIP events around the launches of every {args.timing_every}-th CG iteration "
+                              "during the timed steps",
+                    "kernels": {names[k]: {"ms_per_launch": round(per[k], 5), "launches": kt[k][1]} for k in names}}
+        log(f"roofline: {names[dom]} {per[dom] * 1e3:.1f} us/launch, {gbs:.0f} GB/s "
+            f"({100 * gbs / HBM_PEAK_GBS:.1f}% of HBM)")
 
-    cpu = None
-    parity = None
+    forms = {f: {"value": round(r["value"], 4), "cg_iters_per_em_mean": round(float(np.mean(
+        [x["cg_iters"] for x in r["stats"]])), 2), "nrmse_vs_truth": round(float(np.linalg.norm(r["mu_T"] - p.z) / nz), 6)}
+        for f, r in runs.items()}
+    if "bf16_ir" in runs:
+        forms["bf16_ir"]["ir_sweeps_per_em_mean"] = round(float(np.mean([x["ir_sweeps"] for x in
+                                                                         runs["bf16_ir"]["stats"]])), 2)
+    if "fp32" in runs:
+        forms["nmse_mu_T_vs_fp32"] = {f: nmse(r["mu_T"], runs["fp32"]["mu_T"]) for f, r in runs.items()}
+
+    cpu = parity = None
     if not args.no_cpu_baseline:
         import oracle as O
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [os.cpu_count()])
-        except Exception:
-            threads = os.cpu_count()
-        if p.kind == "dense":
-            op = O.DenseOperator(p.phi.astype(np.float64))
-        else:
-            op = O.ConvOperator(p.taps.astype(np.float64), p.H, p.W)
+        threads = blas_threads()
+        op = O.DenseOperator(p.phi.astype(np.float64))
+        first = head["first"]
         n1 = first["cg_iters"]
         tc0 = time.perf_counter()
         b0 = p.beta * op.apply_t(p.y.astype(np.float64))
-        if args.form == "bf16_ir":
-            # the oracle's refinement replays the GPU's sweeps (inner operator bf16(Phi))
+        if form == "bf16_ir":
             opb = O.DenseOperator(synth.round_to_bf16(p.phi).astype(np.float64))
             e, _ = O.cofem_estep_ir(op, opb, b0, p.beta, np.ones(p.D), p.K, p.tol, args.ir_inner_tol or 0.1,
-                                    p.max_iter, 20, p.seed, 1, fixed_inner=first_sweeps)
-            n_ops = n1 + 2 * len(first_sweeps)  # inner iterations + outer residuals (2 operator halves each)
+                                    p.max_iter, 20, p.seed, 1, fixed_inner=head["first_sweeps"])
+            # inner iterations plus the outer residuals: one operator application each
+            n_ops = n1 + len(head["first_sweeps"])
         else:
-            e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1,
-                              fixed_iters=n1)
+            e = O.cofem_estep(op, b0, p.beta, np.ones(p.D), p.K, p.tol, p.max_iter, p.seed, 1, fixed_iters=n1)
             n_ops = n1
         a_ref, _ = O.mstep(e.mu, e.s)
         t_sample = time.perf_counter() - tc0
         per_cg = t_sample / max(n_ops, 1)
-        scale_cg = mean_cg_fp32 if mean_cg_fp32 is not None else mean_cg
-        cpu_em_per_s = 1.0 / (per_cg * scale_cg)
-        cpu = {"value": round(cpu_em_per_s, 5), "unit": "EM it/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"first E-step + M-step of {p.name} ({n_ops} operator applications) took "
-                         f"{t_sample:.2f}s on the host; scaled to the plain float32 GPU run's mean of "
-                         f"{scale_cg:.1f} CG iterations per EM iteration"}
-
-        def rel(a, b):
-            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-        parity = {"step": 1, "cg_iters": n1, "relerr_mu": rel(mu1, e.mu), "relerr_s": rel(s1, e.s),
-                  "relerr_alpha": rel(a1, a_ref), "nmse_mu": rel(mu1, e.mu) ** 2}
-        if first_sweeps is not None:
-            parity["ir_sweeps"] = first_sweeps
-        log(f"cpu oracle: {cpu_em_per_s:.4f} EM it/s on {threads} threads; parity {parity}")
+        scale = float(np.mean([x["cg_iters"] for x in runs["fp32"]["stats"]])) if "fp32" in runs else mean_cg
+        model, ncpu = cpu_info()
+        cpu = {"value": round(1.0 / (per_cg * scale), 5), "unit": "EM it/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"first E-step + M-step of {p.name} ({n_ops} operator applications) took {t_sample:.2f}s "
+                         f"on the host; scaled to the plain float32 form's mean of {scale:.1f} CG iterations per "
+                         f"EM iteration", "host": {"cpu_model": model, "nproc": ncpu}}
+        mu1, s1, a1 = head["first_post"]
+        parity = {"step": 1, "cg_iters": n1, "relerr_mu": float(np.linalg.norm(mu1 - e.mu) / np.linalg.norm(e.mu)),
+                  "relerr_s": float(np.linalg.norm(s1 - e.s) / np.linalg.norm(e.s)),
+                  "relerr_inv_alpha": float(np.linalg.norm(1 / a1 - 1 / a_ref) / np.linalg.norm(1 / a_ref))}
+        if head["first_sweeps"] is not None:
+            parity["ir_sweeps"] = head["first_sweeps"]
+        log(f"cpu oracle: {cpu['value']:.4f} EM it/s on {threads} threads; parity {parity}")
 
     out = {
-        "metric": METRIC,
-        "value": round(value, 4),
-        "unit": "EM it/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "bf16+f32" if args.form == "bf16_ir" else "f32",
-        "data": "synthetic",
+        "metric": METRIC if emit else "EM it/s of the dense workload (secondary)", "value": round(value, 4),
+        "unit": "EM it/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32" if form == "bf16_ir" else "f32", "data": "synthetic",
         "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
-                   "cg_max_iter": p.max_iter, "T_em": T_em,
-                   "form": FORMS[args.form] + (", each E-step warm-started from the previous mean and diagonal "
-                                               "estimate" if args.form == "bf16_ir" and not args.no_warm else ""),
-                   "cg_iters_per_em_mean": round(mean_cg, 2), "nrmse_vs_truth": round(nrmse, 6)},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "parity": parity,
-        "forms": forms,
-        "oracle_trajectory": traj,
+                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": form, "form_detail": FORMS[form],
+                   "cg_iters_per_em_mean": round(mean_cg, 2), "nrmse_vs_truth": forms[form]["nrmse_vs_truth"]},
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "forms": forms,
     }
-    print(json.dumps(out), flush=True)
-    g.close()
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="conv_1024x1024_k9",
+                    choices=["conv_1024x1024_k9", "conv_256x256_k7", "dense_4096x16384", "dense_256x1024",
+                             "batched_64", "dct_4096", "dct_262144"])
+    ap.add_argument("--em-iters", type=int, default=0, help="EM iterations per step (default: workload's)")
+    ap.add_argument("--tasks", type=int, default=1,
+                    help="DCT workloads: T > 1 tasks sharing alpha (multi-task SBL)")
+    ap.add_argument("--timing-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the float64 oracle (CPU sample, parity and the NMSE reference)")
+    ap.add_argument("--oracle-em-iters", type=int, default=3,
+                    help="conv workloads: EM iterations of the float64 oracle reference and CPU sample")
+    ap.add_argument("--timing-every", type=int, default=13,
+                    help="time the launches of every n-th CG iteration with HIP events (1: all; each timed "
+                         "iteration's events cost a few microseconds of stream time; 13 is coprime to the "
+                         "solver's 8-iteration polling chunks, so the timed iterations fall evenly on every "
+                         "chunk position)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time the steps without the per-launch events (roofline from cofem_time_operator)")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first run 3 plain device copies of this many MiB (counter calibration)")
+    ap.add_argument("--form", default=None, choices=sorted(FORMS),
+                    help="solver form timed for the headline value (default: learned for conv, bf16_ir for "
+                         "dense, control for DCT)")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="bf16_ir: start every E-step's refinement from zero instead of the previous mean and "
+                         "diagonal estimate")
+    ap.add_argument("--ir-inner-tol", type=float, default=0.0,
+                    help="bf16_ir: relative tolerance of each inner solve (0: the library default, 0.1)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="time only the headline form")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="conv workloads: skip the dense 4096 x 16384 summary carried in the same line")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    if args.workload == "batched_64":
+        return run_batched(args)
+    if args.workload.startswith("dct"):
+        return run_dct(args)
+    if args.workload.startswith("conv"):
+        return run_conv(args)
+    return run_dense(args)
 
 
 if __name__ == "__main__":

@@ -624,7 +624,8 @@ def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
           max_iter: int, seed: int, alpha_max: float = ALPHA_MAX_DEFAULT,
           alpha0: Optional[np.ndarray] = None, t0: int = 1,
           fixed_iters=None, stop_rule: str = "frobenius",
-          em_tol: Optional[float] = None) -> CoFEMResult:
+          em_tol: Optional[float] = None, warm_start: bool = False,
+          jacobi: bool = False) -> CoFEMResult:
     """CovarianceFreeEM(y, Phi, beta, T_em, K) of Algorithm 1.
 
     alpha starts at 1 (or ``alpha0``); EM iterations are numbered t0, t0+1, ...
@@ -633,16 +634,28 @@ def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
     alpha together with mu and s of the last E-step, as Algorithm 1 does.
     With ``em_tol`` the loop also ends after the first M-step whose
     ``gamma_change`` is below em_tol (at most T_em iterations).
+
+    ``warm_start`` / ``jacobi`` (not in the paper): each solve after the first
+    starts from X0 = [max(s_prev, 0) (.) p_k | mu_prev], and/or is
+    preconditioned by the inverse diagonal of A, 1 / (beta ||Phi e_j||^2 +
+    alpha_j) (``cofem_estep_pcg``); the stop test is unchanged.
     """
     D = op.D
     alpha = np.ones(D) if alpha0 is None else np.asarray(alpha0, np.float64).copy()
     b0 = beta * op.apply_t(np.asarray(y, np.float64))
+    cn = op.column_norms_sq() if jacobi else None
     stats = []
     mu = s = None
     for i in range(T_em):
         t = t0 + i
         fi = fixed_iters[i] if isinstance(fixed_iters, (list, tuple, np.ndarray)) else fixed_iters
-        e = cofem_estep(op, b0, beta, alpha, K, tol, max_iter, seed, t, fi, stop_rule)
+        if warm_start or jacobi:
+            start = dict(mu0=mu, d0=np.maximum(s, 0.0)) if (warm_start and mu is not None) else {}
+            minv = 1.0 / (beta * cn + alpha) if jacobi else None
+            e = cofem_estep_pcg(op, b0, beta, alpha, K, tol, max_iter, seed, t, minv=minv, fixed_iters=fi,
+                                stop_rule=stop_rule, **start)
+        else:
+            e = cofem_estep(op, b0, beta, alpha, K, tol, max_iter, seed, t, fi, stop_rule)
         mu, s = e.mu, e.s
         alpha_old = alpha
         alpha, n_clamped = mstep(mu, s, alpha_max)

@@ -343,6 +343,8 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   if (lowp) {
     COFEM_TRY(alloc(c, &c->phiA16, (size_t)dd.Np * dd.Dp));
     COFEM_TRY(alloc(c, &c->phiB16, (size_t)dd.Np * dd.Dp));
+  }
+  if (lowp || (c->flags & COFEM_FLAG_WARM_PREV)) {
     COFEM_TRY(alloc(c, &c->Xt, blk));
     COFEM_TRY(alloc(c, &c->xtm, dd.Dp));
   }
@@ -798,11 +800,10 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
            COFEM_ERR_UNSUPPORTED;
   if ((q->flags & COFEM_FLAG_JACOBI) && (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
     return *why = "the Jacobi preconditioner is built for convolution and DCT dictionaries", COFEM_ERR_UNSUPPORTED;
-  if ((q->flags & COFEM_FLAG_WARM_PREV) &&
-      (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK &&
-                  !(p->kind == COFEM_DENSE && q->precision == COFEM_PREC_BF16_IR))))
-    return *why = "warm starts are built for convolution and DCT dictionaries and the dense COFEM_PREC_BF16_IR form",
-           COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & COFEM_FLAG_WARM_PREV) && (n != 1 || (q->flags & COFEM_FLAG_BATCHED) || p->phi_dtype != COFEM_F32))
+    return *why = "warm starts are built for single problems (not the batched form)", COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & COFEM_FLAG_WARM_PREV) && p->kind == COFEM_DENSE && q->stop_rule == COFEM_STOP_PER_COLUMN)
+    return *why = "the dense warm start runs the joint Frobenius stop rule", COFEM_ERR_UNSUPPORTED;
   for (int32_t i = 0; i < n; ++i)
     if (p[i].n_tasks > 1 && (n != 1 || p[i].kind != COFEM_DCT_MASK))
       return *why = "several tasks (n_tasks > 1) are built for one DCT-dictionary problem", COFEM_ERR_UNSUPPORTED;
@@ -1222,9 +1223,112 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
   return COFEM_OK;
 }
 
+// Dense float32 CG from the previous E-step's mean and diagonal estimate
+// (COFEM_FLAG_WARM_PREV): X0 = [max(s_prev, 0) (.) p_k | mu_prev] in Xt, R0 =
+// B - A X0, and plain CG on A D = R0 from D = 0, whose stop test
+// ||R||_F / ||R0||_F < eps ||B||_F / ||R0||_F is the solve's own test
+// ||R||_F / ||B||_F < eps (Sec. 3.2); X = X0 + D.  The first E-step (no
+// previous solution) starts from zero as plain CG does.
+cofem_status em_iteration_dense_warm(cofem_ctx* c, cofem_iter_stats* out) {
+  const int t = c->t_next;
+  const DenseDims& dd = c->dd;
+  COFEM_TRY(iter_start(c));
+  c->cg_enq = 0;
+  c->kev_used = 0;
+  COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
+  COFEM_HIP(c, dense_init(dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->parts_init,
+                          c->cnts_init, c->st, c->stream));
+  const bool warm = c->has_solution;
+  double tol_eff = c->tol;
+  if (warm) {
+    COFEM_HIP(c, dense_warm_start(dd, c->seed, t, c->K, c->sdiag, c->Xt, c->stream));
+    COFEM_HIP(c, dense_pass1(dd, c->phiA, c->Xt, c->xtm, c->Wpart, c->wmpart, c->W, c->wm, c->cnt_split1, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_pass2(dd, c->phiB, c->W, c->wm, c->Xt, c->xtm, c->R, c->rm, c->alpha, c->beta, c->Qpart,
+                             c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_ir_residual(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->X, c->R, c->P, c->xm, c->rm, c->pm,
+                                   c->parts_upd, c->cnts_upd, c->st, c->fixed_iters > 0 ? c->fixed_iters : c->U,
+                                   c->stream));
+    COFEM_TRY(read_state(c));
+    if (c->host_st->numeric_error)
+      return fail(c, COFEM_ERR_NUMERIC, "non-finite warm-start residual at EM iteration " + std::to_string(t));
+    const double r0 = c->host_st->true_ratio;  // ||R0||_F / ||B||_F
+    tol_eff = r0 > 0.0 ? c->tol / r0 : c->tol;
+    if (c->fixed_iters > 0) tol_eff = 0.0;
+    COFEM_HIP(c, hipMemcpyAsync(&c->st->tol, &tol_eff, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  } else {
+    COFEM_HIP(c, fill_f32(c->Xt, 0.0f, dd.Dp * kDenseKP, c->stream));
+    COFEM_HIP(c, hipMemsetAsync(c->xtm, 0, sizeof(double) * dd.Dp, c->stream));
+  }
+  const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
+  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 : c->poll;
+  if (chunk > limit) chunk = limit;
+  int enqueued = 0;
+  for (;;) {
+    if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk));
+    enqueued += chunk;
+    int extra = 0;
+    COFEM_TRY(poll_state(c, enqueued < limit, false, &extra));
+    enqueued += extra;
+    if (c->host_st->stop) break;
+    if (enqueued > limit + 2) return fail(c, COFEM_ERR_DEVICE, "CG did not report completion after the iteration cap");
+    chunk = c->poll - extra;
+    if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
+  }
+  if (c->host_st->numeric_error)
+    return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
+  const int iters = c->host_st->iter;
+  // the solve's ratio against ||B||_F
+  const double ratio = c->host_st->ratio * (warm ? c->tol / (tol_eff > 0.0 ? tol_eff : c->tol) : 1.0);
+  if (warm) {
+    double tol = c->tol;  // restore the solve's own tolerance for the next E-step's cold start
+    COFEM_HIP(c, hipMemcpyAsync(&c->st->tol, &tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  COFEM_HIP(c, dense_ir_accumulate(dd, c->Xt, c->X, c->xtm, c->xm, c->stream));
+  if (c->true_resid) {
+    COFEM_TRY(mark(c, COFEM_KT_CHECK, 0));
+    COFEM_HIP(c, dense_pass1(dd, c->phiA, c->Xt, c->xtm, c->Wpart, c->wmpart, c->W, c->wm, c->cnt_split1, c->st, 1,
+                             c->stream));
+    COFEM_HIP(c, dense_pass2(dd, c->phiB, c->W, c->wm, c->Xt, c->xtm, c->R, c->rm, c->alpha, c->beta, c->Qpart,
+                             c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2, c->st, 1,
+                             c->stream));
+    // ||B - A X||_F / ||B||_F: the true-residual sums use nB, which the warm
+    // start moved to ||R0||_F; the ratio is rescaled below
+    COFEM_HIP(c, dense_true_resid(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->parts_upd, c->cnts_upd, c->st,
+                                  c->stream));
+  }
+  COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
+  COFEM_HIP(c, dense_mstep(dd, c->seed, t, c->K, c->Xt, c->xtm, c->alpha, c->alpha_max, c->mu, c->sdiag,
+                           c->parts_upd, c->cnts_upd, c->st, c->stream));
+  COFEM_TRY(mark(c, -1, 0));
+  COFEM_TRY(iter_end(c));
+  COFEM_TRY(read_state(c));
+  COFEM_TRY(collect_times(c, iters));
+  c->has_solution = true;
+  c->prev_iters = iters;
+  c->t_next = t + 1;
+  if (out) {
+    float ms = 0.0f;
+    COFEM_TRY(iter_ms(c, &ms));
+    const double nB0 = c->host_st->nB0, nB = c->host_st->nB;
+    out->t = t;
+    out->cg_iters = iters;
+    out->converged = ratio < c->tol ? 1 : 0;
+    out->n_clamped = c->host_st->n_clamped;
+    out->rel_resid = ratio;
+    out->ms = ms;
+    out->rel_resid_true = c->true_resid ? c->host_st->true_ratio * (nB0 > 0.0 ? nB / nB0 : 1.0) : -1.0;
+    out->ir_sweeps = 0;
+    out->gamma_change = c->host_st->gamma_change;
+  }
+  return COFEM_OK;
+}
+
 cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   if (c->batch) return em_iteration_batch(c, out);
   if (c->precision == COFEM_PREC_BF16_IR) return em_iteration_ir(c, out);
+  if (c->kind == COFEM_DENSE && (c->flags & COFEM_FLAG_WARM_PREV)) return em_iteration_dense_warm(c, out);
   const int t = c->t_next;
   COFEM_TRY(iter_start(c));
   c->cg_enq = 0;
@@ -1630,7 +1734,8 @@ cofem_status cofem_get_solution(cofem_ctx* ctx, int32_t problem, float* probes, 
     return COFEM_OK;
   }
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
-  const bool ir = ctx->precision == COFEM_PREC_BF16_IR;
+  // dense forms that accumulate the solution (refinement, warm start) keep it in Xt
+  const bool ir = ctx->kind == COFEM_DENSE && ctx->Xt != nullptr;
   if (probes) {
     if (ctx->kind == COFEM_DENSE) {
       COFEM_HIP(ctx, dense_to_colmajor(ctx->dd, ctx->K, ir ? ctx->Xt : ctx->X, probes, ctx->stream));

@@ -32,12 +32,31 @@ def conv_gram_float32(op_fft, beta, alpha):
     return apply
 
 
-def cg_float32(apply32, B, iters):
-    """`iters` CG steps from X = 0 on the float32 block B (D x n)."""
+def dense_float32(phi, beta, alpha):
+    """q = beta Phi^T (Phi p) + alpha p with float32 products (single-precision
+    BLAS, as the GPU's float32 MFMA passes round)."""
+    ph = np.asarray(phi, np.float32)
+    a32 = np.asarray(alpha, np.float32)
+    b32 = np.float32(beta)
+
+    def apply(V):
+        V = np.asarray(V, np.float32)
+        return (b32 * (ph.T @ (ph @ V)) + a32[:, None] * V).astype(np.float32)
+
+    return apply
+
+
+def cg_float32(apply32, B, iters, X0=None):
+    """`iters` CG steps on the float32 block B (D x n), from X0 (float32,
+    R0 = B - A X0 evaluated in float32) or from zero."""
     B = np.asarray(B, np.float32)
-    X = np.zeros_like(B)
-    R = B.copy()
-    P = B.copy()
+    if X0 is None:
+        X = np.zeros_like(B)
+        R = B.copy()
+    else:
+        X = np.asarray(X0, np.float32).copy()
+        R = (B - apply32(X)).astype(np.float32)
+    P = R.copy()
     f64 = lambda M: M.astype(np.float64)  # noqa: E731
     rho = np.einsum("dc,dc->c", f64(R), f64(R))
     for _ in range(iters):

@@ -48,6 +48,8 @@ def _ctx(torch, p, **kw):
 
 # ------------------------------------------------------------------ restart
 _WARM_FORMS = {
+    "dense_fp32_warm": (lambda: synth.dense_problem(200, 700, nnz=8, beta=1e3, K=12, tol=1e-5, seed=11),
+                        {"warm_start": True}),
     "dense_bf16_ir_warm": (lambda: synth.dense_problem(200, 700, nnz=8, beta=1e3, K=12, tol=1e-5, seed=11),
                            {"precision": "bf16_ir", "warm_start": True}),
     "conv_warm_jacobi": (lambda: synth.conv_problem(40, 36, 5, rho=0.03, beta=1e3, K=8, tol=1e-5, seed=11),

@@ -910,3 +910,63 @@ def test_training_reduces_loss_and_cg_iterations(torch_dev):
          {k: float(np.sum((m - mus["plain"]) ** 2) / np.sum(mus["plain"] ** 2)) for k, m in mus.items()})
     assert sum(counts["learned"][1:]) < sum(counts["plain"][1:])
     net.close()
+
+
+# ------------------------------------------------------------------ dense float32 warm start
+@pytest.mark.parametrize("shape", ["256x1024", "300x777"])
+def test_dense_fp32_warm_step_parity(torch_dev, shape):
+    # plain float32 CG started from the previous mean and diagonal estimate
+    # (COFEM_FLAG_WARM_PREV without a preconditioner) against the oracle's CG
+    # from the same start, at the GPU's iteration count
+    torch = torch_dev
+    p = (synth.dense_256x1024(0) if shape == "256x1024"
+         else synth.dense_problem(300, 777, nnz=9, beta=5e3, K=13, tol=1e-6, seed=3))
+    op = _oracle_op(p)
+    b0 = p.beta * op.apply_t(p.y.astype(np.float64))
+    with _dense_ctx(torch, p, warm_start=True) as g:
+        g.em_step(3)
+        _, s_prev, alpha = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+        mu_prev = g.solution()[1].cpu().numpy()
+        st = g.em_step(1)[0]
+        mu, s, a_new = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
+    d0 = np.maximum(s_prev, 0.0)
+    e = O.cofem_estep_pcg(op, b0, p.beta, alpha, p.K, p.tol, p.max_iter, p.seed, st["t"], mu0=mu_prev,
+                          d0=d0, fixed_iters=st["cg_iters"])
+    a_ref, _ = O.mstep(e.mu, e.s)
+    pairs = ((mu, e.mu), (s, e.s), (1.0 / a_new, 1.0 / a_ref))
+    errs = [relerr(a, b) for a, b in pairs]
+    # the float32 floor of the probe columns: B - A X0 cancels most of B, and
+    # its float32 evaluation bounds how close float32 columns can follow the
+    # float64 iterates; a float32 model of the same recurrences from the same
+    # start measures it on this problem
+    from tests.float32_cg import cg_float32, dense_float32
+    X32 = cg_float32(dense_float32(p.phi, p.beta, alpha), e.P, st["cg_iters"], X0=d0[:, None] * e.P)
+    floor_s = relerr(O.diag_estimate(e.P, X32.astype(np.float64)), e.s)
+    _say("dense fp32 warm", shape, "t", st["t"], "cg", st["cg_iters"], "ratio", st["rel_resid"],
+         "oracle", e.cg.rel_resid, "true", st["rel_resid_true"], "relerr", errs, "float32 model on s", floor_s)
+    # B - A X0 cancels most of B; the float32 probe columns' true residual then
+    # sits at a float32 floor when that is above eps: the float32 model's own
+    # true residual (its probe columns, the float64 mean column) measures it
+    B = np.concatenate([e.P, b0[:, None]], axis=1)
+    Xm = np.concatenate([X32.astype(np.float64), e.X[:, -1:]], axis=1)
+    A = O.make_apply_A(op, p.beta, alpha)
+    floor = float(np.linalg.norm(B - A(Xm)) / np.linalg.norm(B))
+    _say("float32 model true residual", floor)
+    assert st["converged"] == 1
+    assert st["rel_resid_true"] < max(1.5 * p.tol, 3.0 * floor)
+    assert errs[0] < STEP_TOL  # the float64 mean column
+    bar = max(STEP_TOL, 3.0 * floor_s)
+    assert errs[1] < bar and errs[2] < bar, (errs, bar)
+    assert maxerr(mu, e.mu) < ELEM_TOL
+
+
+def test_dense_fp32_warm_start_cuts_iterations(torch_dev):
+    torch = torch_dev
+    p = synth.dense_256x1024(0)
+    counts = {}
+    for warm in (False, True):
+        with _dense_ctx(torch, p, warm_start=warm) as g:
+            counts[warm] = [x["cg_iters"] for x in g.em_step(12)]
+    _say("dense fp32 cg counts cold", counts[False], "warm", counts[True])
+    assert counts[True][0] == counts[False][0]
+    assert sum(counts[True][1:]) < sum(counts[False][1:])

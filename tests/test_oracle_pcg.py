@@ -77,3 +77,27 @@ def test_estep_pcg_warm_start_layout():
     ref = O.cofem_estep(op, b0, beta, alpha, 4, 1e-11, 500, seed=3, t=2)
     np.testing.assert_allclose(e.mu, ref.mu, rtol=1e-6)
     np.testing.assert_allclose(e.s, ref.s, rtol=1e-5, atol=1e-9)
+
+
+def test_warm_jacobi_trajectory_equals_plain_at_tight_tolerance():
+    # the E-step's solution A^-1 B does not depend on the start or the
+    # preconditioner, so with solves run to 1e-12 the warm-started Jacobi
+    # trajectory is the plain trajectory (same probes), while its later solves
+    # need fewer iterations
+    from paper_2202_12808_amd import synth
+    p = synth.dense_problem(48, 128, nnz=5, beta=200.0, K=6, tol=1e-12, seed=5)
+    op = O.DenseOperator(p.phi.astype(np.float64))
+    r1 = O.cofem(op, p.y, p.beta, 6, p.K, tol=1e-12, max_iter=2000, seed=3)
+    r2 = O.cofem(op, p.y, p.beta, 6, p.K, tol=1e-12, max_iter=2000, seed=3, warm_start=True, jacobi=True)
+    assert np.allclose(r2.mu, r1.mu, rtol=1e-7, atol=1e-10 * np.abs(r1.mu).max())
+    assert np.allclose(1.0 / r2.alpha, 1.0 / r1.alpha, rtol=1e-6)
+    assert sum(x["cg_iters"] for x in r2.stats[1:]) < sum(x["cg_iters"] for x in r1.stats[1:])
+    # jacobi alone at the first E-step with alpha = 1: a multiple of the
+    # identity when the columns have equal norms is plain CG (identity check on
+    # the conv dictionary, whose columns all have norm ||h||)
+    q = synth.conv_problem(16, 12, 3, rho=0.05, beta=50.0, K=4, tol=1e-10, seed=2)
+    cop = O.ConvOperator(q.taps.astype(np.float64), q.H, q.W)
+    a = O.cofem(cop, q.y, q.beta, 1, q.K, tol=1e-10, max_iter=500, seed=1)
+    b = O.cofem(cop, q.y, q.beta, 1, q.K, tol=1e-10, max_iter=500, seed=1, jacobi=True)
+    assert a.stats[0]["cg_iters"] == b.stats[0]["cg_iters"]
+    assert np.allclose(a.mu, b.mu, rtol=1e-9, atol=1e-12)
