@@ -307,7 +307,7 @@ class CoFEM:
     """One CoFEM problem on the current GPU.
 
     dense:  CoFEM.dense(phi[N, D] float32 cuda, y[N] float32 cuda, beta, K, ...)
-    conv:   CoFEM.conv(taps[k, k] float32 cuda, y[H*W] float32 cuda, H, W, beta, K, ...)
+    conv:   CoFEM.conv(taps[k, k] float32 cuda, y[H*W] (or [T, H*W] for T tasks) float32 cuda, H, W, beta, K, ...)
     dct:    CoFEM.dct(rows[N] int32 cuda, y[N] float32 cuda, D, beta, K, ...)
     """
 
@@ -363,11 +363,16 @@ class CoFEM:
         taps = taps.contiguous()
         y = y.contiguous()
         th, tw = taps.shape
+        T = 1 if y.dim() == 1 else int(y.shape[0])
+        if y.numel() != T * H * W:
+            raise CofemError(COFEM_ERR_INVALID_ARG, "y must be (H*W,) or (T, H*W)")
         prob = cofem_problem(kind=COFEM_CONV2D_CIRC, N=H * W, D=H * W, phi=None, ld_phi=0,
                              phi_dtype=COFEM_F32, H=H, W=W, kh=th, kw=tw, taps=taps.data_ptr(),
-                             y=y.data_ptr())
-        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (taps, y), taps.device,
-                   workspace=workspace)
+                             y=y.data_ptr(), n_tasks=T)
+        ctx = cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (taps, y), taps.device,
+                  workspace=workspace)
+        ctx.T = T
+        return ctx
 
     @classmethod
     def dct(cls, rows, y, D, beta, K, tol=1e-5, max_iter=400, seed=0, workspace=None, **kw):

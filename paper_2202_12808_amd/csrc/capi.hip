@@ -372,10 +372,10 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   cd.tilesY = (p.H + kConvTile - 1) / kConvTile;
   c->KP = c->K;
   cd.fp64 = c->precision == COFEM_PREC_FP64 ? 1 : 0;
-  cd.nt = 1;
-  const size_t blk = (size_t)cd.ldD * c->K;
+  cd.nt = c->NT;
+  const size_t blk = (size_t)cd.ldD * c->K, DT = (size_t)cd.ldD * c->NT;
   COFEM_TRY(alloc(c, &c->taps, (size_t)p.kh * p.kw));
-  COFEM_TRY(alloc(c, &c->b0, cd.ldD));
+  COFEM_TRY(alloc(c, &c->b0, DT));  // one column per task
   COFEM_TRY(alloc(c, &c->alpha, cd.ldD));
   COFEM_TRY(alloc(c, &c->alpha_prev, cd.ldD));
   COFEM_TRY(alloc(c, &c->mu, cd.ldD));
@@ -395,16 +395,9 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
       *b = q;
     }
   }
-  COFEM_TRY(alloc(c, &c->xm, cd.ldD));
-  COFEM_TRY(alloc(c, &c->rm, cd.ldD));
-  COFEM_TRY(alloc(c, &c->pm, cd.ldD));
-  COFEM_TRY(alloc(c, &c->qm, cd.ldD));
-  COFEM_TRY(alloc(c, &c->rm2, cd.ldD));
-  COFEM_TRY(alloc(c, &c->pm2, cd.ldD));
-  COFEM_TRY(alloc(c, &c->qm2, cd.ldD));
-  COFEM_TRY(alloc(c, &c->Vsm, cd.ldD));
-  COFEM_TRY(alloc(c, &c->Qsm, cd.ldD));
-  const int ncols = c->K + 1;
+  double** vecs[9] = {&c->xm, &c->rm, &c->pm, &c->qm, &c->rm2, &c->pm2, &c->qm2, &c->Vsm, &c->Qsm};
+  for (double** v : vecs) COFEM_TRY(alloc(c, v, DT));  // one float64 column per task
+  const int ncols = c->K + c->NT;
   const int64_t nupd = conv_update_blocks(cd), npass = conv_pass_blocks(cd);
   ConvReduce* reds[3] = {&c->red_init, &c->red_upd, &c->red_pass};
   // red_pass also serves the start of a preconditioned solve (nupd blocks)
@@ -418,7 +411,8 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   if (c->sizing) return COFEM_OK;
   COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
                               c->stream));
-  COFEM_HIP(c, conv_b0(cd, c->taps, p.y, c->beta, c->b0, c->stream));
+  for (int t = 0; t < c->NT; ++t)
+    COFEM_HIP(c, conv_b0(cd, c->taps, p.y + (size_t)t * cd.D, c->beta, c->b0 + (size_t)t * cd.ldD, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha_prev, 1.0f, cd.ldD, c->stream));
   return COFEM_OK;
@@ -805,8 +799,11 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if ((q->flags & COFEM_FLAG_WARM_PREV) && p->kind == COFEM_DENSE && q->stop_rule == COFEM_STOP_PER_COLUMN)
     return *why = "the dense warm start runs the joint Frobenius stop rule", COFEM_ERR_UNSUPPORTED;
   for (int32_t i = 0; i < n; ++i)
-    if (p[i].n_tasks > 1 && (n != 1 || p[i].kind != COFEM_DCT_MASK))
-      return *why = "several tasks (n_tasks > 1) are built for one DCT-dictionary problem", COFEM_ERR_UNSUPPORTED;
+    if (p[i].n_tasks > 1 && (n != 1 || (p[i].kind != COFEM_DCT_MASK && p[i].kind != COFEM_CONV2D_CIRC)))
+      return *why = "several tasks (n_tasks > 1) are built for one convolution or DCT problem",
+             COFEM_ERR_UNSUPPORTED;
+  if (p->n_tasks < 0 || q->K + (p->n_tasks > 1 ? p->n_tasks : 1) > kMaxCols)
+    return *why = "n_tasks must be >= 0 with K + n_tasks <= 64", COFEM_ERR_INVALID_ARG;
   if (n > 1 || p->phi_dtype == COFEM_BF16 || (q->flags & COFEM_FLAG_BATCHED)) {
     // batched form: dense problems whose bfloat16 dictionary is the problem
     if (q->precision != COFEM_PREC_FP32)
@@ -840,8 +837,6 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
     if (p->N != (int64_t)p->H * p->W || p->D != p->N) return *why = "conv needs N == D == H*W", COFEM_ERR_INVALID_ARG;
     if ((int64_t)p->H * p->W > (int64_t)1 << 30) return *why = "image too large", COFEM_ERR_INVALID_ARG;
   } else if (p->kind == COFEM_DCT_MASK) {
-    if (p->n_tasks < 0 || q->K + (p->n_tasks > 1 ? p->n_tasks : 1) > kMaxCols)
-      return *why = "n_tasks must be >= 0 with K + n_tasks <= 64", COFEM_ERR_INVALID_ARG;
     if (p->D < ((int64_t)1 << 12) || p->D > ((int64_t)1 << 20) || (p->D & (p->D - 1)) != 0)
       return *why = "the DCT dictionary needs D = 2^p, 12 <= p <= 20", COFEM_ERR_UNSUPPORTED;
     if (p->N < 1 || p->N > p->D) return *why = "the DCT dictionary needs 1 <= N <= D", COFEM_ERR_INVALID_ARG;
@@ -1673,13 +1668,20 @@ cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha
 cofem_status cofem_get_means(cofem_ctx* ctx, int32_t problem, double* mu) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (!mu) return fail(ctx, COFEM_ERR_INVALID_ARG, "mu is null");
-  if (ctx->batch || ctx->precision == COFEM_PREC_BF16_IR || ctx->kind != COFEM_DCT_MASK) {
+  if (ctx->batch || ctx->NT == 1) {
     // one task: the mean column of the solution
     return cofem_get_solution(ctx, problem, nullptr, mu);
   }
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
-  for (int t = 0; t < ctx->NT; ++t)
-    COFEM_HIP(ctx, perm_out_f64(ctx->cd, ctx->xm + (size_t)t * ctx->D, mu + (size_t)t * ctx->D, ctx->stream));
+  // task t's column sits at t * ldD (ldD = D for the DCT dictionary)
+  for (int t = 0; t < ctx->NT; ++t) {
+    const double* src = ctx->xm + (size_t)t * ctx->cd.ldD;
+    double* dst = mu + (size_t)t * ctx->D;
+    if (ctx->kind == COFEM_DCT_MASK)
+      COFEM_HIP(ctx, perm_out_f64(ctx->cd, src, dst, ctx->stream));
+    else
+      COFEM_HIP(ctx, hipMemcpyAsync(dst, src, sizeof(double) * (size_t)ctx->D, hipMemcpyDeviceToDevice, ctx->stream));
+  }
   return COFEM_OK;
 }
 
@@ -1962,6 +1964,8 @@ cofem_status cofem_set_predictor(cofem_ctx* ctx, cofem_net* net) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (ctx->kind != COFEM_CONV2D_CIRC || ctx->batch)
     return fail(ctx, COFEM_ERR_UNSUPPORTED, "the learned form is built for convolution dictionaries");
+  if (net && ctx->NT > 1)
+    return fail(ctx, COFEM_ERR_UNSUPPORTED, "the learned form predicts one mean: single-task contexts only");
   if (net && (net_height(net) != ctx->cd.H || net_width(net) != ctx->cd.W))
     return fail(ctx, COFEM_ERR_INVALID_ARG, "the net's image size differs from the problem's");
   ctx->predictor = net ? predictor_hook : nullptr;

@@ -339,7 +339,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const float* __restrict__ taps, int H, int W, int64_t ldD, int K, int tilesX, const TP* __restrict__ P,
     const double* __restrict__ pm, const TP* __restrict__ R, const double* __restrict__ rm,
     const float* __restrict__ alpha, double beta, const float* __restrict__ minv, TP* __restrict__ Q,
-    double* __restrict__ qm, ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st, int apply_only) {
+    double* __restrict__ qm, ConvReduce red, int64_t nblk_alloc, int nt, CgScalars* __restrict__ st,
+    int apply_only) {
   if (!apply_only && st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   using G64 = ConvGeom<KS, kConvTile>;
@@ -362,15 +363,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   int64_t tile = blockIdx.x;
   if ((ntiles & 7) == 0) tile = (tile & 7) * (ntiles >> 3) + (tile >> 3);
   const int ty = (int)(tile / tilesX), tx = (int)(tile - (tile / tilesX) * tilesX);
+  // z < 4 nt: quadrant z % 4 of mean column z / 4 (column K + z / 4); then
+  // the probe columns' parts
   const int z = blockIdx.z;
   int col, part, nparts;
-  if (z < 4) {
-    col = K;
-    part = z;
+  if (z < 4 * nt) {
+    col = K + (z >> 2);
+    part = z & 3;
     nparts = 4;
   } else {
-    col = (z - 4) / kS;
-    part = (z - 4) - col * kS;
+    col = (z - 4 * nt) / kS;
+    part = (z - 4 * nt) - col * kS;
     nparts = kS;
   }
   int tu0 = ty * kConvTile, tv0 = tx * kConvTile;
@@ -387,9 +390,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const bool near = H >= G32::TR && W >= G32::SPW - 2 * G32::c;
     double* sb = reinterpret_cast<double*>(sbuf);
     Taps<double> hd(sTapsD);
-    if (col == K) {
-      conv_tile<KS, kConvTile / 2, double>(hd, H, W, tu0, tv0, near, pm, rm, alpha, beta, minv, qm, sb,
-                                           sb + G32::SPH * G32::SPW, dots);
+    if (col >= K) {
+      const int64_t mo = (int64_t)(col - K) * ldD;
+      conv_tile<KS, kConvTile / 2, double>(hd, H, W, tu0, tv0, near, pm + mo, rm + mo, alpha, beta, minv, qm + mo,
+                                           sb, sb + G32::SPH * G32::SPW, dots);
     } else {
       const int64_t off = (int64_t)col * ldD;
       conv_tile<KS, kConvTile / 2, double>(hd, H, W, tu0, tv0, near, reinterpret_cast<const double*>(P) + off,
@@ -419,7 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   __syncthreads();
   if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, tile * nparts + part, ntiles * nparts,
-                          nblk_alloc, col, K + 1, 3, mine, tot))
+                          nblk_alloc, col, K + nt, 3, mine, tot))
     return;
   finish_step(st, tot, ctl);
 }
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     TP* __restrict__ R1, TP* __restrict__ Q1, const double* __restrict__ pm0, const double* __restrict__ rm0,
     const double* __restrict__ qm0, double* __restrict__ xm, double* __restrict__ pm1, double* __restrict__ rm1,
     double* __restrict__ qm1, const float* __restrict__ alpha, double beta, const float* __restrict__ minv,
-    ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st) {
+    ConvReduce red, int64_t nblk_alloc, int nt, CgScalars* __restrict__ st) {
   if (st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   using G64 = ConvGeom<KS, kConvTile>;
@@ -466,13 +470,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int ty = (int)(tile / tilesX), tx = (int)(tile - (tile / tilesX) * tilesX);
   const int z = blockIdx.z;
   int col, part, nparts;
-  if (z < 4) {
-    col = K;
-    part = z;
+  if (z < 4 * nt) {
+    col = K + (z >> 2);
+    part = z & 3;
     nparts = 4;
   } else {
-    col = (z - 4) / kS;
-    part = (z - 4) - col * kS;
+    col = (z - 4 * nt) / kS;
+    part = (z - 4 * nt) - col * kS;
     nparts = kS;
   }
   int tu0 = ty * kConvTile, tv0 = tx * kConvTile;
@@ -488,11 +492,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     double* sb = reinterpret_cast<double*>(sbuf);
     Taps<double> hd(sTapsD);
     const double a = st->a[col], b = st->b[col];
-    if (col == K) {
-      const FusedUpd<double> fu{pm0, rm0, qm0, xm, pm1, rm1, a, b};
+    if (col >= K) {
+      const int64_t mo = (int64_t)(col - K) * ldD;
+      const FusedUpd<double> fu{pm0 + mo, rm0 + mo, qm0 + mo, xm + mo, pm1 + mo, rm1 + mo, a, b};
       conv_tile<KS, kConvTile / 2, double, Taps<double>, true>(hd, H, W, tu0, tv0, near, nullptr, nullptr, alpha,
-                                                               beta, minv, qm1, sb, sb + G32::SPH * G32::SPW, dots,
-                                                               &fu);
+                                                               beta, minv, qm1 + mo, sb, sb + G32::SPH * G32::SPW,
+                                                               dots, &fu);
     } else {
       const int64_t off = (int64_t)col * ldD;
       const double* dP0 = reinterpret_cast<const double*>(P0) + off;
@@ -534,9 +539,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   __syncthreads();
   if (!column_tree_reduce(red.parts, red.cnts, red.colsum, red.cnt_cols, tile * nparts + part, ntiles * nparts,
-                          nblk_alloc, col, K + 1, 5, mine, tot))
+                          nblk_alloc, col, K + nt, 5, mine, tot))
     return;
-  finish_fused(st, tot, K + 1, ctl);
+  finish_fused(st, tot, K + nt, ctl);
 }
 
 template <typename TP>
@@ -544,7 +549,7 @@ static hipError_t launch_conv_fused(const ConvDims& cd, const float* taps, const
                                     void* X, double* xm, const float* alpha, double beta, const float* minv,
                                     const ConvReduce& red, CgScalars* st, hipStream_t s) {
   constexpr int kS = sizeof(TP) == 8 ? 4 : 1;
-  const dim3 grid((unsigned)(cd.tilesX * cd.tilesY), 1, (unsigned)(4 + cd.K * kS));
+  const dim3 grid((unsigned)(cd.tilesX * cd.tilesY), 1, (unsigned)(4 * cd.nt + cd.K * kS));
   const int64_t nblk_alloc = conv_pass_blocks(cd);
 #define COFEM_FUSED_CASE(KS)                                                                                    \
   case KS:                                                                                                      \
@@ -552,7 +557,7 @@ static hipError_t launch_conv_fused(const ConvDims& cd, const float* taps, const
                        cd.tilesX, static_cast<const TP*>(s0.P), static_cast<const TP*>(s0.R),                     \
                        static_cast<const TP*>(s0.Q), static_cast<TP*>(X), static_cast<TP*>(s1.P),                  \
                        static_cast<TP*>(s1.R), static_cast<TP*>(s1.Q), s0.pm, s0.rm, s0.qm, xm, s1.pm, s1.rm,      \
-                       s1.qm, alpha, beta, minv, red, nblk_alloc, st);                                            \
+                       s1.qm, alpha, beta, minv, red, nblk_alloc, cd.nt, st);                                     \
     break;
   switch (cd.ks) {
     COFEM_FUSED_CASE(1)
@@ -580,7 +585,7 @@ static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const 
                                    const float* alpha, double beta, const float* minv, void* Q, double* qm,
                                    const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s) {
   constexpr int kS = sizeof(TP) == 8 ? 4 : 1;
-  const dim3 grid((unsigned)(cd.tilesX * cd.tilesY), 1, (unsigned)(4 + cd.K * kS));
+  const dim3 grid((unsigned)(cd.tilesX * cd.tilesY), 1, (unsigned)(4 * cd.nt + cd.K * kS));
   const TP* Pt = static_cast<const TP*>(P);
   const TP* Rt = static_cast<const TP*>(R);
   TP* Qt = static_cast<TP*>(Q);
@@ -588,7 +593,8 @@ static hipError_t launch_conv_pass(const ConvDims& cd, const float* taps, const 
 #define COFEM_CONV_CASE(KS)                                                                             \
   case KS:                                                                                              \
     hipLaunchKernelGGL((k_conv_pass<KS, TP>), grid, dim3(kThreads), 0, s, taps, cd.H, cd.W, cd.ldD, cd.K,  \
-                       cd.tilesX, Pt, pm, Rt, rm, alpha, beta, minv, Qt, qm, red, nblk_alloc, st, apply_only); \
+                       cd.tilesX, Pt, pm, Rt, rm, alpha, beta, minv, Qt, qm, red, nblk_alloc, cd.nt, st,      \
+                       apply_only);                                                                     \
     break;
   switch (cd.ks) {
     COFEM_CONV_CASE(1)

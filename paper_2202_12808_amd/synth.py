@@ -130,6 +130,35 @@ def conv_problem(H, W, k, *, rho, beta, K, tol, max_iter=400, T_em=30, seed=0,
                    taps=taps, H=H, W=W, name=name)
 
 
+def conv_multitask(H, W, k, T, *, rho, beta, K, tol, max_iter=400, T_em=30, seed=0, name="") -> Problem:
+    """T tasks on one circular-convolution dictionary (taps as conv_problem):
+    the signals share their support (round(rho D) pixels, uniform) with
+    independent N(0,1) values per task; y_t = Phi z_t + N(0, 1/beta) noise."""
+    rng = np.random.default_rng(seed)
+    taps = conv_taps(rng, k, k)
+    D = H * W
+    pos = rng.choice(D, size=_nnz(rho, D), replace=False)
+    Z = np.zeros((T, D))
+    Z[:, pos] = rng.standard_normal((T, len(pos)))
+    Y = np.stack([_circ_conv_f64(taps.astype(np.float64), Z[t].reshape(H, W)).reshape(D) for t in range(T)])
+    Y = (Y + rng.standard_normal((T, D)) / math.sqrt(beta)).astype(np.float32)
+    return Problem("conv", D, D, Y, Z, float(beta), K, tol, max_iter, T_em, seed, taps=taps, H=H, W=W,
+                   tasks=T, name=name)
+
+
+def dense_multitask(N, D, T, *, rho, beta, K, tol, max_iter=400, T_em=30, seed=0, name="") -> Problem:
+    """T tasks on one dense dictionary (iid N(0, 1/N) as dense_problem) with a
+    shared support and independent N(0,1) values per task."""
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((N, D), dtype=np.float32)
+    phi *= np.float32(1.0 / math.sqrt(N))
+    pos = rng.choice(D, size=_nnz(rho, D), replace=False)
+    Z = np.zeros((T, D))
+    Z[:, pos] = rng.standard_normal((T, len(pos)))
+    Y = (Z @ phi.astype(np.float64).T + rng.standard_normal((T, N)) / math.sqrt(beta)).astype(np.float32)
+    return Problem("dense", N, D, Y, Z, float(beta), K, tol, max_iter, T_em, seed, phi=phi, tasks=T, name=name)
+
+
 def _inverse_dct_f64(z):
     """Forward model for data synthesis only: the orthonormal inverse DCT
     (scipy's DCT-III) of the coefficient vector."""
