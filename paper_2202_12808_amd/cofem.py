@@ -306,7 +306,7 @@ def cofem_destroy(ctx):
 class CoFEM:
     """One CoFEM problem on the current GPU.
 
-    dense:  CoFEM.dense(phi[N, D] float32 cuda, y[N] float32 cuda, beta, K, ...)
+    dense:  CoFEM.dense(phi[N, D] float32 cuda, y[N] (or [T, N] for T tasks) float32 cuda, beta, K, ...)
     conv:   CoFEM.conv(taps[k, k] float32 cuda, y[H*W] (or [T, H*W] for T tasks) float32 cuda, H, W, beta, K, ...)
     dct:    CoFEM.dct(rows[N] int32 cuda, y[N] float32 cuda, D, beta, K, ...)
     """
@@ -350,10 +350,15 @@ class CoFEM:
         phi = phi.contiguous()
         y = y.contiguous()
         N, D = phi.shape
+        T = 1 if y.dim() == 1 else int(y.shape[0])
+        if y.numel() != T * N:
+            raise CofemError(COFEM_ERR_INVALID_ARG, "y must be (N,) or (T, N)")
         prob = cofem_problem(kind=COFEM_DENSE, N=N, D=D, phi=phi.data_ptr(), ld_phi=D,
-                             phi_dtype=COFEM_F32, H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr())
-        return cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (phi, y), phi.device,
-                   workspace=workspace)
+                             phi_dtype=COFEM_F32, H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr(), n_tasks=T)
+        ctx = cls(prob, cls._params(beta, K, tol, max_iter, seed, **kw), (phi, y), phi.device,
+                  workspace=workspace)
+        ctx.T = T
+        return ctx
 
     @classmethod
     def conv(cls, taps, y, H, W, beta, K, tol=1e-5, max_iter=400, seed=0, workspace=None, **kw):

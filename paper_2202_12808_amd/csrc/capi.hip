@@ -291,14 +291,16 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   dd.D = p.D;
   dd.Np = round_up(p.N, 64);
   dd.Dp = round_up(p.D, 64);
-  dd.S1 = dense_split(dd.Np / 32, dd.Dp / 8);
-  dd.S2 = dense_split(dd.Dp / 32, dd.Np / 8);
+  dd.nt = c->NT;
+  dd.S1 = dense_split(dd.Np / 32, dd.Dp / 8, dd.nt);
+  dd.S2 = dense_split(dd.Dp / 32, dd.Np / 8, dd.nt);
   dd.ring = 4;
   // tuning override: COFEM_GEMM="S1,S2,ring"
   if (const char* e = getenv("COFEM_GEMM")) {
     int s1, s2, rg;
-    if (sscanf(e, "%d,%d,%d", &s1, &s2, &rg) == 3 && dense_split_ok(dd.Dp / 8, s1) &&
-        dense_split_ok(dd.Np / 8, s2) && s1 <= 64 && s2 <= 64 && (rg == 1 || rg == 2 || rg == 4 || rg == 8)) {
+    if (sscanf(e, "%d,%d,%d", &s1, &s2, &rg) == 3 && dense_split_ok(dd.Dp / 8, s1, dd.nt) &&
+        dense_split_ok(dd.Np / 8, s2, dd.nt) && s1 <= 64 && s2 <= 64 &&
+        (rg == 1 || rg == 2 || rg == 4 || rg == 8)) {
       dd.S1 = s1;
       dd.S2 = s2;
       dd.ring = rg;
@@ -311,10 +313,10 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   const int s1 = lowp && dd.S1h > dd.S1 ? dd.S1h : dd.S1;
   const int s2 = lowp && dd.S2h > dd.S2 ? dd.S2h : dd.S2;
 
-  const size_t blk = (size_t)dd.Dp * kDenseKP;
+  const size_t blk = (size_t)dd.Dp * kDenseKP, DT = (size_t)dd.Dp * dd.nt;
   COFEM_TRY(alloc(c, &c->phiA, (size_t)dd.Np * dd.Dp));
   COFEM_TRY(alloc(c, &c->phiB, (size_t)dd.Np * dd.Dp));
-  COFEM_TRY(alloc(c, &c->b0, dd.Dp));
+  COFEM_TRY(alloc(c, &c->b0, DT));  // one float64 column per task
   COFEM_TRY(alloc(c, &c->alpha, dd.Dp));
   COFEM_TRY(alloc(c, &c->mu, dd.Dp));
   COFEM_TRY(alloc(c, &c->sdiag, dd.Dp));
@@ -324,22 +326,19 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->Q, blk));
   COFEM_TRY(alloc(c, &c->Vs, blk));
   COFEM_TRY(alloc(c, &c->Qs, blk));
-  COFEM_TRY(alloc(c, &c->xm, dd.Dp));
-  COFEM_TRY(alloc(c, &c->rm, dd.Dp));
-  COFEM_TRY(alloc(c, &c->pm, dd.Dp));
-  COFEM_TRY(alloc(c, &c->qm, dd.Dp));
-  COFEM_TRY(alloc(c, &c->Vsm, dd.Dp));
-  COFEM_TRY(alloc(c, &c->Qsm, dd.Dp));
+  double** vecs[6] = {&c->xm, &c->rm, &c->pm, &c->qm, &c->Vsm, &c->Qsm};
+  for (double** v : vecs) COFEM_TRY(alloc(c, v, DT));
   COFEM_TRY(alloc(c, &c->W, (size_t)dd.Np * kDenseKP));
-  COFEM_TRY(alloc(c, &c->wm, dd.Np));
+  COFEM_TRY(alloc(c, &c->wm, (size_t)dd.Np * dd.nt));
   const int64_t nupd = dense_update_blocks(dd);
-  COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, kDenseKP + 1));
-  COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, kDenseKP + 1));
-  COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 32, 3 * (kDenseKP + 1)));
+  const int ncols = kDenseKP + dd.nt;
+  COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, ncols));
+  COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, ncols));
+  COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 32, 3 * ncols));
   COFEM_TRY(alloc(c, &c->Wpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np * kDenseKP));
-  COFEM_TRY(alloc(c, &c->wmpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np));
+  COFEM_TRY(alloc(c, &c->wmpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np * dd.nt));
   COFEM_TRY(alloc(c, &c->Qpart, (size_t)(s2 > 1 ? s2 : 0) * dd.Dp * kDenseKP));
-  COFEM_TRY(alloc(c, &c->qmpart, (size_t)(s2 > 1 ? s2 : 0) * dd.Dp));
+  COFEM_TRY(alloc(c, &c->qmpart, (size_t)(s2 > 1 ? s2 : 0) * dd.Dp * dd.nt));
   if (lowp) {
     COFEM_TRY(alloc(c, &c->phiA16, (size_t)dd.Np * dd.Dp));
     COFEM_TRY(alloc(c, &c->phiB16, (size_t)dd.Np * dd.Dp));
@@ -355,7 +354,9 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   COFEM_HIP(c, dense_pack(static_cast<const float*>(p.phi), p.ld_phi, dd, c->phiA, c->phiB, c->stream));
   if (lowp)
     COFEM_HIP(c, dense_pack16(p.phi, kDictF32ToBf16, p.ld_phi, dd, c->phiA16, c->phiB16, c->stream));
-  COFEM_HIP(c, dense_b0(p.phi, kDictF32, p.ld_phi, p.y, c->beta, dd, c->b0, c->stream));
+  for (int t = 0; t < dd.nt; ++t)
+    COFEM_HIP(c, dense_b0(p.phi, kDictF32, p.ld_phi, p.y + (size_t)t * p.N, c->beta, dd, c->b0 + (size_t)t * dd.Dp,
+                          c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, dd.Dp, c->stream));
   return COFEM_OK;
 }
@@ -799,9 +800,14 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if ((q->flags & COFEM_FLAG_WARM_PREV) && p->kind == COFEM_DENSE && q->stop_rule == COFEM_STOP_PER_COLUMN)
     return *why = "the dense warm start runs the joint Frobenius stop rule", COFEM_ERR_UNSUPPORTED;
   for (int32_t i = 0; i < n; ++i)
-    if (p[i].n_tasks > 1 && (n != 1 || (p[i].kind != COFEM_DCT_MASK && p[i].kind != COFEM_CONV2D_CIRC)))
-      return *why = "several tasks (n_tasks > 1) are built for one convolution or DCT problem",
+    if (p[i].n_tasks > 1 && (n != 1 || (q->flags & COFEM_FLAG_BATCHED) || p[i].phi_dtype != COFEM_F32))
+      return *why = "several tasks (n_tasks > 1) are built for single problems (not the batched form)",
              COFEM_ERR_UNSUPPORTED;
+  if (p->n_tasks > 1 && p->kind == COFEM_DENSE &&
+      (q->precision != COFEM_PREC_FP32 || (q->flags & COFEM_FLAG_WARM_PREV) || p->n_tasks > kMaxDenseTasks))
+    return *why = "several tasks on a dense dictionary: plain float32 CG (precision COFEM_PREC_FP32, no warm "
+                  "start), at most 4 tasks",
+           COFEM_ERR_UNSUPPORTED;
   if (p->n_tasks < 0 || q->K + (p->n_tasks > 1 ? p->n_tasks : 1) > kMaxCols)
     return *why = "n_tasks must be >= 0 with K + n_tasks <= 64", COFEM_ERR_INVALID_ARG;
   if (n > 1 || p->phi_dtype == COFEM_BF16 || (q->flags & COFEM_FLAG_BATCHED)) {
@@ -1673,9 +1679,10 @@ cofem_status cofem_get_means(cofem_ctx* ctx, int32_t problem, double* mu) {
     return cofem_get_solution(ctx, problem, nullptr, mu);
   }
   if (problem != 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "problem index out of range");
-  // task t's column sits at t * ldD (ldD = D for the DCT dictionary)
+  // task t's column sits at t * ldD (ldD = D for the DCT dictionary, Dp for a dense one)
+  const int64_t ld = ctx->kind == COFEM_DENSE ? ctx->dd.Dp : ctx->cd.ldD;
   for (int t = 0; t < ctx->NT; ++t) {
-    const double* src = ctx->xm + (size_t)t * ctx->cd.ldD;
+    const double* src = ctx->xm + (size_t)t * ld;
     double* dst = mu + (size_t)t * ctx->D;
     if (ctx->kind == COFEM_DCT_MASK)
       COFEM_HIP(ctx, perm_out_f64(ctx->cd, src, dst, ctx->stream));

@@ -238,21 +238,32 @@ __device__ __forceinline__ bool column_tree_reduce(double* parts, uint32_t* cnts
 }
 
 // ------------------------------------------------ per-block column sums (dense)
-// Thread tid owns probe column tid & 31 (acc) and a share of the mean column
-// (accm); leaves the block's 33 sums in out_sh (256-thread blocks).
-__device__ __forceinline__ void dense_block_sums(double acc, double accm, double* out_sh) {
+// Thread tid owns probe column tid & 31 (acc) and a share of each of the nt
+// mean columns (accm[j]); leaves the block's kDenseKP + nt sums in out_sh
+// (256-thread blocks).
+constexpr int kMaxDenseTasks = 4;  // mean columns of a dense problem (tasks sharing alpha)
+
+__device__ __forceinline__ void dense_block_sums(double acc, const double* accm, int nt, double* out_sh) {
   __shared__ double sh[kThreads];
   __shared__ double shm[8];
+  __shared__ double msum[kMaxDenseTasks];
   sh[threadIdx.x] = acc;
-  const double m = block_sum(accm, shm);  // synchronises
+  for (int j = 0; j < nt; ++j) {
+    const double m = block_sum(accm[j], shm);  // synchronises
+    if (threadIdx.x == 0) msum[j] = m;
+  }
+  __syncthreads();
   if (threadIdx.x < kDenseKP) {
     double v = 0.0;
     for (int t = threadIdx.x; t < kThreads; t += kDenseKP) v += sh[t];
     out_sh[threadIdx.x] = v;
-  } else if (threadIdx.x == kDenseKP) {
-    out_sh[kDenseKP] = m;
+  } else if (threadIdx.x < kDenseKP + nt) {
+    out_sh[threadIdx.x] = msum[threadIdx.x - kDenseKP];
   }
   __syncthreads();
+}
+__device__ __forceinline__ void dense_block_sums(double acc, double accm, double* out_sh) {
+  dense_block_sums(acc, &accm, 1, out_sh);
 }
 
 // The finish_* helpers run in the last block of a reduction, all threads,
@@ -567,6 +578,7 @@ struct DenseDims {
   int S1, S2;  // workgroups sharing one tile's reduction in pass 1 / pass 2
   int ring;    // outstanding 8-wide groups per wave (1, 2, 4 or 8)
   int S1h, S2h;  // splits of the bfloat16 passes (two tiles per workgroup)
+  int nt = 1;    // float64 mean columns (tasks sharing alpha), stride Dp (Np for W)
 };
 
 __host__ __device__ __forceinline__ int64_t blk4(int64_t d, int c) {
@@ -591,8 +603,8 @@ hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, c
 hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
                         double* xm, double* rm, double* pm, const double* qm, double* parts,
                         uint32_t* cnts, CgScalars* st, hipStream_t s);
-int dense_split(int64_t tiles, int64_t groups);
-bool dense_split_ok(int64_t groups, int splits);
+int dense_split(int64_t tiles, int64_t groups, int nt = 1);
+bool dense_split_ok(int64_t groups, int splits, int nt = 1);
 // diagonal estimate and M-step; the update's reduction tree (parts, cnts)
 // serves its sums (clamp count, change of 1/alpha)
 hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,

@@ -104,6 +104,7 @@ int dense_update_blocks(const DenseDims& dd) {
 }
 
 // ------------------------------------------------ initial residual R = P = B (Eq. 7)
+// (nt mean columns at stride Dp: task j's b0, x, r, p at + j Dp)
 __device__ __forceinline__ void dense_init_body(int64_t blk, int64_t nblk, int64_t D, int64_t Dp, uint64_t seed, int t,
                                                     int K, const double* __restrict__ b0,
                                                     float* __restrict__ X, float* __restrict__ R,
@@ -111,7 +112,7 @@ __device__ __forceinline__ void dense_init_body(int64_t blk, int64_t nblk, int64
                                                     double* __restrict__ rm,
                                                     double* __restrict__ pm,
                                                     double* __restrict__ parts, uint32_t* cnts,
-                                                    CgScalars* st) {
+                                                    CgScalars* st, int nt = 1) {
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
@@ -129,17 +130,18 @@ __device__ __forceinline__ void dense_init_body(int64_t blk, int64_t nblk, int64
     reinterpret_cast<float4*>(P)[e4] = r;
     reinterpret_cast<float4*>(X)[e4] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  double accm = 0.0;
-  for (int64_t d = gtid; d < Dp; d += gstride) {
-    const double b = b0[d];
-    rm[d] = b;
-    pm[d] = b;
-    xm[d] = 0.0;
-    accm += b * b;
-  }
-  __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
-  dense_block_sums(acc, accm, mine);
-  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + 1, mine, tot)) return;
+  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < nt; ++j)
+    for (int64_t d = gtid; d < Dp; d += gstride) {
+      const double b = b0[j * Dp + d];
+      rm[j * Dp + d] = b;
+      pm[j * Dp + d] = b;
+      xm[j * Dp + d] = 0.0;
+      accm[j] += b * b;
+    }
+  __shared__ double mine[kDenseKP + kMaxDenseTasks], tot[kDenseKP + kMaxDenseTasks];
+  dense_block_sums(acc, accm, nt, mine);
+  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + nt, mine, tot)) return;
   finish_init(st, tot);
 }
 
@@ -150,15 +152,15 @@ __global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint6
                                                     double* __restrict__ rm,
                                                     double* __restrict__ pm,
                                                     double* __restrict__ parts, uint32_t* cnts,
-                                                    CgScalars* st) {
-  dense_init_body(blockIdx.x, gridDim.x, D, Dp, seed, t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st);
+                                                    CgScalars* st, int nt) {
+  dense_init_body(blockIdx.x, gridDim.x, D, Dp, seed, t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st, nt);
 }
 
 hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
                       float* X, float* R, float* P, double* xm, double* rm, double* pm,
                       double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_init, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed,
-                     t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st);
+                     t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st, dd.nt);
   return hipGetLastError();
 }
 
@@ -173,47 +175,62 @@ hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const do
 // Vector loads complete in order, so the A and B streams share one ring of
 // RING outstanding groups; the LDS reads of the mean values do not touch it.
 
-// One 8-wide group: four MFMAs into the probe tile, four float64 FMAs into the
-// lane's share of the mean column (m: the four mean-column values of the
-// lane's half, from LDS).
-__device__ __forceinline__ void mma_group(const float4& av, const float4& bv, const double4& m,
-                                          floatx16& acc, double& accm) {
+// One 8-wide group: four MFMAs into the probe tile, four float64 FMAs per
+// mean column into the lane's share of that column (m[j]: the four values of
+// mean column j for the lane's half, from LDS).
+template <int NT>
+__device__ __forceinline__ void mma_group(const float4& av, const float4& bv, const double4 (&m)[NT],
+                                          floatx16& acc, double (&accm)[NT]) {
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.y, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, bv.z, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, bv.w, acc, 0, 0, 0);
-  accm = fma((double)av.x, m.x, accm);
-  accm = fma((double)av.y, m.y, accm);
-  accm = fma((double)av.z, m.z, accm);
-  accm = fma((double)av.w, m.w, accm);
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    accm[j] = fma((double)av.x, m[j].x, accm[j]);
+    accm[j] = fma((double)av.y, m[j].y, accm[j]);
+    accm[j] = fma((double)av.z, m[j].z, accm[j]);
+    accm[j] = fma((double)av.w, m[j].w, accm[j]);
+  }
 }
 
 // The workgroup's mean-column operand for groups [g0, g1): staged once in LDS
 // (coalesced), read per group with LDS broadcasts -- the LDS counter is
-// separate from the vector-memory counter that paces the Phi ring.
+// separate from the vector-memory counter that paces the Phi ring.  With NT
+// mean columns (tasks sharing alpha) the stage holds NT columns, so a range
+// may span kMaxStageGroups / NT groups.
 constexpr int kMaxStageGroups = 512;  // 4096 values, 32 KiB
 
-template <int WAVES, int RING>
+template <int WAVES, int RING, int NT>
 __device__ __forceinline__ void gemm32(const float4* __restrict__ pa, int64_t g0, int64_t g1,
-                                       const float4* __restrict__ B4, const double* __restrict__ bm,
-                                       floatx16& acc, double& accm) {
-  __shared__ double4 sm[kMaxStageGroups * 2];  // [group][half] -> 4 values
+                                       const float4* __restrict__ B4, const double* __restrict__ bm, int64_t ldm,
+                                       floatx16& acc, double (&accm)[NT]) {
+  __shared__ double4 sm[kMaxStageGroups * 2];  // [column][group][half] -> 4 values
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = lane & 31, h = lane >> 5;
   const int64_t span = g1 - g0;
-  // (host guarantees span <= kMaxStageGroups)
-  for (int64_t e = threadIdx.x; e < span * 2; e += blockDim.x)
-    sm[e] = *reinterpret_cast<const double4*>(bm + 8 * g0 + 4 * e);
+  const int span2 = (int)(2 * span);
+  // (host guarantees NT * span <= kMaxStageGroups)
+  for (int64_t e = threadIdx.x; e < span2 * NT; e += blockDim.x) {
+    const int64_t j = e / span2, k = e - (e / span2) * span2;
+    sm[e] = *reinterpret_cast<const double4*>(bm + j * ldm + 8 * g0 + 4 * k);
+  }
   __syncthreads();
   const int64_t n = span > wave ? (span - wave + WAVES - 1) / WAVES : 0;  // steps of this wave
   const int64_t gw = g0 + wave;  // group of step i: gw + WAVES * i
-  const int smw = 2 * wave + h;  // sm index of step i: smw + 2 WAVES i
+  const int smw = 2 * wave + h;  // sm index of step i: smw + 2 WAVES i (+ j span2 for column j)
   const float4* paw = pa + lane;
+  auto mean_of = [&](int64_t i, double4 (&m)[NT]) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) m[j] = sm[j * span2 + smw + 2 * WAVES * i];
+  };
+  double4 m[NT];
   if (n < 2 * RING) {  // short range: no ring
     for (int64_t i = 0; i < n; ++i) {
       const int64_t g = gw + (int64_t)WAVES * i;
-      mma_group(paw[g * 64], B4[(2 * g + h) * 32 + c], sm[smw + 2 * WAVES * i], acc, accm);
+      mean_of(i, m);
+      mma_group<NT>(paw[g * 64], B4[(2 * g + h) * 32 + c], m, acc, accm);
     }
   } else {
     float4 a[RING], b[RING];
@@ -232,7 +249,8 @@ __device__ __forceinline__ void gemm32(const float4* __restrict__ pa, int64_t g0
     for (; i0 + 2 * RING <= n; i0 += RING) {
 #pragma unroll
       for (int r = 0; r < RING; ++r) {
-        mma_group(a[r], b[r], sm[smw + 2 * WAVES * (i0 + r)], acc, accm);
+        mean_of(i0 + r, m);
+        mma_group<NT>(a[r], b[r], m, acc, accm);
         __builtin_amdgcn_sched_barrier(0);
         const int64_t gn = gw + (int64_t)WAVES * (i0 + r + RING);
         a[r] = paw[gn * 64];
@@ -244,7 +262,8 @@ __device__ __forceinline__ void gemm32(const float4* __restrict__ pa, int64_t g0
 #pragma unroll
     for (int r = 0; r < RING; ++r) {
       const int64_t i = i0 + r;
-      mma_group(a[r], b[r], sm[smw + 2 * WAVES * i], acc, accm);
+      mean_of(i, m);
+      mma_group<NT>(a[r], b[r], m, acc, accm);
       if (i + RING < n) {
         const int64_t gn = gw + (int64_t)WAVES * (i + RING);
         a[r] = paw[gn * 64];
@@ -254,24 +273,31 @@ __device__ __forceinline__ void gemm32(const float4* __restrict__ pa, int64_t g0
 #pragma unroll
     for (int r = 0; r < RING; ++r) {
       const int64_t i = i0 + RING + r;
-      if (i < n) mma_group(a[r], b[r], sm[smw + 2 * WAVES * i], acc, accm);
+      if (i < n) {
+        mean_of(i, m);
+        mma_group<NT>(a[r], b[r], m, acc, accm);
+      }
     }
   }
-  accm += __shfl_xor(accm, 32, 64);  // both halves of tile row c
+#pragma unroll
+  for (int j = 0; j < NT; ++j) accm[j] += __shfl_xor(accm[j], 32, 64);  // both halves of tile row c
 }
 
 // Sums the waves' tiles through LDS.  Thread e < 256 gets tile rows
 // 8k + 4h .. +3 of column c (k = e/64, l = e%64, c = l%32, h = l/32) as a
 // float4 -- four consecutive coordinates, i.e. one blocked-4 float4; thread
-// e < 32 gets the mean-column sum of tile row e.
-template <int WAVES>
-__device__ __forceinline__ void wg_reduce32(const floatx16& acc, double accm, float4* out, double* outm) {
+// e < 32 gets the sums of tile row e of every mean column.
+template <int WAVES, int NT>
+__device__ __forceinline__ void wg_reduce32(const floatx16& acc, const double (&accm)[NT], float4* out,
+                                            double (&outm)[NT]) {
   __shared__ float red[WAVES][16][64];
-  __shared__ double redm[WAVES][32];
+  __shared__ double redm[WAVES][NT][32];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int r = 0; r < 16; ++r) red[wave][r][lane] = acc[r];
-  if (lane < 32) redm[wave][lane] = accm;
+  if (lane < 32)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) redm[wave][j][lane] = accm[j];
   __syncthreads();
   if (threadIdx.x < 256) {
     const int k = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -283,10 +309,13 @@ __device__ __forceinline__ void wg_reduce32(const floatx16& acc, double accm, fl
     *out = make_float4(v[0], v[1], v[2], v[3]);
   }
   if (threadIdx.x < 32) {
-    double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) v += redm[w][threadIdx.x];
-    *outm = v;
+    for (int j = 0; j < NT; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) v += redm[w][j][threadIdx.x];
+      outm[j] = v;
+    }
   }
 }
 
@@ -298,9 +327,11 @@ __device__ __forceinline__ int64_t tile_f4(int64_t row0, int e) {
 
 // Cross-workgroup split of a tile's reduction: the last of `nsplit`
 // workgroups sums the stored partials (split order).  False in the others.
+// Mean column j's partial of split sp sits at (sp NT + j) rows_total + row.
+template <int NT>
 __device__ __forceinline__ bool split_reduce32(int nsplit, int split, int64_t row0, int64_t rows_total,
                                                float* __restrict__ part, double* __restrict__ partm,
-                                               uint32_t* counter, float4* v, double* vm) {
+                                               uint32_t* counter, float4* v, double (&vm)[NT]) {
   if (nsplit == 1) return true;
   const int e = threadIdx.x;
   if (e < 256) {
@@ -310,7 +341,9 @@ __device__ __forceinline__ bool split_reduce32(int nsplit, int split, int64_t ro
     store_agent(dst + 2, v->z);
     store_agent(dst + 3, v->w);
   }
-  if (e < 32) store_agent(&partm[(int64_t)split * rows_total + row0 + e], *vm);
+  if (e < 32)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) store_agent(&partm[((int64_t)split * NT + j) * rows_total + row0 + e], vm[j]);
   if (!last_block_ticket(counter, (uint32_t)nsplit)) return false;
   // partials loaded four splits at a time (16 loads in flight), summed in
   // split order
@@ -334,19 +367,22 @@ __device__ __forceinline__ bool split_reduce32(int nsplit, int split, int64_t ro
     *v = make_float4(t[0], t[1], t[2], t[3]);
   }
   if (e < 32) {
-    double t = 0.0;
-    for (int sp0 = 0; sp0 < nsplit; sp0 += 4) {
-      double x[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int sp = sp0 + u < nsplit ? sp0 + u : sp0;
-        x[u] = load_agent(&partm[(int64_t)sp * rows_total + row0 + e]);
+    for (int j = 0; j < NT; ++j) {
+      double t = 0.0;
+      for (int sp0 = 0; sp0 < nsplit; sp0 += 4) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int sp = sp0 + u < nsplit ? sp0 + u : sp0;
+          x[u] = load_agent(&partm[((int64_t)sp * NT + j) * rows_total + row0 + e]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (sp0 + u < nsplit) t += x[u];
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (sp0 + u < nsplit) t += x[u];
+      vm[j] = t;
     }
-    *vm = t;
   }
   if (e == 0) store_agent(counter, 0u);
   return true;
@@ -355,9 +391,11 @@ __device__ __forceinline__ bool split_reduce32(int nsplit, int split, int64_t ro
 constexpr int kGemmWaves = 8;
 
 // ------------------------------------------------ pass 1: W = Phi P
-template <int RING>
+// NT mean columns (tasks sharing alpha): column j of the float64 block at
+// pm + j Dp, its product at wm + j Np.
+template <int RING, int NT>
 __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass1(
-    const float4* __restrict__ phiA, int64_t G, int64_t gps, int nsplit, int64_t Np,
+    const float4* __restrict__ phiA, int64_t G, int64_t gps, int nsplit, int64_t Np, int64_t Dp,
     const float* __restrict__ P, const double* __restrict__ pm, float* __restrict__ Wpart,
     double* __restrict__ wmpart, float* __restrict__ W, double* __restrict__ wm,
     uint32_t* __restrict__ cnts, CgScalars* __restrict__ st, int apply_only) {
@@ -369,33 +407,46 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass1(
   floatx16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-  double accm = 0.0;
-  gemm32<kGemmWaves, RING>(phiA + tile * G * 64, g0, g1, reinterpret_cast<const float4*>(P), pm, acc,
-                           accm);
+  double accm[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) accm[j] = 0.0;
+  gemm32<kGemmWaves, RING, NT>(phiA + tile * G * 64, g0, g1, reinterpret_cast<const float4*>(P), pm, Dp, acc,
+                               accm);
   float4 v;
-  double vm;
-  wg_reduce32<kGemmWaves>(acc, accm, &v, &vm);
+  double vm[NT];
+  wg_reduce32<kGemmWaves, NT>(acc, accm, &v, vm);
   const int64_t row0 = tile * 32;
-  if (!split_reduce32(nsplit, split, row0, Np, Wpart, wmpart, &cnts[tile * kCounterStride], &v, &vm)) return;
+  if (!split_reduce32<NT>(nsplit, split, row0, Np, Wpart, wmpart, &cnts[tile * kCounterStride], &v, vm)) return;
   if (threadIdx.x < 256) reinterpret_cast<float4*>(W)[tile_f4(row0, threadIdx.x)] = v;
-  if (threadIdx.x < 32) wm[row0 + threadIdx.x] = vm;
+  if (threadIdx.x < 32)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) wm[j * Np + row0 + threadIdx.x] = vm[j];
 }
 
 hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, const double* pm,
                        float* Wpart, double* wmpart, float* W, double* wm, uint32_t* cnts,
                        CgScalars* st, int apply_only, hipStream_t s) {
   const int64_t tiles = dd.Np / 32, G = dd.Dp / 8;
-  if (!dense_split_ok(G, dd.S1)) return hipErrorInvalidValue;
+  if (!dense_split_ok(G, dd.S1, dd.nt)) return hipErrorInvalidValue;
   const int64_t gps = (G + dd.S1 - 1) / dd.S1;
-#define COFEM_PASS1(RG)                                                                              \
-  hipLaunchKernelGGL(k_dense_pass1<RG>, dim3((unsigned)tiles, (unsigned)dd.S1), dim3(64 * kGemmWaves), 0, \
-                     s, reinterpret_cast<const float4*>(phiA), G, gps, dd.S1, dd.Np, P, pm, Wpart, wmpart, \
-                     W, wm, cnts, st, apply_only)
-  switch (dd.ring) {
-    case 1: COFEM_PASS1(1); break;
-    case 2: COFEM_PASS1(2); break;
-    case 8: COFEM_PASS1(8); break;
-    default: COFEM_PASS1(4); break;
+#define COFEM_PASS1(RG, NT)                                                                               \
+  hipLaunchKernelGGL((k_dense_pass1<RG, NT>), dim3((unsigned)tiles, (unsigned)dd.S1), dim3(64 * kGemmWaves), \
+                     0, s, reinterpret_cast<const float4*>(phiA), G, gps, dd.S1, dd.Np, dd.Dp, P, pm, Wpart,   \
+                     wmpart, W, wm, cnts, st, apply_only)
+  if (dd.nt == 1) {
+    switch (dd.ring) {
+      case 1: COFEM_PASS1(1, 1); break;
+      case 2: COFEM_PASS1(2, 1); break;
+      case 8: COFEM_PASS1(8, 1); break;
+      default: COFEM_PASS1(4, 1); break;
+    }
+  } else {
+    switch (dd.nt) {  // several tasks: the default ring only
+      case 2: COFEM_PASS1(4, 2); break;
+      case 3: COFEM_PASS1(4, 3); break;
+      case 4: COFEM_PASS1(4, 4); break;
+      default: return hipErrorInvalidValue;
+    }
   }
 #undef COFEM_PASS1
   return hipGetLastError();
@@ -404,9 +455,10 @@ hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, c
 // ------------------------------------------------ pass 2: Q = beta Phi^T W + alpha (.) P
 // The epilogue also forms the per-column dots gam = p^T q, del = r^T q and
 // eta = q^T q; the tree reduction's final workgroup turns them into a_c, b_c.
-template <int RING>
+// NT mean columns: column j of W at wm + j Np, of p, r, q at + j Dp.
+template <int RING, int NT>
 __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
-    const float4* __restrict__ phiB, int64_t G2, int64_t gps, int nsplit, int64_t Dp,
+    const float4* __restrict__ phiB, int64_t G2, int64_t gps, int nsplit, int64_t Np, int64_t Dp,
     const float* __restrict__ W, const double* __restrict__ wm, const float* __restrict__ P,
     const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
     const float* __restrict__ alpha, double beta, float* __restrict__ Qpart,
@@ -415,7 +467,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
     CgScalars* __restrict__ st, int apply_only) {
   if (!apply_only && st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
-  constexpr int nc = kDenseKP + 1;
+  constexpr int nc = kDenseKP + NT;
   const int64_t tile = blockIdx.x;
   const int split = blockIdx.y;
   const int64_t g0 = split * gps;
@@ -423,14 +475,17 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
   floatx16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-  double accm = 0.0;
-  gemm32<kGemmWaves, RING>(phiB + tile * G2 * 64, g0, g1, reinterpret_cast<const float4*>(W), wm, acc,
-                           accm);
+  double accm[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) accm[j] = 0.0;
+  gemm32<kGemmWaves, RING, NT>(phiB + tile * G2 * 64, g0, g1, reinterpret_cast<const float4*>(W), wm, Np, acc,
+                               accm);
   float4 v;
-  double vm;
-  wg_reduce32<kGemmWaves>(acc, accm, &v, &vm);
+  double vm[NT];
+  wg_reduce32<kGemmWaves, NT>(acc, accm, &v, vm);
   const int64_t d0 = tile * 32;
-  if (!split_reduce32(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[tile * kCounterStride], &v, &vm)) return;
+  if (!split_reduce32<NT>(nsplit, split, d0, Dp, Qpart, qmpart, &split_cnts[tile * kCounterStride], &v, vm))
+    return;
 
   __shared__ double sdots[3][256];
   __shared__ double mine[3 * nc], tot[3 * nc];
@@ -454,27 +509,36 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
       sdots[2][e] = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
     }
   }
-  double gmm = 0.0, dmm = 0.0, emm = 0.0;
+  double gmm[NT], dmm[NT], emm[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) gmm[j] = dmm[j] = emm[j] = 0.0;
   if (e < 32) {
     const int64_t d = d0 + e;
-    const double p = pm[d];
-    const double q = beta * vm + (double)alpha[d] * p;
-    qm[d] = q;
-    gmm = p * q;
-    dmm = rm[d] * q;
-    emm = q * q;
+    const double a = (double)alpha[d];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const double p = pm[j * Dp + d];
+      const double q = beta * vm[j] + a * p;
+      qm[j * Dp + d] = q;
+      gmm[j] = p * q;
+      dmm[j] = rm[j * Dp + d] * q;
+      emm[j] = q * q;
+    }
   }
   if (apply_only) return;
   if (e < 64) {  // wave 0: mean-column dots over the tile's 32 coordinates
-    for (int off = 16; off > 0; off >>= 1) {
-      gmm += __shfl_xor(gmm, off, 64);
-      dmm += __shfl_xor(dmm, off, 64);
-      emm += __shfl_xor(emm, off, 64);
-    }
-    if (e == 0) {
-      mine[kDenseKP] = gmm;
-      mine[nc + kDenseKP] = dmm;
-      mine[2 * nc + kDenseKP] = emm;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      for (int off = 16; off > 0; off >>= 1) {
+        gmm[j] += __shfl_xor(gmm[j], off, 64);
+        dmm[j] += __shfl_xor(dmm[j], off, 64);
+        emm[j] += __shfl_xor(emm[j], off, 64);
+      }
+      if (e == 0) {
+        mine[kDenseKP + j] = gmm[j];
+        mine[nc + kDenseKP + j] = dmm[j];
+        mine[2 * nc + kDenseKP + j] = emm[j];
+      }
     }
   }
   __syncthreads();
@@ -496,17 +560,26 @@ hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, c
                        double* qm, double* gpart, uint32_t* counter, uint32_t* split_cnts,
                        CgScalars* st, int apply_only, hipStream_t s) {
   const int64_t tiles = dd.Dp / 32, G2 = dd.Np / 8;
-  if (!dense_split_ok(G2, dd.S2)) return hipErrorInvalidValue;
+  if (!dense_split_ok(G2, dd.S2, dd.nt)) return hipErrorInvalidValue;
   const int64_t gps = (G2 + dd.S2 - 1) / dd.S2;
-#define COFEM_PASS2(RG)                                                                              \
-  hipLaunchKernelGGL(k_dense_pass2<RG>, dim3((unsigned)tiles, (unsigned)dd.S2), dim3(64 * kGemmWaves), 0, \
-                     s, reinterpret_cast<const float4*>(phiB), G2, gps, dd.S2, dd.Dp, W, wm, P, pm, R, rm, \
-                     alpha, beta, Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only)
-  switch (dd.ring) {
-    case 1: COFEM_PASS2(1); break;
-    case 2: COFEM_PASS2(2); break;
-    case 8: COFEM_PASS2(8); break;
-    default: COFEM_PASS2(4); break;
+#define COFEM_PASS2(RG, NT)                                                                               \
+  hipLaunchKernelGGL((k_dense_pass2<RG, NT>), dim3((unsigned)tiles, (unsigned)dd.S2), dim3(64 * kGemmWaves), \
+                     0, s, reinterpret_cast<const float4*>(phiB), G2, gps, dd.S2, dd.Np, dd.Dp, W, wm, P, pm, R, \
+                     rm, alpha, beta, Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only)
+  if (dd.nt == 1) {
+    switch (dd.ring) {
+      case 1: COFEM_PASS2(1, 1); break;
+      case 2: COFEM_PASS2(2, 1); break;
+      case 8: COFEM_PASS2(8, 1); break;
+      default: COFEM_PASS2(4, 1); break;
+    }
+  } else {
+    switch (dd.nt) {
+      case 2: COFEM_PASS2(4, 2); break;
+      case 3: COFEM_PASS2(4, 3); break;
+      case 4: COFEM_PASS2(4, 4); break;
+      default: return hipErrorInvalidValue;
+    }
   }
 #undef COFEM_PASS2
   return hipGetLastError();
@@ -516,18 +589,19 @@ hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, c
 // 512-thread workgroups per CU (512 in all), at least 32 groups per wave.
 // Measured on the 4096 x 16384 problem, 1024 workgroups (more splits, more
 // partial-sum traffic) was no faster than 512.
-int dense_split(int64_t tiles, int64_t groups) {
+int dense_split(int64_t tiles, int64_t groups, int nt) {
   int64_t s = (512 + tiles - 1) / tiles;
   const int64_t most = groups / (32 * kGemmWaves);
   if (s > most) s = most;
   if (s > 16) s = 16;
-  const int64_t least = (groups + kMaxStageGroups - 1) / kMaxStageGroups;  // LDS staging limit
+  const int64_t stage = kMaxStageGroups / nt;  // LDS staging limit (nt mean columns)
+  const int64_t least = (groups + stage - 1) / stage;
   if (s < least) s = least;
   return (int)(s < 1 ? 1 : s);
 }
 
-bool dense_split_ok(int64_t groups, int splits) {
-  return splits >= 1 && (groups + splits - 1) / splits <= kMaxStageGroups;
+bool dense_split_ok(int64_t groups, int splits, int nt) {
+  return splits >= 1 && nt >= 1 && (groups + splits - 1) / splits <= kMaxStageGroups / nt;
 }
 
 // ------------------------------------------------ CG update
@@ -540,7 +614,7 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
                                                       double* __restrict__ pm,
                                                       const double* __restrict__ qm,
                                                       double* __restrict__ parts, uint32_t* cnts,
-                                                      CgScalars* st) {
+                                                      CgScalars* st, int nt = 1) {
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
@@ -604,7 +678,7 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
       }
     }
   }
-  double accm = 0.0;
+  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t d = gtid; d < Dp; d += gstride) {
     if (d != gtid) {
       m_x = xm[d];
@@ -616,11 +690,24 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
     const double rv = fma(-am, m_q, m_r);
     rm[d] = rv;
     pm[d] = fma(bmm, m_p, rv);
-    accm += rv * rv;
+    accm[0] += rv * rv;
   }
-  __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
-  dense_block_sums(acc, accm, mine);
-  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + 1, mine, tot)) return;
+  // further mean columns (tasks sharing alpha)
+  for (int j = 1; j < nt; ++j) {
+    const double aj = st->a[kDenseKP + j], bj = st->b[kDenseKP + j];
+    const int64_t o = j * Dp;
+    for (int64_t d = gtid; d < Dp; d += gstride) {
+      const double xv = xm[o + d], rv0 = rm[o + d], pv = pm[o + d], qv = qm[o + d];
+      xm[o + d] = fma(aj, pv, xv);
+      const double rv = fma(-aj, qv, rv0);
+      rm[o + d] = rv;
+      pm[o + d] = fma(bj, pv, rv);
+      accm[j] += rv * rv;
+    }
+  }
+  __shared__ double mine[kDenseKP + kMaxDenseTasks], tot[kDenseKP + kMaxDenseTasks];
+  dense_block_sums(acc, accm, nt, mine);
+  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + nt, mine, tot)) return;
   finish_update(st, tot, ctl);
 }
 
@@ -632,15 +719,15 @@ __global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restr
                                                       double* __restrict__ pm,
                                                       const double* __restrict__ qm,
                                                       double* __restrict__ parts, uint32_t* cnts,
-                                                      CgScalars* st) {
-  dense_update_body(blockIdx.x, gridDim.x, Dp, X, R, P, Q, xm, rm, pm, qm, parts, cnts, st);
+                                                      CgScalars* st, int nt) {
+  dense_update_body(blockIdx.x, gridDim.x, Dp, X, R, P, Q, xm, rm, pm, qm, parts, cnts, st, nt);
 }
 
 hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
                         double* xm, double* rm, double* pm, const double* qm, double* parts,
                         uint32_t* cnts, CgScalars* st, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_update, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.Dp, X, R, P,
-                     Q, xm, rm, pm, qm, parts, cnts, st);
+                     Q, xm, rm, pm, qm, parts, cnts, st, dd.nt);
   return hipGetLastError();
 }
 
@@ -653,7 +740,7 @@ __global__ __launch_bounds__(256) void k_dense_true_resid(int64_t D, int64_t Dp,
                                                           const float* __restrict__ Q,
                                                           const double* __restrict__ qm,
                                                           double* __restrict__ parts, uint32_t* cnts,
-                                                          CgScalars* st) {
+                                                          CgScalars* st, int nt) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   const int c = threadIdx.x & 31;  // gstride is a multiple of 32: fixed column per thread
@@ -670,14 +757,15 @@ __global__ __launch_bounds__(256) void k_dense_true_resid(int64_t D, int64_t Dp,
       acc += e * e;
     }
   }
-  double accm = 0.0;
-  for (int64_t d = gtid; d < Dp; d += gstride) {
-    const double e = b0[d] - qm[d];
-    accm += e * e;
-  }
-  __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
-  dense_block_sums(acc, accm, mine);
-  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, kDenseKP + 1, mine, tot)) return;
+  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < nt; ++j)
+    for (int64_t d = gtid; d < Dp; d += gstride) {
+      const double e = b0[j * Dp + d] - qm[j * Dp + d];
+      accm[j] += e * e;
+    }
+  __shared__ double mine[kDenseKP + kMaxDenseTasks], tot[kDenseKP + kMaxDenseTasks];
+  dense_block_sums(acc, accm, nt, mine);
+  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, kDenseKP + nt, mine, tot)) return;
   finish_true_resid(st, tot);
 }
 
@@ -685,7 +773,7 @@ hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, co
                             const float* Q, const double* qm, double* parts, uint32_t* cnts,
                             CgScalars* st, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_true_resid, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed,
-                     t, K, b0, Q, qm, parts, cnts, st);
+                     t, K, b0, Q, qm, parts, cnts, st, dd.nt);
   return hipGetLastError();
 }
 
@@ -696,7 +784,7 @@ __device__ __forceinline__ void dense_mstep_body(int64_t blk, int64_t nblk, int6
                                                      float* __restrict__ alpha, double alpha_max,
                                                      float* __restrict__ mu,
                                                      float* __restrict__ sdiag, double* parts, uint32_t* cnts,
-                                                     CgScalars* st) {
+                                                     CgScalars* st, int nt = 1, int64_t ldm = 0) {
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
@@ -707,7 +795,16 @@ __device__ __forceinline__ void dense_mstep_body(int64_t blk, int64_t nblk, int6
       acc += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)d) * (double)X[blk4(d, k)];
     const double s = acc / (double)K;
     const double m = xm[d];
-    const double den = m * m + s;
+    // tasks sharing alpha: the mean of their squared means
+    double m2 = m * m;
+    if (nt > 1) {
+      for (int j = 1; j < nt; ++j) {
+        const double mj = xm[j * ldm + d];
+        m2 += mj * mj;
+      }
+      m2 /= (double)nt;
+    }
+    const double den = m2 + s;
     if (!(den >= floor_v)) clamped += 1.0;
     const float a_new = (float)(1.0 / (den >= floor_v ? den : floor_v));
     // change of the prior variance 1/alpha as the stored (float32) alpha has it
@@ -739,8 +836,9 @@ __global__ __launch_bounds__(256) void k_dense_mstep(int64_t D, uint64_t seed, i
                                                      float* __restrict__ alpha, double alpha_max,
                                                      float* __restrict__ mu,
                                                      float* __restrict__ sdiag, double* parts, uint32_t* cnts,
-                                                     CgScalars* st) {
-  dense_mstep_body(blockIdx.x, gridDim.x, D, seed, t, K, X, xm, alpha, alpha_max, mu, sdiag, parts, cnts, st);
+                                                     CgScalars* st, int nt, int64_t ldm) {
+  dense_mstep_body(blockIdx.x, gridDim.x, D, seed, t, K, X, xm, alpha, alpha_max, mu, sdiag, parts, cnts, st, nt,
+                   ldm);
 }
 
 hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const float* X,
@@ -751,7 +849,7 @@ hipError_t dense_mstep(const DenseDims& dd, uint64_t seed, int t, int K, const f
   const int64_t want = (dd.D + 255) / 256, cap = dense_update_blocks(dd);
   const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > cap ? cap : want));
   hipLaunchKernelGGL(k_dense_mstep, dim3(blocks), dim3(256), 0, s, dd.D, seed, t, K, X, xm, alpha,
-                     alpha_max, mu, sdiag, parts, cnts, st);
+                     alpha_max, mu, sdiag, parts, cnts, st, dd.nt, dd.Dp);
   return hipGetLastError();
 }
 

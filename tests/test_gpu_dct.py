@@ -315,7 +315,7 @@ def test_dct_multitask_true_residual_covers_every_task(torch_dev):
     assert abs(st["rel_resid_true"] - ref) <= 0.02 * ref + floor
 
 
-def test_multitask_is_rejected_outside_the_dct_dictionary(torch_dev):
+def test_multitask_rejections(torch_dev):
     torch = torch_dev
     from paper_2202_12808_amd import cofem as C
     rng = np.random.default_rng(1)
@@ -323,8 +323,9 @@ def test_multitask_is_rejected_outside_the_dct_dictionary(torch_dev):
     y = torch.from_numpy(rng.standard_normal(32).astype(np.float32)).cuda()
     prob = C.cofem_problem(kind=C.COFEM_DENSE, N=16, D=64, phi=phi.data_ptr(), ld_phi=64, phi_dtype=C.COFEM_F32,
                            H=0, W=0, kh=0, kw=0, taps=None, y=y.data_ptr(), rows=None, n_tasks=2)
+    # several tasks are not built for the mixed-precision refinement
     with pytest.raises(C.CofemError) as ei:
-        C.CoFEM(prob, C.CoFEM._params(10.0, 4, 1e-5, 100, 0), (phi, y), phi.device)
+        C.CoFEM(prob, C.CoFEM._params(10.0, 4, 1e-5, 100, 0, precision="bf16_ir"), (phi, y), phi.device)
     assert ei.value.status == C.COFEM_ERR_UNSUPPORTED
     p = synth.dct_multitask(4096, 60, rho=0.04, beta=4e4, K=8, tol=1e-5, seed=1)  # K + T > 64
     with pytest.raises(C.CofemError) as ei:

@@ -1,5 +1,5 @@
 """Multi-task SBL (the extension Sec. 5 names: T observation vectors sharing
-alpha) on the convolution dictionary, through the C ABI, against the float64
+alpha) on the convolution and dense dictionaries, through the C ABI, against the float64
 multi-task oracle: one teacher-forced E-step + M-step at the GPU's CG count,
 with and without the warm-started Jacobi form, and the true residual of
 every task's column."""
@@ -53,6 +53,9 @@ def _op(p):
 
 
 _CASES = {
+    "dense_T2": (lambda: synth.dense_multitask(256, 1024, 2, rho=0.02, beta=1e4, K=20, tol=1e-6, seed=5), {}),
+    "dense_T4_ragged": (lambda: synth.dense_multitask(300, 777, 4, rho=0.02, beta=5e3, K=13, tol=1e-6, seed=6), {}),
+    "dense_T3_split": (lambda: synth.dense_multitask(512, 8192, 3, rho=0.02, beta=1e3, K=32, tol=1e-5, seed=7), {}),
     "conv_T3": (lambda: synth.conv_multitask(64, 48, 7, 3, rho=0.02, beta=100.0, K=8, tol=1e-6, seed=5), {}),
     "conv_T4_jacobi_warm": (lambda: synth.conv_multitask(40, 52, 5, 4, rho=0.03, beta=1e3, K=6, tol=1e-5, seed=6),
                             {"jacobi": True, "warm_start": True}),
@@ -70,6 +73,7 @@ def test_multitask_step_parity(torch_dev, case):
     op = _op(p)
     B0 = p.beta * op.apply_t(p.y.T.astype(np.float64))
     pcg = kw.get("jacobi") or kw.get("warm_start")
+    _say("multitask case", case, "kind", p.kind, "T", T, "D", p.D, "K", p.K)
     with _ctx(torch, p, **kw) as g:
         g.em_step(3)
         _, s_prev, alpha = [x.cpu().numpy().astype(np.float64) for x in g.posterior()]
@@ -99,9 +103,11 @@ def test_multitask_step_parity(torch_dev, case):
     assert max(per_task) < STEP_TOL
 
 
-def test_multitask_true_residual_covers_every_task(torch_dev):
+@pytest.mark.parametrize("kind", ["conv", "dense"])
+def test_multitask_true_residual_covers_every_task(torch_dev, kind):
     torch = torch_dev
-    p = synth.conv_multitask(40, 36, 5, 3, rho=0.03, beta=1e3, K=8, tol=1e-5, seed=8)
+    p = (synth.conv_multitask(40, 36, 5, 3, rho=0.03, beta=1e3, K=8, tol=1e-5, seed=8) if kind == "conv"
+         else synth.dense_multitask(200, 700, 3, rho=0.02, beta=1e3, K=10, tol=1e-5, seed=8))
     op = _op(p)
     B0 = p.beta * op.apply_t(p.y.T.astype(np.float64))
     with _ctx(torch, p) as g:
@@ -117,16 +123,31 @@ def test_multitask_true_residual_covers_every_task(torch_dev):
     assert abs(st["rel_resid_true"] - ref) <= 0.05 * ref + 1e-7
 
 
-def test_one_task_array_equals_single_task(torch_dev):
-    # y given as a (1, D) array is the single-task problem, bit for bit
+@pytest.mark.parametrize("kind", ["conv", "dense"])
+def test_one_task_array_equals_single_task(torch_dev, kind):
+    # y given as a (1, N) array is the single-task problem, bit for bit
     torch = torch_dev
-    p = synth.conv_problem(40, 36, 5, rho=0.03, beta=1e3, K=6, tol=1e-5, seed=9)
-    from paper_2202_12808_amd.cofem import CoFEM
+    p = (synth.conv_problem(40, 36, 5, rho=0.03, beta=1e3, K=6, tol=1e-5, seed=9) if kind == "conv"
+         else synth.dense_problem(200, 700, nnz=8, beta=1e3, K=12, tol=1e-5, seed=9))
     outs = []
     for y in (p.y, p.y[None, :]):
-        with CoFEM.conv(torch.from_numpy(p.taps).cuda(), torch.from_numpy(np.ascontiguousarray(y)).cuda(), p.H, p.W,
-                        p.beta, p.K, tol=p.tol, seed=p.seed) as g:
+        q = synth.Problem(**{**p.__dict__, "y": np.ascontiguousarray(y)})
+        with _ctx(torch, q) as g:
             g.em_step(3)
             outs.append([x.cpu().numpy() for x in g.posterior()])
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_dense_multitask_rejections(torch_dev):
+    torch = torch_dev
+    from paper_2202_12808_amd import cofem as C
+    p = synth.dense_multitask(64, 128, 2, rho=0.05, beta=100.0, K=4, tol=1e-5, seed=1)
+    for kw in ({"precision": "bf16_ir"}, {"warm_start": True}):
+        with pytest.raises(C.CofemError) as ei:
+            _ctx(torch, p, **kw)
+        assert ei.value.status == C.COFEM_ERR_UNSUPPORTED
+    p5 = synth.dense_multitask(64, 128, 5, rho=0.05, beta=100.0, K=4, tol=1e-5, seed=1)
+    with pytest.raises(C.CofemError) as ei:
+        _ctx(torch, p5)
+    assert ei.value.status == C.COFEM_ERR_UNSUPPORTED
