@@ -28,6 +28,7 @@ from .cofem_oracle import (  # noqa: F401
     mstep,
     pcg_solve,
     rademacher_probes,
+    spectral_operator,
     splitmix64_mix,
     splitmix64_stream,
     true_relative_residual,

@@ -214,6 +214,16 @@ class ConvOperatorFFT:
     def column_norms_sq(self) -> np.ndarray:
         return np.full(self.D, float(np.sum(self.taps ** 2)))
 
+    def solve_shifted(self, B: np.ndarray, beta: float, a: float) -> np.ndarray:
+        """X = (beta Phi^T Phi + a I)^-1 B: with a uniform alpha = a the matrix
+        A of Eq. 3 is block-circulant (Phi^T Phi is a circular convolution), so
+        the 2D DFT diagonalises it with eigenvalues beta |h_hat|^2 + a and the
+        solve is a division in the Fourier domain (not in the paper: the exact
+        start of the spectral form)."""
+        if not a > 0.0:
+            raise ValueError("a must be positive")
+        return self._filter(B, 1.0 / (beta * self.gram_hat + float(a)))
+
 
 class DctMaskOperator:
     """Inverse DCT followed by an undersampling mask (the structured dictionary
@@ -578,18 +588,34 @@ def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray,
     return EStepResult(mu=mu, s=s, X=X, P=P, cg=cg), info
 
 
+def spectral_operator(op) -> "ConvOperatorFFT":
+    """The Fourier-domain form of a circular-convolution dictionary."""
+    if isinstance(op, ConvOperatorFFT):
+        return op
+    if isinstance(op, ConvOperator):
+        return ConvOperatorFFT(op.taps, op.H, op.W)
+    raise ValueError("the spectral start needs a circular-convolution dictionary")
+
+
 def cofem_estep_pcg(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int, tol: float, max_iter: int,
                     seed: int, t: int, minv=None, mu0=None, d0=None, fixed_iters=None,
-                    stop_rule: str = "frobenius") -> EStepResult:
+                    stop_rule: str = "frobenius", spectral: bool = False) -> EStepResult:
     """The E-step of Algorithm 1 solved by ``pcg_solve``: M^-1 = diag(minv);
     starting block X0 = [d0 (.) p_1 .. d0 (.) p_K | mu0] (a warm start for
     the probe solves x_k ~ Sigma p_k from a diagonal estimate d0, and for mu);
-    None entries start from zero."""
+    None entries start from zero.  ``spectral`` (convolution dictionaries,
+    alpha uniform): X0 = A^-1 B from ``ConvOperatorFFT.solve_shifted``
+    instead, and the solve goes on from there with its own stop test."""
     D = op.D
     P = rademacher_probes(seed, t, K, D)
     B = np.concatenate([P, np.asarray(b0, np.float64)[:, None]], axis=1)
     X0 = None
-    if mu0 is not None or d0 is not None:
+    if spectral:
+        alpha = np.asarray(alpha, np.float64)
+        if not np.all(alpha == alpha[0]):
+            raise ValueError("the spectral start needs a uniform alpha")
+        X0 = spectral_operator(op).solve_shifted(B, beta, float(alpha[0]))
+    elif mu0 is not None or d0 is not None:
         X0 = np.zeros_like(B)
         if d0 is not None:
             X0[:, :K] = np.asarray(d0, np.float64)[:, None] * P
@@ -625,7 +651,7 @@ def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
           alpha0: Optional[np.ndarray] = None, t0: int = 1,
           fixed_iters=None, stop_rule: str = "frobenius",
           em_tol: Optional[float] = None, warm_start: bool = False,
-          jacobi: bool = False) -> CoFEMResult:
+          jacobi: bool = False, spectral_start: bool = False) -> CoFEMResult:
     """CovarianceFreeEM(y, Phi, beta, T_em, K) of Algorithm 1.
 
     alpha starts at 1 (or ``alpha0``); EM iterations are numbered t0, t0+1, ...
@@ -639,6 +665,9 @@ def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
     starts from X0 = [max(s_prev, 0) (.) p_k | mu_prev], and/or is
     preconditioned by the inverse diagonal of A, 1 / (beta ||Phi e_j||^2 +
     alpha_j) (``cofem_estep_pcg``); the stop test is unchanged.
+    ``spectral_start`` (convolution dictionaries, not in the paper): every
+    E-step whose alpha is uniform (the first one from alpha = 1) starts from
+    the exact solve of ``ConvOperatorFFT.solve_shifted``.
     """
     D = op.D
     alpha = np.ones(D) if alpha0 is None else np.asarray(alpha0, np.float64).copy()
@@ -649,8 +678,10 @@ def cofem(op, y: np.ndarray, beta: float, T_em: int, K: int, *, tol: float,
     for i in range(T_em):
         t = t0 + i
         fi = fixed_iters[i] if isinstance(fixed_iters, (list, tuple, np.ndarray)) else fixed_iters
-        if warm_start or jacobi:
+        if warm_start or jacobi or spectral_start:
             start = dict(mu0=mu, d0=np.maximum(s, 0.0)) if (warm_start and mu is not None) else {}
+            if spectral_start and np.all(alpha == alpha[0]):
+                start = dict(spectral=True)
             minv = 1.0 / (beta * cn + alpha) if jacobi else None
             e = cofem_estep_pcg(op, b0, beta, alpha, K, tol, max_iter, seed, t, minv=minv, fixed_iters=fi,
                                 stop_rule=stop_rule, **start)
