@@ -96,6 +96,7 @@ FORMS = {"fp32": "fp32 probes + fp64 mean column",
                     "previous mean and diagonal estimate",
          "control": "fp32 CG started from the previous mean and diagonal estimate, Jacobi-preconditioned",
          "learned": "fp32 CG started from a learned prediction, Jacobi-preconditioned"}
+SPECTRAL_NOTE = "; the first E-step (alpha = 1) starts from the 2D-DFT solve of its block-circulant system"
 DENSE_FORM_ORDER = ("bf16_ir", "fp32_warm", "fp32")
 FORMS_DCT = {"fp32": "inverse-DCT + mask dictionary, plain fp32 CG + fp64 mean column",
              "control": "inverse-DCT + mask dictionary, fp32 CG started from the previous mean and diagonal "
@@ -138,7 +139,8 @@ def stored_traffic(kind, kernel, workload):
         return None
 
 
-def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=None, epochs=20, lr=1e-3):
+def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=None, epochs=20, lr=1e-3,
+                    spectral=True):
     """Trains the learned form's network on EM iterates of `seeds` (disjoint
     from the evaluation seed) at train_size^2 with the workload's kernel law,
     beta, K and tolerance (warm-started Jacobi solves give the targets), then
@@ -158,7 +160,8 @@ def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=N
         q = synth.conv_problem(hs, ws, p.taps.shape[0], rho=float(round(p.z.astype(bool).mean(), 4)), beta=p.beta,
                                K=p.K, tol=p.tol, max_iter=p.max_iter, seed=sd, name="train")
         return CoFEM.conv(torch.from_numpy(q.taps).to(dev), torch.from_numpy(q.y).to(dev), q.H, q.W, q.beta, q.K,
-                          tol=q.tol, max_iter=q.max_iter, seed=sd, jacobi=True, warm_start=True)
+                          tol=q.tol, max_iter=q.max_iter, seed=sd, jacobi=True, warm_start=True,
+                          spectral_start=spectral)
 
     # every EM iteration of the workload's run: late iterations, where the
     # previous iterate is already a good start, must be learned too
@@ -587,12 +590,13 @@ def run_conv(args):
     y = torch.from_numpy(p.y).to(dev)
     net = train_info = None
     if form == "learned" or not args.no_compare:
-        net, train_info = train_predictor(p, dev)
+        net, train_info = train_predictor(p, dev, spectral=not args.no_spectral)
 
     def make(f):
         ctl = f == "control"
+        spec = f in ("control", "learned") and not args.no_spectral
         c = CoFEM.conv(taps, y, p.H, p.W, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, jacobi=ctl,
-                       warm_start=ctl)
+                       warm_start=ctl, spectral_start=spec)
         if f == "learned":
             c.set_predictor(net)
         return c
@@ -752,7 +756,8 @@ def run_conv(args):
         "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": p.name, "N": p.N, "D": p.D, "K": p.K, "beta": p.beta, "cg_tol": p.tol,
-                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": form, "form_detail": FORMS[form],
+                   "cg_max_iter": p.max_iter, "T_em": T_em, "form": form,
+                   "form_detail": FORMS[form] + ("" if args.no_spectral or form == "fp32" else SPECTRAL_NOTE),
                    "cg_iters_per_em_mean": round(float(np.mean(cg_counts)), 2),
                    "nrmse_vs_truth": forms[form]["nrmse_vs_truth"]},
         "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "oracle_trajectory": traj,
@@ -989,6 +994,9 @@ def main():
                     help="time only the headline form")
     ap.add_argument("--no-secondary", action="store_true",
                     help="conv workloads: skip the dense 4096 x 16384 summary carried in the same line")
+    ap.add_argument("--no-spectral", action="store_true",
+                    help="conv workloads: start the control and learned forms' first E-step from zero instead "
+                         "of the 2D-DFT solve")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -100,7 +100,20 @@ enum {
   /* Convolution and DCT dictionaries: diagonal (Jacobi) preconditioner
    * M^-1 = 1 / (beta ||h||^2 + alpha), the inverse diagonal of A.  The stop
    * test stays the unpreconditioned one of Sec. 3.2. */
-  COFEM_FLAG_JACOBI = 16
+  COFEM_FLAG_JACOBI = 16,
+  /* Convolution dictionaries (single problems, H and W powers of two, each at
+   * most 4096): while alpha is uniform -- the first E-step after cofem_init
+   * or cofem_restart, alpha = 1 -- start the solve from X0 = A^-1 B formed by
+   * 2D DFTs.  With alpha = a everywhere, A = beta Phi^T Phi + a I (Eq. 3) is
+   * block-circulant and the DFT diagonalises it with eigenvalues
+   * beta |h_hat|^2 + a, so X0 is the exact solve up to single-precision
+   * rounding (complex float32 transforms); CG's stop test (Sec. 3.2) then
+   * judges X0 and corrects it, usually in one to three iterations (not in the
+   * paper: a start).  Later E-steps start as the other flags say.  After
+   * cofem_set_alpha alpha counts as non-uniform until cofem_restart.  Costs
+   * ceil((K + T)/2) * D * 8 bytes of transform workspace plus D * 4 bytes of
+   * eigenvalue table. */
+  COFEM_FLAG_SPECTRAL_START = 32
 };
 
 /* Maximum number of probe vectors K per problem. */

@@ -40,6 +40,7 @@ COFEM_FLAG_EAGER = 2
 COFEM_FLAG_BATCHED = 4
 COFEM_FLAG_WARM_PREV = 8
 COFEM_FLAG_JACOBI = 16
+COFEM_FLAG_SPECTRAL_START = 32
 _PRECISIONS = {"fp32": COFEM_PREC_FP32, "bf16_ir": COFEM_PREC_BF16_IR, "fp64": COFEM_PREC_FP64}
 COFEM_MAX_K = 32
 
@@ -333,9 +334,9 @@ class CoFEM:
     @staticmethod
     def _params(beta, K, tol, max_iter, seed, alpha_max=1e10, poll_interval=0, precision="fp32",
                 true_residual=True, ir_inner_tol=0.0, ir_max_sweeps=0, warm_start=False, jacobi=False,
-                stop_rule="frobenius"):
+                stop_rule="frobenius", spectral_start=False):
         flags = ((COFEM_FLAG_TRUE_RESIDUAL if true_residual else 0) | (COFEM_FLAG_WARM_PREV if warm_start else 0)
-                 | (COFEM_FLAG_JACOBI if jacobi else 0))
+                 | (COFEM_FLAG_JACOBI if jacobi else 0) | (COFEM_FLAG_SPECTRAL_START if spectral_start else 0))
         return cofem_params(beta=float(beta), K=int(K), cg_tol=float(tol), cg_max_iter=int(max_iter),
                             seed=int(seed) & 0xFFFFFFFFFFFFFFFF, precision=_PRECISIONS[precision],
                             stop_rule=_STOP_RULES[stop_rule], alpha_max=float(alpha_max), flags=flags,

@@ -84,6 +84,14 @@ struct cofem_ctx {
   cofem_status (*predictor)(cofem_ctx*, void*, float*, double*) = nullptr;
   void* predictor_user = nullptr;
   bool has_solution = false;
+  // spectral start (COFEM_FLAG_SPECTRAL_START): |h_hat|^2, twiddles, the
+  // transform workspace; alpha is known to be uniform (= alpha_a0) from
+  // cofem_init / cofem_restart until the first M-step or cofem_set_alpha
+  float* spec_g = nullptr;
+  float2* spec_tw = nullptr;
+  float2* spec_z = nullptr;
+  bool alpha_uniform = false;
+  double alpha_a0 = 1.0;
   hipStream_t stream = nullptr;
   int device = 0;
   DenseDims dd{};
@@ -409,6 +417,12 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
     COFEM_TRY(alloc(c, &reds[i]->colsum, (size_t)ncols * nvs[i]));
     COFEM_TRY(alloc(c, &reds[i]->cnt_cols, 1));
   }
+  const bool spectral = (c->flags & COFEM_FLAG_SPECTRAL_START) != 0;
+  if (spectral) {
+    COFEM_TRY(alloc(c, &c->spec_g, (size_t)cd.D));
+    COFEM_TRY(alloc(c, &c->spec_tw, (size_t)conv_spectral_twiddles(cd)));
+    COFEM_TRY(alloc(c, &c->spec_z, (size_t)(conv_spectral_pairs(cd) * cd.D)));
+  }
   if (c->sizing) return COFEM_OK;
   COFEM_HIP(c, hipMemcpyAsync(c->taps, p.taps, sizeof(float) * p.kh * p.kw, hipMemcpyDeviceToDevice,
                               c->stream));
@@ -416,6 +430,9 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
     COFEM_HIP(c, conv_b0(cd, c->taps, p.y + (size_t)t * cd.D, c->beta, c->b0 + (size_t)t * cd.ldD, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, cd.ldD, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha_prev, 1.0f, cd.ldD, c->stream));
+  c->alpha_uniform = true;
+  c->alpha_a0 = 1.0;
+  if (spectral) COFEM_HIP(c, conv_spectral_tables(cd, c->taps, c->spec_g, c->spec_tw, c->stream));
   return COFEM_OK;
 }
 
@@ -799,6 +816,11 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
     return *why = "warm starts are built for single problems (not the batched form)", COFEM_ERR_UNSUPPORTED;
   if ((q->flags & COFEM_FLAG_WARM_PREV) && p->kind == COFEM_DENSE && q->stop_rule == COFEM_STOP_PER_COLUMN)
     return *why = "the dense warm start runs the joint Frobenius stop rule", COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & COFEM_FLAG_SPECTRAL_START) &&
+      (n != 1 || (q->flags & COFEM_FLAG_BATCHED) || p->kind != COFEM_CONV2D_CIRC))
+    return *why = "the spectral start is built for single convolution problems", COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & COFEM_FLAG_SPECTRAL_START) && !conv_spectral_ok(p->H, p->W))
+    return *why = "the spectral start needs power-of-two H and W, each at most 4096", COFEM_ERR_UNSUPPORTED;
   for (int32_t i = 0; i < n; ++i)
     if (p[i].n_tasks > 1 && (n != 1 || (q->flags & COFEM_FLAG_BATCHED) || p[i].phi_dtype != COFEM_F32))
       return *why = "several tasks (n_tasks > 1) are built for single problems (not the batched form)",
@@ -916,10 +938,11 @@ cofem_status collect_times(cofem_ctx* c, int iters) {
 
 // Conv solves that start from a block X0 and/or use a diagonal preconditioner:
 // COFEM_FLAG_WARM_PREV (X0 = [max(s_prev, 0) (.) p_k | mu_prev]),
+// COFEM_FLAG_SPECTRAL_START (X0 = A^-1 B by 2D DFTs while alpha is uniform),
 // COFEM_FLAG_JACOBI (M^-1 = 1/diag(A)), or a predictor set by the caller.
 bool conv_pcg(const cofem_ctx* c) {
   return (c->kind == COFEM_CONV2D_CIRC || c->kind == COFEM_DCT_MASK) &&
-         (c->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI) || c->predictor);
+         (c->flags & (COFEM_FLAG_WARM_PREV | COFEM_FLAG_JACOBI | COFEM_FLAG_SPECTRAL_START) || c->predictor);
 }
 
 // Q = A X into the scratch blocks (no reduction, no stop check).
@@ -949,7 +972,7 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
   const ConvDims& cd = c->cd;
   const float* d0 = nullptr;
   const double* mu0 = nullptr;
-  bool start = false;
+  bool start = false, spectral = false;
   c->active_minv = nullptr;
   if (c->predictor && c->has_solution) {
     // learned: X0 = [d (.) p_k | mu_hat] from the network, M^-1 = Jacobi.
@@ -968,7 +991,13 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
       COFEM_TRY(pcg_jacobi(c));
       c->active_minv = c->minv;
     }
-    if ((c->flags & COFEM_FLAG_WARM_PREV) && c->has_solution) {
+    if ((c->flags & COFEM_FLAG_SPECTRAL_START) && c->alpha_uniform && c->kind == COFEM_CONV2D_CIRC) {
+      // A = beta Phi^T Phi + a0 I is block-circulant: X0 = A^-1 B by 2D DFTs
+      COFEM_HIP(c, conv_spectral_start(cd, c->seed, t, c->b0, c->spec_g, c->spec_tw, c->beta, c->alpha_a0,
+                                       c->spec_z, c->vX, c->xm, c->stream));
+      spectral = true;
+      start = true;
+    } else if ((c->flags & COFEM_FLAG_WARM_PREV) && c->has_solution) {
       d0 = c->sdiag;  // clamped at zero by conv_start
       start = true;
     }
@@ -977,7 +1006,7 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
   // column): conv sizes red_pass for it, the DCT dictionary red_upd
   const ConvReduce& rs = c->kind == COFEM_DCT_MASK ? c->red_upd : c->red_pass;
   if (start) {
-    COFEM_HIP(c, conv_start(cd, c->seed, t, d0, mu0, c->vX, c->xm, c->stream));
+    if (!spectral) COFEM_HIP(c, conv_start(cd, c->seed, t, d0, mu0, c->vX, c->xm, c->stream));
     COFEM_TRY(apply_to_scratch(c, c->vX, c->xm));
     COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, c->vQs, c->Qsm, c->vX, c->vR, c->vP, c->xm,
                                c->rm, c->pm, rs, c->st, c->stream));
@@ -1379,6 +1408,7 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
                             c->red_upd, c->st, c->stream));
   }
+  c->alpha_uniform = false;
   COFEM_TRY(mark(c, -1, 0));
   COFEM_TRY(iter_end(c));
   COFEM_TRY(read_state(c));
@@ -1547,6 +1577,8 @@ cofem_status cofem_em_step_static(const cofem_problem* problem, const cofem_para
     return fail(nullptr, COFEM_ERR_UNSUPPORTED, "the allocation-free step runs COFEM_PREC_FP32 or COFEM_PREC_FP64");
   if (params->flags & COFEM_FLAG_WARM_PREV)
     return fail(nullptr, COFEM_ERR_UNSUPPORTED, "a single stateless step has no previous E-step to start from");
+  if (params->flags & COFEM_FLAG_SPECTRAL_START)
+    return fail(nullptr, COFEM_ERR_UNSUPPORTED, "the allocation-free step takes any alpha: no spectral start");
   if (!alpha_in) return fail(nullptr, COFEM_ERR_INVALID_ARG, "alpha_in is null");
   if (t < 0 || t >= (1 << 16)) return fail(nullptr, COFEM_ERR_INVALID_ARG, "t must be in [0, 65535]");
   // the layout this problem needs, counted without touching the device
@@ -1664,6 +1696,7 @@ cofem_status cofem_set_alpha(cofem_ctx* ctx, int32_t problem, const float* alpha
   if (!alpha) return fail(ctx, COFEM_ERR_INVALID_ARG, "alpha is null");
   float* dst = ctx->batch ? ctx->batch->probs[problem].alpha : ctx->alpha;
   const int64_t D = ctx->batch ? ctx->batch->probs[problem].D : ctx->D;
+  ctx->alpha_uniform = false;  // not inspected: the spectral start waits for cofem_restart
   if (ctx->kind == COFEM_DCT_MASK)
     COFEM_HIP(ctx, perm_in_f32(ctx->cd, alpha, dst, ctx->stream));
   else
@@ -1716,6 +1749,8 @@ cofem_status cofem_restart(cofem_ctx* ctx) {
   }
   const int64_t n = ctx->kind == COFEM_DENSE ? ctx->dd.Dp : ctx->cd.ldD;
   COFEM_HIP(ctx, fill_f32(ctx->alpha, 1.0f, n, ctx->stream));
+  ctx->alpha_uniform = true;
+  ctx->alpha_a0 = 1.0;
   if (ctx->alpha_prev) COFEM_HIP(ctx, fill_f32(ctx->alpha_prev, 1.0f, n, ctx->stream));
   COFEM_HIP(ctx, fill_f32(ctx->mu, 0.0f, n, ctx->stream));
   COFEM_HIP(ctx, fill_f32(ctx->sdiag, 0.0f, n, ctx->stream));

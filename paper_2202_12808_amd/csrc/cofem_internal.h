@@ -705,6 +705,19 @@ hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, c
 hipError_t conv_probes_out(const ConvDims& cd, const void* X, float* out, hipStream_t s);
 hipError_t conv_probes_in(const ConvDims& cd, const float* in, void* X, hipStream_t s);
 
+// Spectral start (kernels_spectral.hip): with a uniform alpha = a0, the start
+// block X0 = A^-1 [p_1 .. p_K | b0_1 .. b0_T] by 2D DFTs, for power-of-two H
+// and W up to kSpecMaxSide.  Tables: g (D floats, |h_hat|^2) and tw
+// (conv_spectral_twiddles float2); workspace Z: conv_spectral_pairs * D float2.
+constexpr int kSpecMaxSide = 4096;
+bool conv_spectral_ok(int H, int W);
+int64_t conv_spectral_pairs(const ConvDims& cd);
+int64_t conv_spectral_twiddles(const ConvDims& cd);
+hipError_t conv_spectral_tables(const ConvDims& cd, const float* taps, float* g, float2* tw, hipStream_t s);
+hipError_t conv_spectral_start(const ConvDims& cd, uint64_t seed, int t, const double* b0, const float* g,
+                               const float2* tw, double beta, double a0, float2* Z, void* X, double* xm,
+                               hipStream_t s);
+
 hipError_t probe_signs_colmajor(uint64_t seed, int t, int K, int64_t D, float* out, hipStream_t s);
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
 

@@ -152,6 +152,30 @@ def test_workspace_size_without_device(lib):
         C.COFEM_ERR_INVALID_ARG
 
 
+def test_spectral_start_sizing_and_rejections(lib):
+    # the spectral start adds its transform workspace (ceil((K + 1)/2) complex
+    # float32 images), the |h_hat|^2 table and the twiddles; it needs a single
+    # convolution problem with power-of-two sides up to 4096
+    conv = dict(kind=C.COFEM_CONV2D_CIRC, H=64, W=128, N=64 * 128, D=64 * 128, kh=7, kw=7, taps=3, phi=None)
+    st0, n0 = _ws(lib, _problem(**conv), _params(K=7))
+    st1, n1 = _ws(lib, _problem(**conv), _params(K=7, flags=C.COFEM_FLAG_SPECTRAL_START))
+    D = 64 * 128
+    assert st0 == st1 == C.COFEM_OK
+    assert n1 - n0 >= 4 * D * 8 + D * 4 + 64 * 8
+    assert n1 - n0 <= 4 * D * 8 + D * 4 + 64 * 8 + 3 * 256
+    flag = _params(flags=C.COFEM_FLAG_SPECTRAL_START)
+    for bad in (dict(conv, H=48, N=48 * 128, D=48 * 128), dict(conv, W=8192, N=64 * 8192, D=64 * 8192)):
+        assert _ws(lib, _problem(**bad), flag)[0] == C.COFEM_ERR_UNSUPPORTED
+        assert b"power-of-two" in lib.cofem_last_error(None)
+    assert _ws(lib, _problem(), flag)[0] == C.COFEM_ERR_UNSUPPORTED
+    dct = _problem(kind=C.COFEM_DCT_MASK, N=8, D=16, phi=None, ld_phi=0, rows=4)
+    assert _ws(lib, dct, flag)[0] == C.COFEM_ERR_UNSUPPORTED
+    # the allocation-free step takes any alpha: it has no spectral start
+    st = lib.cofem_em_step_static(ctypes.byref(_problem(**conv)), ctypes.byref(flag), 5, 1, None, None, None,
+                                  None, None)
+    assert st == C.COFEM_ERR_UNSUPPORTED
+
+
 def test_null_context_calls_fail_cleanly(lib):
     assert lib.cofem_em_step(None, 1, None) == C.COFEM_ERR_INVALID_ARG
     assert lib.cofem_em_run(None, 1, 0.0, None, None) == C.COFEM_ERR_INVALID_ARG
