@@ -468,7 +468,8 @@ class IRInfo:
 
 
 def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
-             max_iter: int, max_sweeps: int, fixed_inner=None, X0: Optional[np.ndarray] = None):
+             max_iter: int, max_sweeps: int, fixed_inner=None, X0: Optional[np.ndarray] = None,
+             minv: Optional[np.ndarray] = None):
     """Iterative refinement: X = X0 (or 0), R = B - A X; while ||R||_F/||B||_F >= tol (and
     fewer than ``max_iter`` inner iterations and ``max_sweeps`` sweeps so far,
     and fewer than IR_STALL sweeps in a row failed to halve the best ratio --
@@ -476,7 +477,8 @@ def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
     stalls its evaluation has reached its rounding floor):
     D = CG(apply_A_inner, R, tol_in, remaining budget); X += D; R = B - A X.
     With ``fixed_inner`` (a list of counts) exactly those sweeps run, each for
-    exactly its count."""
+    exactly its count.  ``minv`` (not in the paper): the inner solves are
+    ``pcg_solve`` from zero with M^-1 = diag(minv) and the same stop test."""
     B = np.asarray(B, dtype=np.float64)
     if X0 is None:
         X = np.zeros_like(B)
@@ -504,7 +506,10 @@ def ir_solve(apply_A, apply_A_inner, B: np.ndarray, tol: float, tol_in: float,
               or stall >= IR_STALL):
             break
         n = None if fixed_inner is None else int(fixed_inner[len(sweeps)])
-        Dx, info = cg_solve(apply_A_inner, R, tol_in, max_iter - total, fixed_iters=n)
+        if minv is None:
+            Dx, info = cg_solve(apply_A_inner, R, tol_in, max_iter - total, fixed_iters=n)
+        else:
+            Dx, info = pcg_solve(apply_A_inner, R, tol_in, max_iter - total, minv=minv, fixed_iters=n)
         X += Dx
         total += info.iters
         sweeps.append(info.iters)
@@ -564,12 +569,13 @@ def cofem_estep(op, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
 
 def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray, K: int,
                    tol: float, tol_in: float, max_iter: int, max_sweeps: int, seed: int, t: int,
-                   fixed_inner=None, mu0=None, d0=None):
+                   fixed_inner=None, mu0=None, d0=None, minv=None):
     """The E-step of Algorithm 1 with the solve done by ``ir_solve``: outer
     residual with ``op`` (the problem's Phi), inner corrections with
     ``op_inner`` (a lower-precision Phi).  With mu0 / d0 the refinement starts
     from X0 = [d0 (.) p_1 .. d0 (.) p_K | mu0] (the warm start of
-    ``cofem_estep_pcg``; None entries zero).  Returns (EStepResult, IRInfo)."""
+    ``cofem_estep_pcg``; None entries zero).  ``minv``: the inner solves'
+    diagonal preconditioner (``ir_solve``).  Returns (EStepResult, IRInfo)."""
     D = op.D
     P = rademacher_probes(seed, t, K, D)
     B = np.concatenate([P, np.asarray(b0, np.float64)[:, None]], axis=1)
@@ -581,7 +587,7 @@ def cofem_estep_ir(op, op_inner, b0: np.ndarray, beta: float, alpha: np.ndarray,
         if mu0 is not None:
             X0[:, K] = np.asarray(mu0, np.float64)
     X, info = ir_solve(make_apply_A(op, beta, alpha), make_apply_A(op_inner, beta, alpha), B, tol,
-                       tol_in, max_iter, max_sweeps, fixed_inner, X0)
+                       tol_in, max_iter, max_sweeps, fixed_inner, X0, minv=minv)
     mu = X[:, K].copy()
     s = diag_estimate(P, X[:, :K])
     cg = CGInfo(info.iters, info.converged, info.rel_resid, info.history)

@@ -159,3 +159,48 @@ def test_estep_ir_warm_start_matches_pcg_warm_start():
     assert info.converged
     assert np.allclose(e_ir.X, e_pcg.X, rtol=1e-8, atol=1e-10)
 
+
+
+def test_ir_with_jacobi_inner_solves():
+    # the preconditioned inner solves: with the exact inner operator one sweep
+    # is one PCG solve from zero; with the bf16 inner operator the refinement
+    # reaches the true tolerance and the Cholesky solution, in fewer inner
+    # iterations than the unpreconditioned refinement on this badly scaled
+    # diagonal (alpha spread over three orders of magnitude)
+    phi, alpha, beta, A, B = _spd_problem(seed=3)
+    alpha = np.exp(np.random.default_rng(4).uniform(-2.0, 5.0, alpha.size))
+    A = beta * phi.T @ phi + np.diag(alpha)
+    op, opb = O.DenseOperator(phi), O.DenseOperator(_bf16(phi))
+    minv = 1.0 / (beta * op.column_norms_sq() + alpha)
+    apply_A = make_apply_A(op, beta, alpha)
+    X, info = ir_solve(apply_A, apply_A, B, tol=1e-6, tol_in=1e-9, max_iter=400, max_sweeps=10, minv=minv)
+    Xp, pi = O.pcg_solve(apply_A, B, 1e-9, 400, minv=minv)
+    assert info.sweeps == [pi.iters]
+    np.testing.assert_allclose(X, Xp, rtol=0, atol=1e-12 * np.abs(Xp).max())
+    tol = 1e-9
+    Xj, ij = ir_solve(apply_A, make_apply_A(opb, beta, alpha), B, tol=tol, tol_in=1e-2, max_iter=4000,
+                      max_sweeps=50, minv=minv)
+    Xn, inn = ir_solve(apply_A, make_apply_A(opb, beta, alpha), B, tol=tol, tol_in=1e-2, max_iter=4000,
+                       max_sweeps=50)
+    assert ij.converged and O.true_relative_residual(apply_A, Xj, B) < tol
+    Xe = np.linalg.solve(A, B)
+    assert np.linalg.norm(Xj - Xe) / np.linalg.norm(Xe) < np.linalg.cond(A) * tol
+    print("inner iterations with and without Jacobi:", ij.iters, inn.iters)
+    assert ij.iters < inn.iters
+
+
+def test_estep_ir_jacobi_matches_pcg():
+    # E-step with the refinement's preconditioned inner solves and the
+    # problem's own Phi inside: the preconditioned E-step's X
+    rng = np.random.default_rng(23)
+    N, D, K = 24, 40, 4
+    phi = rng.standard_normal((N, D)) / np.sqrt(N)
+    op = O.DenseOperator(phi)
+    y = rng.standard_normal(N)
+    alpha = rng.uniform(0.5, 40.0, D)
+    b0 = 10.0 * op.apply_t(y)
+    minv = 1.0 / (10.0 * op.column_norms_sq() + alpha)
+    e_ir, info = O.cofem_estep_ir(op, op, b0, 10.0, alpha, K, 1e-11, 1e-3, 400, 20, seed=5, t=3, minv=minv)
+    e_pcg = O.cofem_estep_pcg(op, b0, 10.0, alpha, K, 1e-11, 400, seed=5, t=3, minv=minv)
+    assert info.converged
+    assert np.allclose(e_ir.X, e_pcg.X, rtol=1e-8, atol=1e-10)
