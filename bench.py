@@ -91,8 +91,10 @@ KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "u
                 "dense_bf16_ir": {"pass1": "k_dense16_pass1", "pass2": "k_dense16_pass2", "update": "k_dense_update"},
                 "conv": {"pass1": "k_conv_fused"}}
 FORMS = {"fp32": "fp32 probes + fp64 mean column",
-         "fp32_warm": "fp32 CG started from the previous mean and diagonal estimate (fp64 mean column)",
-         "bf16_ir": "bf16 Phi inner CG + float32-Phi iterative refinement (fp64 mean column), started from the "
+         "fp32_warm": "fp32 Jacobi-preconditioned CG started from the previous mean and diagonal estimate (fp64 "
+                      "mean column)",
+         "bf16_ir": "bf16 Phi inner Jacobi-preconditioned CG + float32-Phi iterative refinement (fp64 mean column), "
+                    "started from the "
                     "previous mean and diagonal estimate",
          "control": "fp32 CG started from the previous mean and diagonal estimate, Jacobi-preconditioned",
          "learned": "fp32 CG started from a learned prediction, Jacobi-preconditioned"}
@@ -836,8 +838,9 @@ def run_dense(args, emit=True):
     def make(f):
         prec = "bf16_ir" if f == "bf16_ir" else "fp32"
         warm = (f == "bf16_ir" and not args.no_warm) or f == "fp32_warm"
+        # the warm-started forms also take the Jacobi diagonal; plain fp32 stays plain CG
         return CoFEM.dense(phi, y, p.beta, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, precision=prec,
-                           ir_inner_tol=args.ir_inner_tol, warm_start=warm)
+                           ir_inner_tol=args.ir_inner_tol, warm_start=warm, jacobi=warm and not args.no_jacobi)
 
     def timed(f, kernel_timing):
         g = make(f)
@@ -994,6 +997,8 @@ def main():
                     help="time only the headline form")
     ap.add_argument("--no-secondary", action="store_true",
                     help="conv workloads: skip the dense 4096 x 16384 summary carried in the same line")
+    ap.add_argument("--no-jacobi", action="store_true",
+                    help="dense workloads: run the warm-started forms without the Jacobi diagonal")
     ap.add_argument("--no-spectral", action="store_true",
                     help="conv workloads: start the control and learned forms' first E-step from zero instead "
                          "of the 2D-DFT solve")

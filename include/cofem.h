@@ -97,9 +97,14 @@ enum {
    * estimate and mean (not in the paper: a warm start).  The mixed-precision
    * form starts its refinement there: the first outer residual is B - A X0. */
   COFEM_FLAG_WARM_PREV = 8,
-  /* Convolution and DCT dictionaries: diagonal (Jacobi) preconditioner
-   * M^-1 = 1 / (beta ||h||^2 + alpha), the inverse diagonal of A.  The stop
-   * test stays the unpreconditioned one of Sec. 3.2. */
+  /* Single problems (not the batched form): diagonal (Jacobi)
+   * preconditioner M^-1 = 1 / diag(A) = 1 / (beta ||Phi e_d||^2 + alpha_d),
+   * recomputed from alpha at every E-step (conv: ||h||^2 for every d; DCT:
+   * the column norms of the masked inverse DCT; dense: the column norms of
+   * the caller's Phi, summed in float64 once at cofem_init).  Preconditioned
+   * CG; the stop test stays the unpreconditioned one of Sec. 3.2.  Under
+   * COFEM_PREC_BF16_IR it preconditions the inner solves of the refinement
+   * (the outer residual is unchanged). */
   COFEM_FLAG_JACOBI = 16,
   /* Convolution dictionaries (single problems, H and W powers of two, each at
    * most 4096): while alpha is uniform -- the first E-step after cofem_init

@@ -76,6 +76,7 @@ struct cofem_ctx {
   std::vector<int32_t> sweeps;
   // warm-started / preconditioned / learned forms (conv): M^-1 and the start
   float* minv = nullptr;
+  float* dense_cn = nullptr;  // dense Jacobi: ||Phi e_d||^2 (Dp floats)
   float* d0 = nullptr;
   double* mu0 = nullptr;
   const float* active_minv = nullptr;
@@ -340,8 +341,14 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   COFEM_TRY(alloc(c, &c->wm, (size_t)dd.Np * dd.nt));
   const int64_t nupd = dense_update_blocks(dd);
   const int ncols = kDenseKP + dd.nt;
-  COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, ncols));
-  COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, ncols));
+  const bool jacobi = (c->flags & COFEM_FLAG_JACOBI) != 0;
+  // the preconditioned start reduces three values per column, its update two
+  COFEM_TRY(alloc_tree(c, &c->parts_init, &c->cnts_init, nupd, jacobi ? 3 * ncols : ncols));
+  COFEM_TRY(alloc_tree(c, &c->parts_upd, &c->cnts_upd, nupd, jacobi ? 2 * ncols : ncols));
+  if (jacobi) {
+    COFEM_TRY(alloc(c, &c->dense_cn, dd.Dp));
+    COFEM_TRY(alloc(c, &c->minv, dd.Dp));
+  }
   COFEM_TRY(alloc_tree(c, &c->parts_pass, &c->cnts_pass, dd.Dp / 32, 3 * ncols));
   COFEM_TRY(alloc(c, &c->Wpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np * kDenseKP));
   COFEM_TRY(alloc(c, &c->wmpart, (size_t)(s1 > 1 ? s1 : 0) * dd.Np * dd.nt));
@@ -365,7 +372,17 @@ cofem_status init_dense(cofem_ctx* c, const cofem_problem& p) {
   for (int t = 0; t < dd.nt; ++t)
     COFEM_HIP(c, dense_b0(p.phi, kDictF32, p.ld_phi, p.y + (size_t)t * p.N, c->beta, dd, c->b0 + (size_t)t * dd.Dp,
                           c->stream));
+  if (jacobi) COFEM_HIP(c, dense_colnorms(p.phi, kDictF32, p.ld_phi, dd, c->dense_cn, c->stream));
   COFEM_HIP(c, fill_f32(c->alpha, 1.0f, dd.Dp, c->stream));
+  return COFEM_OK;
+}
+
+// Dense Jacobi diagonal of this E-step's A (COFEM_FLAG_JACOBI), else none.
+cofem_status dense_set_minv(cofem_ctx* c) {
+  c->active_minv = nullptr;
+  if (!c->dense_cn) return COFEM_OK;
+  COFEM_HIP(c, dense_jacobi(c->dd, c->dense_cn, c->beta, c->alpha, c->minv, c->stream));
+  c->active_minv = c->minv;
   return COFEM_OK;
 }
 
@@ -810,8 +827,9 @@ cofem_status validate(const cofem_problem* p, int32_t n, const cofem_params* q, 
   if (q->stop_rule == COFEM_STOP_PER_COLUMN && q->precision == COFEM_PREC_BF16_IR)
     return *why = "COFEM_STOP_PER_COLUMN is not built for the refinement of COFEM_PREC_BF16_IR",
            COFEM_ERR_UNSUPPORTED;
-  if ((q->flags & COFEM_FLAG_JACOBI) && (n != 1 || (p->kind != COFEM_CONV2D_CIRC && p->kind != COFEM_DCT_MASK)))
-    return *why = "the Jacobi preconditioner is built for convolution and DCT dictionaries", COFEM_ERR_UNSUPPORTED;
+  if ((q->flags & COFEM_FLAG_JACOBI) && (n != 1 || (q->flags & COFEM_FLAG_BATCHED) || p->phi_dtype != COFEM_F32))
+    return *why = "the Jacobi preconditioner is built for single problems (not the batched form)",
+           COFEM_ERR_UNSUPPORTED;
   if ((q->flags & COFEM_FLAG_WARM_PREV) && (n != 1 || (q->flags & COFEM_FLAG_BATCHED) || p->phi_dtype != COFEM_F32))
     return *why = "warm starts are built for single problems (not the batched form)", COFEM_ERR_UNSUPPORTED;
   if ((q->flags & COFEM_FLAG_WARM_PREV) && p->kind == COFEM_DENSE && q->stop_rule == COFEM_STOP_PER_COLUMN)
@@ -1029,10 +1047,10 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dense16_pass2(c->dd, c->phiB16, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
                                  c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
-                                 c->cnt_split2, c->st, 0, c->stream));
+                                 c->cnt_split2, c->st, 0, c->stream, c->active_minv));
       COFEM_TRY(cg_mark(c, samp, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
-                                c->cnts_upd, c->st, c->stream));
+                                c->cnts_upd, c->st, c->stream, c->active_minv));
     } else if (c->kind == COFEM_DENSE) {
       COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS1, it));
       COFEM_HIP(c, dense_pass1(c->dd, c->phiA, c->P, c->pm, c->Wpart, c->wmpart, c->W, c->wm,
@@ -1040,10 +1058,10 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS2, it));
       COFEM_HIP(c, dense_pass2(c->dd, c->phiB, c->W, c->wm, c->P, c->pm, c->R, c->rm, c->alpha, c->beta,
                                c->Qpart, c->qmpart, c->Q, c->qm, c->parts_pass, c->cnts_pass,
-                               c->cnt_split2, c->st, 0, c->stream));
+                               c->cnt_split2, c->st, 0, c->stream, c->active_minv));
       COFEM_TRY(cg_mark(c, samp, COFEM_KT_UPDATE, it));
       COFEM_HIP(c, dense_update(c->dd, c->X, c->R, c->P, c->Q, c->xm, c->rm, c->pm, c->qm, c->parts_upd,
-                                c->cnts_upd, c->st, c->stream));
+                                c->cnts_upd, c->st, c->stream, c->active_minv));
     } else if (c->kind == COFEM_DCT_MASK) {
       // DCT: the first iteration of a solve is the operator on the start
       // direction; each later one folds the previous update into its first
@@ -1150,8 +1168,9 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
   c->kev_used = 0;
   c->sweeps.clear();
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
+  COFEM_TRY(dense_set_minv(c));
   COFEM_HIP(c, dense_init(dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->parts_init,
-                          c->cnts_init, c->st, c->stream));
+                          c->cnts_init, c->st, c->stream, c->active_minv));
   const bool warm = (c->flags & COFEM_FLAG_WARM_PREV) && c->has_solution;
   if (warm) {
     // X0 = [max(s_prev, 0) (.) p_k | mu_prev] (Xt still holds the previous
@@ -1164,7 +1183,7 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
                              c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2, c->st, 1,
                              c->stream));
     COFEM_HIP(c, dense_ir_residual(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->X, c->R, c->P, c->xm, c->rm, c->pm,
-                                   c->parts_upd, c->cnts_upd, c->st, c->U, c->stream));
+                                   c->parts_upd, c->cnts_upd, c->st, c->U, c->stream, c->active_minv));
   } else {
     COFEM_HIP(c, fill_f32(c->Xt, 0.0f, dd.Dp * kDenseKP, c->stream));
     COFEM_HIP(c, hipMemsetAsync(c->xtm, 0, sizeof(double) * dd.Dp, c->stream));
@@ -1219,7 +1238,7 @@ cofem_status em_iteration_ir(cofem_ctx* c, cofem_iter_stats* out) {
                              c->qmpart, c->Qs, c->Qsm, c->parts_pass, c->cnts_pass, c->cnt_split2, c->st, 1,
                              c->stream));
     COFEM_HIP(c, dense_ir_residual(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->X, c->R, c->P, c->xm, c->rm, c->pm,
-                                   c->parts_upd, c->cnts_upd, c->st, c->U - total, c->stream));
+                                   c->parts_upd, c->cnts_upd, c->st, c->U - total, c->stream, c->active_minv));
     COFEM_TRY(mark(c, -1, 0));
     COFEM_TRY(read_state(c));
     COFEM_TRY(collect_times(c, 0));
@@ -1266,8 +1285,9 @@ cofem_status em_iteration_dense_warm(cofem_ctx* c, cofem_iter_stats* out) {
   c->cg_enq = 0;
   c->kev_used = 0;
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
+  COFEM_TRY(dense_set_minv(c));
   COFEM_HIP(c, dense_init(dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm, c->parts_init,
-                          c->cnts_init, c->st, c->stream));
+                          c->cnts_init, c->st, c->stream, c->active_minv));
   const bool warm = c->has_solution;
   double tol_eff = c->tol;
   if (warm) {
@@ -1279,7 +1299,7 @@ cofem_status em_iteration_dense_warm(cofem_ctx* c, cofem_iter_stats* out) {
                              c->stream));
     COFEM_HIP(c, dense_ir_residual(dd, c->seed, t, c->K, c->b0, c->Qs, c->Qsm, c->X, c->R, c->P, c->xm, c->rm, c->pm,
                                    c->parts_upd, c->cnts_upd, c->st, c->fixed_iters > 0 ? c->fixed_iters : c->U,
-                                   c->stream));
+                                   c->stream, c->active_minv));
     COFEM_TRY(read_state(c));
     if (c->host_st->numeric_error)
       return fail(c, COFEM_ERR_NUMERIC, "non-finite warm-start residual at EM iteration " + std::to_string(t));
@@ -1364,9 +1384,11 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   c->cg_enq = 0;
   c->kev_used = 0;
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
-  if (c->kind == COFEM_DENSE)
+  if (c->kind == COFEM_DENSE) {
+    COFEM_TRY(dense_set_minv(c));
     COFEM_HIP(c, dense_init(c->dd, c->seed, t, c->K, c->b0, c->X, c->R, c->P, c->xm, c->rm, c->pm,
-                            c->parts_init, c->cnts_init, c->st, c->stream));
+                            c->parts_init, c->cnts_init, c->st, c->stream, c->active_minv));
+  }
   else if (conv_pcg(c)) {
     COFEM_TRY(conv_start_pcg(c, t));
   } else {

@@ -348,6 +348,33 @@ __device__ __forceinline__ void finish_update(CgScalars* st, const double* new_r
   finish_update(st, new_rho, load_cg_ctl(st));
 }
 
+// Finishes a preconditioned CG update (z = M^-1 r): v holds, per column (nc
+// values each), rho' = r^T z and r^T r.  rho <- rho' (the next step length's
+// numerator), the iteration count, and the stop test on the unpreconditioned
+// residual, sqrt(sum r^T r) / ||B||_F (Sec. 3.2), or the per-column rule on
+// r^T r.
+__device__ __forceinline__ void finish_update_pcg(CgScalars* st, const double* v, int nc, const CgCtl& k) {
+  if ((int)threadIdx.x < nc) st->rho[threadIdx.x] = v[threadIdx.x];
+  int mine_done;
+  const bool all = per_column_finish(st, k, (int)threadIdx.x < nc ? v[nc + threadIdx.x] : 0.0, &mine_done);
+  if (threadIdx.x == 0) {
+    const int it = k.iter + 1;
+    double rr = 0.0, rz = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      rz += v[c];
+      rr += v[nc + c];
+    }
+    const bool finite = isfinite(rr) && isfinite(rz);
+    if (!finite) st->numeric_error = 1;
+    const double ratio = k.nB > 0.0 ? sqrt(rr) / k.nB : 0.0;
+    st->ratio = ratio;
+    st->iter = it;
+    st->all_done = all ? 1 : 0;
+    const bool met = k.per_col ? all : (!k.fixed && ratio < k.tol);
+    st->stop = (it >= k.limit) || met || !finite;
+  }
+}
+
 // Finishes a step-length computation from the three dot products of the
 // operator pass (gam = p^T q, del = r^T q, eta = q^T q, each kp+1 entries in
 // shared memory, laid out gam | del | eta):
@@ -567,6 +594,36 @@ __device__ __forceinline__ void finish_ir_residual(CgScalars* st, const double* 
   }
 }
 
+// The preconditioned form of finish_ir_residual: v holds, per column (nc
+// values each), r^T z and r^T r of the new outer residual R and Z = M^-1 R.
+// rho <- r^T z; the reference norm and the true ratio come from r^T r.
+__device__ __forceinline__ void finish_ir_residual_pcg(CgScalars* st, const double* v, int limit) {
+  const int nc = st->kp + st->nt;
+  if ((int)threadIdx.x < nc) {
+    st->rho[threadIdx.x] = v[threadIdx.x];
+    st->true_res[threadIdx.x] = v[nc + threadIdx.x];
+    st->a[threadIdx.x] = 0.0;
+    st->b[threadIdx.x] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    const double nB0 = st->nB0;
+    double rr = 0.0, rz = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      rz += v[c];
+      rr += v[nc + c];
+    }
+    const bool finite = isfinite(rr) && isfinite(rz);
+    const double nr = sqrt(rr);
+    st->nB = nr;
+    st->true_ratio = nB0 > 0.0 ? nr / nB0 : 0.0;
+    st->ratio = rr > 0.0 ? 1.0 : 0.0;
+    st->iter = 0;
+    st->limit = limit;
+    if (!finite) st->numeric_error = 1;
+    st->stop = (rr == 0.0) || (limit <= 0) || !finite;
+  }
+}
+
 // ------------------------------------------------------------ host launchers
 // Dense problem geometry.  Np and Dp are N and D padded to multiples of 64.
 // Probe-column state uses the blocked-4 layout: element (d, c) of a Dp x 32
@@ -589,9 +646,14 @@ hipError_t dense_pack(const float* phi, int64_t ld, const DenseDims& dd, float* 
                       hipStream_t s);
 hipError_t dense_b0(const void* phi, int dict_kind, int64_t ld, const float* y, double beta, const DenseDims& dd,
                     double* b0, hipStream_t s);
+// minv (dense vector kernels and the second passes): the Jacobi diagonal
+// M^-1 (Dp floats, zero in the padding rows), or null for plain CG.  With it
+// the start and the update form z = M^-1 r, p = z + b p, r^T z (the step's
+// numerator) and r^T r (the stop test); the second pass weights its del and
+// eta by M^-1.
 hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
                       float* X, float* R, float* P, double* xm, double* rm, double* pm,
-                      double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s);
+                      double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s, const float* minv = nullptr);
 hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, const double* pm,
                        float* Wpart, double* wmpart, float* W, double* wm, uint32_t* cnts,
                        CgScalars* st, int apply_only, hipStream_t s);
@@ -599,10 +661,16 @@ hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, c
                        const float* P, const double* pm, const float* R, const double* rm,
                        const float* alpha, double beta, float* Qpart, double* qmpart, float* Q,
                        double* qm, double* gpart, uint32_t* counter, uint32_t* split_cnts,
-                       CgScalars* st, int apply_only, hipStream_t s);
+                       CgScalars* st, int apply_only, hipStream_t s, const float* minv = nullptr);
 hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
                         double* xm, double* rm, double* pm, const double* qm, double* parts,
-                        uint32_t* cnts, CgScalars* st, hipStream_t s);
+                        uint32_t* cnts, CgScalars* st, hipStream_t s, const float* minv = nullptr);
+// ||Phi e_d||^2 for d < D (float64 sums over the caller's Phi), zero in the padding
+hipError_t dense_colnorms(const void* phi, int dict_kind, int64_t ld, const DenseDims& dd, float* cn,
+                          hipStream_t s);
+// M^-1 = 1 / (beta ||Phi e_d||^2 + alpha_d) for d < D, zero in the padding
+hipError_t dense_jacobi(const DenseDims& dd, const float* cn, double beta, const float* alpha, float* minv,
+                        hipStream_t s);
 int dense_split(int64_t tiles, int64_t groups, int nt = 1);
 bool dense_split_ok(int64_t groups, int splits, int nt = 1);
 // diagonal estimate and M-step; the update's reduction tree (parts, cnts)
@@ -624,7 +692,8 @@ hipError_t dense16_pass1(const DenseDims& dd, const void* phiA16, const float* P
 hipError_t dense16_pass2(const DenseDims& dd, const void* phiB16, const float* W, const double* wm,
                          const float* P, const double* pm, const float* R, const double* rm, const float* alpha,
                          double beta, float* Qpart, double* qmpart, float* Q, double* qm, double* gpart,
-                         uint32_t* counter, uint32_t* split_cnts, CgScalars* st, int apply_only, hipStream_t s);
+                         uint32_t* counter, uint32_t* split_cnts, CgScalars* st, int apply_only, hipStream_t s,
+                         const float* minv = nullptr);
 // Xt's probe columns <- max(s_prev, 0) (.) p_k (EM iteration t); the mean column is kept
 hipError_t dense_warm_start(const DenseDims& dd, uint64_t seed, int t, int K, const float* sprev, float* Xt,
                             hipStream_t s);
@@ -632,7 +701,8 @@ hipError_t dense_ir_accumulate(const DenseDims& dd, float* Xt, const float* Xi, 
                                hipStream_t s);
 hipError_t dense_ir_residual(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0, const float* Q,
                              const double* qm, float* Xi, float* R, float* P, double* xim, double* rm, double* pm,
-                             double* parts, uint32_t* cnts, CgScalars* st, int limit, hipStream_t s);
+                             double* parts, uint32_t* cnts, CgScalars* st, int limit, hipStream_t s,
+                             const float* minv = nullptr);
 // ||B - Q||^2 per column with B regenerated (probes of EM iteration t, b0) and
 // Q = A X from the operator passes (blocked-4 probe block + float64 column).
 hipError_t dense_true_resid(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,

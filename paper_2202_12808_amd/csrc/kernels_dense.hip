@@ -104,7 +104,9 @@ int dense_update_blocks(const DenseDims& dd) {
 }
 
 // ------------------------------------------------ initial residual R = P = B (Eq. 7)
-// (nt mean columns at stride Dp: task j's b0, x, r, p at + j Dp)
+// (nt mean columns at stride Dp: task j's b0, x, r, p at + j Dp).  With a
+// Jacobi diagonal minv: P = Z = M^-1 R and the sums r^T z, r^T r, b^T b
+// (= r^T r) per column for finish_init_pcg.
 __device__ __forceinline__ void dense_init_body(int64_t blk, int64_t nblk, int64_t D, int64_t Dp, uint64_t seed, int t,
                                                     int K, const double* __restrict__ b0,
                                                     float* __restrict__ X, float* __restrict__ R,
@@ -112,37 +114,54 @@ __device__ __forceinline__ void dense_init_body(int64_t blk, int64_t nblk, int64
                                                     double* __restrict__ rm,
                                                     double* __restrict__ pm,
                                                     double* __restrict__ parts, uint32_t* cnts,
-                                                    CgScalars* st, int nt = 1) {
+                                                    CgScalars* st, int nt = 1, const float* __restrict__ minv = nullptr) {
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
-  double acc = 0.0;
+  double acc = 0.0, accz = 0.0;
   for (int64_t e4 = gtid; e4 < Dp * 8; e4 += gstride) {
     const int64_t d0 = (e4 >> 5) * 4;
-    float v[4];
+    float v[4], z[4];
+    const float4 mv = minv ? *reinterpret_cast<const float4*>(minv + d0) : make_float4(1.f, 1.f, 1.f, 1.f);
+    const float m4[4] = {mv.x, mv.y, mv.z, mv.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       v[i] = (d0 + i < D && c < K) ? probe_sign(seed, (uint32_t)t, (uint32_t)c, (uint64_t)(d0 + i)) : 0.0f;
+      z[i] = m4[i] * v[i];
       acc += (double)v[i] * (double)v[i];
+      accz += (double)v[i] * (double)z[i];
     }
     const float4 r = make_float4(v[0], v[1], v[2], v[3]);
     reinterpret_cast<float4*>(R)[e4] = r;
-    reinterpret_cast<float4*>(P)[e4] = r;
+    reinterpret_cast<float4*>(P)[e4] = make_float4(z[0], z[1], z[2], z[3]);
     reinterpret_cast<float4*>(X)[e4] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
+  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0}, accmz[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
   for (int j = 0; j < nt; ++j)
     for (int64_t d = gtid; d < Dp; d += gstride) {
       const double b = b0[j * Dp + d];
+      const double z = minv ? (double)minv[d] * b : b;
       rm[j * Dp + d] = b;
-      pm[j * Dp + d] = b;
+      pm[j * Dp + d] = z;
       xm[j * Dp + d] = 0.0;
       accm[j] += b * b;
+      accmz[j] += b * z;
     }
-  __shared__ double mine[kDenseKP + kMaxDenseTasks], tot[kDenseKP + kMaxDenseTasks];
-  dense_block_sums(acc, accm, nt, mine);
-  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + nt, mine, tot)) return;
-  finish_init(st, tot);
+  constexpr int kN = kDenseKP + kMaxDenseTasks;
+  __shared__ double mine[3 * kN], tot[3 * kN];
+  const int nc = kDenseKP + nt;
+  if (!minv) {
+    dense_block_sums(acc, accm, nt, mine);
+    if (!tree_reduce(parts, cnts, blk, nblk, nc, mine, tot)) return;
+    finish_init(st, tot);
+    return;
+  }
+  dense_block_sums(accz, accmz, nt, mine);
+  dense_block_sums(acc, accm, nt, mine + nc);
+  if ((int)threadIdx.x < nc) mine[2 * nc + threadIdx.x] = mine[nc + threadIdx.x];
+  __syncthreads();
+  if (!tree_reduce(parts, cnts, blk, nblk, 3 * nc, mine, tot)) return;
+  finish_init_pcg(st, tot, nc);
 }
 
 __global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint64_t seed, int t,
@@ -152,15 +171,15 @@ __global__ __launch_bounds__(256) void k_dense_init(int64_t D, int64_t Dp, uint6
                                                     double* __restrict__ rm,
                                                     double* __restrict__ pm,
                                                     double* __restrict__ parts, uint32_t* cnts,
-                                                    CgScalars* st, int nt) {
-  dense_init_body(blockIdx.x, gridDim.x, D, Dp, seed, t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st, nt);
+                                                    CgScalars* st, int nt, const float* __restrict__ minv) {
+  dense_init_body(blockIdx.x, gridDim.x, D, Dp, seed, t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st, nt, minv);
 }
 
 hipError_t dense_init(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0,
                       float* X, float* R, float* P, double* xm, double* rm, double* pm,
-                      double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s) {
+                      double* parts, uint32_t* cnts, CgScalars* st, hipStream_t s, const float* minv) {
   hipLaunchKernelGGL(k_dense_init, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed,
-                     t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st, dd.nt);
+                     t, K, b0, X, R, P, xm, rm, pm, parts, cnts, st, dd.nt, minv);
   return hipGetLastError();
 }
 
@@ -454,7 +473,9 @@ hipError_t dense_pass1(const DenseDims& dd, const float* phiA, const float* P, c
 
 // ------------------------------------------------ pass 2: Q = beta Phi^T W + alpha (.) P
 // The epilogue also forms the per-column dots gam = p^T q, del = r^T q and
-// eta = q^T q; the tree reduction's final workgroup turns them into a_c, b_c.
+// eta = q^T q (del and eta weighted by M^-1 when minv is set, so b_c comes
+// out as the preconditioned r'^T z' / r^T z); the tree reduction's final
+// workgroup turns them into a_c, b_c.
 // NT mean columns: column j of W at wm + j Np, of p, r, q at + j Dp.
 template <int RING, int NT>
 __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
@@ -464,7 +485,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
     const float* __restrict__ alpha, double beta, float* __restrict__ Qpart,
     double* __restrict__ qmpart, float* __restrict__ Q, double* __restrict__ qm,
     double* __restrict__ parts, uint32_t* __restrict__ cnts, uint32_t* __restrict__ split_cnts,
-    CgScalars* __restrict__ st, int apply_only) {
+    CgScalars* __restrict__ st, int apply_only, const float* __restrict__ minv) {
   if (!apply_only && st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   constexpr int nc = kDenseKP + NT;
@@ -505,8 +526,13 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
     if (!apply_only) {
       const float4 r = reinterpret_cast<const float4*>(R)[i4];
       sdots[0][e] = (double)p.x * q.x + (double)p.y * q.y + (double)p.z * q.z + (double)p.w * q.w;
-      sdots[1][e] = (double)r.x * q.x + (double)r.y * q.y + (double)r.z * q.z + (double)r.w * q.w;
-      sdots[2][e] = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
+      float4 mq = q;  // M^-1 q
+      if (minv) {
+        const float4 mv = *reinterpret_cast<const float4*>(minv + dq);
+        mq = make_float4(mv.x * q.x, mv.y * q.y, mv.z * q.z, mv.w * q.w);
+      }
+      sdots[1][e] = (double)r.x * mq.x + (double)r.y * mq.y + (double)r.z * mq.z + (double)r.w * mq.w;
+      sdots[2][e] = (double)q.x * mq.x + (double)q.y * mq.y + (double)q.z * mq.z + (double)q.w * mq.w;
     }
   }
   double gmm[NT], dmm[NT], emm[NT];
@@ -515,14 +541,15 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_dense_pass2(
   if (e < 32) {
     const int64_t d = d0 + e;
     const double a = (double)alpha[d];
+    const double mvd = minv ? (double)minv[d] : 1.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const double p = pm[j * Dp + d];
       const double q = beta * vm[j] + a * p;
       qm[j * Dp + d] = q;
       gmm[j] = p * q;
-      dmm[j] = rm[j * Dp + d] * q;
-      emm[j] = q * q;
+      dmm[j] = rm[j * Dp + d] * (mvd * q);
+      emm[j] = q * (mvd * q);
     }
   }
   if (apply_only) return;
@@ -558,14 +585,14 @@ hipError_t dense_pass2(const DenseDims& dd, const float* phiB, const float* W, c
                        const float* P, const double* pm, const float* R, const double* rm,
                        const float* alpha, double beta, float* Qpart, double* qmpart, float* Q,
                        double* qm, double* gpart, uint32_t* counter, uint32_t* split_cnts,
-                       CgScalars* st, int apply_only, hipStream_t s) {
+                       CgScalars* st, int apply_only, hipStream_t s, const float* minv) {
   const int64_t tiles = dd.Dp / 32, G2 = dd.Np / 8;
   if (!dense_split_ok(G2, dd.S2, dd.nt)) return hipErrorInvalidValue;
   const int64_t gps = (G2 + dd.S2 - 1) / dd.S2;
 #define COFEM_PASS2(RG, NT)                                                                               \
   hipLaunchKernelGGL((k_dense_pass2<RG, NT>), dim3((unsigned)tiles, (unsigned)dd.S2), dim3(64 * kGemmWaves), \
                      0, s, reinterpret_cast<const float4*>(phiB), G2, gps, dd.S2, dd.Np, dd.Dp, W, wm, P, pm, R, \
-                     rm, alpha, beta, Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only)
+                     rm, alpha, beta, Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only, minv)
   if (dd.nt == 1) {
     switch (dd.ring) {
       case 1: COFEM_PASS2(1, 1); break;
@@ -606,6 +633,8 @@ bool dense_split_ok(int64_t groups, int splits, int nt) {
 
 // ------------------------------------------------ CG update
 // x += a p ; r -= a q ; p <- r + b p ; rho' = ||r||^2 and the stop test.
+// With a Jacobi diagonal minv: z = M^-1 r, p <- z + b p, and the sums r^T z
+// (rho') and r^T r (the stop test) per column for finish_update_pcg.
 __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int64_t Dp, float* __restrict__ X,
                                                       float* __restrict__ R, float* __restrict__ P,
                                                       const float* __restrict__ Q,
@@ -614,7 +643,8 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
                                                       double* __restrict__ pm,
                                                       const double* __restrict__ qm,
                                                       double* __restrict__ parts, uint32_t* cnts,
-                                                      CgScalars* st, int nt = 1) {
+                                                      CgScalars* st, int nt = 1,
+                                                      const float* __restrict__ minv = nullptr) {
   const int64_t gtid = (int64_t)blk * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)nblk * blockDim.x;
   const int c = threadIdx.x & 31;
@@ -650,7 +680,7 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
   const float a = (float)st->a[c], b = (float)st->b[c];
   const double am = st->a[kDenseKP], bmm = st->b[kDenseKP];
   if (stop) return;
-  double acc = 0.0;
+  double acc = 0.0, accz = 0.0;
   for (int64_t e4 = gtid; e4 < n4; e4 += 2 * gstride) {
     if (e4 != gtid) load2(e4);
 #pragma unroll
@@ -667,10 +697,16 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
         rv.y = fmaf(-a, qv.y, rv.y);
         rv.z = fmaf(-a, qv.z, rv.z);
         rv.w = fmaf(-a, qv.w, rv.w);
-        pv.x = fmaf(b, pv.x, rv.x);
-        pv.y = fmaf(b, pv.y, rv.y);
-        pv.z = fmaf(b, pv.z, rv.z);
-        pv.w = fmaf(b, pv.w, rv.w);
+        float4 zv = rv;
+        if (minv) {  // e's four coordinates start at (e >> 5) * 4
+          const float4 mv = *reinterpret_cast<const float4*>(minv + (e >> 5) * 4);
+          zv = make_float4(mv.x * rv.x, mv.y * rv.y, mv.z * rv.z, mv.w * rv.w);
+          accz += (double)rv.x * zv.x + (double)rv.y * zv.y + (double)rv.z * zv.z + (double)rv.w * zv.w;
+        }
+        pv.x = fmaf(b, pv.x, zv.x);
+        pv.y = fmaf(b, pv.y, zv.y);
+        pv.z = fmaf(b, pv.z, zv.z);
+        pv.w = fmaf(b, pv.w, zv.w);
         reinterpret_cast<float4*>(X)[e] = xv;
         reinterpret_cast<float4*>(R)[e] = rv;
         reinterpret_cast<float4*>(P)[e] = pv;
@@ -678,7 +714,7 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
       }
     }
   }
-  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
+  double accm[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0}, accmz[kMaxDenseTasks] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t d = gtid; d < Dp; d += gstride) {
     if (d != gtid) {
       m_x = xm[d];
@@ -688,9 +724,11 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
     }
     xm[d] = fma(am, m_p, m_x);
     const double rv = fma(-am, m_q, m_r);
+    const double zv = minv ? (double)minv[d] * rv : rv;
     rm[d] = rv;
-    pm[d] = fma(bmm, m_p, rv);
+    pm[d] = fma(bmm, m_p, zv);
     accm[0] += rv * rv;
+    accmz[0] += rv * zv;
   }
   // further mean columns (tasks sharing alpha)
   for (int j = 1; j < nt; ++j) {
@@ -700,15 +738,26 @@ __device__ __forceinline__ void dense_update_body(int64_t blk, int64_t nblk, int
       const double xv = xm[o + d], rv0 = rm[o + d], pv = pm[o + d], qv = qm[o + d];
       xm[o + d] = fma(aj, pv, xv);
       const double rv = fma(-aj, qv, rv0);
+      const double zv = minv ? (double)minv[d] * rv : rv;
       rm[o + d] = rv;
-      pm[o + d] = fma(bj, pv, rv);
+      pm[o + d] = fma(bj, pv, zv);
       accm[j] += rv * rv;
+      accmz[j] += rv * zv;
     }
   }
-  __shared__ double mine[kDenseKP + kMaxDenseTasks], tot[kDenseKP + kMaxDenseTasks];
-  dense_block_sums(acc, accm, nt, mine);
-  if (!tree_reduce(parts, cnts, blk, nblk, kDenseKP + nt, mine, tot)) return;
-  finish_update(st, tot, ctl);
+  constexpr int kN = kDenseKP + kMaxDenseTasks;
+  __shared__ double mine[2 * kN], tot[2 * kN];
+  const int nc = kDenseKP + nt;
+  if (!minv) {
+    dense_block_sums(acc, accm, nt, mine);
+    if (!tree_reduce(parts, cnts, blk, nblk, nc, mine, tot)) return;
+    finish_update(st, tot, ctl);
+    return;
+  }
+  dense_block_sums(accz, accmz, nt, mine);
+  dense_block_sums(acc, accm, nt, mine + nc);
+  if (!tree_reduce(parts, cnts, blk, nblk, 2 * nc, mine, tot)) return;
+  finish_update_pcg(st, tot, nc, ctl);
 }
 
 __global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restrict__ X,
@@ -719,15 +768,55 @@ __global__ __launch_bounds__(256) void k_dense_update(int64_t Dp, float* __restr
                                                       double* __restrict__ pm,
                                                       const double* __restrict__ qm,
                                                       double* __restrict__ parts, uint32_t* cnts,
-                                                      CgScalars* st, int nt) {
-  dense_update_body(blockIdx.x, gridDim.x, Dp, X, R, P, Q, xm, rm, pm, qm, parts, cnts, st, nt);
+                                                      CgScalars* st, int nt, const float* __restrict__ minv) {
+  dense_update_body(blockIdx.x, gridDim.x, Dp, X, R, P, Q, xm, rm, pm, qm, parts, cnts, st, nt, minv);
 }
 
 hipError_t dense_update(const DenseDims& dd, float* X, float* R, float* P, const float* Q,
                         double* xm, double* rm, double* pm, const double* qm, double* parts,
-                        uint32_t* cnts, CgScalars* st, hipStream_t s) {
+                        uint32_t* cnts, CgScalars* st, hipStream_t s, const float* minv) {
   hipLaunchKernelGGL(k_dense_update, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.Dp, X, R, P,
-                     Q, xm, rm, pm, qm, parts, cnts, st, dd.nt);
+                     Q, xm, rm, pm, qm, parts, cnts, st, dd.nt, minv);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ Jacobi diagonal (Sec. 3.2 solver, not in the paper)
+// cn_d = ||Phi e_d||^2 = sum_n Phi[n][d]^2 (float64 sums; one thread per
+// column d, so a row's entries are read by consecutive threads), zero for the
+// padding columns.
+__global__ void k_dense_colnorm(const void* __restrict__ phi, int kind, int64_t ld, int64_t N, int64_t D, int64_t Dp,
+                                float* __restrict__ cn) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= Dp) return;
+  double acc = 0.0;
+  if (d < D)
+    for (int64_t n = 0; n < N; ++n) {
+      const double v = (double)dict_value(phi, kind, n * ld + d);
+      acc += v * v;
+    }
+  cn[d] = (float)acc;
+}
+
+hipError_t dense_colnorms(const void* phi, int dict_kind, int64_t ld, const DenseDims& dd, float* cn,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_colnorm, dim3((unsigned)((dd.Dp + 255) / 256)), dim3(256), 0, s, phi, dict_kind, ld,
+                     dd.N, dd.D, dd.Dp, cn);
+  return hipGetLastError();
+}
+
+// M^-1 = 1 / diag(A) = 1 / (beta ||Phi e_d||^2 + alpha_d) for d < D; zero in
+// the padding, whose state stays zero.
+__global__ void k_dense_jacobi(int64_t D, int64_t Dp, const float* __restrict__ cn, double beta,
+                               const float* __restrict__ alpha, float* __restrict__ minv) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= Dp) return;
+  minv[d] = d < D ? (float)(1.0 / (beta * (double)cn[d] + (double)alpha[d])) : 0.0f;
+}
+
+hipError_t dense_jacobi(const DenseDims& dd, const float* cn, double beta, const float* alpha, float* minv,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_jacobi, dim3((unsigned)((dd.Dp + 255) / 256)), dim3(256), 0, s, dd.D, dd.Dp, cn, beta,
+                     alpha, minv);
   return hipGetLastError();
 }
 

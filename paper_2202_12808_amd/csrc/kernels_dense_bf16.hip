@@ -342,7 +342,8 @@ __device__ __forceinline__ void dense16_pass2_body(
     const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
     const float* __restrict__ alpha, double beta, float* __restrict__ Qpart, double* __restrict__ qmpart,
     float* __restrict__ Q, double* __restrict__ qm, double* __restrict__ parts, uint32_t* __restrict__ cnts,
-    uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only) {
+    uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only,
+    const float* __restrict__ minv = nullptr) {
   if (!apply_only && st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   constexpr int nc = kDenseKP + 1;
@@ -380,18 +381,24 @@ __device__ __forceinline__ void dense16_pass2_body(
     if (!apply_only) {
       const float4 r = reinterpret_cast<const float4*>(R)[i4];
       sdots[0][e] = (double)p.x * q.x + (double)p.y * q.y + (double)p.z * q.z + (double)p.w * q.w;
-      sdots[1][e] = (double)r.x * q.x + (double)r.y * q.y + (double)r.z * q.z + (double)r.w * q.w;
-      sdots[2][e] = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
+      float4 mq = q;  // M^-1 q (del and eta of the preconditioned step)
+      if (minv) {
+        const float4 mv = *reinterpret_cast<const float4*>(minv + dq);
+        mq = make_float4(mv.x * q.x, mv.y * q.y, mv.z * q.z, mv.w * q.w);
+      }
+      sdots[1][e] = (double)r.x * mq.x + (double)r.y * mq.y + (double)r.z * mq.z + (double)r.w * mq.w;
+      sdots[2][e] = (double)q.x * mq.x + (double)q.y * mq.y + (double)q.z * mq.z + (double)q.w * mq.w;
     }
   }
   if (ee < 32) {
     const int64_t d = dt + ee;
     const double p = pm[d];
     const double q = beta * vm + (double)alpha[d] * p;
+    const double mq = minv ? (double)minv[d] * q : q;
     qm[d] = q;
     smean[0][32 * tt + ee] = p * q;
-    smean[1][32 * tt + ee] = rm[d] * q;
-    smean[2][32 * tt + ee] = q * q;
+    smean[1][32 * tt + ee] = rm[d] * mq;
+    smean[2][32 * tt + ee] = q * mq;
   }
   if (apply_only) return;
   __syncthreads();
@@ -421,9 +428,9 @@ __global__ __launch_bounds__(64 * kG16Waves) void k_dense16_pass2(
     const double* __restrict__ pm, const float* __restrict__ R, const double* __restrict__ rm,
     const float* __restrict__ alpha, double beta, float* __restrict__ Qpart, double* __restrict__ qmpart,
     float* __restrict__ Q, double* __restrict__ qm, double* __restrict__ parts, uint32_t* __restrict__ cnts,
-    uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only) {
+    uint32_t* __restrict__ split_cnts, CgScalars* __restrict__ st, int apply_only, const float* __restrict__ minv) {
   dense16_pass2_body<RING>(blockIdx.x, blockIdx.y, gridDim.x, phiB, G2, gps, nsplit, Dp, W, wm, P, pm, R, rm, alpha,
-                           beta, Qpart, qmpart, Q, qm, parts, cnts, split_cnts, st, apply_only);
+                           beta, Qpart, qmpart, Q, qm, parts, cnts, split_cnts, st, apply_only, minv);
 }
 
 // Splits of a low-precision pass: ~256 workgroups of two tiles each (one
@@ -458,13 +465,14 @@ hipError_t dense16_pass1(const DenseDims& dd, const void* phiA16, const float* P
 hipError_t dense16_pass2(const DenseDims& dd, const void* phiB16, const float* W, const double* wm,
                          const float* P, const double* pm, const float* R, const double* rm, const float* alpha,
                          double beta, float* Qpart, double* qmpart, float* Q, double* qm, double* gpart,
-                         uint32_t* counter, uint32_t* split_cnts, CgScalars* st, int apply_only, hipStream_t s) {
+                         uint32_t* counter, uint32_t* split_cnts, CgScalars* st, int apply_only, hipStream_t s,
+                         const float* minv) {
   const int64_t pairs = dd.Dp / 64, G2 = dd.Np / 16;
   if (!dense16_split_ok(G2, dd.S2h)) return hipErrorInvalidValue;
   const int64_t gps = (G2 + dd.S2h - 1) / dd.S2h;
   hipLaunchKernelGGL(k_dense16_pass2<4>, dim3((unsigned)pairs, (unsigned)dd.S2h), dim3(64 * kG16Waves), 0, s,
                      static_cast<const uint4*>(phiB16), G2, gps, dd.S2h, dd.Dp, W, wm, P, pm, R, rm, alpha, beta,
-                     Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only);
+                     Qpart, qmpart, Q, qm, gpart, counter, split_cnts, st, apply_only, minv);
   return hipGetLastError();
 }
 
@@ -527,53 +535,68 @@ hipError_t dense_ir_accumulate(const DenseDims& dd, float* Xt, const float* Xi, 
 // Outer residual of the refinement: with Q = A Xt (float32 Phi passes) and B
 // regenerated (probes of EM iteration t in rows d < D, b0 for the mean),
 // R = B - Q, P = R, Xi = 0; rho_c = ||r_c||^2 (float64 sums of the stored
-// values).  The finish sets up the next inner solve: reference norm ||R||_F,
+// values).  With a Jacobi diagonal minv: P = M^-1 R and the sums r^T z and
+// r^T r (finish_ir_residual_pcg).  The finish sets up the next inner solve: reference norm ||R||_F,
 // iteration count 0, cap `limit`, and the true ratio ||R||_F / ||B||_F.
 __global__ __launch_bounds__(256) void k_dense_ir_residual(
     int64_t D, int64_t Dp, uint64_t seed, int t, int K, const double* __restrict__ b0, const float* __restrict__ Q,
     const double* __restrict__ qm, float* __restrict__ Xi, float* __restrict__ R, float* __restrict__ P,
     double* __restrict__ xim, double* __restrict__ rm, double* __restrict__ pm, double* __restrict__ parts,
-    uint32_t* cnts, CgScalars* st, int limit) {
+    uint32_t* cnts, CgScalars* st, int limit, const float* __restrict__ minv) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   const int c = threadIdx.x & 31;
-  double acc = 0.0;
+  double acc = 0.0, accz = 0.0;
   for (int64_t e4 = gtid; e4 < Dp * 8; e4 += gstride) {
     const float4 q = reinterpret_cast<const float4*>(Q)[e4];
     const int64_t d0 = (e4 >> 5) * 4;
     const float qv[4] = {q.x, q.y, q.z, q.w};
-    float rv[4];
+    const float4 mv = minv ? *reinterpret_cast<const float4*>(minv + d0) : make_float4(1.f, 1.f, 1.f, 1.f);
+    const float m4[4] = {mv.x, mv.y, mv.z, mv.w};
+    float rv[4], zv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t d = d0 + i;
       const float b = (c < K && d < D) ? probe_sign(seed, (uint32_t)t, (uint32_t)c, (uint64_t)d) : 0.0f;
       rv[i] = b - qv[i];
+      zv[i] = m4[i] * rv[i];
       acc += (double)rv[i] * (double)rv[i];
+      accz += (double)rv[i] * (double)zv[i];
     }
-    const float4 r = make_float4(rv[0], rv[1], rv[2], rv[3]);
-    reinterpret_cast<float4*>(R)[e4] = r;
-    reinterpret_cast<float4*>(P)[e4] = r;
+    reinterpret_cast<float4*>(R)[e4] = make_float4(rv[0], rv[1], rv[2], rv[3]);
+    reinterpret_cast<float4*>(P)[e4] = make_float4(zv[0], zv[1], zv[2], zv[3]);
     reinterpret_cast<float4*>(Xi)[e4] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  double accm = 0.0;
+  double accm = 0.0, accmz = 0.0;
   for (int64_t d = gtid; d < Dp; d += gstride) {
     const double r = b0[d] - qm[d];
+    const double z = minv ? (double)minv[d] * r : r;
     rm[d] = r;
-    pm[d] = r;
+    pm[d] = z;
     xim[d] = 0.0;
     accm += r * r;
+    accmz += r * z;
   }
-  __shared__ double mine[kDenseKP + 1], tot[kDenseKP + 1];
-  dense_block_sums(acc, accm, mine);
-  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, kDenseKP + 1, mine, tot)) return;
-  finish_ir_residual(st, tot, limit);
+  constexpr int nc = kDenseKP + 1;
+  __shared__ double mine[2 * nc], tot[2 * nc];
+  if (!minv) {
+    dense_block_sums(acc, accm, mine);
+    if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, nc, mine, tot)) return;
+    finish_ir_residual(st, tot, limit);
+    return;
+  }
+  dense_block_sums(accz, accmz, mine);
+  dense_block_sums(acc, accm, mine + nc);
+  if (!tree_reduce(parts, cnts, blockIdx.x, gridDim.x, 2 * nc, mine, tot)) return;
+  finish_ir_residual_pcg(st, tot, limit);
 }
 
 hipError_t dense_ir_residual(const DenseDims& dd, uint64_t seed, int t, int K, const double* b0, const float* Q,
                              const double* qm, float* Xi, float* R, float* P, double* xim, double* rm, double* pm,
-                             double* parts, uint32_t* cnts, CgScalars* st, int limit, hipStream_t s) {
+                             double* parts, uint32_t* cnts, CgScalars* st, int limit, hipStream_t s,
+                             const float* minv) {
   hipLaunchKernelGGL(k_dense_ir_residual, dim3(dense_update_blocks(dd)), dim3(256), 0, s, dd.D, dd.Dp, seed, t, K,
-                     b0, Q, qm, Xi, R, P, xim, rm, pm, parts, cnts, st, limit);
+                     b0, Q, qm, Xi, R, P, xim, rm, pm, parts, cnts, st, limit, minv);
   return hipGetLastError();
 }
 

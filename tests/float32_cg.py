@@ -46,9 +46,12 @@ def dense_float32(phi, beta, alpha):
     return apply
 
 
-def cg_float32(apply32, B, iters, X0=None):
+def cg_float32(apply32, B, iters, X0=None, minv=None):
     """`iters` CG steps on the float32 block B (D x n), from X0 (float32,
-    R0 = B - A X0 evaluated in float32) or from zero."""
+    R0 = B - A X0 evaluated in float32) or from zero.  With `minv` (a float32
+    diagonal M^-1) the preconditioned recurrences of the library's Jacobi
+    form: z = M^-1 r, rho = r^T z, del = r^T M^-1 q, eta = q^T M^-1 q, and
+    p = z + b p."""
     B = np.asarray(B, np.float32)
     if X0 is None:
         X = np.zeros_like(B)
@@ -56,20 +59,24 @@ def cg_float32(apply32, B, iters, X0=None):
     else:
         X = np.asarray(X0, np.float32).copy()
         R = (B - apply32(X)).astype(np.float32)
-    P = R.copy()
+    m = None if minv is None else np.asarray(minv, np.float32)[:, None]
+    Z = R.copy() if m is None else (m * R).astype(np.float32)
+    P = Z.copy()
     f64 = lambda M: M.astype(np.float64)  # noqa: E731
-    rho = np.einsum("dc,dc->c", f64(R), f64(R))
+    rho = np.einsum("dc,dc->c", f64(R), f64(Z))
     for _ in range(iters):
         Q = apply32(P)
+        MQ = Q if m is None else (m * Q).astype(np.float32)
         gam = np.einsum("dc,dc->c", f64(P), f64(Q))
-        dl = np.einsum("dc,dc->c", f64(R), f64(Q))
-        et = np.einsum("dc,dc->c", f64(Q), f64(Q))
+        dl = np.einsum("dc,dc->c", f64(R), f64(MQ))
+        et = np.einsum("dc,dc->c", f64(Q), f64(MQ))
         a = np.divide(rho, gam, out=np.zeros_like(rho), where=gam != 0.0)
         rn = np.maximum(rho - 2.0 * a * dl + a * a * et, 0.0)
         b = np.divide(rn, rho, out=np.zeros_like(rho), where=rho != 0.0)
         a32, b32 = a.astype(np.float32), b.astype(np.float32)
         X = X + a32 * P
         R = R - a32 * Q
-        P = R + b32 * P
-        rho = np.einsum("dc,dc->c", f64(R), f64(R))
+        Z = R if m is None else (m * R).astype(np.float32)
+        P = Z + b32 * P
+        rho = np.einsum("dc,dc->c", f64(R), f64(Z))
     return X
