@@ -694,7 +694,7 @@ def run_conv(args):
         log(f"oracle reference: {m_ref} EM iterations of the control's algorithm on {op.workers} threads ...")
         t0 = time.perf_counter()
         ref = O.cofem(op, y64, p.beta, m_ref, p.K, tol=p.tol, max_iter=p.max_iter, seed=p.seed, warm_start=True,
-                      jacobi=True)
+                      jacobi=True, spectral_start=not args.no_spectral)
         el = time.perf_counter() - t0
         cg_or = [x["cg_iters"] for x in ref.stats]
         # the per-EM-iteration work besides CG (probes, diagonal estimate, M-step)
@@ -734,8 +734,8 @@ def run_conv(args):
                "one_thread": {"value": round(em_rate(c_cg1, c_em), 6), "ms_per_cg_iter": round(c_cg1 * 1e3, 1),
                               "sample": "two CG iterations of the first E-step on one thread, scaled the same way"},
                "host": {"cpu_model": model, "nproc": ncpu}}
-        traj = {"em_iters": m_ref, "reference": "float64 oracle, control's algorithm (warm start + Jacobi), "
-                                                "FFT route", "oracle_cg_iters": cg_or, "host_seconds": round(el, 1),
+        traj = {"em_iters": m_ref, "reference": "float64 oracle, control's algorithm (warm start + Jacobi"
+                                                + ("" if args.no_spectral else ", exact first E-step") + "), FFT route", "oracle_cg_iters": cg_or, "host_seconds": round(el, 1),
                 "nmse_mu_vs_oracle": {f: nmse(r["mu_m"], ref.mu) for f, r in runs.items()},
                 "cg_iters_gpu": {f: [x["cg_iters"] for x in r["stats_m"]] for f, r in runs.items()}}
         log(f"cpu oracle: {cpu['value']:.5f} EM it/s ({c_cg * 1e3:.0f} ms per CG iteration on {op.workers} threads, "
@@ -974,7 +974,7 @@ def main():
     ap.add_argument("--timing-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the float64 oracle (CPU sample, parity and the NMSE reference)")
-    ap.add_argument("--oracle-em-iters", type=int, default=3,
+    ap.add_argument("--oracle-em-iters", type=int, default=5,
                     help="conv workloads: EM iterations of the float64 oracle reference and CPU sample")
     ap.add_argument("--timing-every", type=int, default=13,
                     help="time the launches of every n-th CG iteration with HIP events (1: all; each timed "

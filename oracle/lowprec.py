@@ -16,6 +16,9 @@ refinement converges iff the spectral radius of I - A~^-1 A is below one.
   max |Phi| 2^e <= 448), rounded to E4M3, scaled back (exact).
 * ``refinement_contraction``: max |1 - lambda| over the eigenvalues lambda of
   A~^-1 A (computed as the symmetric L^-1 A L^-T, A~ = L L^T).
+* ``conv_refinement_contraction``: the same for a circular-convolution
+  dictionary under a uniform alpha = a, where A and A~ share the 2D DFT as
+  eigenvectors: lambda_k = (beta |h_hat_k|^2 + a) / (beta |h~_hat_k|^2 + a).
 """
 from __future__ import annotations
 
@@ -71,3 +74,16 @@ def refinement_contraction(phi: np.ndarray, phi_low: np.ndarray, beta: float, al
     Li = np.linalg.solve(L, np.eye(L.shape[0]))
     ev = np.linalg.eigvalsh(Li @ A @ Li.T)
     return float(max(abs(1.0 - ev.min()), abs(1.0 - ev.max())))
+
+
+def conv_refinement_contraction(taps: np.ndarray, taps_low: np.ndarray, H: int, W: int, beta: float,
+                                a: float) -> float:
+    """Spectral radius of I - A~^-1 A for the circular convolution with
+    `taps` (A) and with `taps_low` (A~) on an H x W image, alpha = a
+    everywhere: max_k |beta (g~_k - g_k)| / (beta g~_k + a) with g = |h_hat|^2
+    from the oracle's Fourier-domain operator (any image size)."""
+    from .cofem_oracle import ConvOperatorFFT
+
+    g = ConvOperatorFFT(np.asarray(taps, np.float64), H, W).gram_hat
+    gl = ConvOperatorFFT(np.asarray(taps_low, np.float64), H, W).gram_hat
+    return float(np.max(np.abs(beta * (gl - g)) / (beta * gl + a)))

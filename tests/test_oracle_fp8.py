@@ -82,3 +82,40 @@ def test_e4m3_refinement_diverges_early_and_contracts_late(scaled_c2):
     assert rho[(1, "fp8")] > rho[(5, "fp8")] > rho[(12, "fp8")]
     assert rho[(12, "fp8")] < 1.0         # contracts once most alpha are large
     assert all(rho[(t, "bf16")] < 0.25 for t in alphas)
+
+
+# ------------------------------------------------------------------ bf16 taps
+def _dense_conv(taps, H, W):
+    op = O.ConvOperator(np.asarray(taps, np.float64), H, W)
+    return op.apply(np.eye(H * W))
+
+
+def test_conv_contraction_pins():
+    from oracle.lowprec import conv_refinement_contraction, refinement_contraction
+    rng = np.random.default_rng(12)
+    # the Fourier-domain formula against the dense eigen-decomposition
+    for H, W, k in ((8, 8, 3), (6, 10, 5)):
+        taps = rng.standard_normal((k, k))
+        low = taps + 1e-2 * rng.standard_normal((k, k))
+        for a in (0.5, 7.0):
+            r = conv_refinement_contraction(taps, low, H, W, 30.0, a)
+            ref = refinement_contraction(_dense_conv(taps, H, W), _dense_conv(low, H, W), 30.0, np.full(H * W, a))
+            assert abs(r - ref) <= 1e-10 * max(ref, 1.0)
+    # closed form of a 1 x 1 kernel: |beta (c~^2 - c^2)| / (beta c~^2 + a)
+    r = conv_refinement_contraction(np.array([[1.5]]), np.array([[1.25]]), 4, 4, 2.0, 3.0)
+    assert np.isclose(r, 2.0 * abs(1.25 ** 2 - 1.5 ** 2) / (2.0 * 1.25 ** 2 + 3.0))
+
+
+def test_bf16_taps_refinement_contracts_on_the_9x9_law():
+    # A refinement whose inner solves used the 9x9 taps rounded to bfloat16
+    # would converge on the 9x9 kernel law of the 1024 x 1024 workload (beta =
+    # 1e4, here on a 256 x 256 grid): the contraction at
+    # alpha = 1 (the first E-step) is 0.17..0.35 and falls as alpha grows.
+    from oracle.lowprec import conv_refinement_contraction
+    from paper_2202_12808_amd import synth
+    for seed in (0, 1, 2):
+        p = synth.conv_problem(256, 256, 9, rho=0.01, beta=1e4, K=4, tol=1e-5, seed=seed)
+        low = synth.round_to_bf16(p.taps)
+        r = [conv_refinement_contraction(p.taps, low, 256, 256, p.beta, a) for a in (1.0, 10.0, 100.0)]
+        print("bf16-taps contraction, seed", seed, "alpha 1/10/100:", r)
+        assert 0.1 < r[0] < 0.5 and r[2] < r[1] < r[0]
