@@ -141,6 +141,24 @@ def stored_traffic(kind, kernel, workload):
         return None
 
 
+def calibration_copies(args, dev):
+    """--calibration-copy-mib m: three plain device copies of m MiB before the
+    workload, whose FETCH_SIZE and WRITE_SIZE counters scale the kernels' (a
+    copy reads and writes exactly 2^20 m bytes)."""
+    if args.calibration_copy_mib <= 0:
+        return
+    import torch
+
+    n = args.calibration_copy_mib << 18
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration: 3 copies of {4 * n} bytes")
+    del src, dst
+
+
 def train_predictor(p, dev, train_size=256, seeds=(1000, 1001, 1002), em_iters=None, epochs=20, lr=1e-3,
                     spectral=True):
     """Trains the learned form's network on EM iterates of `seeds` (disjoint
@@ -363,15 +381,7 @@ def run_dct(args):
 
     g = make(args.form)
     ones = torch.ones(p.D, dtype=torch.float32, device=dev)
-    if args.calibration_copy_mib > 0:
-        n = args.calibration_copy_mib << 18
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration: 3 copies of {4 * n} bytes")
-        del src, dst
+    calibration_copies(args, dev)
 
     def one_step(c):
         c.set_alpha(ones)
@@ -603,15 +613,7 @@ def run_conv(args):
             c.set_predictor(net)
         return c
 
-    if args.calibration_copy_mib > 0:
-        n = args.calibration_copy_mib << 18
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration: 3 copies of {4 * n} bytes")
-        del src, dst
+    calibration_copies(args, dev)
 
     def timed(f, kernel_timing):
         g = make(f)
@@ -654,7 +656,7 @@ def run_conv(args):
     # roofline of the fused stencil iteration (the dominant kernel)
     roofline = None
     if "kt" in head:
-        kt = head["kt"]["pass1"]
+        kt = head["kt"]["pass1"]  # the fused iterations (a solve's first pass is timed apart, in "pass2")
         ms = kt[0] / max(kt[1], 1)
         nbytes = algorithmic_bytes(p, "pass1")
         nflops = algorithmic_flops(p, "pass1")
@@ -670,6 +672,10 @@ def run_conv(args):
                             "peak_issue_tflops": FP32_VALU_ISSUE_TFS, "frac_issue": round(tfs / FP32_VALU_ISSUE_TFS, 4),
                             "peak_published_tflops": FP32_VALU_PEAK_TFS,
                             "frac_published": round(tfs / FP32_VALU_PEAK_TFS, 4)}}
+        k0 = head["kt"]["pass2"]
+        if k0[1]:
+            roofline["first_pass"] = {"kernel": "k_conv_pass", "ms_per_launch": round(k0[0] / k0[1], 5),
+                                      "launches": k0[1]}
         log(f"roofline: k_conv_fused {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of "
             f"HBM), {tfs:.2f} TFLOP/s ({100 * tfs / FP32_VALU_ISSUE_TFS:.1f}% of the non-packed fp32 issue rate)")
 
@@ -834,6 +840,7 @@ def run_dense(args, emit=True):
         sys.exit(2)
     y = torch.from_numpy(p.y).to(dev)
     phi = torch.from_numpy(p.phi).to(dev)
+    calibration_copies(args, dev)
 
     def make(f):
         prec = "bf16_ir" if f == "bf16_ir" else "fp32"

@@ -482,8 +482,9 @@ cofem_status cofem_set_predictor(cofem_ctx* ctx, cofem_net* net);
 
 /* Kernel slots of cofem_get_kernel_timing. */
 enum {
-  COFEM_KT_PASS1 = 0,  /* dense: W = Phi P;  conv: the fused stencil pass */
-  COFEM_KT_PASS2 = 1,  /* dense: Q = beta Phi^T W + alpha P with the CG dots */
+  COFEM_KT_PASS1 = 0,  /* dense: W = Phi P;  conv: the fused iteration (update + stencil pass) */
+  COFEM_KT_PASS2 = 1,  /* dense: Q = beta Phi^T W + alpha P with the CG dots;
+                        * conv: a solve's first launch, the stencil pass on its start direction */
   COFEM_KT_UPDATE = 2, /* CG update x, r, p and the new residual norms */
   COFEM_KT_INIT = 3,   /* probes, R = P = B, X = 0 */
   COFEM_KT_MSTEP = 4,  /* diagonal estimate and M-step */

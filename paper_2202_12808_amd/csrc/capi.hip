@@ -1083,7 +1083,9 @@ cofem_status run_cg_iterations(cofem_ctx* c, int n, bool lowp = false) {
       const float* minv = conv_pcg(c) ? c->active_minv : nullptr;
       const ConvState sets[2] = {{c->vP, c->vR, c->vQ, c->pm, c->rm, c->qm},
                                  {c->vP2, c->vR2, c->vQ2, c->pm2, c->rm2, c->qm2}};
-      COFEM_TRY(cg_mark(c, samp, COFEM_KT_PASS1, it));
+      // (timed apart: the fused iterations in the pass-1 slot, a solve's first
+      // pass in the pass-2 slot)
+      COFEM_TRY(cg_mark(c, samp, it == 0 ? COFEM_KT_PASS2 : COFEM_KT_PASS1, it));
       if (it == 0)
         COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vP, c->pm, c->vR, c->rm, c->alpha, c->beta, c->vQ, c->qm,
                                c->red_pass, c->st, 0, c->stream, minv));
