@@ -89,7 +89,7 @@ def algorithmic_bytes(p, which, phi_bytes=4):
 KERNEL_NAMES = {"dense": {"pass1": "k_dense_pass1", "pass2": "k_dense_pass2", "update": "k_dense_update"},
                 "dct": {"pass1": "k_dct_rows_in", "pass2": "k_dct_mid", "update": "k_dct_rows_out"},
                 "dense_bf16_ir": {"pass1": "k_dense16_pass1", "pass2": "k_dense16_pass2", "update": "k_dense_update"},
-                "conv": {"pass1": "k_conv_fused"}}
+                "conv": {"pass1": "k_conv_fused"}, "conv_ws": {"pass1": "k_conv_ws"}}
 FORMS = {"fp32": "fp32 probes + fp64 mean column",
          "fp32_warm": "fp32 Jacobi-preconditioned CG started from the previous mean and diagonal estimate (fp64 "
                       "mean column)",
@@ -106,7 +106,10 @@ FORMS_DCT = {"fp32": "inverse-DCT + mask dictionary, plain fp32 CG + fp64 mean c
 KERNEL_SOURCES = {"dense": ("paper_2202_12808_amd/csrc/kernels_dense.hip", "paper_2202_12808_amd/csrc/cofem_internal.h"),
                   "dense_bf16_ir": ("paper_2202_12808_amd/csrc/kernels_dense_bf16.hip",
                                     "paper_2202_12808_amd/csrc/cofem_internal.h"),
-                  "conv": ("paper_2202_12808_amd/csrc/kernels_conv.hip", "paper_2202_12808_amd/csrc/cofem_internal.h"),
+                  "conv": ("paper_2202_12808_amd/csrc/kernels_conv.hip", "paper_2202_12808_amd/csrc/conv_tile.h",
+                           "paper_2202_12808_amd/csrc/cofem_internal.h"),
+                  "conv_ws": ("paper_2202_12808_amd/csrc/kernels_conv_ws.hip", "paper_2202_12808_amd/csrc/conv_tile.h",
+                              "paper_2202_12808_amd/csrc/cofem_internal.h"),
                   "dct": ("paper_2202_12808_amd/csrc/kernels_dct.hip", "paper_2202_12808_amd/csrc/cofem_internal.h")}
 
 
@@ -633,6 +636,7 @@ def run_conv(args):
                "mu_T": g.solution()[1].cpu().numpy()}
         if kernel_timing:
             res["kt"] = g.kernel_timing()
+            res["kt_names"] = {"pass1": g.kernel_name("pass1"), "pass2": g.kernel_name("pass2")}
             g.set_kernel_timing(0)
         if not args.no_cpu_baseline:  # the first m EM iterations, for the float64 reference
             g.restart()
@@ -653,9 +657,11 @@ def run_conv(args):
     value, elapsed = head["value"], head["elapsed"]
     cg_counts = [x["cg_iters"] for x in head["stats"]]
 
-    # roofline of the fused stencil iteration (the dominant kernel)
+    # roofline of the fused stencil iteration (the dominant kernel: the
+    # persistent k_conv_ws at this size, or the per-tile k_conv_fused)
     roofline = None
     if "kt" in head:
+        kname = head["kt_names"]["pass1"]
         kt = head["kt"]["pass1"]  # the fused iterations (a solve's first pass is timed apart, in "pass2")
         ms = kt[0] / max(kt[1], 1)
         nbytes = algorithmic_bytes(p, "pass1")
@@ -664,7 +670,8 @@ def run_conv(args):
         tfs = nflops / (ms * 1e-3) / 1e12
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": stored_traffic("conv", "k_conv_fused", p.name), "kernel": "k_conv_fused",
+                    "traffic": stored_traffic("conv_ws" if kname == "k_conv_ws" else "conv", kname, p.name),
+                    "kernel": kname,
                     "bytes_per_launch": nbytes, "ms_per_launch": round(ms, 5), "launches": kt[1],
                     "timing": f"HIP events around the launches of every {args.timing_every}-th CG iteration "
                               "during the timed steps",
@@ -674,9 +681,9 @@ def run_conv(args):
                             "frac_published": round(tfs / FP32_VALU_PEAK_TFS, 4)}}
         k0 = head["kt"]["pass2"]
         if k0[1]:
-            roofline["first_pass"] = {"kernel": "k_conv_pass", "ms_per_launch": round(k0[0] / k0[1], 5),
+            roofline["first_pass"] = {"kernel": head["kt_names"]["pass2"], "ms_per_launch": round(k0[0] / k0[1], 5),
                                       "launches": k0[1]}
-        log(f"roofline: k_conv_fused {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of "
+        log(f"roofline: {kname} {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f}% of "
             f"HBM), {tfs:.2f} TFLOP/s ({100 * tfs / FP32_VALU_ISSUE_TFS:.1f}% of the non-packed fp32 issue rate)")
 
     # the float64 reference: the oracle run of the control's algorithm over

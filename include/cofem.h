@@ -517,6 +517,18 @@ cofem_status cofem_set_kernel_timing(cofem_ctx* ctx, int32_t enable);
  */
 cofem_status cofem_get_kernel_timing(cofem_ctx* ctx, double* ms_total, int64_t* launches);
 
+/*
+ * The name of the kernel that the COFEM_KT_PASS1 or COFEM_KT_PASS2 timing
+ * slot times for this context (its kind, precision and problem shape decide
+ * it: the convolution dictionary's fused iteration runs as k_conv_ws, the
+ * persistent warp-specialised form, once every workgroup of one per compute
+ * unit gets four or more tiles, else as the per-tile k_conv_fused; the
+ * environment variable COFEM_CONV_KERNEL=tile|ws|ws:<workgroups>, read by
+ * cofem_init, overrides that choice), or NULL for a null context or another
+ * slot.  A static string; for measurement and profiling tools.
+ */
+const char* cofem_kernel_name(const cofem_ctx* ctx, int32_t slot);
+
 /* Frees every device buffer of the context (after synchronising its stream). */
 void cofem_destroy(cofem_ctx* ctx);
 

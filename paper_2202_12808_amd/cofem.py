@@ -114,6 +114,7 @@ _SIGNATURES = {
     "cofem_get_ir_sweeps": (c_int32, [c_void_p, POINTER(c_int32), c_int32, POINTER(c_int32)]),
     "cofem_apply_A_lowp": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cofem_get_kernel_timing": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(c_int64)]),
+    "cofem_kernel_name": (ctypes.c_char_p, [c_void_p, c_int32]),
     "cofem_destroy": (None, [c_void_p]),
     "cofem_last_error": (c_char_p, [c_void_p]),
     "cofem_status_string": (c_char_p, [c_int32]),
@@ -288,6 +289,12 @@ def cofem_get_ir_sweeps(ctx):
 def cofem_set_kernel_timing(ctx, enable):
     """enable: False/0 off, True/1 every CG iteration, n > 1 every n-th."""
     _check(load().cofem_set_kernel_timing(ctx, int(enable)), ctx)
+
+
+def cofem_kernel_name(ctx, slot: str):
+    """The kernel a timing slot ("pass1", ...) times for this context."""
+    name = load().cofem_kernel_name(ctx, KERNEL_SLOTS.index(slot))
+    return name.decode() if name else None
 
 
 def cofem_get_kernel_timing(ctx):
@@ -489,6 +496,9 @@ class CoFEM:
 
     def kernel_timing(self):
         return cofem_get_kernel_timing(self.ctx)
+
+    def kernel_name(self, slot):
+        return cofem_kernel_name(self.ctx, slot)
 
     def close(self):
         if getattr(self, "ctx", None):

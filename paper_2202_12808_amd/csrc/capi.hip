@@ -399,6 +399,26 @@ cofem_status init_conv(cofem_ctx* c, const cofem_problem& p) {
   c->KP = c->K;
   cd.fp64 = c->precision == COFEM_PREC_FP64 ? 1 : 0;
   cd.nt = c->NT;
+  // the fused CG iteration as one persistent warp-specialised launch (one
+  // workgroup per compute unit) once every workgroup gets several tiles;
+  // tuning override: COFEM_CONV_KERNEL=tile | ws | ws:<workgroups>
+  cd.ws_grid = 0;
+  if (!c->sizing && conv_ws_ok(cd)) {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
+      const int64_t units = (4 * (int64_t)cd.nt + cd.K) * cd.tilesX * cd.tilesY;
+      int mode = 0, grid = ncu;
+      if (const char* e = getenv("COFEM_CONV_KERNEL")) {
+        if (strcmp(e, "tile") == 0) mode = -1;
+        else if (strncmp(e, "ws", 2) == 0) {
+          mode = 1;
+          if (e[2] == ':' && atoi(e + 3) > 0) grid = atoi(e + 3);
+        }
+      }
+      if (mode > 0 || (mode == 0 && units >= 4 * (int64_t)ncu)) cd.ws_grid = (int)(units < grid ? units : grid);
+    }
+  }
   const size_t blk = (size_t)cd.ldD * c->K, DT = (size_t)cd.ldD * c->NT;
   COFEM_TRY(alloc(c, &c->taps, (size_t)p.kh * p.kw));
   COFEM_TRY(alloc(c, &c->b0, DT));  // one column per task
@@ -475,6 +495,7 @@ cofem_status init_dct(cofem_ctx* c, const cofem_problem& p) {
   cd.fp64 = 0;
   cd.perm = xd.l1 | (xd.l2 << 8);
   cd.nt = c->NT;
+  cd.ws_grid = 0;
   c->KP = c->K;
   // the observed samples must be distinct and in range (checked once, here)
   if (!c->sizing) {
@@ -1996,6 +2017,18 @@ cofem_status cofem_get_kernel_timing(cofem_ctx* ctx, double* ms_total, int64_t* 
     launches[i] = ctx->kt_n[i];
   }
   return COFEM_OK;
+}
+
+const char* cofem_kernel_name(const cofem_ctx* ctx, int32_t slot) {
+  if (!ctx || (slot != COFEM_KT_PASS1 && slot != COFEM_KT_PASS2)) return nullptr;
+  const bool p1 = slot == COFEM_KT_PASS1;
+  if (ctx->kind == COFEM_DENSE) {
+    if (ctx->precision == COFEM_PREC_BF16_IR) return p1 ? "k_dense16_pass1" : "k_dense16_pass2";
+    return p1 ? "k_dense_pass1" : "k_dense_pass2";
+  }
+  if (ctx->kind == COFEM_DCT_MASK) return p1 ? "k_dct_rows_in" : "k_dct_mid";
+  if (!p1) return "k_conv_pass";
+  return ctx->cd.ws_grid > 0 ? "k_conv_ws" : "k_conv_fused";
 }
 
 cofem_status cofem_batch_plan(cofem_ctx* ctx, int32_t* target_wgs, float* candidate_ms, int32_t* splits1,

@@ -723,6 +723,9 @@ struct ConvDims {
   int perm;
   // float64 mean columns (tasks sharing alpha), blocks of ldD after xm etc.
   int nt;
+  // workgroups of the persistent warp-specialised fused iteration
+  // (kernels_conv_ws.hip); 0: the per-tile kernel
+  int ws_grid;
 };
 
 __host__ __device__ __forceinline__ int64_t perm_nat(int perm, int64_t pos) {
@@ -755,6 +758,12 @@ struct ConvState {
 hipError_t conv_fused(const ConvDims& cd, const float* taps, const ConvState& s0, const ConvState& s1, void* X,
                       double* xm, const float* alpha, double beta, const float* minv, const ConvReduce& red,
                       CgScalars* st, hipStream_t s);
+// The persistent warp-specialised form of conv_fused (float probe columns):
+// whether the problem's shape admits it, and the launch on `grid` workgroups.
+bool conv_ws_ok(const ConvDims& cd);
+hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const ConvState& s0, const ConvState& s1,
+                         void* X, double* xm, const float* alpha, double beta, const float* minv,
+                         const ConvReduce& red, CgScalars* st, hipStream_t s);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,

@@ -18,72 +18,9 @@
 // State layout: probe columns are column-major images (column k at k * ldD,
 // pixel j = u * W + v) of type TP (float, or double in the float64 mode); the
 // mean column is always a float64 image.
-#include "cofem_internal.h"
+#include "conv_tile.h"
 
 namespace cofem {
-
-__device__ __forceinline__ int wrap(int x, int n) {
-  x %= n;
-  return x < 0 ? x + n : x;
-}
-
-// Geometry of one fused pass over a TILE x TILE output tile with KS x KS taps
-// (c = (KS-1)/2).  Stage 1 forms t = Phi p on the tile plus a c halo (TR x TR,
-// rounded up to 4x4 blocks) from p staged with a 2c halo (SPH x SPW); stage 2
-// forms Phi^T t on the tile.  Each thread computes 4x4 output blocks; a block
-// reads KS+3 rows of XW values (KS+3 rounded up to whole float4s).
-template <int KS, int TILE>
-struct ConvGeom {
-  static constexpr int c = (KS - 1) / 2;
-  static constexpr int TR = ((TILE + 2 * c + 3) / 4) * 4;
-  static constexpr int XW = ((KS + 3 + 3) / 4) * 4;
-  static constexpr int SPH = TR + 2 * c;
-  static constexpr int SPW = TR + XW - 4;
-  static constexpr int NB1 = (TR / 4) * (TR / 4);
-  static constexpr int NB2 = (TILE / 4) * (TILE / 4);
-  static constexpr int LDS = SPH * SPW + TR * TR;  // values
-};
-
-// Taps of the 4x4 blocks, read from LDS as broadcasts.  Each input row uses
-// at most 4 tap rows (4 KS values), which stay in registers for that row;
-// fence() is an empty asm that the compiler must assume changes the (zero)
-// index offset, so tap reads of later rows are neither merged with nor
-// hoisted above earlier ones (keeping all KS*KS taps live would crowd out the
-// accumulators and the double-buffered input rows).
-template <typename T>
-struct Taps {
-  typedef __attribute__((address_space(3))) const T* lds_ptr;
-  lds_ptr s;     // the taps in LDS (an LDS-typed pointer, so reads stay ds_read)
-  lds_ptr base;  // s laundered by fence(): one address register per input
-                 // row, the row's tap reads use immediate offsets from it
-  __device__ __forceinline__ explicit Taps(const T* p) : s((lds_ptr)p), base((lds_ptr)p) {}
-  __device__ __forceinline__ T operator()(int i) const { return base[i]; }
-  __device__ __forceinline__ void fence() {
-    base = s;
-    asm volatile("" : "+v"(base));
-  }
-};
-
-template <typename T, int N>
-__device__ __forceinline__ void lds_row(const T* src, T (&x)[N]) {
-  if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int q = 0; q < N / 4; ++q) {
-      const float4 v = reinterpret_cast<const float4*>(src)[q];
-      x[4 * q] = v.x;
-      x[4 * q + 1] = v.y;
-      x[4 * q + 2] = v.z;
-      x[4 * q + 3] = v.w;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < N / 2; ++q) {
-      const double2 v = reinterpret_cast<const double2*>(src)[q];
-      x[2 * q] = v.x;
-      x[2 * q + 1] = v.y;
-    }
-  }
-}
 
 // The CG update that a fused iteration applies while it stages p: the
 // previous iteration's p, r and q (read: a neighbouring tile's halo reads
@@ -202,78 +139,14 @@ __device__ __forceinline__ void conv_tile(TapsT h, int H, int W, int tu0, int tv
     }
   }
   __syncthreads();
-  // stage 1: t = Phi p on the tile plus a c halo, 4x4 blocks:
-  //   t(i, j) = sum_{a,b} h[a][b] sP(i - a + 2c, j - b + 2c)
-  for (int item = tid; item < G::NB1; item += kThreads) {
-    const int bi = item / (G::TR / 4), bj = item - (item / (G::TR / 4)) * (G::TR / 4);
-    T acc[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) acc[r][cc] = T(0);
-    // rows are double-buffered: row q + 1 is read from LDS while row q is
-    // used; the scheduling barrier keeps later rows' loads from being hoisted
-    // (which would hold every row in registers at once)
-    const T* src1 = sP + (4 * bi) * G::SPW + 4 * bj;
-    T x[2][G::XW];
-    lds_row(src1, x[0]);
-#pragma unroll
-    for (int q = 0; q < KS + 3; ++q) {  // input row 4 bi + q
-      h.fence();
-      if (q + 1 < KS + 3) lds_row(src1 + (q + 1) * G::SPW, x[(q + 1) & 1]);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = r + 2 * c - q;
-        if (a < 0 || a >= KS) continue;
-#pragma unroll
-        for (int b = 0; b < KS; ++b) {
-          const T hv = h(a * KS + b);
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) acc[r][cc] = fma(hv, x[q & 1][cc + 2 * c - b], acc[r][cc]);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      T* dst = sT + (4 * bi + r) * G::TR + 4 * bj;
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) dst[cc] = acc[r][cc];
-    }
-  }
+  // stage 1: t = Phi p on the tile plus a c halo
+  conv_stage1<KS, TILE, T>(h, sP, sT, tid, kThreads);
   __syncthreads();
-  // stage 2: q = beta Phi^T t + alpha p on the tile, 4x4 blocks:
-  //   (Phi^T t)(i, j) = sum_{a,b} h[a][b] t(i + a, j + b)
+  // stage 2: q = beta Phi^T t + alpha p on the tile
   double g = 0.0, dl = 0.0, et = 0.0;
   const int bi2 = tid / (TILE / 4), bj2 = tid - (tid / (TILE / 4)) * (TILE / 4);
   T acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) acc[r][cc] = T(0);
-  if (tid < G::NB2) {
-    const int bi = bi2, bj = bj2;
-    const T* src2 = sT + (4 * bi) * G::TR + 4 * bj;
-    T x[2][G::XW];
-    lds_row(src2, x[0]);
-#pragma unroll
-    for (int q = 0; q < KS + 3; ++q) {  // t row 4 bi + q
-      h.fence();
-      if (q + 1 < KS + 3) lds_row(src2 + (q + 1) * G::TR, x[(q + 1) & 1]);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = q - r;
-        if (a < 0 || a >= KS) continue;
-#pragma unroll
-        for (int b = 0; b < KS; ++b) {
-          const T hv = h(a * KS + b);
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) acc[r][cc] = fma(hv, x[q & 1][cc + b], acc[r][cc]);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
+  if (tid < G::NB2) conv_stage2<KS, TILE, T>(h, sT, tid, acc);
   __syncthreads();  // every thread is done reading t
   if (tid < G::NB2) {
     T* dst = sT + (4 * bi2) * TILE + 4 * bj2;  // Phi^T t of the tile, TILE x TILE
@@ -313,7 +186,7 @@ __device__ __forceinline__ void conv_tile(TapsT h, int H, int W, int tu0, int tv
       const int e = tid + (k0 + k) * kThreads;
       const int i = e / TILE, j = e - (e / TILE) * TILE;
       const T p = sP[(i + 2 * c) * G::SPW + j + 2 * c];
-      const T q = beta * sT[e] + (T)al[k] * p;
+      const T q = fma(beta, sT[e], (T)al[k] * p);  // one rounding order in every kernel
       Q[ix[k]] = q;
       const double qd = (double)q;
       // with a diagonal preconditioner the step's dots are weighted by it:
@@ -575,6 +448,7 @@ static hipError_t launch_conv_fused(const ConvDims& cd, const float* taps, const
 hipError_t conv_fused(const ConvDims& cd, const float* taps, const ConvState& s0, const ConvState& s1, void* X,
                       double* xm, const float* alpha, double beta, const float* minv, const ConvReduce& red,
                       CgScalars* st, hipStream_t s) {
+  if (cd.ws_grid > 0) return conv_fused_ws(cd, cd.ws_grid, taps, s0, s1, X, xm, alpha, beta, minv, red, st, s);
   if (cd.fp64) return launch_conv_fused<double>(cd, taps, s0, s1, X, xm, alpha, beta, minv, red, st, s);
   return launch_conv_fused<float>(cd, taps, s0, s1, X, xm, alpha, beta, minv, red, st, s);
 }

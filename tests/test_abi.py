@@ -188,6 +188,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.cofem_apply_A(None, 0, None, None, None, None) == C.COFEM_ERR_INVALID_ARG
     assert lib.cofem_probe_signs(0, 1, 1, 10, None, None) == C.COFEM_ERR_INVALID_ARG
     assert lib.cofem_probe_signs(0, -1, 1, 10, 8, None) == C.COFEM_ERR_INVALID_ARG
+    assert lib.cofem_kernel_name(None, 0) is None
     lib.cofem_destroy(None)
 
 
