@@ -8,19 +8,12 @@
 // (the two stencil stages, 2 KS^2 FMAs per pixel).  In the per-tile kernel a
 // workgroup runs them one after the other; here each workgroup is persistent
 // and splits its waves by role so the two parts of different tiles overlap:
-//   compute waves (4): stage 1 and stage 2 of unit n (LDS only);
-//   memory waves (8):  staging of unit n + 1 and the epilogue of unit n - 1.
-// Step s of a workgroup's loop has two phases separated by block barriers:
-//   phase 1: compute: stage 1 of unit s-1 (sP[(s-1)%3] -> sT)
-//            memory:  epilogue of unit s-2 (sU[s%2], sP[(s-2)%3]), staging of
-//                     unit s, first part (-> sP[s%3])
-//   phase 2: compute: stage 2 of unit s-1 (sT -> sU[(s-1)%2])
-//            memory:  staging of unit s, second part; the partial sums of
-//                     unit s-2 deposited and, for a column's last unit, the
-//                     column summed
-// so sP is triple-buffered (staged at s, read at s+1 and s+2) and sU
-// double-buffered.  Every wave runs the same number of steps and exactly two
-// barriers per step; the role functions contain none.
+//   compute waves (4): stage 1 and stage 2 of unit s (LDS only);
+//   memory waves (8):  staging of unit s + 1 and the epilogue of unit s - 1.
+// The staging keeps r' and M^-1 of the unit's own pixels in LDS beside p',
+// so the epilogue reads only alpha from memory.  The schedule of one step
+// (two barriers, the same count for every wave) is described at
+// ws_compute_loop; the role functions contain no other barrier.
 //
 // Units: the 32 x 32 quadrants of the float64 mean columns first, then the
 // 64 x 64 tiles of the float probe columns.  Unit u belongs to workgroup
@@ -51,8 +44,10 @@ struct WsGeom {
   static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
   static constexpr size_t SP = (mx(GF::SPH * GF::SPW * 4, GD::SPH * GD::SPW * 8) + 15) / 16 * 16;
   static constexpr size_t ST = (mx(GF::TR * GF::TR * 4, GD::TR * GD::TR * 8) + 15) / 16 * 16;
+  // a unit's own pixels: Phi^T t (sU) and the staged r', M^-1 (sR, sM)
   static constexpr size_t SU = mx(kConvTile * kConvTile * 4, (kConvTile / 2) * (kConvTile / 2) * 8);
-  static constexpr size_t BYTES = 3 * SP + ST + 2 * SU;
+  // two staged regions, stage-1 output, stage-2 output, two r' and two M^-1
+  static constexpr size_t BYTES = 2 * SP + ST + 5 * SU;
   static_assert(GF::SPW % 4 == 0 && GD::SPW % 2 == 0 && (2 * GF::c) % 4 == 0, "vector rows");
 };
 
@@ -130,7 +125,7 @@ struct WsStageRaw {
   bool own[kWsOwnVecs];
 };
 struct WsEpiRaw {
-  uint32_t al[kWsEpiVecs][4], mv[kWsEpiVecs][4], r0[kWsEpiVecs][4], q0[kWsEpiVecs][4];
+  uint32_t al[kWsEpiVecs][4];
   uint32_t ix[kWsEpiVecs];
   bool ok[kWsEpiVecs];
 };
@@ -166,11 +161,43 @@ __device__ __forceinline__ T raw_get(const uint32_t (&w)[4], int n) {
   }
 }
 template <typename T>
+__device__ __forceinline__ void vload(T (&v)[16 / sizeof(T)], const T* p) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+  } else {
+    const double2 x = *reinterpret_cast<const double2*>(p);
+    v[0] = x.x;
+    v[1] = x.y;
+  }
+}
+template <typename T>
 __device__ __forceinline__ void vstore(T* p, const T (&v)[16 / sizeof(T)]) {
   if constexpr (sizeof(T) == 4)
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
   else
     *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+}
+
+// Stores of a unit's own pixels as raw buffer stores: a lane or unit that
+// must not store is given an offset (or a record count) outside the buffer,
+// which the hardware drops.  So the staging issues the same number of
+// stores on every path, and the compiler's count of memory operations in
+// flight after the epilogue's alpha loads is exact (a branch around the
+// stores would make it wait for them too: loads and stores retire in order).
+typedef unsigned int ws_u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kWsNoStore = 0x80000000u;  // beyond every column (D < 2^28)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ws_rsrc(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ void ws_bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, const T (&v)[16 / sizeof(T)]) {
+  ws_u32x4 w;
+  __builtin_memcpy(&w, v, 16);
+  __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)off, 0, 0);
 }
 
 // The staged region is [-2c, TILE + 2c)^2 around the tile (ConvGeom: SPH =
@@ -219,16 +246,19 @@ struct WsStageMap {
 // region, so a wrap is one compare and add; W a multiple of 4 keeps each
 // vector in one period), and x on the own pixels; ws_stage_finish applies
 // the previous CG update (r' = r - a q, z = M^-1 r', p' = z + b p,
-// x += a p), writes p' to LDS and x, r', p' of the own pixels inside the
-// image to memory, and adds their r'^T z and r'^T r' to rz, rr.
-template <int KS, int TILE, typename T>
+// x += a p), writes p' to the LDS region, r' and M^-1 of the own pixels to
+// sR, sM (TILE x TILE, for the epilogue), x, r', p' of the own pixels inside
+// the image to memory, and adds their r'^T z and r'^T r' to rz, rr.
+// Slots [K0, K1) of a thread's staging loads (the caller issues the own
+// slots and the halo slots at different points of phase 1).
+template <int KS, int TILE, typename T, bool PRE, int K0, int K1>
 __device__ __forceinline__ void ws_stage_load(WsStageRaw& g, const T* __restrict__ P0, const T* __restrict__ R0,
                                               const T* __restrict__ Q0, const T* __restrict__ X,
                                               const float* __restrict__ minv, int H, int W, int tu0, int tv0,
                                               int mt) {
   using M = WsStageMap<KS, TILE, T>;
 #pragma unroll
-  for (int k = 0; k < M::KOWN + M::KHALO; ++k) {
+  for (int k = K0; k < (K1 < M::KOWN + M::KHALO ? K1 : M::KOWN + M::KHALO); ++k) {
     if (!M::exists(mt, k)) continue;
     int i, j;
     M::pos(mt, k, i, j);
@@ -240,7 +270,7 @@ __device__ __forceinline__ void ws_stage_load(WsStageRaw& g, const T* __restrict
     raw_load16(g.p0[k], at(P0, g.ix[k]));
     raw_load16(g.r0[k], at(R0, g.ix[k]));
     raw_load16(g.q0[k], at(Q0, g.ix[k]));
-    if (minv) {
+    if constexpr (PRE) {
       if constexpr (sizeof(T) == 4)
         raw_load16(g.mv[k], at(minv, g.ix[k]));
       else
@@ -252,20 +282,23 @@ __device__ __forceinline__ void ws_stage_load(WsStageRaw& g, const T* __restrict
 
 template <int KS, int TILE, typename T>
 __device__ __forceinline__ void ws_stage_finish(const WsStageRaw& g, T* __restrict__ X, T* __restrict__ P1,
-                                                T* __restrict__ R1, bool precond, T a, T b, int mt, T* sP,
-                                                double& rz, double& rr) {
+                                                T* __restrict__ R1, uint32_t col_bytes, bool precond, bool valid,
+                                                T a, T b, int mt, T* sP, T* sR, T* sM, double& rz, double& rr) {
   using M = WsStageMap<KS, TILE, T>;
   constexpr int N = M::N;
+  const uint32_t nb = valid ? col_bytes : 0u;
+  const __amdgpu_buffer_rsrc_t rX = ws_rsrc(X, nb), rR = ws_rsrc(R1, nb), rP = ws_rsrc(P1, nb);
 #pragma unroll
   for (int k = 0; k < M::KOWN + M::KHALO; ++k) {
     if (!M::exists(mt, k)) continue;
-    const bool own = k < M::KOWN && g.own[k < M::KOWN ? k : 0];
-    T r1[N], p1[N], x1[N];
+    const bool own = valid && k < M::KOWN && g.own[k < M::KOWN ? k : 0];
+    T r1[N], p1[N], x1[N], mv[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const T p0 = raw_get<T>(g.p0[k], n);
       r1[n] = fma(-a, raw_get<T>(g.q0[k], n), raw_get<T>(g.r0[k], n));
-      const T z = precond ? (T)__uint_as_float(g.mv[k][n]) * r1[n] : r1[n];
+      mv[n] = precond ? (T)__uint_as_float(g.mv[k][n]) : T(1);
+      const T z = precond ? mv[n] * r1[n] : r1[n];
       p1[n] = fma(b, p0, z);
       if (k < M::KOWN) {
         x1[n] = fma(a, p0, raw_get<T>(g.x0[k < M::KOWN ? k : 0], n));
@@ -275,28 +308,32 @@ __device__ __forceinline__ void ws_stage_finish(const WsStageRaw& g, T* __restri
         }
       }
     }
+    if (k < M::KOWN) {
+      const uint32_t off = own ? g.ix[k] * (uint32_t)sizeof(T) : kWsNoStore;
+      ws_bstore<T>(rX, off, x1);
+      ws_bstore<T>(rR, off, r1);
+      ws_bstore<T>(rP, off, p1);
+    }
+    if (!valid) continue;
     int i, j;
     M::pos(mt, k, i, j);
     vstore<T>(sP + i * M::G::SPW + j, p1);
-    if (own) {
-      vstore<T>(at(X, g.ix[k]), x1);
-      vstore<T>(at(R1, g.ix[k]), r1);
-      vstore<T>(at(P1, g.ix[k]), p1);
+    if (k < M::KOWN) {
+      const int o = (i - M::c2) * TILE + (j - M::c2);
+      vstore<T>(sR + o, r1);
+      if (precond) vstore<T>(sM + o, mv);
     }
   }
 }
 
 // Epilogue of a unit: q = beta Phi^T t + alpha p' on its own pixels (Phi^T t
 // in sU, p' in the staged region), written to Q1, and gam = p'^T q,
-// del = r'^T M^-1 q, eta = q^T M^-1 q, with r' = r - a q recomputed from the
-// previous iteration's r and q (as the staging formed it; those buffers are
-// not written in this launch, so no ordering against the staging's stores
-// is needed).  Loads (alpha, M^-1, r, q) by ws_epi_load (pixels outside the
-// image read pixel 0 and are not used), the rest by ws_epi_finish.
+// del = r'^T M^-1 q, eta = q^T M^-1 q, with r' and M^-1 as the staging left
+// them in sR, sM.  ws_epi_load issues the alpha loads (pixels outside the
+// image read pixel 0 and are not used), ws_epi_finish does the rest.
 template <int TILE, typename T>
-__device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const T* __restrict__ R0, const T* __restrict__ Q0,
-                                            const float* __restrict__ alpha, const float* __restrict__ minv, int H,
-                                            int W, int tu0, int tv0, int mt) {
+__device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const float* __restrict__ alpha, int H, int W, int tu0,
+                                            int tv0, int mt) {
   constexpr int N = 16 / sizeof(T), VT = TILE / N, NV = TILE * VT, KE = NV / kWsMemory;
   static_assert(NV % kWsMemory == 0 && KE <= kWsEpiVecs, "epilogue vectors per thread");
 #pragma unroll
@@ -306,50 +343,72 @@ __device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const T* __restrict__ R
     const int u = tu0 + i, v = tv0 + j;
     g.ok[k] = u < H && v < W;
     g.ix[k] = g.ok[k] ? (uint32_t)(u * W + v) : 0u;
-    raw_load16(g.r0[k], at(R0, g.ix[k]));
-    raw_load16(g.q0[k], at(Q0, g.ix[k]));
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4)
       raw_load16(g.al[k], at(alpha, g.ix[k]));
-      if (minv) raw_load16(g.mv[k], at(minv, g.ix[k]));
-    } else {
+    else
       raw_load8(g.al[k], at(alpha, g.ix[k]));
-      if (minv) raw_load8(g.mv[k], at(minv, g.ix[k]));
-    }
   }
 }
 
+// q of a thread's epilogue vectors, kept in registers until it is stored
+// (ws_epi_store, in the next phase: a store issued behind the staging loads
+// would wait for them to be accepted)
+struct WsEpiOut {
+  uint32_t q[kWsEpiVecs][4];
+  uint32_t off[kWsEpiVecs];  // byte offset, or kWsNoStore
+};
 template <int KS, int TILE, typename T>
-__device__ __forceinline__ void ws_epi_finish(const WsEpiRaw& g, T* __restrict__ Q1, bool precond, T a, T beta,
-                                              int mt, const T* sP, const T* sU, double& gm, double& dl, double& et) {
+__device__ __forceinline__ void ws_epi_finish(const WsEpiRaw& g, WsEpiOut& out, bool precond, bool valid, T beta,
+                                              int mt, const T* sP, const T* sU, const T* sR, const T* sM,
+                                              double& gm, double& dl, double& et) {
   using G = ConvGeom<KS, TILE>;
   constexpr int c = G::c, N = 16 / sizeof(T), VT = TILE / N, KE = TILE * VT / kWsMemory;
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
-    if (!g.ok[k]) continue;
+    const bool use = valid && g.ok[k];
     const int e = mt + k * kWsMemory;
     const int i = e / VT, j = (e - (e / VT) * VT) * N;
-    const T* ps = sP + (i + 2 * c) * G::SPW + j + 2 * c;
-    const T* ts = sU + i * TILE + j;
-    T q[N];
+    const int o = i * TILE + j;
+    T q[N], pv[N], tv[N], rv[N], mv[N];
+    vload<T>(pv, sP + (i + 2 * c) * G::SPW + j + 2 * c);
+    vload<T>(tv, sU + o);
+    vload<T>(rv, sR + o);
+    if (precond) vload<T>(mv, sM + o);
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-      const T p = ps[n];
-      q[n] = fma(beta, ts[n], (T)__uint_as_float(g.al[k][n]) * p);  // as the per-tile kernel
-      const T r1 = fma(-a, raw_get<T>(g.q0[k], n), raw_get<T>(g.r0[k], n));
+      const T p = pv[n];
+      q[n] = fma(beta, tv[n], (T)__uint_as_float(g.al[k][n]) * p);  // as the per-tile kernel
       const double qd = (double)q[n];
-      const double mq = precond ? (double)__uint_as_float(g.mv[k][n]) * qd : qd;
-      gm += (double)p * qd;
-      dl += (double)r1 * mq;
-      et += qd * mq;
+      const double mq = precond ? (double)mv[n] * qd : qd;
+      if (use) {
+        gm += (double)p * qd;
+        dl += (double)rv[n] * mq;
+        et += qd * mq;
+      }
     }
-    vstore<T>(at(Q1, g.ix[k]), q);
+    __builtin_memcpy(out.q[k], q, 16);
+    out.off[k] = use ? g.ix[k] * (uint32_t)sizeof(T) : kWsNoStore;
+  }
+}
+template <int TILE, typename T>
+__device__ __forceinline__ void ws_epi_store(const WsEpiOut& out, T* __restrict__ Q1, uint32_t col_bytes,
+                                             bool valid) {
+  constexpr int KE = TILE * (TILE * sizeof(T) / 16) / kWsMemory;
+  const __amdgpu_buffer_rsrc_t rQ = ws_rsrc(Q1, valid ? col_bytes : 0u);
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    ws_u32x4 w;
+    __builtin_memcpy(&w, out.q[k], 16);
+    __builtin_amdgcn_raw_buffer_store_b128(w, rQ, (int)out.off[k], 0, 0);
   }
 }
 
-// One wave (all 64 lanes): the unit's five sums (wave partials in LDS, summed
-// in wave order) to the column's partial rows; the deposit that completes the
-// column sums its rows (lane l: rows l, l + 64, ... in order, then a fixed
-// butterfly) into colsum and re-arms the column's counter.
+// A unit's deposit, by compute wave 0 at the end of a phase 2: its five
+// sums (wave partials in LDS, summed in wave order) to its row of the
+// column's partials.  The columns are summed once, by the launch's last
+// workgroup (ws_column_sums): a column completed inside the loop would fall
+// to the workgroup that happens to arrive last, which then runs later still
+// and is last again for the next column.
 __device__ __forceinline__ void ws_deposit(const WsUnit& un, const double* stg, const double* epi,
                                            const ConvReduce& red, int64_t nblk_alloc, int lane) {
   double v = 0.0;
@@ -359,42 +418,66 @@ __device__ __forceinline__ void ws_deposit(const WsUnit& un, const double* stg, 
     for (int w = 0; w < kWsMemWaves; ++w) v += epi[w * 3 + lane - 2];
   }
   double* pc = red.parts + (int64_t)un.col * tree_rows(nblk_alloc) * 5;
-  uint32_t* cnt = red.cnts + (int64_t)un.col * tree_counters(nblk_alloc) * kCounterStride;
   if (lane < 5) store_agent(&pc[(int64_t)un.blk * 5 + lane], v);
-  __builtin_amdgcn_s_waitcnt(0);
-  uint32_t prev = 0;
-  if (lane == 0) prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  prev = __shfl(prev, 0, 64);
-  if (prev != (uint32_t)(un.nblk - 1)) return;
-  const int n5 = un.nblk * 5;
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
-  constexpr int CH = 8;
-  for (int f0 = 0; f0 < n5; f0 += 64 * CH) {
-    double x[CH];
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-      const int f = f0 + lane + 64 * k;
-      x[k] = f < n5 ? load_agent(&pc[f]) : 0.0;
+}
+
+// The launch's column totals, by its last workgroup: tot[v * nc + col] =
+// sum over the column's rows of value v, in a fixed order (rows in chunks
+// of RC summed in row order, one chunk per thread, then the chunks in
+// order), so the result does not depend on timing.  cp: LDS scratch of
+// at least ws_sum_items(...) doubles.
+__device__ __forceinline__ int ws_sum_chunks(int nblk, int rc) { return (nblk + rc - 1) / rc; }
+// rows per chunk: 32, or more where the chunk partials would not fit in cap
+// doubles of LDS
+__device__ __forceinline__ int ws_sum_rows(int K, int nt, int ntiles, int cap) {
+  int rc = 32;
+  while (5 * (K * ws_sum_chunks(ntiles, rc) + nt * ws_sum_chunks(4 * ntiles, rc)) > cap) rc *= 2;
+  return rc;
+}
+__device__ __forceinline__ void ws_column_sums(const ConvReduce& red, int64_t nblk_alloc, int K, int nt,
+                                               int ntiles, int rc, double* cp, double* tot) {
+  const int nc = K + nt;
+  const int chF = ws_sum_chunks(ntiles, rc), chD = ws_sum_chunks(4 * ntiles, rc);
+  const int nF = K * 5 * chF, nItems = nF + nt * 5 * chD;
+  const int64_t rows = tree_rows(nblk_alloc);
+  for (int i = threadIdx.x; i < nItems; i += blockDim.x) {
+    int col, v, c, nblk;
+    if (i < nF) {
+      col = i / (5 * chF);
+      const int r = i - col * 5 * chF;
+      v = r / chF;
+      c = r - v * chF;
+      nblk = ntiles;
+    } else {
+      const int j = i - nF;
+      const int m = j / (5 * chD), r = j - m * 5 * chD;
+      col = K + m;
+      v = r / chD;
+      c = r - v * chD;
+      nblk = 4 * ntiles;
     }
+    const double* pc = red.parts + (int64_t)col * rows * 5;
+    const int r0 = c * rc, r1 = r0 + rc < nblk ? r0 + rc : nblk;
+    double t = 0.0;
+    for (int q = r0; q < r1; q += 32) {  // 32 loads in flight at once
+      double x[32];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) {
-      const int f = f0 + lane + 64 * k;
-      const int r = f - (f / 5) * 5;
-      t0 += r == 0 ? x[k] : 0.0;
-      t1 += r == 1 ? x[k] : 0.0;
-      t2 += r == 2 ? x[k] : 0.0;
-      t3 += r == 3 ? x[k] : 0.0;
-      t4 += r == 4 ? x[k] : 0.0;
+      for (int k = 0; k < 32; ++k) x[k] = q + k < r1 ? load_agent(&pc[(int64_t)(q + k) * 5 + v]) : 0.0;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) t += x[k];
     }
+    cp[i] = t;
   }
-  t0 = wave_sum(t0);
-  t1 = wave_sum(t1);
-  t2 = wave_sum(t2);
-  t3 = wave_sum(t3);
-  t4 = wave_sum(t4);
-  const double mine = lane == 0 ? t0 : lane == 1 ? t1 : lane == 2 ? t2 : lane == 3 ? t3 : t4;
-  if (lane < 5) store_agent(&red.colsum[un.col * 5 + lane], mine);
-  if (lane == 0) store_agent(cnt, 0u);
+  __syncthreads();
+  for (int e = threadIdx.x; e < nc * 5; e += blockDim.x) {
+    const int col = e / 5, v = e - (e / 5) * 5;
+    const int ch = col < K ? chF : chD;
+    const int base = col < K ? (col * 5 + v) * chF : nF + ((col - K) * 5 + v) * chD;
+    double t = 0.0;
+    for (int c = 0; c < ch; ++c) t += cp[base + c];
+    tot[v * nc + col] = t;
+  }
+  __syncthreads();
 }
 
 }  // namespace
@@ -411,9 +494,10 @@ struct WsCols {
 };
 
 struct WsLds {
-  unsigned char *sP, *sT, *sU;  // 3 staged regions, stage-1 output, 2 stage-2 outputs
+  unsigned char *sP, *sT, *sU, *sR, *sM;  // 2 staged regions, stage-1 and stage-2 outputs, 2 r', 2 M^-1
   const float* tapsF;
   const double* tapsD;
+  const double *a, *b;  // the step scalars a and b of every column
   double (*red_stage)[kWsMemWaves * 2];
   double* red_epi;
 };
@@ -426,32 +510,39 @@ struct WsGrid {
 };
 
 // Steps of a loop over n units of one kind (the workgroup's units i0 ..
-// i0 + n - 1): s = -1 .. n + 1, two barriers each.  In step s:
-//   phase 1  compute: stage 1 of unit s (sP[s % 3] -> sT)
-//            memory:  the loads of unit s + 1's staging and unit s - 1's
-//                     epilogue issued
-//   phase 2  compute: stage 2 of unit s (sT -> sU[s % 2])
-//            memory:  unit s - 2's sums deposited (wave 0), unit s + 1 staged
-//                     (the previous CG update applied, p' written to
-//                     sP[(s + 1) % 3]) and unit s - 1's epilogue
-//                     (sP[(s - 1) % 3], sU[(s - 1) % 2]), from those loads
-// So both load blocks are in flight across a barrier while the compute waves
-// run stage 1.  Nothing this launch writes is read back by it, so no wait for
-// stores is needed but the deposit's own.
+// i0 + n - 1): s = -1 .. n, two barriers each.  In step s:
+//   phase 1  compute: stage 1 of unit s (sP[s % 2] -> sT)
+//            memory:  the staging loads of unit s + 1 issued; the epilogue
+//                     of unit s - 1 (sU, sP[(s - 1) % 2], sR and sM
+//                     [(s - 1) % 2], the alpha loads issued in the last
+//                     phase 2)
+//   phase 2  compute: stage 2 of unit s (sT -> sU); wave 0 stores the sums
+//                     of unit s - 1
+//            memory:  the alpha loads of unit s's epilogue issued; unit
+//                     s + 1 staged from the phase-1 loads (the previous CG
+//                     update applied, p' written to sP[(s + 1) % 2], r' and
+//                     M^-1 to sR and sM [(s + 1) % 2])
+// so the staging loads are in flight through stage 1 (the longer stencil
+// stage) and the alpha loads through stage 2, and every LDS buffer is
+// rewritten only a barrier after its last reader.  The memory waves never
+// wait for a store: nothing this launch writes to memory is read back by
+// it but the deposits, which the compute wave orders.
 
 // Compute waves: the stencil stages of unit s.
 template <int KS, int TILE, typename T>
-__device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L, int i0, int n, int tid) {
+__device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L, const ConvReduce& red,
+                                                int64_t nblk_alloc, int i0, int n, int tid) {
   using WG = WsGeom<KS>;
   using G = ConvGeom<KS, TILE>;
-  for (int s = -1; s <= n + 1; ++s) {
+  T* const uC = reinterpret_cast<T*>(L.sU);
+  T* const sT = reinterpret_cast<T*>(L.sT);
+  const bool dep = tid < 64;  // compute wave 0 deposits the units' sums
+  for (int s = -1; s <= n; ++s) {
     int ct = tid;  // laundered per step, as in the memory loop
     asm volatile("" : "+v"(ct));
     const WsUnit uc = gr.unit(s, i0, n);
     const bool work = uc.exists && uc.inside;
-    const T* const bC = reinterpret_cast<const T*>(L.sP + ((s + 3) % 3) * WG::SP);
-    T* const uC = reinterpret_cast<T*>(L.sU + ((s + 2) & 1) * WG::SU);
-    T* const sT = reinterpret_cast<T*>(L.sT);
+    const T* const bC = reinterpret_cast<const T*>(L.sP + ((s + 2) & 1) * WG::SP);
     if (work) {
       if constexpr (sizeof(T) == 4 && Stage1W6<KS, TILE>::ok)
         conv_stage1_w6<KS, TILE>(TapsReg<KS>(L.tapsF), bC, sT, ct, kWsCompute);
@@ -477,83 +568,107 @@ __device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L
           vstore<T>(dst + r * TILE + 2, *reinterpret_cast<const T(*)[2]>(row + 2));
       }
     }
+    // unit s - 1's sums: its staging sums from two steps back, its epilogue
+    // sums from this step's phase 1
+    const WsUnit ud = gr.unit(s - 1, i0, n);
+    if (dep && ud.exists) ws_deposit(ud, L.red_stage[(s + 3) & 3], L.red_epi, red, nblk_alloc, ct);
     ws_barrier();
   }
 }
 
 // Memory waves.
-template <int KS, int TILE, typename T>
+template <int KS, int TILE, typename T, bool PRE>
 __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L, const WsCols<T>& C,
                                                const float* __restrict__ alpha, const float* __restrict__ minv,
-                                               double beta, const CgScalars* st, const ConvReduce& red,
-                                               int64_t nblk_alloc, int i0, int n, int tid) {
+                                               double beta, int i0, int n, int tid) {
   using WG = WsGeom<KS>;
-  const bool precond = minv != nullptr;
+  constexpr bool precond = PRE;  // a compile-time choice, so every path issues the same loads
   const int mw = (tid - kWsCompute) >> 6, lane = tid & 63;
+  const T* const sU = reinterpret_cast<const T*>(L.sU);
+  const uint32_t col_bytes = (uint32_t)(gr.H * gr.W) * (uint32_t)sizeof(T);
   WsStageRaw gs;
   WsEpiRaw ge;
-  for (int s = -1; s <= n + 1; ++s) {
+  WsEpiOut eo;
+  // Every load block and every store is issued on every path, a missing
+  // unit's loads from the first tile of the kind's first column (and then not
+  // used) and its stores dropped (ws_bstore): the compiler then counts the
+  // memory operations in flight exactly, and each consumer waits for its own
+  // block only, never for a block or a store issued after it.
+  using M = WsStageMap<KS, TILE, T>;
+  auto stage_load_own = [&](const WsUnit& u, int mt) {
+    const bool v = u.exists && u.inside;
+    const int64_t o = v ? C.off(u.col) : 0;
+    ws_stage_load<KS, TILE, T, PRE, 0, M::KOWN>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H, gr.W,
+                                                v ? u.tu0 : 0, v ? u.tv0 : 0, mt);
+  };
+  auto stage_load_halo = [&](const WsUnit& u, int mt) {
+    const bool v = u.exists && u.inside;
+    const int64_t o = v ? C.off(u.col) : 0;
+    ws_stage_load<KS, TILE, T, PRE, M::KOWN, kWsStageVecs>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H,
+                                                           gr.W, v ? u.tu0 : 0, v ? u.tv0 : 0, mt);
+  };
+  for (int s = -1; s <= n; ++s) {
     // the thread index laundered once per step: the positions derived from
     // it are recomputed each step instead of being hoisted out of the loop
     // (kept live across it they would spill, and a reload from scratch waits
     // for every load in flight)
     int mt = tid - kWsCompute;
     asm volatile("" : "+v"(mt));
-    const WsUnit un = gr.unit(s + 1, i0, n);  // staged
     const WsUnit ue = gr.unit(s - 1, i0, n);  // epilogue
-    const WsUnit ud = gr.unit(s - 2, i0, n);  // deposited
+    const WsUnit ua = gr.unit(s, i0, n);      // alpha loads for the next epilogue
+    const WsUnit un = gr.unit(s + 1, i0, n);  // staged
+    const bool ev = ue.exists && ue.inside, av = ua.exists && ua.inside, sv = un.exists && un.inside;
+    const int col = sv ? un.col : C.col0;
     // ---------------- phase 1
-    if (un.exists && un.inside) {
-      const int64_t o = C.off(un.col);
-      ws_stage_load<KS, TILE, T>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H, gr.W, un.tu0, un.tv0, mt);
-    }
-    if (ue.exists && ue.inside) {
-      const int64_t o = C.off(ue.col);
-      ws_epi_load<TILE, T>(ge, C.R0 + o, C.Q0 + o, alpha, minv, gr.H, gr.W, ue.tu0, ue.tv0, mt);
-    }
-    ws_barrier();  // the loads just issued stay in flight across it
-    // ---------------- phase 2
-    // wave 0 deposits unit s - 2 first: its wait for the deposit's stores then
-    // covers only the loads this phase consumes anyway
-    if (mw == 0 && ud.exists)
-      ws_deposit(ud, L.red_stage[(s + 2) & 3], L.red_epi + (s & 1) * kWsMemWaves * 3, red, nblk_alloc, lane);
-    if (un.exists) {
-      double rz = 0.0, rr = 0.0;
-      if (un.inside) {
-        const int64_t o = C.off(un.col);
-        ws_stage_finish<KS, TILE, T>(gs, C.X + o, C.P1 + o, C.R1 + o, precond, (T)st->a[un.col], (T)st->b[un.col],
-                                     mt, reinterpret_cast<T*>(L.sP + ((s + 4) % 3) * WG::SP), rz, rr);
-      }
-      rz = wave_sum(rz);
-      rr = wave_sum(rr);
-      if (lane == 0) {
-        L.red_stage[(s + 5) & 3][mw * 2 + 0] = rz;
-        L.red_stage[(s + 5) & 3][mw * 2 + 1] = rr;
-      }
-    }
-    if (ue.exists) {
+    // the staging loads of the own pixels first, then the epilogue (it
+    // waits only for its alpha block, issued before them), then those of
+    // the halo: the loads are in flight through most of stage 1, and the
+    // epilogue's work fills the time their issue would stall
+    stage_load_own(un, mt);
+    {
       double gm = 0.0, dl = 0.0, et = 0.0;
-      if (ue.inside) {
-        const int64_t o = C.off(ue.col);
-        ws_epi_finish<KS, TILE, T>(ge, C.Q1 + o, precond, (T)st->a[ue.col], (T)beta, mt,
-                                   reinterpret_cast<const T*>(L.sP + ((s + 2) % 3) * WG::SP),
-                                   reinterpret_cast<const T*>(L.sU + ((s + 1) & 1) * WG::SU), gm, dl, et);
-      }
-      gm = wave_sum(gm);
-      dl = wave_sum(dl);
-      et = wave_sum(et);
-      if (lane == 0) {
-        double* re = L.red_epi + ((s + 1) & 1) * kWsMemWaves * 3;
-        re[mw * 3 + 0] = gm;
-        re[mw * 3 + 1] = dl;
-        re[mw * 3 + 2] = et;
+      const int b = (s + 1) & 1;
+      ws_epi_finish<KS, TILE, T>(ge, eo, precond, ev, (T)beta, mt,
+                                 reinterpret_cast<const T*>(L.sP + b * WG::SP), sU,
+                                 reinterpret_cast<const T*>(L.sR + b * WG::SU),
+                                 reinterpret_cast<const T*>(L.sM + b * WG::SU), gm, dl, et);
+      stage_load_halo(un, mt);
+      if (ue.exists) {
+        gm = wave_sum(gm);
+        dl = wave_sum(dl);
+        et = wave_sum(et);
+        if (lane == 0) {
+          L.red_epi[mw * 3 + 0] = gm;
+          L.red_epi[mw * 3 + 1] = dl;
+          L.red_epi[mw * 3 + 2] = et;
+        }
       }
     }
-    ws_barrier();
+    ws_barrier();  // the staging loads stay in flight across it
+    // ---------------- phase 2
+    ws_epi_load<TILE, T>(ge, alpha, gr.H, gr.W, av ? ua.tu0 : 0, av ? ua.tv0 : 0, mt);
+    ws_epi_store<TILE, T>(eo, C.Q1 + (ev ? C.off(ue.col) : 0), col_bytes, ev);
+    {
+      double rz = 0.0, rr = 0.0;
+      const int64_t o = sv ? C.off(un.col) : 0;
+      const int b = (s + 1) & 1;
+      ws_stage_finish<KS, TILE, T>(gs, C.X + o, C.P1 + o, C.R1 + o, col_bytes, precond, sv, (T)L.a[col], (T)L.b[col], mt,
+                                   reinterpret_cast<T*>(L.sP + b * WG::SP), reinterpret_cast<T*>(L.sR + b * WG::SU),
+                                   reinterpret_cast<T*>(L.sM + b * WG::SU), rz, rr);
+      if (un.exists) {
+        rz = wave_sum(rz);
+        rr = wave_sum(rr);
+        if (lane == 0) {
+          L.red_stage[(s + 5) & 3][mw * 2 + 0] = rz;
+          L.red_stage[(s + 5) & 3][mw * 2 + 1] = rr;
+        }
+      }
+    }
+    ws_barrier();  // the alpha loads stay in flight across it
   }
 }
 
-template <int KS>
+template <int KS, bool PRE>
 __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     const float* __restrict__ taps, int H, int W, int64_t ldD, int K, int nt, int tilesX, int ntiles,
     const float* __restrict__ P0, const float* __restrict__ R0, const float* __restrict__ Q0, float* __restrict__ X,
@@ -570,16 +685,26 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
   __shared__ double sTapsD[KS * KS];
   __shared__ float sTapsF[KS * KS];
   __shared__ double red_stage[4][kWsMemWaves * 2];
-  __shared__ double red_epi[2 * kWsMemWaves * 3];
+  __shared__ double red_epi[kWsMemWaves * 3];
+  // the step scalars are read once: they do not change until the launch's
+  // last workgroup finishes (and a scalar load in the loop would share its
+  // wait counter with the LDS reads, at memory latency)
+  __shared__ double sA[kMaxCols], sB[kMaxCols];
   const int tid = threadIdx.x;
   if (tid < KS * KS) {
     sTapsD[tid] = (double)taps[tid];
     sTapsF[tid] = taps[tid];
   }
+  if (tid < K + nt) {
+    sA[tid] = st->a[tid];
+    sB[tid] = st->b[tid];
+  }
   __syncthreads();
   unsigned char* const sPb = smem;
-  unsigned char* const sTb = smem + 3 * WG::SP;
+  unsigned char* const sTb = smem + 2 * WG::SP;
   unsigned char* const sUb = sTb + WG::ST;
+  unsigned char* const sRb = sUb + WG::SU;
+  unsigned char* const sMb = sRb + 2 * WG::SU;
   const bool isC = tid < kWsCompute;
   const int G = (int)gridDim.x;
   const int wgi = (int)blockIdx.x;
@@ -594,27 +719,24 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
   const int N64 = slot < U64 ? (U64 - 1 - slot) / G + 1 : 0;
   const int NF = N - N64;
   const WsGrid gr{U, ntiles, tilesX, K, nt, H, W, G, slot};
-  const WsLds L{sPb, sTb, sUb, sTapsF, sTapsD, red_stage, red_epi};
+  const WsLds L{sPb, sTb, sUb, sRb, sMb, sTapsF, sTapsD, sA, sB, red_stage, red_epi};
   if (isC) {
-    ws_compute_loop<KS, kConvTile / 2, double>(gr, L, 0, N64, tid);
-    ws_compute_loop<KS, kConvTile, float>(gr, L, N64, NF, tid);
+    ws_compute_loop<KS, kConvTile / 2, double>(gr, L, red, nblk_alloc, 0, N64, tid);
+    ws_compute_loop<KS, kConvTile, float>(gr, L, red, nblk_alloc, N64, NF, tid);
   } else {
     const WsCols<double> cd{pm0, rm0, qm0, xm, pm1, rm1, qm1, K, ldD};
     const WsCols<float> cf{P0, R0, Q0, X, P1, R1, Q1, 0, ldD};
-    ws_memory_loop<KS, kConvTile / 2, double>(gr, L, cd, alpha, minv, beta, st, red, nblk_alloc, 0, N64, tid);
-    ws_memory_loop<KS, kConvTile, float>(gr, L, cf, alpha, minv, beta, st, red, nblk_alloc, N64, NF, tid);
+    ws_memory_loop<KS, kConvTile / 2, double, PRE>(gr, L, cd, alpha, minv, beta, 0, N64, tid);
+    ws_memory_loop<KS, kConvTile, float, PRE>(gr, L, cf, alpha, minv, beta, N64, NF, tid);
   }
-  // the last workgroup to finish takes the step's scalars from the column totals
+  // the last workgroup to finish sums the columns and takes the step's
+  // scalars from the totals
   __shared__ double tot[5 * kMaxCols];
   if (!last_block_ticket(red.cnt_cols, (uint32_t)G)) return;
-  const int nc = K + nt;
-  for (int e = tid; e < nc * 5; e += kWsThreads) {
-    const int cc = e / 5, v = e - (e / 5) * 5;
-    tot[v * nc + cc] = load_agent(&red.colsum[e]);
-  }
   if (tid == 0) store_agent(red.cnt_cols, 0u);
-  __syncthreads();
-  finish_fused(st, tot, nc, ctl);
+  ws_column_sums(red, nblk_alloc, K, nt, ntiles, ws_sum_rows(K, nt, ntiles, (int)(WG::BYTES / sizeof(double))),
+                 reinterpret_cast<double*>(smem), tot);
+  finish_fused(st, tot, K + nt, ctl);
 }
 
 bool conv_ws_ok(const ConvDims& cd) {
@@ -640,13 +762,18 @@ hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const 
   if (!conv_ws_ok(cd) || grid < 1) return hipErrorInvalidValue;
   const int ntiles = cd.tilesX * cd.tilesY;
   const int64_t nblk_alloc = conv_pass_blocks(cd);
-#define COFEM_WS_CASE(KS)                                                                                          \
-  case KS:                                                                                                         \
-    hipLaunchKernelGGL((k_conv_ws<KS>), dim3((unsigned)grid), dim3(kWsThreads), 0, s, taps, cd.H, cd.W, cd.ldD,    \
-                       cd.K, cd.nt, cd.tilesX, ntiles, static_cast<const float*>(s0.P),                             \
-                       static_cast<const float*>(s0.R), static_cast<const float*>(s0.Q), static_cast<float*>(X),    \
-                       static_cast<float*>(s1.P), static_cast<float*>(s1.R), static_cast<float*>(s1.Q), s0.pm,      \
-                       s0.rm, s0.qm, xm, s1.pm, s1.rm, s1.qm, alpha, beta, minv, red, nblk_alloc, st);              \
+#define COFEM_WS_LAUNCH(KS, PRE)                                                                                   \
+  hipLaunchKernelGGL((k_conv_ws<KS, PRE>), dim3((unsigned)grid), dim3(kWsThreads), 0, s, taps, cd.H, cd.W, cd.ldD,  \
+                     cd.K, cd.nt, cd.tilesX, ntiles, static_cast<const float*>(s0.P),                               \
+                     static_cast<const float*>(s0.R), static_cast<const float*>(s0.Q), static_cast<float*>(X),      \
+                     static_cast<float*>(s1.P), static_cast<float*>(s1.R), static_cast<float*>(s1.Q), s0.pm, s0.rm, \
+                     s0.qm, xm, s1.pm, s1.rm, s1.qm, alpha, beta, minv, red, nblk_alloc, st)
+#define COFEM_WS_CASE(KS)      \
+  case KS:                     \
+    if (minv)                  \
+      COFEM_WS_LAUNCH(KS, true);  \
+    else                       \
+      COFEM_WS_LAUNCH(KS, false); \
     break;
   switch (cd.ks) {
     COFEM_WS_CASE(1)
@@ -656,6 +783,7 @@ hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const 
       return hipErrorInvalidValue;
   }
 #undef COFEM_WS_CASE
+#undef COFEM_WS_LAUNCH
   return hipGetLastError();
 }
 
