@@ -520,9 +520,10 @@ cofem_status cofem_get_kernel_timing(cofem_ctx* ctx, double* ms_total, int64_t* 
 /*
  * The name of the kernel that the COFEM_KT_PASS1 or COFEM_KT_PASS2 timing
  * slot times for this context (its kind, precision and problem shape decide
- * it: the convolution dictionary's fused iteration runs as k_conv_ws, the
- * persistent warp-specialised form, once every workgroup of one per compute
- * unit gets four or more tiles, else as the per-tile k_conv_fused; the
+ * it: the convolution dictionary's fused iteration and operator pass run as
+ * k_conv_ws, the persistent warp-specialised form, once every workgroup of
+ * one per compute unit gets four or more tiles, else as the per-tile
+ * k_conv_fused and k_conv_pass; the
  * environment variable COFEM_CONV_KERNEL=tile|ws|ws:<workgroups>, read by
  * cofem_init, overrides that choice), or NULL for a null context or another
  * slot.  A static string; for measurement and profiling tools.

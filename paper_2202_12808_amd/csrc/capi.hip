@@ -2027,8 +2027,8 @@ const char* cofem_kernel_name(const cofem_ctx* ctx, int32_t slot) {
     return p1 ? "k_dense_pass1" : "k_dense_pass2";
   }
   if (ctx->kind == COFEM_DCT_MASK) return p1 ? "k_dct_rows_in" : "k_dct_mid";
-  if (!p1) return "k_conv_pass";
-  return ctx->cd.ws_grid > 0 ? "k_conv_ws" : "k_conv_fused";
+  if (ctx->cd.ws_grid > 0) return "k_conv_ws";
+  return p1 ? "k_conv_fused" : "k_conv_pass";
 }
 
 cofem_status cofem_batch_plan(cofem_ctx* ctx, int32_t* target_wgs, float* candidate_ms, int32_t* splits1,

@@ -758,12 +758,16 @@ struct ConvState {
 hipError_t conv_fused(const ConvDims& cd, const float* taps, const ConvState& s0, const ConvState& s1, void* X,
                       double* xm, const float* alpha, double beta, const float* minv, const ConvReduce& red,
                       CgScalars* st, hipStream_t s);
-// The persistent warp-specialised form of conv_fused (float probe columns):
-// whether the problem's shape admits it, and the launch on `grid` workgroups.
+// The persistent warp-specialised forms of conv_fused and conv_pass (float
+// probe columns): whether the problem's shape admits them, and the launches
+// on `grid` workgroups.
 bool conv_ws_ok(const ConvDims& cd);
 hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const ConvState& s0, const ConvState& s1,
                          void* X, double* xm, const float* alpha, double beta, const float* minv,
                          const ConvReduce& red, CgScalars* st, hipStream_t s);
+hipError_t conv_pass_ws(const ConvDims& cd, int grid, const float* taps, const void* P, const double* pm,
+                        const void* R, const double* rm, const float* alpha, double beta, void* Q, double* qm,
+                        const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s, const float* minv);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,

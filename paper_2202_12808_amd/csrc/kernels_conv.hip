@@ -487,6 +487,7 @@ hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,
                      const float* minv) {
+  if (cd.ws_grid > 0) return conv_pass_ws(cd, cd.ws_grid, taps, P, pm, R, rm, alpha, beta, Q, qm, red, st, apply_only, s, minv);
   if (cd.fp64)
     return launch_conv_pass<double>(cd, taps, P, pm, R, rm, alpha, beta, minv, Q, qm, red, st, apply_only, s);
   return launch_conv_pass<float>(cd, taps, P, pm, R, rm, alpha, beta, minv, Q, qm, red, st, apply_only, s);

@@ -32,6 +32,14 @@ namespace cofem {
 
 namespace {
 
+// What a launch computes (a template parameter):
+//   kWsFused  the previous CG update folded into the operator pass (one CG
+//             iteration after a solve's first);
+//   kWsPass   the operator pass on p with the step's dots gam = p^T q,
+//             del = r^T M^-1 q, eta = q^T M^-1 q (a solve's first iteration);
+//   kWsApply  q = A p alone (the warm start's A X0, the true residual's A X).
+constexpr int kWsFused = 0, kWsPass = 1, kWsApply = 2;
+
 constexpr int kWsCompute = 256;  // compute threads (waves 0-3)
 constexpr int kWsMemory = 512;   // memory threads (waves 4-11)
 constexpr int kWsThreads = kWsCompute + kWsMemory;
@@ -251,7 +259,7 @@ struct WsStageMap {
 // the image to memory, and adds their r'^T z and r'^T r' to rz, rr.
 // Slots [K0, K1) of a thread's staging loads (the caller issues the own
 // slots and the halo slots at different points of phase 1).
-template <int KS, int TILE, typename T, bool PRE, int K0, int K1>
+template <int KS, int TILE, typename T, bool PRE, int MD, int K0, int K1>
 __device__ __forceinline__ void ws_stage_load(WsStageRaw& g, const T* __restrict__ P0, const T* __restrict__ R0,
                                               const T* __restrict__ Q0, const T* __restrict__ X,
                                               const float* __restrict__ minv, int H, int W, int tu0, int tv0,
@@ -268,19 +276,29 @@ __device__ __forceinline__ void ws_stage_load(WsStageRaw& g, const T* __restrict
     v = v < 0 ? v + W : (v >= W ? v - W : v);
     g.ix[k] = (uint32_t)(u * W + v);
     raw_load16(g.p0[k], at(P0, g.ix[k]));
-    raw_load16(g.r0[k], at(R0, g.ix[k]));
-    raw_load16(g.q0[k], at(Q0, g.ix[k]));
+    // the fused iteration needs r, q, M^-1 over the region and x on the own
+    // pixels; the pass r and M^-1 on the own pixels (for its dots).  (k is a
+    // constant once the loop is unrolled, so these tests are not branches.)
+    const bool rm = MD == kWsFused || (MD == kWsPass && k < M::KOWN);
+    if (rm) raw_load16(g.r0[k], at(R0, g.ix[k]));
+    if constexpr (MD == kWsFused) raw_load16(g.q0[k], at(Q0, g.ix[k]));
     if constexpr (PRE) {
-      if constexpr (sizeof(T) == 4)
-        raw_load16(g.mv[k], at(minv, g.ix[k]));
-      else
-        raw_load8(g.mv[k], at(minv, g.ix[k]));
+      if (rm) {
+        if constexpr (sizeof(T) == 4)
+          raw_load16(g.mv[k], at(minv, g.ix[k]));
+        else
+          raw_load8(g.mv[k], at(minv, g.ix[k]));
+      }
     }
-    if (k < M::KOWN) raw_load16(g.x0[k < M::KOWN ? k : 0], at(X, g.ix[k]));
+    if constexpr (MD == kWsFused) {
+      if (k < M::KOWN) raw_load16(g.x0[k < M::KOWN ? k : 0], at(X, g.ix[k]));
+    }
   }
 }
 
-template <int KS, int TILE, typename T>
+// In the pass and apply modes nothing is updated: p' = p (and r' = r on the
+// own pixels, for the pass's dots), and nothing is written to memory.
+template <int KS, int TILE, typename T, int MD>
 __device__ __forceinline__ void ws_stage_finish(const WsStageRaw& g, T* __restrict__ X, T* __restrict__ P1,
                                                 T* __restrict__ R1, uint32_t col_bytes, bool precond, bool valid,
                                                 T a, T b, int mt, T* sP, T* sR, T* sM, double& rz, double& rr) {
@@ -296,29 +314,39 @@ __device__ __forceinline__ void ws_stage_finish(const WsStageRaw& g, T* __restri
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const T p0 = raw_get<T>(g.p0[k], n);
-      r1[n] = fma(-a, raw_get<T>(g.q0[k], n), raw_get<T>(g.r0[k], n));
-      mv[n] = precond ? (T)__uint_as_float(g.mv[k][n]) : T(1);
-      const T z = precond ? mv[n] * r1[n] : r1[n];
-      p1[n] = fma(b, p0, z);
-      if (k < M::KOWN) {
-        x1[n] = fma(a, p0, raw_get<T>(g.x0[k < M::KOWN ? k : 0], n));
-        if (own) {
-          rz += (double)r1[n] * (double)z;
-          rr += (double)r1[n] * (double)r1[n];
+      if constexpr (MD == kWsFused) {
+        r1[n] = fma(-a, raw_get<T>(g.q0[k], n), raw_get<T>(g.r0[k], n));
+        mv[n] = precond ? (T)__uint_as_float(g.mv[k][n]) : T(1);
+        const T z = precond ? mv[n] * r1[n] : r1[n];
+        p1[n] = fma(b, p0, z);
+        if (k < M::KOWN) {
+          x1[n] = fma(a, p0, raw_get<T>(g.x0[k < M::KOWN ? k : 0], n));
+          if (own) {
+            rz += (double)r1[n] * (double)z;
+            rr += (double)r1[n] * (double)r1[n];
+          }
+        }
+      } else {
+        p1[n] = p0;
+        if (MD == kWsPass && k < M::KOWN) {
+          r1[n] = raw_get<T>(g.r0[k], n);
+          mv[n] = precond ? (T)__uint_as_float(g.mv[k][n]) : T(1);
         }
       }
     }
-    if (k < M::KOWN) {
-      const uint32_t off = own ? g.ix[k] * (uint32_t)sizeof(T) : kWsNoStore;
-      ws_bstore<T>(rX, off, x1);
-      ws_bstore<T>(rR, off, r1);
-      ws_bstore<T>(rP, off, p1);
+    if constexpr (MD == kWsFused) {
+      if (k < M::KOWN) {
+        const uint32_t off = own ? g.ix[k] * (uint32_t)sizeof(T) : kWsNoStore;
+        ws_bstore<T>(rX, off, x1);
+        ws_bstore<T>(rR, off, r1);
+        ws_bstore<T>(rP, off, p1);
+      }
     }
     if (!valid) continue;
     int i, j;
     M::pos(mt, k, i, j);
     vstore<T>(sP + i * M::G::SPW + j, p1);
-    if (k < M::KOWN) {
+    if (MD != kWsApply && k < M::KOWN) {
       const int o = (i - M::c2) * TILE + (j - M::c2);
       vstore<T>(sR + o, r1);
       if (precond) vstore<T>(sM + o, mv);
@@ -357,7 +385,7 @@ struct WsEpiOut {
   uint32_t q[kWsEpiVecs][4];
   uint32_t off[kWsEpiVecs];  // byte offset, or kWsNoStore
 };
-template <int KS, int TILE, typename T>
+template <int KS, int TILE, typename T, int MD>
 __device__ __forceinline__ void ws_epi_finish(const WsEpiRaw& g, WsEpiOut& out, bool precond, bool valid, T beta,
                                               int mt, const T* sP, const T* sU, const T* sR, const T* sM,
                                               double& gm, double& dl, double& et) {
@@ -372,15 +400,17 @@ __device__ __forceinline__ void ws_epi_finish(const WsEpiRaw& g, WsEpiOut& out, 
     T q[N], pv[N], tv[N], rv[N], mv[N];
     vload<T>(pv, sP + (i + 2 * c) * G::SPW + j + 2 * c);
     vload<T>(tv, sU + o);
-    vload<T>(rv, sR + o);
-    if (precond) vload<T>(mv, sM + o);
+    if constexpr (MD != kWsApply) {
+      vload<T>(rv, sR + o);
+      if (precond) vload<T>(mv, sM + o);
+    }
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const T p = pv[n];
       q[n] = fma(beta, tv[n], (T)__uint_as_float(g.al[k][n]) * p);  // as the per-tile kernel
       const double qd = (double)q[n];
       const double mq = precond ? (double)mv[n] * qd : qd;
-      if (use) {
+      if (MD != kWsApply && use) {
         gm += (double)p * qd;
         dl += (double)rv[n] * mq;
         et += qd * mq;
@@ -529,14 +559,14 @@ struct WsGrid {
 // it but the deposits, which the compute wave orders.
 
 // Compute waves: the stencil stages of unit s.
-template <int KS, int TILE, typename T>
+template <int KS, int TILE, typename T, int MD>
 __device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L, const ConvReduce& red,
                                                 int64_t nblk_alloc, int i0, int n, int tid) {
   using WG = WsGeom<KS>;
   using G = ConvGeom<KS, TILE>;
   T* const uC = reinterpret_cast<T*>(L.sU);
   T* const sT = reinterpret_cast<T*>(L.sT);
-  const bool dep = tid < 64;  // compute wave 0 deposits the units' sums
+  const bool dep = MD != kWsApply && tid < 64;  // compute wave 0 deposits the units' sums
   for (int s = -1; s <= n; ++s) {
     int ct = tid;  // laundered per step, as in the memory loop
     asm volatile("" : "+v"(ct));
@@ -577,7 +607,7 @@ __device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L
 }
 
 // Memory waves.
-template <int KS, int TILE, typename T, bool PRE>
+template <int KS, int TILE, typename T, bool PRE, int MD>
 __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L, const WsCols<T>& C,
                                                const float* __restrict__ alpha, const float* __restrict__ minv,
                                                double beta, int i0, int n, int tid) {
@@ -598,13 +628,13 @@ __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L,
   auto stage_load_own = [&](const WsUnit& u, int mt) {
     const bool v = u.exists && u.inside;
     const int64_t o = v ? C.off(u.col) : 0;
-    ws_stage_load<KS, TILE, T, PRE, 0, M::KOWN>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H, gr.W,
+    ws_stage_load<KS, TILE, T, PRE, MD, 0, M::KOWN>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H, gr.W,
                                                 v ? u.tu0 : 0, v ? u.tv0 : 0, mt);
   };
   auto stage_load_halo = [&](const WsUnit& u, int mt) {
     const bool v = u.exists && u.inside;
     const int64_t o = v ? C.off(u.col) : 0;
-    ws_stage_load<KS, TILE, T, PRE, M::KOWN, kWsStageVecs>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H,
+    ws_stage_load<KS, TILE, T, PRE, MD, M::KOWN, kWsStageVecs>(gs, C.P0 + o, C.R0 + o, C.Q0 + o, C.X + o, minv, gr.H,
                                                            gr.W, v ? u.tu0 : 0, v ? u.tv0 : 0, mt);
   };
   for (int s = -1; s <= n; ++s) {
@@ -628,7 +658,7 @@ __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L,
     {
       double gm = 0.0, dl = 0.0, et = 0.0;
       const int b = (s + 1) & 1;
-      ws_epi_finish<KS, TILE, T>(ge, eo, precond, ev, (T)beta, mt,
+      ws_epi_finish<KS, TILE, T, MD>(ge, eo, precond, ev, (T)beta, mt,
                                  reinterpret_cast<const T*>(L.sP + b * WG::SP), sU,
                                  reinterpret_cast<const T*>(L.sR + b * WG::SU),
                                  reinterpret_cast<const T*>(L.sM + b * WG::SU), gm, dl, et);
@@ -652,7 +682,7 @@ __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L,
       double rz = 0.0, rr = 0.0;
       const int64_t o = sv ? C.off(un.col) : 0;
       const int b = (s + 1) & 1;
-      ws_stage_finish<KS, TILE, T>(gs, C.X + o, C.P1 + o, C.R1 + o, col_bytes, precond, sv, (T)L.a[col], (T)L.b[col], mt,
+      ws_stage_finish<KS, TILE, T, MD>(gs, C.X + o, C.P1 + o, C.R1 + o, col_bytes, precond, sv, (T)L.a[col], (T)L.b[col], mt,
                                    reinterpret_cast<T*>(L.sP + b * WG::SP), reinterpret_cast<T*>(L.sR + b * WG::SU),
                                    reinterpret_cast<T*>(L.sM + b * WG::SU), rz, rr);
       if (un.exists) {
@@ -668,7 +698,7 @@ __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L,
   }
 }
 
-template <int KS, bool PRE>
+template <int KS, bool PRE, int MD>
 __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     const float* __restrict__ taps, int H, int W, int64_t ldD, int K, int nt, int tilesX, int ntiles,
     const float* __restrict__ P0, const float* __restrict__ R0, const float* __restrict__ Q0, float* __restrict__ X,
@@ -676,7 +706,7 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     const double* __restrict__ rm0, const double* __restrict__ qm0, double* __restrict__ xm,
     double* __restrict__ pm1, double* __restrict__ rm1, double* __restrict__ qm1, const float* __restrict__ alpha,
     double beta, const float* __restrict__ minv, ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st) {
-  if (st->stop) return;
+  if (MD != kWsApply && st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   using WG = WsGeom<KS>;
   using GF = typename WG::GF;
@@ -721,22 +751,27 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
   const WsGrid gr{U, ntiles, tilesX, K, nt, H, W, G, slot};
   const WsLds L{sPb, sTb, sUb, sRb, sMb, sTapsF, sTapsD, sA, sB, red_stage, red_epi};
   if (isC) {
-    ws_compute_loop<KS, kConvTile / 2, double>(gr, L, red, nblk_alloc, 0, N64, tid);
-    ws_compute_loop<KS, kConvTile, float>(gr, L, red, nblk_alloc, N64, NF, tid);
+    ws_compute_loop<KS, kConvTile / 2, double, MD>(gr, L, red, nblk_alloc, 0, N64, tid);
+    ws_compute_loop<KS, kConvTile, float, MD>(gr, L, red, nblk_alloc, N64, NF, tid);
   } else {
     const WsCols<double> cd{pm0, rm0, qm0, xm, pm1, rm1, qm1, K, ldD};
     const WsCols<float> cf{P0, R0, Q0, X, P1, R1, Q1, 0, ldD};
-    ws_memory_loop<KS, kConvTile / 2, double, PRE>(gr, L, cd, alpha, minv, beta, 0, N64, tid);
-    ws_memory_loop<KS, kConvTile, float, PRE>(gr, L, cf, alpha, minv, beta, N64, NF, tid);
+    ws_memory_loop<KS, kConvTile / 2, double, PRE, MD>(gr, L, cd, alpha, minv, beta, 0, N64, tid);
+    ws_memory_loop<KS, kConvTile, float, PRE, MD>(gr, L, cf, alpha, minv, beta, N64, NF, tid);
   }
-  // the last workgroup to finish sums the columns and takes the step's
-  // scalars from the totals
-  __shared__ double tot[5 * kMaxCols];
-  if (!last_block_ticket(red.cnt_cols, (uint32_t)G)) return;
-  if (tid == 0) store_agent(red.cnt_cols, 0u);
-  ws_column_sums(red, nblk_alloc, K, nt, ntiles, ws_sum_rows(K, nt, ntiles, (int)(WG::BYTES / sizeof(double))),
-                 reinterpret_cast<double*>(smem), tot);
-  finish_fused(st, tot, K + nt, ctl);
+  if constexpr (MD != kWsApply) {
+    // the last workgroup to finish sums the columns and takes the step's
+    // scalars from the totals (gam, del, eta are values 2-4 of a unit's sums)
+    __shared__ double tot[5 * kMaxCols];
+    if (!last_block_ticket(red.cnt_cols, (uint32_t)G)) return;
+    if (tid == 0) store_agent(red.cnt_cols, 0u);
+    ws_column_sums(red, nblk_alloc, K, nt, ntiles, ws_sum_rows(K, nt, ntiles, (int)(WG::BYTES / sizeof(double))),
+                   reinterpret_cast<double*>(smem), tot);
+    if constexpr (MD == kWsFused)
+      finish_fused(st, tot, K + nt, ctl);
+    else
+      finish_step(st, tot + 2 * (K + nt), ctl);
+  }
 }
 
 bool conv_ws_ok(const ConvDims& cd) {
@@ -756,24 +791,29 @@ bool conv_ws_ok(const ConvDims& cd) {
   return cd.H >= need_h && cd.W >= need_w;
 }
 
-hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const ConvState& s0, const ConvState& s1,
-                         void* X, double* xm, const float* alpha, double beta, const float* minv,
-                         const ConvReduce& red, CgScalars* st, hipStream_t s) {
+template <int MD>
+static hipError_t ws_launch(const ConvDims& cd, int grid, const float* taps, const void* P0, const void* R0,
+                            const void* Q0, void* X, void* P1, void* R1, void* Q1, const double* pm0,
+                            const double* rm0, const double* qm0, double* xm, double* pm1, double* rm1, double* qm1,
+                            const float* alpha, double beta, const float* minv, const ConvReduce& red, CgScalars* st,
+                            hipStream_t s) {
   if (!conv_ws_ok(cd) || grid < 1) return hipErrorInvalidValue;
   const int ntiles = cd.tilesX * cd.tilesY;
   const int64_t nblk_alloc = conv_pass_blocks(cd);
 #define COFEM_WS_LAUNCH(KS, PRE)                                                                                   \
-  hipLaunchKernelGGL((k_conv_ws<KS, PRE>), dim3((unsigned)grid), dim3(kWsThreads), 0, s, taps, cd.H, cd.W, cd.ldD,  \
-                     cd.K, cd.nt, cd.tilesX, ntiles, static_cast<const float*>(s0.P),                               \
-                     static_cast<const float*>(s0.R), static_cast<const float*>(s0.Q), static_cast<float*>(X),      \
-                     static_cast<float*>(s1.P), static_cast<float*>(s1.R), static_cast<float*>(s1.Q), s0.pm, s0.rm, \
-                     s0.qm, xm, s1.pm, s1.rm, s1.qm, alpha, beta, minv, red, nblk_alloc, st)
-#define COFEM_WS_CASE(KS)      \
-  case KS:                     \
-    if (minv)                  \
-      COFEM_WS_LAUNCH(KS, true);  \
-    else                       \
-      COFEM_WS_LAUNCH(KS, false); \
+  hipLaunchKernelGGL((k_conv_ws<KS, PRE, MD>), dim3((unsigned)grid), dim3(kWsThreads), 0, s, taps, cd.H, cd.W,     \
+                     cd.ldD, cd.K, cd.nt, cd.tilesX, ntiles, static_cast<const float*>(P0),                        \
+                     static_cast<const float*>(R0), static_cast<const float*>(Q0), static_cast<float*>(X),         \
+                     static_cast<float*>(P1), static_cast<float*>(R1), static_cast<float*>(Q1), pm0, rm0, qm0, xm, \
+                     pm1, rm1, qm1, alpha, beta, minv, red, nblk_alloc, st)
+#define COFEM_WS_CASE(KS)                       \
+  case KS:                                      \
+    if constexpr (MD == kWsApply)               \
+      COFEM_WS_LAUNCH(KS, false); /* no M^-1 */ \
+    else if (minv)                              \
+      COFEM_WS_LAUNCH(KS, true);                \
+    else                                        \
+      COFEM_WS_LAUNCH(KS, false);               \
     break;
   switch (cd.ks) {
     COFEM_WS_CASE(1)
@@ -785,6 +825,23 @@ hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const 
 #undef COFEM_WS_CASE
 #undef COFEM_WS_LAUNCH
   return hipGetLastError();
+}
+
+hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const ConvState& s0, const ConvState& s1,
+                         void* X, double* xm, const float* alpha, double beta, const float* minv,
+                         const ConvReduce& red, CgScalars* st, hipStream_t s) {
+  return ws_launch<kWsFused>(cd, grid, taps, s0.P, s0.R, s0.Q, X, s1.P, s1.R, s1.Q, s0.pm, s0.rm, s0.qm, xm, s1.pm,
+                             s1.rm, s1.qm, alpha, beta, minv, red, st, s);
+}
+
+hipError_t conv_pass_ws(const ConvDims& cd, int grid, const float* taps, const void* P, const double* pm,
+                        const void* R, const double* rm, const float* alpha, double beta, void* Q, double* qm,
+                        const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s, const float* minv) {
+  if (apply_only)
+    return ws_launch<kWsApply>(cd, grid, taps, P, nullptr, nullptr, nullptr, nullptr, nullptr, Q, pm, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, qm, alpha, beta, nullptr, red, st, s);
+  return ws_launch<kWsPass>(cd, grid, taps, P, R, nullptr, nullptr, nullptr, nullptr, Q, pm, rm, nullptr, nullptr,
+                            nullptr, nullptr, qm, alpha, beta, minv, red, st, s);
 }
 
 }  // namespace cofem

@@ -16,7 +16,10 @@ several-task shapes run it here:
 * against the float64 oracle: one teacher-forced step at the GPU's CG count
   (plain CG, warm-started Jacobi PCG, and three tasks sharing alpha), at the
   1e-4 norm-wise and 1e-3 element-wise bars of the other step tests;
-* bit-reproducible runs (every sum is reduced in a fixed order).
+* bit-reproducible runs (every sum is reduced in a fixed order);
+* the operator alone (the apply mode, used for the warm start's A X0 and the
+  true residual's A X): bit-equal to the per-tile kernel's q and within the
+  float32 rounding bound of the float64 oracle's A v, element by element.
 
 The full-size 1024 x 1024 step tests (test_gpu_fullsize.py) run it too, since
 the library chooses it there.
@@ -216,3 +219,44 @@ def test_ws_multitask_step_parity(torch_dev):
     assert st["converged"] == 1
     assert all(e < STEP_TOL for e in errs), errs
     assert max(relerr(mu[:, j], mu_ref[:, j]) for j in range(3)) < STEP_TOL
+
+
+_APPLY_SHAPES = {
+    "256x256_k9_K16": (256, 256, 9, 16),
+    "200x328_k5_K5_ragged": (200, 328, 5, 5),
+    "136x72_k9_K3": (136, 72, 9, 3),
+    "64x64_k1_K4": (64, 64, 1, 4),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_APPLY_SHAPES))
+def test_ws_apply_matches_tile_and_oracle(torch_dev, case):
+    torch = torch_dev
+    H, W, k, K = _APPLY_SHAPES[case]
+    p = synth.conv_problem(H, W, k, rho=0.05, beta=321.0, K=K, tol=1e-6, seed=H * W + k)
+    rng = np.random.default_rng(21)
+    D = H * W
+    alpha = (10.0 ** rng.uniform(-2, 6, D)).astype(np.float32)
+    V = rng.standard_normal((D, K)).astype(np.float32)
+    vm = rng.standard_normal(D)
+    _say("ws apply", case)
+    out = {}
+    for mode in ("tile", "ws"):
+        with _kernel(mode):
+            with _ctx(torch, p) as g:
+                g.set_alpha(torch.from_numpy(alpha))
+                q, qm = g.apply_A(torch.from_numpy(V.T.copy()), torch.from_numpy(vm))
+                out[mode] = (q.cpu().numpy().T, qm.cpu().numpy())
+    assert np.array_equal(out["ws"][0], out["tile"][0])
+    assert relerr(out["ws"][1], out["tile"][1]) < 1e-15
+    op = O.ConvOperator(p.taps.astype(np.float64), H, W)
+    A = O.make_apply_A(op, p.beta, alpha.astype(np.float64))
+    ref = A(V.astype(np.float64))
+    # element-wise: float32 rounding of the two stencil stages, relative to
+    # the magnitudes that enter each output (beta |Phi|^T |Phi| |v| + alpha |v|)
+    habs = O.ConvOperator(np.abs(p.taps.astype(np.float64)), H, W)
+    scale = p.beta * habs.apply_t(habs.apply(np.abs(V.astype(np.float64)))) + alpha[:, None] * np.abs(V)
+    err = np.abs(out["ws"][0] - ref) / scale
+    _say(case, "max error / magnitude", float(err.max()))
+    assert float(err.max()) < (2 * k * k + 4) * 2 ** -23
+    assert relerr(out["ws"][1], A(vm)) < 1e-13
