@@ -451,60 +451,109 @@ __device__ __forceinline__ void ws_deposit(const WsUnit& un, const double* stg, 
   if (lane < 5) store_agent(&pc[(int64_t)un.blk * 5 + lane], v);
 }
 
+// Whether this workgroup is the launch's last to finish, in two levels: the
+// workgroups of each of the 8 XCD groups (blockIdx mod 8) arrive at their
+// group's counter, and each group's last arrival at the top counter.  A
+// single counter took 256 arrivals on one address, which the memory side
+// serialises (~13 us at the end of every launch); here the last workgroup
+// waits for at most 32 + 8.  Every store a workgroup made is complete before
+// it arrives, and the counters are left at zero.  cnts: 8 counters
+// kCounterStride slots apart.
+__device__ __forceinline__ bool ws_last_block(uint32_t* cnts, uint32_t* top, int G) {
+  __shared__ bool s_last;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool last;
+    if ((G & 7) == 0) {
+      uint32_t* c1 = cnts + (blockIdx.x & 7) * kCounterStride;
+      last = __hip_atomic_fetch_add(c1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)(G / 8 - 1);
+      if (last) {
+        store_agent(c1, 0u);
+        last = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 7u;
+      }
+    } else {
+      last = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)(G - 1);
+    }
+    if (last) store_agent(top, 0u);
+    s_last = last;
+  }
+  __syncthreads();
+  return s_last;
+}
+
 // The launch's column totals, by its last workgroup: tot[v * nc + col] =
-// sum over the column's rows of value v, in a fixed order (rows in chunks
-// of RC summed in row order, one chunk per thread, then the chunks in
-// order), so the result does not depend on timing.  cp: LDS scratch of
-// at least ws_sum_items(...) doubles.
-__device__ __forceinline__ int ws_sum_chunks(int nblk, int rc) { return (nblk + rc - 1) / rc; }
-// rows per chunk: 32, or more where the chunk partials would not fit in cap
-// doubles of LDS
-__device__ __forceinline__ int ws_sum_rows(int K, int nt, int ntiles, int cap) {
-  int rc = 32;
-  while (5 * (K * ws_sum_chunks(ntiles, rc) + nt * ws_sum_chunks(4 * ntiles, rc)) > cap) rc *= 2;
-  return rc;
+// the sum over the column's rows of value v, in a fixed order.  A column's
+// flat array [row * 5 + v] is cut into segments of kWsSeg elements, one per
+// wave (two in flight at once): lane l reads the segment at l, l + 64, ...
+// (each load one contiguous 512-byte span; these loads are coherent across
+// the chip's L2s, so each is a full memory round trip) and adds each element
+// to its value's sum in that order; the lanes' sums meet in a fixed
+// butterfly, and a column's segments are then added in order.  cp: LDS
+// scratch of ws_seg_items(...) * 5 doubles.
+constexpr int kWsSegLoads = 20, kWsSeg = 64 * kWsSegLoads;
+__host__ __device__ __forceinline__ int ws_col_segs(int n5) { return (n5 + kWsSeg - 1) / kWsSeg; }
+__host__ __device__ __forceinline__ int ws_seg_items(int K, int nt, int ntiles) {
+  return K * ws_col_segs(5 * ntiles) + nt * ws_col_segs(20 * ntiles);
 }
 __device__ __forceinline__ void ws_column_sums(const ConvReduce& red, int64_t nblk_alloc, int K, int nt,
-                                               int ntiles, int rc, double* cp, double* tot) {
-  const int nc = K + nt;
-  const int chF = ws_sum_chunks(ntiles, rc), chD = ws_sum_chunks(4 * ntiles, rc);
-  const int nF = K * 5 * chF, nItems = nF + nt * 5 * chD;
+                                               int ntiles, double* cp, double* tot) {
+  const int nc = K + nt, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   const int64_t rows = tree_rows(nblk_alloc);
-  for (int i = threadIdx.x; i < nItems; i += blockDim.x) {
-    int col, v, c, nblk;
+  const int sF = ws_col_segs(5 * ntiles), sD = ws_col_segs(20 * ntiles), nF = K * sF;
+  const int nItems = ws_seg_items(K, nt, ntiles);
+  // item -> (column, segment)
+  auto where = [&](int i, int& col, int& seg, int& n5) {
     if (i < nF) {
-      col = i / (5 * chF);
-      const int r = i - col * 5 * chF;
-      v = r / chF;
-      c = r - v * chF;
-      nblk = ntiles;
+      col = i / sF;
+      seg = i - col * sF;
+      n5 = 5 * ntiles;
     } else {
       const int j = i - nF;
-      const int m = j / (5 * chD), r = j - m * 5 * chD;
-      col = K + m;
-      v = r / chD;
-      c = r - v * chD;
-      nblk = 4 * ntiles;
+      col = K + j / sD;
+      seg = j - (j / sD) * sD;
+      n5 = 20 * ntiles;
     }
-    const double* pc = red.parts + (int64_t)col * rows * 5;
-    const int r0 = c * rc, r1 = r0 + rc < nblk ? r0 + rc : nblk;
-    double t = 0.0;
-    for (int q = r0; q < r1; q += 32) {  // 32 loads in flight at once
-      double x[32];
+  };
+  for (int i0 = wave; i0 < nItems; i0 += 2 * nw) {
+    double x[2][kWsSegLoads];
+    int f0[2], n5[2];
 #pragma unroll
-      for (int k = 0; k < 32; ++k) x[k] = q + k < r1 ? load_agent(&pc[(int64_t)(q + k) * 5 + v]) : 0.0;
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + h * nw;
+      int col = 0, seg = 0, n = 0;
+      if (i < nItems) where(i, col, seg, n);
+      const double* pc = red.parts + (int64_t)col * rows * 5;
+      f0[h] = seg * kWsSeg;
+      n5[h] = i < nItems ? (f0[h] + kWsSeg < n ? f0[h] + kWsSeg : n) : 0;
 #pragma unroll
-      for (int k = 0; k < 32; ++k) t += x[k];
+      for (int k = 0; k < kWsSegLoads; ++k) {
+        const int f = f0[h] + lane + 64 * k;
+        x[h][k] = f < n5[h] ? load_agent(&pc[f]) : 0.0;
+      }
     }
-    cp[i] = t;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + h * nw;
+      double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < kWsSegLoads; ++k) {
+        const int f = f0[h] + lane + 64 * k, r = f - (f / 5) * 5;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) t[v] += r == v ? x[h][k] : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) t[v] = wave_sum(t[v]);
+      if (i < nItems && lane < 5)
+        cp[i * 5 + lane] = lane == 0 ? t[0] : lane == 1 ? t[1] : lane == 2 ? t[2] : lane == 3 ? t[3] : t[4];
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nc * 5; e += blockDim.x) {
     const int col = e / 5, v = e - (e / 5) * 5;
-    const int ch = col < K ? chF : chD;
-    const int base = col < K ? (col * 5 + v) * chF : nF + ((col - K) * 5 + v) * chD;
+    const int first = col < K ? col * sF : nF + (col - K) * sD, ns = col < K ? sF : sD;
     double t = 0.0;
-    for (int c = 0; c < ch; ++c) t += cp[base + c];
+    for (int g = 0; g < ns; ++g) t += cp[(first + g) * 5 + v];
     tot[v * nc + col] = t;
   }
   __syncthreads();
@@ -763,10 +812,8 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     // the last workgroup to finish sums the columns and takes the step's
     // scalars from the totals (gam, del, eta are values 2-4 of a unit's sums)
     __shared__ double tot[5 * kMaxCols];
-    if (!last_block_ticket(red.cnt_cols, (uint32_t)G)) return;
-    if (tid == 0) store_agent(red.cnt_cols, 0u);
-    ws_column_sums(red, nblk_alloc, K, nt, ntiles, ws_sum_rows(K, nt, ntiles, (int)(WG::BYTES / sizeof(double))),
-                   reinterpret_cast<double*>(smem), tot);
+    if (!ws_last_block(red.cnts, red.cnt_cols, G)) return;
+    ws_column_sums(red, nblk_alloc, K, nt, ntiles, reinterpret_cast<double*>(smem), tot);
     if constexpr (MD == kWsFused)
       finish_fused(st, tot, K + nt, ctl);
     else
@@ -782,6 +829,11 @@ bool conv_ws_ok(const ConvDims& cd) {
   if (cd.K + cd.nt > kMaxCols) return false;
   if ((4 * (int64_t)cd.nt + cd.K) * cd.tilesX * cd.tilesY >= ((int64_t)1 << 30)) return false;
   if (cd.D >= ((int64_t)1 << 28)) return false;  // 32-bit pixel offsets within a column
+  // the two-level finish ticket takes 8 of the reduction's counters
+  if (tree_counters(conv_pass_blocks(cd)) * (cd.K + cd.nt) < 8) return false;
+  // the final column sums' segment partials fit in the LDS staging buffers
+  if ((size_t)ws_seg_items(cd.K, cd.nt, cd.tilesX * cd.tilesY) * 5 * sizeof(double) > WsGeom<9>::BYTES / 2)
+    return false;
   // the staged regions of both unit kinds wrap at most one period
   const int c = (cd.ks - 1) / 2;
   const int trf = ((kConvTile + 2 * c + 3) / 4) * 4, trd = ((kConvTile / 2 + 2 * c + 3) / 4) * 4;
