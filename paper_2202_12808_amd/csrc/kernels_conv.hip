@@ -615,17 +615,33 @@ __global__ __launch_bounds__(256) void k_conv_init_pcg(int64_t D, int64_t ldD, i
       bb += b * b;
     }
   } else {
+    // four pixels per pass, their loads issued together (the same per-pixel
+    // arithmetic and summation order as one at a time)
+    constexpr int G = 4;
     const int64_t off = (int64_t)col * ldD;
-    for (int64_t d = gtid; d < D; d += gstride) {
-      const TP b = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)perm_nat(perm, d));
-      const TP r = Qx ? b - Qx[off + d] : b;
-      const TP z = minv ? (TP)minv[d] * r : r;
-      R[off + d] = r;
-      P[off + d] = z;
-      if (!Qx) X[off + d] = TP(0);
-      rz += (double)r * (double)z;
-      rr += (double)r * (double)r;
-      bb += 1.0;
+    for (int64_t d0 = gtid; d0 < D; d0 += G * gstride) {
+      TP qv[G];
+      float mv[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int64_t d = d0 + g * gstride;
+        qv[g] = (Qx && d < D) ? Qx[off + d] : TP(0);
+        mv[g] = (minv && d < D) ? minv[d] : 1.0f;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int64_t d = d0 + g * gstride;
+        if (d >= D) continue;
+        const TP b = (TP)probe_sign(seed, (uint32_t)t, (uint32_t)col, (uint64_t)perm_nat(perm, d));
+        const TP r = Qx ? b - qv[g] : b;
+        const TP z = minv ? (TP)mv[g] * r : r;
+        R[off + d] = r;
+        P[off + d] = z;
+        if (!Qx) X[off + d] = TP(0);
+        rz += (double)r * (double)z;
+        rr += (double)r * (double)r;
+        bb += 1.0;
+      }
     }
   }
   __shared__ double shm[8];
@@ -761,44 +777,68 @@ hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const doubl
 }
 
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
+// 512 threads per block (conv_update_blocks blocks), each taking its pixels
+// kMsGroup at a time: the group's probe-column loads are issued together, so
+// a thread has 4 K loads in flight instead of K (the launch is one block per
+// compute unit, and with one pixel at a time it waited on every load).
+constexpr int kMsThreads = 512, kMsGroup = 4;
 template <typename TP>
-__global__ __launch_bounds__(256) void k_conv_mstep(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed,
-                                                    int t, const TP* __restrict__ X,
-                                                    const double* __restrict__ xm,
-                                                    float* __restrict__ alpha, double alpha_max,
-                                                    float* __restrict__ mu,
-                                                    float* __restrict__ sdiag, double* parts, uint32_t* cnts,
-                                                    CgScalars* st) {
+__global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ldD, int K, int perm, int nt,
+                                                           uint64_t seed, int t, const TP* __restrict__ X,
+                                                           const double* __restrict__ xm,
+                                                           float* __restrict__ alpha, double alpha_max,
+                                                           float* __restrict__ mu,
+                                                           float* __restrict__ sdiag, double* parts, uint32_t* cnts,
+                                                           CgScalars* st) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
   double clamped = 0.0, dg2 = 0.0, g2 = 0.0;
-  for (int64_t d = gtid; d < D; d += gstride) {
-    double acc = 0.0;
-    const uint64_t dn = (uint64_t)perm_nat(perm, d);
-    for (int k = 0; k < K; ++k)
-      acc += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, dn) * (double)X[(int64_t)k * ldD + d];
-    const double s = acc / (double)K;
-    const double m = xm[d];
-    // tasks sharing alpha: the mean of their squared means
-    double m2 = m * m;
-    if (nt > 1) {
-      for (int j = 1; j < nt; ++j) {
-        const double mj = xm[(int64_t)j * ldD + d];
-        m2 += mj * mj;
+  for (int64_t d0 = gtid; d0 < D; d0 += kMsGroup * gstride) {
+    double acc[kMsGroup];
+#pragma unroll
+    for (int g = 0; g < kMsGroup; ++g) acc[g] = 0.0;
+    // the K probe columns in order for every pixel of the group (the same
+    // summation order as one pixel at a time)
+    for (int k = 0; k < K; ++k) {
+      TP x[kMsGroup];
+#pragma unroll
+      for (int g = 0; g < kMsGroup; ++g) {
+        const int64_t d = d0 + g * gstride;
+        x[g] = d < D ? X[(int64_t)k * ldD + d] : TP(0);
       }
-      m2 /= (double)nt;
+#pragma unroll
+      for (int g = 0; g < kMsGroup; ++g) {
+        const int64_t d = d0 + g * gstride;
+        if (d < D) acc[g] += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d)) * (double)x[g];
+      }
     }
-    const double den = m2 + s;
-    if (!(den >= floor_v)) clamped += 1.0;
-    const float a_new = (float)(1.0 / (den >= floor_v ? den : floor_v));
-    // change of the prior variance 1/alpha as the stored (float32) alpha has it
-    const double g_new = 1.0 / (double)a_new, g_old = 1.0 / (double)alpha[d];
-    dg2 += (g_new - g_old) * (g_new - g_old);
-    g2 += g_new * g_new;
-    alpha[d] = a_new;
-    mu[d] = (float)m;
-    sdiag[d] = (float)s;
+#pragma unroll
+    for (int g = 0; g < kMsGroup; ++g) {
+      const int64_t d = d0 + g * gstride;
+      if (d >= D) continue;
+      const double s = acc[g] / (double)K;
+      const double m = xm[d];
+      // tasks sharing alpha: the mean of their squared means
+      double m2 = m * m;
+      if (nt > 1) {
+        for (int j = 1; j < nt; ++j) {
+          const double mj = xm[(int64_t)j * ldD + d];
+          m2 += mj * mj;
+        }
+        m2 /= (double)nt;
+      }
+      const double den = m2 + s;
+      if (!(den >= floor_v)) clamped += 1.0;
+      const float a_new = (float)(1.0 / (den >= floor_v ? den : floor_v));
+      // change of the prior variance 1/alpha as the stored (float32) alpha has it
+      const double g_new = 1.0 / (double)a_new, g_old = 1.0 / (double)alpha[d];
+      dg2 += (g_new - g_old) * (g_new - g_old);
+      g2 += g_new * g_new;
+      alpha[d] = a_new;
+      mu[d] = (float)m;
+      sdiag[d] = (float)s;
+    }
   }
   __shared__ double shm[8];
   __shared__ double mine[3], tot[3];
@@ -822,10 +862,10 @@ hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, c
   // reduction workspace (three values per block) serves the M-step's sums
   const unsigned blocks = (unsigned)conv_update_blocks(cd);
   if (cd.fp64)
-    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
+    hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(kMsThreads), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
                        static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st);
   else
-    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
+    hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(kMsThreads), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
                        static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st);
   return hipGetLastError();
 }
