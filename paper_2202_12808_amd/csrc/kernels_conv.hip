@@ -794,10 +794,25 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
   double clamped = 0.0, dg2 = 0.0, g2 = 0.0;
-  for (int64_t d0 = gtid; d0 < D; d0 += kMsGroup * gstride) {
+  // the loop test is uniform across a wave (its first pixel), so every lane
+  // takes part in the shared hashing below; each pixel is guarded on its own
+  for (int64_t d0 = gtid; (d0 & ~(int64_t)63) < D; d0 += kMsGroup * gstride) {
     double acc[kMsGroup];
 #pragma unroll
     for (int g = 0; g < kMsGroup; ++g) acc[g] = 0.0;
+    // In the natural element order a wave's 64 pixels d (a multiple of 64
+    // onwards, d & 63 = lane) share probe k's 64-bit SplitMix64 word (the sign
+    // is its bit d & 63): lane k forms the word of probe k once, and the wave
+    // reads it from that lane, instead of every lane hashing all K words.
+    uint64_t wk[kMsGroup];
+    const int lane = threadIdx.x & 63;
+    if (perm == 0) {
+#pragma unroll
+      for (int g = 0; g < kMsGroup; ++g) {
+        const uint64_t idx = ((uint64_t)t << 48) | ((uint64_t)lane << 32) | ((uint64_t)(d0 + g * gstride) >> 6);
+        wk[g] = splitmix64_mix(seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
+      }
+    }
     // the K probe columns in order for every pixel of the group (the same
     // summation order as one pixel at a time)
     for (int k = 0; k < K; ++k) {
@@ -810,7 +825,16 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
 #pragma unroll
       for (int g = 0; g < kMsGroup; ++g) {
         const int64_t d = d0 + g * gstride;
-        if (d < D) acc[g] += (double)probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d)) * (double)x[g];
+        float sg;
+        if (perm == 0) {
+          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)wk[g], k);
+          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(wk[g] >> 32), k);
+          const uint64_t w = ((uint64_t)hi << 32) | lo;
+          sg = ((w >> lane) & 1ull) ? -1.0f : 1.0f;
+        } else {
+          sg = probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d));
+        }
+        if (d < D) acc[g] += (double)sg * (double)x[g];
       }
     }
 #pragma unroll
