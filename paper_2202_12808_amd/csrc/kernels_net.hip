@@ -186,7 +186,9 @@ __global__ __launch_bounds__(256) void k_net_conv3_mfma(const void* __restrict__
     for (int k = 0; k < GRP; ++k) {
       const int e = threadIdx.x + (k0 + k) * kThreads;
       if (k0 + k < PER && e < ITEMS) {
-        const int o = e / NPIX, pix = e - (e / NPIX) * NPIX;
+        // consecutive threads take consecutive octets of a pixel, so a wave
+        // reads contiguous 16-byte pieces of the pixel-major rows
+        const int pix = e / NOCT, o = e - (e / NOCT) * NOCT;
         const int i = pix / SW, j = pix - (pix / SW) * SW;
         const int64_t src = (int64_t)nwrap(u0 + i - 1, H) * W + nwrap(v0 + j - 1, W);
         if constexpr (IN_BF) {
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256) void k_net_conv3_mfma(const void* __restrict__
     for (int k = 0; k < GRP; ++k) {
       const int e = threadIdx.x + (k0 + k) * kThreads;
       if (k0 + k < PER && e < ITEMS) {
-        const int o = e / NPIX, pix = e - (e / NPIX) * NPIX;
+        const int pix = e / NOCT, o = e - (e / NOCT) * NOCT;
         *reinterpret_cast<uint4*>(s_x + pix * CP + 8 * o) = vals[k];
       }
     }
