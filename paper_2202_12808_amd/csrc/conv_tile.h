@@ -229,4 +229,109 @@ __device__ __forceinline__ void conv_stage2(TapsT h, const T* sT, int tid, T (&a
   }
 }
 
+// The stencil stages in BR x BC output blocks (any block shape that divides
+// the region; used where the 4x4 blocks would leave waves idle, e.g. the
+// 32 x 32 float64 quadrants: 100 stage-1 and 64 stage-2 blocks of 4x4 on four
+// waves).  Each output's sum runs over the same (input row, tap column) order
+// as in the 4x4 forms.  Rows of XW = BC + 2c values are read as 16-byte
+// vectors (XW * sizeof(T) and the block origins 16-byte aligned).
+template <int KS, int TILE, int BR, int BC, typename T>
+struct StageBlk {
+  using G = ConvGeom<KS, TILE>;
+  static constexpr int c = G::c, XW = BC + 2 * c, NV = 16 / sizeof(T);
+  static constexpr int NB1 = (G::TR / BR) * (G::TR / BC), NB2 = (TILE / BR) * (TILE / BC);
+  static_assert(G::TR % BR == 0 && G::TR % BC == 0 && TILE % BR == 0 && TILE % BC == 0, "block divides region");
+  static_assert(XW % NV == 0 && (BC * sizeof(T)) % 16 == 0, "16-byte rows");
+};
+template <typename T, int N>
+__device__ __forceinline__ void lds_row_v(const T* src, T (&x)[N]) {
+  constexpr int NV = 16 / sizeof(T);
+#pragma unroll
+  for (int q = 0; q < N / NV; ++q) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = reinterpret_cast<const float4*>(src)[q];
+      x[4 * q] = v.x;
+      x[4 * q + 1] = v.y;
+      x[4 * q + 2] = v.z;
+      x[4 * q + 3] = v.w;
+    } else {
+      const double2 v = reinterpret_cast<const double2*>(src)[q];
+      x[2 * q] = v.x;
+      x[2 * q + 1] = v.y;
+    }
+  }
+}
+template <int KS, int TILE, int BR, int BC, typename T, typename TapsT>
+__device__ __forceinline__ void conv_stage1_blk(TapsT h, const T* sP, T* sT, int tid, int nthr) {
+  using G = ConvGeom<KS, TILE>;
+  using S = StageBlk<KS, TILE, BR, BC, T>;
+  constexpr int c = G::c, NBJ = G::TR / BC;
+  for (int item = tid; item < S::NB1; item += nthr) {
+    const int bi = item / NBJ, bj = item - (item / NBJ) * NBJ;
+    T acc[BR][BC];
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int cc = 0; cc < BC; ++cc) acc[r][cc] = T(0);
+    const T* src1 = sP + (BR * bi) * G::SPW + BC * bj;
+    T x[2][S::XW];
+    lds_row_v(src1, x[0]);
+#pragma unroll
+    for (int q = 0; q < KS + BR - 1; ++q) {  // input row BR bi + q
+      h.fence();
+      if (q + 1 < KS + BR - 1) lds_row_v(src1 + (q + 1) * G::SPW, x[(q + 1) & 1]);
+#pragma unroll
+      for (int r = 0; r < BR; ++r) {
+        const int a = r + 2 * c - q;
+        if (a < 0 || a >= KS) continue;
+#pragma unroll
+        for (int b = 0; b < KS; ++b) {
+          const T hv = h(a * KS + b);
+#pragma unroll
+          for (int cc = 0; cc < BC; ++cc) acc[r][cc] = fma(hv, x[q & 1][cc + 2 * c - b], acc[r][cc]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      T* dst = sT + (BR * bi + r) * G::TR + BC * bj;
+#pragma unroll
+      for (int cc = 0; cc < BC; ++cc) dst[cc] = acc[r][cc];
+    }
+  }
+}
+// Stage 2 for block `item` (< NB2) of the tile: acc = (Phi^T t) on the block.
+template <int KS, int TILE, int BR, int BC, typename T, typename TapsT>
+__device__ __forceinline__ void conv_stage2_blk(TapsT h, const T* sT, int item, T (&acc)[BR][BC]) {
+  using G = ConvGeom<KS, TILE>;
+  using S = StageBlk<KS, TILE, BR, BC, T>;
+  constexpr int NBJ = TILE / BC;
+  const int bi = item / NBJ, bj = item - (item / NBJ) * NBJ;
+#pragma unroll
+  for (int r = 0; r < BR; ++r)
+#pragma unroll
+    for (int cc = 0; cc < BC; ++cc) acc[r][cc] = T(0);
+  const T* src2 = sT + (BR * bi) * G::TR + BC * bj;
+  T x[2][S::XW];
+  lds_row_v(src2, x[0]);
+#pragma unroll
+  for (int q = 0; q < KS + BR - 1; ++q) {  // t row BR bi + q
+    h.fence();
+    if (q + 1 < KS + BR - 1) lds_row_v(src2 + (q + 1) * G::TR, x[(q + 1) & 1]);
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int a = q - r;
+      if (a < 0 || a >= KS) continue;
+#pragma unroll
+      for (int b = 0; b < KS; ++b) {
+        const T hv = h(a * KS + b);
+#pragma unroll
+        for (int cc = 0; cc < BC; ++cc) acc[r][cc] = fma(hv, x[q & 1][cc + b], acc[r][cc]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 }  // namespace cofem

@@ -627,24 +627,31 @@ __device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L
         conv_stage1_w6<KS, TILE>(TapsReg<KS>(L.tapsF), bC, sT, ct, kWsCompute);
       else if constexpr (sizeof(T) == 4)
         conv_stage1<KS, TILE, T>(TapsReg<KS>(L.tapsF), bC, sT, ct, kWsCompute);
-      else
-        conv_stage1<KS, TILE, T>(Taps<double>(L.tapsD), bC, sT, ct, kWsCompute);
+      else  // float64 quadrants: 4x2 blocks (200 of them) keep all four waves busy
+        conv_stage1_blk<KS, TILE, 4, 2, T>(Taps<double>(L.tapsD), bC, sT, ct, kWsCompute);
     }
     ws_barrier();
-    if (work && ct < G::NB2) {
-      T acc[4][4];
-      if constexpr (sizeof(T) == 4)
+    if constexpr (sizeof(T) == 4) {
+      if (work && ct < G::NB2) {
+        T acc[4][4];
         conv_stage2<KS, TILE, T>(TapsReg<KS>(L.tapsF), sT, ct, acc);
-      else
-        conv_stage2<KS, TILE, T>(Taps<double>(L.tapsD), sT, ct, acc);
-      const int bi = ct / (TILE / 4), bj = ct - (ct / (TILE / 4)) * (TILE / 4);
-      T* dst = uC + (4 * bi) * TILE + 4 * bj;
+        const int bi = ct / (TILE / 4), bj = ct - (ct / (TILE / 4)) * (TILE / 4);
+        T* dst = uC + (4 * bi) * TILE + 4 * bj;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const T row[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
-        vstore<T>(dst + r * TILE, *reinterpret_cast<const T(*)[16 / sizeof(T)]>(row));
-        if constexpr (sizeof(T) == 8)
-          vstore<T>(dst + r * TILE + 2, *reinterpret_cast<const T(*)[2]>(row + 2));
+        for (int r = 0; r < 4; ++r) {
+          const T row[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
+          vstore<T>(dst + r * TILE, *reinterpret_cast<const T(*)[4]>(row));
+        }
+      }
+    } else {  // float64 quadrants: 2x2 blocks, 256 of them, one per compute thread
+      using S2 = StageBlk<KS, TILE, 2, 2, T>;
+      if (work && ct < S2::NB2) {
+        T acc[2][2];
+        conv_stage2_blk<KS, TILE, 2, 2, T>(Taps<double>(L.tapsD), sT, ct, acc);
+        const int bi = ct / (TILE / 2), bj = ct - (ct / (TILE / 2)) * (TILE / 2);
+        T* dst = uC + (2 * bi) * TILE + 2 * bj;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) vstore<T>(dst + r * TILE, acc[r]);
       }
     }
     // unit s - 1's sums: its staging sums from two steps back, its epilogue
