@@ -260,3 +260,18 @@ def test_ws_apply_matches_tile_and_oracle(torch_dev, case):
     _say(case, "max error / magnitude", float(err.max()))
     assert float(err.max()) < (2 * k * k + 4) * 2 ** -23
     assert relerr(out["ws"][1], A(vm)) < 1e-13
+
+
+@pytest.mark.parametrize("grid", [100, 64])
+def test_ws_other_grids_match_tile_kernel(torch_dev, grid):
+    # a grid that is not a multiple of 8 takes the single-level finish ticket
+    # and the plain slot order; 64 workgroups take several units per step
+    torch = torch_dev
+    mk, kw = _SHAPES["200x328_k5_K5_ragged"]
+    p = mk()
+    _say("ws grid", grid)
+    X_t, m_t, r_t = _one_fused(torch, p, kw, "tile")
+    X_w, m_w, r_w = _one_fused(torch, p, kw, f"ws:{grid}")
+    assert np.array_equal(X_w, X_t)
+    assert relerr(m_w, m_t) < 1e-13
+    assert abs(r_w - r_t) <= 1e-12 * r_t
