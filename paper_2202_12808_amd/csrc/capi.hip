@@ -1046,9 +1046,16 @@ cofem_status conv_start_pcg(cofem_ctx* c, int t) {
   const ConvReduce& rs = c->kind == COFEM_DCT_MASK ? c->red_upd : c->red_pass;
   if (start) {
     if (!spectral) COFEM_HIP(c, conv_start(cd, c->seed, t, d0, mu0, c->vX, c->xm, c->stream));
-    COFEM_TRY(apply_to_scratch(c, c->vX, c->xm));
-    COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, c->vQs, c->Qsm, c->vX, c->vR, c->vP, c->xm,
-                               c->rm, c->pm, rs, c->st, c->stream));
+    if (c->kind == COFEM_CONV2D_CIRC && cd.ws_grid > 0) {
+      // the persistent kernel forms R = B - A X0 and P = M^-1 R with their sums
+      // in its epilogue (A X0 is not stored)
+      COFEM_HIP(c, conv_init_ws(cd, cd.ws_grid, c->taps, c->seed, t, c->b0, c->active_minv, c->vX, c->xm, c->vR,
+                                c->vP, c->rm, c->pm, c->alpha, c->beta, c->red_pass, c->st, c->stream));
+    } else {
+      COFEM_TRY(apply_to_scratch(c, c->vX, c->xm));
+      COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, c->vQs, c->Qsm, c->vX, c->vR, c->vP, c->xm,
+                                 c->rm, c->pm, rs, c->st, c->stream));
+    }
   } else {
     COFEM_HIP(c, conv_init_pcg(cd, c->seed, t, c->b0, c->active_minv, nullptr, nullptr, c->vX, c->vR, c->vP, c->xm,
                                c->rm, c->pm, rs, c->st, c->stream));
@@ -1141,6 +1148,11 @@ cofem_status true_residual(cofem_ctx* c, int t) {
       COFEM_HIP(c, dct_mid(c->xd, c->xb, c->st, 1, c->stream));
       COFEM_HIP(c, dct_rows_out(c->xd, c->xb, c->vX, nullptr, c->vQs, c->xm, nullptr, c->Qsm, c->alpha, nullptr,
                                 c->red_pass, c->st, 0, 1, c->stream));
+    } else if (c->cd.ws_grid > 0) {
+      // the persistent kernel sums ||b - A x||^2 in its epilogue (A X is not stored)
+      COFEM_HIP(c, conv_resid_ws(c->cd, c->cd.ws_grid, c->taps, c->seed, t, c->b0, c->vX, c->xm, c->alpha, c->beta,
+                                 c->red_pass, c->st, c->stream));
+      return COFEM_OK;
     } else {
       COFEM_HIP(c, conv_pass(c->cd, c->taps, c->vX, c->xm, c->vR, c->rm, c->alpha, c->beta, c->vQs, c->Qsm,
                              c->red_pass, c->st, 1, c->stream));

@@ -768,6 +768,16 @@ hipError_t conv_fused_ws(const ConvDims& cd, int grid, const float* taps, const 
 hipError_t conv_pass_ws(const ConvDims& cd, int grid, const float* taps, const void* P, const double* pm,
                         const void* R, const double* rm, const float* alpha, double beta, void* Q, double* qm,
                         const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s, const float* minv);
+// The start of a warm-started solve (conv_init_pcg on A X0, with A X0 formed
+// in the same launch) and the true-residual check (conv_true_resid on A X),
+// as modes of the persistent kernel; natural element order.
+hipError_t conv_init_ws(const ConvDims& cd, int grid, const float* taps, uint64_t seed, int t, const double* b0,
+                        const float* minv, const void* X, const double* xm, void* R, void* P, double* rm,
+                        double* pm, const float* alpha, double beta, const ConvReduce& red, CgScalars* st,
+                        hipStream_t s);
+hipError_t conv_resid_ws(const ConvDims& cd, int grid, const float* taps, uint64_t seed, int t, const double* b0,
+                         const void* X, const double* xm, const float* alpha, double beta, const ConvReduce& red,
+                         CgScalars* st, hipStream_t s);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,

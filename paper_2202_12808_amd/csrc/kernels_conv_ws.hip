@@ -37,8 +37,15 @@ namespace {
 //             iteration after a solve's first);
 //   kWsPass   the operator pass on p with the step's dots gam = p^T q,
 //             del = r^T M^-1 q, eta = q^T M^-1 q (a solve's first iteration);
-//   kWsApply  q = A p alone (the warm start's A X0, the true residual's A X).
-constexpr int kWsFused = 0, kWsPass = 1, kWsApply = 2;
+//   kWsApply  q = A p alone;
+//   kWsInit   the start of a warm-started solve: with q = A x0, r = b - q and
+//             z = M^-1 r written as the solve's R and P, and per column
+//             r^T z, r^T r, b^T b (q itself is not stored);
+//   kWsResid  the true residual after a solve: per column ||b - A x||^2
+//             (nothing is stored).
+// The last three stage p (x) alone; b is the probe (regenerated from its
+// counter-based hash) or the mean column's b0.
+constexpr int kWsFused = 0, kWsPass = 1, kWsApply = 2, kWsInit = 3, kWsResid = 4;
 
 constexpr int kWsCompute = 256;  // compute threads (waves 0-3)
 constexpr int kWsMemory = 512;   // memory threads (waves 4-11)
@@ -134,6 +141,7 @@ struct WsStageRaw {
 };
 struct WsEpiRaw {
   uint32_t al[kWsEpiVecs][4];
+  uint32_t mv[kWsEpiVecs][4], b0[kWsEpiVecs][4];  // the init and residual modes
   uint32_t ix[kWsEpiVecs];
   bool ok[kWsEpiVecs];
 };
@@ -346,7 +354,7 @@ __device__ __forceinline__ void ws_stage_finish(const WsStageRaw& g, T* __restri
     int i, j;
     M::pos(mt, k, i, j);
     vstore<T>(sP + i * M::G::SPW + j, p1);
-    if (MD != kWsApply && k < M::KOWN) {
+    if ((MD == kWsFused || MD == kWsPass) && k < M::KOWN) {
       const int o = (i - M::c2) * TILE + (j - M::c2);
       vstore<T>(sR + o, r1);
       if (precond) vstore<T>(sM + o, mv);
@@ -359,9 +367,10 @@ __device__ __forceinline__ void ws_stage_finish(const WsStageRaw& g, T* __restri
 // del = r'^T M^-1 q, eta = q^T M^-1 q, with r' and M^-1 as the staging left
 // them in sR, sM.  ws_epi_load issues the alpha loads (pixels outside the
 // image read pixel 0 and are not used), ws_epi_finish does the rest.
-template <int TILE, typename T>
-__device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const float* __restrict__ alpha, int H, int W, int tu0,
-                                            int tv0, int mt) {
+template <int TILE, typename T, bool PRE, int MD>
+__device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const float* __restrict__ alpha,
+                                            const float* __restrict__ minv, const double* __restrict__ b0, int H,
+                                            int W, int tu0, int tv0, int mt) {
   constexpr int N = 16 / sizeof(T), VT = TILE / N, NV = TILE * VT, KE = NV / kWsMemory;
   static_assert(NV % kWsMemory == 0 && KE <= kWsEpiVecs, "epilogue vectors per thread");
 #pragma unroll
@@ -375,6 +384,14 @@ __device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const float* __restrict
       raw_load16(g.al[k], at(alpha, g.ix[k]));
     else
       raw_load8(g.al[k], at(alpha, g.ix[k]));
+    if constexpr (MD == kWsInit && PRE) {
+      if constexpr (sizeof(T) == 4)
+        raw_load16(g.mv[k], at(minv, g.ix[k]));
+      else
+        raw_load8(g.mv[k], at(minv, g.ix[k]));
+    }
+    // the float64 units' b: the mean column's b0 (a float unit's b is its probe)
+    if constexpr ((MD == kWsInit || MD == kWsResid) && sizeof(T) == 8) raw_load16(g.b0[k], at(b0, g.ix[k]));
   }
 }
 
@@ -382,13 +399,22 @@ __device__ __forceinline__ void ws_epi_load(WsEpiRaw& g, const float* __restrict
 // (ws_epi_store, in the next phase: a store issued behind the staging loads
 // would wait for them to be accepted)
 struct WsEpiOut {
-  uint32_t q[kWsEpiVecs][4];
-  uint32_t off[kWsEpiVecs];  // byte offset, or kWsNoStore
+  uint32_t q[kWsEpiVecs][4];  // q (r in the init mode)
+  uint32_t z[kWsEpiVecs][4];  // the init mode's z
+  uint32_t off[kWsEpiVecs];   // byte offset, or kWsNoStore
 };
+// The probe signs of 16 / sizeof(T) consecutive pixels from ix (natural
+// element order; they share one 64-bit word of the probe's hash): bit
+// (j & 63) of SplitMix64 output (t << 48 | k << 32 | j >> 6) + 1.
+__device__ __forceinline__ uint64_t ws_probe_word(uint64_t seed, uint32_t t, uint32_t k, uint32_t ix) {
+  const uint64_t idx = ((uint64_t)t << 48) | ((uint64_t)k << 32) | (uint64_t)(ix >> 6);
+  return splitmix64_mix(seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
+}
 template <int KS, int TILE, typename T, int MD>
 __device__ __forceinline__ void ws_epi_finish(const WsEpiRaw& g, WsEpiOut& out, bool precond, bool valid, T beta,
                                               int mt, const T* sP, const T* sU, const T* sR, const T* sM,
-                                              double& gm, double& dl, double& et) {
+                                              double& gm, double& dl, double& et, uint64_t seed = 0,
+                                              uint32_t tt = 0, uint32_t col = 0) {
   using G = ConvGeom<KS, TILE>;
   constexpr int c = G::c, N = 16 / sizeof(T), VT = TILE / N, KE = TILE * VT / kWsMemory;
 #pragma unroll
@@ -400,36 +426,73 @@ __device__ __forceinline__ void ws_epi_finish(const WsEpiRaw& g, WsEpiOut& out, 
     T q[N], pv[N], tv[N], rv[N], mv[N];
     vload<T>(pv, sP + (i + 2 * c) * G::SPW + j + 2 * c);
     vload<T>(tv, sU + o);
-    if constexpr (MD != kWsApply) {
+    if constexpr (MD == kWsFused || MD == kWsPass) {
       vload<T>(rv, sR + o);
       if (precond) vload<T>(mv, sM + o);
     }
+    uint64_t w = 0;
+    if constexpr ((MD == kWsInit || MD == kWsResid) && sizeof(T) == 4) w = ws_probe_word(seed, tt, col, g.ix[k]);
+    T zo[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
       const T p = pv[n];
       q[n] = fma(beta, tv[n], (T)__uint_as_float(g.al[k][n]) * p);  // as the per-tile kernel
-      const double qd = (double)q[n];
-      const double mq = precond ? (double)mv[n] * qd : qd;
-      if (MD != kWsApply && use) {
-        gm += (double)p * qd;
-        dl += (double)rv[n] * mq;
-        et += qd * mq;
+      if constexpr (MD == kWsFused || MD == kWsPass) {
+        const double qd = (double)q[n];
+        const double mq = precond ? (double)mv[n] * qd : qd;
+        if (use) {
+          gm += (double)p * qd;
+          dl += (double)rv[n] * mq;
+          et += qd * mq;
+        }
+      } else if constexpr (MD == kWsInit || MD == kWsResid) {
+        // b: the probe sign (float units), b0 (float64 units); as the
+        // start and true-residual kernels form them
+        T b;
+        if constexpr (sizeof(T) == 4)
+          b = ((w >> ((g.ix[k] + n) & 63)) & 1ull) ? -1.0f : 1.0f;
+        else
+          b = raw_get<T>(g.b0[k], n);
+        if constexpr (MD == kWsInit) {
+          const T r = b - q[n];
+          const T z = precond ? (T)__uint_as_float(g.mv[k][n]) * r : r;
+          q[n] = r;
+          zo[n] = z;
+          if (use) {
+            gm += (double)r * (double)z;
+            dl += (double)r * (double)r;
+            et += sizeof(T) == 4 ? 1.0 : (double)b * (double)b;
+          }
+        } else {
+          const double e = (double)b - (double)q[n];
+          if (use) gm += e * e;
+        }
       }
     }
     __builtin_memcpy(out.q[k], q, 16);
+    if constexpr (MD == kWsInit) __builtin_memcpy(out.z[k], zo, 16);
     out.off[k] = use ? g.ix[k] * (uint32_t)sizeof(T) : kWsNoStore;
   }
 }
-template <int TILE, typename T>
-__device__ __forceinline__ void ws_epi_store(const WsEpiOut& out, T* __restrict__ Q1, uint32_t col_bytes,
-                                             bool valid) {
+// q to Q1 (the init mode: r to R1 and z to P1; the residual mode stores
+// nothing)
+template <int TILE, typename T, int MD>
+__device__ __forceinline__ void ws_epi_store(const WsEpiOut& out, T* __restrict__ Q1, T* __restrict__ R1,
+                                             T* __restrict__ P1, uint32_t col_bytes, bool valid) {
   constexpr int KE = TILE * (TILE * sizeof(T) / 16) / kWsMemory;
-  const __amdgpu_buffer_rsrc_t rQ = ws_rsrc(Q1, valid ? col_bytes : 0u);
+  if constexpr (MD == kWsResid) return;
+  const uint32_t nb = valid ? col_bytes : 0u;
+  const __amdgpu_buffer_rsrc_t rQ = ws_rsrc(MD == kWsInit ? R1 : Q1, nb), rP = ws_rsrc(P1, nb);
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
     ws_u32x4 w;
     __builtin_memcpy(&w, out.q[k], 16);
     __builtin_amdgcn_raw_buffer_store_b128(w, rQ, (int)out.off[k], 0, 0);
+    if constexpr (MD == kWsInit) {
+      ws_u32x4 wz;
+      __builtin_memcpy(&wz, out.z[k], 16);
+      __builtin_amdgcn_raw_buffer_store_b128(wz, rP, (int)out.off[k], 0, 0);
+    }
   }
 }
 
@@ -567,7 +630,8 @@ template <typename T>
 struct WsCols {
   const T *P0, *R0, *Q0;
   T *X, *P1, *R1, *Q1;
-  int col0;  // first column of this kind
+  const double* B0;  // the mean columns' b0 (the init and residual modes)
+  int col0;          // first column of this kind
   int64_t ldD;
   __device__ __forceinline__ int64_t off(int col) const { return (int64_t)(col - col0) * ldD; }
 };
@@ -666,7 +730,7 @@ __device__ __forceinline__ void ws_compute_loop(const WsGrid& gr, const WsLds& L
 template <int KS, int TILE, typename T, bool PRE, int MD>
 __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L, const WsCols<T>& C,
                                                const float* __restrict__ alpha, const float* __restrict__ minv,
-                                               double beta, int i0, int n, int tid) {
+                                               double beta, uint64_t seed, uint32_t tt, int i0, int n, int tid) {
   using WG = WsGeom<KS>;
   constexpr bool precond = PRE;  // a compile-time choice, so every path issues the same loads
   const int mw = (tid - kWsCompute) >> 6, lane = tid & 63;
@@ -717,7 +781,8 @@ __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L,
       ws_epi_finish<KS, TILE, T, MD>(ge, eo, precond, ev, (T)beta, mt,
                                  reinterpret_cast<const T*>(L.sP + b * WG::SP), sU,
                                  reinterpret_cast<const T*>(L.sR + b * WG::SU),
-                                 reinterpret_cast<const T*>(L.sM + b * WG::SU), gm, dl, et);
+                                 reinterpret_cast<const T*>(L.sM + b * WG::SU), gm, dl, et, seed, tt,
+                                 (uint32_t)(ev ? ue.col : 0));
       stage_load_halo(un, mt);
       if (ue.exists) {
         gm = wave_sum(gm);
@@ -732,8 +797,12 @@ __device__ __forceinline__ void ws_memory_loop(const WsGrid& gr, const WsLds& L,
     }
     ws_barrier();  // the staging loads stay in flight across it
     // ---------------- phase 2
-    ws_epi_load<TILE, T>(ge, alpha, gr.H, gr.W, av ? ua.tu0 : 0, av ? ua.tv0 : 0, mt);
-    ws_epi_store<TILE, T>(eo, C.Q1 + (ev ? C.off(ue.col) : 0), col_bytes, ev);
+    ws_epi_load<TILE, T, PRE, MD>(ge, alpha, minv, C.B0 + (av ? C.off(ua.col) : 0), gr.H, gr.W, av ? ua.tu0 : 0,
+                                  av ? ua.tv0 : 0, mt);
+    {
+      const int64_t o = ev ? C.off(ue.col) : 0;
+      ws_epi_store<TILE, T, MD>(eo, C.Q1 + o, C.R1 + o, C.P1 + o, col_bytes, ev);
+    }
     {
       double rz = 0.0, rr = 0.0;
       const int64_t o = sv ? C.off(un.col) : 0;
@@ -761,8 +830,11 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     float* __restrict__ P1, float* __restrict__ R1, float* __restrict__ Q1, const double* __restrict__ pm0,
     const double* __restrict__ rm0, const double* __restrict__ qm0, double* __restrict__ xm,
     double* __restrict__ pm1, double* __restrict__ rm1, double* __restrict__ qm1, const float* __restrict__ alpha,
-    double beta, const float* __restrict__ minv, ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st) {
-  if (MD != kWsApply && st->stop) return;
+    double beta, const float* __restrict__ minv, ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st,
+    const double* __restrict__ b0, uint64_t seed, int tt) {
+  // a CG iteration does nothing once the solve has stopped; the other modes
+  // run at a solve's start or after it
+  if ((MD == kWsFused || MD == kWsPass) && st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   using WG = WsGeom<KS>;
   using GF = typename WG::GF;
@@ -810,10 +882,10 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     ws_compute_loop<KS, kConvTile / 2, double, MD>(gr, L, red, nblk_alloc, 0, N64, tid);
     ws_compute_loop<KS, kConvTile, float, MD>(gr, L, red, nblk_alloc, N64, NF, tid);
   } else {
-    const WsCols<double> cd{pm0, rm0, qm0, xm, pm1, rm1, qm1, K, ldD};
-    const WsCols<float> cf{P0, R0, Q0, X, P1, R1, Q1, 0, ldD};
-    ws_memory_loop<KS, kConvTile / 2, double, PRE, MD>(gr, L, cd, alpha, minv, beta, 0, N64, tid);
-    ws_memory_loop<KS, kConvTile, float, PRE, MD>(gr, L, cf, alpha, minv, beta, N64, NF, tid);
+    const WsCols<double> cd{pm0, rm0, qm0, xm, pm1, rm1, qm1, b0, K, ldD};
+    const WsCols<float> cf{P0, R0, Q0, X, P1, R1, Q1, nullptr, 0, ldD};
+    ws_memory_loop<KS, kConvTile / 2, double, PRE, MD>(gr, L, cd, alpha, minv, beta, seed, (uint32_t)tt, 0, N64, tid);
+    ws_memory_loop<KS, kConvTile, float, PRE, MD>(gr, L, cf, alpha, minv, beta, seed, (uint32_t)tt, N64, NF, tid);
   }
   if constexpr (MD != kWsApply) {
     // the last workgroup to finish sums the columns and takes the step's
@@ -823,8 +895,12 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     ws_column_sums(red, nblk_alloc, K, nt, ntiles, reinterpret_cast<double*>(smem), tot);
     if constexpr (MD == kWsFused)
       finish_fused(st, tot, K + nt, ctl);
-    else
+    else if constexpr (MD == kWsPass)
       finish_step(st, tot + 2 * (K + nt), ctl);
+    else if constexpr (MD == kWsInit)
+      finish_init_pcg(st, tot + 2 * (K + nt), K + nt);
+    else
+      finish_true_resid(st, tot + 2 * (K + nt));
   }
 }
 
@@ -855,7 +931,7 @@ static hipError_t ws_launch(const ConvDims& cd, int grid, const float* taps, con
                             const void* Q0, void* X, void* P1, void* R1, void* Q1, const double* pm0,
                             const double* rm0, const double* qm0, double* xm, double* pm1, double* rm1, double* qm1,
                             const float* alpha, double beta, const float* minv, const ConvReduce& red, CgScalars* st,
-                            hipStream_t s) {
+                            hipStream_t s, const double* b0 = nullptr, uint64_t seed = 0, int t = 0) {
   if (!conv_ws_ok(cd) || grid < 1) return hipErrorInvalidValue;
   const int ntiles = cd.tilesX * cd.tilesY;
   const int64_t nblk_alloc = conv_pass_blocks(cd);
@@ -864,10 +940,10 @@ static hipError_t ws_launch(const ConvDims& cd, int grid, const float* taps, con
                      cd.ldD, cd.K, cd.nt, cd.tilesX, ntiles, static_cast<const float*>(P0),                        \
                      static_cast<const float*>(R0), static_cast<const float*>(Q0), static_cast<float*>(X),         \
                      static_cast<float*>(P1), static_cast<float*>(R1), static_cast<float*>(Q1), pm0, rm0, qm0, xm, \
-                     pm1, rm1, qm1, alpha, beta, minv, red, nblk_alloc, st)
+                     pm1, rm1, qm1, alpha, beta, minv, red, nblk_alloc, st, b0, seed, t)
 #define COFEM_WS_CASE(KS)                       \
   case KS:                                      \
-    if constexpr (MD == kWsApply)               \
+    if constexpr (MD == kWsApply || MD == kWsResid) \
       COFEM_WS_LAUNCH(KS, false); /* no M^-1 */ \
     else if (minv)                              \
       COFEM_WS_LAUNCH(KS, true);                \
@@ -901,6 +977,24 @@ hipError_t conv_pass_ws(const ConvDims& cd, int grid, const float* taps, const v
                                nullptr, nullptr, nullptr, nullptr, qm, alpha, beta, nullptr, red, st, s);
   return ws_launch<kWsPass>(cd, grid, taps, P, R, nullptr, nullptr, nullptr, nullptr, Q, pm, rm, nullptr, nullptr,
                             nullptr, nullptr, qm, alpha, beta, minv, red, st, s);
+}
+
+hipError_t conv_init_ws(const ConvDims& cd, int grid, const float* taps, uint64_t seed, int t, const double* b0,
+                        const float* minv, const void* X, const double* xm, void* R, void* P, double* rm,
+                        double* pm, const float* alpha, double beta, const ConvReduce& red, CgScalars* st,
+                        hipStream_t s) {
+  if (cd.perm != 0) return hipErrorInvalidValue;  // the probe words assume the natural order
+  return ws_launch<kWsInit>(cd, grid, taps, X, nullptr, nullptr, nullptr, P, R, nullptr, xm, nullptr, nullptr,
+                            nullptr, pm, rm, nullptr, alpha, beta, minv, red, st, s, b0, seed, t);
+}
+
+hipError_t conv_resid_ws(const ConvDims& cd, int grid, const float* taps, uint64_t seed, int t, const double* b0,
+                         const void* X, const double* xm, const float* alpha, double beta, const ConvReduce& red,
+                         CgScalars* st, hipStream_t s) {
+  if (cd.perm != 0) return hipErrorInvalidValue;
+  return ws_launch<kWsResid>(cd, grid, taps, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, xm, nullptr,
+                             nullptr, nullptr, nullptr, nullptr, nullptr, alpha, beta, nullptr, red, st, s, b0, seed,
+                             t);
 }
 
 }  // namespace cofem
