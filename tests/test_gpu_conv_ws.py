@@ -17,9 +17,15 @@ several-task shapes run it here:
   (plain CG, warm-started Jacobi PCG, and three tasks sharing alpha), at the
   1e-4 norm-wise and 1e-3 element-wise bars of the other step tests;
 * bit-reproducible runs (every sum is reduced in a fixed order);
-* the operator alone (the apply mode, used for the warm start's A X0 and the
-  true residual's A X): bit-equal to the per-tile kernel's q and within the
-  float32 rounding bound of the float64 oracle's A v, element by element.
+* the operator alone (the apply mode): bit-equal to the per-tile kernel's q
+  and within the float32 rounding bound of the float64 oracle's A v, element
+  by element;
+* a warm-started E-step (its start in the init mode, R = B - A X0 and
+  P = M^-1 R formed in the launch, and its true residual in the residual
+  mode): launch for launch as the per-tile kernels, two float64 tasks
+  included;
+* grids other than one workgroup per compute unit (the single-level finish
+  ticket, several units per step).
 
 The full-size 1024 x 1024 step tests (test_gpu_fullsize.py) run it too, since
 the library chooses it there.
@@ -272,6 +278,35 @@ def test_ws_other_grids_match_tile_kernel(torch_dev, grid):
     _say("ws grid", grid)
     X_t, m_t, r_t = _one_fused(torch, p, kw, "tile")
     X_w, m_w, r_w = _one_fused(torch, p, kw, f"ws:{grid}")
+    assert np.array_equal(X_w, X_t)
+    assert relerr(m_w, m_t) < 1e-13
+    assert abs(r_w - r_t) <= 1e-12 * r_t
+
+
+def _warm_second_step(torch, p, kw, mode):
+    """A first E-step, then a warm-started second one, both stopped after two
+    CG iterations: the second starts with the init mode (R, P from A X0) and
+    ends with the residual mode (the true residual)."""
+    with _kernel(mode):
+        with _ctx(torch, p, **kw) as g:
+            g.set_fixed_cg_iters(2)
+            g.em_step(1)
+            st = g.em_step(1)[0]
+            X, _ = g.solution()
+            means = g.means().cpu().numpy().astype(np.float64)
+    return X.cpu().numpy(), means, st["rel_resid"]
+
+
+@pytest.mark.parametrize("case", ["200x328_k5_K5_ragged", "96x160_k5_T3"])
+def test_ws_warm_start_and_residual_match_tile_kernel(torch_dev, case):
+    torch = torch_dev
+    mk, kw = _SHAPES[case]
+    p = mk()
+    assert kw.get("warm_start")
+    _say("ws warm start + residual vs tile", case)
+    X_t, m_t, r_t = _warm_second_step(torch, p, kw, "tile")
+    X_w, m_w, r_w = _warm_second_step(torch, p, kw, "ws")
+    _say(case, "probe entries differing", int((X_t != X_w).sum()), "mean relerr", relerr(m_w, m_t), "ratio", r_t, r_w)
     assert np.array_equal(X_w, X_t)
     assert relerr(m_w, m_t) < 1e-13
     assert abs(r_w - r_t) <= 1e-12 * r_t
