@@ -777,11 +777,11 @@ hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const doubl
 }
 
 // ------------------------------------------------ diagonal estimate + M-step (Eq. 6, Eq. 8)
-// 512 threads per block (conv_update_blocks blocks), each taking its pixels
+// 1024 threads per block (conv_update_blocks blocks), each taking its pixels
 // kMsGroup at a time: the group's probe-column loads are issued together, so
 // a thread has 4 K loads in flight instead of K (the launch is one block per
 // compute unit, and with one pixel at a time it waited on every load).
-constexpr int kMsThreads = 512, kMsGroup = 4;
+constexpr int kMsThreads = 1024, kMsGroup = 4;
 template <typename TP>
 __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ldD, int K, int perm, int nt,
                                                            uint64_t seed, int t, const TP* __restrict__ X,
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
       sdiag[d] = (float)s;
     }
   }
-  __shared__ double shm[8];
+  __shared__ double shm[kMsThreads / 64];
   __shared__ double mine[3], tot[3];
   const double v0 = block_sum(clamped, shm);
   const double v1 = block_sum(dg2, shm);
