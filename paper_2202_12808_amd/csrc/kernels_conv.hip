@@ -681,13 +681,14 @@ hipError_t conv_init_pcg(const ConvDims& cd, uint64_t seed, int t, const double*
 // Starting block X0 = [max(d0, 0) (.) p_1 .. max(d0, 0) (.) p_K | mu0] (d0 null:
 // zero probe columns; mu0 null: keep xm as it is, the previous solve's mean
 // column).
+// Grid: x over the pixels, y over the columns (no 64-bit division per element).
 template <typename TP>
 __global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, int nt, uint64_t seed, int t,
                              const float* __restrict__ d0, const double* __restrict__ mu0, TP* __restrict__ X,
                              double* __restrict__ xm) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= D * (K + nt)) return;
-  const int64_t k = idx / D, d = idx - (idx / D) * D;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (d >= D) return;
   if (k >= K) {  // mean column k - K
     if (mu0) xm[(k - K) * ldD + d] = mu0[(k - K) * ldD + d];
   } else {
@@ -698,8 +699,7 @@ __global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, int nt, ui
 
 hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
                       double* xm, hipStream_t s) {
-  const int64_t tot = cd.D * (cd.K + cd.nt);
-  const dim3 grid((unsigned)((tot + 255) / 256));
+  const dim3 grid((unsigned)((cd.D + 255) / 256), (unsigned)(cd.K + cd.nt));
   if (cd.fp64)
     hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, d0, mu0,
                        static_cast<double*>(X), xm);
