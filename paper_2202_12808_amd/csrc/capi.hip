@@ -139,10 +139,13 @@ struct cofem_ctx {
   ConvReduce red_init{}, red_upd{}, red_pass{};
   CgScalars* st = nullptr;
   CgScalars* host_st = nullptr;  // pinned
+  CgScalars* host_end = nullptr; // pinned (host_st + 1): the state after an EM iteration's M-step
   // outputs of the last E-step / M-step
   float *mu = nullptr, *sdiag = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t ev_state = nullptr;  // completion of the state copy of a poll
+  hipEvent_t ev_end = nullptr;    // completion of the copy into host_end
+  hipEvent_t ev0_alt = nullptr;   // the next EM iteration's start while one is finished
   double t0_host = 0.0;           // host clock at the start of an EM iteration
   // optional per-kernel timing: one event before each timed launch, an end
   // marker after the last; CG iterations timed every kt_every-th
@@ -255,6 +258,8 @@ void destroy_ctx(cofem_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->ev_state) (void)hipEventDestroy(c->ev_state);
+  if (c->ev_end) (void)hipEventDestroy(c->ev_end);
+  if (c->ev0_alt) (void)hipEventDestroy(c->ev0_alt);
   for (hipEvent_t e : c->kev) (void)hipEventDestroy(e);
   if (BatchHost* b = c->batch) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -955,13 +960,25 @@ cofem_status cg_mark(cofem_ctx* c, bool samp, int slot, int iter) { return samp 
 // Adds the recorded launches of a finished EM iteration to the totals.  CG
 // launches enqueued after the solve stopped (they return at once) are not
 // counted: `iters` is the solve's CG count.
-cofem_status collect_times(cofem_ctx* c, int iters) {
-  if (!c->ktime || c->kev_used < 2) {
-    c->kev_used = 0;
-    return COFEM_OK;
-  }
-  COFEM_HIP(c, hipEventSynchronize(c->kev[c->kev_used - 1]));
-  for (size_t i = 0; i + 1 < c->kev_used; ++i) {
+// Reads the first `n_marks` marks (all by default) and drops them; marks
+// recorded after them (the next EM iteration's start) move to the front.
+cofem_status collect_times(cofem_ctx* c, int iters, size_t n_marks = SIZE_MAX) {
+  const size_t n = n_marks < c->kev_used ? n_marks : c->kev_used;
+  struct Drop {
+    cofem_ctx* c;
+    size_t n;
+    ~Drop() {
+      if (n < c->kev_used) {
+        std::rotate(c->kev.begin(), c->kev.begin() + n, c->kev.begin() + c->kev_used);
+        std::rotate(c->kev_slot.begin(), c->kev_slot.begin() + n, c->kev_slot.begin() + c->kev_used);
+        std::rotate(c->kev_iter.begin(), c->kev_iter.begin() + n, c->kev_iter.begin() + c->kev_used);
+      }
+      c->kev_used -= n;
+    }
+  } drop{c, n};
+  if (!c->ktime || n < 2) return COFEM_OK;
+  COFEM_HIP(c, hipEventSynchronize(c->kev[n - 1]));
+  for (size_t i = 0; i + 1 < n; ++i) {
     const int slot = c->kev_slot[i];
     if (slot < 0 || slot >= COFEM_KT_SLOTS) continue;
     if ((slot == COFEM_KT_PASS1 || slot == COFEM_KT_PASS2 || slot == COFEM_KT_UPDATE) && c->kev_iter[i] >= iters)
@@ -971,7 +988,6 @@ cofem_status collect_times(cofem_ctx* c, int iters) {
     c->kt_ms[slot] += ms;
     c->kt_n[slot] += 1;
   }
-  c->kev_used = 0;
   return COFEM_OK;
 }
 
@@ -1188,6 +1204,31 @@ cofem_status poll_state(cofem_ctx* c, bool ahead, bool lowp, int* extra) {
   return COFEM_OK;
 }
 
+// Launch plan of a solve.  The first chunk is the previous solve's launch
+// count (CG counts drift slowly across EM iterations), so that the poll after
+// it sees the stop when the count is unchanged; a cold solve starts with
+// `poll` launches.  `folded` is the launch a solve has beyond its updates.
+int first_chunk(const cofem_ctx* c, int folded, int limit) {
+  const int chunk = c->prev_iters > 0 ? c->prev_iters + folded : c->poll;
+  return chunk < limit ? chunk : limit;
+}
+
+// The chunk after the `misses`-th poll that did not see the stop (`extra`:
+// the launch that poll enqueued ahead).  A predicted solve that ran past the
+// previous count is near its end: chunks of 1, 2, 4, ... launches (the poll's
+// own launch ahead included) up to `poll`; a cold one takes `poll` at a time.
+// Never past the cap, and never an empty round once the cap is reached (no
+// launch ahead then).
+int next_chunk(const cofem_ctx* c, bool predicted, int misses, int extra, int enqueued, int limit) {
+  int want = c->poll;
+  if (predicted && misses <= 16 && (1 << (misses - 1)) < want) want = 1 << (misses - 1);
+  int chunk = want - extra;
+  if (chunk < 0) chunk = 0;
+  if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
+  if (chunk == 0 && enqueued >= limit) chunk = 1;
+  return chunk;
+}
+
 // Mixed-precision E-step (COFEM_PREC_BF16_IR): iterative refinement.  X = 0,
 // R = B; each sweep solves A~ D = R by CG with the bfloat16 Phi to the inner
 // tolerance (relative to ||R||_F), adds D to X, and forms the outer residual
@@ -1347,9 +1388,9 @@ cofem_status em_iteration_dense_warm(cofem_ctx* c, cofem_iter_stats* out) {
     COFEM_HIP(c, hipMemsetAsync(c->xtm, 0, sizeof(double) * dd.Dp, c->stream));
   }
   const int limit = c->fixed_iters > 0 ? c->fixed_iters : c->U;
-  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 : c->poll;
-  if (chunk > limit) chunk = limit;
-  int enqueued = 0;
+  const bool predicted = c->prev_iters > 0;
+  int chunk = first_chunk(c, 0, limit);
+  int enqueued = 0, misses = 0;
   for (;;) {
     if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk));
     enqueued += chunk;
@@ -1358,8 +1399,7 @@ cofem_status em_iteration_dense_warm(cofem_ctx* c, cofem_iter_stats* out) {
     enqueued += extra;
     if (c->host_st->stop) break;
     if (enqueued > limit + 2) return fail(c, COFEM_ERR_DEVICE, "CG did not report completion after the iteration cap");
-    chunk = c->poll - extra;
-    if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
+    chunk = next_chunk(c, predicted, ++misses, extra, enqueued, limit);
   }
   if (c->host_st->numeric_error)
     return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
@@ -1410,14 +1450,25 @@ cofem_status em_iteration_dense_warm(cofem_ctx* c, cofem_iter_stats* out) {
   return COFEM_OK;
 }
 
-cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
-  if (c->batch) return em_iteration_batch(c, out);
-  if (c->precision == COFEM_PREC_BF16_IR) return em_iteration_ir(c, out);
-  if (c->kind == COFEM_DENSE && (c->flags & COFEM_FLAG_WARM_PREV)) return em_iteration_dense_warm(c, out);
+// The plain EM iteration in three parts, so that a run of EM iterations can
+// enqueue the start of the next one before it waits for the end of this one
+// (the GPU then runs that start while the host reads this one's results):
+// em_begin (iteration clock, the solve's start), em_solve (CG with its polls,
+// the final checks, the M-step, an asynchronous copy of the state) and
+// em_finish (waits for that copy; kernel times and statistics).
+struct EmPending {
+  int iters = 0;           // the solve's CG count
+  size_t marks = 0;        // timing marks of this iteration (the first ones recorded)
+  hipEvent_t e0 = nullptr; // the iteration's start event
+  double t0_host = 0.0;
+};
+
+// `keep_marks`: timing marks of an earlier iteration are still to be read.
+cofem_status em_begin(cofem_ctx* c, bool keep_marks) {
   const int t = c->t_next;
   COFEM_TRY(iter_start(c));
   c->cg_enq = 0;
-  c->kev_used = 0;
+  if (!keep_marks) c->kev_used = 0;
   COFEM_TRY(mark(c, COFEM_KT_INIT, 0));
   if (c->kind == COFEM_DENSE) {
     COFEM_TRY(dense_set_minv(c));
@@ -1430,14 +1481,18 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     COFEM_HIP(c, conv_init(c->cd, c->seed, t, c->b0, c->vX, c->vR, c->vP, c->xm, c->rm, c->pm, c->red_init,
                            c->st, c->stream));
   }
+  return COFEM_OK;
+}
+
+cofem_status em_solve(cofem_ctx* c, EmPending* pd) {
+  const int t = c->t_next;
   // launches per solve: conv needs one more than its updates (the first
   // operator pass)
-  const int limit = (c->fixed_iters > 0 ? c->fixed_iters : c->U) + (folded_update(c) ? 1 : 0);
-  // First chunk: the previous solve's count (CG counts drift slowly across EM
-  // iterations), then `poll`-sized chunks until the device flag says stop.
-  int chunk = c->prev_iters > 1 ? c->prev_iters - 1 + (folded_update(c) ? 1 : 0) : c->poll;
-  if (chunk > limit) chunk = limit;
-  int enqueued = 0;
+  const int folded = folded_update(c) ? 1 : 0;
+  const int limit = (c->fixed_iters > 0 ? c->fixed_iters : c->U) + folded;
+  const bool predicted = c->prev_iters > 0;
+  int chunk = first_chunk(c, folded, limit);
+  int enqueued = 0, misses = 0;
   for (;;) {
     if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk));
     enqueued += chunk;
@@ -1447,11 +1502,11 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
     if (c->host_st->stop) break;
     if (enqueued > limit + 2)
       return fail(c, COFEM_ERR_DEVICE, "CG did not report completion after the iteration cap");
-    chunk = c->poll - extra;
-    if (enqueued + chunk > limit) chunk = limit - enqueued > 0 ? limit - enqueued : 1;
+    chunk = next_chunk(c, predicted, ++misses, extra, enqueued, limit);
   }
   if (c->host_st->numeric_error)
     return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
+  const int iters = c->host_st->iter;  // launches after the stop return at once
   if (c->true_resid) COFEM_TRY(true_residual(c, t));
   COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
   if (c->kind == COFEM_DENSE)
@@ -1468,25 +1523,88 @@ cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
   c->alpha_uniform = false;
   COFEM_TRY(mark(c, -1, 0));
   COFEM_TRY(iter_end(c));
-  COFEM_TRY(read_state(c));
-  // (a conv solve of n updates has n + 1 working launches)
-  COFEM_TRY(collect_times(c, c->host_st->iter + (folded_update(c) ? 1 : 0)));
+  CgScalars* end = c->host_end ? c->host_end : c->host_st;
+  COFEM_HIP(c, hipMemcpyAsync(end, c->st, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+  if (c->ev_end) COFEM_HIP(c, hipEventRecord(c->ev_end, c->stream));
+  pd->iters = iters;
+  pd->marks = c->kev_used;
+  pd->e0 = c->ev0;
+  pd->t0_host = c->t0_host;
   c->has_solution = true;
-  c->prev_iters = c->host_st->iter;
+  c->prev_iters = iters;
   c->t_next = t + 1;
+  return COFEM_OK;
+}
+
+cofem_status em_finish(cofem_ctx* c, const EmPending& pd, int t, cofem_iter_stats* out) {
+  if (c->ev_end)
+    COFEM_HIP(c, hipEventSynchronize(c->ev_end));
+  else
+    COFEM_HIP(c, hipStreamSynchronize(c->stream));
+  const CgScalars* end = c->host_end ? c->host_end : c->host_st;
+  // (a conv solve of n updates has n + 1 working launches)
+  COFEM_TRY(collect_times(c, pd.iters + (folded_update(c) ? 1 : 0), pd.marks));
   if (out) {
     float ms = 0.0f;
-    COFEM_TRY(iter_ms(c, &ms));
+    if (pd.e0 && c->ev1)
+      COFEM_HIP(c, hipEventElapsedTime(&ms, pd.e0, c->ev1));
+    else
+      ms = (float)(host_ms() - pd.t0_host);
     out->t = t;
-    out->cg_iters = c->host_st->iter;
-    out->converged = c->host_st->ratio < c->tol ? 1 : 0;
-    out->n_clamped = c->host_st->n_clamped;
-    out->rel_resid = c->host_st->ratio;
+    out->cg_iters = end->iter;
+    out->converged = end->ratio < c->tol ? 1 : 0;
+    out->n_clamped = end->n_clamped;
+    out->rel_resid = end->ratio;
     out->ms = ms;
-    out->rel_resid_true = c->true_resid ? c->host_st->true_ratio : -1.0;
+    out->rel_resid_true = c->true_resid ? end->true_ratio : -1.0;
     out->ir_sweeps = 0;
-    out->gamma_change = c->host_st->gamma_change;
-    if (c->per_col) out->converged = c->host_st->all_done;
+    out->gamma_change = end->gamma_change;
+    if (c->per_col) out->converged = end->all_done;
+  }
+  return COFEM_OK;
+}
+
+// Whether an EM iteration takes the plain path (em_begin / em_solve / em_finish).
+bool plain_em(const cofem_ctx* c) {
+  return !c->batch && c->precision != COFEM_PREC_BF16_IR &&
+         !(c->kind == COFEM_DENSE && (c->flags & COFEM_FLAG_WARM_PREV));
+}
+
+cofem_status em_iteration(cofem_ctx* c, cofem_iter_stats* out) {
+  if (c->batch) return em_iteration_batch(c, out);
+  if (c->precision == COFEM_PREC_BF16_IR) return em_iteration_ir(c, out);
+  if (c->kind == COFEM_DENSE && (c->flags & COFEM_FLAG_WARM_PREV)) return em_iteration_dense_warm(c, out);
+  const int t = c->t_next;
+  EmPending pd;
+  COFEM_TRY(em_begin(c, false));
+  COFEM_TRY(em_solve(c, &pd));
+  return em_finish(c, pd, t, out);
+}
+
+// n EM iterations of the plain path, each one's start enqueued before the
+// previous one's end is read.  The device work and its order are those of n
+// calls of em_iteration; only the host waits move.
+cofem_status em_iterations_pipelined(cofem_ctx* c, int n, cofem_iter_stats* stats) {
+  if (n <= 0) return COFEM_OK;
+  if (c->t_next >= (1 << 16)) return fail(c, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
+  COFEM_TRY(em_begin(c, false));
+  for (int i = 0; i < n; ++i) {
+    const int t = c->t_next;
+    EmPending pd;
+    COFEM_TRY(em_solve(c, &pd));
+    cofem_status next = COFEM_OK;
+    if (i + 1 < n) {
+      if (c->t_next >= (1 << 16)) {
+        next = fail(c, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
+      } else {
+        // the next iteration's clock starts on the spare event: pd.e0 still
+        // holds this one's start
+        std::swap(c->ev0, c->ev0_alt);
+        next = em_begin(c, true);
+      }
+    }
+    COFEM_TRY(em_finish(c, pd, t, stats ? &stats[i] : nullptr));
+    if (next != COFEM_OK) return next;
   }
   return COFEM_OK;
 }
@@ -1603,7 +1721,10 @@ cofem_status cofem_init(const cofem_problem* problems, int32_t n_problems, const
   if (e == hipSuccess) e = hipEventCreate(&c->ev0);
   if (e == hipSuccess) e = hipEventCreate(&c->ev1);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_state, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->host_st), sizeof(CgScalars));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_end, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&c->ev0_alt);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&c->host_st), 2 * sizeof(CgScalars));
+  if (e == hipSuccess) c->host_end = c->host_st + 1;
   if (e != hipSuccess) {
     s = fail(c, COFEM_ERR_DEVICE, std::string("HIP set-up: ") + hipGetErrorString(e));
   }
@@ -1681,6 +1802,12 @@ cofem_status cofem_em_step_static(const cofem_problem* problem, const cofem_para
 cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats) {
   if (!ctx) return fail(nullptr, COFEM_ERR_INVALID_ARG, "ctx is null");
   if (n_iters < 0) return fail(ctx, COFEM_ERR_INVALID_ARG, "n_iters < 0");
+  if (plain_em(ctx) && ctx->ev_end && ctx->ev0_alt && ctx->host_end) {
+    const cofem_status s = em_iterations_pipelined(ctx, n_iters, stats);
+    // a failed E-step may leave non-finite iterates: no later solve starts there
+    if (s != COFEM_OK) forget_solution(ctx);
+    return s;
+  }
   for (int i = 0; i < n_iters; ++i) {
     if (ctx->t_next >= (1 << 16)) return fail(ctx, COFEM_ERR_INVALID_ARG, "EM iteration index beyond 65535");
     const int np = ctx->batch ? ctx->batch->n : 1;

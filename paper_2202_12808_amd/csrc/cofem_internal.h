@@ -88,6 +88,23 @@ __device__ __forceinline__ float probe_sign(uint64_t seed, uint32_t t, uint32_t 
   return ((w >> (j & 63)) & 1ull) ? -1.0f : 1.0f;
 }
 
+// ||h||^2 in float64, the taps summed in order (every column of the
+// convolution dictionary has this norm); loads go out in batches of 9 so a
+// thread does not wait on each tap in turn.
+__device__ __forceinline__ double taps_sq_sum(const float* __restrict__ taps, int ntaps) {
+  double hh = 0.0;
+  int i = 0;
+  for (; i + 9 <= ntaps; i += 9) {
+    float tv[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) tv[u] = taps[i + u];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) hh += (double)tv[u] * (double)tv[u];
+  }
+  for (; i < ntaps; ++i) hh += (double)taps[i] * (double)taps[i];
+  return hh;
+}
+
 template <typename T>
 __device__ __forceinline__ T load_agent(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -688,13 +688,24 @@ __global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, int nt, ui
                              double* __restrict__ xm) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = blockIdx.y;
-  if (d >= D) return;
   if (k >= K) {  // mean column k - K
-    if (mu0) xm[(k - K) * ldD + d] = mu0[(k - K) * ldD + d];
-  } else {
-    const float dv = d0 ? fmaxf(d0[d], 0.0f) : 0.0f;
-    X[k * ldD + d] = (TP)(dv * probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d)));
+    if (d < D && mu0) xm[(k - K) * ldD + d] = mu0[(k - K) * ldD + d];
+    return;
   }
+  float sg;
+  if (perm == 0) {
+    // natural order: a wave's 64 pixels (from a multiple of 64, d & 63 =
+    // lane) share one SplitMix64 word of probe k, formed once per wave
+    const uint64_t j6 = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)d >> 6));
+    const uint64_t idx = ((uint64_t)t << 48) | ((uint64_t)k << 32) | j6;
+    const uint64_t w = splitmix64_mix(seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull);
+    sg = ((w >> (d & 63)) & 1ull) ? -1.0f : 1.0f;
+  } else {
+    sg = probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d));
+  }
+  if (d >= D) return;
+  const float dv = d0 ? fmaxf(d0[d], 0.0f) : 0.0f;
+  X[k * ldD + d] = (TP)(dv * sg);
 }
 
 hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
@@ -714,8 +725,7 @@ __global__ void k_conv_jacobi(int64_t D, const float* __restrict__ taps, int nta
                               const float* __restrict__ alpha, float* __restrict__ minv) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= D) return;
-  double hh = 0.0;
-  for (int i = 0; i < ntaps; ++i) hh += (double)taps[i] * (double)taps[i];
+  const double hh = taps_sq_sum(taps, ntaps);
   minv[d] = (float)(1.0 / (beta * hh + (double)alpha[d]));
 }
 

@@ -469,9 +469,7 @@ __global__ void k_net_features(const float* __restrict__ alpha, const float* __r
                                float* __restrict__ aux) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= HW) return;
-  double hh = 0.0;
-  for (int i = 0; i < ntaps; ++i) hh += (double)taps[i] * (double)taps[i];
-  const double bh = beta * hh;
+  const double bh = beta * taps_sq_sum(taps, ntaps);
   const double a = alpha[p], d = bh + a;
   double rms = sqrt(musq[0] / (double)HW);
   if (!(rms > 0.0)) rms = 1.0;

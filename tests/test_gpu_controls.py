@@ -280,3 +280,51 @@ def test_caller_workspace_batched_and_too_small(torch_dev):
         CoFEM.dense(torch.from_numpy(p.phi).cuda(), torch.from_numpy(p.y).cuda(), p.beta, p.K, tol=p.tol,
                     workspace=small[off:off + n - 1])
     assert ei.value.status == C.COFEM_ERR_OUT_OF_MEMORY
+
+
+# ------------------------------------------------------------------ several EM iterations per call
+_PIPE_FORMS = {
+    "dense_plain": (lambda: synth.dense_problem(200, 700, nnz=8, beta=1e3, K=12, tol=1e-5, seed=12), {}),
+    "conv_plain_ragged": (lambda: synth.conv_problem(40, 36, 5, rho=0.03, beta=1e3, K=8, tol=1e-5, seed=12), {}),
+    "conv_warm_jacobi": (lambda: synth.conv_problem(40, 36, 5, rho=0.03, beta=1e3, K=8, tol=1e-5, seed=12),
+                         {"warm_start": True, "jacobi": True}),
+    "conv_learned": (lambda: synth.conv_problem(64, 32, 5, rho=0.03, beta=1e3, K=8, tol=1e-5, seed=12),
+                     {"spectral_start": True}),
+    "dct_warm_jacobi": (lambda: synth.dct_problem(4096, rho=0.04, beta=4e4, K=6, tol=1e-5, seed=12),
+                        {"warm_start": True, "jacobi": True}),
+}
+
+
+@pytest.mark.parametrize("form", sorted(_PIPE_FORMS))
+def test_em_steps_in_one_call_equal_single_calls(torch_dev, form):
+    # cofem_em_step(n) enqueues each EM iteration's start before it reads the
+    # previous one's end; the device work is that of n calls of one
+    # iteration: the same statistics (host clock aside), the same posterior
+    # bits and the same timed launches
+    torch = torch_dev
+    from paper_2202_12808_amd.cofem import CoFEMNet
+    mk, kw = _PIPE_FORMS[form]
+    p = mk()
+    _say("em_step(n) vs n x em_step(1)", form)
+    net = CoFEMNet(p.H, p.W, seed=5) if form == "conv_learned" else None
+    runs = []
+    with _ctx(torch, p, **kw) as g:
+        if net is not None:
+            g.set_predictor(net)
+        for one_by_one in (False, True):
+            g.restart()
+            g.set_kernel_timing(1)
+            st = [g.em_step(1)[0] for _ in range(5)] if one_by_one else g.em_step(5)
+            kt = g.kernel_timing()
+            g.set_kernel_timing(0)
+            runs.append((st, kt, [x.cpu().numpy() for x in g.posterior()], [x.cpu().numpy() for x in g.solution()]))
+    if net is not None:
+        net.close()
+    (st_a, kt_a, post_a, sol_a), (st_b, kt_b, post_b, sol_b) = runs
+    _say("cg", [x["cg_iters"] for x in st_a], [x["cg_iters"] for x in st_b])
+    for a, b in zip(st_a, st_b):
+        assert {k: v for k, v in a.items() if k != "ms"} == {k: v for k, v in b.items() if k != "ms"}
+        assert a["ms"] > 0.0 and b["ms"] > 0.0
+    assert {k: v[1] for k, v in kt_a.items()} == {k: v[1] for k, v in kt_b.items()}
+    for a, b in zip(post_a + sol_a, post_b + sol_b):
+        assert np.array_equal(a, b)
