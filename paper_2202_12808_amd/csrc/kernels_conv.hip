@@ -708,8 +708,54 @@ __global__ void k_conv_start(int64_t D, int64_t ldD, int K, int perm, int nt, ui
   X[k * ldD + d] = (TP)(dv * sg);
 }
 
+// The same start, four pixels per thread with 16-byte accesses (natural
+// order, D and ldD multiples of 4): a quarter of the blocks, and one
+// SplitMix64 word per thread (its four signs are bits d & 63 .. + 3).
+template <typename TP>
+__global__ void k_conv_start4(int64_t D, int64_t ldD, int K, uint64_t seed, int t, const float* __restrict__ d0,
+                              const double* __restrict__ mu0, TP* __restrict__ X, double* __restrict__ xm) {
+  const int64_t d = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const int64_t k = blockIdx.y;
+  if (d >= D) return;
+  if (k >= K) {  // mean column k - K
+    if (mu0) {
+      const double2* src = reinterpret_cast<const double2*>(mu0 + (k - K) * ldD + d);
+      double2* dst = reinterpret_cast<double2*>(xm + (k - K) * ldD + d);
+      const double2 a = src[0], b = src[1];
+      dst[0] = a;
+      dst[1] = b;
+    }
+    return;
+  }
+  const uint64_t idx = ((uint64_t)t << 48) | ((uint64_t)k << 32) | ((uint64_t)d >> 6);
+  const uint32_t bits = (uint32_t)(splitmix64_mix(seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull) >> (d & 63));
+  float4 dv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (d0) dv = *reinterpret_cast<const float4*>(d0 + d);
+  const float x0 = fmaxf(dv.x, 0.0f) * ((bits & 1u) ? -1.0f : 1.0f);
+  const float x1 = fmaxf(dv.y, 0.0f) * ((bits & 2u) ? -1.0f : 1.0f);
+  const float x2 = fmaxf(dv.z, 0.0f) * ((bits & 4u) ? -1.0f : 1.0f);
+  const float x3 = fmaxf(dv.w, 0.0f) * ((bits & 8u) ? -1.0f : 1.0f);
+  TP* out = X + k * ldD + d;
+  if constexpr (sizeof(TP) == 4) {
+    *reinterpret_cast<float4*>(out) = make_float4(x0, x1, x2, x3);
+  } else {
+    reinterpret_cast<double2*>(out)[0] = make_double2(x0, x1);
+    reinterpret_cast<double2*>(out)[1] = make_double2(x2, x3);
+  }
+}
+
 hipError_t conv_start(const ConvDims& cd, uint64_t seed, int t, const float* d0, const double* mu0, void* X,
                       double* xm, hipStream_t s) {
+  if (cd.perm == 0 && cd.D % 4 == 0 && cd.ldD % 4 == 0) {
+    const dim3 grid4((unsigned)((cd.D / 4 + 255) / 256), (unsigned)(cd.K + cd.nt));
+    if (cd.fp64)
+      hipLaunchKernelGGL(k_conv_start4<double>, grid4, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, d0, mu0,
+                         static_cast<double*>(X), xm);
+    else
+      hipLaunchKernelGGL(k_conv_start4<float>, grid4, dim3(256), 0, s, cd.D, cd.ldD, cd.K, seed, t, d0, mu0,
+                         static_cast<float*>(X), xm);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)((cd.D + 255) / 256), (unsigned)(cd.K + cd.nt));
   if (cd.fp64)
     hipLaunchKernelGGL(k_conv_start<double>, grid, dim3(256), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t, d0, mu0,

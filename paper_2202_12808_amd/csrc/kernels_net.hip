@@ -516,6 +516,9 @@ struct cofem_net {
   float *g0 = nullptr, *g1 = nullptr, *wt = nullptr, *wpart = nullptr;
   float *feats = nullptr, *aux = nullptr;  // predictor scratch
   uint16_t* wbf = nullptr;                 // bfloat16 weights of the MFMA forward pass
+  bool wbf_ok = false;                     // wbf holds the current theta (cleared where theta changes)
+  hipEvent_t ev_pack = nullptr;            // end of the last packing of wbf ...
+  hipStream_t pack_stream = nullptr;       // ... on this stream
   uint16_t* actb[2] = {};                  // its bfloat16 activations, pixel-major, 32 channels
   double *dpart = nullptr, *dscal = nullptr;
   int step = 0;
@@ -554,6 +557,10 @@ cofem_status net_alloc(cofem_net* n, T** p, size_t count) {
 void net_free(cofem_net* n) {
   if (!n) return;
   if (n->stream) (void)hipStreamSynchronize(n->stream);
+  if (n->ev_pack) {
+    (void)hipEventSynchronize(n->ev_pack);
+    (void)hipEventDestroy(n->ev_pack);
+  }
   for (void* p : n->allocs) (void)hipFree(p);
   delete n;
 }
@@ -602,22 +609,34 @@ cofem_status net_forward_impl(cofem_net* n, const float* feats) {
   return COFEM_OK;
 }
 
-// The forward pass on bfloat16 MFMA (inference): weights packed per layer,
-// then one implicit-GEMM launch per layer into act[1..4].
+// The forward pass on bfloat16 MFMA (inference): the weights packed per
+// layer when theta has changed since the last packing, then one
+// implicit-GEMM launch per layer into act[1..4].
 cofem_status net_forward_bf16_impl(cofem_net* n, const float* feats) {
+  auto layer_kp = [](int l) { return l == 0 ? MfmaGeom<8>::KP : MfmaGeom<32>::KP; };
+  if (!n->wbf_ok) {
+    int64_t off = 0;
+    for (int l = 0; l < kNetLayers; ++l) {
+      const int ci = kNetCh[l], co = kNetCh[l + 1], KP = layer_kp(l);
+      hipLaunchKernelGGL(k_net_pack_bf16, dim3((unsigned)((32 * KP + 255) / 256)), dim3(256), 0, n->stream,
+                         n->theta + layer_offset(l), ci, co, l == 0 ? 8 : 32, KP, n->wbf + off);
+      off += 32 * KP;
+    }
+    NET_HIP(hipGetLastError());
+    if (!n->ev_pack) NET_HIP(hipEventCreateWithFlags(&n->ev_pack, hipEventDisableTiming));
+    NET_HIP(hipEventRecord(n->ev_pack, n->stream));
+    n->pack_stream = n->stream;
+    n->wbf_ok = true;
+  } else if (n->stream != n->pack_stream) {
+    NET_HIP(hipStreamWaitEvent(n->stream, n->ev_pack, 0));
+  }
   int64_t off = 0;
   const dim3 grid((unsigned)((n->W + kMC - 1) / kMC), (unsigned)((n->H + kMR - 1) / kMR));
   for (int l = 0; l < kNetLayers; ++l) {
     const int ci = kNetCh[l], co = kNetCh[l + 1];
-    const int64_t o = layer_offset(l);
-    const float* w = n->theta + o;
-    const float* bias = w + (int64_t)co * ci * 9;
-    const int CP = l == 0 ? 8 : 32;
-    const int KP = CP == 8 ? MfmaGeom<8>::KP : MfmaGeom<32>::KP;
-    uint16_t* wb = n->wbf + off;
-    off += 32 * KP;
-    hipLaunchKernelGGL(k_net_pack_bf16, dim3((unsigned)((32 * KP + 255) / 256)), dim3(256), 0, n->stream, w, ci, co,
-                       CP, KP, wb);
+    const float* bias = n->theta + layer_offset(l) + (int64_t)co * ci * 9;
+    const uint16_t* wb = n->wbf + off;
+    off += 32 * layer_kp(l);
     // layer 0: float32 features -> bf16 act; 1, 2: bf16 -> bf16; 3: bf16 -> float32 output
     uint16_t* ping = n->actb[l & 1];
     const uint16_t* pong = n->actb[(l + 1) & 1];
@@ -780,6 +799,7 @@ cofem_status cofem_net_set_params(cofem_net* n, const float* host_params, int64_
   NET_HIP(hipMemsetAsync(n->v, 0, sizeof(float) * count, n->stream));
   NET_HIP(hipStreamSynchronize(n->stream));
   n->step = 0;
+  n->wbf_ok = false;
   return COFEM_OK;
 }
 
@@ -826,6 +846,7 @@ cofem_status cofem_net_train_step(cofem_net* n, const float* feats, const float*
   hipLaunchKernelGGL(k_net_adam, dim3((unsigned)((n->np + 255) / 256)), dim3(256), 0, n->stream, n->theta, n->grad,
                      n->m, n->v, n->np, lr, n->step);
   NET_HIP(hipGetLastError());
+  n->wbf_ok = false;
   if (loss) {
     NET_HIP(hipMemcpyAsync(loss, n->dscal + 1, sizeof(double), hipMemcpyDeviceToHost, n->stream));
     NET_HIP(hipStreamSynchronize(n->stream));

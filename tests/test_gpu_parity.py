@@ -798,16 +798,28 @@ def test_net_bf16_forward_within_rounding_bound(torch_dev):
     torch = torch_dev
     from paper_2202_12808_amd.cofem import CoFEMNet
     H, W = 37, 45
-    theta, feats, _, _ = _net_sample(torch, H, W, seed=3)
+    theta, feats, aux, tg = _net_sample(torch, H, W, seed=3)
     net = CoFEMNet(H, W)
+    xin = torch.from_numpy(feats.reshape(5, H * W)).cuda()
+    net.forward_bf16(xin)  # packs the initial weights: set_params must replace them
     net.set_params(theta)
-    out = net.forward_bf16(torch.from_numpy(feats.reshape(5, H * W)).cuda()).cpu().numpy().reshape(2, H, W)
+    out = net.forward_bf16(xin).cpu().numpy().reshape(2, H, W)
     ref, bound = _bf16_forward_bound(theta.astype(np.float64), feats.astype(np.float64))
     err = np.abs(out.astype(np.float64) - ref)
     _say("bf16 forward: max err", float(err.max()), "max bound", float(bound.max()), "relerr", relerr(out, ref),
          "max err/bound", float(np.max(err / (bound + 1e-30))))
     assert np.all(err <= 1.05 * bound + 1e-7)
     assert relerr(out, ref) < 3e-2  # norm-wise, for the record
+    # after a training step the packed weights follow the new parameters: the
+    # same bits as a fresh net given those parameters
+    net.train_step(xin, torch.from_numpy(aux.reshape(3, H * W)).cuda(), torch.from_numpy(tg.reshape(2, H * W)).cuda(),
+                   lr=1e-2)
+    trained = net.forward_bf16(xin).cpu().numpy()
+    fresh = CoFEMNet(H, W)
+    fresh.set_params(net.get_params())
+    assert not np.array_equal(trained.reshape(2, H, W), out)
+    assert np.array_equal(trained, fresh.forward_bf16(xin).cpu().numpy())
+    fresh.close()
     net.close()
 
 
