@@ -870,27 +870,49 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
       }
     }
     // the K probe columns in order for every pixel of the group (the same
-    // summation order as one pixel at a time)
-    for (int k = 0; k < K; ++k) {
-      TP x[kMsGroup];
+    // summation order as one pixel at a time); loads unconditional (a pixel
+    // past D reads pixel D - 1; its sum is never used) so that several
+    // columns' loads are in flight
+    int64_t dc[kMsGroup];
 #pragma unroll
-      for (int g = 0; g < kMsGroup; ++g) {
-        const int64_t d = d0 + g * gstride;
-        x[g] = d < D ? X[(int64_t)k * ldD + d] : TP(0);
-      }
+    for (int g = 0; g < kMsGroup; ++g) {
+      const int64_t d = d0 + g * gstride;
+      dc[g] = d < D ? d : D - 1;
+    }
+    if (perm == 0) {
+      auto add = [&](int k, const TP* x) {
 #pragma unroll
-      for (int g = 0; g < kMsGroup; ++g) {
-        const int64_t d = d0 + g * gstride;
-        float sg;
-        if (perm == 0) {
+        for (int g = 0; g < kMsGroup; ++g) {
           const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)wk[g], k);
           const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(wk[g] >> 32), k);
           const uint64_t w = ((uint64_t)hi << 32) | lo;
-          sg = ((w >> lane) & 1ull) ? -1.0f : 1.0f;
-        } else {
-          sg = probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, d));
+          const float sg = ((w >> lane) & 1ull) ? -1.0f : 1.0f;
+          acc[g] += (double)sg * (double)x[g];
         }
-        if (d < D) acc[g] += (double)sg * (double)x[g];
+      };
+      int k = 0;
+      for (; k + 4 <= K; k += 4) {  // four columns' loads first, then their sums in order
+        TP x[4][kMsGroup];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int g = 0; g < kMsGroup; ++g) x[u][g] = X[(int64_t)(k + u) * ldD + dc[g]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(k + u, x[u]);
+      }
+      for (; k < K; ++k) {
+        TP x[kMsGroup];
+#pragma unroll
+        for (int g = 0; g < kMsGroup; ++g) x[g] = X[(int64_t)k * ldD + dc[g]];
+        add(k, x);
+      }
+    } else {
+      for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int g = 0; g < kMsGroup; ++g) {
+          const float sg = probe_sign(seed, (uint32_t)t, (uint32_t)k, (uint64_t)perm_nat(perm, dc[g]));
+          acc[g] += (double)sg * (double)X[(int64_t)k * ldD + dc[g]];
+        }
       }
     }
 #pragma unroll
