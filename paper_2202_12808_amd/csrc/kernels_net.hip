@@ -159,6 +159,17 @@ __global__ void k_net_pack_bf16(const float* __restrict__ w, int cin, int cout, 
 // staged).  OUT_BF: the output is written that way for the next layer (else
 // float32 channel-major images).  Bias and ReLU are applied in float32 before
 // the rounding, so the values match rounding at the next layer's input.
+// LDS slot of channel octet o of staged pixel pix.  With 32 channels a
+// pixel takes 64 bytes, so the B fragments of 16 neighbouring pixels (one
+// 16-byte read per lane) would share a quarter of the banks; the octet is
+// XOR-swizzled with bits 2-3 of the pixel index, which puts 16 consecutive
+// pixels on 16 distinct 16-byte bank groups.
+template <int CP>
+__device__ __forceinline__ int net_lds_off(int pix, int o) {
+  if constexpr (CP == 32) return pix * CP + 8 * (o ^ ((pix >> 2) & 3));
+  return pix * CP + 8 * o;
+}
+
 template <int CP, bool IN_BF, bool OUT_BF>
 __global__ __launch_bounds__(256) void k_net_conv3_mfma(const void* __restrict__ in_, int cin,
                                                         const uint16_t* __restrict__ wb, const float* __restrict__ b,
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(256) void k_net_conv3_mfma(const void* __restrict__
       const int e = threadIdx.x + (k0 + k) * kThreads;
       if (k0 + k < PER && e < ITEMS) {
         const int pix = e / NOCT, o = e - (e / NOCT) * NOCT;
-        *reinterpret_cast<uint4*>(s_x + pix * CP + 8 * o) = vals[k];
+        *reinterpret_cast<uint4*>(s_x + net_lds_off<CP>(pix, o)) = vals[k];
       }
     }
   }
@@ -232,7 +243,7 @@ __global__ __launch_bounds__(256) void k_net_conv3_mfma(const void* __restrict__
       const int ci0 = k0 - tap * CP;
       if (tap >= 9) tap = 0;  // padding k: zero weights, any staged value
       const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-      const uint4 bx = *reinterpret_cast<const uint4*>(s_x + ((i + ky) * SW + j + kx) * CP + ci0);
+      const uint4 bx = *reinterpret_cast<const uint4*>(s_x + net_lds_off<CP>((i + ky) * SW + j + kx, ci0 / 8));
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[st]),
                                                     __builtin_bit_cast(bf16x8, bx), acc, 0, 0, 0);
     }
