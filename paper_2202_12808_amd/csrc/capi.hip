@@ -1189,11 +1189,21 @@ cofem_status read_state(cofem_ctx* c) {
 // before waiting for the copy, so the GPU is not idle while the host reads the
 // flag.  After a stop that iteration returns at once.  Returns the number of
 // iterations it enqueued (0 or 1).
-cofem_status poll_state(cofem_ctx* c, bool ahead, bool lowp, int* extra) {
+// With `resid_t` >= 0 the launch ahead is instead the true residual of EM
+// iteration resid_t in the form that runs only if the solve has stopped (the
+// persistent conv kernel): the copy is taken just before it, so it runs
+// exactly when the host then reads the stop.
+cofem_status poll_state(cofem_ctx* c, bool ahead, bool lowp, int* extra, int resid_t = -1) {
   COFEM_HIP(c, hipMemcpyAsync(c->host_st, c->st, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
   if (c->ev_state) COFEM_HIP(c, hipEventRecord(c->ev_state, c->stream));
   *extra = 0;
-  if (ahead) {
+  if (resid_t >= 0) {
+    COFEM_TRY(close_mark(c));
+    COFEM_TRY(mark(c, COFEM_KT_CHECK, 0));
+    COFEM_HIP(c, conv_resid_ws(c->cd, c->cd.ws_grid, c->taps, c->seed, resid_t, c->b0, c->vX, c->xm, c->alpha,
+                               c->beta, c->red_pass, c->st, c->stream, true));
+    COFEM_TRY(mark(c, -1, 0));
+  } else if (ahead) {
     COFEM_TRY(run_cg_iterations(c, 1, lowp));
     *extra = 1;
   }
@@ -1491,15 +1501,24 @@ cofem_status em_solve(cofem_ctx* c, EmPending* pd) {
   const int folded = folded_update(c) ? 1 : 0;
   const int limit = (c->fixed_iters > 0 ? c->fixed_iters : c->U) + folded;
   const bool predicted = c->prev_iters > 0;
+  // where the previous count predicts the stop at the first poll, the launch
+  // ahead of it is the true residual itself (persistent conv kernel): no idle
+  // round trip between the solve and the residual
+  const bool spec_resid = predicted && c->true_resid && c->kind == COFEM_CONV2D_CIRC && c->cd.ws_grid > 0;
+  bool resid_done = false;
   int chunk = first_chunk(c, folded, limit);
   int enqueued = 0, misses = 0;
   for (;;) {
     if (chunk > 0) COFEM_TRY(run_cg_iterations(c, chunk));
     enqueued += chunk;
     int extra = 0;
-    COFEM_TRY(poll_state(c, enqueued < limit, false, &extra));
+    const bool spec = spec_resid && misses == 0;
+    COFEM_TRY(poll_state(c, enqueued < limit, false, &extra, spec ? t : -1));
     enqueued += extra;
-    if (c->host_st->stop) break;
+    if (c->host_st->stop) {
+      resid_done = spec;
+      break;
+    }
     if (enqueued > limit + 2)
       return fail(c, COFEM_ERR_DEVICE, "CG did not report completion after the iteration cap");
     chunk = next_chunk(c, predicted, ++misses, extra, enqueued, limit);
@@ -1507,7 +1526,7 @@ cofem_status em_solve(cofem_ctx* c, EmPending* pd) {
   if (c->host_st->numeric_error)
     return fail(c, COFEM_ERR_NUMERIC, "non-finite value in a CG scalar at EM iteration " + std::to_string(t));
   const int iters = c->host_st->iter;  // launches after the stop return at once
-  if (c->true_resid) COFEM_TRY(true_residual(c, t));
+  if (c->true_resid && !resid_done) COFEM_TRY(true_residual(c, t));
   COFEM_TRY(mark(c, COFEM_KT_MSTEP, 0));
   if (c->kind == COFEM_DENSE)
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,

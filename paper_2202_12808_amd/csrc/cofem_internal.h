@@ -792,9 +792,11 @@ hipError_t conv_init_ws(const ConvDims& cd, int grid, const float* taps, uint64_
                         const float* minv, const void* X, const double* xm, void* R, void* P, double* rm,
                         double* pm, const float* alpha, double beta, const ConvReduce& red, CgScalars* st,
                         hipStream_t s);
+// only_if_stopped: the launch does nothing unless the solve's stop flag is set
+// when it starts (a residual enqueued before the host has read the flag)
 hipError_t conv_resid_ws(const ConvDims& cd, int grid, const float* taps, uint64_t seed, int t, const double* b0,
                          const void* X, const double* xm, const float* alpha, double beta, const ConvReduce& red,
-                         CgScalars* st, hipStream_t s);
+                         CgScalars* st, hipStream_t s, bool only_if_stopped = false);
 hipError_t conv_pass(const ConvDims& cd, const float* taps, const void* P, const double* pm,
                      const void* R, const double* rm, const float* alpha, double beta, void* Q,
                      double* qm, const ConvReduce& red, CgScalars* st, int apply_only, hipStream_t s,

@@ -831,10 +831,13 @@ __global__ __launch_bounds__(kWsThreads) void k_conv_ws(
     const double* __restrict__ rm0, const double* __restrict__ qm0, double* __restrict__ xm,
     double* __restrict__ pm1, double* __restrict__ rm1, double* __restrict__ qm1, const float* __restrict__ alpha,
     double beta, const float* __restrict__ minv, ConvReduce red, int64_t nblk_alloc, CgScalars* __restrict__ st,
-    const double* __restrict__ b0, uint64_t seed, int tt) {
+    const double* __restrict__ b0, uint64_t seed, int tt, int only_if_stopped) {
   // a CG iteration does nothing once the solve has stopped; the other modes
-  // run at a solve's start or after it
+  // run at a solve's start or after it.  A residual launch enqueued before the
+  // host knows whether the solve has stopped (`only_if_stopped`) does nothing
+  // unless it has.
   if ((MD == kWsFused || MD == kWsPass) && st->stop) return;
+  if (MD == kWsResid && only_if_stopped && !st->stop) return;
   const CgCtl ctl = load_cg_ctl(st);
   using WG = WsGeom<KS>;
   using GF = typename WG::GF;
@@ -931,7 +934,8 @@ static hipError_t ws_launch(const ConvDims& cd, int grid, const float* taps, con
                             const void* Q0, void* X, void* P1, void* R1, void* Q1, const double* pm0,
                             const double* rm0, const double* qm0, double* xm, double* pm1, double* rm1, double* qm1,
                             const float* alpha, double beta, const float* minv, const ConvReduce& red, CgScalars* st,
-                            hipStream_t s, const double* b0 = nullptr, uint64_t seed = 0, int t = 0) {
+                            hipStream_t s, const double* b0 = nullptr, uint64_t seed = 0, int t = 0,
+                            int only_if_stopped = 0) {
   if (!conv_ws_ok(cd) || grid < 1) return hipErrorInvalidValue;
   const int ntiles = cd.tilesX * cd.tilesY;
   const int64_t nblk_alloc = conv_pass_blocks(cd);
@@ -940,7 +944,7 @@ static hipError_t ws_launch(const ConvDims& cd, int grid, const float* taps, con
                      cd.ldD, cd.K, cd.nt, cd.tilesX, ntiles, static_cast<const float*>(P0),                        \
                      static_cast<const float*>(R0), static_cast<const float*>(Q0), static_cast<float*>(X),         \
                      static_cast<float*>(P1), static_cast<float*>(R1), static_cast<float*>(Q1), pm0, rm0, qm0, xm, \
-                     pm1, rm1, qm1, alpha, beta, minv, red, nblk_alloc, st, b0, seed, t)
+                     pm1, rm1, qm1, alpha, beta, minv, red, nblk_alloc, st, b0, seed, t, only_if_stopped)
 #define COFEM_WS_CASE(KS)                       \
   case KS:                                      \
     if constexpr (MD == kWsApply || MD == kWsResid) \
@@ -990,11 +994,11 @@ hipError_t conv_init_ws(const ConvDims& cd, int grid, const float* taps, uint64_
 
 hipError_t conv_resid_ws(const ConvDims& cd, int grid, const float* taps, uint64_t seed, int t, const double* b0,
                          const void* X, const double* xm, const float* alpha, double beta, const ConvReduce& red,
-                         CgScalars* st, hipStream_t s) {
+                         CgScalars* st, hipStream_t s, bool only_if_stopped) {
   if (cd.perm != 0) return hipErrorInvalidValue;
   return ws_launch<kWsResid>(cd, grid, taps, X, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, xm, nullptr,
                              nullptr, nullptr, nullptr, nullptr, nullptr, alpha, beta, nullptr, red, st, s, b0, seed,
-                             t);
+                             t, only_if_stopped ? 1 : 0);
 }
 
 }  // namespace cofem

@@ -310,3 +310,47 @@ def test_ws_warm_start_and_residual_match_tile_kernel(torch_dev, case):
     assert np.array_equal(X_w, X_t)
     assert relerr(m_w, m_t) < 1e-13
     assert abs(r_w - r_t) <= 1e-12 * r_t
+
+
+def test_ws_residual_launched_ahead_of_the_stop_read(torch_dev):
+    # With the true residual on, the persistent kernel's residual is the launch
+    # enqueued ahead of a predicted solve's first poll, and it runs only if the
+    # solve has stopped by then.  Both outcomes: warm-started EM iterations whose
+    # counts fall (that launch is the residual), then set_alpha to another wide
+    # alpha, whose solve from the previous solution needs more iterations than
+    # the last one (that launch does nothing; the residual follows the stop).
+    # Against the per-tile path, which computes the residual in its own
+    # launches after the stop.
+    torch = torch_dev
+    p = synth.conv_problem(200, 328, 5, rho=0.02, beta=1e3, K=5, tol=1e-5, seed=12)
+    kw = {"jacobi": True, "warm_start": True}
+    a1, a2 = (np.exp(np.random.default_rng(s).uniform(np.log(1e-2), np.log(1e3), p.D)).astype(np.float32)
+              for s in (6, 7))
+    runs = {}
+    for mode in ("tile", "ws"):
+        with _kernel(mode):
+            with _ctx(torch, p, **kw) as g:
+                st = g.em_step(1)
+                g.set_alpha(torch.from_numpy(a1).cuda())
+                st += g.em_step(3)
+                g.set_alpha(torch.from_numpy(a2).cuda())
+                st += g.em_step(1)
+                runs[mode] = st
+                X, _ = g.solution()
+                runs[mode + "_X"] = X.cpu().numpy()
+    cg = [x["cg_iters"] for x in runs["ws"]]
+    _say("cg ws", cg, "tile", [x["cg_iters"] for x in runs["tile"]],
+         "true ratios ws", [x["rel_resid_true"] for x in runs["ws"]],
+         "tile", [x["rel_resid_true"] for x in runs["tile"]])
+    assert all(cg[i] <= cg[i - 1] for i in range(1, 4))  # the launch ahead found the solve stopped
+    assert cg[4] > cg[3]  # ... and running
+    assert cg == [x["cg_iters"] for x in runs["tile"]]
+    # (the two paths' float64 sums differ in order, so over several EM
+    # iterations a float32 alpha may round differently at some pixel: ratios to
+    # 1e-6; a residual taken before the last update, or one left from the
+    # previous E-step, is off by far more)
+    for w, t in zip(runs["ws"], runs["tile"]):
+        assert w["rel_resid_true"] > 0.0
+        assert abs(w["rel_resid_true"] - t["rel_resid_true"]) <= 1e-6 * t["rel_resid_true"]
+        assert abs(w["rel_resid"] - t["rel_resid"]) <= 1e-6 * t["rel_resid"]
+    assert relerr(runs["ws_X"], runs["tile_X"]) < 1e-5
