@@ -1532,12 +1532,10 @@ cofem_status em_solve(cofem_ctx* c, EmPending* pd) {
     COFEM_HIP(c, dense_mstep(c->dd, c->seed, t, c->K, c->X, c->xm, c->alpha, c->alpha_max, c->mu,
                              c->sdiag, c->parts_upd, c->cnts_upd, c->st, c->stream));
   else {
-    // the learned form's features see how far this M-step moves alpha
-    if (c->alpha_prev)
-      COFEM_HIP(c, hipMemcpyAsync(c->alpha_prev, c->alpha, sizeof(float) * c->cd.D, hipMemcpyDeviceToDevice,
-                                  c->stream));
+    // the learned form's features see how far this M-step moves alpha: the
+    // M-step keeps the old alpha in alpha_prev as it replaces it
     COFEM_HIP(c, conv_mstep(c->cd, c->seed, t, c->vX, c->xm, c->alpha, c->alpha_max, c->mu, c->sdiag,
-                            c->red_upd, c->st, c->stream));
+                            c->red_upd, c->st, c->stream, c->alpha_prev));
   }
   c->alpha_uniform = false;
   COFEM_TRY(mark(c, -1, 0));

@@ -811,9 +811,10 @@ hipError_t conv_jacobi(const ConvDims& cd, const float* taps, double beta, const
                        hipStream_t s);
 hipError_t conv_true_resid(const ConvDims& cd, uint64_t seed, int t, const double* b0, const void* Q,
                            const double* qm, const ConvReduce& red, CgScalars* st, hipStream_t s);
+// alpha_prev (may be null): receives the alpha this M-step replaces
 hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
                       float* alpha, double alpha_max, float* mu, float* sdiag, const ConvReduce& red, CgScalars* st,
-                      hipStream_t s);
+                      hipStream_t s, float* alpha_prev = nullptr);
 hipError_t conv_probes_out(const ConvDims& cd, const void* X, float* out, hipStream_t s);
 hipError_t conv_probes_in(const ConvDims& cd, const float* in, void* X, hipStream_t s);
 

@@ -845,7 +845,7 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
                                                            float* __restrict__ alpha, double alpha_max,
                                                            float* __restrict__ mu,
                                                            float* __restrict__ sdiag, double* parts, uint32_t* cnts,
-                                                           CgScalars* st) {
+                                                           CgScalars* st, float* __restrict__ alpha_prev) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
   const double floor_v = 1.0 / alpha_max;
@@ -934,9 +934,11 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
       if (!(den >= floor_v)) clamped += 1.0;
       const float a_new = (float)(1.0 / (den >= floor_v ? den : floor_v));
       // change of the prior variance 1/alpha as the stored (float32) alpha has it
-      const double g_new = 1.0 / (double)a_new, g_old = 1.0 / (double)alpha[d];
+      const float a_old = alpha[d];
+      const double g_new = 1.0 / (double)a_new, g_old = 1.0 / (double)a_old;
       dg2 += (g_new - g_old) * (g_new - g_old);
       g2 += g_new * g_new;
+      if (alpha_prev) alpha_prev[d] = a_old;  // the learned form's features see the step
       alpha[d] = a_new;
       mu[d] = (float)m;
       sdiag[d] = (float)s;
@@ -959,16 +961,16 @@ __global__ __launch_bounds__(kMsThreads) void k_conv_mstep(int64_t D, int64_t ld
 
 hipError_t conv_mstep(const ConvDims& cd, uint64_t seed, int t, const void* X, const double* xm,
                       float* alpha, double alpha_max, float* mu, float* sdiag, const ConvReduce& red, CgScalars* st,
-                      hipStream_t s) {
+                      hipStream_t s, float* alpha_prev) {
   // conv_update_blocks(cd) blocks: the first column region of the update's
   // reduction workspace (three values per block) serves the M-step's sums
   const unsigned blocks = (unsigned)conv_update_blocks(cd);
   if (cd.fp64)
     hipLaunchKernelGGL(k_conv_mstep<double>, dim3(blocks), dim3(kMsThreads), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
-                       static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st);
+                       static_cast<const double*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st, alpha_prev);
   else
     hipLaunchKernelGGL(k_conv_mstep<float>, dim3(blocks), dim3(kMsThreads), 0, s, cd.D, cd.ldD, cd.K, cd.perm, cd.nt, seed, t,
-                       static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st);
+                       static_cast<const float*>(X), xm, alpha, alpha_max, mu, sdiag, red.parts, red.cnts, st, alpha_prev);
   return hipGetLastError();
 }
 
