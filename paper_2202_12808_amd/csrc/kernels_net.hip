@@ -488,11 +488,13 @@ __global__ void k_net_features(const float* __restrict__ alpha, const float* __r
   sd = sd < 1e-3 ? 1e-3 : (sd > 1e3 ? 1e3 : sd);
   feats[p] = (float)(a / d);
   feats[HW + p] = (float)(mu[p] / rms);
-  feats[2 * HW + p] = (float)(log(sd) / 3.0);
-  feats[3 * HW + p] = (float)(log(d / bh) / 10.0);
-  double lr = log((bh + (double)alpha_prev[p]) / d);
-  lr = lr < -10.0 ? -10.0 : (lr > 10.0 ? 10.0 : lr);
-  feats[4 * HW + p] = (float)(lr / 10.0);
+  // the logs in float32 of the float64 ratios (the features are float32
+  // network inputs; about one ulp from the float64 logs)
+  feats[2 * HW + p] = logf((float)sd) / 3.0f;
+  feats[3 * HW + p] = logf((float)(d / bh)) / 10.0f;
+  float lr = logf((float)((bh + (double)alpha_prev[p]) / d));
+  lr = lr < -10.0f ? -10.0f : (lr > 10.0f ? 10.0f : lr);
+  feats[4 * HW + p] = lr / 10.0f;
   aux[p] = (float)mu[p];
   aux[HW + p] = (float)d;
   double sb = (double)s[p] * d;
