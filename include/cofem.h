@@ -286,10 +286,16 @@ cofem_status cofem_em_step_static(const cofem_problem* problem, const cofem_para
 
 /*
  * Runs `n_iters` EM iterations of Algorithm 1 (E-step by CG, diagonal
- * estimate, M-step).  Synchronises the stream at the end of every EM
- * iteration (the host reads the CG stop flag).  `stats` (host, nullable)
- * receives n_iters entries, or n_iters * n_problems for a batched context
- * (entry it * n_problems + i for problem i).
+ * estimate, M-step).  The host waits on the stream during each solve (it
+ * reads the CG stop flag) and for each iteration's statistics; on return every
+ * iteration's device work has completed.  Except for the batched form, the
+ * bfloat16 refinement and warm-started dense solves, each iteration's start
+ * (predictor, preconditioner, start block) is enqueued before the host waits
+ * for the previous iteration's statistics:
+ * the device work and its order are those of n_iters calls of one iteration,
+ * and so are the results.  `stats` (host, nullable) receives n_iters entries,
+ * or n_iters * n_problems for a batched context (entry it * n_problems + i for
+ * problem i).
  */
 cofem_status cofem_em_step(cofem_ctx* ctx, int32_t n_iters, cofem_iter_stats* stats);
 
